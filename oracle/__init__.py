@@ -1,0 +1,223 @@
+"""Python face of the CPU FP64 oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Imported by tests/, __graft_entry__.smoke() and
+the cpu_baseline leg of bench.py; the product package never imports it and it
+never imports the product package (model descriptions arrive as plain
+arrays from the seeded input generators).
+
+Everything here is computed in the full occupation basis of one sector
+(Eq. 1 of the paper written out term by term), not in the bipartite form.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+ORC_SPIN = 1
+ORC_HUBBARD = 2
+ORC_CUT_SPATIAL = 1
+ORC_CUT_UPDN = 2
+
+_lib = None
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_sites", ctypes.c_int32),
+                ("n_bonds", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("bi", ctypes.c_void_p), ("bj", ctypes.c_void_p),
+                ("jxy", ctypes.c_void_p), ("jz", ctypes.c_void_p),
+                ("t", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        i64, i32, vp, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_sector_size.restype = i64
+        L.orc_sector_size.argtypes = [ctypes.c_int] * 4
+        L.orc_enumerate.restype = i64
+        L.orc_enumerate.argtypes = [ctypes.c_int] * 4 + [vp]
+        L.orc_enumerate_bruteforce.restype = i64
+        L.orc_enumerate_bruteforce.argtypes = [ctypes.c_int, ctypes.c_int, vp]
+        L.orc_find.restype = i64
+        L.orc_find.argtypes = [vp, i64, ctypes.c_uint64]
+        L.orc_build_csr.restype = i64
+        L.orc_build_csr.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.orc_spmv_csr.restype = None
+        L.orc_spmv_csr.argtypes = [i64, vp, vp, vp, vp, vp]
+        L.orc_apply_rows.restype = ctypes.c_int
+        L.orc_apply_rows.argtypes = [vp, vp, i64, vp, vp, i64, vp]
+        L.orc_apply_full.restype = ctypes.c_int
+        L.orc_apply_full.argtypes = [vp, vp, i64, vp, vp]
+        L.orc_bipartite_positions.restype = ctypes.c_int
+        L.orc_bipartite_positions.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                              ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, ctypes.c_int]
+        L.orc_tridiag_eig.restype = dbl
+        L.orc_tridiag_eig.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
+        L.orc_lanczos.restype = ctypes.c_int
+        L.orc_lanczos.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, dbl,
+                                  vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class OracleModel:
+    """Holds the model arrays alive and the C struct that points at them.
+
+    `m` is any object with attributes kind ('spin'|'hubbard'), n_sites,
+    bonds (k x 2 int), and jxy/jz (spin) or t/u (Hubbard)."""
+
+    def __init__(self, m):
+        self.kind = ORC_SPIN if m.kind == "spin" else ORC_HUBBARD
+        self.n_sites = int(m.n_sites)
+        b = np.ascontiguousarray(np.asarray(m.bonds, dtype=np.int32).reshape(-1, 2))
+        self.bi = np.ascontiguousarray(b[:, 0])
+        self.bj = np.ascontiguousarray(b[:, 1])
+        self.n_bonds = len(self.bi)
+        z = np.zeros(max(self.n_bonds, 1))
+        if self.kind == ORC_SPIN:
+            self.jxy = np.ascontiguousarray(m.jxy, dtype=np.float64)
+            self.jz = np.ascontiguousarray(m.jz, dtype=np.float64)
+            self.t, self.u = z, None
+        else:
+            self.t = np.ascontiguousarray(m.t, dtype=np.float64)
+            self.u = None if m.u is None else np.ascontiguousarray(m.u, dtype=np.float64)
+            self.jxy = self.jz = z
+        self.c = _Model(self.kind, self.n_sites, self.n_bonds, 0,
+                        _ptr(self.bi), _ptr(self.bj), _ptr(self.jxy), _ptr(self.jz),
+                        _ptr(self.t), _ptr(self.u))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def sector_size(kind, n_sites, n_up, n_dn=0):
+    k = ORC_SPIN if kind == "spin" else ORC_HUBBARD
+    return lib().orc_sector_size(k, n_sites, n_up, n_dn)
+
+
+def enumerate_basis(kind, n_sites, n_up, n_dn=0):
+    """Sector basis words in increasing integer order (uint64)."""
+    k = ORC_SPIN if kind == "spin" else ORC_HUBBARD
+    n = lib().orc_enumerate(k, n_sites, n_up, n_dn, None)
+    if n < 0:
+        raise ValueError("unsupported sector")
+    w = np.empty(n, dtype=np.uint64)
+    lib().orc_enumerate(k, n_sites, n_up, n_dn, _ptr(w))
+    return w
+
+
+def enumerate_bruteforce(n_sites, n_up):
+    n = lib().orc_enumerate_bruteforce(n_sites, n_up, None)
+    w = np.empty(n, dtype=np.uint64)
+    lib().orc_enumerate_bruteforce(n_sites, n_up, _ptr(w))
+    return w
+
+
+class Sector:
+    """One symmetry sector of one model in the occupation basis."""
+
+    def __init__(self, model, n_up, n_dn=0):
+        self.model = model
+        self.om = OracleModel(model)
+        self.n_up, self.n_dn = int(n_up), int(n_dn)
+        self.words = enumerate_basis(model.kind, model.n_sites, n_up, n_dn)
+        self.n = len(self.words)
+        self._csr = None
+
+    def find(self, w):
+        return lib().orc_find(_ptr(self.words), self.n, int(w))
+
+    def csr(self):
+        if self._csr is None:
+            rp = np.empty(self.n + 1, dtype=np.int64)
+            nnz = lib().orc_build_csr(self.om.ref, _ptr(self.words), self.n, _ptr(rp), None, None)
+            if nnz < 0:
+                raise RuntimeError(f"oracle CSR build failed ({nnz})")
+            col = np.empty(nnz, dtype=np.int32)
+            val = np.empty(nnz, dtype=np.float64)
+            r = lib().orc_build_csr(self.om.ref, _ptr(self.words), self.n, _ptr(rp), _ptr(col), _ptr(val))
+            if r < 0:
+                raise RuntimeError(f"oracle CSR fill failed ({r})")
+            self._csr = (rp, col, val)
+        return self._csr
+
+    def dense(self):
+        rp, col, val = self.csr()
+        H = np.zeros((self.n, self.n))
+        for r in range(self.n):
+            H[r, col[rp[r]:rp[r + 1]]] = val[rp[r]:rp[r + 1]]
+        return H
+
+    def apply(self, x, use_csr=True):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(self.n)
+        if use_csr:
+            rp, col, val = self.csr()
+            lib().orc_spmv_csr(self.n, _ptr(rp), _ptr(col), _ptr(val), _ptr(x), _ptr(y))
+        else:
+            if lib().orc_apply_full(self.om.ref, _ptr(self.words), self.n, _ptr(x), _ptr(y)):
+                raise RuntimeError("oracle apply failed")
+        return y
+
+    def apply_rows(self, x, rows):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        y = np.empty(len(rows))
+        if lib().orc_apply_rows(self.om.ref, _ptr(self.words), self.n, _ptr(x), _ptr(rows), len(rows), _ptr(y)):
+            raise RuntimeError("oracle apply_rows failed")
+        return y
+
+    def bipartite(self, cut_kind, left_mask=0):
+        """(pos, blocks): pos[i] = bipartite position of canonical index i;
+        blocks = int64 array of rows (q_l, d_L, d_R, offset)."""
+        ck = ORC_CUT_SPATIAL if cut_kind == "spatial" else ORC_CUT_UPDN
+        pos = np.empty(self.n, dtype=np.int64)
+        blocks = np.empty(4 * 65, dtype=np.int64)
+        nb = lib().orc_bipartite_positions(self.om.kind, ck, self.model.n_sites, int(left_mask),
+                                           self.n_up, self.n_dn, _ptr(self.words), self.n,
+                                           _ptr(pos), _ptr(blocks), 65)
+        if nb < 0:
+            raise ValueError(f"oracle bipartite map failed ({nb})")
+        return pos, blocks[:4 * nb].reshape(nb, 4).copy()
+
+    def lanczos(self, v0, max_steps, reorth=False, tol=0.0, use_csr=True):
+        """Returns (energies per step, alpha, beta)."""
+        v0 = np.ascontiguousarray(v0, dtype=np.float64)
+        a = np.zeros(max_steps)
+        b = np.zeros(max_steps)
+        e = np.zeros(max_steps)
+        basis = np.empty((max_steps, self.n)) if reorth else None
+        if use_csr:
+            rp, col, val = self.csr()
+        else:
+            rp = col = val = None
+        s = lib().orc_lanczos(self.om.ref, _ptr(self.words), self.n, _ptr(rp), _ptr(col), _ptr(val),
+                              _ptr(v0), max_steps, 1 if reorth else 0, tol,
+                              _ptr(a), _ptr(b), _ptr(e), _ptr(basis))
+        if s < 0:
+            raise RuntimeError(f"oracle lanczos failed ({s})")
+        return e[:s].copy(), a[:s].copy(), b[:s].copy()
+
+
+def tridiag_eig(alpha, beta, k=0):
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    if len(b) < max(len(a) - 1, 1):
+        b = np.concatenate([b, np.zeros(max(len(a) - 1, 1) - len(b))])
+    return lib().orc_tridiag_eig(_ptr(a), _ptr(b), len(a), k)

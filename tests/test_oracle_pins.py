@@ -1,0 +1,365 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test ties an oracle function to mathematics the paper fixes or to an
+independent construction:
+  - basis enumeration vs brute force over all 2^n words and vs binomials;
+  - Hamiltonian entries vs dense Kronecker-product constructions (Pauli
+    matrices for spins; Jordan-Wigner strings for fermions), which share no
+    code with the oracle's term-by-term sign counting;
+  - the bipartite map vs the block identity of Eq. (2) with the
+    Vec-Kronecker rule (left operator from the left, right operator from
+    the right) built from independently enumerated subsystem sectors;
+  - Lanczos energies vs closed forms (free fermions, XX chain, two-site
+    problems) and vs dense diagonalisation;
+  - Sturm bisection vs a library tridiagonal eigensolver.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_07621_amd import inputs as I
+
+
+# ---------------------------------------------------------------- bases
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 12, 16])
+def test_enumeration_matches_bruteforce(n):
+    for k in range(n + 1):
+        w = O.enumerate_basis("spin", n, k)
+        assert len(w) == math.comb(n, k)
+        np.testing.assert_array_equal(w, O.enumerate_bruteforce(n, k))
+
+
+def test_hubbard_enumeration_is_up_major_product():
+    L = 6
+    w = O.enumerate_basis("hubbard", L, 2, 3)
+    assert len(w) == math.comb(6, 2) * math.comb(6, 3)
+    assert np.all(np.diff(w.astype(np.int64)) > 0)
+    up = O.enumerate_bruteforce(L, 2)
+    dn = O.enumerate_bruteforce(L, 3)
+    ref = np.array([(int(a) << L) | int(b) for a in up for b in dn], dtype=np.uint64)
+    np.testing.assert_array_equal(w, ref)
+
+
+def test_sector_sizes_of_measured_workloads():
+    # 16-site chain at Sz=0: C(16,8); 12-site Hubbard half filling: C(12,6)^2;
+    # 16-site Hubbard: C(16,8)^2; 6x5 lattice at Sz=0: C(30,15).
+    assert O.sector_size("spin", 16, 8) == 12870
+    assert O.sector_size("hubbard", 12, 6, 6) == 924 * 924 == 853776
+    assert O.sector_size("hubbard", 16, 8, 8) == 12870 ** 2 == 165636900
+    assert O.sector_size("spin", 30, 15) == 155117520
+
+
+def test_find():
+    w = O.enumerate_basis("spin", 10, 4)
+    s = O.Sector(I.heisenberg_chain(10), 4)
+    for i in [0, 1, 57, len(w) - 1]:
+        assert s.find(w[i]) == i
+    assert s.find(0b1111000000) == list(w).index(0b1111000000)
+    assert s.find(0b111) == -1
+
+
+# ---------------------------------------------------------------- spin H vs Pauli Kronecker products
+
+SZ = np.diag([-0.5, 0.5])          # local basis: index 0 = down, 1 = up (bit set)
+SP = np.array([[0.0, 0.0], [1.0, 0.0]])   # S+ |down> = |up>
+SM = SP.T
+ID2 = np.eye(2)
+
+
+def site_op(op, i, n):
+    """Operator on site i of n; matrix index = sum_i bit_i 2^i."""
+    out = np.array([[1.0]])
+    for s in range(n - 1, -1, -1):
+        out = np.kron(out, op if s == i else ID2)
+    return out
+
+
+def dense_spin(model):
+    n = model.n_sites
+    H = np.zeros((2 ** n, 2 ** n))
+    for (i, j), jxy, jz in zip(model.bonds, model.jxy, model.jz):
+        H += jz * site_op(SZ, i, n) @ site_op(SZ, j, n)
+        H += 0.5 * jxy * (site_op(SP, i, n) @ site_op(SM, j, n) + site_op(SM, i, n) @ site_op(SP, j, n))
+    return H
+
+
+@pytest.mark.parametrize("seed,n", [(1, 4), (2, 6), (3, 7), (4, 8)])
+def test_spin_hamiltonian_vs_pauli_kron(seed, n):
+    rng = np.random.default_rng(seed)
+    m = I.random_spin_model(rng, n)
+    Hfull = dense_spin(m)
+    for k in range(n + 1):
+        s = O.Sector(m, k)
+        idx = s.words.astype(np.int64)
+        np.testing.assert_allclose(s.dense(), Hfull[np.ix_(idx, idx)], atol=1e-14, rtol=0)
+
+
+def test_spin_sector_blocks_cover_full_matrix():
+    # Sz conservation: the Kronecker H has no element between sectors.
+    m = I.random_spin_model(np.random.default_rng(9), 6)
+    Hfull = dense_spin(m)
+    w = np.arange(2 ** 6)
+    pc = np.array([bin(x).count("1") for x in w])
+    assert np.abs(Hfull[pc[:, None] != pc[None, :]]).max() == 0.0
+
+
+# ---------------------------------------------------------------- Hubbard H vs Jordan-Wigner strings
+
+ZF = np.diag([1.0, -1.0])          # (-1)^n
+AF = np.array([[0.0, 1.0], [0.0, 0.0]])   # a|1> = |0>
+
+
+def jw_annihilator(m, M):
+    """c_m = Z_0 ... Z_{m-1} a_m on M modes; matrix index = sum_m n_m 2^m."""
+    out = np.array([[1.0]])
+    for k in range(M - 1, -1, -1):
+        op = AF if k == m else (ZF if k < m else ID2)
+        out = np.kron(out, op)
+    return out
+
+
+def dense_hubbard_word_basis(model):
+    """Dense Hubbard H via Jordan-Wigner, modes ordered (0,up)..(L-1,up),
+    (0,dn)..(L-1,dn), re-indexed to the word (up << L) | dn."""
+    L = model.n_sites
+    M = 2 * L
+    c = [jw_annihilator(m, M) for m in range(M)]
+    H = np.zeros((2 ** M, 2 ** M))
+    for (i, j), t in zip(model.bonds, model.t):
+        for sp in range(2):
+            a, b = sp * L + i, sp * L + j
+            H += -t * (c[a].T @ c[b] + c[b].T @ c[a])
+    for s in range(L):
+        H += model.u[s] * (c[s].T @ c[s]) @ (c[L + s].T @ c[L + s])
+    # mode-bit index -> word index: up site s (mode s) is word bit L+s, dn site s (mode L+s) is bit s
+    perm = np.zeros(2 ** M, dtype=np.int64)
+    for idx in range(2 ** M):
+        word = 0
+        for m in range(M):
+            if (idx >> m) & 1:
+                word |= 1 << ((L + m) if m < L else (m - L))
+        perm[idx] = word
+    Hw = np.zeros_like(H)
+    Hw[np.ix_(perm, perm)] = H
+    return Hw
+
+
+@pytest.mark.parametrize("seed,L", [(11, 2), (12, 3), (13, 4), (14, 4)])
+def test_hubbard_hamiltonian_vs_jordan_wigner(seed, L):
+    rng = np.random.default_rng(seed)
+    m = I.random_hubbard_model(rng, L, n_bonds=min(L * (L - 1) // 2, 2 * L))
+    Hfull = dense_hubbard_word_basis(m)
+    for nu in range(L + 1):
+        for nd in range(L + 1):
+            s = O.Sector(m, nu, nd)
+            idx = s.words.astype(np.int64)
+            np.testing.assert_allclose(s.dense(), Hfull[np.ix_(idx, idx)], atol=1e-14, rtol=0)
+
+
+def test_long_range_hop_carries_fermion_sign():
+    # A hop 0<->2 over an occupied site 1 must pick up a minus sign relative
+    # to the same hop over an empty site (same-spin electrons only).
+    m = I.Model("hubbard", 3, np.array([[0, 2]], dtype=np.int32), t=np.array([1.0]), u=np.zeros(3))
+    s = O.Sector(m, 2, 0)
+    H = s.dense()
+    L = 3
+    w_a = (0b011 << L)   # up on sites 0,1
+    w_b = (0b110 << L)   # up on sites 1,2
+    ia, ib = s.find(w_a), s.find(w_b)
+    assert H[ia, ib] == pytest.approx(+1.0)   # -t * (-1)
+    s0 = O.Sector(m, 1, 0)
+    H0 = s0.dense()
+    assert H0[s0.find(0b001 << L), s0.find(0b100 << L)] == pytest.approx(-1.0)
+
+
+@pytest.mark.parametrize("kind", ["spin", "hubbard"])
+def test_hermiticity(kind):
+    rng = np.random.default_rng(5)
+    if kind == "spin":
+        s = O.Sector(I.random_spin_model(rng, 10), 5)
+    else:
+        s = O.Sector(I.random_hubbard_model(rng, 5), 2, 3)
+    phi = rng.standard_normal(s.n)
+    psi = rng.standard_normal(s.n)
+    lhs = phi @ s.apply(psi)
+    rhs = s.apply(phi) @ psi
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+
+
+def test_row_generator_matches_csr():
+    rng = np.random.default_rng(6)
+    s = O.Sector(I.random_hubbard_model(rng, 6), 3, 2)
+    x = rng.standard_normal(s.n)
+    y1 = s.apply(x, use_csr=True)
+    y2 = s.apply(x, use_csr=False)
+    np.testing.assert_array_equal(y1, y2)
+    rows = rng.integers(0, s.n, 50)
+    np.testing.assert_array_equal(s.apply_rows(x, rows), y1[rows])
+
+
+# ---------------------------------------------------------------- bipartite map vs Eq. (2) block identity
+
+def _submodel_spin(model, sites):
+    """Restrict a spin model to the bonds inside `sites`, renumbered 0..k-1."""
+    idx = {s: k for k, s in enumerate(sites)}
+    keep = [b for b in range(len(model.bonds)) if model.bonds[b][0] in idx and model.bonds[b][1] in idx]
+    bonds = np.array([[idx[model.bonds[b][0]], idx[model.bonds[b][1]]] for b in keep], dtype=np.int32).reshape(-1, 2)
+    return I.Model("spin", len(sites), bonds, jxy=model.jxy[keep], jz=model.jz[keep])
+
+
+@pytest.mark.parametrize("seed,n,left", [(21, 8, [0, 1, 2]), (22, 9, [1, 4, 5, 8]), (23, 10, [0, 2, 4, 6, 8])])
+def test_spatial_bipartite_map_vs_block_identity(seed, n, left):
+    """With no bond across the cut, H = H_L x 1 + 1 x H_R, so in the
+    bipartite layout every block obeys Y_q = H_L^{q_l} Psi_q + Psi_q H_R^{q_r T}
+    (the Vec-Kronecker rule for column-stacked blocks)."""
+    rng = np.random.default_rng(seed)
+    right = [s for s in range(n) if s not in left]
+    full = I.random_spin_model(rng, n, n_bonds=3 * n)
+    keep = [b for b in range(len(full.bonds))
+            if (full.bonds[b][0] in left) == (full.bonds[b][1] in left)]
+    model = I.Model("spin", n, full.bonds[keep], jxy=full.jxy[keep], jz=full.jz[keep])
+    mask = sum(1 << s for s in left)
+    for n_up in range(n + 1):
+        s = O.Sector(model, n_up)
+        pos, blocks = s.bipartite("spatial", mask)
+        assert sorted(pos.tolist()) == list(range(s.n))
+        x = rng.standard_normal(s.n)
+        y = s.apply(x)
+        xb = np.empty(s.n); xb[pos] = x
+        yb = np.empty(s.n); yb[pos] = y
+        mL, mR = _submodel_spin(model, left), _submodel_spin(model, right)
+        for q_l, dL, dR, off in blocks:
+            HL = O.Sector(mL, int(q_l)).dense()
+            HR = O.Sector(mR, n_up - int(q_l)).dense()
+            P = xb[off:off + dL * dR].reshape(dL, dR)
+            np.testing.assert_allclose(yb[off:off + dL * dR].reshape(dL, dR), HL @ P + P @ HR.T,
+                                       atol=1e-12, rtol=0)
+
+
+def test_spatial_cut_cross_term_vs_kron():
+    """One bond across the cut: Y = [H_L x 1 + 1 x H_R + sum_m L_m x R_m] Psi
+    evaluated with np.kron on each block pair (q, k) must agree with the
+    oracle's full H in bipartite order."""
+    rng = np.random.default_rng(31)
+    n, left = 6, [0, 1, 2]
+    bonds = np.array([[0, 1], [1, 2], [3, 4], [4, 5], [2, 3]], dtype=np.int32)
+    model = I.Model("spin", n, bonds, jxy=rng.uniform(0.5, 1.5, 5), jz=rng.uniform(0.5, 1.5, 5))
+    n_up = 3
+    s = O.Sector(model, n_up)
+    pos, blocks = s.bipartite("spatial", 0b000111)
+    Hb = np.zeros((s.n, s.n))
+    Hb[np.ix_(pos, pos)] = s.dense()
+    # Independent construction: full 2^6 Kronecker H, then pick rows/cols by
+    # the (l, r) words of each block, L word = bits of sites 0..2, R word = sites 3..5.
+    Hk = dense_spin(model)
+    order = []
+    for q_l, dL, dR, off in blocks:
+        lw = O.enumerate_bruteforce(3, int(q_l))
+        rw = O.enumerate_bruteforce(3, n_up - int(q_l))
+        for a in lw:
+            for b in rw:
+                order.append(int(a) | (int(b) << 3))
+    order = np.array(order)
+    np.testing.assert_allclose(Hb, Hk[np.ix_(order, order)], atol=1e-14, rtol=0)
+
+
+def test_updn_bipartite_map_vs_block_identity():
+    """Up/down cut at U=0: H = H_up x 1 + 1 x H_dn, so Y = H_up Psi + Psi H_dn^T
+    with Psi[up, dn]; at U != 0 the extra term is diagonal in (up, dn)."""
+    rng = np.random.default_rng(41)
+    L = 6
+    m = I.random_hubbard_model(rng, L, n_bonds=8)
+    m0 = I.Model("hubbard", L, m.bonds, t=m.t, u=np.zeros(L))
+    nu, nd = 3, 2
+    s = O.Sector(m0, nu, nd)
+    pos, blocks = s.bipartite("updn")
+    np.testing.assert_array_equal(pos, np.arange(s.n))
+    assert blocks.tolist() == [[nu, math.comb(L, nu), math.comb(L, nd), 0]]
+    Hup = O.Sector(m0, nu, 0).dense()
+    Hdn = O.Sector(m0, 0, nd).dense()
+    x = rng.standard_normal(s.n)
+    P = x.reshape(math.comb(L, nu), math.comb(L, nd))
+    np.testing.assert_allclose(s.apply(x).reshape(P.shape), Hup @ P + P @ Hdn.T, atol=1e-12, rtol=0)
+    # the U part is diagonal: H(U) - H(0) has no off-diagonal element
+    D = O.Sector(m, nu, nd).dense() - s.dense()
+    assert np.abs(D - np.diag(np.diag(D))).max() == 0.0
+
+
+# ---------------------------------------------------------------- energies: closed forms and dense
+
+def free_fermion_chain_energy(L, n_per_spin, t=1.0, spins=2):
+    eps = np.sort(-2.0 * t * np.cos(np.arange(1, L + 1) * np.pi / (L + 1)))
+    return spins * eps[:n_per_spin].sum()
+
+
+def test_u0_hubbard_12_sites_closed_form():
+    p = I.hubbard12()
+    m = I.hubbard_chain(12, 1.0, 0.0)
+    s = O.Sector(m, 6, 6)
+    e, a, b = s.lanczos(I.psi(p.meta["seed"] + 1, s.n), 200)
+    ref = free_fermion_chain_energy(12, 6)
+    assert ref == pytest.approx(-14.592459621117511, abs=1e-12)
+    assert abs(e[-1] - ref) <= 1e-10
+
+
+def test_xx_chain_closed_form():
+    n = 16
+    m = I.xxz_chain(n, 1.0, 0.0)
+    s = O.Sector(m, n // 2)
+    e, _, _ = s.lanczos(I.psi(7, s.n), 150)
+    # Jordan-Wigner: free fermions with hopping J/2, levels J cos(k pi/(N+1)).
+    lev = np.sort(np.cos(np.arange(1, n + 1) * np.pi / (n + 1)))
+    assert abs(e[-1] - lev[: n // 2].sum()) <= 1e-10
+
+
+@pytest.mark.parametrize("U", [0.0, 1.0, 4.0, 8.0])
+def test_two_site_hubbard_closed_form(U):
+    m = I.hubbard_chain(2, 1.0, U)
+    s = O.Sector(m, 1, 1)
+    ev = np.linalg.eigvalsh(s.dense())
+    assert ev[0] == pytest.approx((U - math.sqrt(U * U + 16.0)) / 2.0, abs=1e-13)
+
+
+def test_two_site_heisenberg_singlet():
+    s = O.Sector(I.heisenberg_chain(2), 1)
+    assert np.linalg.eigvalsh(s.dense())[0] == pytest.approx(-0.75, abs=1e-15)
+
+
+@pytest.mark.parametrize("kind,seed", [("spin", 1), ("spin", 2), ("hubbard", 3), ("hubbard", 4)])
+def test_lanczos_vs_dense(kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "spin":
+        s = O.Sector(I.random_spin_model(rng, 10), 5)
+    else:
+        s = O.Sector(I.random_hubbard_model(rng, 5), 2, 3)
+    ev = np.linalg.eigvalsh(s.dense())
+    e, a, b = s.lanczos(rng.standard_normal(s.n), min(s.n, 120), reorth=True)
+    assert abs(e[-1] - ev[0]) <= 1e-10
+    # Cauchy interlacing: the lowest Ritz value never increases
+    assert np.all(np.diff(e) <= 1e-12)
+
+
+def test_heisenberg16_dense_vs_lanczos():
+    p = I.heisenberg16()
+    s = O.Sector(p.model, 8)
+    e, _, _ = s.lanczos(I.psi(p.meta["seed"] + 1, s.n), 100)
+    rp, col, val = s.csr()
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    H = sp.csr_matrix((val, col, rp), shape=(s.n, s.n))
+    ref = sla.eigsh(H, k=1, which="SA", tol=1e-14)[0][0]
+    assert abs(e[-1] - ref) <= 1e-10
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 40])
+def test_bisection_vs_eigvalsh(m):
+    rng = np.random.default_rng(m)
+    a = rng.standard_normal(m)
+    b = rng.standard_normal(max(m - 1, 0))
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    ev = np.linalg.eigvalsh(T)
+    for k in range(m):
+        assert O.tridiag_eig(a, b, k) == pytest.approx(ev[k], abs=1e-13)
