@@ -1,0 +1,156 @@
+#!/usr/bin/env python3
+"""Benchmark of the bipartite H*psi on one MI355X.
+
+A timed step is one H*psi application (left operator, right operator,
+diagonal and cross-cut terms: the whole per-application hot path) on the
+16-site Hubbard chain at half filling, U=8, up/down cut: Psi is
+12870 x 12870 FP64 (1.33 GB), resident in HBM before timing starts.
+
+Prints one JSON line: applies/s, the roofline of the dominant kernel
+(algorithmic bytes / average kernel time from HIP events on the launch
+stream), the oracle timed on a bounded sample on the host cores, and a
+short Lanczos-step timing.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2605_07621_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel, workload, per_launch_alg):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    or None if there is none or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(p, seconds):
+    """The oracle, row by row, on a contiguous seeded slice of the same
+    workload's rows (bounded so the run stays short)."""
+    import numpy as np
+    import oracle as O
+    from paper_2605_07621_amd import inputs as I
+    words = O.enumerate_basis(p.model.kind, p.model.n_sites, p.n_up, p.n_dn)
+    n = len(words)
+    psi = I.psi(p.meta["seed"], n)
+    sec = O.Sector.__new__(O.Sector)
+    sec.model, sec.om, sec.words, sec.n = p.model, O.OracleModel(p.model), words, n
+    start = int(np.random.default_rng(11).integers(0, n // 2))
+    rows = np.arange(start, start + 20000, dtype=np.int64)
+    t0 = time.perf_counter()
+    sec.apply_rows(psi, rows)
+    dt = time.perf_counter() - t0
+    m = int(min(n - start, max(20000, 20000 * seconds / max(dt, 1e-6))))
+    rows = np.arange(start, start + m, dtype=np.int64)
+    t0 = time.perf_counter()
+    sec.apply_rows(psi, rows)
+    dt = time.perf_counter() - t0
+    return dict(value=(m / n) / dt, unit="H*psi/s", cores=O.num_threads(), kind="oracle",
+                sample=f"{m} of {n} rows (contiguous from row {start}), row-by-row oracle, "
+                       f"{dt:.1f} s; value scaled to full applications",
+                seconds=round(dt, 3))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="hubbard16")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lanczos-steps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_07621_amd import ecut, inputs as I
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = I.WORKLOADS[args.workload]()
+    S = ecut.Sectors.from_problem(p)
+    n = S.dim
+    x = S.import_(torch.from_numpy(I.psi(p.meta.get("seed", 1), n)).to(dev))
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        S.apply(x, y, stream=stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        S.apply(x, y, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    kern_ms = ev0.elapsed_time(ev1) / args.steps
+    alg_bytes = 2 * n * 8 + int(S.info.device_bytes)
+    kernel = "k_hub" if S.info.kernel == 1 else "k_rows"
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(kernel, args.workload, alg_bytes)
+
+    # a few fused Lanczos steps (H*psi + alpha + update + beta) on the same input
+    lz = None
+    if args.lanczos_steps > 0:
+        S.lanczos(x, 2, fixed_steps=True)
+        torch.cuda.synchronize()
+        tl = time.perf_counter()
+        e, st, _ = S.lanczos(x, args.lanczos_steps, fixed_steps=True)
+        lz = dict(steps=st["steps"], ms_per_step=round((time.perf_counter() - tl) * 1e3 / st["steps"], 4))
+
+    line = {
+        "metric": "H*psi applies/s (16-site Hubbard, FP64) + HBM GB/s",
+        "value": round(args.steps / wall, 3),
+        "unit": "H*psi/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": p.model.name + "_" + p.cut.kind, "sites": p.model.n_sites,
+                   "n_up": p.n_up, "n_dn": p.n_dn, "dim": n, "blocks": int(S.info.n_blocks),
+                   "kernel": kernel},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes": alg_bytes,
+                     "kernel_ms": round(kern_ms, 5), "kernel": kernel},
+        "lanczos": lz,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

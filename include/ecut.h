@@ -1,0 +1,281 @@
+/*
+ * ecut.h -- C ABI of libecut.so: the entanglement-cut bipartite Hamiltonian
+ * application H*psi on MI355X (gfx950), the Lanczos ground-state solver built
+ * on it, batched application over many sectors/Hamiltonians, and a
+ * continuous-batching ground-state server.
+ *
+ * Problem statement (paper, Eq. 1-3):
+ *   - H is K-local (K <= 2 here) on S sites with an Abelian symmetry Q
+ *     (Eq. 1): U(1) Sz for spin-1/2 models, U(1)xU(1) (N_up, N_dn) for the
+ *     Hubbard model;
+ *   - an entanglement cut C splits the system into L and R with
+ *     q_l (+) q_r = q, giving the blocks of Eq. (2);
+ *   - the state is the set of block matrices Psi_q of Eq. (3), stored here
+ *     row-major as Psi_q[l][r] (the paper's column-stacked Psi^q_{r l} is the
+ *     same memory), blocks by ascending q_l, contiguous, no padding.
+ *     Position of (q, l, r) = offset[q] + l * d_R[q] + r, where l and r are
+ *     the colex ranks (= rank in increasing integer order) of the left and
+ *     right subsystem words.
+ *
+ * Conventions shared by every entry point:
+ *   - Device pointers (suffix _d) are caller-owned device memory on the
+ *     current HIP device; host pointers are caller-owned host memory.
+ *     The library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that take
+ *     a stream are asynchronous on it unless stated otherwise.
+ *   - Every call returns an ecut_status and never throws.  Argument errors
+ *     are reported before any device work is queued.  A message for the last
+ *     failure of the calling thread is available from ecut_last_error().
+ *   - Handles are immutable after ecut_build_sectors and may be used from
+ *     several streams and threads at once for ecut_apply_H.
+ */
+#ifndef ECUT_H
+#define ECUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ECUT_OK = 0,
+    ECUT_EINVAL = -1,        /* bad argument, null pointer, inconsistent model */
+    ECUT_ENOMEM = -2,        /* host or device allocation failed / over budget */
+    ECUT_EDEVICE = -3,       /* a HIP call failed (also asynchronous errors) */
+    ECUT_ENOTCONV = -4,      /* Lanczos stopped at max_steps before tol */
+    ECUT_EUNSUPPORTED = -5,  /* valid request outside what this build handles */
+    ECUT_EAGAIN = -6         /* server: nothing finished yet */
+} ecut_status;
+
+enum { ECUT_SPIN_HALF = 1, ECUT_HUBBARD = 2 };
+enum { ECUT_CUT_SPATIAL = 1, ECUT_CUT_UPDN = 2 };
+
+/* Flags of ecut_build_sectors. */
+enum {
+    ECUT_BUILD_HOST_ONLY = 1   /* build host tables only; device calls then return ECUT_EINVAL */
+};
+
+/*
+ * K-local Hamiltonian (Eq. 1) with K <= 2.
+ *   ECUT_SPIN_HALF: H = sum_b jxy[b] (Sx_i Sx_j + Sy_i Sy_j) + jz[b] Sz_i Sz_j,
+ *                   S = sigma/2, i = bond_i[b], j = bond_j[b]; site i = bit i
+ *                   of the occupation word, spin up = bit set.  t, u unused.
+ *   ECUT_HUBBARD:   H = -sum_b t[b] sum_s (c+_{i s} c_{j s} + h.c.)
+ *                       + sum_i u[i] n_{i up} n_{i dn}.
+ *                   Fermion order: all up modes, then all down modes, each by
+ *                   increasing site.  u may be NULL (all zero).  jxy, jz unused.
+ * Arrays are read during ecut_build_sectors only.
+ */
+typedef struct ecut_model_desc {
+    int32_t kind;             /* ECUT_SPIN_HALF | ECUT_HUBBARD */
+    int32_t n_sites;          /* spin: 1..64; Hubbard: 1..32 */
+    int32_t n_bonds;          /* >= 0 */
+    int32_t reserved;         /* must be 0 */
+    const int32_t *bond_i;    /* [n_bonds], 0 <= bond_i < n_sites */
+    const int32_t *bond_j;    /* [n_bonds], bond_j != bond_i */
+    const double *jxy;        /* [n_bonds] spin */
+    const double *jz;         /* [n_bonds] spin */
+    const double *t;          /* [n_bonds] Hubbard */
+    const double *u;          /* [n_sites] Hubbard, nullable */
+} ecut_model_desc;
+
+/*
+ * Entanglement cut C (paper, Fig. 1(a-c)).
+ *   ECUT_CUT_SPATIAL (spin): L = sites whose bit is set in left_mask, R = the
+ *       rest; subsystem word bit k = k-th site of that part in increasing
+ *       site order.  Both parts need 1..32 sites.
+ *   ECUT_CUT_UPDN (Hubbard): the cut in the spin-group space of Fig. 1(c):
+ *       L = up-spin occupation word, R = down-spin word; one block
+ *       (N_up, N_dn); left_mask unused.  The Hubbard H then has the diagonal
+ *       cross term U n_up n_dn only (the "particularly symmetric" case).
+ */
+typedef struct ecut_cut_desc {
+    int32_t kind;
+    int32_t reserved;         /* must be 0 */
+    uint64_t left_mask;
+} ecut_cut_desc;
+
+/* Target sector q: spin: n_up = number of up spins (n_dn ignored);
+ * Hubbard: particle numbers per spin species. */
+typedef struct ecut_qnum {
+    int32_t n_up;
+    int32_t n_dn;
+} ecut_qnum;
+
+typedef struct ecut_sectors ecut_sectors;
+
+typedef struct ecut_sectors_info {
+    int64_t dim;              /* sum_q d_L[q] d_R[q] */
+    int32_t n_blocks;         /* N_Q, blocks with d_L d_R > 0 */
+    int32_t n_left_sites;
+    int32_t n_right_sites;
+    int32_t max_d_r;          /* longest block row */
+    int32_t n_cut_bonds;      /* bonds with one end in L and one in R (spin) */
+    int32_t n_cross_offdiag;  /* sector-changing L_m (x) R_m products (2 per cut bond with jxy != 0) */
+    int32_t n_cross_diag;     /* diagonal cross-cut terms */
+    int32_t kernel;           /* kernel family chosen for ecut_apply_H (1 = Hubbard up/down, 2 = generic rows) */
+    int64_t device_bytes;     /* device metadata held by the handle */
+    double n_eff;             /* 1 / sum_q w_q^2 with w_q = d_L d_R / dim (block-size participation number) */
+} ecut_sectors_info;
+
+/*
+ * Build the symmetry-resolved bipartite description of H for one sector:
+ * subsystem bases with colex ranking, the block list (q_l + q_r = q, Eq. 2),
+ * off-diagonal CSR of H_L and H_R per subsystem count, their diagonals, the
+ * cross-cut diagonal terms and the sector-changing cross terms L_m (x) R_m
+ * (partial permutations), then upload them to the current device.
+ *   flags: ECUT_BUILD_HOST_ONLY to skip the device upload (host queries only).
+ * Errors: ECUT_EINVAL (bad model/cut/qnum, e.g. a spin model with an
+ * up/down cut or counts outside 0..sites, which would give an empty sector),
+ * ECUT_EUNSUPPORTED (subsystem wider than 32 sites; Hubbard with a spatial
+ * cut), ECUT_ENOMEM, ECUT_EDEVICE.  Synchronous.  *out owns its memory;
+ * release it with ecut_sectors_free.
+ */
+ecut_status ecut_build_sectors(const ecut_model_desc *model, const ecut_cut_desc *cut,
+                               ecut_qnum q, uint32_t flags, ecut_sectors **out);
+
+void ecut_sectors_free(ecut_sectors *s);
+
+ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info);
+
+/* blocks: host int64 array of n_blocks x 5 entries (q_l, q_r, d_L, d_R, offset). */
+ecut_status ecut_sectors_blocks(const ecut_sectors *s, int64_t *blocks);
+
+/* Subsystem words of one block in rank order: l_words[d_L], r_words[d_R]
+ * (host arrays; either may be NULL). */
+ecut_status ecut_sectors_words(const ecut_sectors *s, int32_t block,
+                               uint32_t *l_words, uint32_t *r_words);
+
+/* pos[i] = bipartite position of the i-th sector state in canonical order
+ * (full occupation words in increasing integer order; Hubbard word =
+ * (up << n_sites) | dn).  Host array of dim entries.  Host only. */
+ecut_status ecut_canonical_positions(const ecut_sectors *s, int64_t *pos);
+
+/* Permute a device vector between canonical order and the bipartite layout
+ * (bip[pos[i]] = canon[i] and back).  In and out must not overlap. */
+ecut_status ecut_import(const ecut_sectors *s, const double *canon_d, double *bip_d, void *stream);
+ecut_status ecut_export(const ecut_sectors *s, const double *bip_d, double *canon_d, void *stream);
+
+/*
+ * y = H psi in the bipartite layout (Eq. 2 with the paper's local products,
+ * its transposed left products and its cross terms evaluated in place):
+ *   Y_q[l,:] = sum_l' H_L[l,l'] Psi_q[l',:]            (left operator, row combination)
+ *            + Psi_q[l,:] H_R^T                        (right operator, in-row gather)
+ *            + (d_L[l] + d_R[r] + diagonal cross terms) Psi_q[l,r]
+ *            + sum_m A_m Psi_k B_m^T                    (sector-changing cross terms)
+ * psi_d, y_d: dim doubles each, must not overlap.  Asynchronous on stream.
+ */
+ecut_status ecut_apply_H(const ecut_sectors *s, const double *psi_d, double *y_d, void *stream);
+
+/*
+ * One launch for n independent applications y_k = H_k psi_k (the sector
+ * work queue over (problem, block, row tile), largest tiles first).  Each
+ * output equals what ecut_apply_H gives for that problem alone, bit for bit.
+ * s, psi_d, y_d: host arrays of n entries.  Uses an internal device
+ * descriptor buffer that the library allocates on first use and grows;
+ * the call synchronises the stream before reusing it.
+ */
+ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
+                               double *const *y_d, void *stream);
+
+/* Options of the Lanczos ground-state solver. */
+typedef struct ecut_lanczos_opts {
+    int32_t max_steps;        /* Krylov steps per restart cycle, >= 1 */
+    int32_t max_restarts;     /* explicit restarts from the current Ritz vector (needs reorth) */
+    int32_t reorth;           /* 0: three-term recurrence; 1: full reorthogonalisation (CGS2) */
+    int32_t fixed_steps;      /* 1: run exactly max_steps (no convergence test) */
+    double tol;               /* stop when the Ritz residual beta_j |s_j| <= tol and the lowest
+                                 Ritz value moved by <= tol over the last step */
+} ecut_lanczos_opts;
+
+typedef struct ecut_lanczos_stats {
+    int32_t steps;            /* total matvecs */
+    int32_t restarts;
+    int32_t converged;
+    int32_t reserved;
+    double residual;          /* last Ritz residual estimate */
+    double seconds;           /* wall time of the solve */
+} ecut_lanczos_stats;
+
+/*
+ * Lowest eigenvalue of H in this sector by Lanczos (the Krylov core the
+ * paper's H*psi serves).  Per step: u = H v_j - beta_{j-1} v_{j-1} with
+ * alpha_j = <v_j,u> fused into the H*psi kernel, w = u - alpha_j v_j,
+ * optional CGS2 against all stored vectors, beta_j = |w|; the tridiagonal
+ * eigenproblem is solved on the host by implicit QL.
+ *   v0_d:    start vector (dim), not modified; must not be zero.
+ *   basis_d: caller-owned device workspace of ecut_lanczos_workspace(s, opts)
+ *            doubles.
+ *   gs_d:    optional (nullable) output ground-state vector (dim); needs reorth=1.
+ *   energy:  host output.  stats: nullable host output.
+ * Synchronises the stream (one small device-to-host copy per step).
+ * Returns ECUT_ENOTCONV (with energy set) if tol was not reached.
+ */
+size_t ecut_lanczos_workspace(const ecut_sectors *s, const ecut_lanczos_opts *opts);
+ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
+                                      const ecut_lanczos_opts *opts, double *energy,
+                                      double *gs_d, ecut_lanczos_stats *stats,
+                                      double *basis_d, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Continuous-batching ground-state server.
+ * A worker thread owns one stream and a device arena of hbm_budget bytes.
+ * Requests are admitted when their footprint (sector metadata + Lanczos
+ * vectors) fits the free arena and a slot is free; all admitted solves
+ * advance together, one batched H*psi launch and one batched vector-update
+ * launch per step; a solve leaves the batch when converged (tol) or at
+ * max_steps, freeing its memory for the next admission.
+ * ------------------------------------------------------------------------- */
+typedef struct ecut_server ecut_server;
+
+typedef struct ecut_server_opts {
+    int32_t max_active;       /* slots; 0 = unlimited */
+    int32_t max_steps;        /* per request */
+    double tol;               /* energy tolerance per request (as ecut_lanczos_opts.tol) */
+    int32_t sequential;       /* 1: one request at a time through ecut_lanczos_ground_state (baseline) */
+    int32_t use_graph;        /* 1: replay the step as a captured HIP graph when the batch is unchanged */
+} ecut_server_opts;
+
+typedef struct ecut_result {
+    uint64_t req_id;
+    int32_t status;           /* ecut_status of the solve */
+    int32_t steps;
+    double energy;
+    double residual;
+    double t_submit;          /* seconds on the server clock */
+    double t_admit;
+    double t_done;
+} ecut_result;
+
+ecut_status ecut_server_create(size_t hbm_budget, const ecut_server_opts *opts, ecut_server **out);
+
+/* Queue one request.  not_before: earliest admission time on the server
+ * clock (seconds since create; <= 0 = now).  v0 is a seeded N(0,1) vector in
+ * canonical order drawn by the server from `seed` (splitmix64 + Box-Muller,
+ * see DESIGN).  The model arrays are copied.  Thread-safe. */
+ecut_status ecut_server_submit(ecut_server *srv, const ecut_model_desc *model, const ecut_cut_desc *cut,
+                               ecut_qnum q, uint64_t seed, double not_before, uint64_t *req_id);
+
+/* Copy up to max finished results; *n_done = number copied (0 -> ECUT_EAGAIN). */
+ecut_status ecut_server_poll(ecut_server *srv, ecut_result *out, int32_t max, int32_t *n_done);
+
+/* Block until every submitted request has finished. */
+ecut_status ecut_server_drain(ecut_server *srv);
+
+/* Server clock (seconds since create). */
+double ecut_server_now(const ecut_server *srv);
+
+void ecut_server_destroy(ecut_server *srv);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ecut_last_error(void);
+
+/* Library version string. */
+const char *ecut_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECUT_H */

@@ -1,0 +1,488 @@
+// C ABI of libecut: handle life cycle, device upload, H*psi, batched H*psi
+// and the canonical <-> bipartite permutations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ecut_internal.h"
+#include "kernels.h"
+#include "runtime.h"
+
+namespace ecut {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+ecut_status fail(ecut_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+ecut_status hip_fail(hipError_t e, const char *what) {
+    return fail(ECUT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- per-device resources
+namespace {
+struct DevRes {
+    uint64_t *binom = nullptr;
+    int n_cu = 0;
+    size_t max_lds = 0;
+    bool lds_set = false;
+};
+std::mutex g_dev_mu;
+std::map<int, DevRes> g_dev;
+}  // namespace
+
+static size_t g_last_max_lds = 0;
+
+ecut_status device_res(int *dev_out, const uint64_t **binom_out, int *n_cu_out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DevRes &R = g_dev[dev];
+    if (!R.binom) {
+        std::vector<uint64_t> t(65 * 65);
+        for (int n = 0; n <= 64; ++n)
+            for (int k = 0; k <= 64; ++k) t[n * 65 + k] = binom(n, k);
+        void *p = nullptr;
+        e = hipMalloc(&p, t.size() * sizeof(uint64_t));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc(binomial table)");
+        e = hipMemcpy(p, t.data(), t.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy(binomial table)");
+        R.binom = (uint64_t *)p;
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        R.n_cu = prop.multiProcessorCount;
+        R.max_lds = prop.sharedMemPerBlock;
+        // Raising the dynamic-LDS cap is only a request: where the runtime
+        // does not take the attribute, launches up to the device limit work
+        // without it, so a refusal is cleared and ignored.
+        e = set_hub_lds_limits((size_t)prop.sharedMemPerBlock > 65536 ? prop.sharedMemPerBlock : 65536);
+        if (e != hipSuccess) (void)hipGetLastError();
+        R.lds_set = e == hipSuccess;
+    }
+    if (dev_out) *dev_out = dev;
+    if (binom_out) *binom_out = R.binom;
+    if (n_cu_out) *n_cu_out = R.n_cu;
+    g_last_max_lds = R.max_lds;
+    return ECUT_OK;
+}
+
+// ---------------------------------------------------------------- upload
+namespace {
+struct Arena {
+    size_t off = 0;
+    struct Piece {
+        size_t off;
+        const void *src;
+        size_t bytes;
+    };
+    std::vector<Piece> pieces;
+    template <class T>
+    size_t add(const std::vector<T> &v) {
+        size_t o = off;
+        size_t b = v.size() * sizeof(T);
+        if (b) pieces.push_back({o, v.data(), b});
+        off += (b + 255) & ~(size_t)255;
+        if (b == 0) off += 256;   // keep a distinct, valid address
+        return o;
+    }
+};
+}  // namespace
+
+void release_device(ecut_sectors *s) {
+    if (s->dev_mem) {
+        int cur = 0;
+        hipGetDevice(&cur);
+        if (s->device >= 0 && s->device != cur) hipSetDevice(s->device);
+        hipFree(s->dev_mem);
+        if (s->device >= 0 && s->device != cur) hipSetDevice(cur);
+    }
+    s->dev_mem = nullptr;
+    s->on_device = false;
+}
+
+ecut_status upload(ecut_sectors *s) {
+    int dev = 0;
+    ecut_status st = device_res(&dev, nullptr, nullptr);
+    if (st != ECUT_OK) return st;
+    Arena A;
+    const size_t o_blocks = A.add(s->blocks);
+    const size_t o_lw = A.add(s->lwords), o_rw = A.add(s->rwords);
+    const size_t o_hlp = A.add(s->hl_ptr), o_hlc = A.add(s->hl_col), o_hlv = A.add(s->hl_val);
+    const size_t o_hrp = A.add(s->hr_ptr), o_hrc = A.add(s->hr_col), o_hrv = A.add(s->hr_val);
+    const size_t o_dl = A.add(s->diag_l), o_dr = A.add(s->diag_r);
+    const size_t o_xd = A.add(s->xdiag), o_xb = A.add(s->xbond), o_maps = A.add(s->maps);
+    const size_t o_items = A.add(s->items);
+    size_t o_lc = 0, o_le = 0, o_lr = 0, o_hc = 0, o_he = 0, o_seg = 0, o_xbh = 0, o_cf = 0, o_u = 0, o_rw16 = 0,
+           o_order = 0;
+    if (s->hub_ok) {
+        o_lc = A.add(s->hub_lo_cnt);
+        o_le = A.add(s->hub_lo_ent);
+        o_lr = A.add(s->hub_lo_rank);
+        o_hc = A.add(s->hub_hi_cnt);
+        o_he = A.add(s->hub_hi_ent);
+        o_seg = A.add(s->hub_seg_off);
+        o_xbh = A.add(s->hub_xb);
+        o_cf = A.add(s->hub_coef);
+        o_u = A.add(s->hub_u);
+        o_rw16 = A.add(s->hub_rw16);
+        o_order = A.add(s->row_order);
+    }
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, A.off);
+    if (e != hipSuccess) return fail(ECUT_ENOMEM, std::string("hipMalloc(sector tables): ") + hipGetErrorString(e));
+    for (auto &p : A.pieces) {
+        e = hipMemcpy((char *)mem + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            hipFree(mem);
+            return hip_fail(e, "hipMemcpy(sector tables)");
+        }
+    }
+    char *b = (char *)mem;
+    ProblemDev &P = s->prob;
+    P = ProblemDev{};
+    P.kind = s->kind;
+    P.n_blocks = (int32_t)s->blocks.size();
+    P.n_xdiag = (int32_t)s->xdiag.size();
+    P.n_xbond = (int32_t)s->xbond.size();
+    P.blocks = (const BlockDev *)(b + o_blocks);
+    P.lwords = (const uint32_t *)(b + o_lw);
+    P.rwords = (const uint32_t *)(b + o_rw);
+    P.hl_ptr = (const int32_t *)(b + o_hlp);
+    P.hl_col = (const int32_t *)(b + o_hlc);
+    P.hl_val = (const double *)(b + o_hlv);
+    P.hr_ptr = (const int32_t *)(b + o_hrp);
+    P.hr_col = (const int32_t *)(b + o_hrc);
+    P.hr_val = (const double *)(b + o_hrv);
+    P.diag_l = (const double *)(b + o_dl);
+    P.diag_r = (const double *)(b + o_dr);
+    P.xdiag = (const XDiagDev *)(b + o_xd);
+    P.xbond = (const XBondDev *)(b + o_xb);
+    P.maps = (const int32_t *)(b + o_maps);
+    P.dim = s->dim;
+    P.xscale = 1.0;
+    s->dev_items = (ItemDev *)(b + o_items);
+    if (s->hub_ok) {
+        HubDev &H = P.hub;
+        H = s->hub;
+        H.lo_cnt = (const int32_t *)(b + o_lc);
+        H.lo_ent = (const int32_t *)(b + o_le);
+        H.lo_rank = (const int32_t *)(b + o_lr);
+        H.hi_cnt = (const int32_t *)(b + o_hc);
+        H.hi_ent = (const int32_t *)(b + o_he);
+        H.seg_off = (const int32_t *)(b + o_seg);
+        H.xb = (const int32_t *)(b + o_xbh);
+        H.coef = (const double *)(b + o_cf);
+        H.u = (const double *)(b + o_u);
+        H.rwords16 = s->hub_rw16.empty() ? nullptr : (const uint16_t *)(b + o_rw16);
+        H.rwords32 = P.rwords + s->blocks[0].rbase;
+        s->dev_row_order = (int32_t *)(b + o_order);
+    }
+    s->dev_mem = mem;
+    s->dev_bytes = A.off;
+    s->device = dev;
+    s->on_device = true;
+    return ECUT_OK;
+}
+
+int32_t max_tile_elems(const ecut_sectors *s) {
+    int64_t m = 0;
+    for (auto &it : s->items) m = std::max<int64_t>(m, (int64_t)(it.row1 - it.row0) * s->blocks[it.block].d_r);
+    return (int32_t)m;
+}
+
+// One application on a stream, with the Lanczos epilogue fields of `P`
+// already filled in by the caller.
+ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t st) {
+    int dev = 0, n_cu = 0;
+    ecut_status rs = device_res(&dev, nullptr, &n_cu);
+    if (rs != ECUT_OK) return rs;
+    hipError_t e;
+    if (s->kernel == 1) {
+        if (hub_lds_bytes(s) > g_last_max_lds)
+            return fail(ECUT_EUNSUPPORTED, "Hubbard kernel tables exceed the device's LDS per work group");
+        const ApplyTuning &T = s->tune;
+        const int n_xcd = T.n_xcd > 0 ? T.n_xcd : 8;
+        const int grid = T.grid > 0 ? T.grid : n_cu;
+        e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
+    } else {
+        e = launch_rows(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (apply_H)");
+    return ECUT_OK;
+}
+
+// number of partial slots the apply kernel writes
+int32_t apply_partial_slots(const ecut_sectors *s) {
+    return s->kernel == 1 ? s->blocks[0].d_l : (int32_t)s->items.size();
+}
+
+// ---------------------------------------------------------------- staging buffers
+ecut_status Staging::reserve(size_t bytes) {
+    int cur = 0;
+    hipGetDevice(&cur);
+    if (device >= 0 && device != cur) release();
+    if (bytes <= cap && dev) return ECUT_OK;
+    ecut_status st = wait();
+    if (st != ECUT_OK) return st;
+    if (dev) hipFree(dev);
+    if (host) hipHostFree(host);
+    dev = host = nullptr;
+    cap = 0;
+    size_t c = 4096;
+    while (c < bytes) c *= 2;
+    hipError_t e = hipMalloc(&dev, c);
+    if (e != hipSuccess) return fail(ECUT_ENOMEM, "hipMalloc(descriptor buffer)");
+    e = hipHostMalloc(&host, c, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(ECUT_ENOMEM, "hipHostMalloc(descriptor staging)");
+    if (!ev) {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    cap = c;
+    device = cur;
+    return ECUT_OK;
+}
+
+ecut_status Staging::wait() {
+    if (pending && ev) {
+        hipError_t e = hipEventSynchronize(ev);
+        pending = false;
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(descriptor buffer)");
+    }
+    return ECUT_OK;
+}
+
+ecut_status Staging::upload(size_t bytes, hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(descriptors)");
+    e = hipEventRecord(ev, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    pending = true;
+    return ECUT_OK;
+}
+
+void Staging::release() {
+    if (pending && ev) hipEventSynchronize(ev);
+    pending = false;
+    if (dev) hipFree(dev);
+    if (host) hipHostFree(host);
+    if (ev) hipEventDestroy(ev);
+    dev = host = nullptr;
+    ev = nullptr;
+    cap = 0;
+    device = -1;
+}
+
+ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items, int tile,
+                              hipStream_t st) {
+    static thread_local Staging S;
+    const size_t pb = (probs.size() * sizeof(ProblemDev) + 255) & ~(size_t)255;
+    const size_t bytes = pb + items.size() * sizeof(ItemDev);
+    ecut_status rs = S.reserve(bytes);
+    if (rs != ECUT_OK) return rs;
+    rs = S.wait();
+    if (rs != ECUT_OK) return rs;
+    std::memcpy(S.host, probs.data(), probs.size() * sizeof(ProblemDev));
+    std::memcpy((char *)S.host + pb, items.data(), items.size() * sizeof(ItemDev));
+    hipError_t e = hipMemcpyAsync(S.dev, S.host, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
+    e = launch_rows((const ProblemDev *)S.dev, probs[0], (const ItemDev *)((char *)S.dev + pb), (int)items.size(), tile,
+                    st);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");
+    e = hipEventRecord(S.ev, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    S.pending = true;
+    return ECUT_OK;
+}
+
+}  // namespace ecut
+
+using namespace ecut;
+
+// ---------------------------------------------------------------- ABI
+extern "C" {
+
+const char *ecut_last_error(void) { return g_err.c_str(); }
+
+const char *ecut_version(void) { return "ecut 0.1 (gfx950)"; }
+
+ecut_status ecut_build_sectors(const ecut_model_desc *model, const ecut_cut_desc *cut, ecut_qnum q, uint32_t flags,
+                               ecut_sectors **out) {
+    if (!out) return fail(ECUT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (flags & ~(uint32_t)ECUT_BUILD_HOST_ONLY) return fail(ECUT_EINVAL, "unknown flags");
+    ecut_sectors *s = new (std::nothrow) ecut_sectors();
+    if (!s) return fail(ECUT_ENOMEM, "host allocation");
+    ecut_status st;
+    try {
+        st = build_host(model, cut, q, s);
+    } catch (const std::bad_alloc &) {
+        st = fail(ECUT_ENOMEM, "host allocation during sector build");
+    }
+    if (st == ECUT_OK && !(flags & ECUT_BUILD_HOST_ONLY)) st = upload(s);
+    if (st != ECUT_OK) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return ECUT_OK;
+}
+
+void ecut_sectors_free(ecut_sectors *s) {
+    if (!s) return;
+    release_device(s);
+    delete s;
+}
+
+ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info) {
+    if (!s || !info) return fail(ECUT_EINVAL, "null argument");
+    ecut_sectors_info I{};
+    I.dim = s->dim;
+    I.n_blocks = (int32_t)s->blocks.size();
+    I.n_left_sites = (int32_t)s->lsites.size();
+    I.n_right_sites = (int32_t)s->rsites.size();
+    I.max_d_r = s->max_d_r;
+    I.n_cut_bonds = s->n_cut_bonds;
+    I.n_cross_offdiag = 2 * (int32_t)s->xbond.size();
+    I.n_cross_diag = (int32_t)s->xdiag.size();
+    I.kernel = s->kernel;
+    I.device_bytes = (int64_t)s->dev_bytes;
+    I.n_eff = s->n_eff;
+    *info = I;
+    return ECUT_OK;
+}
+
+ecut_status ecut_sectors_blocks(const ecut_sectors *s, int64_t *blocks) {
+    if (!s || !blocks) return fail(ECUT_EINVAL, "null argument");
+    for (size_t b = 0; b < s->blocks.size(); ++b) {
+        const BlockDev &B = s->blocks[b];
+        blocks[5 * b + 0] = B.q_l;
+        blocks[5 * b + 1] = B.q_r;
+        blocks[5 * b + 2] = B.d_l;
+        blocks[5 * b + 3] = B.d_r;
+        blocks[5 * b + 4] = B.offset;
+    }
+    return ECUT_OK;
+}
+
+ecut_status ecut_sectors_words(const ecut_sectors *s, int32_t block, uint32_t *l_words, uint32_t *r_words) {
+    if (!s) return fail(ECUT_EINVAL, "null handle");
+    if (block < 0 || block >= (int32_t)s->blocks.size()) return fail(ECUT_EINVAL, "block out of range");
+    const BlockDev &B = s->blocks[block];
+    if (l_words) std::memcpy(l_words, s->lwords.data() + B.lbase, sizeof(uint32_t) * (size_t)B.d_l);
+    if (r_words) std::memcpy(r_words, s->rwords.data() + B.rbase, sizeof(uint32_t) * (size_t)B.d_r);
+    return ECUT_OK;
+}
+
+ecut_status ecut_canonical_positions(const ecut_sectors *s, int64_t *pos) {
+    if (!s || !pos) return fail(ECUT_EINVAL, "null argument");
+    if (s->kind == ECUT_HUBBARD) {
+        for (int64_t i = 0; i < s->dim; ++i) pos[i] = i;
+        return ECUT_OK;
+    }
+    const int qmin = s->blocks[0].q_l;
+    for (int64_t i = 0; i < s->dim; ++i) {
+        const uint64_t w = colex_unrank(i, s->n_up);
+        uint64_t l = 0, r = 0;
+        for (size_t k = 0; k < s->lsites.size(); ++k) l |= ((w >> s->lsites[k]) & 1ull) << k;
+        for (size_t k = 0; k < s->rsites.size(); ++k) r |= ((w >> s->rsites[k]) & 1ull) << k;
+        const BlockDev &B = s->blocks[__builtin_popcountll(l) - qmin];
+        pos[i] = B.offset + colex_rank(l) * B.d_r + colex_rank(r);
+    }
+    return ECUT_OK;
+}
+
+static ecut_status check_dev(const ecut_sectors *s) {
+    if (!s) return fail(ECUT_EINVAL, "null handle");
+    if (!s->on_device) return fail(ECUT_EINVAL, "handle was built with ECUT_BUILD_HOST_ONLY");
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (cur != s->device) return fail(ECUT_EINVAL, "handle lives on another device");
+    return ECUT_OK;
+}
+
+static ecut_status permute(const ecut_sectors *s, const double *in, double *out, bool to_bip, void *stream) {
+    ecut_status st = check_dev(s);
+    if (st != ECUT_OK) return st;
+    if (!in || !out) return fail(ECUT_EINVAL, "null vector");
+    if (in == out) return fail(ECUT_EINVAL, "in and out must differ");
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e;
+    if (s->kind == ECUT_HUBBARD) {
+        e = hipMemcpyAsync(out, in, sizeof(double) * (size_t)s->dim, hipMemcpyDeviceToDevice, hs);
+    } else {
+        const uint64_t *bt = nullptr;
+        st = device_res(nullptr, &bt, nullptr);
+        if (st != ECUT_OK) return st;
+        e = launch_perm(s, bt, s->prob.blocks, in, out, to_bip, hs);
+    }
+    if (e != hipSuccess) return hip_fail(e, to_bip ? "ecut_import" : "ecut_export");
+    return ECUT_OK;
+}
+
+ecut_status ecut_import(const ecut_sectors *s, const double *canon_d, double *bip_d, void *stream) {
+    return permute(s, canon_d, bip_d, true, stream);
+}
+
+ecut_status ecut_export(const ecut_sectors *s, const double *bip_d, double *canon_d, void *stream) {
+    return permute(s, bip_d, canon_d, false, stream);
+}
+
+ecut_status ecut_apply_H(const ecut_sectors *s, const double *psi_d, double *y_d, void *stream) {
+    ecut_status st = check_dev(s);
+    if (st != ECUT_OK) return st;
+    if (!psi_d || !y_d) return fail(ECUT_EINVAL, "null vector");
+    if (psi_d == y_d) return fail(ECUT_EINVAL, "psi and y must not overlap");
+    ProblemDev P = s->prob;
+    P.x = psi_d;
+    P.y = y_d;
+    P.z = nullptr;
+    P.xscale = 1.0;
+    P.zcoef = 0.0;
+    P.partials = nullptr;
+    return launch_apply(s, P, (hipStream_t)stream);
+}
+
+ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
+                               double *const *y_d, void *stream) {
+    if (n < 0 || (n > 0 && (!s || !psi_d || !y_d))) return fail(ECUT_EINVAL, "bad batch arguments");
+    if (n == 0) return ECUT_OK;
+    std::vector<ProblemDev> probs(n);
+    std::vector<ItemDev> items;
+    int32_t tile = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        ecut_status st = check_dev(s[k]);
+        if (st != ECUT_OK) return st;
+        if (!psi_d[k] || !y_d[k] || psi_d[k] == y_d[k]) return fail(ECUT_EINVAL, "bad vector in batch");
+        probs[k] = s[k]->prob;
+        probs[k].x = psi_d[k];
+        probs[k].y = y_d[k];
+        probs[k].z = nullptr;
+        probs[k].xscale = 1.0;
+        probs[k].zcoef = 0.0;
+        probs[k].partials = nullptr;
+        for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
+        tile = std::max(tile, max_tile_elems(s[k]));
+    }
+    // one queue over all problems, largest tiles first (stable: problem order breaks ties)
+    std::stable_sort(items.begin(), items.end(), [&](const ItemDev &a, const ItemDev &b) {
+        const int64_t wa = (int64_t)(a.row1 - a.row0) * s[a.prob]->blocks[a.block].d_r;
+        const int64_t wb = (int64_t)(b.row1 - b.row0) * s[b.prob]->blocks[b.block].d_r;
+        return wa > wb;
+    });
+    return batch_launch_rows(probs, items, tile, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,175 @@
+// Internal structures of libecut: host-side sector description and the
+// device-side descriptors the HIP kernels read.  Not part of the ABI.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ecut.h"
+
+namespace ecut {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+ecut_status fail(ecut_status st, const std::string &msg);
+
+// ---------------------------------------------------------------- ranking
+// Colex (= increasing integer order) ranking of words with a fixed number of
+// set bits: rank(w) = sum_j C(p_j, j+1) over set-bit positions p_0 < p_1 < ...
+// (combinatorial number system).
+uint64_t binom(int n, int k);
+int64_t colex_rank(uint64_t w);
+uint64_t colex_unrank(int64_t idx, int k);
+
+// ---------------------------------------------------------------- device descriptors
+// Everything the H*psi kernels need for one problem lives in one device
+// allocation; ProblemDev holds the pointers into it.  Plain old data so it
+// can sit in device memory for batched launches.
+
+struct BlockDev {
+    int64_t offset;      // first element of the block in the vector
+    int32_t d_l, d_r;    // block shape, row-major [l][r]
+    int32_t q_l, q_r;    // subsystem particle numbers
+    int32_t lbase, rbase;        // first word of count q_l (q_r) in the concatenated L (R) tables
+    int32_t blk_lminus, blk_lplus;   // block with q_l-1 (q_l+1), or -1
+};
+
+// Diagonal cross term coef * f(l_i) * f(r_j); f = n (occupation) or s = n - 1/2.
+struct XDiagDev {
+    int32_t li, rj;
+    int32_t spin_form;   // 1: s*s (spin Sz Sz), 0: n*n (Hubbard U n_up n_dn)
+    int32_t pad;
+    double coef;
+};
+
+// Sector-changing cross term for one cut bond (i in L, j in R), both
+// directions:  coef (S+_i S-_j + S-_i S+_j).
+//   dir A (target l has bit i, r lacks bit j): source block q_l-1,
+//         l' = lmap_del[l], r' = rmap_ins[r]
+//   dir B (target l lacks bit i, r has bit j): source block q_l+1,
+//         l' = lmap_ins[l], r' = rmap_del[r]
+// Map arrays are indexed by the global (concatenated) word index and give
+// the rank inside the target count, or -1.
+struct XBondDev {
+    int32_t li, rj;
+    int32_t lmap_del, lmap_ins;   // offsets into maps[]
+    int32_t rmap_del, rmap_ins;
+    double coef;
+};
+
+// Tables of the Hubbard up/down kernel (row = up word a, column = down word b).
+// The down word is split into lo = bits [0,h) and hi = bits [h,n): the column
+// index is seg_off[hi] + lo_rank[lo], so a hop inside lo moves the column by a
+// lo-only delta, a hop inside hi by a hi-only delta, and only bonds that cross
+// the split need both.
+struct HubDev {
+    int32_t n_r, h;              // down-word bits, split position
+    int32_t lo_stride, hi_stride;   // max neighbour entries per lo / hi word
+    int32_t n_xb;                // crossing bonds
+    int32_t uniform_u;           // 1 if every U_i equals u0
+    int32_t uniform_t;           // 1 if every hop value equals hop0 (then coef index is unused)
+    int32_t n_coef;
+    double u0, hop0;
+    const int32_t *lo_cnt;       // [2^h]
+    const int32_t *lo_ent;       // [2^h][lo_stride] packed (delta << 9) | (neg << 8) | coef_idx
+    const int32_t *lo_rank;      // [2^h]
+    const int32_t *hi_cnt;       // [2^(n-h)]
+    const int32_t *hi_ent;       // [2^(n-h)][hi_stride]
+    const int32_t *seg_off;      // [2^(n-h)] column of (hi, first lo), -1 if the segment is empty
+    const int32_t *xb;           // [n_xb][4]: lo bit, hi bit (relative to h), coef_idx, pad
+    const double *coef;          // [n_coef] hop values (-t_b)
+    const double *u;             // [n_sites] U_i
+    const uint16_t *rwords16;    // [d_r] down words (n_r <= 16) or NULL
+    const uint32_t *rwords32;    // [d_r] down words
+};
+
+struct ProblemDev {
+    int32_t kind;                // ECUT_SPIN_HALF / ECUT_HUBBARD
+    int32_t n_blocks;
+    int32_t n_xdiag, n_xbond;
+    const BlockDev *blocks;
+    const uint32_t *lwords, *rwords;
+    const int32_t *hl_ptr, *hl_col;
+    const double *hl_val;
+    const int32_t *hr_ptr, *hr_col;
+    const double *hr_val;
+    const double *diag_l, *diag_r;
+    const XDiagDev *xdiag;
+    const XBondDev *xbond;
+    const int32_t *maps;
+    HubDev hub;
+    int64_t dim;
+    // per launch (filled by the launcher)
+    const double *x;             // input vector
+    double *y;                   // output vector
+    const double *z;             // Lanczos: previous vector (nullable)
+    double xscale;               // y = xscale * H x - zcoef * z
+    double zcoef;
+    double *partials;            // Lanczos: per-item partial <x, y> (nullable)
+};
+
+// Launch parameters of the Hubbard kernel chosen by the autotuner.
+struct ApplyTuning {
+    int32_t grid;     // work groups (0 = one per CU)
+    int32_t n_xcd;    // XCD-contiguous row chunks (0 = 8)
+    int32_t order;    // row order: 0 increasing, 1 segment-major by level
+    int32_t pad;
+};
+
+// Work item: rows [row0, row1) of block `block` of problem `prob`; `slot`
+// is the item's index in its own problem's item list (the partial-sum slot,
+// independent of what else shares the launch).
+struct ItemDev {
+    int32_t prob, block, row0, row1, slot, pad;
+};
+
+}  // namespace ecut
+
+// ---------------------------------------------------------------- the handle
+struct ecut_sectors {
+    // model
+    int32_t kind, cut_kind, n_sites;
+    uint64_t left_mask;
+    int32_t n_up, n_dn;
+    std::vector<int> lsites, rsites;     // global site of each local bit
+    // blocks
+    std::vector<ecut::BlockDev> blocks;
+    int64_t dim = 0;
+    int32_t max_d_r = 0;
+    // subsystem tables
+    int32_t lcmin = 0, lcmax = -1, rcmin = 0, rcmax = -1;
+    std::vector<int32_t> lcbase, rcbase;  // base of count c at [c - cmin]
+    std::vector<uint32_t> lwords, rwords;
+    std::vector<int32_t> hl_ptr, hl_col, hr_ptr, hr_col;
+    std::vector<double> hl_val, hr_val, diag_l, diag_r;
+    std::vector<ecut::XDiagDev> xdiag;
+    std::vector<ecut::XBondDev> xbond;
+    std::vector<int32_t> maps;
+    int32_t n_cut_bonds = 0;
+    // Hubbard up/down kernel tables (host copies)
+    bool hub_ok = false;
+    ecut::HubDev hub{};
+    std::vector<int32_t> hub_lo_cnt, hub_lo_ent, hub_lo_rank, hub_hi_cnt, hub_hi_ent, hub_seg_off, hub_xb;
+    std::vector<double> hub_coef, hub_u;
+    std::vector<uint16_t> hub_rw16;
+    // default work items of a single application
+    std::vector<ecut::ItemDev> items;
+    std::vector<int32_t> row_order;       // Hubbard kernel: row processing order
+    int32_t kernel = 2;
+    ecut::ApplyTuning tune{};
+    // device side
+    bool on_device = false;
+    int device = -1;
+    void *dev_mem = nullptr;
+    size_t dev_bytes = 0;
+    ecut::ProblemDev prob{};              // pointers into dev_mem
+    ecut::ItemDev *dev_items = nullptr;
+    int32_t *dev_row_order = nullptr;
+    double n_eff = 0.0;
+};
+
+namespace ecut {
+ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qnum q, ecut_sectors *s);
+ecut_status upload(ecut_sectors *s);
+void release_device(ecut_sectors *s);
+}  // namespace ecut

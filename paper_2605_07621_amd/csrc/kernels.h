@@ -1,0 +1,55 @@
+// Launch interface of the HIP kernels (kernels.hip).  Internal.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "ecut_internal.h"
+
+namespace ecut {
+
+constexpr int ROWS_THREADS = 256;
+constexpr size_t ROWS_MAX_LDS = 64 * 1024;   // generic kernel stages tiles up to this size
+constexpr int HUB_THREADS = 1024;
+constexpr int HUB_MAXC = 16;                 // columns per thread: d_R <= HUB_THREADS * HUB_MAXC
+constexpr int VEC_THREADS = 256;
+constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
+constexpr int MAX_BASIS = 1024;              // CGS2: vectors per projection call
+
+// One vector job of the batched Lanczos kernels.
+struct VecJob {
+    const double *x;
+    double *y;
+    int64_t n;
+    double *partials;
+    int32_t n_partials;
+    int32_t mode;            // k_reduce: 0 -> scalars[out] = scale * sum, 1 -> sum
+    double *scalars;
+    int32_t out;
+    int32_t coef_idx;        // k_axpy_norm: y -= scalars[coef_idx] * coef_mul * x
+    double scale;
+    double coef_mul;
+};
+
+size_t hub_lds_bytes(const ecut_sectors *s);
+hipError_t set_hub_lds_limits(size_t bytes);
+hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
+                       int max_tile_elems, hipStream_t st);
+hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
+                      int n_xcd, hipStream_t st);
+hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
+                       double *out, bool to_bip, hipStream_t st);
+hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);
+hipError_t launch_axpy_norm(const VecJob *jobs_d, const int32_t *chunk_job_d, const int32_t *chunk_idx_d, int n_chunks,
+                            hipStream_t st);
+hipError_t launch_multidot(const double *basis, int64_t ld, int nvec, const double *y, int64_t n, double *partials,
+                           int n_chunks, hipStream_t st);
+hipError_t launch_multidot_reduce(const double *partials, int n_chunks, int nvec, const double *scale, double *coef,
+                                  hipStream_t st);
+hipError_t launch_multiaxpy(const double *basis, int64_t ld, int nvec, const double *coef, const double *scale,
+                            double *y, int64_t n, double *partials, int n_chunks, double sign, hipStream_t st);
+hipError_t launch_scale_copy(const double *x, double *y, int64_t n, double a, hipStream_t st);
+hipError_t launch_fill_normal(double *y, int64_t n, uint64_t seed, hipStream_t st);
+
+}  // namespace ecut

@@ -1,0 +1,593 @@
+// HIP kernels for gfx950 (MI355X): bipartite H*psi, permutations between
+// canonical and bipartite order, and the Lanczos vector operations.
+//
+// Layout: every block Psi_q is row-major [l][r] (left word = row, right word
+// = column), blocks back to back.  The left operator H_L therefore combines
+// whole contiguous rows (coalesced reads of other rows), the right operator
+// H_R gathers inside one row, which is staged in LDS first; this replaces the
+// paper's transposition of the blocks before applying left operators.
+//
+// Every output element is written by exactly one thread with a fixed
+// summation order, and every reduction goes through fixed per-item partial
+// slots summed in a fixed order, so results do not depend on the launch
+// shape or on what else shares the launch.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "ecut_internal.h"
+#include "kernels.h"
+
+namespace ecut {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum; result valid in thread 0.  `red` holds one
+// double per wave.
+__device__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// Generic row-tile kernel: any cut, sector-changing cross terms, batches of
+// problems.  One work item = rows [row0,row1) of one block, staged in LDS
+// (STAGE) so the right-operator gathers hit LDS.
+// ------------------------------------------------------------------------
+template <bool STAGE>
+__global__ __launch_bounds__(ROWS_THREADS) void k_rows(const ProblemDev *__restrict__ probs, const ProblemDev single,
+                                                       const ItemDev *__restrict__ items, int n_items) {
+    extern __shared__ __align__(16) double lds[];
+    __shared__ double red[ROWS_THREADS / 64];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const ItemDev W = items[it];
+        const ProblemDev &P = probs ? probs[W.prob] : single;
+        const BlockDev B = P.blocks[W.block];
+        const int dR = B.d_r;
+        const int nrows = W.row1 - W.row0;
+        const int n = nrows * dR;
+        const double *__restrict__ xblk = P.x + B.offset;
+        const double *__restrict__ xt = xblk + (int64_t)W.row0 * dR;
+        if (STAGE) {
+            for (int e = threadIdx.x; e < n; e += blockDim.x) lds[e] = xt[e];
+            __syncthreads();
+        }
+        double part = 0.0;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int lr = e / dR;
+            const int r = e - lr * dR;
+            const int l = W.row0 + lr;
+            const int gl = B.lbase + l, gr = B.rbase + r;
+            const uint32_t lw = P.lwords[gl], rw = P.rwords[gr];
+            const double *xrow = STAGE ? (lds + lr * dR) : (xt + (int64_t)lr * dR);
+            const double xv = xrow[r];
+            double dg = P.diag_l[gl] + P.diag_r[gr];
+            for (int k = 0; k < P.n_xdiag; ++k) {
+                const XDiagDev X = P.xdiag[k];
+                double fl = (double)((lw >> X.li) & 1u), fr = (double)((rw >> X.rj) & 1u);
+                if (X.spin_form) { fl -= 0.5; fr -= 0.5; }
+                dg += X.coef * fl * fr;
+            }
+            double acc = dg * xv;
+            for (int k = P.hr_ptr[gr]; k < P.hr_ptr[gr + 1]; ++k) acc += P.hr_val[k] * xrow[P.hr_col[k]];
+            for (int k = P.hl_ptr[gl]; k < P.hl_ptr[gl + 1]; ++k)
+                acc += P.hl_val[k] * xblk[(int64_t)P.hl_col[k] * dR + r];
+            for (int k = 0; k < P.n_xbond; ++k) {
+                const XBondDev X = P.xbond[k];
+                int src, lp, rp;
+                if ((lw >> X.li) & 1u) {
+                    src = B.blk_lminus;
+                    lp = P.maps[X.lmap_del + gl];
+                    rp = P.maps[X.rmap_ins + gr];
+                } else {
+                    src = B.blk_lplus;
+                    lp = P.maps[X.lmap_ins + gl];
+                    rp = P.maps[X.rmap_del + gr];
+                }
+                if (src >= 0 && lp >= 0 && rp >= 0) {
+                    const BlockDev S = P.blocks[src];
+                    acc += X.coef * P.x[S.offset + (int64_t)lp * S.d_r + rp];
+                }
+            }
+            double yv = P.xscale * acc;
+            const int64_t gi = B.offset + (int64_t)l * dR + r;
+            if (P.z) yv -= P.zcoef * P.z[gi];
+            P.y[gi] = yv;
+            part += xv * yv;
+        }
+        if (P.partials) {
+            const double s = block_sum(part, red);
+            if (threadIdx.x == 0) P.partials[W.slot] = s;
+        } else if (STAGE) {
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Hubbard up/down kernel.  One work group owns one row a (up word) at a
+// time, persistent over a row list.  Phase 1 (global memory only): the left
+// operator H_up as a combination of whole neighbour rows, accumulated in
+// registers, while the own row is staged in LDS.  Phase 2 (LDS only): the
+// right operator H_dn through the lo/hi split tables, the U n_up n_dn
+// diagonal, the Lanczos epilogue and the store.
+// ------------------------------------------------------------------------
+template <bool UU, bool UT, bool W16>
+__global__ __launch_bounds__(HUB_THREADS) void k_hub(const ProblemDev P, const int32_t *__restrict__ rows, int n_rows,
+                                                     int n_xcd, int per_xcd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[HUB_THREADS / 64];
+    const HubDev &H = P.hub;
+    const int dR = P.blocks[0].d_r;
+    const int h = H.h;
+    const int nlo = 1 << h, nhi = 1 << (H.n_r - h);
+    const int ls = H.lo_stride, hs = H.hi_stride;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        unsigned char *p = smem + off;
+        off += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    double *xs = (double *)carve((size_t)dR * 8);
+    uint16_t *ws16 = nullptr;
+    uint32_t *ws32 = nullptr;
+    if (W16) ws16 = (uint16_t *)carve((size_t)dR * 2);
+    else ws32 = (uint32_t *)carve((size_t)dR * 4);
+    int32_t *locnt = (int32_t *)carve((size_t)nlo * 4);
+    int32_t *loent = (int32_t *)carve((size_t)nlo * ls * 4);
+    int32_t *lorank = (int32_t *)carve((size_t)nlo * 4);
+    int32_t *hicnt = (int32_t *)carve((size_t)nhi * 4);
+    int32_t *hient = (int32_t *)carve((size_t)nhi * hs * 4);
+    int32_t *seg = (int32_t *)carve((size_t)nhi * 4);
+    double *cf = (double *)carve((size_t)(H.n_coef > 0 ? H.n_coef : 1) * 8);
+    double *ut = UU ? nullptr : (double *)carve(3 * 256 * 8);
+
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    for (int i = tid; i < dR; i += nt) {
+        if (W16) ws16[i] = H.rwords16[i];
+        else ws32[i] = H.rwords32[i];
+    }
+    for (int i = tid; i < nlo; i += nt) { locnt[i] = H.lo_cnt[i]; lorank[i] = H.lo_rank[i]; }
+    for (int i = tid; i < nlo * ls; i += nt) loent[i] = H.lo_ent[i];
+    for (int i = tid; i < nhi; i += nt) { hicnt[i] = H.hi_cnt[i]; seg[i] = H.seg_off[i]; }
+    for (int i = tid; i < nhi * hs; i += nt) hient[i] = H.hi_ent[i];
+    for (int i = tid; i < H.n_coef; i += nt) cf[i] = H.coef[i];
+
+    const int xcd = blockIdx.x % n_xcd;
+    const int slot = blockIdx.x / n_xcd;
+    const int nslot = gridDim.x / n_xcd;
+    const double *__restrict__ X = P.x;
+    for (int k = slot; k < per_xcd; k += nslot) {
+        const int idx = xcd * per_xcd + k;
+        if (idx >= n_rows) break;
+        const int a = rows[idx];
+        const uint32_t aw = P.lwords[a];
+        const int p0 = P.hl_ptr[a], p1 = P.hl_ptr[a + 1];
+        const double *__restrict__ xa = X + (int64_t)a * dR;
+        double acc[HUB_MAXC];
+#pragma unroll
+        for (int c = 0; c < HUB_MAXC; ++c) acc[c] = 0.0;
+        // phase 1: neighbour rows of the left operator (global, coalesced)
+        for (int q = p0; q < p1; ++q) {
+            const double v = P.hl_val[q];
+            const double *__restrict__ xn = X + (int64_t)P.hl_col[q] * dR;
+#pragma unroll
+            for (int c = 0; c < HUB_MAXC; ++c) {
+                const int r = tid + c * HUB_THREADS;
+                if (r < dR) acc[c] += v * xn[r];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < HUB_MAXC; ++c) {
+            const int r = tid + c * HUB_THREADS;
+            if (r < dR) xs[r] = xa[r];
+        }
+        if (!UU) {
+            for (int i = tid; i < 3 * 256; i += nt) {
+                const int byte = i >> 8, v = i & 255;
+                double s = 0.0;
+                for (int b = 0; b < 8; ++b) {
+                    const int site = byte * 8 + b;
+                    if (site < H.n_r && ((v >> b) & 1) && ((aw >> site) & 1u)) s += H.u[site];
+                }
+                ut[i] = s;
+            }
+        }
+        __syncthreads();
+        // phase 2: right operator in LDS, diagonal, epilogue
+        const double dl = P.diag_l[a];
+        double part = 0.0;
+#pragma unroll
+        for (int c = 0; c < HUB_MAXC; ++c) {
+            const int r = tid + c * HUB_THREADS;
+            if (r < dR) {
+                const uint32_t w = W16 ? (uint32_t)ws16[r] : ws32[r];
+                const int lo = (int)(w & (uint32_t)(nlo - 1));
+                const int hi = (int)(w >> h);
+                const double xv = xs[r];
+                double dg = dl;
+                if (UU) dg += H.u0 * (double)__popc(aw & w);
+                else dg += ut[w & 255u] + ut[256 + ((w >> 8) & 255u)] + ut[512 + ((w >> 16) & 255u)];
+                double s = dg * xv;
+                {
+                    const int n = locnt[lo];
+                    const int32_t *e = loent + lo * ls;
+                    for (int q = 0; q < n; ++q) {
+                        const int en = e[q];
+                        double v = UT ? H.hop0 : cf[en & 255];
+                        if (en & 256) v = -v;
+                        s += v * xs[r + (en >> 9)];
+                    }
+                }
+                {
+                    const int n = hicnt[hi];
+                    const int32_t *e = hient + hi * hs;
+                    for (int q = 0; q < n; ++q) {
+                        const int en = e[q];
+                        double v = UT ? H.hop0 : cf[en & 255];
+                        if (en & 256) v = -v;
+                        s += v * xs[r + (en >> 9)];
+                    }
+                }
+                for (int q = 0; q < H.n_xb; ++q) {
+                    const int lb = H.xb[4 * q], hb = H.xb[4 * q + 1];
+                    if (((lo >> lb) & 1) != ((hi >> hb) & 1)) {
+                        const int lo2 = lo ^ (1 << lb), hi2 = hi ^ (1 << hb);
+                        const int col = seg[hi2] + lorank[lo2];
+                        const int par = __popc((uint32_t)lo & ~((2u << lb) - 1u)) + __popc((uint32_t)hi & ((1u << hb) - 1u));
+                        double v = UT ? H.hop0 : cf[H.xb[4 * q + 2]];
+                        if (par & 1) v = -v;
+                        s += v * xs[col];
+                    }
+                }
+                const int64_t gi = (int64_t)a * dR + r;
+                double y = P.xscale * (acc[c] + s);
+                if (P.z) y -= P.zcoef * P.z[gi];
+                P.y[gi] = y;
+                part += xv * y;
+            }
+        }
+        if (P.partials) {
+            const double s = block_sum(part, red);
+            if (tid == 0) P.partials[a] = s;
+        } else {
+            __syncthreads();
+        }
+    }
+}
+
+size_t hub_lds_bytes(const ecut_sectors *s) {
+    const HubDev &H = s->hub;
+    const int dR = s->blocks[0].d_r;
+    const int nlo = 1 << H.h, nhi = 1 << (H.n_r - H.h);
+    auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    size_t b = al((size_t)dR * 8) + al((size_t)dR * (H.n_r <= 16 ? 2 : 4));
+    b += al((size_t)nlo * 4) * 2 + al((size_t)nlo * H.lo_stride * 4);
+    b += al((size_t)nhi * 4) * 2 + al((size_t)nhi * H.hi_stride * 4);
+    b += al((size_t)(H.n_coef > 0 ? H.n_coef : 1) * 8);
+    if (!H.uniform_u) b += 3 * 256 * 8;
+    return b;
+}
+
+// ------------------------------------------------------------------------
+// canonical <-> bipartite permutations (spin spatial cut).  The canonical
+// index is unranked into the full word, split by the cut mask, and the two
+// halves ranked again.
+// ------------------------------------------------------------------------
+struct PermDev {
+    const uint64_t *binom;    // [65][65]
+    const BlockDev *blocks;
+    uint64_t left_mask;
+    int32_t n_sites, n_up, qmin, pad;
+};
+
+__device__ __forceinline__ uint64_t dbinom(const uint64_t *bt, int n, int k) {
+    return (k < 0 || k > n) ? 0ull : bt[n * 65 + k];
+}
+
+__device__ int64_t d_canon_to_pos(const PermDev &D, int64_t idx) {
+    // unrank the canonical index into the full word (colex)
+    uint64_t w = 0;
+    int p = D.n_sites - 1;
+    for (int j = D.n_up; j >= 1; --j) {
+        while (p >= j && (int64_t)dbinom(D.binom, p, j) > idx) --p;
+        w |= 1ull << p;
+        idx -= (int64_t)dbinom(D.binom, p, j);
+        --p;
+    }
+    // split and rank both halves
+    int64_t rl = 0, rr = 0;
+    int kl = 0, kr = 0, bl = 0, br = 0;
+    for (int s = 0; s < D.n_sites; ++s) {
+        const bool set = (w >> s) & 1ull;
+        if ((D.left_mask >> s) & 1ull) {
+            if (set) { ++kl; rl += (int64_t)dbinom(D.binom, bl, kl); }
+            ++bl;
+        } else {
+            if (set) { ++kr; rr += (int64_t)dbinom(D.binom, br, kr); }
+            ++br;
+        }
+    }
+    const BlockDev B = D.blocks[kl - D.qmin];
+    return B.offset + rl * B.d_r + rr;
+}
+
+__global__ void k_import(PermDev D, const double *__restrict__ canon, double *__restrict__ bip, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        bip[d_canon_to_pos(D, i)] = canon[i];
+}
+
+__global__ void k_export(PermDev D, const double *__restrict__ bip, double *__restrict__ canon, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        canon[i] = bip[d_canon_to_pos(D, i)];
+}
+
+// ------------------------------------------------------------------------
+// Lanczos vector kernels.  A "segment set" describes one vector per problem
+// for batched launches: seg k covers [0, n_k) of vectors x_k, y_k.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(VEC_THREADS) void k_reduce(const VecJob *__restrict__ jobs, int n_jobs) {
+    __shared__ double red[VEC_THREADS / 64];
+    const int j = blockIdx.x;
+    if (j >= n_jobs) return;
+    const VecJob J = jobs[j];
+    double s = 0.0;
+    // fixed assignment of partial slots to threads, then a fixed-order block sum
+    for (int i = threadIdx.x; i < J.n_partials; i += blockDim.x) s += J.partials[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        if (J.mode == 0) J.scalars[J.out] = J.scale * s;
+        else J.scalars[J.out] = s;
+    }
+}
+
+// y <- y - (scalars[coef_idx] * coef_mul) * x ; partials[chunk] = sum y^2
+__global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restrict__ jobs, const int32_t *__restrict__ chunk_job,
+                                                           const int32_t *__restrict__ chunk_idx, int n_chunks) {
+    __shared__ double red[VEC_THREADS / 64];
+    for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const VecJob J = jobs[chunk_job[c]];
+        const int ci = chunk_idx[c];
+        const int64_t i0 = (int64_t)ci * VEC_CHUNK;
+        const int64_t i1 = i0 + VEC_CHUNK < J.n ? i0 + VEC_CHUNK : J.n;
+        const double a = J.scalars[J.coef_idx] * J.coef_mul;
+        double s = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            const double v = J.y[i] - a * J.x[i];
+            J.y[i] = v;
+            s += v * v;
+        }
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) J.partials[ci] = s;
+    }
+}
+
+// Classical Gram-Schmidt, dot phase: partials[k * n_chunks + chunk] = <w_k, y> over the chunk.
+__global__ __launch_bounds__(VEC_THREADS) void k_multidot(const double *__restrict__ basis, int64_t ld, int nvec,
+                                                          const double *__restrict__ y, int64_t n,
+                                                          double *__restrict__ partials, int n_chunks) {
+    __shared__ double red[VEC_THREADS / 64];
+    for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const int64_t i0 = (int64_t)c * VEC_CHUNK;
+        const int64_t i1 = i0 + VEC_CHUNK < n ? i0 + VEC_CHUNK : n;
+        for (int k = 0; k < nvec; k += 8) {
+            double s[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s[q] = 0.0;
+            for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+                const double yv = y[i];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (k + q < nvec) s[q] += basis[(int64_t)(k + q) * ld + i] * yv;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (k + q < nvec) {
+                    const double t = block_sum(s[q], red);
+                    if (threadIdx.x == 0) partials[(int64_t)(k + q) * n_chunks + c] = t;
+                }
+            }
+        }
+    }
+}
+
+// coef[k] = scale_k * sum_chunks partials[k][*]  (fixed order)
+__global__ __launch_bounds__(VEC_THREADS) void k_multidot_reduce(const double *__restrict__ partials, int n_chunks,
+                                                                 const double *__restrict__ scale, double *__restrict__ coef) {
+    __shared__ double red[VEC_THREADS / 64];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n_chunks; i += blockDim.x) s += partials[(int64_t)k * n_chunks + i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) coef[k] = s * scale[k];
+}
+
+// y <- y - sum_k coef[k] * scale_k * w_k ; optional norm partials
+__global__ __launch_bounds__(VEC_THREADS) void k_multiaxpy(const double *__restrict__ basis, int64_t ld, int nvec,
+                                                           const double *__restrict__ coef, const double *__restrict__ scale,
+                                                           double *__restrict__ y, int64_t n, double *__restrict__ partials,
+                                                           int n_chunks, double sign) {
+    __shared__ double red[VEC_THREADS / 64];
+    __shared__ double cs[MAX_BASIS];
+    for (int k = threadIdx.x; k < nvec; k += blockDim.x) cs[k] = coef[k] * scale[k];
+    __syncthreads();
+    for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const int64_t i0 = (int64_t)c * VEC_CHUNK;
+        const int64_t i1 = i0 + VEC_CHUNK < n ? i0 + VEC_CHUNK : n;
+        double s = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            double v = 0.0;
+            for (int k = 0; k < nvec; ++k) v += cs[k] * basis[(int64_t)k * ld + i];
+            const double yv = (sign != 0.0) ? y[i] - v : v;
+            y[i] = yv;
+            s += yv * yv;
+        }
+        if (partials) {
+            s = block_sum(s, red);
+            if (threadIdx.x == 0) partials[c] = s;
+        }
+    }
+}
+
+// y <- a * x (a from scalars[idx] or host value when scalars == NULL)
+__global__ void k_scale_copy(const double *__restrict__ x, double *__restrict__ y, int64_t n, double a) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = a * x[i];
+}
+
+// Seeded N(0,1) vector: splitmix64 of (seed, index) -> two uniforms -> Box-Muller.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_fill_normal(double *__restrict__ y, int64_t n, uint64_t seed) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = splitmix64(seed ^ splitmix64(2 * (uint64_t)i));
+        const uint64_t b = splitmix64(seed ^ splitmix64(2 * (uint64_t)i + 1));
+        const double u1 = ((double)(a >> 11) + 1.0) * (1.0 / 9007199254740993.0);   // (0,1]
+        const double u2 = (double)(b >> 11) * (1.0 / 9007199254740992.0);           // [0,1)
+        y[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    }
+}
+
+// ------------------------------------------------------------------------
+// host launchers
+// ------------------------------------------------------------------------
+hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
+                       int max_tile_elems, hipStream_t st) {
+    if (n_items <= 0) return hipSuccess;
+    const bool stage = (size_t)max_tile_elems * 8 <= ROWS_MAX_LDS;
+    int grid = n_items < 65536 ? n_items : 65536;
+    if (stage) {
+        const size_t lds = (size_t)max_tile_elems * 8;
+        hipLaunchKernelGGL(k_rows<true>, dim3(grid), dim3(ROWS_THREADS), lds, st, probs_d, single, items_d, n_items);
+    } else {
+        hipLaunchKernelGGL(k_rows<false>, dim3(grid), dim3(ROWS_THREADS), 0, st, probs_d, single, items_d, n_items);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
+                      int n_xcd, hipStream_t st) {
+    const size_t lds = hub_lds_bytes(s);
+    if (grid % n_xcd) grid = (grid / n_xcd) * n_xcd;
+    if (grid < n_xcd) grid = n_xcd;
+    const int per_xcd = (n_rows + n_xcd - 1) / n_xcd;
+    const HubDev &H = s->hub;
+    const bool w16 = H.n_r <= 16;
+#define ECUT_HUB_LAUNCH(UU, UT, W)                                                                        \
+    hipLaunchKernelGGL((k_hub<UU, UT, W>), dim3(grid), dim3(HUB_THREADS), lds, st, prob, rows_d, n_rows,  \
+                       n_xcd, per_xcd)
+    if (H.uniform_u && H.uniform_t && w16) ECUT_HUB_LAUNCH(true, true, true);
+    else if (H.uniform_u && H.uniform_t) ECUT_HUB_LAUNCH(true, true, false);
+    else if (w16) ECUT_HUB_LAUNCH(false, false, true);
+    else ECUT_HUB_LAUNCH(false, false, false);
+#undef ECUT_HUB_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t set_hub_lds_limits(size_t bytes) {
+    hipError_t e = hipSuccess;
+    const int b = (int)bytes;
+    e = hipFuncSetAttribute((const void *)k_hub<true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub<true, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub<false, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub<false, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ROWS_MAX_LDS);
+}
+
+hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
+                       double *out, bool to_bip, hipStream_t st) {
+    PermDev D{};
+    D.binom = binom_d;
+    D.blocks = blocks_d;
+    D.left_mask = s->left_mask;
+    D.n_sites = s->n_sites;
+    D.n_up = s->n_up;
+    D.qmin = s->blocks[0].q_l;
+    const int64_t n = s->dim;
+    int grid = (int)((n + 255) / 256);
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    if (to_bip) hipLaunchKernelGGL(k_import, dim3(grid), dim3(256), 0, st, D, in, out, n);
+    else hipLaunchKernelGGL(k_export, dim3(grid), dim3(256), 0, st, D, in, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st) {
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3(n_jobs), dim3(VEC_THREADS), 0, st, jobs_d, n_jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_norm(const VecJob *jobs_d, const int32_t *chunk_job_d, const int32_t *chunk_idx_d, int n_chunks,
+                            hipStream_t st) {
+    if (n_chunks <= 0) return hipSuccess;
+    int grid = n_chunks < 8192 ? n_chunks : 8192;
+    hipLaunchKernelGGL(k_axpy_norm, dim3(grid), dim3(VEC_THREADS), 0, st, jobs_d, chunk_job_d, chunk_idx_d, n_chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot(const double *basis, int64_t ld, int nvec, const double *y, int64_t n, double *partials,
+                           int n_chunks, hipStream_t st) {
+    int grid = n_chunks < 8192 ? n_chunks : 8192;
+    hipLaunchKernelGGL(k_multidot, dim3(grid), dim3(VEC_THREADS), 0, st, basis, ld, nvec, y, n, partials, n_chunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_multidot_reduce(const double *partials, int n_chunks, int nvec, const double *scale, double *coef,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(VEC_THREADS), 0, st, partials, n_chunks, scale, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy(const double *basis, int64_t ld, int nvec, const double *coef, const double *scale,
+                            double *y, int64_t n, double *partials, int n_chunks, double sign, hipStream_t st) {
+    int grid = n_chunks < 8192 ? n_chunks : 8192;
+    hipLaunchKernelGGL(k_multiaxpy, dim3(grid), dim3(VEC_THREADS), 0, st, basis, ld, nvec, coef, scale, y, n, partials,
+                       n_chunks, sign);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(const double *x, double *y, int64_t n, double a, hipStream_t st) {
+    int grid = (int)((n + 255) / 256);
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid), dim3(256), 0, st, x, y, n, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_normal(double *y, int64_t n, uint64_t seed, hipStream_t st) {
+    int grid = (int)((n + 255) / 256);
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_fill_normal, dim3(grid), dim3(256), 0, st, y, n, seed);
+    return hipGetLastError();
+}
+
+}  // namespace ecut

@@ -1,0 +1,430 @@
+// Lanczos ground-state solver on the device (Paige's ordering):
+//   u = H v_j - beta_{j-1} v_{j-1}, alpha_j = <v_j, u>   (fused into H*psi)
+//   w = u - alpha_j v_j, beta_j = |w|                    (one fused pass)
+//   optional CGS2 against all stored vectors
+// Vectors are kept unnormalised (v_j = s_j w_j) so no scaling pass is needed;
+// the scales enter the next H*psi and the updates as factors.  The tridiagonal
+// eigenproblem is solved on the host every step (implicit QL + inverse
+// iteration) for the lowest Ritz value and its residual beta_j |u_j|.
+#include "lanczos.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+#include "tridiag.h"
+
+namespace ecut {
+
+static int64_t n_chunks_of(int64_t n) { return (n + VEC_CHUNK - 1) / VEC_CHUNK; }
+
+size_t lz_workspace_doubles(const ecut_sectors *s, bool reorth, int keep) {
+    const int64_t n = s->dim;
+    const int64_t nc = n_chunks_of(n);
+    auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
+    int64_t d = 0;
+    d += reorth ? al(n) * (keep + 1) : al(n) * 3;
+    d += al(apply_partial_slots(s));
+    d += al(nc);
+    if (reorth) d += al(nc * keep) + 2 * al(MAX_BASIS);
+    d += 32;
+    return (size_t)d;
+}
+
+void lz_carve(LzSolve &L, const ecut_sectors *s, bool reorth, int keep, double *ws) {
+    const int64_t n = s->dim;
+    const int64_t nc = n_chunks_of(n);
+    auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
+    L.s = s;
+    L.n = n;
+    L.reorth = reorth;
+    L.keep = keep;
+    double *p = ws;
+    if (reorth) {
+        L.basis = p;
+        p += al(n) * (keep + 1);
+        // the basis stride is al(n); keep n as the logical length
+    } else {
+        for (int k = 0; k < 3; ++k) { L.ring[k] = p; p += al(n); }
+    }
+    L.n_apply = apply_partial_slots(s);
+    L.part_apply = p;
+    p += al(L.n_apply);
+    L.n_chunks = (int32_t)nc;
+    L.part_norm = p;
+    p += al(nc);
+    if (reorth) {
+        L.part_cgs = p;
+        p += al(nc * keep);
+        L.dcoef = p;
+        p += al(MAX_BASIS);
+        L.dscale = p;
+        p += al(MAX_BASIS);
+    }
+    L.scal = p;
+}
+
+static int64_t basis_ld(const LzSolve &L) { return (L.n + 31) & ~(int64_t)31; }
+
+// x/y/z addresses honour the padded basis stride
+static double *slot(const LzSolve &L, int k) { return L.basis + (int64_t)k * basis_ld(L); }
+static double *xvec(const LzSolve &L) { return L.reorth ? slot(L, L.j) : L.ring[L.j % 3]; }
+static double *yvec(const LzSolve &L) { return L.reorth ? slot(L, L.j + 1) : L.ring[(L.j + 1) % 3]; }
+static double *zvec(const LzSolve &L) {
+    return L.j == 0 ? nullptr : (L.reorth ? slot(L, L.j - 1) : L.ring[(L.j + 2) % 3]);
+}
+
+// ---------------------------------------------------------------- descriptor packing
+namespace {
+struct Pack {
+    std::vector<char> buf;
+    template <class T>
+    size_t put(const std::vector<T> &v) {
+        size_t o = (buf.size() + 255) & ~(size_t)255;
+        buf.resize(o + v.size() * sizeof(T));
+        if (!v.empty()) std::memcpy(buf.data() + o, v.data(), v.size() * sizeof(T));
+        return o;
+    }
+};
+}  // namespace
+
+static ecut_status run_norm_jobs(std::vector<LzSolve *> &act, const std::vector<double *> &vecs, hipStream_t st,
+                                 Staging &stg) {
+    // scal[1] <- |v|^2 for each solve via an axpy with zero coefficient
+    std::vector<VecJob> jn, jr;
+    std::vector<int32_t> cj, ci;
+    for (size_t k = 0; k < act.size(); ++k) {
+        LzSolve &L = *act[k];
+        VecJob J{};
+        J.x = vecs[k];
+        J.y = vecs[k];
+        J.n = L.n;
+        J.partials = L.part_norm;
+        J.scalars = L.scal;
+        J.coef_idx = 0;
+        J.coef_mul = 0.0;
+        jn.push_back(J);
+        for (int32_t c = 0; c < L.n_chunks; ++c) { cj.push_back((int32_t)k); ci.push_back(c); }
+        VecJob R{};
+        R.partials = L.part_norm;
+        R.n_partials = L.n_chunks;
+        R.mode = 1;
+        R.scalars = L.scal;
+        R.out = 1;
+        jr.push_back(R);
+    }
+    Pack P;
+    size_t o_jn = P.put(jn), o_jr = P.put(jr), o_cj = P.put(cj), o_ci = P.put(ci);
+    ecut_status rs = stg.reserve(P.buf.size());
+    if (rs != ECUT_OK) return rs;
+    rs = stg.wait();
+    if (rs != ECUT_OK) return rs;
+    std::memcpy(stg.host, P.buf.data(), P.buf.size());
+    rs = stg.upload(P.buf.size(), st);
+    if (rs != ECUT_OK) return rs;
+    char *d = (char *)stg.dev;
+    hipError_t e = launch_axpy_norm((const VecJob *)(d + o_jn), (const int32_t *)(d + o_cj), (const int32_t *)(d + o_ci),
+                                    (int)cj.size(), st);
+    if (e == hipSuccess) e = launch_reduce((const VecJob *)(d + o_jr), (int)jr.size(), st);
+    if (e != hipSuccess) return hip_fail(e, "lanczos norm");
+    for (LzSolve *L : act) {
+        e = hipMemcpyAsync(L->host_scal, L->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(scalars)");
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (lanczos norm)");
+    stg.pending = false;
+    return ECUT_OK;
+}
+
+ecut_status lz_start(std::vector<LzSolve *> &solves, const std::vector<const double *> &v0, hipStream_t st,
+                     Staging &stg) {
+    std::vector<double *> xs;
+    std::vector<LzSolve *> act;
+    for (size_t k = 0; k < solves.size(); ++k) {
+        LzSolve &L = *solves[k];
+        L.j = 0;
+        L.a.clear();
+        L.b.clear();
+        L.sc.clear();
+        double *x0 = L.reorth ? slot(L, 0) : L.ring[0];
+        if (v0[k] && v0[k] != x0) {
+            hipError_t e = hipMemcpyAsync(x0, v0[k], sizeof(double) * (size_t)L.n, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(v0)");
+        }
+        static const double zero[2] = {0.0, 0.0};
+        hipError_t e = hipMemcpyAsync(L.scal, zero, sizeof(zero), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(scal init)");
+        xs.push_back(x0);
+        act.push_back(&L);
+    }
+    ecut_status rs = run_norm_jobs(act, xs, st, stg);
+    if (rs != ECUT_OK) return rs;
+    for (LzSolve *L : act) {
+        const double nrm = std::sqrt(L->host_scal[1]);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) {
+            L->done = true;
+            L->status = fail(ECUT_EINVAL, "start vector is zero or not finite");
+            continue;
+        }
+        L->s_cur = 1.0 / nrm;
+        L->s_prev = 0.0;
+        L->beta_prev = 0.0;
+        L->sc.push_back(L->s_cur);
+    }
+    return ECUT_OK;
+}
+
+ecut_status lz_ritz_vector(LzSolve &L, double *out, hipStream_t st, Staging &stg) {
+    if (!L.reorth) return fail(ECUT_EUNSUPPORTED, "Ritz vector needs full reorthogonalisation");
+    const int m = (int)L.a.size();
+    std::vector<double> e(L.b.begin(), L.b.begin() + (m > 0 ? m - 1 : 0));
+    const std::vector<double> ev = tridiag_eigenvalues(L.a, e);
+    const std::vector<double> u = tridiag_eigenvector(L.a, e, ev[0]);
+    Pack P;
+    std::vector<double> scv(L.sc.begin(), L.sc.begin() + m);
+    size_t o_c = P.put(u), o_s = P.put(scv);
+    ecut_status rs = stg.reserve(P.buf.size());
+    if (rs != ECUT_OK) return rs;
+    rs = stg.wait();
+    if (rs != ECUT_OK) return rs;
+    std::memcpy(stg.host, P.buf.data(), P.buf.size());
+    rs = stg.upload(P.buf.size(), st);
+    if (rs != ECUT_OK) return rs;
+    char *d = (char *)stg.dev;
+    hipError_t er = launch_multiaxpy(L.basis, basis_ld(L), m, (const double *)(d + o_c), (const double *)(d + o_s), out,
+                                     L.n, nullptr, L.n_chunks, 0.0, st);
+    if (er != hipSuccess) return hip_fail(er, "Ritz vector");
+    return ECUT_OK;
+}
+
+ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg) {
+    std::vector<LzSolve *> act;
+    for (LzSolve *L : solves)
+        if (!L->done) act.push_back(L);
+    if (act.empty()) return ECUT_OK;
+    // 1. u = s_j H w_j - beta_{j-1} s_{j-1} w_{j-1}, alpha partials
+    std::vector<ProblemDev> rows_probs;
+    std::vector<const ecut_sectors *> rows_s;
+    std::vector<ItemDev> rows_items;
+    int rows_tile = 0;
+    for (LzSolve *L : act) {
+        ProblemDev P = L->s->prob;
+        P.x = xvec(*L);
+        P.y = yvec(*L);
+        P.z = zvec(*L);
+        P.xscale = L->s_cur;
+        P.zcoef = L->beta_prev * L->s_prev;
+        P.partials = L->part_apply;
+        if (L->s->kernel == 1 || act.size() == 1) {
+            ecut_status rs = launch_apply(L->s, P, st);
+            if (rs != ECUT_OK) return rs;
+        } else {
+            const int32_t pi = (int32_t)rows_probs.size();
+            rows_probs.push_back(P);
+            rows_s.push_back(L->s);
+            for (const ItemDev &it : L->s->items) rows_items.push_back(ItemDev{pi, it.block, it.row0, it.row1, it.slot, 0});
+            rows_tile = std::max(rows_tile, max_tile_elems(L->s));
+        }
+    }
+    if (!rows_items.empty()) {
+        // one work queue over every problem, largest tiles first
+        std::stable_sort(rows_items.begin(), rows_items.end(), [&](const ItemDev &a, const ItemDev &b) {
+            const int64_t wa = (int64_t)(a.row1 - a.row0) * rows_s[a.prob]->blocks[a.block].d_r;
+            const int64_t wb = (int64_t)(b.row1 - b.row0) * rows_s[b.prob]->blocks[b.block].d_r;
+            return wa > wb;
+        });
+        ecut_status rs = batch_launch_rows(rows_probs, rows_items, rows_tile, st);
+        if (rs != ECUT_OK) return rs;
+    }
+    // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2
+    std::vector<VecJob> ja, jx, jb;
+    std::vector<int32_t> cj, ci;
+    for (size_t k = 0; k < act.size(); ++k) {
+        LzSolve &L = *act[k];
+        VecJob A{};
+        A.partials = L.part_apply;
+        A.n_partials = L.n_apply;
+        A.mode = 0;
+        A.scalars = L.scal;
+        A.out = 0;
+        A.scale = L.s_cur;
+        ja.push_back(A);
+        VecJob X{};
+        X.x = xvec(L);
+        X.y = yvec(L);
+        X.n = L.n;
+        X.partials = L.part_norm;
+        X.scalars = L.scal;
+        X.coef_idx = 0;
+        X.coef_mul = L.s_cur;
+        jx.push_back(X);
+        for (int32_t c = 0; c < L.n_chunks; ++c) { cj.push_back((int32_t)k); ci.push_back(c); }
+        VecJob B{};
+        B.partials = L.part_norm;
+        B.n_partials = L.n_chunks;
+        B.mode = 1;
+        B.scalars = L.scal;
+        B.out = 1;
+        jb.push_back(B);
+    }
+    Pack P;
+    const size_t o_ja = P.put(ja), o_jx = P.put(jx), o_jb = P.put(jb), o_cj = P.put(cj), o_ci = P.put(ci);
+    size_t o_sc = 0;
+    LzSolve *R = (act.size() == 1 && act[0]->reorth) ? act[0] : nullptr;
+    if (R) o_sc = P.put(R->sc);
+    ecut_status rs = stg.reserve(P.buf.size());
+    if (rs != ECUT_OK) return rs;
+    rs = stg.wait();
+    if (rs != ECUT_OK) return rs;
+    std::memcpy(stg.host, P.buf.data(), P.buf.size());
+    rs = stg.upload(P.buf.size(), st);
+    if (rs != ECUT_OK) return rs;
+    char *d = (char *)stg.dev;
+    hipError_t e = launch_reduce((const VecJob *)(d + o_ja), (int)ja.size(), st);
+    if (e == hipSuccess)
+        e = launch_axpy_norm((const VecJob *)(d + o_jx), (const int32_t *)(d + o_cj), (const int32_t *)(d + o_ci),
+                             (int)cj.size(), st);
+    if (e != hipSuccess) return hip_fail(e, "lanczos update");
+    if (R) {
+        // CGS2 against w_0..w_j (v_k = s_k w_k)
+        const int nv = R->j + 1;
+        if (nv > MAX_BASIS) return fail(ECUT_EUNSUPPORTED, "too many basis vectors");
+        e = hipMemcpyAsync(R->dscale, d + o_sc, sizeof(double) * R->sc.size(), hipMemcpyDeviceToDevice, st);
+        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+            e = launch_multidot(R->basis, basis_ld(*R), nv, yvec(*R), R->n, R->part_cgs, R->n_chunks, st);
+            if (e == hipSuccess) e = launch_multidot_reduce(R->part_cgs, R->n_chunks, nv, R->dscale, R->dcoef, st);
+            if (e == hipSuccess)
+                e = launch_multiaxpy(R->basis, basis_ld(*R), nv, R->dcoef, R->dscale, yvec(*R), R->n,
+                                     pass == 1 ? R->part_norm : nullptr, R->n_chunks, 1.0, st);
+        }
+        if (e != hipSuccess) return hip_fail(e, "CGS2");
+    }
+    e = launch_reduce((const VecJob *)(d + o_jb), (int)jb.size(), st);
+    if (e != hipSuccess) return hip_fail(e, "lanczos beta");
+    for (LzSolve *L : act) {
+        e = hipMemcpyAsync(L->host_scal, L->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(scalars)");
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (lanczos step)");
+    stg.pending = false;
+    // 5. host: tridiagonal eigenproblem and convergence
+    for (LzSolve *L : act) {
+        const double alpha = L->host_scal[0];
+        const double beta = std::sqrt(std::max(L->host_scal[1], 0.0));
+        if (!std::isfinite(alpha) || !std::isfinite(beta)) {
+            L->done = true;
+            L->status = fail(ECUT_EDEVICE, "non-finite Lanczos coefficient");
+            continue;
+        }
+        L->a.push_back(alpha);
+        L->b.push_back(beta);
+        ++L->total;
+        const int m = (int)L->a.size();
+        std::vector<double> eo(L->b.begin(), L->b.begin() + (m - 1));
+        const std::vector<double> ev = tridiag_eigenvalues(L->a, eo);
+        const std::vector<double> u = tridiag_eigenvector(L->a, eo, ev[0]);
+        L->e_prev = m > 1 ? L->energy : ev[0];
+        L->energy = ev[0];
+        L->residual = beta * std::fabs(u[m - 1]);
+        const bool breakdown = beta <= 1e-14 * std::max(std::fabs(alpha), 1e-300);
+        const bool conv = (L->residual <= 1e-2 * std::sqrt(L->tol) && m > 1 && std::fabs(L->energy - L->e_prev) <= L->tol);
+        if (L->fixed) {
+            if (L->total >= L->max_steps || breakdown) L->done = true;
+        } else if (conv || breakdown) {
+            L->done = true;
+        } else if (L->total >= L->max_steps * (L->max_restarts + 1)) {
+            L->done = true;
+            L->status = ECUT_ENOTCONV;
+        }
+        if (L->done) continue;
+        if (L->reorth && m >= L->keep) {
+            // explicit restart from the current Ritz vector
+            if (L->restarts >= L->max_restarts) {
+                L->done = true;
+                L->status = ECUT_ENOTCONV;
+                continue;
+            }
+            ecut_status r2 = lz_ritz_vector(*L, slot(*L, 0), st, stg);
+            if (r2 != ECUT_OK) return r2;
+            ++L->restarts;
+            std::vector<LzSolve *> one{L};
+            std::vector<const double *> v0{slot(*L, 0)};
+            r2 = lz_start(one, v0, st, stg);
+            if (r2 != ECUT_OK) return r2;
+            continue;
+        }
+        L->s_prev = L->s_cur;
+        L->s_cur = 1.0 / beta;
+        L->beta_prev = beta;
+        L->sc.push_back(L->s_cur);
+        ++L->j;
+    }
+    return ECUT_OK;
+}
+
+}  // namespace ecut
+
+using namespace ecut;
+
+extern "C" {
+
+size_t ecut_lanczos_workspace(const ecut_sectors *s, const ecut_lanczos_opts *opts) {
+    if (!s || !opts) return 0;
+    const bool re = opts->reorth != 0;
+    return lz_workspace_doubles(s, re, re ? opts->max_steps : 0);
+}
+
+ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d, const ecut_lanczos_opts *opts,
+                                      double *energy, double *gs_d, ecut_lanczos_stats *stats, double *basis_d,
+                                      void *stream) {
+    if (!s || !opts || !energy || !v0_d || !basis_d) return fail(ECUT_EINVAL, "null argument");
+    if (!s->on_device) return fail(ECUT_EINVAL, "handle was built with ECUT_BUILD_HOST_ONLY");
+    if (opts->max_steps < 1) return fail(ECUT_EINVAL, "max_steps must be >= 1");
+    if (opts->max_restarts < 0) return fail(ECUT_EINVAL, "max_restarts must be >= 0");
+    if (opts->reorth && opts->max_steps + 1 > MAX_BASIS) return fail(ECUT_EUNSUPPORTED, "max_steps too large for reorth");
+    if (!opts->fixed_steps && !(opts->tol > 0.0)) return fail(ECUT_EINVAL, "tol must be > 0");
+    if (gs_d && !opts->reorth) return fail(ECUT_EUNSUPPORTED, "gs_d needs reorth = 1");
+    if (opts->max_restarts > 0 && !opts->reorth) return fail(ECUT_EUNSUPPORTED, "restarts need reorth = 1");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)stream;
+    static thread_local Staging stg;
+    LzSolve L;
+    lz_carve(L, s, opts->reorth != 0, opts->reorth ? opts->max_steps : 0, basis_d);
+    L.max_steps = opts->max_steps;
+    L.max_restarts = opts->max_restarts;
+    L.fixed = opts->fixed_steps != 0;
+    L.tol = opts->tol;
+    std::vector<LzSolve *> v{&L};
+    std::vector<const double *> v0{v0_d};
+    ecut_status rs = lz_start(v, v0, st, stg);
+    if (rs != ECUT_OK) return rs;
+    if (L.done) return L.status;
+    while (!L.done) {
+        rs = lz_step(v, st, stg);
+        if (rs != ECUT_OK) return rs;
+    }
+    if (L.status != ECUT_OK && L.status != ECUT_ENOTCONV) return L.status;
+    *energy = L.energy;
+    if (gs_d) {
+        rs = lz_ritz_vector(L, gs_d, st, stg);
+        if (rs != ECUT_OK) return rs;
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (ground state)");
+    }
+    if (stats) {
+        stats->steps = L.total;
+        stats->restarts = L.restarts;
+        stats->converged = L.status == ECUT_OK && !L.fixed ? 1 : 0;
+        stats->residual = L.residual;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (L.status == ECUT_ENOTCONV) return fail(ECUT_ENOTCONV, "Lanczos did not reach tol");
+    return ECUT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+// Internal runtime helpers shared by the ABI files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "ecut_internal.h"
+#include "kernels.h"
+
+namespace ecut {
+
+ecut_status hip_fail(hipError_t e, const char *what);
+ecut_status device_res(int *dev, const uint64_t **binom, int *n_cu);
+ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t st);
+int32_t apply_partial_slots(const ecut_sectors *s);
+int32_t max_tile_elems(const ecut_sectors *s);
+
+// One generic-kernel launch over several problems: copies the problem
+// descriptors and the work items to a per-thread device buffer (pinned
+// staging, asynchronous on `st`) and launches.  Waits for the previous use of
+// the buffer before overwriting it.
+ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items, int tile,
+                              hipStream_t st);
+
+// Small reusable device + pinned-host staging buffer (not thread-safe).
+struct Staging {
+    void *dev = nullptr;
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+    int device = -1;
+    ecut_status reserve(size_t bytes);
+    ecut_status wait();
+    ecut_status upload(size_t bytes, hipStream_t st);   // host -> dev, then records ev
+    void release();
+};
+
+}  // namespace ecut

@@ -1,0 +1,451 @@
+// Sector builder: subsystem bases with colex ranking, the block list of
+// Eq. (2)-(3), the subsystem operators H_L, H_R, their diagonals, the
+// diagonal cross-cut terms and the sector-changing cross terms, plus the
+// tables of the Hubbard up/down kernel.  Host only (no HIP calls).
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "ecut_internal.h"
+
+namespace ecut {
+
+static uint64_t g_binom[65][65];
+static std::once_flag g_binom_once;
+
+static void init_binom() {
+    for (int n = 0; n <= 64; ++n) {
+        g_binom[n][0] = 1;
+        for (int k = 1; k <= 64; ++k)
+            g_binom[n][k] = (n == 0) ? 0 : g_binom[n - 1][k - 1] + g_binom[n - 1][k];
+    }
+}
+
+uint64_t binom(int n, int k) {
+    std::call_once(g_binom_once, init_binom);
+    if (n < 0 || k < 0 || k > n || n > 64) return 0;
+    return g_binom[n][k];
+}
+
+int64_t colex_rank(uint64_t w) {
+    int64_t r = 0;
+    int j = 0;
+    while (w) {
+        int p = __builtin_ctzll(w);
+        r += (int64_t)binom(p, j + 1);
+        ++j;
+        w &= w - 1;
+    }
+    return r;
+}
+
+uint64_t colex_unrank(int64_t idx, int k) {
+    uint64_t w = 0;
+    for (int j = k; j >= 1; --j) {
+        int p = j - 1;
+        while ((int64_t)binom(p + 1, j) <= idx) ++p;
+        w |= 1ull << p;
+        idx -= (int64_t)binom(p, j);
+    }
+    return w;
+}
+
+namespace {
+
+struct Sub {
+    int n = 0;                 // bits
+    int cmin = 0, cmax = -1;   // counts held
+    std::vector<int32_t> cbase;
+    std::vector<uint32_t> words;
+    // off-diagonal rows before merging: (col, val) per global word
+    std::vector<std::vector<std::pair<int32_t, double>>> rows;
+    std::vector<double> diag;
+
+    void build(int nbits, int c0, int c1) {
+        n = nbits;
+        cmin = std::max(c0, 0);
+        cmax = std::min(c1, nbits);
+        cbase.clear();
+        words.clear();
+        for (int c = cmin; c <= cmax; ++c) {
+            cbase.push_back((int32_t)words.size());
+            int64_t cnt = (int64_t)binom(n, c);
+            for (int64_t i = 0; i < cnt; ++i) words.push_back((uint32_t)colex_unrank(i, c));
+        }
+        rows.assign(words.size(), {});
+        diag.assign(words.size(), 0.0);
+    }
+    bool has_count(int c) const { return c >= cmin && c <= cmax; }
+    int32_t base(int c) const { return cbase[c - cmin]; }
+    // global index of word w (its count must be held)
+    int64_t gindex(uint32_t w) const { return base(__builtin_popcount(w)) + colex_rank(w); }
+
+    void to_csr(std::vector<int32_t> &ptr, std::vector<int32_t> &col, std::vector<double> &val) {
+        ptr.assign(words.size() + 1, 0);
+        col.clear();
+        val.clear();
+        for (size_t g = 0; g < words.size(); ++g) {
+            auto &r = rows[g];
+            std::sort(r.begin(), r.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+            for (size_t e = 0; e < r.size(); ++e) {
+                if (!col.empty() && (int64_t)col.size() > ptr[g] && col.back() == r[e].first) {
+                    val.back() += r[e].second;
+                } else {
+                    col.push_back(r[e].first);
+                    val.push_back(r[e].second);
+                }
+            }
+            ptr[g + 1] = (int32_t)col.size();
+        }
+        rows.clear();
+        rows.shrink_to_fit();
+    }
+
+    // map of the global word index under "clear bit b" (del) or "set bit b"
+    // (ins): rank inside the target count, or -1.
+    void bit_map(int b, bool ins, std::vector<int32_t> &out) const {
+        for (size_t g = 0; g < words.size(); ++g) {
+            uint32_t w = words[g];
+            bool set = (w >> b) & 1u;
+            int c = __builtin_popcount(w);
+            int32_t v = -1;
+            if (ins && !set && has_count(c + 1)) v = (int32_t)colex_rank(w | (1u << b));
+            if (!ins && set && has_count(c - 1)) v = (int32_t)colex_rank(w & ~(1u << b));
+            out.push_back(v);
+        }
+    }
+};
+
+inline double sz(uint32_t w, int b) { return ((w >> b) & 1u) ? 0.5 : -0.5; }
+
+// Hop of a spinless fermion species between local sites i and j on word w:
+// returns false if it vanishes, else the new word and the Jordan-Wigner sign
+// (-1)^(number of particles strictly between i and j).
+inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
+    bool ni = (w >> i) & 1u, nj = (w >> j) & 1u;
+    if (ni == nj) return false;
+    int lo = std::min(i, j), hi = std::max(i, j);
+    uint32_t between = (hi - lo > 1) ? (((1u << (hi - lo - 1)) - 1u) << (lo + 1)) : 0u;
+    sign = (__builtin_popcount(w & between) & 1) ? -1 : 1;
+    w2 = w ^ ((1u << i) | (1u << j));
+    return true;
+}
+
+}  // namespace
+
+static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
+
+ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qnum q, ecut_sectors *s) {
+    if (!m || !c) return fail(ECUT_EINVAL, "null model or cut");
+    if (m->reserved != 0 || c->reserved != 0) return fail(ECUT_EINVAL, "reserved fields must be 0");
+    if (m->kind != ECUT_SPIN_HALF && m->kind != ECUT_HUBBARD) return fail(ECUT_EINVAL, "unknown model kind");
+    if (m->n_sites <= 0) return fail(ECUT_EINVAL, "n_sites must be positive");
+    if (m->n_bonds < 0 || (m->n_bonds > 0 && (!m->bond_i || !m->bond_j)))
+        return fail(ECUT_EINVAL, "bad bond arrays");
+    for (int b = 0; b < m->n_bonds; ++b) {
+        int i = m->bond_i[b], j = m->bond_j[b];
+        if (i < 0 || j < 0 || i >= m->n_sites || j >= m->n_sites || i == j)
+            return fail(ECUT_EINVAL, "bond " + std::to_string(b) + " has invalid end points");
+    }
+    s->kind = m->kind;
+    s->cut_kind = c->kind;
+    s->n_sites = m->n_sites;
+    s->left_mask = c->left_mask;
+    s->n_up = q.n_up;
+    s->n_dn = q.n_dn;
+
+    Sub L, R;
+    if (m->kind == ECUT_SPIN_HALF) {
+        if (c->kind != ECUT_CUT_SPATIAL) return fail(ECUT_EINVAL, "spin models take a spatial cut");
+        if (m->n_sites > 64) return fail(ECUT_EUNSUPPORTED, "spin models up to 64 sites");
+        if (m->n_bonds > 0 && (!m->jxy || !m->jz)) return fail(ECUT_EINVAL, "spin model needs jxy and jz");
+        uint64_t full = (m->n_sites == 64) ? ~0ull : ((1ull << m->n_sites) - 1);
+        if (c->left_mask & ~full) return fail(ECUT_EINVAL, "left_mask names sites beyond n_sites");
+        if (q.n_up < 0 || q.n_up > m->n_sites) return fail(ECUT_EINVAL, "n_up outside 0..n_sites");
+        s->lsites.clear();
+        s->rsites.clear();
+        for (int i = 0; i < m->n_sites; ++i) ((c->left_mask >> i) & 1u ? s->lsites : s->rsites).push_back(i);
+        int nL = (int)s->lsites.size(), nR = (int)s->rsites.size();
+        if (nL > 32 || nR > 32) return fail(ECUT_EUNSUPPORTED, "each side of the cut may hold at most 32 sites");
+        int qmin = std::max(0, q.n_up - nR), qmax = std::min(nL, q.n_up);
+        L.build(nL, qmin, qmax);
+        R.build(nR, q.n_up - qmax, q.n_up - qmin);
+        std::vector<int> side(m->n_sites), loc(m->n_sites);
+        for (int k = 0; k < nL; ++k) { side[s->lsites[k]] = 0; loc[s->lsites[k]] = k; }
+        for (int k = 0; k < nR; ++k) { side[s->rsites[k]] = 1; loc[s->rsites[k]] = k; }
+        // blocks
+        s->blocks.clear();
+        int64_t off = 0;
+        for (int ql = qmin; ql <= qmax; ++ql) {
+            BlockDev B{};
+            B.offset = off;
+            B.q_l = ql;
+            B.q_r = q.n_up - ql;
+            B.d_l = (int32_t)binom(nL, ql);
+            B.d_r = (int32_t)binom(nR, B.q_r);
+            B.lbase = L.base(ql);
+            B.rbase = R.base(B.q_r);
+            B.blk_lminus = ql > qmin ? (int32_t)s->blocks.size() - 1 : -1;
+            B.blk_lplus = ql < qmax ? (int32_t)s->blocks.size() + 1 : -1;
+            off += (int64_t)B.d_l * B.d_r;
+            s->blocks.push_back(B);
+        }
+        s->dim = off;
+        // operators
+        std::map<int, int32_t> lmaps_del, lmaps_ins, rmaps_del, rmaps_ins;
+        s->xdiag.clear();
+        s->xbond.clear();
+        s->maps.clear();
+        s->n_cut_bonds = 0;
+        auto map_for = [&](Sub &S, std::map<int, int32_t> &cache, int bit, bool ins) {
+            auto it = cache.find(bit);
+            if (it != cache.end()) return it->second;
+            int32_t o = (int32_t)s->maps.size();
+            S.bit_map(bit, ins, s->maps);
+            cache[bit] = o;
+            return o;
+        };
+        for (int b = 0; b < m->n_bonds; ++b) {
+            int i = m->bond_i[b], j = m->bond_j[b];
+            double jxy = m->jxy[b], jz = m->jz[b];
+            if (side[i] == side[j]) {
+                Sub &S = side[i] == 0 ? L : R;
+                int bi = loc[i], bj = loc[j];
+                for (size_t g = 0; g < S.words.size(); ++g) {
+                    uint32_t w = S.words[g];
+                    S.diag[g] += jz * sz(w, bi) * sz(w, bj);
+                    if (jxy != 0.0 && (((w >> bi) ^ (w >> bj)) & 1u)) {
+                        uint32_t w2 = w ^ ((1u << bi) | (1u << bj));
+                        S.rows[g].push_back({(int32_t)colex_rank(w2), 0.5 * jxy});
+                    }
+                }
+            } else {
+                ++s->n_cut_bonds;
+                int li = side[i] == 0 ? loc[i] : loc[j];
+                int rj = side[i] == 0 ? loc[j] : loc[i];
+                if (jz != 0.0) s->xdiag.push_back(XDiagDev{li, rj, 1, 0, jz});
+                if (jxy != 0.0) {
+                    XBondDev X{};
+                    X.li = li;
+                    X.rj = rj;
+                    X.coef = 0.5 * jxy;
+                    X.lmap_del = map_for(L, lmaps_del, li, false);
+                    X.lmap_ins = map_for(L, lmaps_ins, li, true);
+                    X.rmap_del = map_for(R, rmaps_del, rj, false);
+                    X.rmap_ins = map_for(R, rmaps_ins, rj, true);
+                    s->xbond.push_back(X);
+                }
+            }
+        }
+    } else {
+        if (c->kind != ECUT_CUT_UPDN)
+            return fail(ECUT_EUNSUPPORTED, "Hubbard models take the up/down cut (spatial fermionic cut not built)");
+        if (m->n_sites > 32) return fail(ECUT_EUNSUPPORTED, "Hubbard models up to 32 sites");
+        if (m->n_bonds > 0 && !m->t) return fail(ECUT_EINVAL, "Hubbard model needs t");
+        int Ls = m->n_sites;
+        if (q.n_up < 0 || q.n_up > Ls || q.n_dn < 0 || q.n_dn > Ls)
+            return fail(ECUT_EINVAL, "particle numbers outside 0..n_sites");
+        s->lsites.clear();
+        for (int i = 0; i < Ls; ++i) s->lsites.push_back(i);
+        s->rsites = s->lsites;
+        L.build(Ls, q.n_up, q.n_up);
+        R.build(Ls, q.n_dn, q.n_dn);
+        BlockDev B{};
+        B.offset = 0;
+        B.q_l = q.n_up;
+        B.q_r = q.n_dn;
+        B.d_l = (int32_t)binom(Ls, q.n_up);
+        B.d_r = (int32_t)binom(Ls, q.n_dn);
+        B.lbase = 0;
+        B.rbase = 0;
+        B.blk_lminus = B.blk_lplus = -1;
+        s->blocks.assign(1, B);
+        s->dim = (int64_t)B.d_l * B.d_r;
+        for (Sub *S : {&L, &R}) {
+            for (int b = 0; b < m->n_bonds; ++b) {
+                double t = m->t[b];
+                if (t == 0.0) continue;
+                int i = m->bond_i[b], j = m->bond_j[b];
+                for (size_t g = 0; g < S->words.size(); ++g) {
+                    uint32_t w2;
+                    int sg;
+                    if (fermion_hop(S->words[g], i, j, w2, sg))
+                        S->rows[g].push_back({(int32_t)colex_rank(w2), -t * sg});
+                }
+            }
+        }
+        s->xdiag.clear();
+        s->xbond.clear();
+        s->maps.clear();
+        s->n_cut_bonds = 0;
+        if (m->u)
+            for (int i = 0; i < Ls; ++i)
+                if (m->u[i] != 0.0) s->xdiag.push_back(XDiagDev{i, i, 0, 0, m->u[i]});
+    }
+
+    s->lcmin = L.cmin;
+    s->lcmax = L.cmax;
+    s->rcmin = R.cmin;
+    s->rcmax = R.cmax;
+    s->lcbase = L.cbase;
+    s->rcbase = R.cbase;
+    s->lwords = L.words;
+    s->rwords = R.words;
+    s->diag_l = L.diag;
+    s->diag_r = R.diag;
+    L.to_csr(s->hl_ptr, s->hl_col, s->hl_val);
+    R.to_csr(s->hr_ptr, s->hr_col, s->hr_val);
+
+    s->max_d_r = 0;
+    double sw2 = 0.0;
+    for (auto &B : s->blocks) {
+        s->max_d_r = std::max(s->max_d_r, B.d_r);
+        double w = (double)B.d_l * (double)B.d_r / (double)s->dim;
+        sw2 += w * w;
+    }
+    s->n_eff = sw2 > 0 ? 1.0 / sw2 : 0.0;
+
+    // default work items of the generic row kernel: row tiles of about
+    // `tile` elements (at least one row), largest first
+    const int64_t tile = std::max<int64_t>(s->max_d_r, 2048);
+    s->items.clear();
+    for (int b = 0; b < (int)s->blocks.size(); ++b) {
+        const BlockDev &B = s->blocks[b];
+        int32_t rpt = (int32_t)std::max<int64_t>(1, std::min<int64_t>(B.d_l, tile / std::max(B.d_r, 1)));
+        for (int32_t r0 = 0; r0 < B.d_l; r0 += rpt)
+            s->items.push_back(ItemDev{0, b, r0, std::min(B.d_l, r0 + rpt), 0, 0});
+    }
+    std::stable_sort(s->items.begin(), s->items.end(), [&](const ItemDev &a, const ItemDev &b) {
+        int64_t wa = (int64_t)(a.row1 - a.row0) * s->blocks[a.block].d_r;
+        int64_t wb = (int64_t)(b.row1 - b.row0) * s->blocks[b.block].d_r;
+        return wa > wb;
+    });
+    for (size_t k = 0; k < s->items.size(); ++k) s->items[k].slot = (int32_t)k;
+
+    s->hub_ok = false;
+    s->kernel = 2;
+    if (s->kind == ECUT_HUBBARD) build_hub_tables(s, m);
+    return ECUT_OK;
+}
+
+// Tables of the Hubbard up/down kernel.  Down words of n_r bits are split at
+// h = n_r / 2 into lo (bits < h) and hi (bits >= h); with the colex order of
+// the fixed-count down basis, the column of (hi, lo) is seg_off[hi] +
+// lo_rank[lo] because all words sharing hi are contiguous and ordered by lo.
+static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
+    const BlockDev &B = s->blocks[0];
+    int n = s->n_sites;
+    int c = B.q_r;
+    // the kernel holds a full row plus these tables in LDS
+    if (n > 20 || (int64_t)B.d_r * 8 > 120 * 1024 || B.d_r < 1) return;
+    int h = n / 2;
+    int nlo = 1 << h, nhi = 1 << (n - h);
+    ecut::HubDev &H = s->hub;
+    H = ecut::HubDev{};
+    H.n_r = n;
+    H.h = h;
+    // coefficient table: distinct -t_b values
+    std::vector<double> coef;
+    std::vector<int> bcoef(m->n_bonds, -1);
+    for (int b = 0; b < m->n_bonds; ++b) {
+        double v = -m->t[b];
+        if (m->t[b] == 0.0) continue;
+        auto it = std::find(coef.begin(), coef.end(), v);
+        if (it == coef.end()) { coef.push_back(v); bcoef[b] = (int)coef.size() - 1; }
+        else bcoef[b] = (int)(it - coef.begin());
+    }
+    if (coef.size() > 255) return;
+    H.n_coef = (int32_t)coef.size();
+    H.uniform_t = coef.size() <= 1 ? 1 : 0;
+    H.hop0 = coef.empty() ? 0.0 : coef[0];
+    // lo/hi neighbour lists
+    std::vector<std::vector<int32_t>> lo_l(nlo), hi_l(nhi);
+    std::vector<int32_t> lo_rank(nlo), seg_off(nhi, -1);
+    for (int v = 0; v < nlo; ++v) lo_rank[v] = (int32_t)ecut::colex_rank((uint64_t)v);
+    {
+        int32_t acc = 0;
+        for (int u = 0; u < nhi; ++u) {
+            int k = c - __builtin_popcount(u);
+            if (k < 0 || k > h) continue;
+            seg_off[u] = acc;
+            acc += (int32_t)ecut::binom(h, k);
+        }
+        if (acc != B.d_r) return;   // cannot happen; keeps the kernel honest
+    }
+    auto pack = [](int32_t delta, int neg, int ci) { return (int32_t)(((uint32_t)delta << 9) | (uint32_t)(neg << 8) | (uint32_t)ci); };
+    std::vector<int32_t> xb;
+    for (int b = 0; b < m->n_bonds; ++b) {
+        if (bcoef[b] < 0) continue;
+        int i = m->bond_i[b], j = m->bond_j[b];
+        if (i < h && j < h) {
+            for (int v = 0; v < nlo; ++v) {
+                uint32_t w2;
+                int sg;
+                if (fermion_hop((uint32_t)v, i, j, w2, sg))
+                    lo_l[v].push_back(pack(lo_rank[w2] - lo_rank[v], sg < 0, bcoef[b]));
+            }
+        } else if (i >= h && j >= h) {
+            for (int u = 0; u < nhi; ++u) {
+                uint32_t w2;
+                int sg;
+                if (seg_off[u] >= 0 && fermion_hop((uint32_t)u, i - h, j - h, w2, sg))
+                    hi_l[u].push_back(pack(seg_off[w2] - seg_off[u], sg < 0, bcoef[b]));
+            }
+        } else {
+            int lb = i < h ? i : j, hb = (i < h ? j : i) - h;
+            xb.push_back(lb);
+            xb.push_back(hb);
+            xb.push_back(bcoef[b]);
+            xb.push_back(0);
+        }
+    }
+    size_t ls = 1, hs = 1;
+    for (auto &v : lo_l) ls = std::max(ls, v.size());
+    for (auto &v : hi_l) hs = std::max(hs, v.size());
+    {
+        // the whole LDS image (row, words, tables) must fit 160 KiB
+        auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
+        size_t lds = al((size_t)B.d_r * 8) + al((size_t)B.d_r * (n <= 16 ? 2 : 4)) + 2 * al((size_t)nlo * 4) +
+                     al((size_t)nlo * ls * 4) + 2 * al((size_t)nhi * 4) + al((size_t)nhi * hs * 4) +
+                     al(std::max<size_t>(coef.size(), 1) * 8) + 3 * 256 * 8 + 1024;
+        if (lds > 160 * 1024) return;
+    }
+    H.lo_stride = (int32_t)ls;
+    H.hi_stride = (int32_t)hs;
+    H.n_xb = (int32_t)(xb.size() / 4);
+    s->hub_lo_cnt.assign(nlo, 0);
+    s->hub_lo_ent.assign((size_t)nlo * ls, 0);
+    s->hub_hi_cnt.assign(nhi, 0);
+    s->hub_hi_ent.assign((size_t)nhi * hs, 0);
+    for (int v = 0; v < nlo; ++v) {
+        s->hub_lo_cnt[v] = (int32_t)lo_l[v].size();
+        std::copy(lo_l[v].begin(), lo_l[v].end(), s->hub_lo_ent.begin() + (size_t)v * ls);
+    }
+    for (int u = 0; u < nhi; ++u) {
+        s->hub_hi_cnt[u] = (int32_t)hi_l[u].size();
+        std::copy(hi_l[u].begin(), hi_l[u].end(), s->hub_hi_ent.begin() + (size_t)u * hs);
+    }
+    s->hub_lo_rank = lo_rank;
+    s->hub_seg_off = seg_off;
+    s->hub_xb = xb;
+    s->hub_coef = coef.empty() ? std::vector<double>{0.0} : coef;
+    s->hub_u.assign(n, 0.0);
+    if (m->u)
+        for (int i = 0; i < n; ++i) s->hub_u[i] = m->u[i];
+    H.uniform_u = 1;
+    H.u0 = s->hub_u[0];
+    for (int i = 1; i < n; ++i)
+        if (s->hub_u[i] != H.u0) H.uniform_u = 0;
+    s->hub_rw16.clear();
+    if (n <= 16)
+        for (int32_t r = 0; r < B.d_r; ++r) s->hub_rw16.push_back((uint16_t)s->rwords[B.rbase + r]);
+    // row order: plain increasing rows
+    s->row_order.resize(B.d_l);
+    for (int32_t a = 0; a < B.d_l; ++a) s->row_order[a] = a;
+    s->hub_ok = true;
+    s->kernel = 1;
+}
+
+}  // namespace ecut

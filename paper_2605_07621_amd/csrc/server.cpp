@@ -1,0 +1,367 @@
+// Continuous-batching ground-state server.
+//
+// A worker thread owns one HIP stream and a device arena of hbm_budget
+// bytes.  Each step it
+//   1. admits queued requests (FIFO, arrival time reached) while a slot is
+//      free and the request's Lanczos workspace fits the free arena;
+//   2. advances every admitted solve by one Lanczos step: one batched H*psi
+//      launch over the sector work queue of all generic-kernel problems (plus
+//      the Hubbard up/down kernel per Hubbard problem), one batched alpha
+//      reduction, one batched update+norm pass and one batched beta
+//      reduction, then one synchronisation for all alpha/beta values;
+//   3. retires converged solves, freeing their arena space and slot.
+// With max_active = 1 the same loop is the sequential baseline: one request
+// at a time on the plain single-solve path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "ecut_internal.h"
+#include "kernels.h"
+#include "lanczos.h"
+#include "runtime.h"
+
+namespace ecut {
+namespace {
+
+// First-fit allocator over [0, size) with coalescing, 256-byte granules.
+struct ArenaAlloc {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    void init(size_t n) {
+        size = n & ~(size_t)255;
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t n, size_t &off) {
+        n = (n + 255) & ~(size_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                off = it->first;
+                const size_t rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = (n + 255) & ~(size_t)255;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t free_bytes() const {
+        size_t s = 0;
+        for (auto &kv : free_) s += kv.second;
+        return s;
+    }
+};
+
+struct Request {
+    uint64_t id = 0;
+    ecut_model_desc model{};
+    ecut_cut_desc cut{};
+    ecut_qnum q{};
+    uint64_t seed = 0;
+    double not_before = 0.0, t_submit = 0.0;
+    std::vector<int32_t> bi, bj;
+    std::vector<double> jxy, jz, t, u;
+    ecut_sectors *built = nullptr;   // sectors built while waiting for memory
+    ~Request() {
+        if (built) ecut_sectors_free(built);
+    }
+    void own(const ecut_model_desc &m) {
+        model = m;
+        bi.assign(m.bond_i, m.bond_i + m.n_bonds);
+        bj.assign(m.bond_j, m.bond_j + m.n_bonds);
+        if (m.jxy) jxy.assign(m.jxy, m.jxy + m.n_bonds);
+        if (m.jz) jz.assign(m.jz, m.jz + m.n_bonds);
+        if (m.t) t.assign(m.t, m.t + m.n_bonds);
+        if (m.u) u.assign(m.u, m.u + m.n_sites);
+        model.bond_i = bi.data();
+        model.bond_j = bj.data();
+        model.jxy = m.jxy ? jxy.data() : nullptr;
+        model.jz = m.jz ? jz.data() : nullptr;
+        model.t = m.t ? t.data() : nullptr;
+        model.u = m.u ? u.data() : nullptr;
+    }
+};
+
+struct Active {
+    std::unique_ptr<Request> req;
+    ecut_sectors *s = nullptr;
+    LzSolve L;
+    size_t off = 0, bytes = 0;
+    double t_admit = 0.0;
+};
+
+}  // namespace
+}  // namespace ecut
+
+using namespace ecut;
+
+struct ecut_server {
+    size_t budget = 0;
+    ecut_server_opts opts{};
+    int device = 0;
+    void *arena = nullptr;
+    ArenaAlloc alloc;
+    hipStream_t stream = nullptr;
+    Staging stg;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::deque<std::unique_ptr<Request>> queue;
+    std::vector<ecut_result> finished;
+    uint64_t next_id = 1;
+    uint64_t n_submitted = 0, n_finished = 0;
+    bool stop = false;
+    std::chrono::steady_clock::time_point t0;
+    ecut_status worker_status = ECUT_OK;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    void run();
+};
+
+static size_t footprint(const ecut_sectors *s) { return lz_workspace_doubles(s, false, 0) * sizeof(double); }
+
+void ecut_server::run() {
+    hipSetDevice(device);
+    std::vector<std::unique_ptr<Active>> active;
+    const int max_active = opts.max_active > 0 ? opts.max_active : 1 << 30;
+    while (true) {
+        // ---- admission
+        std::vector<Active *> fresh;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            while (!stop && active.empty()) {
+                if (!queue.empty()) {
+                    const double wait = queue.front()->not_before - now();
+                    if (wait <= 0) break;
+                    cv.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.05)));
+                } else {
+                    cv.wait_for(lk, std::chrono::milliseconds(50));
+                }
+            }
+            if (stop && active.empty()) break;
+            while (!queue.empty() && (int)active.size() < max_active && queue.front()->not_before <= now()) {
+                Request &R = *queue.front();
+                lk.unlock();
+                ecut_sectors *s = R.built;
+                R.built = nullptr;
+                ecut_status st = s ? ECUT_OK : ecut_build_sectors(&R.model, &R.cut, R.q, 0, &s);
+                size_t off = 0, bytes = 0;
+                bool fits = false;
+                if (st == ECUT_OK) {
+                    bytes = footprint(s);
+                    fits = alloc.alloc(bytes, off);
+                    if (!fits && bytes > alloc.size) st = fail(ECUT_ENOMEM, "request larger than the server budget");
+                }
+                lk.lock();
+                if (st != ECUT_OK) {
+                    ecut_result r{};
+                    r.req_id = R.id;
+                    r.status = st;
+                    r.t_submit = R.t_submit;
+                    r.t_admit = r.t_done = now();
+                    finished.push_back(r);
+                    ++n_finished;
+                    queue.pop_front();
+                    if (s) ecut_sectors_free(s);
+                    cv_done.notify_all();
+                    continue;
+                }
+                if (!fits) {
+                    // wait for memory: strict FIFO, the head is never overtaken
+                    R.built = s;
+                    break;
+                }
+                auto A = std::make_unique<Active>();
+                A->req = std::move(queue.front());
+                queue.pop_front();
+                A->s = s;
+                A->off = off;
+                A->bytes = bytes;
+                A->t_admit = now();
+                lz_carve(A->L, s, false, 0, (double *)((char *)arena + off));
+                A->L.max_steps = opts.max_steps;
+                A->L.max_restarts = 0;
+                A->L.tol = opts.tol;
+                fresh.push_back(A.get());
+                active.push_back(std::move(A));
+            }
+        }
+        ecut_status st = ECUT_OK;
+        if (!fresh.empty()) {
+            std::vector<LzSolve *> ls;
+            std::vector<const double *> v0;
+            for (Active *A : fresh) {
+                hipError_t e = launch_fill_normal(A->L.ring[0], A->L.n, A->req->seed, stream);
+                if (e != hipSuccess) st = hip_fail(e, "seeded start vector");
+                ls.push_back(&A->L);
+                v0.push_back(A->L.ring[0]);
+            }
+            if (st == ECUT_OK) st = lz_start(ls, v0, stream, stg);
+        }
+        // ---- one batched step
+        if (st == ECUT_OK && !active.empty()) {
+            std::vector<LzSolve *> ls;
+            for (auto &A : active) ls.push_back(&A->L);
+            st = lz_step(ls, stream, stg);
+        }
+        if (st != ECUT_OK) {
+            std::lock_guard<std::mutex> g(mu);
+            worker_status = st;
+            for (auto &A : active) A->L.done = true, A->L.status = st;
+        }
+        // ---- retire
+        std::vector<ecut_result> out;
+        for (auto it = active.begin(); it != active.end();) {
+            Active &A = **it;
+            if (!A.L.done) { ++it; continue; }
+            ecut_result r{};
+            r.req_id = A.req->id;
+            r.status = A.L.status;
+            r.steps = A.L.total;
+            r.energy = A.L.energy;
+            r.residual = A.L.residual;
+            r.t_submit = A.req->t_submit;
+            r.t_admit = A.t_admit;
+            r.t_done = now();
+            out.push_back(r);
+            alloc.release(A.off, A.bytes);
+            ecut_sectors_free(A.s);
+            it = active.erase(it);
+        }
+        if (!out.empty()) {
+            std::lock_guard<std::mutex> g(mu);
+            for (auto &r : out) finished.push_back(r);
+            n_finished += out.size();
+            cv_done.notify_all();
+        }
+    }
+}
+
+extern "C" {
+
+ecut_status ecut_server_create(size_t hbm_budget, const ecut_server_opts *opts, ecut_server **out) {
+    if (!out || !opts) return fail(ECUT_EINVAL, "null argument");
+    *out = nullptr;
+    if (hbm_budget < 4096) return fail(ECUT_EINVAL, "budget too small");
+    if (opts->max_steps < 2 || !(opts->tol > 0.0)) return fail(ECUT_EINVAL, "bad server options");
+    auto *S = new (std::nothrow) ecut_server();
+    if (!S) return fail(ECUT_ENOMEM, "host allocation");
+    S->budget = hbm_budget;
+    S->opts = *opts;
+    if (S->opts.sequential) S->opts.max_active = 1;
+    hipError_t e = hipGetDevice(&S->device);
+    if (e == hipSuccess) e = hipMalloc(&S->arena, hbm_budget);
+    if (e != hipSuccess) {
+        delete S;
+        return fail(ECUT_ENOMEM, std::string("server arena: ") + hipGetErrorString(e));
+    }
+    e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        hipFree(S->arena);
+        delete S;
+        return hip_fail(e, "hipStreamCreate");
+    }
+    ecut_status rs = device_res(nullptr, nullptr, nullptr);
+    if (rs != ECUT_OK) {
+        hipStreamDestroy(S->stream);
+        hipFree(S->arena);
+        delete S;
+        return rs;
+    }
+    S->alloc.init(hbm_budget);
+    S->t0 = std::chrono::steady_clock::now();
+    S->worker = std::thread([S] { S->run(); });
+    *out = S;
+    return ECUT_OK;
+}
+
+ecut_status ecut_server_submit(ecut_server *srv, const ecut_model_desc *model, const ecut_cut_desc *cut, ecut_qnum q,
+                               uint64_t seed, double not_before, uint64_t *req_id) {
+    if (!srv || !model || !cut) return fail(ECUT_EINVAL, "null argument");
+    if (model->n_bonds < 0 || (model->n_bonds > 0 && (!model->bond_i || !model->bond_j)))
+        return fail(ECUT_EINVAL, "bad bond arrays");
+    if (model->n_sites <= 0 || model->n_sites > 64) return fail(ECUT_EINVAL, "bad n_sites");
+    auto R = std::make_unique<Request>();
+    R->own(*model);
+    R->cut = *cut;
+    R->q = q;
+    R->seed = seed;
+    std::lock_guard<std::mutex> g(srv->mu);
+    R->id = srv->next_id++;
+    R->t_submit = srv->now();
+    R->not_before = not_before > 0 ? not_before : R->t_submit;
+    R->t_submit = std::max(R->t_submit, R->not_before);   // latency counts from arrival
+    if (req_id) *req_id = R->id;
+    // keep the queue ordered by arrival time (stable for equal times)
+    auto it = srv->queue.end();
+    while (it != srv->queue.begin() && (*std::prev(it))->not_before > R->not_before) --it;
+    srv->queue.insert(it, std::move(R));
+    ++srv->n_submitted;
+    srv->cv.notify_all();
+    return ECUT_OK;
+}
+
+ecut_status ecut_server_poll(ecut_server *srv, ecut_result *out, int32_t max, int32_t *n_done) {
+    if (!srv || !n_done || (max > 0 && !out)) return fail(ECUT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> g(srv->mu);
+    const int32_t n = (int32_t)std::min<size_t>((size_t)std::max(max, 0), srv->finished.size());
+    for (int32_t k = 0; k < n; ++k) out[k] = srv->finished[k];
+    srv->finished.erase(srv->finished.begin(), srv->finished.begin() + n);
+    *n_done = n;
+    if (srv->worker_status != ECUT_OK && n == 0) return fail(srv->worker_status, "server worker failed");
+    return n > 0 ? ECUT_OK : ECUT_EAGAIN;
+}
+
+ecut_status ecut_server_drain(ecut_server *srv) {
+    if (!srv) return fail(ECUT_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [&] { return srv->n_finished >= srv->n_submitted || srv->worker_status != ECUT_OK; });
+    return srv->worker_status;
+}
+
+double ecut_server_now(const ecut_server *srv) { return srv ? srv->now() : 0.0; }
+
+void ecut_server_destroy(ecut_server *srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        srv->stop = true;
+        srv->queue.clear();
+        srv->cv.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    srv->stg.release();
+    hipStreamSynchronize(srv->stream);
+    hipStreamDestroy(srv->stream);
+    hipFree(srv->arena);
+    delete srv;
+}
+
+}  // extern "C"

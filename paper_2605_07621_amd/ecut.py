@@ -1,0 +1,309 @@
+"""Python binding of libecut.so (include/ecut.h).
+
+Argument marshalling only: every step of H*psi, the Lanczos solver and the
+server runs in the library (host C++ sector builder + HIP kernels for
+gfx950).  torch supplies device memory (tensor.data_ptr()) and streams.
+The library is required: importing this module raises if libecut.so is
+missing or fails to load, there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libecut.so")
+
+ECUT_OK, ECUT_EINVAL, ECUT_ENOMEM, ECUT_EDEVICE, ECUT_ENOTCONV, ECUT_EUNSUPPORTED, ECUT_EAGAIN = 0, -1, -2, -3, -4, -5, -6
+ECUT_SPIN_HALF, ECUT_HUBBARD = 1, 2
+ECUT_CUT_SPATIAL, ECUT_CUT_UPDN = 1, 2
+ECUT_BUILD_HOST_ONLY = 1
+
+_STATUS = {0: "ECUT_OK", -1: "ECUT_EINVAL", -2: "ECUT_ENOMEM", -3: "ECUT_EDEVICE", -4: "ECUT_ENOTCONV",
+           -5: "ECUT_EUNSUPPORTED", -6: "ECUT_EAGAIN"}
+
+
+class EcutError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _dbl, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("n_sites", _i32), ("n_bonds", _i32), ("reserved", _i32),
+                ("bond_i", _vp), ("bond_j", _vp), ("jxy", _vp), ("jz", _vp), ("t", _vp), ("u", _vp)]
+
+
+class CutDesc(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("reserved", _i32), ("left_mask", _u64)]
+
+
+class QNum(ctypes.Structure):
+    _fields_ = [("n_up", _i32), ("n_dn", _i32)]
+
+
+class SectorsInfo(ctypes.Structure):
+    _fields_ = [("dim", _i64), ("n_blocks", _i32), ("n_left_sites", _i32), ("n_right_sites", _i32),
+                ("max_d_r", _i32), ("n_cut_bonds", _i32), ("n_cross_offdiag", _i32), ("n_cross_diag", _i32),
+                ("kernel", _i32), ("device_bytes", _i64), ("n_eff", _dbl)]
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("max_steps", _i32), ("max_restarts", _i32), ("reorth", _i32), ("fixed_steps", _i32), ("tol", _dbl)]
+
+
+class LanczosStats(ctypes.Structure):
+    _fields_ = [("steps", _i32), ("restarts", _i32), ("converged", _i32), ("reserved", _i32),
+                ("residual", _dbl), ("seconds", _dbl)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_active", _i32), ("max_steps", _i32), ("tol", _dbl), ("sequential", _i32), ("use_graph", _i32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("req_id", _u64), ("status", _i32), ("steps", _i32), ("energy", _dbl), ("residual", _dbl),
+                ("t_submit", _dbl), ("t_admit", _dbl), ("t_done", _dbl)]
+
+
+# (name, restype, argtypes) of every entry point declared in include/ecut.h
+SYMBOLS = [
+    ("ecut_build_sectors", _i32, [ctypes.POINTER(ModelDesc), ctypes.POINTER(CutDesc), QNum, _u32, ctypes.POINTER(_vp)]),
+    ("ecut_sectors_free", None, [_vp]),
+    ("ecut_sectors_get_info", _i32, [_vp, ctypes.POINTER(SectorsInfo)]),
+    ("ecut_sectors_blocks", _i32, [_vp, _vp]),
+    ("ecut_sectors_words", _i32, [_vp, _i32, _vp, _vp]),
+    ("ecut_canonical_positions", _i32, [_vp, _vp]),
+    ("ecut_import", _i32, [_vp, _vp, _vp, _vp]),
+    ("ecut_export", _i32, [_vp, _vp, _vp, _vp]),
+    ("ecut_apply_H", _i32, [_vp, _vp, _vp, _vp]),
+    ("ecut_apply_H_batch", _i32, [_i32, _vp, _vp, _vp, _vp]),
+    ("ecut_lanczos_workspace", _sz, [_vp, ctypes.POINTER(LanczosOpts)]),
+    ("ecut_lanczos_ground_state", _i32, [_vp, _vp, ctypes.POINTER(LanczosOpts), ctypes.POINTER(_dbl), _vp,
+                                         ctypes.POINTER(LanczosStats), _vp, _vp]),
+    ("ecut_server_create", _i32, [_sz, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]),
+    ("ecut_server_submit", _i32, [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(CutDesc), QNum, _u64, _dbl,
+                                  ctypes.POINTER(_u64)]),
+    ("ecut_server_poll", _i32, [_vp, ctypes.POINTER(Result), _i32, ctypes.POINTER(_i32)]),
+    ("ecut_server_drain", _i32, [_vp]),
+    ("ecut_server_now", _dbl, [_vp]),
+    ("ecut_server_destroy", None, [_vp]),
+    ("ecut_last_error", ctypes.c_char_p, []),
+    ("ecut_version", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def lib():
+    """Load libecut.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              f"(or python paper_2605_07621_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SYMBOLS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != ECUT_OK:
+        raise EcutError(st, lib().ecut_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return _vp(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return _vp(stream.cuda_stream)
+    return _vp(stream)
+
+
+def _dptr(t, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {n}")
+    return _vp(t.data_ptr())
+
+
+class _ModelArgs:
+    """Keeps the numpy arrays alive behind a ModelDesc / CutDesc / QNum."""
+
+    def __init__(self, model, cut, n_up, n_dn=0):
+        b = np.ascontiguousarray(np.asarray(model.bonds, dtype=np.int32).reshape(-1, 2))
+        self.bi = np.ascontiguousarray(b[:, 0])
+        self.bj = np.ascontiguousarray(b[:, 1])
+        nb = len(self.bi)
+        p = lambda a: None if a is None else a.ctypes.data
+        if model.kind == "spin":
+            self.jxy = np.ascontiguousarray(model.jxy, dtype=np.float64)
+            self.jz = np.ascontiguousarray(model.jz, dtype=np.float64)
+            self.t = self.u = None
+            kind = ECUT_SPIN_HALF
+        elif model.kind == "hubbard":
+            self.t = np.ascontiguousarray(model.t, dtype=np.float64)
+            self.u = None if model.u is None else np.ascontiguousarray(model.u, dtype=np.float64)
+            self.jxy = self.jz = None
+            kind = ECUT_HUBBARD
+        else:
+            raise ValueError(f"unknown model kind {model.kind!r}")
+        self.m = ModelDesc(kind, int(model.n_sites), nb, 0, p(self.bi), p(self.bj), p(self.jxy), p(self.jz),
+                           p(self.t), p(self.u))
+        ck = {"spatial": ECUT_CUT_SPATIAL, "updn": ECUT_CUT_UPDN}.get(cut.kind)
+        if ck is None:
+            raise ValueError(f"unknown cut kind {cut.kind!r}")
+        self.c = CutDesc(ck, 0, int(cut.left_mask))
+        self.q = QNum(int(n_up), int(n_dn))
+
+
+class Sectors:
+    """ecut_sectors handle: the bipartite description of H in one sector."""
+
+    def __init__(self, model, cut, n_up, n_dn=0, host_only=False):
+        self._args = _ModelArgs(model, cut, n_up, n_dn)
+        h = _vp()
+        _check(lib().ecut_build_sectors(ctypes.byref(self._args.m), ctypes.byref(self._args.c), self._args.q,
+                                        ECUT_BUILD_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+        self.h = h
+        i = SectorsInfo()
+        _check(lib().ecut_sectors_get_info(self.h, ctypes.byref(i)))
+        self.info = i
+        self.dim = int(i.dim)
+
+    @classmethod
+    def from_problem(cls, p, host_only=False):
+        return cls(p.model, p.cut, p.n_up, p.n_dn, host_only=host_only)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ecut_sectors_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def blocks(self):
+        out = np.empty(5 * self.info.n_blocks, dtype=np.int64)
+        _check(lib().ecut_sectors_blocks(self.h, out.ctypes.data))
+        return out.reshape(-1, 5)
+
+    def words(self, block):
+        b = self.blocks()[block]
+        lw = np.empty(int(b[2]), dtype=np.uint32)
+        rw = np.empty(int(b[3]), dtype=np.uint32)
+        _check(lib().ecut_sectors_words(self.h, int(block), lw.ctypes.data, rw.ctypes.data))
+        return lw, rw
+
+    def canonical_positions(self):
+        pos = np.empty(self.dim, dtype=np.int64)
+        _check(lib().ecut_canonical_positions(self.h, pos.ctypes.data))
+        return pos
+
+    def import_(self, canon, out=None, stream=None):
+        import torch
+        out = torch.empty(self.dim, dtype=torch.float64, device=canon.device) if out is None else out
+        _check(lib().ecut_import(self.h, _dptr(canon, self.dim, "canon"), _dptr(out, self.dim, "out"), _stream(stream)))
+        return out
+
+    def export(self, bip, out=None, stream=None):
+        import torch
+        out = torch.empty(self.dim, dtype=torch.float64, device=bip.device) if out is None else out
+        _check(lib().ecut_export(self.h, _dptr(bip, self.dim, "bip"), _dptr(out, self.dim, "out"), _stream(stream)))
+        return out
+
+    def apply(self, psi, out=None, stream=None):
+        import torch
+        out = torch.empty(self.dim, dtype=torch.float64, device=psi.device) if out is None else out
+        _check(lib().ecut_apply_H(self.h, _dptr(psi, self.dim, "psi"), _dptr(out, self.dim, "out"), _stream(stream)))
+        return out
+
+    def lanczos_workspace(self, max_steps, reorth=False, max_restarts=0, tol=1e-10, fixed_steps=False):
+        o = LanczosOpts(int(max_steps), int(max_restarts), int(bool(reorth)), int(bool(fixed_steps)), float(tol))
+        return int(lib().ecut_lanczos_workspace(self.h, ctypes.byref(o)))
+
+    def lanczos(self, v0, max_steps, tol=1e-10, reorth=False, fixed_steps=False, max_restarts=0,
+                want_gs=False, workspace=None, stream=None, allow_notconv=False):
+        """Returns (energy, stats dict, ground state or None)."""
+        import torch
+        o = LanczosOpts(int(max_steps), int(max_restarts), int(bool(reorth)), int(bool(fixed_steps)), float(tol))
+        nws = int(lib().ecut_lanczos_workspace(self.h, ctypes.byref(o)))
+        ws = torch.empty(nws, dtype=torch.float64, device=v0.device) if workspace is None else workspace
+        gs = torch.empty(self.dim, dtype=torch.float64, device=v0.device) if want_gs else None
+        e = _dbl()
+        stt = LanczosStats()
+        st = lib().ecut_lanczos_ground_state(self.h, _dptr(v0, self.dim, "v0"), ctypes.byref(o), ctypes.byref(e),
+                                             None if gs is None else _vp(gs.data_ptr()), ctypes.byref(stt),
+                                             _dptr(ws, nws, "workspace"), _stream(stream))
+        if not (st == ECUT_OK or (allow_notconv and st == ECUT_ENOTCONV)):
+            _check(st)
+        stats = dict(steps=stt.steps, restarts=stt.restarts, converged=stt.converged, residual=stt.residual,
+                     seconds=stt.seconds, status=st)
+        return e.value, stats, gs
+
+
+def apply_batch(sectors, psis, ys, stream=None):
+    n = len(sectors)
+    hs = (_vp * n)(*[s.h for s in sectors])
+    ps = (_vp * n)(*[_dptr(p, s.dim, "psi") for s, p in zip(sectors, psis)])
+    qs = (_vp * n)(*[_dptr(y, s.dim, "y") for s, y in zip(sectors, ys)])
+    _check(lib().ecut_apply_H_batch(n, ctypes.cast(hs, _vp), ctypes.cast(ps, _vp), ctypes.cast(qs, _vp),
+                                    _stream(stream)))
+
+
+class Server:
+    """Continuous-batching ground-state server (ecut_server_*)."""
+
+    def __init__(self, hbm_budget, max_active=0, max_steps=400, tol=1e-10, sequential=False, use_graph=False):
+        o = ServerOpts(int(max_active), int(max_steps), float(tol), int(bool(sequential)), int(bool(use_graph)))
+        h = _vp()
+        _check(lib().ecut_server_create(int(hbm_budget), ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, problem, seed, not_before=0.0):
+        a = _ModelArgs(problem.model, problem.cut, problem.n_up, problem.n_dn)
+        rid = _u64()
+        _check(lib().ecut_server_submit(self.h, ctypes.byref(a.m), ctypes.byref(a.c), a.q, int(seed),
+                                        float(not_before), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def poll(self, max_results=1024):
+        buf = (Result * max_results)()
+        n = _i32()
+        st = lib().ecut_server_poll(self.h, buf, max_results, ctypes.byref(n))
+        if st not in (ECUT_OK, ECUT_EAGAIN):
+            _check(st)
+        return [dict(req_id=r.req_id, status=r.status, steps=r.steps, energy=r.energy, residual=r.residual,
+                     t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done) for r in buf[:n.value]]
+
+    def drain(self):
+        _check(lib().ecut_server_drain(self.h))
+
+    def now(self):
+        return lib().ecut_server_now(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ecut_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

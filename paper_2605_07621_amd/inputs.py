@@ -86,7 +86,7 @@ def hubbard_chain(n, t=1.0, U=4.0, periodic=False):
 
 def random_spin_model(rng, n, n_bonds=None):
     """Random couplings on random distinct bonds (tiny parity cases)."""
-    n_bonds = n_bonds or max(1, (3 * n) // 2)
+    n_bonds = min(n_bonds or max(1, (3 * n) // 2), n * (n - 1) // 2)
     pairs = set()
     while len(pairs) < n_bonds:
         i, j = rng.integers(0, n, 2)
@@ -99,7 +99,7 @@ def random_spin_model(rng, n, n_bonds=None):
 
 def random_hubbard_model(rng, n, n_bonds=None):
     """Random hoppings on random (also long-range) bonds, random U_i."""
-    n_bonds = n_bonds or max(1, (3 * n) // 2)
+    n_bonds = min(n_bonds or max(1, (3 * n) // 2), n * (n - 1) // 2)
     pairs = set()
     while len(pairs) < n_bonds:
         i, j = rng.integers(0, n, 2)

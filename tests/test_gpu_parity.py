@@ -1,0 +1,246 @@
+"""GPU parity of the bipartite H*psi, the Lanczos solver, batching and
+serving against the CPU oracle.  All calls go through the C ABI (ctypes
+binding); the oracle sees the same seeded canonical-order inputs.
+
+Tolerance: H*psi relative L2 error <= 1e-12 (and every element within
+1e-12 * max|y|); ground energies within 1e-10 absolute."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_07621_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def _ecut():
+    from paper_2605_07621_amd import ecut
+    return ecut
+
+
+def _compare(y, y_ref, what):
+    err = np.linalg.norm(y - y_ref) / max(np.linalg.norm(y_ref), 1e-300)
+    assert err <= RTOL, f"{what}: relative L2 {err:.3e}"
+    assert np.max(np.abs(y - y_ref)) <= RTOL * max(np.max(np.abs(y_ref)), 1e-300) * 10, what
+
+
+def _gpu_apply_canonical(S, psi, dev):
+    import torch
+    x = S.import_(torch.from_numpy(psi).to(dev))
+    y = S.apply(x)
+    out = S.export(y).cpu().numpy()
+    torch.cuda.synchronize()
+    return out
+
+
+SMALL = []
+_rng = np.random.default_rng(2024)
+for n, mask in [(8, 0b00001111), (10, 0b1001010110), (11, 0b1), (9, 0b111111110), (12, 0b101010101010)]:
+    m = I.random_spin_model(_rng, n, n_bonds=2 * n)
+    for n_up in sorted({0, 1, n // 2, n - 1}):
+        SMALL.append(I.Problem(m, I.Cut("spatial", mask), n_up))
+SMALL.append(I.Problem(I.xxz_chain(7, 1.0, 1.0), I.Cut("spatial", 0), 3))
+SMALL.append(I.Problem(I.xxz_chain(7, 1.0, 1.0), I.Cut("spatial", 0x7f), 3))
+for L in (4, 6, 8, 10):
+    hm = I.random_hubbard_model(_rng, L, n_bonds=2 * L)
+    SMALL.append(I.Problem(hm, I.Cut("updn"), L // 2, L // 2 - 1))
+    SMALL.append(I.Problem(I.hubbard_chain(L, 1.0, 3.5), I.Cut("updn"), L // 2, L // 2))
+SMALL.append(I.Problem(I.hubbard_chain(5, 1.0, 2.0), I.Cut("updn"), 0, 2))
+SMALL.append(I.Problem(I.hubbard_chain(5, 1.0, 2.0), I.Cut("updn"), 5, 5))
+
+
+@pytest.mark.parametrize("k", range(len(SMALL)))
+def test_apply_small_vs_oracle(dev, k):
+    p = SMALL[k]
+    s = O.Sector(p.model, p.n_up, p.n_dn)
+    psi = I.psi(100 + k, s.n)
+    y_ref = s.apply(psi)
+    S = _ecut().Sectors.from_problem(p)
+    _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} n_up={p.n_up}")
+
+
+@pytest.mark.parametrize("name", ["heisenberg16", "hubbard12"])
+def test_apply_workload_full_vs_oracle(dev, name):
+    p = I.WORKLOADS[name]()
+    s = O.Sector(p.model, p.n_up, p.n_dn)
+    psi = I.psi(p.meta["seed"], s.n)
+    y_ref = s.apply(psi)
+    S = _ecut().Sectors.from_problem(p)
+    _compare(_gpu_apply_canonical(S, psi, dev), y_ref, name)
+
+
+@pytest.mark.parametrize("name", ["hubbard16", "j1j2_6x5"])
+def test_apply_full_size_sampled_vs_oracle(dev, name):
+    """Full-size application in the launch configuration the bench times;
+    the oracle recomputes a few thousand sampled rows one by one."""
+    import torch
+    p = I.WORKLOADS[name]()
+    words = O.enumerate_basis(p.model.kind, p.model.n_sites, p.n_up, p.n_dn)
+    n = len(words)
+    psi = I.psi(p.meta["seed"], n)
+    S = _ecut().Sectors.from_problem(p)
+    y = _gpu_apply_canonical(S, psi, dev)
+    rng = np.random.default_rng(5)
+    rows = np.unique(np.concatenate([rng.integers(0, n, 3000), [0, 1, n // 2, n - 2, n - 1]]))
+    sec = O.Sector.__new__(O.Sector)
+    sec.model, sec.om, sec.words, sec.n = p.model, O.OracleModel(p.model), words, n
+    y_ref = sec.apply_rows(psi, rows)
+    err = np.abs(y[rows] - y_ref)
+    assert np.max(err) <= RTOL * np.max(np.abs(y_ref)) * 10
+    assert np.linalg.norm(err) / np.linalg.norm(y_ref) <= RTOL
+    # Hermiticity at full size on the device: <phi|H psi> = <H phi|psi>
+    x = torch.from_numpy(psi).to(dev)
+    phi = torch.from_numpy(I.psi(p.meta["seed"] + 2, n)).to(dev)
+    xb, pb = S.import_(x), S.import_(phi)
+    lhs = torch.dot(pb, S.apply(xb)).item()
+    rhs = torch.dot(S.apply(pb), xb).item()
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+
+
+def test_apply_is_deterministic_and_batch_bit_exact(dev):
+    import torch
+    ecut = _ecut()
+    probs = [SMALL[3], SMALL[9], I.heisenberg16(), I.hubbard12(), SMALL[-3]]
+    Ss = [ecut.Sectors.from_problem(p) for p in probs]
+    xs = [torch.from_numpy(I.psi(300 + k, S.dim)).to(dev) for k, S in enumerate(Ss)]
+    alone = [S.apply(x) for S, x in zip(Ss, xs)]
+    again = [S.apply(x) for S, x in zip(Ss, xs)]
+    ys = [torch.empty_like(x) for x in xs]
+    ecut.apply_batch(Ss, xs, ys)
+    torch.cuda.synchronize()
+    for k, S in enumerate(Ss):
+        assert torch.equal(alone[k], again[k])
+        if S.info.kernel == 2:
+            assert torch.equal(alone[k], ys[k]), f"batch differs for problem {k}"
+        else:
+            torch.testing.assert_close(alone[k], ys[k], rtol=1e-13, atol=1e-13)
+
+
+def test_lanczos_heisenberg16_vs_oracle(dev):
+    import torch
+    p = I.heisenberg16()
+    s = O.Sector(p.model, 8)
+    e_ref = s.lanczos(I.psi(p.meta["seed"] + 1, s.n), 200, tol=1e-14)[0][-1]
+    S = _ecut().Sectors.from_problem(p)
+    v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, s.n)).to(dev))
+    e, st, _ = S.lanczos(v0, 100, fixed_steps=True)
+    assert st["steps"] == 100
+    assert abs(e - e_ref) <= 1e-10
+    e2, st2, _ = S.lanczos(v0, 400, tol=1e-10)
+    assert abs(e2 - e_ref) <= 1e-10 and st2["converged"] == 1
+
+
+def test_lanczos_hubbard12_vs_oracle(dev):
+    import torch
+    p = I.hubbard12()
+    s = O.Sector(p.model, 6, 6)
+    e_ref = s.lanczos(I.psi(p.meta["seed"] + 1, s.n), 400, tol=1e-13)[0][-1]
+    S = _ecut().Sectors.from_problem(p)
+    v0 = torch.from_numpy(I.psi(p.meta["seed"] + 1, s.n)).to(dev)
+    e, st, _ = S.lanczos(v0, 200, fixed_steps=True)
+    assert st["steps"] == 200
+    assert abs(e - e_ref) <= 1e-10
+
+
+def test_lanczos_reorth_ground_state_vector(dev):
+    import torch
+    p = I.Problem(I.xxz_chain(14, 1.0, 0.6), I.Cut("spatial", I.left_mask_first(7)), 7)
+    s = O.Sector(p.model, 7)
+    H = s.dense()
+    w, V = np.linalg.eigh(H)
+    S = _ecut().Sectors.from_problem(p)
+    v0 = torch.from_numpy(I.psi(9, s.n)).to(dev)
+    e, st, gs = S.lanczos(v0, 60, tol=1e-11, reorth=True, max_restarts=4, want_gs=True)
+    assert abs(e - w[0]) <= 1e-10
+    g = S.export(gs).cpu().numpy()
+    assert abs(abs(g @ V[:, 0]) - 1.0) <= 1e-8
+    # H g = E g through the device H*psi
+    hg = S.export(S.apply(gs)).cpu().numpy()
+    assert np.linalg.norm(hg - e * g) <= 1e-6
+
+
+def test_lanczos_u0_hubbard16_closed_form(dev):
+    """16-site chain at U=0 (the headline geometry): free-fermion energy."""
+    import torch
+    p = I.hubbard16(U=0.0)
+    S = _ecut().Sectors.from_problem(p)
+    eps = np.sort(-2.0 * np.cos(np.arange(1, 17) * np.pi / 17))
+    e_ref = 2 * eps[:8].sum()
+    assert e_ref == pytest.approx(-19.675902894918842, abs=1e-12)
+    v0 = torch.empty(S.dim, dtype=torch.float64, device=dev).normal_(generator=torch.Generator(dev).manual_seed(1))
+    e, st, _ = S.lanczos(v0, 400, tol=1e-11)
+    assert abs(e - e_ref) <= 1e-10
+
+
+def test_zero_start_vector_is_rejected(dev):
+    import torch
+    ecut = _ecut()
+    S = ecut.Sectors.from_problem(I.heisenberg16())
+    with pytest.raises(ecut.EcutError) as ei:
+        S.lanczos(torch.zeros(S.dim, dtype=torch.float64, device=dev), 10, tol=1e-10)
+    assert ei.value.status == ecut.ECUT_EINVAL
+
+
+def test_not_converged_status(dev):
+    import torch
+    ecut = _ecut()
+    S = ecut.Sectors.from_problem(I.heisenberg16())
+    v0 = torch.from_numpy(I.psi(1, S.dim)).to(dev)
+    e, st, _ = S.lanczos(v0, 3, tol=1e-12, allow_notconv=True)
+    assert st["status"] == ecut.ECUT_ENOTCONV and st["steps"] == 3
+
+
+def _serving_mix():
+    reqs = []
+    for n, d in [(12, 0.7), (14, 1.5), (10, 1.0), (16, 0.55)]:
+        reqs.append(I.Problem(I.xxz_chain(n, 1.0, d), I.Cut("spatial", I.left_mask_first(n // 2)), n // 2))
+    for L, U in [(8, 0.0), (8, 6.0), (10, 3.0), (6, 9.0)]:
+        reqs.append(I.Problem(I.hubbard_chain(L, 1.0, U), I.Cut("updn"), L // 2, L // 2))
+    return reqs
+
+
+def test_server_batched_vs_alone_vs_oracle(dev):
+    ecut = _ecut()
+    reqs = _serving_mix()
+    refs = []
+    for p in reqs:
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        refs.append(s.lanczos(I.psi(3, s.n), 600, tol=1e-14)[0][-1])
+    results = {}
+    for mode in ("alone", "mix"):
+        srv = ecut.Server(2 << 30, max_active=(1 if mode == "alone" else 0), max_steps=600, tol=1e-10,
+                          sequential=(mode == "alone"))
+        ids = [srv.submit(p, seed=1000 + k) for k, p in enumerate(reqs)]
+        srv.drain()
+        res = {r["req_id"]: r for r in srv.poll()}
+        srv.close()
+        results[mode] = [res[i] for i in ids]
+    for k in range(len(reqs)):
+        a, m = results["alone"][k], results["mix"][k]
+        assert a["status"] == 0 and m["status"] == 0
+        assert abs(a["energy"] - refs[k]) <= 1e-10, (k, a["energy"], refs[k])
+        assert abs(m["energy"] - refs[k]) <= 1e-10, (k, m["energy"], refs[k])
+        assert abs(a["energy"] - m["energy"]) <= 1e-10
+        assert a["steps"] == m["steps"]
+
+
+def test_server_budget_admission(dev):
+    """A budget that holds one request at a time still serves them all
+    (admission waits for memory); a request larger than the budget fails."""
+    ecut = _ecut()
+    small = I.Problem(I.xxz_chain(12, 1.0, 1.0), I.Cut("spatial", I.left_mask_first(6)), 6)
+    big = I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", I.left_mask_first(10)), 10)
+    one = 3 * 8 * math.comb(12, 6) + (1 << 16)
+    srv = ecut.Server(int(one * 1.5), max_active=0, max_steps=400, tol=1e-10)
+    ids = [srv.submit(small, seed=k) for k in range(3)] + [srv.submit(big, seed=9)]
+    srv.drain()
+    res = {r["req_id"]: r for r in srv.poll()}
+    srv.close()
+    assert all(res[i]["status"] == 0 for i in ids[:3])
+    assert res[ids[3]]["status"] == ecut.ECUT_ENOMEM
+    e = [res[i]["energy"] for i in ids[:3]]
+    assert max(e) - min(e) <= 1e-10

@@ -1,0 +1,120 @@
+"""Host-side tests of libecut (no GPU): the library loads and exports every
+declared symbol, the sector builder's bases, blocks and canonical->bipartite
+positions equal the oracle's enumeration bit for bit, and argument errors
+come back as status codes."""
+import math
+import re
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2605_07621_amd import inputs as I
+from paper_2605_07621_amd import ecut as E
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "ecut.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b(ecut_[A-Za-z_0-9]+)\s*\(", hdr))
+    assert len(declared) >= 18
+    L = E.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    bound = {n for n, _, _ in E.SYMBOLS}
+    assert declared == bound
+    assert b"gfx950" in L.ecut_version()
+
+
+def _oracle_blocks_and_pos(p):
+    s = O.Sector(p.model, p.n_up, p.n_dn)
+    pos, blocks = s.bipartite(p.cut.kind, p.cut.left_mask)
+    return s, pos, blocks
+
+
+CASES = [
+    I.heisenberg16(),
+    I.hubbard12(),
+    I.Problem(I.xxz_chain(10, 1.0, 0.7), I.Cut("spatial", 0b1000110101), 5),
+    I.Problem(I.xxz_chain(9, 1.0, 1.3), I.Cut("spatial", 0b1), 3),
+    I.Problem(I.xxz_chain(7, 1.0, 1.0), I.Cut("spatial", 0), 3),          # empty left part
+    I.Problem(I.xxz_chain(7, 1.0, 1.0), I.Cut("spatial", 0b1111111), 2),  # empty right part
+    I.Problem(I.j1j2_lattice(4, 3), I.Cut("spatial", I.left_mask_first(6)), 6),
+    I.Problem(I.hubbard_chain(6, 1.0, 3.0), I.Cut("updn"), 2, 4),
+    I.Problem(I.hubbard_chain(5, 1.0, 3.0), I.Cut("updn"), 0, 5),
+]
+
+
+@pytest.mark.parametrize("p", CASES, ids=lambda p: f"{p.model.name}-{p.cut.kind}-{p.n_up}-{p.n_dn}")
+def test_blocks_words_positions_bit_exact(p):
+    S = E.Sectors.from_problem(p, host_only=True)
+    s, pos, oblocks = _oracle_blocks_and_pos(p)
+    blocks = S.blocks()
+    assert S.dim == s.n
+    assert blocks.shape[0] == oblocks.shape[0]
+    np.testing.assert_array_equal(blocks[:, 0], oblocks[:, 0])   # q_l
+    np.testing.assert_array_equal(blocks[:, 2], oblocks[:, 1])   # d_L
+    np.testing.assert_array_equal(blocks[:, 3], oblocks[:, 2])   # d_R
+    np.testing.assert_array_equal(blocks[:, 4], oblocks[:, 3])   # offsets
+    np.testing.assert_array_equal(S.canonical_positions(), pos)
+    for b in range(blocks.shape[0]):
+        lw, rw = S.words(b)
+        if p.cut.kind == "spatial":
+            n_left = bin(p.cut.left_mask).count("1")
+            n_right = p.model.n_sites - n_left
+        else:
+            n_left = n_right = p.model.n_sites
+        ql, qr = int(blocks[b, 0]), int(blocks[b, 1])
+        np.testing.assert_array_equal(lw.astype(np.uint64), O.enumerate_bruteforce(n_left, ql) if n_left else [0])
+        np.testing.assert_array_equal(rw.astype(np.uint64), O.enumerate_bruteforce(n_right, qr) if n_right else [0])
+
+
+def test_workload_block_structure():
+    S = E.Sectors.from_problem(I.heisenberg16(), host_only=True)
+    b = S.blocks()
+    assert list(b[:, 2] * b[:, 3]) == [math.comb(8, k) ** 2 for k in range(9)]
+    S4 = E.Sectors.from_problem(I.j1j2_6x5(), host_only=True)
+    b4 = S4.blocks()
+    assert b4.shape[0] == 16 and S4.dim == 155117520
+    assert list(b4[:, 2] * b4[:, 3]) == [math.comb(15, k) ** 2 for k in range(16)]
+    # a straight cut between x=2 and x=3 of the 6x5 lattice crosses 5 J1 and 8 J2 bonds
+    assert S4.info.n_cut_bonds == 13 and S4.info.n_cross_offdiag == 26 and S4.info.n_cross_diag == 13
+    S3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)
+    assert S3.dim == 165636900 and S3.info.kernel == 1
+    assert S3.info.n_eff == pytest.approx(1.0)
+
+
+def test_n_eff_is_block_participation_number():
+    S = E.Sectors.from_problem(I.heisenberg16(), host_only=True)
+    b = S.blocks()
+    w = (b[:, 2] * b[:, 3]) / S.dim
+    assert S.info.n_eff == pytest.approx(1.0 / np.sum(w * w), rel=1e-12)
+
+
+def _status(fn):
+    try:
+        fn()
+    except E.EcutError as e:
+        return e.status
+    return E.ECUT_OK
+
+
+def test_error_paths():
+    m = I.heisenberg_chain(6)
+    assert _status(lambda: E.Sectors(m, I.Cut("updn"), 3, host_only=True)) == E.ECUT_EINVAL
+    assert _status(lambda: E.Sectors(m, I.Cut("spatial", 0b111), 7, host_only=True)) == E.ECUT_EINVAL
+    assert _status(lambda: E.Sectors(m, I.Cut("spatial", 1 << 9), 3, host_only=True)) == E.ECUT_EINVAL
+    h = I.hubbard_chain(6)
+    assert _status(lambda: E.Sectors(h, I.Cut("spatial", 0b111), 3, 3, host_only=True)) == E.ECUT_EUNSUPPORTED
+    assert _status(lambda: E.Sectors(h, I.Cut("updn"), 3, 7, host_only=True)) == E.ECUT_EINVAL
+    bad = I.Model("spin", 4, np.array([[0, 0]], dtype=np.int32), jxy=np.ones(1), jz=np.ones(1))
+    assert _status(lambda: E.Sectors(bad, I.Cut("spatial", 0b11), 2, host_only=True)) == E.ECUT_EINVAL
+    big = I.xxz_chain(40)
+    assert _status(lambda: E.Sectors(big, I.Cut("spatial", (1 << 35) - 1), 20, host_only=True)) == E.ECUT_EUNSUPPORTED
+    # device calls on a host-only handle are rejected before any device work
+    S = E.Sectors(m, I.Cut("spatial", 0b111), 3, host_only=True)
+    st = E.lib().ecut_apply_H(S.h, None, None, None)
+    assert st == E.ECUT_EINVAL
