@@ -180,6 +180,47 @@ ecut_status ecut_apply_H(const ecut_sectors *s, const double *psi_d, double *y_d
 ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
                                double *const *y_d, void *stream);
 
+/*
+ * Launch tuning of ecut_apply_H (used by the Hubbard up/down kernel, whose
+ * work groups each own one row of Psi at a time):
+ *   grid:      work groups (0 = one per compute unit);
+ *   n_xcd:     rows are split into n_xcd contiguous chunks of the row order,
+ *              chunk k served by the work groups with blockIdx % n_xcd == k
+ *              (the accelerator complex that dispatches them), so rows that
+ *              share neighbours share an L2 (0 = 8, 1 = plain grid stride);
+ *   row_order: 0 increasing row index; 1 by inversion level of the left word
+ *              (a nearest-neighbour hop changes it by exactly one, so all
+ *              left-operator neighbours of a row sit in the adjacent levels);
+ *              2 segment-major: rows grouped by the high half of the left
+ *              word, groups ordered by the inversion level of that half;
+ *              3..5: as 0..2 with the column classes of one row processed
+ *              together instead of one class after the other;
+ *   variant:   0 class tiles (rows cut into classes of down words, several
+ *              work groups per CU), 1 whole rows staged in LDS.
+ * ecut_set_tuning re-uploads the row order (synchronous).  Not to be called
+ * while an ecut_apply_H on the same handle is in flight.
+ */
+typedef struct ecut_tuning {
+    int32_t grid;
+    int32_t n_xcd;
+    int32_t row_order;
+    int32_t variant;
+} ecut_tuning;
+
+ecut_status ecut_get_tuning(const ecut_sectors *s, ecut_tuning *t);
+ecut_status ecut_set_tuning(ecut_sectors *s, const ecut_tuning *t);
+
+/*
+ * Autotuner: times ecut_apply_H(x_d -> y_d) for each candidate launch tuning
+ * (grid, XCD chunking, row order) with HIP events on `stream`, keeps the
+ * fastest on the handle and returns it in *best (nullable).  x_d, y_d: dim
+ * doubles each (contents of y_d are overwritten).  If the environment
+ * variable ECUT_TUNE_CACHE names a JSON file, results are read from and
+ * written to it, keyed by device architecture and problem shape.
+ * Synchronous.
+ */
+ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void *stream, ecut_tuning *best);
+
 /* Options of the Lanczos ground-state solver. */
 typedef struct ecut_lanczos_opts {
     int32_t max_steps;        /* Krylov steps per restart cycle, >= 1 */

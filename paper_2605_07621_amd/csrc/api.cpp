@@ -104,9 +104,9 @@ void release_device(ecut_sectors *s) {
     if (s->dev_mem) {
         int cur = 0;
         hipGetDevice(&cur);
-        if (s->device >= 0 && s->device != cur) hipSetDevice(s->device);
-        hipFree(s->dev_mem);
-        if (s->device >= 0 && s->device != cur) hipSetDevice(cur);
+        if (s->device >= 0 && s->device != cur) (void)hipSetDevice(s->device);
+        (void)hipFree(s->dev_mem);
+        if (s->device >= 0 && s->device != cur) (void)hipSetDevice(cur);
     }
     s->dev_mem = nullptr;
     s->on_device = false;
@@ -138,6 +138,26 @@ ecut_status upload(ecut_sectors *s) {
         o_u = A.add(s->hub_u);
         o_rw16 = A.add(s->hub_rw16);
         o_order = A.add(s->row_order);
+    }
+    size_t o_hcc = 0, o_hsc = 0, o_hhw = 0, o_hhc = 0, o_hhe = 0, o_hlw = 0, o_hlcn = 0, o_hle = 0, o_hit = 0;
+    if (s->hub_ok) {
+        o_hcc = A.add(s->hc_cls);
+        o_hsc = A.add(s->hc_segcol);
+        o_hhw = A.add(s->hc_hiw);
+        o_hhc = A.add(s->hc_hicnt);
+        o_hhe = A.add(s->hc_hient);
+        o_hlw = A.add(s->hc_low);
+        o_hlcn = A.add(s->hc_locnt);
+        o_hle = A.add(s->hc_loent);
+        o_hit = A.add(s->hub_items_ord);
+    }
+    size_t o_3si = 0, o_3li = 0, o_3lo = 0, o_3hn = 0, o_3hc = 0;
+    if (s->hub3_ok) {
+        o_3si = A.add(s->h3_seginfo);
+        o_3li = A.add(s->h3_loinfo);
+        o_3lo = A.add(s->h3_looff);
+        o_3hn = A.add(s->h3_hnb);
+        o_3hc = A.add(s->h3_hcnt);
     }
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, A.off);
@@ -188,6 +208,37 @@ ecut_status upload(ecut_sectors *s) {
         H.rwords16 = s->hub_rw16.empty() ? nullptr : (const uint16_t *)(b + o_rw16);
         H.rwords32 = P.rwords + s->blocks[0].rbase;
         s->dev_row_order = (int32_t *)(b + o_order);
+        H.cls = (const int32_t *)(b + o_hcc);
+        H.cls_segcol = (const int32_t *)(b + o_hsc);
+        H.cls_hiw = (const int32_t *)(b + o_hhw);
+        H.cls_hicnt = (const int32_t *)(b + o_hhc);
+        H.cls_hient = (const int32_t *)(b + o_hhe);
+        H.cls_low = (const int32_t *)(b + o_hlw);
+        H.cls_locnt = (const int32_t *)(b + o_hlcn);
+        H.cls_loent = (const int32_t *)(b + o_hle);
+        s->dev_hub_items = (HubItem *)(b + o_hit);
+    }
+    if (s->hub3_ok) {
+        Hub3Args &A3 = s->h3;
+        A3 = Hub3Args{};
+        A3.hop = s->hub.hop0;
+        A3.u0 = s->hub.u0;
+        A3.hl_ptr = P.hl_ptr;
+        A3.hl_col = P.hl_col;
+        A3.lwords = P.lwords;
+        A3.cls = P.hub.cls;
+        A3.seginfo = (const int4 *)(b + o_3si);
+        A3.loinfo = (const int4 *)(b + o_3li);
+        A3.looff = (const int32_t *)(b + o_3lo);
+        A3.hnb = (const int32_t *)(b + o_3hn);
+        A3.hcnt = (const int32_t *)(b + o_3hc);
+        A3.items = s->dev_hub_items;
+        A3.n_items = (int32_t)s->hub_items.size();
+        A3.dR = s->blocks[0].d_r;
+        A3.h = s->hub.h;
+        A3.hs = s->h3_hs;
+        A3.max_tile = s->h3_max_tile;
+        A3.max_nseg = s->hub.max_nseg;
     }
     s->dev_mem = mem;
     s->dev_bytes = A.off;
@@ -210,12 +261,31 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
     if (rs != ECUT_OK) return rs;
     hipError_t e;
     if (s->kernel == 1) {
-        if (hub_lds_bytes(s) > g_last_max_lds)
-            return fail(ECUT_EUNSUPPORTED, "Hubbard kernel tables exceed the device's LDS per work group");
         const ApplyTuning &T = s->tune;
         const int n_xcd = T.n_xcd > 0 ? T.n_xcd : 8;
-        const int grid = T.grid > 0 ? T.grid : n_cu;
-        e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
+        if (T.variant == 0 && s->hub3_ok) {
+            const size_t lds = hub3_lds_bytes(s);
+            if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "class tiles exceed the device's LDS per work group");
+            const int grid = T.grid > 0 ? T.grid : n_cu * hub_blocks_per_cu(3, lds);
+            Hub3Args A3 = s->h3;
+            A3.x = P.x;
+            A3.y = P.y;
+            A3.z = P.z;
+            A3.partials = P.partials;
+            A3.xscale = P.xscale;
+            A3.zcoef = P.zcoef;
+            e = launch_hub3(s, A3, grid, n_xcd, st);
+        } else if ((T.variant == 0 || T.variant == 2) && s->hub2_ok) {
+            const size_t lds = hub2_lds_bytes(s);
+            if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "class tiles exceed the device's LDS per work group");
+            const int grid = T.grid > 0 ? T.grid : n_cu * hub_blocks_per_cu(2, lds);
+            e = launch_hub2(s, P, s->dev_hub_items, (int)s->hub_items.size(), grid, n_xcd, st);
+        } else {
+            if (hub_lds_bytes(s) > g_last_max_lds)
+                return fail(ECUT_EUNSUPPORTED, "Hubbard kernel tables exceed the device's LDS per work group");
+            const int grid = T.grid > 0 ? T.grid : n_cu;
+            e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
+        }
     } else {
         e = launch_rows(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
     }
@@ -225,7 +295,15 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
 
 // number of partial slots the apply kernel writes
 int32_t apply_partial_slots(const ecut_sectors *s) {
-    return s->kernel == 1 ? s->blocks[0].d_l : (int32_t)s->items.size();
+    if (s->kernel != 1) return (int32_t)s->items.size();
+    const bool tiles = (s->tune.variant == 0 && (s->hub3_ok || s->hub2_ok)) || (s->tune.variant == 2 && s->hub2_ok);
+    return tiles ? (int32_t)s->hub_items.size() : s->blocks[0].d_l;
+}
+
+// workspace size: either Hubbard variant may run on the same workspace
+int32_t apply_partial_slots_max(const ecut_sectors *s) {
+    return s->kernel == 1 ? std::max<int32_t>(s->blocks[0].d_l, (int32_t)s->hub_items.size())
+                          : (int32_t)s->items.size();
 }
 
 // ---------------------------------------------------------------- staging buffers

@@ -1,6 +1,8 @@
 // Internal structures of libecut: host-side sector description and the
 // device-side descriptors the HIP kernels read.  Not part of the ABI.
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -81,6 +83,54 @@ struct HubDev {
     const double *u;             // [n_sites] U_i
     const uint16_t *rwords16;    // [d_r] down words (n_r <= 16) or NULL
     const uint32_t *rwords32;    // [d_r] down words
+    // Class tiles.  The down basis splits into classes by the popcount k of
+    // the high part; a class is nseg segments (one per high word) of L
+    // consecutive columns (one per low word of count N_dn - k).  Hops inside
+    // lo or inside hi stay in the class, so one (row, class) tile holds every
+    // operand of the right operator except the crossing bonds.
+    int32_t n_cls;
+    int32_t cls_lo_stride, cls_hi_stride;
+    int32_t max_tile;            // largest rows_per_item * L * nseg
+    int32_t max_nseg;
+    int32_t pad_;
+    const int32_t *cls;          // [n_cls][8]: L, nseg, seg_base, lo_base, rows_per_item, L*nseg, 0, 0
+    const int32_t *cls_segcol;   // [seg_base + s] flat column of segment s
+    const int32_t *cls_hiw;      // [seg_base + s] high word of segment s
+    const int32_t *cls_hicnt;    // [seg_base + s] entries in the segment's high-hop list
+    const int32_t *cls_hient;    // [(seg_base + s) * cls_hi_stride + q] packed (dseg << 9) | (neg << 8) | coef_idx
+    const int32_t *cls_low;      // [lo_base + j] low word of rank j
+    const int32_t *cls_locnt;    // [lo_base + j]
+    const int32_t *cls_loent;    // [(lo_base + j) * cls_lo_stride + q] packed (dj << 9) | (neg << 8) | coef_idx
+};
+
+// Arguments of the fast class-tile kernel (open chains: every hop of either
+// spin is -t with a plus sign, U uniform, at most one bond across the lo/hi
+// split of the down word and it joins bits h-1 and h).  Tiles are stored
+// with a row stride of L+1 doubles whose last element is zero, so inactive
+// low-hop entries point at it and every gather is unconditional.
+struct Hub3Args {
+    const double *x;
+    double *y;
+    const double *z;
+    double *partials;
+    double xscale, zcoef, hop, u0;
+    const int32_t *hl_ptr, *hl_col;   // up-spin hop rows
+    const uint32_t *lwords;           // up words
+    const int32_t *cls;               // [n_cls][8] as HubDev::cls
+    const int4 *seginfo;              // [seg]: column, high word, crossing column, crossing bit (2 = none)
+    const int4 *loinfo;               // [lo]: low word, crossing low rank, crossing bit (2 = none), 0
+    const int32_t *looff;             // [lo][8] low-hop offsets j'-j, or L-j (the zero pad) if unused
+    const int32_t *hnb;               // [seg][hs] high-hop neighbour segment index
+    const int32_t *hcnt;              // [seg] entries of hnb in use
+    const struct HubItem *items;
+    int32_t n_items, n_xcd, per_xcd, dR;
+    int32_t h, hs, max_tile, max_nseg;
+};
+
+// Work item of the class-tile kernel: rows [row0, row0 + nrows) of one class;
+// slot is the item's index in the order-independent item list.
+struct HubItem {
+    int32_t row0, nrows, cls, slot;
 };
 
 struct ProblemDev {
@@ -110,10 +160,10 @@ struct ProblemDev {
 
 // Launch parameters of the Hubbard kernel chosen by the autotuner.
 struct ApplyTuning {
-    int32_t grid;     // work groups (0 = one per CU)
-    int32_t n_xcd;    // XCD-contiguous row chunks (0 = 8)
-    int32_t order;    // row order: 0 increasing, 1 segment-major by level
-    int32_t pad;
+    int32_t grid;     // work groups (0 = default)
+    int32_t n_xcd;    // XCD-contiguous work chunks (0 = 8)
+    int32_t order;    // row order: 0 increasing, 1 by inversion level, 2 segment-major by level
+    int32_t variant;  // Hubbard kernel: 0 class tiles, 1 whole rows
 };
 
 // Work item: rows [row0, row1) of block `block` of problem `prob`; `slot`
@@ -148,10 +198,18 @@ struct ecut_sectors {
     int32_t n_cut_bonds = 0;
     // Hubbard up/down kernel tables (host copies)
     bool hub_ok = false;
+    bool hub2_ok = false;
+    bool hub3_ok = false;                // fast class-tile kernel applies
+    std::vector<int32_t> h3_seginfo, h3_loinfo, h3_looff, h3_hnb, h3_hcnt;
+    int32_t h3_hs = 1, h3_max_tile = 0;
+    ecut::Hub3Args h3{};                 // device pointers (launch fields filled per call)
     ecut::HubDev hub{};
     std::vector<int32_t> hub_lo_cnt, hub_lo_ent, hub_lo_rank, hub_hi_cnt, hub_hi_ent, hub_seg_off, hub_xb;
     std::vector<double> hub_coef, hub_u;
     std::vector<uint16_t> hub_rw16;
+    std::vector<int32_t> hc_cls, hc_segcol, hc_hiw, hc_hicnt, hc_hient, hc_low, hc_locnt, hc_loent;
+    std::vector<ecut::HubItem> hub_items;         // class-tile items, slot order
+    std::vector<ecut::HubItem> hub_items_ord;     // class-tile items, processing order
     // default work items of a single application
     std::vector<ecut::ItemDev> items;
     std::vector<int32_t> row_order;       // Hubbard kernel: row processing order
@@ -165,11 +223,14 @@ struct ecut_sectors {
     ecut::ProblemDev prob{};              // pointers into dev_mem
     ecut::ItemDev *dev_items = nullptr;
     int32_t *dev_row_order = nullptr;
+    ecut::HubItem *dev_hub_items = nullptr;
     double n_eff = 0.0;
 };
 
 namespace ecut {
 ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qnum q, ecut_sectors *s);
 ecut_status upload(ecut_sectors *s);
+void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
+void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 void release_device(ecut_sectors *s);
 }  // namespace ecut

@@ -13,6 +13,11 @@ constexpr int ROWS_THREADS = 256;
 constexpr size_t ROWS_MAX_LDS = 64 * 1024;   // generic kernel stages tiles up to this size
 constexpr int HUB_THREADS = 1024;
 constexpr int HUB_MAXC = 16;                 // columns per thread: d_R <= HUB_THREADS * HUB_MAXC
+constexpr int HUB2_THREADS = 512;
+constexpr int HUB2_M = 16;                   // element passes per thread and item
+constexpr int HUB2_LOREG = 8;                // low-hop entries kept in registers
+constexpr int HUB2_NB = 8;
+constexpr int HUB3_M = 12;                   // element slots per thread and item in the fast kernel                   // left-operator neighbour loads issued together per element
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
 constexpr int MAX_BASIS = 1024;              // CGS2: vectors per projection call
@@ -38,6 +43,12 @@ hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, cons
                        int max_tile_elems, hipStream_t st);
 hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
                       int n_xcd, hipStream_t st);
+size_t hub2_lds_bytes(const ecut_sectors *s);
+hipError_t launch_hub2(const ecut_sectors *s, const ProblemDev &prob, const HubItem *items_d, int n_items, int grid,
+                       int n_xcd, hipStream_t st);
+size_t hub3_lds_bytes(const ecut_sectors *s);
+hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, hipStream_t st);
+int hub_blocks_per_cu(int which, size_t lds);
 hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
                        double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);

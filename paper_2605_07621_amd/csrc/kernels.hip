@@ -274,6 +274,424 @@ __global__ __launch_bounds__(HUB_THREADS) void k_hub(const ProblemDev P, const i
     }
 }
 
+// ------------------------------------------------------------------------
+// Hubbard up/down kernel on class tiles.  A work item is (rows, class): the
+// elements of rows [row0, row0+nrows) whose down word has a high part of
+// popcount k.  Inside the tile, with T[sr][j] (sr = row * nseg + segment,
+// j = low-word rank), a hop inside the low part is a gather along j with
+// j-only offsets (kept in registers: each thread keeps one j for the whole
+// item), a hop inside the high part is a shift along sr by a per-segment
+// offset, so both stay in LDS.  Phase 1 (global): the left operator as a
+// combination of neighbour rows restricted to the tile's columns, the
+// crossing bonds of the down word (their sources sit in the neighbouring
+// classes of the same row) and the staging of the tile.  Phase 2 (LDS): the
+// right operator, the diagonal, the Lanczos epilogue and the store.  Tiles
+// are at most a few tens of KB, so several work groups share a CU and one's
+// LDS phase overlaps another's memory phase.
+// ------------------------------------------------------------------------
+template <bool UU, bool UT>
+__global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const HubItem *__restrict__ items,
+                                                       int n_items, int n_xcd, int per_xcd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[HUB2_THREADS / 64];
+    const HubDev &H = P.hub;
+    const int dR = P.blocks[0].d_r;
+    const int h = H.h;
+    const int nhi = 1 << (H.n_r - h), nlo = 1 << h;
+    const int hs = H.cls_hi_stride, ls = H.cls_lo_stride;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        unsigned char *p = smem + off;
+        off += (bytes + 15) & ~(size_t)15;
+        return p;
+    };
+    double *xs = (double *)carve((size_t)H.max_tile * 8);
+    int32_t *segcol = (int32_t *)carve((size_t)H.max_nseg * 4);
+    int32_t *hiw = (int32_t *)carve((size_t)H.max_nseg * 4);
+    int32_t *hicnt = (int32_t *)carve((size_t)H.max_nseg * 4);
+    int32_t *hient = (int32_t *)carve((size_t)H.max_nseg * hs * 4);
+    int32_t *segoff = (int32_t *)carve((size_t)nhi * 4);
+    int32_t *lorank = (int32_t *)carve((size_t)nlo * 4);
+    double *cf = (double *)carve((size_t)(H.n_coef > 0 ? H.n_coef : 1) * 8);
+
+    const int tid = threadIdx.x;
+    const int NT = blockDim.x;
+    for (int i = tid; i < nhi; i += NT) segoff[i] = H.seg_off[i];
+    for (int i = tid; i < nlo; i += NT) lorank[i] = H.lo_rank[i];
+    for (int i = tid; i < H.n_coef; i += NT) cf[i] = H.coef[i];
+
+    const int xcd = blockIdx.x % n_xcd;
+    const int wslot = blockIdx.x / n_xcd;
+    const int nslot = gridDim.x / n_xcd;
+    const double *__restrict__ X = P.x;
+    int loaded = -1;
+    for (int k = wslot; k < per_xcd; k += nslot) {
+        const int idx = xcd * per_xcd + k;
+        if (idx >= n_items) break;
+        const HubItem it = items[idx];
+        const int32_t *cd = H.cls + 8 * it.cls;
+        const int L = cd[0], nseg = cd[1], seg_base = cd[2], lo_base = cd[3];
+        if (it.cls != loaded) {
+            __syncthreads();   // previous item's readers of the class tables are done
+            for (int i = tid; i < nseg; i += NT) {
+                segcol[i] = H.cls_segcol[seg_base + i];
+                hiw[i] = H.cls_hiw[seg_base + i];
+                hicnt[i] = H.cls_hicnt[seg_base + i];
+            }
+            for (int i = tid; i < nseg * hs; i += NT) hient[i] = H.cls_hient[seg_base * hs + i];
+            loaded = it.cls;
+            __syncthreads();
+        }
+        const int per_pass = NT / L;
+        const int p = tid / L;
+        const int j = tid - p * L;
+        const bool active = p < per_pass;
+        const int nsr = it.nrows * nseg;
+        const float inv_nseg = 1.0f / (float)nseg;
+        int lon = 0;
+        int loe[HUB2_LOREG];
+        uint32_t lw = 0;
+        if (active) {
+            lon = H.cls_locnt[lo_base + j];
+            lw = (uint32_t)H.cls_low[lo_base + j];
+#pragma unroll
+            for (int q = 0; q < HUB2_LOREG; ++q) loe[q] = q < lon ? H.cls_loent[(lo_base + j) * ls + q] : 0;
+        }
+        // phase 1: stage the tile
+        for (int sr = p; active && sr < nsr; sr += per_pass) {
+            const int r = (int)(((float)sr + 0.5f) * inv_nseg);
+            const int s = sr - r * nseg;
+            xs[sr * L + j] = X[(int64_t)(it.row0 + r) * dR + segcol[s] + j];
+        }
+        __syncthreads();
+        // phase 2: left operator and crossing bonds from global memory, right
+        // operator from LDS, diagonal, epilogue.  Two elements per iteration,
+        // and every global load of both is issued before any is consumed.
+        double part = 0.0;
+        const bool one_row = it.nrows == 1;
+        const int uq0 = P.hl_ptr[it.row0], uq1 = P.hl_ptr[it.row0 + 1];
+        for (int sr0 = p; active && sr0 < nsr; sr0 += 2 * per_pass) {
+            double nb[2][HUB2_NB];
+            double xc[2];
+            int rowv[2], colv[2], sv[2], nqv[2];
+            bool ok[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int sr = sr0 + u * per_pass;
+                ok[u] = sr < nsr;
+                const int srs = ok[u] ? sr : sr0;
+                const int r = (int)(((float)srs + 0.5f) * inv_nseg);
+                const int s = srs - r * nseg;
+                rowv[u] = it.row0 + r;
+                sv[u] = s;
+                colv[u] = segcol[s] + j;
+                const int q0 = one_row ? uq0 : P.hl_ptr[rowv[u]];
+                const int q1 = one_row ? uq1 : P.hl_ptr[rowv[u] + 1];
+                nqv[u] = q1 - q0;
+#pragma unroll
+                for (int q = 0; q < HUB2_NB; ++q)
+                    nb[u][q] = (q < nqv[u]) ? X[(int64_t)P.hl_col[q0 + q] * dR + colv[u]] : 0.0;
+                // crossing bonds of the down word (sources in the neighbouring classes)
+                xc[u] = 0.0;
+                const uint32_t hw = (uint32_t)hiw[s];
+                for (int q = 0; q < H.n_xb; ++q) {
+                    const int lb = H.xb[4 * q], hb = H.xb[4 * q + 1];
+                    if (((lw >> lb) ^ (hw >> hb)) & 1u) {
+                        const uint32_t lo2 = lw ^ (1u << lb), hi2 = hw ^ (1u << hb);
+                        const int col2 = segoff[hi2] + lorank[lo2];
+                        const int par = __popc(lw & ~((2u << lb) - 1u)) + __popc(hw & ((1u << hb) - 1u));
+                        double v = UT ? H.hop0 : cf[H.xb[4 * q + 2]];
+                        if (par & 1) v = -v;
+                        xc[u] += v * X[(int64_t)rowv[u] * dR + col2];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (!ok[u]) continue;
+                const int sr = sr0 + u * per_pass;
+                const int s = sv[u];
+                const int row = rowv[u];
+                const int q0 = one_row ? uq0 : P.hl_ptr[row];
+                double a = 0.0;
+#pragma unroll
+                for (int q = 0; q < HUB2_NB; ++q)
+                    if (q < nqv[u]) a += P.hl_val[q0 + q] * nb[u][q];
+                for (int q = HUB2_NB; q < nqv[u]; ++q)
+                    a += P.hl_val[q0 + q] * X[(int64_t)P.hl_col[q0 + q] * dR + colv[u]];
+                a += xc[u];
+                const int e = sr * L + j;
+                const double xv = xs[e];
+#pragma unroll
+                for (int q = 0; q < HUB2_LOREG; ++q) {
+                    if (q < lon) {
+                        const int en = loe[q];
+                        double v = UT ? H.hop0 : cf[en & 255];
+                        if (en & 256) v = -v;
+                        a += v * xs[e + (en >> 9)];
+                    }
+                }
+                for (int q = HUB2_LOREG; q < lon; ++q) {
+                    const int en = H.cls_loent[(lo_base + j) * ls + q];
+                    double v = UT ? H.hop0 : cf[en & 255];
+                    if (en & 256) v = -v;
+                    a += v * xs[e + (en >> 9)];
+                }
+                {
+                    const int n = hicnt[s];
+                    const int32_t *hq = hient + s * hs;
+                    for (int q = 0; q < n; ++q) {
+                        const int en = hq[q];
+                        double v = UT ? H.hop0 : cf[en & 255];
+                        if (en & 256) v = -v;
+                        a += v * xs[e + (en >> 9) * L];
+                    }
+                }
+                const uint32_t aw = P.lwords[row];
+                const uint32_t bw = ((uint32_t)hiw[s] << h) | lw;
+                double dg = P.diag_l[row];
+                if (UU) {
+                    dg += H.u0 * (double)__popc(aw & bw);
+                } else {
+                    uint32_t both = aw & bw;
+                    while (both) {
+                        const int site = __ffs(both) - 1;
+                        dg += H.u[site];
+                        both &= both - 1u;
+                    }
+                }
+                const int64_t gi = (int64_t)row * dR + colv[u];
+                double y = P.xscale * (a + dg * xv);
+                if (P.z) y -= P.zcoef * P.z[gi];
+                P.y[gi] = y;
+                part += xv * y;
+            }
+        }
+        if (P.partials) {
+            const double sum = block_sum(part, red);
+            if (tid == 0) P.partials[it.slot] = sum;
+        } else {
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Fast class-tile kernel for uniform, sign-free hopping (open chains).
+// Same items and tiles as k_hub2, but: every hop value is the same -t, so
+// all neighbour values are summed first and scaled once; tiles have a row
+// stride of L+1 with a zero in the last slot, which unused low-hop entries
+// address, so the low-hop gathers are unconditional; the up-spin neighbour
+// rows of a one-row item are uniform base pointers, so their loads need no
+// per-lane address arithmetic; the crossing bond's source column splits
+// into a per-segment and a per-lane part that are both precomputed.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[HUB2_THREADS / 64];
+    const int hs = A.hs;
+    double *xs = (double *)smem;
+    int4 *sinf = (int4 *)(smem + (((size_t)A.max_tile * 8 + 15) & ~(size_t)15));
+    int32_t *hnb = (int32_t *)(sinf + A.max_nseg);
+    int32_t *hcnt = hnb + A.max_nseg * hs;
+    const int tid = threadIdx.x;
+    const int NT = blockDim.x;
+    const int dR = A.dR;
+    const int xcd = blockIdx.x % A.n_xcd;
+    const int wslot = blockIdx.x / A.n_xcd;
+    const int nslot = gridDim.x / A.n_xcd;
+    int loaded = -1;
+    for (int k = wslot; k < A.per_xcd; k += nslot) {
+        const int idx = xcd * A.per_xcd + k;
+        if (idx >= A.n_items) break;
+        const HubItem it = A.items[idx];
+        const int32_t *cd = A.cls + 8 * it.cls;
+        const int L = cd[0], nseg = cd[1], seg_base = cd[2], lo_base = cd[3];
+        if (it.cls != loaded) {
+            __syncthreads();
+            for (int i = tid; i < nseg; i += NT) {
+                sinf[i] = A.seginfo[seg_base + i];
+                hcnt[i] = A.hcnt[seg_base + i];
+            }
+            for (int i = tid; i < nseg * hs; i += NT) hnb[i] = A.hnb[seg_base * hs + i];
+            loaded = it.cls;
+            __syncthreads();
+        }
+        const int Lp = L + 1;
+        const int nsr = it.nrows * nseg;
+        const float inv_nseg = 1.0f / (float)nseg;
+        const int per_pass = NT / L;
+        const int p = tid / L;
+        const int j = tid - p * L;
+        const bool active = p < per_pass;
+        const bool one_row = it.nrows == 1;
+        // this thread's element slots: (row r, segment s) = sr = p + m * per_pass
+        int col_m[HUB3_M];
+        double acc[HUB3_M];
+#pragma unroll
+        for (int m = 0; m < HUB3_M; ++m) {
+            const int sr = p + m * per_pass;
+            const bool ok = active && sr < nsr;
+            int r = 0, s = sr;
+            if (!one_row) {
+                r = (int)(((float)sr + 0.5f) * inv_nseg);
+                s = sr - r * nseg;
+            }
+            col_m[m] = ok ? (int)((int64_t)r * dR) + sinf[s].x + j : -1;   // element offset from row0, -1 = unused
+            acc[m] = 0.0;
+        }
+        const double *__restrict__ x0row = A.x + (int64_t)it.row0 * dR;
+        // stage the tile (row stride L+1, zero in the pad slot); every load
+        // of a phase is issued before any result is consumed
+        {
+            double v[HUB3_M];
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m) v[m] = col_m[m] >= 0 ? x0row[col_m[m]] : 0.0;
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m)
+                if (col_m[m] >= 0) xs[(p + m * per_pass) * Lp + j] = v[m];
+            for (int sr = tid; sr < nsr; sr += NT) xs[sr * Lp + L] = 0.0;
+        }
+        // up-spin hops: neighbour rows at the same columns
+        if (one_row) {
+            const int uq0 = A.hl_ptr[it.row0], uq1 = A.hl_ptr[it.row0 + 1];
+            for (int q = uq0; q < uq1; ++q) {
+                const double *__restrict__ xn = A.x + (size_t)A.hl_col[q] * (size_t)dR;
+                double v[HUB3_M];
+#pragma unroll
+                for (int m = 0; m < HUB3_M; ++m) v[m] = col_m[m] >= 0 ? xn[col_m[m]] : 0.0;
+#pragma unroll
+                for (int m = 0; m < HUB3_M; ++m) acc[m] += v[m];
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m) {
+                if (col_m[m] < 0) continue;
+                const int r = (int)(((float)(p + m * per_pass) + 0.5f) * inv_nseg);
+                const int row = it.row0 + r;
+                const int cl = col_m[m] - (int)((int64_t)r * dR);
+                const int q1 = A.hl_ptr[row + 1];
+                for (int q = A.hl_ptr[row]; q < q1; ++q) acc[m] += A.x[(int64_t)A.hl_col[q] * dR + cl];
+            }
+        }
+        // down-spin bond across the lo/hi split (source in a neighbouring class)
+        int4 li = make_int4(0, 0, 2, 0);
+        int lof[8];
+        if (active) {
+            li = A.loinfo[lo_base + j];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lof[q] = A.looff[(lo_base + j) * 8 + q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lof[q] = 0;
+        }
+        {
+            double v[HUB3_M];
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m) {
+                v[m] = 0.0;
+                if (col_m[m] >= 0) {
+                    const int srm = p + m * per_pass;
+                    const int s = one_row ? srm : srm - nseg * (int)(((float)srm + 0.5f) * inv_nseg);
+                    const int4 si = sinf[s];
+                    if ((li.z ^ si.w) == 1) v[m] = x0row[col_m[m] - si.x - j + si.z + li.y];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m) acc[m] += v[m];
+        }
+        __syncthreads();
+        // down-spin hops inside the tile, diagonal, epilogue
+        double part = 0.0;
+        const uint32_t aw0 = A.lwords[it.row0];
+#pragma unroll
+        for (int m = 0; m < HUB3_M; ++m) {
+            if (col_m[m] < 0) continue;
+            const int sr = p + m * per_pass;
+            int r = 0, s = sr;
+            if (!one_row) {
+                r = (int)(((float)sr + 0.5f) * inv_nseg);
+                s = sr - r * nseg;
+            }
+            const int rb = sr * Lp;
+            const double x0 = xs[rb + j];
+            double dn = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dn += xs[rb + j + lof[q]];
+            const int hc = hcnt[s];
+            const int32_t *hq = hnb + s * hs;
+            for (int q = 0; q < hc; ++q) dn += xs[rb + (hq[q] - s) * Lp + j];
+            const uint32_t aw = one_row ? aw0 : A.lwords[it.row0 + r];
+            const uint32_t bw = ((uint32_t)sinf[s].y << A.h) | (uint32_t)li.x;
+            const double dg = A.u0 * (double)__popc(aw & bw);
+            const int64_t gi = (int64_t)it.row0 * dR + col_m[m];
+            double y = A.xscale * (A.hop * (acc[m] + dn) + dg * x0);
+            if (A.z) y -= A.zcoef * A.z[gi];
+            A.y[gi] = y;
+            part += x0 * y;
+        }
+        if (A.partials) {
+            const double sum = block_sum(part, red);
+            if (tid == 0) A.partials[it.slot] = sum;
+        } else {
+            __syncthreads();
+        }
+    }
+}
+
+size_t hub3_lds_bytes(const ecut_sectors *s) {
+    auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    const int mns = s->hub.max_nseg;
+    return al((size_t)s->h3_max_tile * 8) + al((size_t)mns * 16) + al((size_t)mns * s->h3_hs * 4) + al((size_t)mns * 4);
+}
+
+hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, hipStream_t st) {
+    Hub3Args A = args;
+    if (grid % n_xcd) grid = (grid / n_xcd) * n_xcd;
+    if (grid < n_xcd) grid = n_xcd;
+    A.n_xcd = n_xcd;
+    A.per_xcd = (A.n_items + n_xcd - 1) / n_xcd;
+    hipLaunchKernelGGL(k_hub3, dim3(grid), dim3(HUB2_THREADS), hub3_lds_bytes(s), st, A);
+    return hipGetLastError();
+}
+
+int hub_blocks_per_cu(int which, size_t lds) {
+    int n = 0;
+    hipError_t e = hipSuccess;
+    if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3, HUB2_THREADS, lds);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub2<true, true>, HUB2_THREADS, lds);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
+size_t hub2_lds_bytes(const ecut_sectors *s) {
+    const HubDev &H = s->hub;
+    const int nlo = 1 << H.h, nhi = 1 << (H.n_r - H.h);
+    auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
+    size_t b = al((size_t)H.max_tile * 8) + 3 * al((size_t)H.max_nseg * 4) + al((size_t)H.max_nseg * H.cls_hi_stride * 4);
+    b += al((size_t)nhi * 4) + al((size_t)nlo * 4) + al((size_t)(H.n_coef > 0 ? H.n_coef : 1) * 8);
+    return b;
+}
+
+hipError_t launch_hub2(const ecut_sectors *s, const ProblemDev &prob, const HubItem *items_d, int n_items, int grid,
+                       int n_xcd, hipStream_t st) {
+    const size_t lds = hub2_lds_bytes(s);
+    if (grid % n_xcd) grid = (grid / n_xcd) * n_xcd;
+    if (grid < n_xcd) grid = n_xcd;
+    const int per_xcd = (n_items + n_xcd - 1) / n_xcd;
+    const HubDev &H = s->hub;
+    if (H.uniform_u && H.uniform_t)
+        hipLaunchKernelGGL((k_hub2<true, true>), dim3(grid), dim3(HUB2_THREADS), lds, st, prob, items_d, n_items, n_xcd,
+                           per_xcd);
+    else
+        hipLaunchKernelGGL((k_hub2<false, false>), dim3(grid), dim3(HUB2_THREADS), lds, st, prob, items_d, n_items,
+                           n_xcd, per_xcd);
+    return hipGetLastError();
+}
+
 size_t hub_lds_bytes(const ecut_sectors *s) {
     const HubDev &H = s->hub;
     const int dR = s->blocks[0].d_r;
@@ -517,6 +935,12 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     e = hipFuncSetAttribute((const void *)k_hub<false, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<false, false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub2<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub2<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub3, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ROWS_MAX_LDS);
 }

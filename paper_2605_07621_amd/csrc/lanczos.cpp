@@ -27,7 +27,7 @@ size_t lz_workspace_doubles(const ecut_sectors *s, bool reorth, int keep) {
     auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
     int64_t d = 0;
     d += reorth ? al(n) * (keep + 1) : al(n) * 3;
-    d += al(apply_partial_slots(s));
+    d += al(apply_partial_slots_max(s));
     d += al(nc);
     if (reorth) d += al(nc * keep) + 2 * al(MAX_BASIS);
     d += 32;
@@ -52,7 +52,7 @@ void lz_carve(LzSolve &L, const ecut_sectors *s, bool reorth, int keep, double *
     }
     L.n_apply = apply_partial_slots(s);
     L.part_apply = p;
-    p += al(L.n_apply);
+    p += al(apply_partial_slots_max(s));
     L.n_chunks = (int32_t)nc;
     L.part_norm = p;
     p += al(nc);
@@ -246,6 +246,7 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
     for (size_t k = 0; k < act.size(); ++k) {
         LzSolve &L = *act[k];
         VecJob A{};
+        L.n_apply = apply_partial_slots(L.s);   // the tuning may have changed since the workspace was carved
         A.partials = L.part_apply;
         A.n_partials = L.n_apply;
         A.mode = 0;

@@ -12,7 +12,8 @@ namespace ecut {
 ecut_status hip_fail(hipError_t e, const char *what);
 ecut_status device_res(int *dev, const uint64_t **binom, int *n_cu);
 ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t st);
-int32_t apply_partial_slots(const ecut_sectors *s);
+int32_t apply_partial_slots(const ecut_sectors *s);        // slots the current launch writes
+int32_t apply_partial_slots_max(const ecut_sectors *s);    // slots any variant may write
 int32_t max_tile_elems(const ecut_sectors *s);
 
 // One generic-kernel launch over several problems: copies the problem

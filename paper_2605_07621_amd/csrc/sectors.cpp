@@ -136,6 +136,8 @@ inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
 }  // namespace
 
 static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
+void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
+void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 
 ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qnum q, ecut_sectors *s) {
     if (!m || !c) return fail(ECUT_EINVAL, "null model or cut");
@@ -441,11 +443,222 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     s->hub_rw16.clear();
     if (n <= 16)
         for (int32_t r = 0; r < B.d_r; ++r) s->hub_rw16.push_back((uint16_t)s->rwords[B.rbase + r]);
-    // row order: plain increasing rows
-    s->row_order.resize(B.d_l);
-    for (int32_t a = 0; a < B.d_l; ++a) s->row_order[a] = a;
+    make_row_order(s, 0, s->row_order);
+
+    // ---- class tiles of the down basis
+    {
+        const int nh = n - h;
+        std::vector<std::vector<int32_t>> his(nh + 1);
+        for (int u = 0; u < nhi; ++u) his[__builtin_popcount(u)].push_back(u);
+        struct Cls {
+            int k, L, nseg;
+            std::vector<int32_t> segcol, hiw, low;
+            std::vector<std::vector<int32_t>> hient, loent;
+        };
+        std::vector<Cls> cl;
+        int max_size = 0;
+        for (int k = 0; k <= nh; ++k) {
+            const int lc = c - k;
+            if (lc < 0 || lc > h) continue;
+            Cls C;
+            C.k = k;
+            C.L = (int)ecut::binom(h, lc);
+            C.nseg = (int)his[k].size();
+            std::vector<int32_t> segidx(nhi, -1);
+            for (int si = 0; si < C.nseg; ++si) {
+                const int u = his[k][si];
+                segidx[u] = si;
+                C.hiw.push_back(u);
+                C.segcol.push_back(seg_off[u]);
+            }
+            C.hient.resize(C.nseg);
+            for (int v = 0; v < nlo; ++v)
+                if (__builtin_popcount(v) == lc) C.low.push_back(v);
+            C.loent.resize(C.L);
+            for (int b = 0; b < m->n_bonds; ++b) {
+                if (bcoef[b] < 0) continue;
+                const int i = m->bond_i[b], j = m->bond_j[b];
+                if (i >= h && j >= h) {
+                    for (int si = 0; si < C.nseg; ++si) {
+                        uint32_t w2;
+                        int sg;
+                        if (fermion_hop((uint32_t)C.hiw[si], i - h, j - h, w2, sg))
+                            C.hient[si].push_back(pack(segidx[w2] - si, sg < 0, bcoef[b]));
+                    }
+                } else if (i < h && j < h) {
+                    for (int jj = 0; jj < C.L; ++jj) {
+                        uint32_t w2;
+                        int sg;
+                        if (fermion_hop((uint32_t)C.low[jj], i, j, w2, sg))
+                            C.loent[jj].push_back(pack(lo_rank[w2] - jj, sg < 0, bcoef[b]));
+                    }
+                }
+            }
+            max_size = std::max(max_size, C.L * C.nseg);
+            cl.push_back(std::move(C));
+        }
+        size_t hs2 = 1, ls2 = 1;
+        for (auto &C : cl) {
+            for (auto &v : C.hient) hs2 = std::max(hs2, v.size());
+            for (auto &v : C.loent) ls2 = std::max(ls2, v.size());
+        }
+        const int tile = std::max(max_size, 2048);
+        s->hc_cls.clear();
+        s->hc_segcol.clear();
+        s->hc_hiw.clear();
+        s->hc_hicnt.clear();
+        s->hc_hient.clear();
+        s->hc_low.clear();
+        s->hc_locnt.clear();
+        s->hc_loent.clear();
+        s->hub_items.clear();
+        int max_nseg = 1, max_tile = 1;
+        for (size_t ci = 0; ci < cl.size(); ++ci) {
+            Cls &C = cl[ci];
+            const int seg_base = (int)s->hc_segcol.size(), lo_base = (int)s->hc_low.size();
+            const int S = C.L * C.nseg;
+            const int rpi = std::max(1, std::min(B.d_l, tile / S));
+            s->hc_cls.insert(s->hc_cls.end(), {C.L, C.nseg, seg_base, lo_base, rpi, S, C.k, 0});
+            for (int si = 0; si < C.nseg; ++si) {
+                s->hc_segcol.push_back(C.segcol[si]);
+                s->hc_hiw.push_back(C.hiw[si]);
+                s->hc_hicnt.push_back((int32_t)C.hient[si].size());
+                for (size_t q = 0; q < hs2; ++q) s->hc_hient.push_back(q < C.hient[si].size() ? C.hient[si][q] : 0);
+            }
+            for (int jj = 0; jj < C.L; ++jj) {
+                s->hc_low.push_back(C.low[jj]);
+                s->hc_locnt.push_back((int32_t)C.loent[jj].size());
+                for (size_t q = 0; q < ls2; ++q) s->hc_loent.push_back(q < C.loent[jj].size() ? C.loent[jj][q] : 0);
+            }
+            for (int32_t r0 = 0; r0 < B.d_l; r0 += rpi)
+                s->hub_items.push_back(HubItem{r0, std::min(rpi, B.d_l - r0), (int32_t)ci, (int32_t)s->hub_items.size()});
+            max_nseg = std::max(max_nseg, C.nseg);
+            max_tile = std::max(max_tile, rpi * S);
+        }
+        // the class-tile kernel needs every class row to fit its thread block
+        // (512 threads, at most 16 element passes) and the tile to fit LDS
+        bool ok = true;
+        for (size_t ci = 0; ci < cl.size(); ++ci) {
+            const int L = s->hc_cls[8 * ci], nseg = s->hc_cls[8 * ci + 1], rpi = s->hc_cls[8 * ci + 4];
+            const int per_pass = 512 / L;
+            if (per_pass < 1 || (rpi * nseg + per_pass - 1) / per_pass > 16) ok = false;
+        }
+        if ((size_t)max_tile * 8 + (size_t)max_nseg * (12 + 4 * hs2) + 4 * (size_t)(nhi + nlo) + 4096 > 150 * 1024) ok = false;
+        s->hub2_ok = ok;
+        H.n_cls = (int32_t)cl.size();
+        // ---- fast path: sign-free uniform hopping on both spins
+        bool fast = ok && coef.size() == 1 && n <= 16 && H.uniform_u && xb.size() <= 4;
+        if (fast && !xb.empty()) fast = xb[0] == h - 1 && xb[1] == 0;
+        for (double v : s->hl_val) fast = fast && v == coef[0];
+        for (auto &C : cl) {
+            for (auto &v : C.hient) for (int en : v) fast = fast && !((en >> 8) & 1);
+            for (auto &v : C.loent) for (int en : v) fast = fast && !((en >> 8) & 1);
+        }
+        if (fast) {
+            s->h3_seginfo.clear();
+            s->h3_loinfo.clear();
+            s->h3_looff.clear();
+            s->h3_hnb.clear();
+            s->h3_hcnt.clear();
+            const int hb = xb.empty() ? -1 : xb[1], lb = xb.empty() ? -1 : xb[0];
+            int mt = 0;
+            for (size_t ci = 0; ci < cl.size(); ++ci) {
+                Cls &C = cl[ci];
+                for (int si = 0; si < C.nseg; ++si) {
+                    const int u = C.hiw[si];
+                    int xcol = 0, xbit = 2;
+                    if (hb >= 0) {
+                        const int u2 = u ^ (1 << hb);
+                        xbit = (u >> hb) & 1;
+                        xcol = seg_off[u2] >= 0 ? seg_off[u2] : 0;
+                    }
+                    s->h3_seginfo.insert(s->h3_seginfo.end(), {C.segcol[si], u, xcol, xbit});
+                    s->h3_hcnt.push_back((int32_t)C.hient[si].size());
+                    for (size_t q = 0; q < hs2; ++q)
+                        s->h3_hnb.push_back(q < C.hient[si].size() ? si + (C.hient[si][q] >> 9) : 0);
+                }
+                for (int jj = 0; jj < C.L; ++jj) {
+                    const int v = C.low[jj];
+                    int xlo = 0, xbit = 2;
+                    if (lb >= 0) {
+                        xbit = (v >> lb) & 1;
+                        xlo = lo_rank[v ^ (1 << lb)];
+                    }
+                    s->h3_loinfo.insert(s->h3_loinfo.end(), {v, xlo, xbit, 0});
+                    for (int q = 0; q < 8; ++q)
+                        s->h3_looff.push_back(q < (int)C.loent[jj].size() ? (C.loent[jj][q] >> 9) : C.L - jj);
+                    if (C.loent[jj].size() > 8) fast = false;
+                }
+                const int rpi = s->hc_cls[8 * ci + 4];
+                mt = std::max(mt, rpi * C.nseg * (C.L + 1));
+            }
+            s->h3_hs = (int32_t)hs2;
+            s->h3_max_tile = mt;
+            // every item must fit HUB3_M (12) element slots per thread of 512
+            for (size_t ci = 0; ci < cl.size(); ++ci) {
+                const int L = s->hc_cls[8 * ci], nseg = s->hc_cls[8 * ci + 1], rpi = s->hc_cls[8 * ci + 4];
+                if ((rpi * nseg + 512 / L - 1) / (512 / L) > 12) fast = false;
+                if ((int64_t)rpi * s->blocks[0].d_r > (1ll << 31) / 2) fast = false;
+            }
+            if ((size_t)mt * 8 + (size_t)max_nseg * (16 + 4 * hs2 + 4) + 2048 > 150 * 1024) fast = false;
+        }
+        s->hub3_ok = fast;
+        H.cls_lo_stride = (int32_t)ls2;
+        H.cls_hi_stride = (int32_t)hs2;
+        H.max_tile = max_tile;
+        H.max_nseg = max_nseg;
+        make_hub_item_order(s, 0, s->hub_items_ord);
+    }
     s->hub_ok = true;
     s->kernel = 1;
+}
+
+void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out) {
+    // order % 3 picks the row order; order < 3 keeps classes apart (class
+    // major), order >= 3 puts the classes of one row next to each other.
+    std::vector<int32_t> ro;
+    make_row_order(s, order % 3, ro);
+    std::vector<int32_t> pos(ro.size());
+    for (size_t k = 0; k < ro.size(); ++k) pos[ro[k]] = (int32_t)k;
+    out = s->hub_items;
+    const bool class_major = order < 3;
+    std::stable_sort(out.begin(), out.end(), [&](const HubItem &a, const HubItem &b) {
+        const int64_t ka = class_major ? ((int64_t)a.cls << 32 | pos[a.row0]) : ((int64_t)pos[a.row0] << 8 | a.cls);
+        const int64_t kb = class_major ? ((int64_t)b.cls << 32 | pos[b.row0]) : ((int64_t)pos[b.row0] << 8 | b.cls);
+        return ka < kb;
+    });
+}
+
+// Inversion number of an occupation word: pairs (particle at p, hole at q > p).
+// A hop of one particle to a neighbouring site changes it by exactly one.
+static int inversions(uint32_t w, int n) {
+    int inv = 0, holes_above = 0;
+    for (int p = n - 1; p >= 0; --p) {
+        if ((w >> p) & 1u) inv += holes_above;
+        else ++holes_above;
+    }
+    return inv;
+}
+
+void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out) {
+    const BlockDev &B = s->blocks[0];
+    const int n = s->n_sites;
+    out.resize(B.d_l);
+    for (int32_t a = 0; a < B.d_l; ++a) out[a] = a;
+    if (order == 0) return;
+    std::vector<int64_t> key(B.d_l);
+    const int h = n / 2;
+    for (int32_t a = 0; a < B.d_l; ++a) {
+        const uint32_t w = s->lwords[B.lbase + a];
+        if (order == 1) {
+            key[a] = (int64_t)inversions(w, n) << 32 | a;
+        } else {
+            const uint32_t hi = w >> h;
+            key[a] = ((int64_t)__builtin_popcount(hi) << 56) | ((int64_t)inversions(hi, n - h) << 40) |
+                     ((int64_t)hi << 24) | (w & ((1u << h) - 1u));
+        }
+    }
+    std::stable_sort(out.begin(), out.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
 }
 
 }  // namespace ecut

@@ -1,0 +1,187 @@
+// Launch tuning of ecut_apply_H and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ecut_internal.h"
+#include "runtime.h"
+
+namespace ecut {
+namespace {
+
+std::mutex g_cache_mu;
+
+std::string shape_key(const ecut_sectors *s) {
+    hipDeviceProp_t prop;
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    std::ostringstream k;
+    k << arch << "/k" << s->kernel << "/s" << s->n_sites << "/u" << s->n_up << "/d" << s->n_dn << "/b"
+      << s->blocks.size() << "/dim" << s->dim;
+    return k.str();
+}
+
+// The cache file is a flat JSON object {"key": [grid, n_xcd, row_order], ...}.
+std::map<std::string, ApplyTuning> read_cache(const char *path) {
+    std::map<std::string, ApplyTuning> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t p = 0;
+    while ((p = t.find('"', p)) != std::string::npos) {
+        const size_t q = t.find('"', p + 1);
+        if (q == std::string::npos) break;
+        const std::string key = t.substr(p + 1, q - p - 1);
+        const size_t a = t.find('[', q), b = t.find(']', q);
+        if (a == std::string::npos || b == std::string::npos) break;
+        ApplyTuning T{};
+        if (std::sscanf(t.substr(a + 1, b - a - 1).c_str(), "%d , %d , %d , %d", &T.grid, &T.n_xcd, &T.order,
+                        &T.variant) == 4)
+            out[key] = T;
+        p = b;
+    }
+    return out;
+}
+
+void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) {
+    std::ofstream f(path);
+    f << "{\n";
+    size_t k = 0;
+    for (auto &kv : m) {
+        f << "  \"" << kv.first << "\": [" << kv.second.grid << ", " << kv.second.n_xcd << ", " << kv.second.order
+          << ", " << kv.second.variant << "]" << (++k < m.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+}
+
+ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
+    if (T.order < 0 || T.order > 5 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 2)
+        return fail(ECUT_EINVAL, "bad tuning");
+    if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
+        return fail(ECUT_EUNSUPPORTED, "class tiles not available");
+    if (s->kernel == 1 && T.order != s->tune.order) {
+        make_row_order(s, T.order % 3, s->row_order);
+        make_hub_item_order(s, T.order, s->hub_items_ord);
+        if (s->on_device && s->dev_row_order) {
+            hipError_t e = hipMemcpy(s->dev_row_order, s->row_order.data(), s->row_order.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice);
+            if (e == hipSuccess && s->dev_hub_items)
+                e = hipMemcpy(s->dev_hub_items, s->hub_items_ord.data(), s->hub_items_ord.size() * sizeof(HubItem),
+                              hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work order)");
+        }
+    }
+    s->tune = T;
+    return ECUT_OK;
+}
+
+}  // namespace
+}  // namespace ecut
+
+using namespace ecut;
+
+extern "C" {
+
+ecut_status ecut_get_tuning(const ecut_sectors *s, ecut_tuning *t) {
+    if (!s || !t) return fail(ECUT_EINVAL, "null argument");
+    t->grid = s->tune.grid;
+    t->n_xcd = s->tune.n_xcd;
+    t->row_order = s->tune.order;
+    t->variant = s->tune.variant;
+    return ECUT_OK;
+}
+
+ecut_status ecut_set_tuning(ecut_sectors *s, const ecut_tuning *t) {
+    if (!s || !t) return fail(ECUT_EINVAL, "bad argument");
+    ApplyTuning T{t->grid, t->n_xcd, t->row_order, t->variant};
+    return apply_tuning(s, T);
+}
+
+ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void *stream, ecut_tuning *best) {
+    if (!s || !x_d || !y_d || x_d == y_d) return fail(ECUT_EINVAL, "bad argument");
+    if (!s->on_device) return fail(ECUT_EINVAL, "handle was built with ECUT_BUILD_HOST_ONLY");
+    hipStream_t st = (hipStream_t)stream;
+    const char *cache_path = std::getenv("ECUT_TUNE_CACHE");
+    const std::string key = shape_key(s);
+    if (cache_path) {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto m = read_cache(cache_path);
+        auto it = m.find(key);
+        if (it != m.end()) {
+            ecut_status rs = apply_tuning(s, it->second);
+            if (rs != ECUT_OK) return rs;
+            if (best) ecut_get_tuning(s, best);
+            return ECUT_OK;
+        }
+    }
+    std::vector<ApplyTuning> cands;
+    if (s->kernel == 1) {
+        if (s->hub2_ok)
+            for (int order = 0; order < 6; ++order)
+                for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 0});
+        if (s->hub3_ok)
+            for (int order : {1, 2})
+                cands.push_back(ApplyTuning{0, 1, order, 2});
+        for (int order : {0, 2})
+            for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 1});
+    } else {
+        cands.push_back(ApplyTuning{0, 0, 0, 0});
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ECUT_EDEVICE, "hipEventCreate");
+    ProblemDev P = s->prob;
+    P.x = x_d;
+    P.y = y_d;
+    P.z = nullptr;
+    P.xscale = 1.0;
+    P.zcoef = 0.0;
+    P.partials = nullptr;
+    float best_ms = 1e30f;
+    ApplyTuning best_t = s->tune;
+    ecut_status rs = ECUT_OK;
+    for (const ApplyTuning &T : cands) {
+        rs = apply_tuning(s, T);
+        if (rs != ECUT_OK) break;
+        rs = launch_apply(s, P, st);   // warm-up
+        if (rs != ECUT_OK) break;
+        hipEventRecord(e0, st);
+        const int reps = 3;
+        for (int r = 0; r < reps && rs == ECUT_OK; ++r) rs = launch_apply(s, P, st);
+        hipEventRecord(e1, st);
+        if (rs != ECUT_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { rs = fail(ECUT_EDEVICE, "autotune timing"); break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_ms) { best_ms = ms; best_t = T; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rs != ECUT_OK) return rs;
+    rs = apply_tuning(s, best_t);
+    if (rs != ECUT_OK) return rs;
+    if (cache_path) {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto m = read_cache(cache_path);
+        m[key] = best_t;
+        write_cache(cache_path, m);
+    }
+    if (best) ecut_get_tuning(s, best);
+    return ECUT_OK;
+}
+
+}  // extern "C"

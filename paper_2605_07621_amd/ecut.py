@@ -61,6 +61,10 @@ class LanczosStats(ctypes.Structure):
                 ("residual", _dbl), ("seconds", _dbl)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("grid", _i32), ("n_xcd", _i32), ("row_order", _i32), ("variant", _i32)]
+
+
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_active", _i32), ("max_steps", _i32), ("tol", _dbl), ("sequential", _i32), ("use_graph", _i32)]
 
@@ -82,6 +86,9 @@ SYMBOLS = [
     ("ecut_export", _i32, [_vp, _vp, _vp, _vp]),
     ("ecut_apply_H", _i32, [_vp, _vp, _vp, _vp]),
     ("ecut_apply_H_batch", _i32, [_i32, _vp, _vp, _vp, _vp]),
+    ("ecut_get_tuning", _i32, [_vp, ctypes.POINTER(Tuning)]),
+    ("ecut_set_tuning", _i32, [_vp, ctypes.POINTER(Tuning)]),
+    ("ecut_autotune", _i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(Tuning)]),
     ("ecut_lanczos_workspace", _sz, [_vp, ctypes.POINTER(LanczosOpts)]),
     ("ecut_lanczos_ground_state", _i32, [_vp, _vp, ctypes.POINTER(LanczosOpts), ctypes.POINTER(_dbl), _vp,
                                          ctypes.POINTER(LanczosStats), _vp, _vp]),
@@ -231,6 +238,21 @@ class Sectors:
         out = torch.empty(self.dim, dtype=torch.float64, device=psi.device) if out is None else out
         _check(lib().ecut_apply_H(self.h, _dptr(psi, self.dim, "psi"), _dptr(out, self.dim, "out"), _stream(stream)))
         return out
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().ecut_get_tuning(self.h, ctypes.byref(t)))
+        return dict(grid=t.grid, n_xcd=t.n_xcd, row_order=t.row_order, variant=t.variant)
+
+    def set_tuning(self, grid=0, n_xcd=0, row_order=0, variant=0):
+        t = Tuning(int(grid), int(n_xcd), int(row_order), int(variant))
+        _check(lib().ecut_set_tuning(self.h, ctypes.byref(t)))
+
+    def autotune(self, x, y, stream=None):
+        t = Tuning()
+        _check(lib().ecut_autotune(self.h, _dptr(x, self.dim, "x"), _dptr(y, self.dim, "y"), _stream(stream),
+                                   ctypes.byref(t)))
+        return dict(grid=t.grid, n_xcd=t.n_xcd, row_order=t.row_order, variant=t.variant)
 
     def lanczos_workspace(self, max_steps, reorth=False, max_restarts=0, tol=1e-10, fixed_steps=False):
         o = LanczosOpts(int(max_steps), int(max_restarts), int(bool(reorth)), int(bool(fixed_steps)), float(tol))

@@ -63,6 +63,29 @@ def test_apply_small_vs_oracle(dev, k):
     _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} n_up={p.n_up}")
 
 
+_HUB_CASES = [I.hubbard12(),
+              I.Problem(I.hubbard_chain(10, 1.0, 2.5), I.Cut("updn"), 5, 4),
+              I.Problem(I.hubbard_chain(11, 0.7, 6.0), I.Cut("updn"), 6, 3),
+              I.Problem(I.random_hubbard_model(np.random.default_rng(77), 9, n_bonds=14), I.Cut("updn"), 4, 5),
+              I.Problem(I.random_hubbard_model(np.random.default_rng(78), 10, n_bonds=12), I.Cut("updn"), 3, 5)]
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("order", [0, 2, 4])
+def test_hubbard_kernel_variants_and_orders(dev, variant, order):
+    """Every Hubbard kernel (class tiles with the uniform-chain fast path,
+    whole rows, generic class tiles) under several work orders agrees with
+    the oracle; uniform chains and random long-range couplings."""
+    for k, p in enumerate(_HUB_CASES):
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        psi = I.psi(500 + k, s.n)
+        y_ref = s.apply(psi)
+        S = _ecut().Sectors.from_problem(p)
+        S.set_tuning(0, 8 if order % 2 == 0 else 1, order, variant)
+        assert S.get_tuning()["variant"] == variant
+        _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} v{variant} o{order}")
+
+
 @pytest.mark.parametrize("name", ["heisenberg16", "hubbard12"])
 def test_apply_workload_full_vs_oracle(dev, name):
     p = I.WORKLOADS[name]()
@@ -120,6 +143,22 @@ def test_apply_is_deterministic_and_batch_bit_exact(dev):
             torch.testing.assert_close(alone[k], ys[k], rtol=1e-13, atol=1e-13)
 
 
+def test_autotune_keeps_parity(dev, tmp_path, monkeypatch):
+    import torch
+    monkeypatch.setenv("ECUT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    p = I.hubbard12()
+    s = O.Sector(p.model, 6, 6)
+    psi = I.psi(77, s.n)
+    y_ref = s.apply(psi)
+    S = _ecut().Sectors.from_problem(p)
+    x = torch.from_numpy(psi).to(dev)
+    best = S.autotune(x, torch.empty_like(x))
+    assert (tmp_path / "tune.json").exists()
+    _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"autotuned {best}")
+    S2 = _ecut().Sectors.from_problem(p)
+    assert S2.autotune(x, torch.empty_like(x)) == best      # served from the cache
+
+
 def test_lanczos_heisenberg16_vs_oracle(dev):
     import torch
     p = I.heisenberg16()
@@ -141,9 +180,13 @@ def test_lanczos_hubbard12_vs_oracle(dev):
     e_ref = s.lanczos(I.psi(p.meta["seed"] + 1, s.n), 400, tol=1e-13)[0][-1]
     S = _ecut().Sectors.from_problem(p)
     v0 = torch.from_numpy(I.psi(p.meta["seed"] + 1, s.n)).to(dev)
-    e, st, _ = S.lanczos(v0, 200, fixed_steps=True)
-    assert st["steps"] == 200
-    assert abs(e - e_ref) <= 1e-10
+    for variant in (0, 1):
+        # a workspace full of NaN: every partial slot the solver reads must be written first
+        S.set_tuning(0, 8, 0, variant)
+        ws = torch.full((S.lanczos_workspace(200),), float("nan"), dtype=torch.float64, device=dev)
+        e, st, _ = S.lanczos(v0, 200, fixed_steps=True, workspace=ws)
+        assert st["steps"] == 200
+        assert abs(e - e_ref) <= 1e-10, (variant, e, e_ref)
 
 
 def test_lanczos_reorth_ground_state_vector(dev):
