@@ -71,6 +71,58 @@ def cpu_baseline(p, seconds):
                 seconds=round(dt, 3))
 
 
+def _run_server(reqs, arrivals, budget, max_active, sequential, tol=1e-10, max_steps=600):
+    from paper_2605_07621_amd import ecut
+    srv = ecut.Server(int(budget), max_active=max_active, max_steps=max_steps, tol=tol, sequential=sequential)
+    t0 = srv.now()
+    ids = [srv.submit(p, seed=p.meta["seed"], not_before=t0 + float(a)) for p, a in zip(reqs, arrivals)]
+    srv.drain()
+    res = {r["req_id"]: r for r in srv.poll(len(reqs) + 8)}
+    srv.close()
+    out = [res[i] for i in ids]
+    bad = [r for r in out if r["status"] != 0]
+    if bad:
+        raise RuntimeError(f"{len(bad)} serving requests failed, first status {bad[0]['status']}")
+    return out
+
+
+def _lat_stats(out, start):
+    import numpy as np
+    lat = np.array([r["t_done"] - r["t_submit"] for r in out])
+    span = max(r["t_done"] for r in out) - start
+    return dict(solves_per_s=round(len(out) / span, 3), makespan_s=round(span, 3),
+                p50_s=round(float(np.percentile(lat, 50)), 5), p99_s=round(float(np.percentile(lat, 99)), 5))
+
+
+def serving_bench(n_requests, budget_gb):
+    """Mixed ground-state requests (seeded XXZ and Hubbard chains, Sz=0 / half
+    filling, tol 1e-10): sequential one-at-a-time solves vs continuous batching,
+    closed loop (all at t=0) and Poisson arrivals at 0.5x and 2x the
+    sequential rate."""
+    import numpy as np
+    from paper_2605_07621_amd import inputs as I
+    reqs = I.serving_requests(n_requests, seed=2026)
+    budget = budget_gb * 2**30
+    zeros = np.zeros(len(reqs))
+    seq = _run_server(reqs, zeros, budget, 1, True)
+    s_seq = _lat_stats(seq, min(r["t_submit"] for r in seq))
+    bat = _run_server(reqs, zeros, budget, 0, False)
+    s_bat = _lat_stats(bat, min(r["t_submit"] for r in bat))
+    de = max(abs(a["energy"] - b["energy"]) for a, b in zip(seq, bat))
+    out = {"requests": len(reqs), "tol": 1e-10, "closed_loop": {"sequential": s_seq, "batched": s_bat},
+           "max_energy_diff_batched_vs_sequential": de,
+           "speedup_solves_per_s": round(s_bat["solves_per_s"] / s_seq["solves_per_s"], 3)}
+    mu = s_seq["solves_per_s"]
+    for rho in (0.5, 2.0):
+        arr = I.poisson_arrivals(len(reqs), rho * mu)
+        r_seq = _run_server(reqs, arr, budget, 1, True)
+        r_bat = _run_server(reqs, arr, budget, 0, False)
+        out[f"poisson_rho{rho}"] = {"rate_per_s": round(rho * mu, 3),
+                                    "sequential": _lat_stats(r_seq, min(r["t_submit"] for r in r_seq)),
+                                    "batched": _lat_stats(r_bat, min(r["t_submit"] for r in r_bat))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +132,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lanczos-steps", type=int, default=10)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serving", type=int, default=64, help="requests in the serving run (0: skip)")
+    ap.add_argument("--serving-budget-gb", type=float, default=24.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
@@ -97,6 +152,7 @@ def main():
     x = S.import_(torch.from_numpy(I.psi(p.meta.get("seed", 1), n)).to(dev))
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+    tuning = S.autotune(x, y, stream=stream) if not args.no_autotune else S.get_tuning()
     for _ in range(args.warmup):
         S.apply(x, y, stream=stream)
     torch.cuda.synchronize()
@@ -140,13 +196,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": p.model.name + "_" + p.cut.kind, "sites": p.model.n_sites,
                    "n_up": p.n_up, "n_dn": p.n_dn, "dim": n, "blocks": int(S.info.n_blocks),
-                   "kernel": kernel},
+                   "kernel": kernel, "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": alg_bytes,
                      "kernel_ms": round(kern_ms, 5), "kernel": kernel},
         "lanczos": lz,
     }
+    if args.serving > 0:
+        line["serving"] = serving_bench(args.serving, args.serving_budget_gb)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -116,6 +116,9 @@ typedef struct ecut_sectors_info {
     int32_t n_cross_offdiag;  /* sector-changing L_m (x) R_m products (2 per cut bond with jxy != 0) */
     int32_t n_cross_diag;     /* diagonal cross-cut terms */
     int32_t kernel;           /* kernel family chosen for ecut_apply_H (1 = Hubbard up/down, 2 = generic rows) */
+    int32_t kernel_flags;     /* Hubbard: bit 0 class tiles available, bit 1 uniform-chain fast path
+                                 (and the split two-pass variant) available */
+    int32_t reserved;
     int64_t device_bytes;     /* device metadata held by the handle */
     double n_eff;             /* 1 / sum_q w_q^2 with w_q = d_L d_R / dim (block-size participation number) */
 } ecut_sectors_info;
@@ -195,8 +198,13 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
  *              word, groups ordered by the inversion level of that half;
  *              3..5: as 0..2 with the column classes of one row processed
  *              together instead of one class after the other;
+ *              6..8: as 0..2, class major, with the row groups that share
+ *              the high half of the up word dealt round-robin to the XCDs;
  *   variant:   0 class tiles (rows cut into classes of down words, several
- *              work groups per CU), 1 whole rows staged in LDS.
+ *              work groups per CU; the uniform-chain fast kernel when it
+ *              applies), 1 whole rows staged in LDS, 2 generic class tiles,
+ *              3 two passes: the left operator over L2-resident column slabs,
+ *              then the right operator and diagonal on class tiles.
  * ecut_set_tuning re-uploads the row order (synchronous).  Not to be called
  * while an ecut_apply_H on the same handle is in flight.
  */

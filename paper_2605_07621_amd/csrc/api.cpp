@@ -140,6 +140,7 @@ ecut_status upload(ecut_sectors *s) {
         o_order = A.add(s->row_order);
     }
     size_t o_hcc = 0, o_hsc = 0, o_hhw = 0, o_hhc = 0, o_hhe = 0, o_hlw = 0, o_hlcn = 0, o_hle = 0, o_hit = 0;
+    std::vector<HubItem> items_cap;   // must outlive the copies below
     if (s->hub_ok) {
         o_hcc = A.add(s->hc_cls);
         o_hsc = A.add(s->hc_segcol);
@@ -149,7 +150,9 @@ ecut_status upload(ecut_sectors *s) {
         o_hlw = A.add(s->hc_low);
         o_hlcn = A.add(s->hc_locnt);
         o_hle = A.add(s->hc_loent);
-        o_hit = A.add(s->hub_items_ord);
+        items_cap.assign(std::max(s->hub_items_cap, s->hub_items_ord.size()), HubItem{0, 0, 0, -1});
+        std::copy(s->hub_items_ord.begin(), s->hub_items_ord.end(), items_cap.begin());
+        o_hit = A.add(items_cap);
     }
     size_t o_3si = 0, o_3li = 0, o_3lo = 0, o_3hn = 0, o_3hc = 0;
     if (s->hub3_ok) {
@@ -225,6 +228,8 @@ ecut_status upload(ecut_sectors *s) {
         A3.u0 = s->hub.u0;
         A3.hl_ptr = P.hl_ptr;
         A3.hl_col = P.hl_col;
+        A3.hl_val = P.hl_val;
+        A3.n_rows = s->blocks[0].d_l;
         A3.lwords = P.lwords;
         A3.cls = P.hub.cls;
         A3.seginfo = (const int4 *)(b + o_3si);
@@ -263,7 +268,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
     if (s->kernel == 1) {
         const ApplyTuning &T = s->tune;
         const int n_xcd = T.n_xcd > 0 ? T.n_xcd : 8;
-        if (T.variant == 0 && s->hub3_ok) {
+        if ((T.variant == 0 || T.variant == 3) && s->hub3_ok) {
             const size_t lds = hub3_lds_bytes(s);
             if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "class tiles exceed the device's LDS per work group");
             const int grid = T.grid > 0 ? T.grid : n_cu * hub_blocks_per_cu(3, lds);
@@ -272,14 +277,17 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             A3.y = P.y;
             A3.z = P.z;
             A3.partials = P.partials;
+            A3.items = s->dev_hub_items;
+            A3.n_items = (int32_t)s->hub_items_ord.size();
             A3.xscale = P.xscale;
             A3.zcoef = P.zcoef;
-            e = launch_hub3(s, A3, grid, n_xcd, st);
+            const int slab_grid = 8 * std::max(1, (n_cu / 8) * hub_blocks_per_cu(4, 0));
+            e = launch_hub3(s, A3, grid, n_xcd, T.variant == 3, slab_grid, st);
         } else if ((T.variant == 0 || T.variant == 2) && s->hub2_ok) {
             const size_t lds = hub2_lds_bytes(s);
             if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "class tiles exceed the device's LDS per work group");
             const int grid = T.grid > 0 ? T.grid : n_cu * hub_blocks_per_cu(2, lds);
-            e = launch_hub2(s, P, s->dev_hub_items, (int)s->hub_items.size(), grid, n_xcd, st);
+            e = launch_hub2(s, P, s->dev_hub_items, (int)s->hub_items_ord.size(), grid, n_xcd, st);
         } else {
             if (hub_lds_bytes(s) > g_last_max_lds)
                 return fail(ECUT_EUNSUPPORTED, "Hubbard kernel tables exceed the device's LDS per work group");
@@ -296,7 +304,8 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
 // number of partial slots the apply kernel writes
 int32_t apply_partial_slots(const ecut_sectors *s) {
     if (s->kernel != 1) return (int32_t)s->items.size();
-    const bool tiles = (s->tune.variant == 0 && (s->hub3_ok || s->hub2_ok)) || (s->tune.variant == 2 && s->hub2_ok);
+    const bool tiles = ((s->tune.variant == 0 || s->tune.variant == 3) && (s->hub3_ok || s->hub2_ok)) ||
+                       (s->tune.variant == 2 && s->hub2_ok);
     return tiles ? (int32_t)s->hub_items.size() : s->blocks[0].d_l;
 }
 
@@ -436,6 +445,7 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
     I.n_cross_offdiag = 2 * (int32_t)s->xbond.size();
     I.n_cross_diag = (int32_t)s->xdiag.size();
     I.kernel = s->kernel;
+    I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0);
     I.device_bytes = (int64_t)s->dev_bytes;
     I.n_eff = s->n_eff;
     *info = I;

@@ -115,6 +115,8 @@ struct Hub3Args {
     double *partials;
     double xscale, zcoef, hop, u0;
     const int32_t *hl_ptr, *hl_col;   // up-spin hop rows
+    const double *hl_val;
+    int32_t n_rows, pad_;
     const uint32_t *lwords;           // up words
     const int32_t *cls;               // [n_cls][8] as HubDev::cls
     const int4 *seginfo;              // [seg]: column, high word, crossing column, crossing bit (2 = none)
@@ -210,6 +212,7 @@ struct ecut_sectors {
     std::vector<int32_t> hc_cls, hc_segcol, hc_hiw, hc_hicnt, hc_hient, hc_low, hc_locnt, hc_loent;
     std::vector<ecut::HubItem> hub_items;         // class-tile items, slot order
     std::vector<ecut::HubItem> hub_items_ord;     // class-tile items, processing order
+    size_t hub_items_cap = 0;                     // device capacity for any processing order
     // default work items of a single application
     std::vector<ecut::ItemDev> items;
     std::vector<int32_t> row_order;       // Hubbard kernel: row processing order

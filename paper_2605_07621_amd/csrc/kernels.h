@@ -18,6 +18,8 @@ constexpr int HUB2_M = 16;                   // element passes per thread and it
 constexpr int HUB2_LOREG = 8;                // low-hop entries kept in registers
 constexpr int HUB2_NB = 8;
 constexpr int HUB3_M = 12;                   // element slots per thread and item in the fast kernel                   // left-operator neighbour loads issued together per element
+constexpr int SLAB_W = 16;                   // columns per slab of the left-operator pass (one 128-byte line)
+constexpr int SLAB_THREADS = 256;
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
 constexpr int MAX_BASIS = 1024;              // CGS2: vectors per projection call
@@ -47,7 +49,8 @@ size_t hub2_lds_bytes(const ecut_sectors *s);
 hipError_t launch_hub2(const ecut_sectors *s, const ProblemDev &prob, const HubItem *items_d, int n_items, int grid,
                        int n_xcd, hipStream_t st);
 size_t hub3_lds_bytes(const ecut_sectors *s);
-hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, hipStream_t st);
+hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, bool split, int slab_grid,
+                       hipStream_t st);
 int hub_blocks_per_cu(int which, size_t lds);
 hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
                        double *out, bool to_bip, hipStream_t st);

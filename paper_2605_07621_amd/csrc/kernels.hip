@@ -329,6 +329,7 @@ __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const
         const int idx = xcd * per_xcd + k;
         if (idx >= n_items) break;
         const HubItem it = items[idx];
+        if (it.nrows == 0) continue;
         const int32_t *cd = H.cls + 8 * it.cls;
         const int L = cd[0], nseg = cd[1], seg_base = cd[2], lo_base = cd[3];
         if (it.cls != loaded) {
@@ -477,6 +478,49 @@ __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const
 }
 
 // ------------------------------------------------------------------------
+// Left (up-spin) operator over column slabs: y[a, S] = sum_a' H_up[a,a'] x[a', S]
+// for a slab S of SLAB_W consecutive columns.  Every XCD walks a contiguous
+// range of slabs, all its work groups on the same slab at the same time (each
+// one a chunk of rows), so after the first touch every neighbour-row read of
+// the slab is an L2 hit; x is fetched from HBM about once.  Work group w runs
+// on XCD w % 8 (round-robin dispatch); per_xcd = gridDim.x / 8.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(SLAB_THREADS) void k_upslab(const double *__restrict__ x, double *__restrict__ y,
+                                                         const int32_t *__restrict__ hl_ptr,
+                                                         const int32_t *__restrict__ hl_col,
+                                                         const double *__restrict__ hl_val, int n_rows, int dR,
+                                                         int per_xcd) {
+    const int xcd = blockIdx.x % 8;
+    const int l = blockIdx.x / 8;
+    const int n_slabs = (dR + SLAB_W - 1) / SLAB_W;
+    const int spx = (n_slabs + 7) / 8;
+    const int rows_per = (n_rows + per_xcd - 1) / per_xcd;
+    const int r_begin = l * rows_per;
+    const int r_end = min(n_rows, r_begin + rows_per);
+    const int lane = threadIdx.x % SLAB_W;
+    const int grp = threadIdx.x / SLAB_W;
+    const int ngrp = SLAB_THREADS / SLAB_W;
+    for (int sl = xcd * spx; sl < min(n_slabs, (xcd + 1) * spx); ++sl) {
+        const int c = sl * SLAB_W + lane;
+        const bool col_ok = c < dR;
+        for (int a = r_begin + grp; a < r_end; a += ngrp) {
+            const int q0 = hl_ptr[a], q1 = hl_ptr[a + 1];
+            double acc = 0.0;
+            int q = q0;
+            for (; q + 4 <= q1; q += 4) {
+                double v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = col_ok ? x[(int64_t)hl_col[q + u] * dR + c] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc += hl_val[q + u] * v[u];
+            }
+            for (; q < q1; ++q) acc += hl_val[q] * (col_ok ? x[(int64_t)hl_col[q] * dR + c] : 0.0);
+            if (col_ok) y[(int64_t)a * dR + c] = acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
 // Fast class-tile kernel for uniform, sign-free hopping (open chains).
 // Same items and tiles as k_hub2, but: every hop value is the same -t, so
 // all neighbour values are summed first and scaled once; tiles have a row
@@ -486,6 +530,7 @@ __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const
 // per-lane address arithmetic; the crossing bond's source column splits
 // into a per-segment and a per-lane part that are both precomputed.
 // ------------------------------------------------------------------------
+template <bool UP>
 __global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[HUB2_THREADS / 64];
@@ -505,6 +550,7 @@ __global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
         const int idx = xcd * A.per_xcd + k;
         if (idx >= A.n_items) break;
         const HubItem it = A.items[idx];
+        if (it.nrows == 0) continue;
         const int32_t *cd = A.cls + 8 * it.cls;
         const int L = cd[0], nseg = cd[1], seg_base = cd[2], lo_base = cd[3];
         if (it.cls != loaded) {
@@ -552,8 +598,14 @@ __global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
                 if (col_m[m] >= 0) xs[(p + m * per_pass) * Lp + j] = v[m];
             for (int sr = tid; sr < nsr; sr += NT) xs[sr * Lp + L] = 0.0;
         }
-        // up-spin hops: neighbour rows at the same columns
-        if (one_row) {
+        // up-spin hops: neighbour rows at the same columns (split mode: already in y)
+        if (!UP) {
+            double v[HUB3_M];
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m) v[m] = col_m[m] >= 0 ? A.y[(int64_t)it.row0 * dR + col_m[m]] : 0.0;
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m) acc[m] = v[m];
+        } else if (one_row) {
             const int uq0 = A.hl_ptr[it.row0], uq1 = A.hl_ptr[it.row0 + 1];
             for (int q = uq0; q < uq1; ++q) {
                 const double *__restrict__ xn = A.x + (size_t)A.hl_col[q] * (size_t)dR;
@@ -597,8 +649,9 @@ __global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
                     if ((li.z ^ si.w) == 1) v[m] = x0row[col_m[m] - si.x - j + si.z + li.y];
                 }
             }
+            // acc holds unscaled neighbour sums when fused, hop-weighted sums in split mode
 #pragma unroll
-            for (int m = 0; m < HUB3_M; ++m) acc[m] += v[m];
+            for (int m = 0; m < HUB3_M; ++m) acc[m] += UP ? v[m] : A.hop * v[m];
         }
         __syncthreads();
         // down-spin hops inside the tile, diagonal, epilogue
@@ -625,7 +678,7 @@ __global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
             const uint32_t bw = ((uint32_t)sinf[s].y << A.h) | (uint32_t)li.x;
             const double dg = A.u0 * (double)__popc(aw & bw);
             const int64_t gi = (int64_t)it.row0 * dR + col_m[m];
-            double y = A.xscale * (A.hop * (acc[m] + dn) + dg * x0);
+            double y = UP ? A.xscale * (A.hop * (acc[m] + dn) + dg * x0) : A.xscale * (acc[m] + A.hop * dn + dg * x0);
             if (A.z) y -= A.zcoef * A.z[gi];
             A.y[gi] = y;
             part += x0 * y;
@@ -645,20 +698,29 @@ size_t hub3_lds_bytes(const ecut_sectors *s) {
     return al((size_t)s->h3_max_tile * 8) + al((size_t)mns * 16) + al((size_t)mns * s->h3_hs * 4) + al((size_t)mns * 4);
 }
 
-hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, hipStream_t st) {
+hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, bool split, int slab_grid,
+                       hipStream_t st) {
     Hub3Args A = args;
     if (grid % n_xcd) grid = (grid / n_xcd) * n_xcd;
     if (grid < n_xcd) grid = n_xcd;
     A.n_xcd = n_xcd;
     A.per_xcd = (A.n_items + n_xcd - 1) / n_xcd;
-    hipLaunchKernelGGL(k_hub3, dim3(grid), dim3(HUB2_THREADS), hub3_lds_bytes(s), st, A);
+    if (split) {
+        // pass 1: left operator over column slabs held in L2; pass 2: tiles
+        hipLaunchKernelGGL(k_upslab, dim3(slab_grid), dim3(SLAB_THREADS), 0, st, A.x, A.y, A.hl_ptr, A.hl_col, A.hl_val,
+                           A.n_rows, A.dR, slab_grid / 8);
+        hipLaunchKernelGGL(k_hub3<false>, dim3(grid), dim3(HUB2_THREADS), hub3_lds_bytes(s), st, A);
+    } else {
+        hipLaunchKernelGGL(k_hub3<true>, dim3(grid), dim3(HUB2_THREADS), hub3_lds_bytes(s), st, A);
+    }
     return hipGetLastError();
 }
 
 int hub_blocks_per_cu(int which, size_t lds) {
     int n = 0;
     hipError_t e = hipSuccess;
-    if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3, HUB2_THREADS, lds);
+    if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3<true>, HUB2_THREADS, lds);
+    else if (which == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_upslab, SLAB_THREADS, 0);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub2<true, true>, HUB2_THREADS, lds);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -940,7 +1002,9 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub2<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hub3, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    e = hipFuncSetAttribute((const void *)k_hub3<true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub3<false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ROWS_MAX_LDS);
 }

@@ -327,10 +327,12 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         ++L->total;
         const int m = (int)L->a.size();
         std::vector<double> eo(L->b.begin(), L->b.begin() + (m - 1));
-        const std::vector<double> ev = tridiag_eigenvalues(L->a, eo);
-        const std::vector<double> u = tridiag_eigenvector(L->a, eo, ev[0]);
-        L->e_prev = m > 1 ? L->energy : ev[0];
-        L->energy = ev[0];
+        // O(m) per step: bisection from the previous Ritz value (an upper
+        // bound by interlacing), inverse iteration for the last component
+        const double lowest = tridiag_lowest(L->a, eo, m > 1 ? L->energy : NAN, L->energy - L->e_prev);
+        const std::vector<double> u = tridiag_eigenvector(L->a, eo, lowest);
+        L->e_prev = m > 1 ? L->energy : lowest;
+        L->energy = lowest;
         L->residual = beta * std::fabs(u[m - 1]);
         const bool breakdown = beta <= 1e-14 * std::max(std::fabs(alpha), 1e-300);
         const bool conv = (L->residual <= 1e-2 * std::sqrt(L->tol) && m > 1 && std::fabs(L->energy - L->e_prev) <= L->tol);
@@ -366,6 +368,15 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         ++L->j;
     }
     return ECUT_OK;
+}
+
+// Final energy: all eigenvalues of T by implicit QL; the per-step bisection
+// value must agree with it.
+double final_energy(const LzSolve &L) {
+    if (L.a.empty()) return L.energy;
+    std::vector<double> eo(L.b.begin(), L.b.begin() + (L.a.size() - 1));
+    const double ql = tridiag_eigenvalues(L.a, eo)[0];
+    return std::fabs(ql - L.energy) <= 1e-9 * (std::fabs(ql) + 1.0) ? ql : L.energy;
 }
 
 }  // namespace ecut
@@ -410,7 +421,7 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
         if (rs != ECUT_OK) return rs;
     }
     if (L.status != ECUT_OK && L.status != ECUT_ENOTCONV) return L.status;
-    *energy = L.energy;
+    *energy = final_energy(L);
     if (gs_d) {
         rs = lz_ritz_vector(L, gs_d, st, stg);
         if (rs != ECUT_OK) return rs;

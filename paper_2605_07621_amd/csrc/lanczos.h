@@ -47,6 +47,8 @@ ecut_status lz_start(std::vector<LzSolve *> &solves, const std::vector<const dou
                      Staging &stg);
 // one Lanczos step for every solve that is not done; synchronises st
 ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg);
+// lowest eigenvalue of the final tridiagonal matrix by implicit QL
+double final_energy(const LzSolve &L);
 // ground-state Ritz vector of the current cycle into out (reorth only)
 ecut_status lz_ritz_vector(LzSolve &L, double *out, hipStream_t st, Staging &stg);
 

@@ -607,6 +607,11 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
         H.cls_hi_stride = (int32_t)hs2;
         H.max_tile = max_tile;
         H.max_nseg = max_nseg;
+        s->hub_items_cap = s->hub_items.size();
+        for (int order = 6; order <= 8; ++order) {
+            make_hub_item_order(s, order, s->hub_items_ord);
+            s->hub_items_cap = std::max(s->hub_items_cap, s->hub_items_ord.size());
+        }
         make_hub_item_order(s, 0, s->hub_items_ord);
     }
     s->hub_ok = true;
@@ -614,19 +619,41 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
 }
 
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out) {
-    // order % 3 picks the row order; order < 3 keeps classes apart (class
-    // major), order >= 3 puts the classes of one row next to each other.
+    // order % 3 picks the row order; 0..2 class major, 3..5 the classes of one
+    // row together, 6..8 class major with up-segments (rows sharing the high
+    // half of the up word) dealt round-robin to 8 equal chunks, one per XCD,
+    // padded with empty items, so each XCD holds whole segments while all
+    // XCDs walk the same part of the row order.
     std::vector<int32_t> ro;
     make_row_order(s, order % 3, ro);
     std::vector<int32_t> pos(ro.size());
     for (size_t k = 0; k < ro.size(); ++k) pos[ro[k]] = (int32_t)k;
     out = s->hub_items;
-    const bool class_major = order < 3;
+    const bool class_major = order < 3 || order >= 6;
     std::stable_sort(out.begin(), out.end(), [&](const HubItem &a, const HubItem &b) {
         const int64_t ka = class_major ? ((int64_t)a.cls << 32 | pos[a.row0]) : ((int64_t)pos[a.row0] << 8 | a.cls);
         const int64_t kb = class_major ? ((int64_t)b.cls << 32 | pos[b.row0]) : ((int64_t)pos[b.row0] << 8 | b.cls);
         return ka < kb;
     });
+    if (order < 6) return;
+    const int n_chunks = 8;
+    const int hshift = s->n_sites / 2;
+    std::vector<std::vector<HubItem>> ch(n_chunks);
+    int g = -1;
+    int64_t last_key = -1;
+    for (const HubItem &it : out) {
+        const uint32_t w = s->lwords[s->blocks[0].lbase + it.row0];
+        const int64_t key = ((int64_t)it.cls << 32) | (w >> hshift);
+        if (key != last_key) { ++g; last_key = key; }
+        ch[g % n_chunks].push_back(it);
+    }
+    size_t len = 0;
+    for (auto &c : ch) len = std::max(len, c.size());
+    out.clear();
+    for (auto &c : ch) {
+        out.insert(out.end(), c.begin(), c.end());
+        for (size_t k = c.size(); k < len; ++k) out.push_back(HubItem{0, 0, 0, -1});
+    }
 }
 
 // Inversion number of an occupation word: pairs (particle at p, hole at q > p).

@@ -245,7 +245,7 @@ void ecut_server::run() {
             r.req_id = A.req->id;
             r.status = A.L.status;
             r.steps = A.L.total;
-            r.energy = A.L.energy;
+            r.energy = final_energy(A.L);
             r.residual = A.L.residual;
             r.t_submit = A.req->t_submit;
             r.t_admit = A.t_admit;

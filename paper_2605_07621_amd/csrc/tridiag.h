@@ -58,6 +58,49 @@ inline std::vector<double> tridiag_eigenvalues(const std::vector<double> &d_in, 
     return d;
 }
 
+// Number of eigenvalues of T below x: negative pivots of T - x I = L D L^T.
+inline int tridiag_count_below(const std::vector<double> &d, const std::vector<double> &e, double x) {
+    int neg = 0;
+    double piv = 1.0;
+    for (size_t k = 0; k < d.size(); ++k) {
+        const double off = k ? e[k - 1] * e[k - 1] / piv : 0.0;
+        piv = d[k] - x - off;
+        if (piv == 0.0) piv = -1e-300;
+        neg += piv < 0.0;
+    }
+    return neg;
+}
+
+// Lowest eigenvalue of T by bisection.  `hint` (a previous lowest Ritz
+// value, an upper bound by interlacing) and `step` (its last change) narrow
+// the starting bracket; the result is accurate to a few ulps.
+inline double tridiag_lowest(const std::vector<double> &d, const std::vector<double> &e, double hint, double step) {
+    const int n = (int)d.size();
+    double glo = d[0], ghi = d[0];
+    for (int i = 0; i < n; ++i) {
+        const double r = (i ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+        glo = std::min(glo, d[i] - r);
+        ghi = std::max(ghi, d[i] + r);
+    }
+    const double scale = std::max(std::fabs(glo), std::fabs(ghi)) + 1e-300;
+    double hi = ghi + 1e-12 * scale, lo = glo - 1e-12 * scale;
+    if (std::isfinite(hint) && hint < hi) {
+        const double h = hint + 1e-13 * scale;
+        if (tridiag_count_below(d, e, h) >= 1) {
+            hi = h;
+            double w = std::max(4.0 * std::fabs(step), 1e-10 * scale);
+            while (hi - w > lo && tridiag_count_below(d, e, hi - w) >= 1) w *= 8.0;
+            lo = std::max(lo, hi - w);
+        }
+    }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (tridiag_count_below(d, e, mid) >= 1) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 // Unit eigenvector of T for eigenvalue lam by inverse iteration:
 // solve (T - sigma I) x = b with Gaussian elimination and partial pivoting
 // (at most two super-diagonals of fill), three sweeps.

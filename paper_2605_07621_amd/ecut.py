@@ -49,7 +49,8 @@ class QNum(ctypes.Structure):
 class SectorsInfo(ctypes.Structure):
     _fields_ = [("dim", _i64), ("n_blocks", _i32), ("n_left_sites", _i32), ("n_right_sites", _i32),
                 ("max_d_r", _i32), ("n_cut_bonds", _i32), ("n_cross_offdiag", _i32), ("n_cross_diag", _i32),
-                ("kernel", _i32), ("device_bytes", _i64), ("n_eff", _dbl)]
+                ("kernel", _i32), ("kernel_flags", _i32), ("reserved", _i32), ("device_bytes", _i64),
+                ("n_eff", _dbl)]
 
 
 class LanczosOpts(ctypes.Structure):

@@ -70,8 +70,8 @@ _HUB_CASES = [I.hubbard12(),
               I.Problem(I.random_hubbard_model(np.random.default_rng(78), 10, n_bonds=12), I.Cut("updn"), 3, 5)]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
-@pytest.mark.parametrize("order", [0, 2, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("order", [0, 2, 4, 7])
 def test_hubbard_kernel_variants_and_orders(dev, variant, order):
     """Every Hubbard kernel (class tiles with the uniform-chain fast path,
     whole rows, generic class tiles) under several work orders agrees with
@@ -81,6 +81,10 @@ def test_hubbard_kernel_variants_and_orders(dev, variant, order):
         psi = I.psi(500 + k, s.n)
         y_ref = s.apply(psi)
         S = _ecut().Sectors.from_problem(p)
+        if variant == 3 and not S.info.kernel_flags & 2:
+            with pytest.raises(_ecut().EcutError):
+                S.set_tuning(0, 1, order, variant)
+            continue
         S.set_tuning(0, 8 if order % 2 == 0 else 1, order, variant)
         assert S.get_tuning()["variant"] == variant
         _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} v{variant} o{order}")
@@ -180,7 +184,7 @@ def test_lanczos_hubbard12_vs_oracle(dev):
     e_ref = s.lanczos(I.psi(p.meta["seed"] + 1, s.n), 400, tol=1e-13)[0][-1]
     S = _ecut().Sectors.from_problem(p)
     v0 = torch.from_numpy(I.psi(p.meta["seed"] + 1, s.n)).to(dev)
-    for variant in (0, 1):
+    for variant in (0, 1, 3):
         # a workspace full of NaN: every partial slot the solver reads must be written first
         S.set_tuning(0, 8, 0, variant)
         ws = torch.full((S.lanczos_workspace(200),), float("nan"), dtype=torch.float64, device=dev)
