@@ -117,7 +117,9 @@ typedef struct ecut_sectors_info {
     int32_t n_cross_diag;     /* diagonal cross-cut terms */
     int32_t kernel;           /* kernel family chosen for ecut_apply_H (1 = Hubbard up/down, 2 = generic rows) */
     int32_t kernel_flags;     /* Hubbard: bit 0 class tiles available, bit 1 uniform-chain fast path
-                                 (and the split two-pass variant) available */
+                                 (and the split two-pass variant) available; spin: bit 2 the
+                                 ranking-table kernel available (both parts <= 16 sites, row
+                                 tiles <= 6656 amplitudes, <= 64 flip-flop terms in the right part) */
     int32_t reserved;
     int64_t device_bytes;     /* device metadata held by the handle */
     double n_eff;             /* 1 / sum_q w_q^2 with w_q = d_L d_R / dim (block-size participation number) */
@@ -200,11 +202,20 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
  *              together instead of one class after the other;
  *              6..8: as 0..2, class major, with the row groups that share
  *              the high half of the up word dealt round-robin to the XCDs;
+ *              9: rows sorted by the popcount of the high half of the left
+ *              word, then by inversion level, class major (the source rows
+ *              of one level then lie in a window of three levels that stays
+ *              in the last-level cache); 10: as 9 with the classes of one
+ *              row together;
  *   variant:   0 class tiles (rows cut into classes of down words, several
  *              work groups per CU; the uniform-chain fast kernel when it
  *              applies), 1 whole rows staged in LDS, 2 generic class tiles,
  *              3 two passes: the left operator over L2-resident column slabs,
  *              then the right operator and diagonal on class tiles.
+ *              Spin and generic problems (kernel 2) take variant 0 (the
+ *              ranking-table spin kernel when kernel_flags bit 2 is set, else
+ *              the generic row kernel) or 1 (the generic row kernel, which
+ *              reads the right operator's CSR); other fields are ignored.
  * ecut_set_tuning re-uploads the row order (synchronous).  Not to be called
  * while an ecut_apply_H on the same handle is in flight.
  */

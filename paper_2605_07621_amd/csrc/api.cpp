@@ -154,6 +154,13 @@ ecut_status upload(ecut_sectors *s) {
         std::copy(s->hub_items_ord.begin(), s->hub_items_ord.end(), items_cap.begin());
         o_hit = A.add(items_cap);
     }
+    size_t o_srl = 0, o_srh = 0, o_sfm = 0, o_sfc = 0;
+    if (s->spin_ok) {
+        o_srl = A.add(s->spin_rank_lo);
+        o_srh = A.add(s->spin_rank_hi);
+        o_sfm = A.add(s->spin_fmask);
+        o_sfc = A.add(s->spin_fcoef);
+    }
     size_t o_3si = 0, o_3li = 0, o_3lo = 0, o_3hn = 0, o_3hc = 0;
     if (s->hub3_ok) {
         o_3si = A.add(s->h3_seginfo);
@@ -195,6 +202,14 @@ ecut_status upload(ecut_sectors *s) {
     P.maps = (const int32_t *)(b + o_maps);
     P.dim = s->dim;
     P.xscale = 1.0;
+    if (s->spin_ok) {
+        P.spin_ok = s->tune.variant == 0 ? 1 : 0;
+        P.n_rflip = (int32_t)s->spin_fmask.size();
+        P.rank_lo = (const int32_t *)(b + o_srl);
+        P.rank_hi = (const int32_t *)(b + o_srh);
+        P.rflip_mask = (const uint32_t *)(b + o_sfm);
+        P.rflip_coef = (const double *)(b + o_sfc);
+    }
     s->dev_items = (ItemDev *)(b + o_items);
     if (s->hub_ok) {
         HubDev &H = P.hub;
@@ -294,6 +309,8 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             const int grid = T.grid > 0 ? T.grid : n_cu;
             e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
         }
+    } else if (P.spin_ok) {
+        e = launch_spin(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
     } else {
         e = launch_rows(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
     }
@@ -372,9 +389,27 @@ void Staging::release() {
     device = -1;
 }
 
-ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items, int tile,
-                              hipStream_t st) {
+ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items_in,
+                              const std::vector<int32_t> &tiles, hipStream_t st) {
     static thread_local Staging S;
+    // the spin kernel takes the problems whose tuning selects it (as their
+    // own ecut_apply_H does), the generic row kernel the others; the order
+    // of the queue is kept within each group
+    std::vector<ItemDev> items;
+    items.reserve(items_in.size());
+    int spin_tile = 0, rows_tile = 0, first_spin = -1;
+    for (const ItemDev &it : items_in)
+        if (probs[it.prob].spin_ok) {
+            items.push_back(it);
+            spin_tile = std::max(spin_tile, tiles[it.prob]);
+            if (first_spin < 0) first_spin = it.prob;
+        }
+    const size_t n_spin = items.size();
+    for (const ItemDev &it : items_in)
+        if (!probs[it.prob].spin_ok) {
+            items.push_back(it);
+            rows_tile = std::max(rows_tile, tiles[it.prob]);
+        }
     const size_t pb = (probs.size() * sizeof(ProblemDev) + 255) & ~(size_t)255;
     const size_t bytes = pb + items.size() * sizeof(ItemDev);
     ecut_status rs = S.reserve(bytes);
@@ -385,8 +420,11 @@ ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::v
     std::memcpy((char *)S.host + pb, items.data(), items.size() * sizeof(ItemDev));
     hipError_t e = hipMemcpyAsync(S.dev, S.host, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
-    e = launch_rows((const ProblemDev *)S.dev, probs[0], (const ItemDev *)((char *)S.dev + pb), (int)items.size(), tile,
-                    st);
+    const ProblemDev *probs_d = (const ProblemDev *)S.dev;
+    const ItemDev *items_d = (const ItemDev *)((char *)S.dev + pb);
+    if (n_spin > 0) e = launch_spin(probs_d, probs[first_spin], items_d, (int)n_spin, spin_tile, st);
+    if (e == hipSuccess && n_spin < items.size())
+        e = launch_rows(probs_d, probs[0], items_d + n_spin, (int)(items.size() - n_spin), rows_tile, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");
     e = hipEventRecord(S.ev, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -445,7 +483,7 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
     I.n_cross_offdiag = 2 * (int32_t)s->xbond.size();
     I.n_cross_diag = (int32_t)s->xdiag.size();
     I.kernel = s->kernel;
-    I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0);
+    I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0);
     I.device_bytes = (int64_t)s->dev_bytes;
     I.n_eff = s->n_eff;
     *info = I;
@@ -549,7 +587,7 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
     if (n == 0) return ECUT_OK;
     std::vector<ProblemDev> probs(n);
     std::vector<ItemDev> items;
-    int32_t tile = 0;
+    std::vector<int32_t> tiles(n);
     for (int32_t k = 0; k < n; ++k) {
         ecut_status st = check_dev(s[k]);
         if (st != ECUT_OK) return st;
@@ -562,7 +600,7 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
         probs[k].zcoef = 0.0;
         probs[k].partials = nullptr;
         for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
-        tile = std::max(tile, max_tile_elems(s[k]));
+        tiles[k] = max_tile_elems(s[k]);
     }
     // one queue over all problems, largest tiles first (stable: problem order breaks ties)
     std::stable_sort(items.begin(), items.end(), [&](const ItemDev &a, const ItemDev &b) {
@@ -570,7 +608,7 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
         const int64_t wb = (int64_t)(b.row1 - b.row0) * s[b.prob]->blocks[b.block].d_r;
         return wa > wb;
     });
-    return batch_launch_rows(probs, items, tile, (hipStream_t)stream);
+    return batch_launch_rows(probs, items, tiles, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -150,6 +150,13 @@ struct ProblemDev {
     const XBondDev *xbond;
     const int32_t *maps;
     HubDev hub;
+    // spin kernel with ranking tables (spatial cut, both sides <= 16 sites)
+    int32_t spin_ok;             // tables below are valid
+    int32_t n_rflip;             // flip-flop terms inside the right part
+    const int32_t *rank_lo;      // colex rank of the low byte: 256 entries
+    const int32_t *rank_hi;      // colex rank of the high byte given popc(low byte): 256 x 9
+    const uint32_t *rflip_mask;  // the two right-part bits of each flip-flop term
+    const double *rflip_coef;    // jxy/2 of each term
     int64_t dim;
     // per launch (filled by the launcher)
     const double *x;             // input vector
@@ -213,6 +220,11 @@ struct ecut_sectors {
     std::vector<ecut::HubItem> hub_items;         // class-tile items, slot order
     std::vector<ecut::HubItem> hub_items_ord;     // class-tile items, processing order
     size_t hub_items_cap = 0;                     // device capacity for any processing order
+    // spin kernel with ranking tables
+    bool spin_ok = false;
+    std::vector<int32_t> spin_rank_lo, spin_rank_hi;
+    std::vector<uint32_t> spin_fmask;
+    std::vector<double> spin_fcoef;
     // default work items of a single application
     std::vector<ecut::ItemDev> items;
     std::vector<int32_t> row_order;       // Hubbard kernel: row processing order
@@ -234,6 +246,8 @@ namespace ecut {
 ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qnum q, ecut_sectors *s);
 ecut_status upload(ecut_sectors *s);
 void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
+// row order used by work order `order` (0..10) of the Hubbard kernels
+inline int row_order_kind(int order) { return order >= 9 ? 3 : order % 3; }
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 void release_device(ecut_sectors *s);
 }  // namespace ecut

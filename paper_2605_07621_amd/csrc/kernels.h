@@ -16,10 +16,14 @@ constexpr int HUB_MAXC = 16;                 // columns per thread: d_R <= HUB_T
 constexpr int HUB2_THREADS = 512;
 constexpr int HUB2_M = 16;                   // element passes per thread and item
 constexpr int HUB2_LOREG = 8;                // low-hop entries kept in registers
-constexpr int HUB2_NB = 8;
-constexpr int HUB3_M = 12;                   // element slots per thread and item in the fast kernel                   // left-operator neighbour loads issued together per element
+constexpr int HUB2_NB = 8;                   // left-operator neighbour loads issued together per element
+constexpr int HUB3_M = 12;                   // element slots per thread and item in the fast kernel
 constexpr int SLAB_W = 16;                   // columns per slab of the left-operator pass (one 128-byte line)
 constexpr int SLAB_THREADS = 256;
+constexpr int SPIN_THREADS = 1024;
+constexpr int SPIN_M = 7;                    // element slots per thread of the spin kernel
+constexpr int SPIN_TILE = SPIN_THREADS * SPIN_M;
+constexpr int SPIN_MAX_FLIP = 64;            // flip-flop terms inside the right part
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
 constexpr int MAX_BASIS = 1024;              // CGS2: vectors per projection call
@@ -42,6 +46,9 @@ struct VecJob {
 size_t hub_lds_bytes(const ecut_sectors *s);
 hipError_t set_hub_lds_limits(size_t bytes);
 hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
+                       int max_tile_elems, hipStream_t st);
+// spin kernel with ranking tables; every problem of the launch must have spin_ok
+hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
                        int max_tile_elems, hipStream_t st);
 hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
                       int n_xcd, hipStream_t st);

@@ -478,6 +478,168 @@ __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const
 }
 
 // ------------------------------------------------------------------------
+// Spin blocks of a spatial cut, both parts at most 16 sites.  One work group
+// per row tile (rows [row0, row1) of one block); the tile is staged in LDS.
+//  - right operator: for each flip-flop term inside the right part whose two
+//    spins differ, the flipped word is ranked with two byte-table lookups
+//    (colex rank) and the amplitude is gathered from the staged tile;
+//  - left operator: whole neighbour rows of the same block, read at the
+//    tile's columns (one-row tiles: wave-uniform CSR, SPIN_M loads in flight
+//    per thread and neighbour);
+//  - cross-cut flip-flops S+_i S-_j + h.c. (Eq. (2), the L_m (x) R_m terms):
+//    the source row in the neighbouring block comes from the left map, the
+//    source column from ranking the flipped right word;
+//  - diagonal: left and right diagonals plus the Jz Sz_i Sz_j cut terms.
+// Epilogue as k_rows: y = xscale H x - zcoef z, per-item partial of <x, y>.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32_t *rh) {
+    const uint32_t lo = w & 255u;
+    return rl[lo] + rh[(w >> 8) * 9u + (uint32_t)__popc(lo)];
+}
+
+__global__ __launch_bounds__(SPIN_THREADS, 4) void k_spin(const ProblemDev *__restrict__ probs,
+                                                          const ProblemDev single, const ItemDev *__restrict__ items,
+                                                          int n_items) {
+    extern __shared__ __align__(16) double xs[];
+    __shared__ double red[SPIN_THREADS / 64];
+    __shared__ int32_t rl[256];
+    __shared__ int32_t rh[256 * 9];
+    __shared__ uint32_t fm[SPIN_MAX_FLIP];
+    __shared__ double fc[SPIN_MAX_FLIP];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 256; i += SPIN_THREADS) rl[i] = single.rank_lo[i];
+    for (int i = tid; i < 256 * 9; i += SPIN_THREADS) rh[i] = single.rank_hi[i];
+    int loaded = -1;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const ItemDev W = items[it];
+        const ProblemDev &P = probs ? probs[W.prob] : single;
+        const int n_flip = P.n_rflip;
+        if (W.prob != loaded) {
+            __syncthreads();
+            for (int i = tid; i < n_flip; i += SPIN_THREADS) {
+                fm[i] = P.rflip_mask[i];
+                fc[i] = P.rflip_coef[i];
+            }
+            loaded = W.prob;
+        }
+        const BlockDev B = P.blocks[W.block];
+        const int dR = B.d_r;
+        const int nrows = W.row1 - W.row0;
+        const int n = nrows * dR;
+        const bool one = nrows == 1;
+        const double *__restrict__ xblk = P.x + B.offset;
+        const double *__restrict__ xt = xblk + (int64_t)W.row0 * dR;
+        double acc[SPIN_M];
+        uint32_t wr[SPIN_M];
+        // stage the tile; right words of this thread's elements
+        {
+            double xv[SPIN_M];
+#pragma unroll
+            for (int m = 0; m < SPIN_M; ++m) {
+                const int e = tid + m * SPIN_THREADS;
+                const bool ok = e < n;
+                const int lr = one ? 0 : e / dR;
+                const int r = e - lr * dR;
+                xv[m] = ok ? xt[e] : 0.0;
+                wr[m] = ok ? P.rwords[B.rbase + r] : 0u;
+                acc[m] = 0.0;
+            }
+            __syncthreads();   // the previous item's readers of xs are done; fm/fc are loaded
+#pragma unroll
+            for (int m = 0; m < SPIN_M; ++m) {
+                const int e = tid + m * SPIN_THREADS;
+                if (e < n) xs[e] = xv[m];
+            }
+        }
+        // left operator: neighbour rows of the same block at the same columns
+        if (one) {
+            const int gl = B.lbase + W.row0;
+            const int q1 = P.hl_ptr[gl + 1];
+            for (int q = P.hl_ptr[gl]; q < q1; ++q) {
+                const double c = P.hl_val[q];
+                const double *__restrict__ xn = xblk + (int64_t)P.hl_col[q] * dR;
+                double v[SPIN_M];
+#pragma unroll
+                for (int m = 0; m < SPIN_M; ++m) {
+                    const int e = tid + m * SPIN_THREADS;
+                    v[m] = e < n ? xn[e] : 0.0;
+                }
+#pragma unroll
+                for (int m = 0; m < SPIN_M; ++m) acc[m] += c * v[m];
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < SPIN_M; ++m) {
+                const int e = tid + m * SPIN_THREADS;
+                if (e >= n) continue;
+                const int lr = e / dR;
+                const int r = e - lr * dR;
+                const int gl = B.lbase + W.row0 + lr;
+                const int q1 = P.hl_ptr[gl + 1];
+                double a = 0.0;
+                for (int q = P.hl_ptr[gl]; q < q1; ++q) a += P.hl_val[q] * xblk[(int64_t)P.hl_col[q] * dR + r];
+                acc[m] += a;
+            }
+        }
+        // cross-cut flip-flops and diagonal cut terms
+        for (int k = 0; k < P.n_xbond; ++k) {
+            const XBondDev X = P.xbond[k];
+#pragma unroll
+            for (int m = 0; m < SPIN_M; ++m) {
+                const int e = tid + m * SPIN_THREADS;
+                if (e >= n) continue;
+                const int lr = one ? 0 : e / dR;
+                const int gl = B.lbase + W.row0 + lr;
+                const uint32_t bl = (P.lwords[gl] >> X.li) & 1u;
+                const uint32_t br = (wr[m] >> X.rj) & 1u;
+                if (bl == br) continue;
+                const int src = bl ? B.blk_lminus : B.blk_lplus;
+                const int lp = P.maps[(bl ? X.lmap_del : X.lmap_ins) + gl];
+                if (src < 0 || lp < 0) continue;
+                const BlockDev S = P.blocks[src];
+                const int rp = rank16(wr[m] ^ (1u << X.rj), rl, rh);
+                acc[m] += X.coef * P.x[S.offset + (int64_t)lp * S.d_r + rp];
+            }
+        }
+        __syncthreads();
+        // right operator from the staged tile, diagonal, epilogue
+        double part = 0.0;
+#pragma unroll
+        for (int m = 0; m < SPIN_M; ++m) {
+            const int e = tid + m * SPIN_THREADS;
+            if (e >= n) continue;
+            const int lr = one ? 0 : e / dR;
+            const int r = e - lr * dR;
+            const int gl = B.lbase + W.row0 + lr;
+            const uint32_t w = wr[m];
+            const double *xrow = xs + lr * dR;
+            double a = 0.0;
+            for (int k = 0; k < n_flip; ++k) {
+                const uint32_t f = fm[k];
+                if (__popc(w & f) == 1) a += fc[k] * xrow[rank16(w ^ f, rl, rh)];
+            }
+            const uint32_t lw = P.lwords[gl];
+            double dg = P.diag_l[gl] + P.diag_r[B.rbase + r];
+            for (int k = 0; k < P.n_xdiag; ++k) {
+                const XDiagDev X = P.xdiag[k];
+                const double fl = (double)((lw >> X.li) & 1u) - 0.5, fr = (double)((w >> X.rj) & 1u) - 0.5;
+                dg += X.coef * fl * fr;
+            }
+            const double x0 = xs[e];
+            double yv = P.xscale * (acc[m] + a + dg * x0);
+            const int64_t gi = B.offset + (int64_t)W.row0 * dR + e;
+            if (P.z) yv -= P.zcoef * P.z[gi];
+            P.y[gi] = yv;
+            part += x0 * yv;
+        }
+        if (P.partials) {
+            const double sum = block_sum(part, red);
+            if (tid == 0) P.partials[W.slot] = sum;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
 // Left (up-spin) operator over column slabs: y[a, S] = sum_a' H_up[a,a'] x[a', S]
 // for a slab S of SLAB_W consecutive columns.  Every XCD walks a contiguous
 // range of slabs, all its work groups on the same slab at the same time (each
@@ -968,6 +1130,16 @@ hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, cons
     return hipGetLastError();
 }
 
+hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
+                       int max_tile_elems, hipStream_t st) {
+    if (n_items <= 0) return hipSuccess;
+    if (max_tile_elems > SPIN_TILE) return hipErrorInvalidValue;
+    const int grid = n_items < 65536 ? n_items : 65536;
+    const size_t lds = (size_t)std::max(max_tile_elems, 1) * 8;
+    hipLaunchKernelGGL(k_spin, dim3(grid), dim3(SPIN_THREADS), lds, st, probs_d, single, items_d, n_items);
+    return hipGetLastError();
+}
+
 hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
                       int n_xcd, hipStream_t st) {
     const size_t lds = hub_lds_bytes(s);
@@ -990,6 +1162,8 @@ hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32
 hipError_t set_hub_lds_limits(size_t bytes) {
     hipError_t e = hipSuccess;
     const int b = (int)bytes;
+    e = hipFuncSetAttribute((const void *)k_spin, hipFuncAttributeMaxDynamicSharedMemorySize, SPIN_TILE * 8);
+    if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<true, true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);

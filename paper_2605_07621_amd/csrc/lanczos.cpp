@@ -210,7 +210,7 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
     std::vector<ProblemDev> rows_probs;
     std::vector<const ecut_sectors *> rows_s;
     std::vector<ItemDev> rows_items;
-    int rows_tile = 0;
+    std::vector<int32_t> rows_tiles;
     for (LzSolve *L : act) {
         ProblemDev P = L->s->prob;
         P.x = xvec(*L);
@@ -227,7 +227,7 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
             rows_probs.push_back(P);
             rows_s.push_back(L->s);
             for (const ItemDev &it : L->s->items) rows_items.push_back(ItemDev{pi, it.block, it.row0, it.row1, it.slot, 0});
-            rows_tile = std::max(rows_tile, max_tile_elems(L->s));
+            rows_tiles.push_back(max_tile_elems(L->s));
         }
     }
     if (!rows_items.empty()) {
@@ -237,7 +237,7 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
             const int64_t wb = (int64_t)(b.row1 - b.row0) * rows_s[b.prob]->blocks[b.block].d_r;
             return wa > wb;
         });
-        ecut_status rs = batch_launch_rows(rows_probs, rows_items, rows_tile, st);
+        ecut_status rs = batch_launch_rows(rows_probs, rows_items, rows_tiles, st);
         if (rs != ECUT_OK) return rs;
     }
     // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2

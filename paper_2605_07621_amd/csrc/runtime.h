@@ -16,12 +16,13 @@ int32_t apply_partial_slots(const ecut_sectors *s);        // slots the current 
 int32_t apply_partial_slots_max(const ecut_sectors *s);    // slots any variant may write
 int32_t max_tile_elems(const ecut_sectors *s);
 
-// One generic-kernel launch over several problems: copies the problem
+// One row-kernel launch over the work items of several problems (two when
+// spin-kernel and generic problems are mixed): copies the problem
 // descriptors and the work items to a per-thread device buffer (pinned
 // staging, asynchronous on `st`) and launches.  Waits for the previous use of
-// the buffer before overwriting it.
-ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items, int tile,
-                              hipStream_t st);
+// the buffer before overwriting it.  tiles[k] = largest row tile of problem k.
+ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items,
+                              const std::vector<int32_t> &tiles, hipStream_t st);
 
 // Small reusable device + pinned-host staging buffer (not thread-safe).
 struct Staging {

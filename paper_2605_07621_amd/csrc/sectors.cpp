@@ -9,6 +9,7 @@
 #include <utility>
 
 #include "ecut_internal.h"
+#include "kernels.h"
 
 namespace ecut {
 
@@ -136,6 +137,7 @@ inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
 }  // namespace
 
 static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
+static void build_spin_tables(ecut_sectors *s);
 void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 
@@ -222,6 +224,10 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
                         uint32_t w2 = w ^ ((1u << bi) | (1u << bj));
                         S.rows[g].push_back({(int32_t)colex_rank(w2), 0.5 * jxy});
                     }
+                }
+                if (side[i] == 1 && jxy != 0.0) {
+                    s->spin_fmask.push_back((1u << bi) | (1u << bj));
+                    s->spin_fcoef.push_back(0.5 * jxy);
                 }
             } else {
                 ++s->n_cut_bonds;
@@ -328,6 +334,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
 
     s->hub_ok = false;
     s->kernel = 2;
+    build_spin_tables(s);
     if (s->kind == ECUT_HUBBARD) build_hub_tables(s, m);
     return ECUT_OK;
 }
@@ -618,24 +625,58 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     s->kernel = 1;
 }
 
+// Tables of the spin kernel.  The colex rank of a word w of up to 16 bits,
+// sum over its set bits p_0 < p_1 < ... of C(p_t, t+1), splits into a part
+// that depends only on the low byte and a part that depends on the high byte
+// and the popcount of the low byte:
+//   rank(w) = rank_lo[w & 255] + rank_hi[(w >> 8) * 9 + popc(w & 255)].
+// The tables do not depend on the sector, so one pair serves every block.
+static void build_spin_tables(ecut_sectors *s) {
+    s->spin_ok = false;
+    if (s->kind != ECUT_SPIN_HALF) return;
+    if (s->lsites.size() > 16 || s->rsites.size() > 16) return;
+    if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP) return;
+    for (const ItemDev &it : s->items)
+        if ((int64_t)(it.row1 - it.row0) * s->blocks[it.block].d_r > SPIN_TILE) return;
+    s->spin_rank_lo.assign(256, 0);
+    s->spin_rank_hi.assign(256 * 9, 0);
+    for (uint32_t lo = 0; lo < 256; ++lo) {
+        int t = 0;
+        int64_t r = 0;
+        for (int p = 0; p < 8; ++p)
+            if ((lo >> p) & 1u) r += (int64_t)binom(p, ++t);
+        s->spin_rank_lo[lo] = (int32_t)r;
+    }
+    for (uint32_t hi = 0; hi < 256; ++hi)
+        for (int c = 0; c <= 8; ++c) {
+            int t = c;
+            int64_t r = 0;
+            for (int p = 0; p < 8; ++p)
+                if ((hi >> p) & 1u) r += (int64_t)binom(8 + p, ++t);
+            s->spin_rank_hi[hi * 9 + c] = (int32_t)r;
+        }
+    s->spin_ok = true;
+}
+
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out) {
     // order % 3 picks the row order; 0..2 class major, 3..5 the classes of one
     // row together, 6..8 class major with up-segments (rows sharing the high
     // half of the up word) dealt round-robin to 8 equal chunks, one per XCD,
     // padded with empty items, so each XCD holds whole segments while all
-    // XCDs walk the same part of the row order.
+    // XCDs walk the same part of the row order.  9 and 10 take row order 3
+    // (up class, then inversion level), class major and row major.
     std::vector<int32_t> ro;
-    make_row_order(s, order % 3, ro);
+    make_row_order(s, row_order_kind(order), ro);
     std::vector<int32_t> pos(ro.size());
     for (size_t k = 0; k < ro.size(); ++k) pos[ro[k]] = (int32_t)k;
     out = s->hub_items;
-    const bool class_major = order < 3 || order >= 6;
+    const bool class_major = order < 3 || (order >= 6 && order != 10);
     std::stable_sort(out.begin(), out.end(), [&](const HubItem &a, const HubItem &b) {
         const int64_t ka = class_major ? ((int64_t)a.cls << 32 | pos[a.row0]) : ((int64_t)pos[a.row0] << 8 | a.cls);
         const int64_t kb = class_major ? ((int64_t)b.cls << 32 | pos[b.row0]) : ((int64_t)pos[b.row0] << 8 | b.cls);
         return ka < kb;
     });
-    if (order < 6) return;
+    if (order < 6 || order >= 9) return;
     const int n_chunks = 8;
     const int hshift = s->n_sites / 2;
     std::vector<std::vector<HubItem>> ch(n_chunks);
@@ -679,6 +720,11 @@ void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out)
         const uint32_t w = s->lwords[B.lbase + a];
         if (order == 1) {
             key[a] = (int64_t)inversions(w, n) << 32 | a;
+        } else if (order == 3) {
+            // class of the high half, then inversion level: every hop inside a
+            // class moves one level, so the source rows of a level lie in the
+            // levels next to it
+            key[a] = ((int64_t)__builtin_popcount(w >> h) << 56) | ((int64_t)inversions(w, n) << 32) | a;
         } else {
             const uint32_t hi = w >> h;
             key[a] = ((int64_t)__builtin_popcount(hi) << 56) | ((int64_t)inversions(hi, n - h) << 40) |

@@ -68,13 +68,14 @@ void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) 
 }
 
 ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
-    if (T.order < 0 || T.order > 8 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 3)
+    if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 3)
         return fail(ECUT_EINVAL, "bad tuning");
+    if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
     if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
         return fail(ECUT_EUNSUPPORTED, "class tiles not available");
     if (T.variant == 3 && s->kernel == 1 && !s->hub3_ok) return fail(ECUT_EUNSUPPORTED, "split passes not available");
     if (s->kernel == 1 && (T.order != s->tune.order || T.variant != s->tune.variant)) {
-        make_row_order(s, T.order % 3, s->row_order);
+        make_row_order(s, row_order_kind(T.order), s->row_order);
         make_hub_item_order(s, T.order, s->hub_items_ord);
         if (s->on_device && s->dev_row_order) {
             hipError_t e = hipMemcpy(s->dev_row_order, s->row_order.data(), s->row_order.size() * sizeof(int32_t),
@@ -87,6 +88,7 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
         }
     }
     s->tune = T;
+    if (s->kernel != 1) s->prob.spin_ok = (s->spin_ok && s->on_device && T.variant == 0) ? 1 : 0;
     return ECUT_OK;
 }
 
@@ -135,13 +137,14 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
             for (int order = 0; order < 6; ++order)
                 for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 0});
         if (s->hub3_ok)
-            for (int order : {6, 7, 8}) cands.push_back(ApplyTuning{0, 8, order, 0});
+            for (int order : {6, 7, 8, 9, 10}) cands.push_back(ApplyTuning{0, 8, order, 0});
         if (s->hub3_ok)
             for (int order : {0, 1}) cands.push_back(ApplyTuning{0, 1, order, 3});
         for (int order : {0, 2})
             for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 1});
     } else {
         cands.push_back(ApplyTuning{0, 0, 0, 0});
+        if (s->spin_ok) cands.push_back(ApplyTuning{0, 0, 0, 1});
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

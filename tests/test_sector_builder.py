@@ -87,6 +87,18 @@ def test_workload_block_structure():
     assert S3.info.n_eff == pytest.approx(1.0)
 
 
+def test_spin_kernel_eligibility():
+    # the ranking-table spin kernel needs both parts <= 16 sites, row tiles
+    # that fit its work group and <= 64 flip-flop terms inside the right part
+    for p in (I.heisenberg16(), I.j1j2_6x5(), I.Problem(I.xxz_chain(24, 1.0, 0.7), I.Cut("spatial", (1 << 12) - 1), 12)):
+        S = E.Sectors.from_problem(p, host_only=True)
+        assert S.info.kernel == 2 and S.info.kernel_flags == 4, p.model.name
+    wide = I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", 0b111), 10)   # right part: 17 sites
+    assert E.Sectors.from_problem(wide, host_only=True).info.kernel_flags == 0
+    dense = I.Problem(I.random_spin_model(np.random.default_rng(3), 14, n_bonds=91), I.Cut("spatial", 0b1), 7)
+    assert E.Sectors.from_problem(dense, host_only=True).info.kernel_flags == 0   # 78 flip-flop terms on the right
+
+
 def test_n_eff_is_block_participation_number():
     S = E.Sectors.from_problem(I.heisenberg16(), host_only=True)
     b = S.blocks()
