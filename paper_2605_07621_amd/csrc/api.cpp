@@ -205,6 +205,7 @@ ecut_status upload(ecut_sectors *s) {
     if (s->spin_ok) {
         P.spin_ok = s->tune.variant == 0 ? 1 : 0;
         P.n_rflip = (int32_t)s->spin_fmask.size();
+        P.max_d_r = s->max_d_r;
         P.rank_lo = (const int32_t *)(b + o_srl);
         P.rank_hi = (const int32_t *)(b + o_srh);
         P.rflip_mask = (const uint32_t *)(b + o_sfm);
@@ -310,7 +311,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
         }
     } else if (P.spin_ok) {
-        e = launch_spin(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
+        e = launch_spin(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), s->max_d_r, st);
     } else {
         e = launch_rows(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
     }
@@ -397,11 +398,12 @@ ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::v
     // of the queue is kept within each group
     std::vector<ItemDev> items;
     items.reserve(items_in.size());
-    int spin_tile = 0, rows_tile = 0, first_spin = -1;
+    int spin_tile = 0, spin_src = 0, rows_tile = 0, first_spin = -1;
     for (const ItemDev &it : items_in)
         if (probs[it.prob].spin_ok) {
             items.push_back(it);
             spin_tile = std::max(spin_tile, tiles[it.prob]);
+            spin_src = std::max(spin_src, probs[it.prob].max_d_r);
             if (first_spin < 0) first_spin = it.prob;
         }
     const size_t n_spin = items.size();
@@ -422,7 +424,7 @@ ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::v
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
     const ProblemDev *probs_d = (const ProblemDev *)S.dev;
     const ItemDev *items_d = (const ItemDev *)((char *)S.dev + pb);
-    if (n_spin > 0) e = launch_spin(probs_d, probs[first_spin], items_d, (int)n_spin, spin_tile, st);
+    if (n_spin > 0) e = launch_spin(probs_d, probs[first_spin], items_d, (int)n_spin, spin_tile, spin_src, st);
     if (e == hipSuccess && n_spin < items.size())
         e = launch_rows(probs_d, probs[0], items_d + n_spin, (int)(items.size() - n_spin), rows_tile, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");

@@ -153,6 +153,7 @@ struct ProblemDev {
     // spin kernel with ranking tables (spatial cut, both sides <= 16 sites)
     int32_t spin_ok;             // tables below are valid
     int32_t n_rflip;             // flip-flop terms inside the right part
+    int32_t max_d_r;             // largest right dimension of any block
     const int32_t *rank_lo;      // colex rank of the low byte: 256 entries
     const int32_t *rank_hi;      // colex rank of the high byte given popc(low byte): 256 x 9
     const uint32_t *rflip_mask;  // the two right-part bits of each flip-flop term

@@ -497,9 +497,211 @@ __device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32
     return rl[lo] + rh[(w >> 8) * 9u + (uint32_t)__popc(lo)];
 }
 
+// One-row item: every per-row quantity (left word, left CSR, source rows of
+// the cross terms) is uniform across the work group.
+__device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
+                                             double *xs2, const int32_t *rl, const int32_t *rh, const uint32_t *fm,
+                                             const double *fc, int n_flip, double *red) {
+    const int tid = threadIdx.x;
+    const int dR = B.d_r;
+    const int l = W.row0;
+    const int gl = B.lbase + l;
+    const uint32_t lw = P.lwords[gl];
+    const double *__restrict__ xblk = P.x + B.offset;
+    const double *__restrict__ xt = xblk + (int64_t)l * dR;
+    double acc[SPIN_M];
+    uint32_t wr[SPIN_M];
+    {
+        double xv[SPIN_M];
+#pragma unroll
+        for (int m = 0; m < SPIN_M; ++m) {
+            const int e = tid + m * SPIN_THREADS;
+            const bool ok = e < dR;
+            xv[m] = ok ? xt[e] : 0.0;
+            wr[m] = ok ? P.rwords[B.rbase + e] : 0u;
+            acc[m] = 0.0;
+        }
+        __syncthreads();   // the previous item's readers of xs / xs2 are done
+#pragma unroll
+        for (int m = 0; m < SPIN_M; ++m) {
+            const int e = tid + m * SPIN_THREADS;
+            if (e < dR) xs[e] = xv[m];
+        }
+    }
+    // left operator: neighbour rows of the same block at the same columns
+    {
+        const int q1 = P.hl_ptr[gl + 1];
+        for (int q = P.hl_ptr[gl]; q < q1; ++q) {
+            const double c = P.hl_val[q];
+            const double *__restrict__ xn = xblk + (int64_t)P.hl_col[q] * dR;
+            double v[SPIN_M];
+#pragma unroll
+            for (int m = 0; m < SPIN_M; ++m) {
+                const int e = tid + m * SPIN_THREADS;
+                v[m] = e < dR ? xn[e] : 0.0;
+            }
+#pragma unroll
+            for (int m = 0; m < SPIN_M; ++m) acc[m] += c * v[m];
+        }
+    }
+    // cross-cut flip-flops, grouped by left site: the source row (one per
+    // left site) is staged in xs2, then every bond of the group gathers from it
+    const int nx = P.n_xbond;
+    int k = 0;
+    while (k < nx) {
+        const int li = P.xbond[k].li;
+        int k1 = k + 1;
+        while (k1 < nx && P.xbond[k1].li == li) ++k1;
+        const uint32_t bl = (lw >> li) & 1u;
+        const int src = bl ? B.blk_lminus : B.blk_lplus;
+        const int lp = src >= 0 ? P.maps[(bl ? P.xbond[k].lmap_del : P.xbond[k].lmap_ins) + gl] : -1;
+        if (lp >= 0) {
+            const BlockDev S = P.blocks[src];
+            const double *__restrict__ srow = P.x + S.offset + (int64_t)lp * S.d_r;
+            __syncthreads();   // earlier readers of xs2 are done
+            for (int e = tid; e < S.d_r; e += SPIN_THREADS) xs2[e] = srow[e];
+            __syncthreads();
+            for (int kk = k; kk < k1; ++kk) {
+                const int rj = P.xbond[kk].rj;
+                const double c = P.xbond[kk].coef;
+#pragma unroll
+                for (int m = 0; m < SPIN_M; ++m) {
+                    const int e = tid + m * SPIN_THREADS;
+                    if (e < dR && ((wr[m] >> rj) & 1u) != bl) acc[m] += c * xs2[rank16(wr[m] ^ (1u << rj), rl, rh)];
+                }
+            }
+        }
+        k = k1;
+    }
+    __syncthreads();   // xs complete
+    // right operator from the staged row, diagonal, epilogue
+    double dgl = P.diag_l[gl];
+    double part = 0.0;
+#pragma unroll
+    for (int m = 0; m < SPIN_M; ++m) {
+        const int e = tid + m * SPIN_THREADS;
+        if (e >= dR) continue;
+        const uint32_t w = wr[m];
+        double a = 0.0;
+        for (int f = 0; f < n_flip; ++f) {
+            const uint32_t msk = fm[f];
+            if (__popc(w & msk) == 1) a += fc[f] * xs[rank16(w ^ msk, rl, rh)];
+        }
+        double dg = dgl + P.diag_r[B.rbase + e];
+        for (int x = 0; x < P.n_xdiag; ++x) {
+            const XDiagDev X = P.xdiag[x];
+            dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
+        }
+        const double x0 = xs[e];
+        double yv = P.xscale * (acc[m] + a + dg * x0);
+        const int64_t gi = B.offset + (int64_t)l * dR + e;
+        if (P.z) yv -= P.zcoef * P.z[gi];
+        P.y[gi] = yv;
+        part += x0 * yv;
+    }
+    if (P.partials) {
+        const double sum = block_sum(part, red);
+        if (tid == 0) P.partials[W.slot] = sum;
+    }
+}
+
+// Item of several short rows: per-element rows, cross terms gathered from
+// global memory (these blocks are small).
+__device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
+                                               const int32_t *rl, const int32_t *rh, const uint32_t *fm,
+                                               const double *fc, int n_flip, double *red) {
+    const int tid = threadIdx.x;
+    const int dR = B.d_r;
+    const int n = (W.row1 - W.row0) * dR;
+    const float inv_d = 1.0f / (float)dR;
+    const double *__restrict__ xblk = P.x + B.offset;
+    const double *__restrict__ xt = xblk + (int64_t)W.row0 * dR;
+    double acc[SPIN_M];
+    uint32_t wr[SPIN_M];
+    int lrow[SPIN_M];   // row within the item (exact: e, dR < 2^13, so the float quotient never rounds across an integer)
+    {
+        double xv[SPIN_M];
+#pragma unroll
+        for (int m = 0; m < SPIN_M; ++m) {
+            const int e = tid + m * SPIN_THREADS;
+            const bool ok = e < n;
+            const int lr = (int)(((float)e + 0.5f) * inv_d);
+            lrow[m] = lr;
+            xv[m] = ok ? xt[e] : 0.0;
+            wr[m] = ok ? P.rwords[B.rbase + e - lr * dR] : 0u;
+            acc[m] = 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < SPIN_M; ++m) {
+            const int e = tid + m * SPIN_THREADS;
+            if (e < n) xs[e] = xv[m];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < SPIN_M; ++m) {
+        const int e = tid + m * SPIN_THREADS;
+        if (e >= n) continue;
+        const int lr = lrow[m];
+        const int r = e - lr * dR;
+        const int gl = B.lbase + W.row0 + lr;
+        const uint32_t lw = P.lwords[gl];
+        double a = 0.0;
+        const int q1 = P.hl_ptr[gl + 1];
+        for (int q = P.hl_ptr[gl]; q < q1; ++q) a += P.hl_val[q] * xblk[(int64_t)P.hl_col[q] * dR + r];
+        for (int k = 0; k < P.n_xbond; ++k) {
+            const XBondDev X = P.xbond[k];
+            const uint32_t bl = (lw >> X.li) & 1u;
+            if (((wr[m] >> X.rj) & 1u) == bl) continue;
+            const int src = bl ? B.blk_lminus : B.blk_lplus;
+            if (src < 0) continue;
+            const int lp = P.maps[(bl ? X.lmap_del : X.lmap_ins) + gl];
+            if (lp < 0) continue;
+            const BlockDev S = P.blocks[src];
+            a += X.coef * P.x[S.offset + (int64_t)lp * S.d_r + rank16(wr[m] ^ (1u << X.rj), rl, rh)];
+        }
+        acc[m] = a;
+    }
+    __syncthreads();
+    double part = 0.0;
+#pragma unroll
+    for (int m = 0; m < SPIN_M; ++m) {
+        const int e = tid + m * SPIN_THREADS;
+        if (e >= n) continue;
+        const int lr = lrow[m];
+        const int r = e - lr * dR;
+        const int gl = B.lbase + W.row0 + lr;
+        const uint32_t w = wr[m];
+        const uint32_t lw = P.lwords[gl];
+        const double *xrow = xs + lr * dR;
+        double a = 0.0;
+        for (int f = 0; f < n_flip; ++f) {
+            const uint32_t msk = fm[f];
+            if (__popc(w & msk) == 1) a += fc[f] * xrow[rank16(w ^ msk, rl, rh)];
+        }
+        double dg = P.diag_l[gl] + P.diag_r[B.rbase + r];
+        for (int x = 0; x < P.n_xdiag; ++x) {
+            const XDiagDev X = P.xdiag[x];
+            dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
+        }
+        const double x0 = xs[e];
+        double yv = P.xscale * (acc[m] + a + dg * x0);
+        const int64_t gi = B.offset + (int64_t)W.row0 * dR + e;
+        if (P.z) yv -= P.zcoef * P.z[gi];
+        P.y[gi] = yv;
+        part += x0 * yv;
+    }
+    if (P.partials) {
+        const double sum = block_sum(part, red);
+        if (tid == 0) P.partials[W.slot] = sum;
+    }
+}
+
+// xs: the item's tile (max_tile doubles); xs2 (one-row items): a source row
+// of the cross terms (max_src doubles, the largest d_r of the launch).
 __global__ __launch_bounds__(SPIN_THREADS, 4) void k_spin(const ProblemDev *__restrict__ probs,
                                                           const ProblemDev single, const ItemDev *__restrict__ items,
-                                                          int n_items) {
+                                                          int n_items, int max_tile) {
     extern __shared__ __align__(16) double xs[];
     __shared__ double red[SPIN_THREADS / 64];
     __shared__ int32_t rl[256];
@@ -507,6 +709,7 @@ __global__ __launch_bounds__(SPIN_THREADS, 4) void k_spin(const ProblemDev *__re
     __shared__ uint32_t fm[SPIN_MAX_FLIP];
     __shared__ double fc[SPIN_MAX_FLIP];
     const int tid = threadIdx.x;
+    double *xs2 = xs + ((max_tile + 1) & ~1);
     for (int i = tid; i < 256; i += SPIN_THREADS) rl[i] = single.rank_lo[i];
     for (int i = tid; i < 256 * 9; i += SPIN_THREADS) rh[i] = single.rank_hi[i];
     int loaded = -1;
@@ -523,119 +726,10 @@ __global__ __launch_bounds__(SPIN_THREADS, 4) void k_spin(const ProblemDev *__re
             loaded = W.prob;
         }
         const BlockDev B = P.blocks[W.block];
-        const int dR = B.d_r;
-        const int nrows = W.row1 - W.row0;
-        const int n = nrows * dR;
-        const bool one = nrows == 1;
-        const double *__restrict__ xblk = P.x + B.offset;
-        const double *__restrict__ xt = xblk + (int64_t)W.row0 * dR;
-        double acc[SPIN_M];
-        uint32_t wr[SPIN_M];
-        // stage the tile; right words of this thread's elements
-        {
-            double xv[SPIN_M];
-#pragma unroll
-            for (int m = 0; m < SPIN_M; ++m) {
-                const int e = tid + m * SPIN_THREADS;
-                const bool ok = e < n;
-                const int lr = one ? 0 : e / dR;
-                const int r = e - lr * dR;
-                xv[m] = ok ? xt[e] : 0.0;
-                wr[m] = ok ? P.rwords[B.rbase + r] : 0u;
-                acc[m] = 0.0;
-            }
-            __syncthreads();   // the previous item's readers of xs are done; fm/fc are loaded
-#pragma unroll
-            for (int m = 0; m < SPIN_M; ++m) {
-                const int e = tid + m * SPIN_THREADS;
-                if (e < n) xs[e] = xv[m];
-            }
-        }
-        // left operator: neighbour rows of the same block at the same columns
-        if (one) {
-            const int gl = B.lbase + W.row0;
-            const int q1 = P.hl_ptr[gl + 1];
-            for (int q = P.hl_ptr[gl]; q < q1; ++q) {
-                const double c = P.hl_val[q];
-                const double *__restrict__ xn = xblk + (int64_t)P.hl_col[q] * dR;
-                double v[SPIN_M];
-#pragma unroll
-                for (int m = 0; m < SPIN_M; ++m) {
-                    const int e = tid + m * SPIN_THREADS;
-                    v[m] = e < n ? xn[e] : 0.0;
-                }
-#pragma unroll
-                for (int m = 0; m < SPIN_M; ++m) acc[m] += c * v[m];
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < SPIN_M; ++m) {
-                const int e = tid + m * SPIN_THREADS;
-                if (e >= n) continue;
-                const int lr = e / dR;
-                const int r = e - lr * dR;
-                const int gl = B.lbase + W.row0 + lr;
-                const int q1 = P.hl_ptr[gl + 1];
-                double a = 0.0;
-                for (int q = P.hl_ptr[gl]; q < q1; ++q) a += P.hl_val[q] * xblk[(int64_t)P.hl_col[q] * dR + r];
-                acc[m] += a;
-            }
-        }
-        // cross-cut flip-flops and diagonal cut terms
-        for (int k = 0; k < P.n_xbond; ++k) {
-            const XBondDev X = P.xbond[k];
-#pragma unroll
-            for (int m = 0; m < SPIN_M; ++m) {
-                const int e = tid + m * SPIN_THREADS;
-                if (e >= n) continue;
-                const int lr = one ? 0 : e / dR;
-                const int gl = B.lbase + W.row0 + lr;
-                const uint32_t bl = (P.lwords[gl] >> X.li) & 1u;
-                const uint32_t br = (wr[m] >> X.rj) & 1u;
-                if (bl == br) continue;
-                const int src = bl ? B.blk_lminus : B.blk_lplus;
-                const int lp = P.maps[(bl ? X.lmap_del : X.lmap_ins) + gl];
-                if (src < 0 || lp < 0) continue;
-                const BlockDev S = P.blocks[src];
-                const int rp = rank16(wr[m] ^ (1u << X.rj), rl, rh);
-                acc[m] += X.coef * P.x[S.offset + (int64_t)lp * S.d_r + rp];
-            }
-        }
-        __syncthreads();
-        // right operator from the staged tile, diagonal, epilogue
-        double part = 0.0;
-#pragma unroll
-        for (int m = 0; m < SPIN_M; ++m) {
-            const int e = tid + m * SPIN_THREADS;
-            if (e >= n) continue;
-            const int lr = one ? 0 : e / dR;
-            const int r = e - lr * dR;
-            const int gl = B.lbase + W.row0 + lr;
-            const uint32_t w = wr[m];
-            const double *xrow = xs + lr * dR;
-            double a = 0.0;
-            for (int k = 0; k < n_flip; ++k) {
-                const uint32_t f = fm[k];
-                if (__popc(w & f) == 1) a += fc[k] * xrow[rank16(w ^ f, rl, rh)];
-            }
-            const uint32_t lw = P.lwords[gl];
-            double dg = P.diag_l[gl] + P.diag_r[B.rbase + r];
-            for (int k = 0; k < P.n_xdiag; ++k) {
-                const XDiagDev X = P.xdiag[k];
-                const double fl = (double)((lw >> X.li) & 1u) - 0.5, fr = (double)((w >> X.rj) & 1u) - 0.5;
-                dg += X.coef * fl * fr;
-            }
-            const double x0 = xs[e];
-            double yv = P.xscale * (acc[m] + a + dg * x0);
-            const int64_t gi = B.offset + (int64_t)W.row0 * dR + e;
-            if (P.z) yv -= P.zcoef * P.z[gi];
-            P.y[gi] = yv;
-            part += x0 * yv;
-        }
-        if (P.partials) {
-            const double sum = block_sum(part, red);
-            if (tid == 0) P.partials[W.slot] = sum;
-        }
+        if (W.row1 - W.row0 == 1)
+            spin_one_row(P, B, W, xs, xs2, rl, rh, fm, fc, n_flip, red);
+        else
+            spin_many_rows(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
     }
 }
 
@@ -1131,12 +1225,13 @@ hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, cons
 }
 
 hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
-                       int max_tile_elems, hipStream_t st) {
+                       int max_tile_elems, int max_src, hipStream_t st) {
     if (n_items <= 0) return hipSuccess;
-    if (max_tile_elems > SPIN_TILE) return hipErrorInvalidValue;
+    if (max_tile_elems > SPIN_TILE || max_src > SPIN_TILE) return hipErrorInvalidValue;
     const int grid = n_items < 65536 ? n_items : 65536;
-    const size_t lds = (size_t)std::max(max_tile_elems, 1) * 8;
-    hipLaunchKernelGGL(k_spin, dim3(grid), dim3(SPIN_THREADS), lds, st, probs_d, single, items_d, n_items);
+    const int tile = std::max(max_tile_elems, 1);
+    const size_t lds = ((size_t)((tile + 1) & ~1) + (size_t)std::max(max_src, 1)) * 8;
+    hipLaunchKernelGGL(k_spin, dim3(grid), dim3(SPIN_THREADS), lds, st, probs_d, single, items_d, n_items, tile);
     return hipGetLastError();
 }
 
@@ -1162,7 +1257,7 @@ hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32
 hipError_t set_hub_lds_limits(size_t bytes) {
     hipError_t e = hipSuccess;
     const int b = (int)bytes;
-    e = hipFuncSetAttribute((const void *)k_spin, hipFuncAttributeMaxDynamicSharedMemorySize, SPIN_TILE * 8);
+    e = hipFuncSetAttribute((const void *)k_spin, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * SPIN_TILE * 8 + 16);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;

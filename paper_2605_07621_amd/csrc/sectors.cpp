@@ -247,6 +247,10 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
                 }
             }
         }
+        // cross bonds grouped by their left site: the spin kernel stages the
+        // one source row of a left site once for all its bonds
+        std::stable_sort(s->xbond.begin(), s->xbond.end(),
+                         [](const XBondDev &a, const XBondDev &b) { return a.li < b.li; });
     } else {
         if (c->kind != ECUT_CUT_UPDN)
             return fail(ECUT_EUNSUPPORTED, "Hubbard models take the up/down cut (spatial fermionic cut not built)");
