@@ -8,8 +8,11 @@ diagonal and cross-cut terms: the whole per-application hot path) on the
 
 Prints one JSON line: applies/s, the roofline of the dominant kernel
 (algorithmic bytes / average kernel time from HIP events on the launch
-stream), the oracle timed on a bounded sample on the host cores, and a
-short Lanczos-step timing.
+stream), the oracle timed on a bounded sample on the host cores, a short
+Lanczos-step timing, the apply time of the other configurations (Heisenberg
+16, Hubbard 12, J1-J2 6x5), the workload's ground-state solve (CGS2 over at
+most 150 stored vectors, tol 1e-10) against the oracle's stored energy, and
+the serving comparison (sequential vs continuous batching).
 """
 import argparse
 import hashlib
@@ -105,6 +108,7 @@ def serving_bench(n_requests, budget_gb):
     budget = budget_gb * 2**30
     zeros = np.zeros(len(reqs))
     seq = _run_server(reqs, zeros, budget, 1, True)
+    progress("serving: sequential closed loop done")
     s_seq = _lat_stats(seq, min(r["t_submit"] for r in seq))
     bat = _run_server(reqs, zeros, budget, 0, False)
     s_bat = _lat_stats(bat, min(r["t_submit"] for r in bat))
@@ -117,9 +121,142 @@ def serving_bench(n_requests, budget_gb):
         arr = I.poisson_arrivals(len(reqs), rho * mu)
         r_seq = _run_server(reqs, arr, budget, 1, True)
         r_bat = _run_server(reqs, arr, budget, 0, False)
+        progress(f"serving: poisson rho={rho} done")
         out[f"poisson_rho{rho}"] = {"rate_per_s": round(rho * mu, 3),
                                     "sequential": _lat_stats(r_seq, min(r["t_submit"] for r in r_seq)),
                                     "batched": _lat_stats(r_bat, min(r["t_submit"] for r in r_bat))}
+    return out
+
+
+def kernel_name(S):
+    """Name of the kernel that carries the apply under the handle's tuning."""
+    info, t = S.info, S.get_tuning()
+    if info.kernel == 1:
+        v = t["variant"]
+        if v == 0:
+            return "k_hub3" if info.kernel_flags & 2 else "k_hub2"
+        return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3"}[v]
+    return "k_spin" if (info.kernel_flags & 4 and t["variant"] == 0) else "k_rows"
+
+
+def time_applies(S, x, y, stream, reps, warmup=2):
+    import torch
+    for _ in range(warmup):
+        S.apply(x, y, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        S.apply(x, y, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def other_workloads(names, stream):
+    """H*psi time of the other measured configurations (autotuned), each
+    with its algorithmic bytes per application (read psi, write y, metadata)."""
+    import torch
+    from paper_2605_07621_amd import ecut, inputs as I
+    out = {}
+    for name in names:
+        p = I.WORKLOADS[name]()
+        S = ecut.Sectors.from_problem(p)
+        x = S.import_(torch.from_numpy(I.psi(p.meta["seed"], S.dim)).to("cuda:0"))
+        y = torch.empty_like(x)
+        S.autotune(x, y, stream=stream)
+        progress(f"{name}: tuned")
+        reps = 10 if S.dim > 10**7 else 200
+        ms = time_applies(S, x, y, stream, reps)
+        alg = 2 * S.dim * 8 + int(S.info.device_bytes)
+        out[name] = {"dim": S.dim, "blocks": int(S.info.n_blocks), "kernel": kernel_name(S), "ms": round(ms, 4),
+                     "applies_per_s": round(1e3 / ms, 2), "algorithmic_GBps": round(alg / (ms * 1e-3) / 1e9, 1)}
+        del S, x, y
+    torch.cuda.empty_cache()
+    return out
+
+
+def ground_state_solve(S, p, n_keep, tol):
+    """Lanczos to the ground energy with CGS2 reorthogonalisation over at
+    most n_keep stored vectors (explicit restarts), compared with the
+    oracle's energy stored under tests/golden."""
+    import torch
+    from paper_2605_07621_amd import inputs as I
+    v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to("cuda:0"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e, st, _ = S.lanczos(v0, n_keep, tol=tol, reorth=True, max_restarts=20)
+    dt = time.perf_counter() - t0
+    out = {"energy": e, "steps": st["steps"], "restarts": st["restarts"], "converged": bool(st["converged"]),
+           "seconds": round(dt, 3), "n_keep": n_keep, "tol": tol, "reorth": "CGS2"}
+    gold = os.path.join(ROOT, "tests", "golden", f"{p.meta.get('name', '')}_energy.json")
+    if os.path.exists(gold):
+        with open(gold) as f:
+            ref = json.load(f)["energy"]
+        out["oracle_energy"] = ref
+        out["abs_diff_vs_oracle"] = abs(e - ref)
+    del v0
+    torch.cuda.empty_cache()
+    return out
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _csv_rows(d, suffix=".csv"):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True):
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize_profiles(workload, kernel, copy_bytes, trace_dir, fetch_dir, write_dir, commands):
+    """Write the committed profile summaries of one kernel and workload:
+    profiles/<kernel>_<workload>_trace.txt, the per-kernel statistics of a
+    rocprofv3 --kernel-trace --stats run, and
+    profiles/<kernel>_<workload>_traffic.json, the HBM bytes per launch from
+    a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each scaled by
+    what the same counter reads for a plain copy of copy_bytes bytes in the
+    same run (the profiled command makes those copies with --copy-probe)."""
+    import statistics
+    stats = [r for r in _csv_rows(trace_dir, "kernel_stats.csv") if "AverageNs" in r and "Calls" in r]
+    lines = [f"# rocprofv3 kernel statistics: {workload}", "", "command (from the repository root):",
+             "  " + commands.get("setup", ""), "  " + commands["trace"], "",
+             f"{'kernel':72s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s}"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"{r['Name'][:72]:72s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.3f}")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"{kernel}_{workload}_trace.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    out = {"kernel": kernel, "workload": workload, "kernel_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
+           "commands": commands}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        ks, cs = [], []
+        for r in _csv_rows(d):
+            if r.get("Counter_Name") != name:
+                continue
+            kn = r["Kernel_Name"]
+            v = float(r["Counter_Value"]) * 1024.0
+            if f"ecut::{kernel}" in kn:
+                ks.append(v)
+            elif "copyBuffer" in kn:
+                cs.append(v)
+        big = [c for c in cs if c > 0.25 * copy_bytes / 2]
+        scale = copy_bytes / statistics.mean(big) if big else None
+        out[name] = {"kernel_raw_bytes_per_launch": statistics.mean(ks) if ks else None,
+                     "copy_raw_bytes": statistics.mean(big) if big else None, "scale": scale}
+    f_, w_ = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    if f_["kernel_raw_bytes_per_launch"] and f_["scale"] and w_["kernel_raw_bytes_per_launch"] and w_["scale"]:
+        out["bytes_per_launch"] = (f_["kernel_raw_bytes_per_launch"] * f_["scale"]
+                                   + w_["kernel_raw_bytes_per_launch"] * w_["scale"])
+    with open(os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
     return out
 
 
@@ -133,9 +270,29 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lanczos-steps", type=int, default=10)
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--serving", type=int, default=64, help="requests in the serving run (0: skip)")
+    ap.add_argument("--serving", type=int, default=256, help="requests in the serving run (0: skip)")
+    ap.add_argument("--no-solve", action="store_true", help="skip the ground-state solve of the workload")
+    ap.add_argument("--solve-keep", type=int, default=150)
+    ap.add_argument("--no-others", action="store_true", help="skip the other configurations")
+    ap.add_argument("--tuning", default=None, help="grid,n_xcd,row_order,variant instead of autotuning")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, make 3 plain device copies of psi (scale reference for counter runs)")
+    ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summaries from rocprofv3 output and exit (no GPU use)")
+    ap.add_argument("--kernel", default="k_hub3", help="kernel named in --summarize")
+    ap.add_argument("--commands", default=None, help="JSON of the profiling commands, for --summarize")
     ap.add_argument("--serving-budget-gb", type=float, default=24.0)
     args = ap.parse_args()
+    if args.summarize:
+        from paper_2605_07621_amd import inputs as I
+        p = I.WORKLOADS[args.workload]()
+        import math
+        dim = math.comb(p.model.n_sites, p.n_up) * (math.comb(p.model.n_sites, p.n_dn) if p.n_dn or
+                                                         p.model.kind == "hubbard" else 1)
+        cmds = json.loads(args.commands) if args.commands else {}
+        out = summarize_profiles(args.workload, args.kernel, 8 * dim, *args.summarize, cmds)
+        print(json.dumps(out))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -152,7 +309,11 @@ def main():
     x = S.import_(torch.from_numpy(I.psi(p.meta.get("seed", 1), n)).to(dev))
     y = torch.empty_like(x)
     stream = torch.cuda.current_stream()
-    tuning = S.autotune(x, y, stream=stream) if not args.no_autotune else S.get_tuning()
+    if args.tuning:
+        S.set_tuning(*[int(v) for v in args.tuning.split(",")])
+        tuning = S.get_tuning()
+    else:
+        tuning = S.autotune(x, y, stream=stream) if not args.no_autotune else S.get_tuning()
     for _ in range(args.warmup):
         S.apply(x, y, stream=stream)
     torch.cuda.synchronize()
@@ -167,8 +328,12 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     kern_ms = ev0.elapsed_time(ev1) / args.steps
+    if args.copy_probe:
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
     alg_bytes = 2 * n * 8 + int(S.info.device_bytes)
-    kernel = "k_hub" if S.info.kernel == 1 else "k_rows"
+    kernel = kernel_name(S)
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic = traffic_from_profile(kernel, args.workload, alg_bytes)
 
@@ -203,8 +368,20 @@ def main():
                      "kernel_ms": round(kern_ms, 5), "kernel": kernel},
         "lanczos": lz,
     }
+    del y
+    torch.cuda.empty_cache()
+    progress(f"headline done: {kern_ms:.4f} ms per apply")
+    if not args.no_others:
+        line["other_workloads"] = other_workloads([w for w in ("heisenberg16", "hubbard12", "j1j2_6x5")
+                                                   if w != args.workload], stream)
+    progress("other workloads done")
+    if not args.no_solve:
+        p.meta["name"] = args.workload
+        line["ground_state"] = ground_state_solve(S, p, args.solve_keep, 1e-10)
+    progress("ground-state solve done")
     if args.serving > 0:
         line["serving"] = serving_bench(args.serving, args.serving_budget_gb)
+    progress("serving done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(line), flush=True)

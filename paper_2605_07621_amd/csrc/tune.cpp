@@ -162,6 +162,7 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
     for (const ApplyTuning &T : cands) {
         rs = apply_tuning(s, T);
         if (rs != ECUT_OK) break;
+        P.spin_ok = s->prob.spin_ok;   // the kernel choice of this candidate
         rs = launch_apply(s, P, st);   // warm-up
         if (rs != ECUT_OK) break;
         hipEventRecord(e0, st);
