@@ -119,7 +119,9 @@ typedef struct ecut_sectors_info {
     int32_t kernel_flags;     /* Hubbard: bit 0 class tiles available, bit 1 uniform-chain fast path
                                  (and the split two-pass variant) available; spin: bit 2 the
                                  ranking-table kernel available (both parts <= 16 sites, row
-                                 tiles <= 6656 amplitudes, <= 64 flip-flop terms in the right part) */
+                                 tiles <= 7168 amplitudes, <= 64 flip-flop terms in the right part);
+                                 Hubbard: bit 3 the whole-row kernel available (<= 16 sites, even
+                                 row length <= 14336, <= 64 bonds) */
     int32_t reserved;
     int64_t device_bytes;     /* device metadata held by the handle */
     double n_eff;             /* 1 / sum_q w_q^2 with w_q = d_L d_R / dim (block-size participation number) */
@@ -211,7 +213,10 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
  *              work groups per CU; the uniform-chain fast kernel when it
  *              applies), 1 whole rows staged in LDS, 2 generic class tiles,
  *              3 two passes: the left operator over L2-resident column slabs,
- *              then the right operator and diagonal on class tiles.
+ *              then the right operator and diagonal on class tiles,
+ *              4 whole rows with 16-byte access: the row in LDS, down-spin
+ *              hops found by ranking the hopped word (any hopping graph;
+ *              needs kernel_flags bit 3 and 16-byte aligned vectors).
  *              Spin and generic problems (kernel 2) take variant 0 (the
  *              ranking-table spin kernel when kernel_flags bit 2 is set, else
  *              the generic row kernel) or 1 (the generic row kernel, which

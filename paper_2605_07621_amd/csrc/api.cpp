@@ -154,10 +154,17 @@ ecut_status upload(ecut_sectors *s) {
         std::copy(s->hub_items_ord.begin(), s->hub_items_ord.end(), items_cap.begin());
         o_hit = A.add(items_cap);
     }
-    size_t o_srl = 0, o_srh = 0, o_sfm = 0, o_sfc = 0;
-    if (s->spin_ok) {
+    size_t o_srl = 0, o_srh = 0, o_sfm = 0, o_sfc = 0, o_hbm = 0, o_hbb = 0, o_hbc = 0;
+    if (s->spin_ok || s->hubrow_ok) {
         o_srl = A.add(s->spin_rank_lo);
         o_srh = A.add(s->spin_rank_hi);
+    }
+    if (s->hubrow_ok) {
+        o_hbm = A.add(s->hrow_bmask);
+        o_hbb = A.add(s->hrow_bbetw);
+        o_hbc = A.add(s->hrow_bcoef);
+    }
+    if (s->spin_ok) {
         o_sfm = A.add(s->spin_fmask);
         o_sfc = A.add(s->spin_fcoef);
     }
@@ -225,6 +232,14 @@ ecut_status upload(ecut_sectors *s) {
         H.coef = (const double *)(b + o_cf);
         H.u = (const double *)(b + o_u);
         H.rwords16 = s->hub_rw16.empty() ? nullptr : (const uint16_t *)(b + o_rw16);
+        if (s->hubrow_ok) {
+            H.n_dbond = (int32_t)s->hrow_bmask.size();
+            H.dbond_mask = (const uint32_t *)(b + o_hbm);
+            H.dbond_betw = (const uint32_t *)(b + o_hbb);
+            H.dbond_coef = (const double *)(b + o_hbc);
+            H.rank_lo = (const int32_t *)(b + o_srl);
+            H.rank_hi = (const int32_t *)(b + o_srh);
+        }
         H.rwords32 = P.rwords + s->blocks[0].rbase;
         s->dev_row_order = (int32_t *)(b + o_order);
         H.cls = (const int32_t *)(b + o_hcc);
@@ -299,6 +314,11 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             A3.zcoef = P.zcoef;
             const int slab_grid = 8 * std::max(1, (n_cu / 8) * hub_blocks_per_cu(4, 0));
             e = launch_hub3(s, A3, grid, n_xcd, T.variant == 3, slab_grid, st);
+        } else if (T.variant == 4 && s->hubrow_ok) {
+            if (((uintptr_t)P.x | (uintptr_t)P.y | (uintptr_t)P.z) & 15)
+                return fail(ECUT_EINVAL, "the whole-row kernel needs 16-byte aligned vectors");
+            const int grid = T.grid > 0 ? T.grid : n_cu;
+            e = launch_hubrow(s, P, s->dev_row_order, s->blocks[0].d_l, grid, st);
         } else if ((T.variant == 0 || T.variant == 2) && s->hub2_ok) {
             const size_t lds = hub2_lds_bytes(s);
             if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "class tiles exceed the device's LDS per work group");
@@ -323,7 +343,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
 int32_t apply_partial_slots(const ecut_sectors *s) {
     if (s->kernel != 1) return (int32_t)s->items.size();
     const bool tiles = ((s->tune.variant == 0 || s->tune.variant == 3) && (s->hub3_ok || s->hub2_ok)) ||
-                       (s->tune.variant == 2 && s->hub2_ok);
+                       (s->tune.variant == 2 && s->hub2_ok);   // variants 1 and 4: one slot per row
     return tiles ? (int32_t)s->hub_items.size() : s->blocks[0].d_l;
 }
 
@@ -485,7 +505,7 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
     I.n_cross_offdiag = 2 * (int32_t)s->xbond.size();
     I.n_cross_diag = (int32_t)s->xdiag.size();
     I.kernel = s->kernel;
-    I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0);
+    I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0) | (s->hubrow_ok ? 8 : 0);
     I.device_bytes = (int64_t)s->dev_bytes;
     I.n_eff = s->n_eff;
     *info = I;

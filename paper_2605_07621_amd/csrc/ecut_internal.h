@@ -83,6 +83,14 @@ struct HubDev {
     const double *u;             // [n_sites] U_i
     const uint16_t *rwords16;    // [d_r] down words (n_r <= 16) or NULL
     const uint32_t *rwords32;    // [d_r] down words
+    // whole-row kernel: down-spin hops by ranking the hopped word
+    int32_t n_dbond;             // bonds with t != 0
+    int32_t dbond_pad_;
+    const uint32_t *dbond_mask;  // [n_dbond] the two sites of the bond
+    const uint32_t *dbond_betw;  // [n_dbond] sites strictly between them (fermion sign)
+    const double *dbond_coef;    // [n_dbond] -t_b
+    const int32_t *rank_lo;      // colex byte tables (see the spin kernel)
+    const int32_t *rank_hi;
     // Class tiles.  The down basis splits into classes by the popcount k of
     // the high part; a class is nseg segments (one per high word) of L
     // consecutive columns (one per low word of count N_dn - k).  Hops inside
@@ -221,6 +229,10 @@ struct ecut_sectors {
     std::vector<ecut::HubItem> hub_items;         // class-tile items, slot order
     std::vector<ecut::HubItem> hub_items_ord;     // class-tile items, processing order
     size_t hub_items_cap = 0;                     // device capacity for any processing order
+    // Hubbard whole-row kernel (16-byte row access, hops ranked in LDS)
+    bool hubrow_ok = false;
+    std::vector<uint32_t> hrow_bmask, hrow_bbetw;
+    std::vector<double> hrow_bcoef;
     // spin kernel with ranking tables
     bool spin_ok = false;
     std::vector<int32_t> spin_rank_lo, spin_rank_hi;

@@ -24,6 +24,10 @@ constexpr int SPIN_THREADS = 1024;
 constexpr int SPIN_M = 7;                    // element slots per thread of the spin kernel
 constexpr int SPIN_TILE = SPIN_THREADS * SPIN_M;
 constexpr int SPIN_MAX_FLIP = 64;            // flip-flop terms inside the right part
+constexpr int HUBROW_THREADS = 1024;
+constexpr int HUBROW_P = 7;                  // column pairs per thread of the whole-row Hubbard kernel
+constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;
+constexpr int HUBROW_MAX_BOND = 64;
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
 constexpr int MAX_BASIS = 1024;              // CGS2: vectors per projection call
@@ -60,6 +64,9 @@ size_t hub3_lds_bytes(const ecut_sectors *s);
 hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, bool split, int slab_grid,
                        hipStream_t st);
 int hub_blocks_per_cu(int which, size_t lds);
+// whole-row Hubbard kernel: rows_d lists the rows in processing order
+hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
+                         hipStream_t st);
 hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
                        double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);

@@ -477,6 +477,146 @@ __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const
     }
 }
 
+// colex rank of a word of at most 16 bits from the two byte tables
+__device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32_t *rh) {
+    const uint32_t lo = w & 255u;
+    return rl[lo] + rh[(w >> 8) * 9u + (uint32_t)__popc(lo)];
+}
+
+// ------------------------------------------------------------------------
+// Hubbard up/down cut, whole rows (down words of at most 16 bits, even row
+// length).  One work group per row a of Psi[a][b]:
+//  - the row is read once with 16-byte loads (column pairs) and staged in LDS;
+//  - up-spin hops: the neighbour rows of the left CSR (wave-uniform), read
+//    at the same column pairs, two rows in flight per thread;
+//  - down-spin hops: for every bond whose two sites hold one particle, the
+//    hopped word is ranked with the colex byte tables and its amplitude read
+//    from the staged row; sign (-1)^(particles strictly between the sites);
+//  - diagonal U_i n_i,up n_i,dn from the two words;
+//  - 16-byte stores of y = xscale H x - zcoef z, one partial <x, y> per row.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P, const int32_t *__restrict__ rows,
+                                                              int n_rows, int dR) {
+    extern __shared__ __align__(16) double xs[];
+    __shared__ int32_t rl[256];
+    __shared__ int32_t rh[256 * 9];
+    __shared__ uint32_t bm[HUBROW_MAX_BOND], bb[HUBROW_MAX_BOND];
+    __shared__ double bc[HUBROW_MAX_BOND];
+    __shared__ double red[HUBROW_THREADS / 64];
+    const HubDev &H = P.hub;
+    const int tid = threadIdx.x;
+    const int n_bond = H.n_dbond;
+    for (int i = tid; i < 256; i += HUBROW_THREADS) rl[i] = H.rank_lo[i];
+    for (int i = tid; i < 256 * 9; i += HUBROW_THREADS) rh[i] = H.rank_hi[i];
+    for (int i = tid; i < n_bond; i += HUBROW_THREADS) {
+        bm[i] = H.dbond_mask[i];
+        bb[i] = H.dbond_betw[i];
+        bc[i] = H.dbond_coef[i];
+    }
+    const int np = dR >> 1;
+    double2 *xs2 = (double2 *)xs;
+    const uint32_t *__restrict__ wpairs = (const uint32_t *)H.rwords16;   // two 16-bit words per column pair
+    for (int k = blockIdx.x; k < n_rows; k += gridDim.x) {
+        const int a = rows[k];
+        const double2 *__restrict__ xr = (const double2 *)(P.x + (int64_t)a * dR);
+        double2 acc[HUBROW_P];
+        {
+            double2 xv[HUBROW_P];
+#pragma unroll
+            for (int m = 0; m < HUBROW_P; ++m) {
+                const int p = tid + m * HUBROW_THREADS;
+                xv[m] = p < np ? xr[p] : make_double2(0.0, 0.0);
+                acc[m] = make_double2(0.0, 0.0);
+            }
+            __syncthreads();   // readers of the previous row are done (and the tables are loaded)
+#pragma unroll
+            for (int m = 0; m < HUBROW_P; ++m) {
+                const int p = tid + m * HUBROW_THREADS;
+                if (p < np) xs2[p] = xv[m];
+            }
+        }
+        // up-spin hops: whole neighbour rows, two in flight
+        {
+            const int q0 = P.hl_ptr[a], q1 = P.hl_ptr[a + 1];
+            for (int q = q0; q < q1; q += 2) {
+                const bool two = q + 1 < q1;
+                const double c0 = P.hl_val[q], c1 = two ? P.hl_val[q + 1] : 0.0;
+                const double2 *__restrict__ n0 = (const double2 *)(P.x + (int64_t)P.hl_col[q] * dR);
+                const double2 *__restrict__ n1 = two ? (const double2 *)(P.x + (int64_t)P.hl_col[q + 1] * dR) : n0;
+                double2 v0[HUBROW_P], v1[HUBROW_P];
+#pragma unroll
+                for (int m = 0; m < HUBROW_P; ++m) {
+                    const int p = tid + m * HUBROW_THREADS;
+                    const bool ok = p < np;
+                    v0[m] = ok ? n0[p] : make_double2(0.0, 0.0);
+                    v1[m] = ok && two ? n1[p] : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int m = 0; m < HUBROW_P; ++m) {
+                    acc[m].x += c0 * v0[m].x + c1 * v1[m].x;
+                    acc[m].y += c0 * v0[m].y + c1 * v1[m].y;
+                }
+            }
+        }
+        __syncthreads();   // the row is staged
+        const uint32_t aw = P.lwords[a];
+        double part = 0.0;
+#pragma unroll
+        for (int m = 0; m < HUBROW_P; ++m) {
+            const int p = tid + m * HUBROW_THREADS;
+            if (p >= np) continue;
+            const uint32_t wp = wpairs[p];
+            double yv[2], x0[2];
+            const double2 xx = xs2[p];
+            x0[0] = xx.x;
+            x0[1] = xx.y;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const uint32_t w = e ? (wp >> 16) : (wp & 0xffffu);
+                double d = 0.0;
+                for (int b = 0; b < n_bond; ++b) {
+                    const uint32_t msk = bm[b];
+                    if (__popc(w & msk) != 1) continue;
+                    const double v = xs[rank16(w ^ msk, rl, rh)];
+                    d += (__popc(w & bb[b]) & 1) ? -bc[b] * v : bc[b] * v;
+                }
+                double dg;
+                if (H.uniform_u) {
+                    dg = H.u0 * (double)__popc(aw & w);
+                } else {
+                    dg = 0.0;
+                    uint32_t both = aw & w;
+                    while (both) {
+                        dg += H.u[__ffs(both) - 1];
+                        both &= both - 1u;
+                    }
+                }
+                yv[e] = P.xscale * ((e ? acc[m].y : acc[m].x) + d + dg * x0[e]);
+            }
+            const int64_t gp = (int64_t)a * np + p;
+            if (P.z) {
+                const double2 zz = ((const double2 *)P.z)[gp];
+                yv[0] -= P.zcoef * zz.x;
+                yv[1] -= P.zcoef * zz.y;
+            }
+            ((double2 *)P.y)[gp] = make_double2(yv[0], yv[1]);
+            part += x0[0] * yv[0] + x0[1] * yv[1];
+        }
+        if (P.partials) {
+            const double sum = block_sum(part, red);
+            if (tid == 0) P.partials[a] = sum;
+        }
+    }
+}
+
+hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
+                         hipStream_t st) {
+    const int dR = s->blocks[0].d_r;
+    if (dR % 2 != 0 || dR > HUBROW_COLS || !prob.hub.rwords16) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_hubrow, dim3(grid), dim3(HUBROW_THREADS), (size_t)dR * 8, st, prob, rows_d, n_rows, dR);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------
 // Spin blocks of a spatial cut, both parts at most 16 sites.  One work group
 // per row tile (rows [row0, row1) of one block); the tile is staged in LDS.
@@ -492,10 +632,6 @@ __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const
 //  - diagonal: left and right diagonals plus the Jz Sz_i Sz_j cut terms.
 // Epilogue as k_rows: y = xscale H x - zcoef z, per-item partial of <x, y>.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32_t *rh) {
-    const uint32_t lo = w & 255u;
-    return rl[lo] + rh[(w >> 8) * 9u + (uint32_t)__popc(lo)];
-}
 
 // One-row item: every per-row quantity (left word, left CSR, source rows of
 // the cross terms) is uniform across the work group.
@@ -1258,6 +1394,8 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     hipError_t e = hipSuccess;
     const int b = (int)bytes;
     e = hipFuncSetAttribute((const void *)k_spin, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * SPIN_TILE * 8 + 16);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hubrow, hipFuncAttributeMaxDynamicSharedMemorySize, HUBROW_COLS * 8);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;

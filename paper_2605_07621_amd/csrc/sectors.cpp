@@ -138,6 +138,8 @@ inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
 
 static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
 static void build_spin_tables(ecut_sectors *s);
+static void make_rank_tables(ecut_sectors *s);
+static void build_hubrow_tables(ecut_sectors *s, const ecut_model_desc *m);
 void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 
@@ -454,6 +456,7 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     s->hub_rw16.clear();
     if (n <= 16)
         for (int32_t r = 0; r < B.d_r; ++r) s->hub_rw16.push_back((uint16_t)s->rwords[B.rbase + r]);
+    build_hubrow_tables(s, m);
     make_row_order(s, 0, s->row_order);
 
     // ---- class tiles of the down basis
@@ -629,19 +632,7 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     s->kernel = 1;
 }
 
-// Tables of the spin kernel.  The colex rank of a word w of up to 16 bits,
-// sum over its set bits p_0 < p_1 < ... of C(p_t, t+1), splits into a part
-// that depends only on the low byte and a part that depends on the high byte
-// and the popcount of the low byte:
-//   rank(w) = rank_lo[w & 255] + rank_hi[(w >> 8) * 9 + popc(w & 255)].
-// The tables do not depend on the sector, so one pair serves every block.
-static void build_spin_tables(ecut_sectors *s) {
-    s->spin_ok = false;
-    if (s->kind != ECUT_SPIN_HALF) return;
-    if (s->lsites.size() > 16 || s->rsites.size() > 16) return;
-    if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP) return;
-    for (const ItemDev &it : s->items)
-        if ((int64_t)(it.row1 - it.row0) * s->blocks[it.block].d_r > SPIN_TILE) return;
+static void make_rank_tables(ecut_sectors *s) {
     s->spin_rank_lo.assign(256, 0);
     s->spin_rank_hi.assign(256 * 9, 0);
     for (uint32_t lo = 0; lo < 256; ++lo) {
@@ -659,6 +650,46 @@ static void build_spin_tables(ecut_sectors *s) {
                 if ((hi >> p) & 1u) r += (int64_t)binom(8 + p, ++t);
             s->spin_rank_hi[hi * 9 + c] = (int32_t)r;
         }
+}
+
+// Tables of the whole-row Hubbard kernel: every bond with t != 0 as the
+// mask of its two sites, the mask of the sites strictly between them (the
+// fermion sign of a hop is the parity of the particles there) and -t.
+// Needs down words of at most 16 bits (byte-table ranking), an even row
+// length (16-byte column pairs) and a row that fits the work group.
+static void build_hubrow_tables(ecut_sectors *s, const ecut_model_desc *m) {
+    s->hubrow_ok = false;
+    const BlockDev &B = s->blocks[0];
+    if (s->n_sites > 16 || B.d_r % 2 != 0 || B.d_r > HUBROW_COLS || B.d_r < 2) return;
+    s->hrow_bmask.clear();
+    s->hrow_bbetw.clear();
+    s->hrow_bcoef.clear();
+    for (int b = 0; b < m->n_bonds; ++b) {
+        if (m->t[b] == 0.0) continue;
+        const int i = std::min(m->bond_i[b], m->bond_j[b]), j = std::max(m->bond_i[b], m->bond_j[b]);
+        s->hrow_bmask.push_back((1u << i) | (1u << j));
+        s->hrow_bbetw.push_back(((1u << j) - 1u) & ~((1u << (i + 1)) - 1u));
+        s->hrow_bcoef.push_back(-m->t[b]);
+    }
+    if (s->hrow_bmask.size() > (size_t)HUBROW_MAX_BOND) return;
+    make_rank_tables(s);
+    s->hubrow_ok = true;
+}
+
+// Tables of the spin kernel.  The colex rank of a word w of up to 16 bits,
+// sum over its set bits p_0 < p_1 < ... of C(p_t, t+1), splits into a part
+// that depends only on the low byte and a part that depends on the high byte
+// and the popcount of the low byte:
+//   rank(w) = rank_lo[w & 255] + rank_hi[(w >> 8) * 9 + popc(w & 255)].
+// The tables do not depend on the sector, so one pair serves every block.
+static void build_spin_tables(ecut_sectors *s) {
+    s->spin_ok = false;
+    if (s->kind != ECUT_SPIN_HALF) return;
+    if (s->lsites.size() > 16 || s->rsites.size() > 16) return;
+    if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP) return;
+    for (const ItemDev &it : s->items)
+        if ((int64_t)(it.row1 - it.row0) * s->blocks[it.block].d_r > SPIN_TILE) return;
+    make_rank_tables(s);
     s->spin_ok = true;
 }
 

@@ -68,12 +68,14 @@ void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) 
 }
 
 ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
-    if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 3)
+    if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 4)
         return fail(ECUT_EINVAL, "bad tuning");
     if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
     if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
         return fail(ECUT_EUNSUPPORTED, "class tiles not available");
     if (T.variant == 3 && s->kernel == 1 && !s->hub3_ok) return fail(ECUT_EUNSUPPORTED, "split passes not available");
+    if (T.variant == 4 && s->kernel == 1 && !s->hubrow_ok)
+        return fail(ECUT_EUNSUPPORTED, "whole-row kernel not available (more than 16 sites, odd or too long rows)");
     if (s->kernel == 1 && (T.order != s->tune.order || T.variant != s->tune.variant)) {
         make_row_order(s, row_order_kind(T.order), s->row_order);
         make_hub_item_order(s, T.order, s->hub_items_ord);
@@ -142,6 +144,8 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
             for (int order : {0, 1}) cands.push_back(ApplyTuning{0, 1, order, 3});
         for (int order : {0, 2})
             for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 1});
+        if (s->hubrow_ok)
+            for (int order : {0, 1, 2}) cands.push_back(ApplyTuning{0, 1, order, 4});
     } else {
         cands.push_back(ApplyTuning{0, 0, 0, 0});
         if (s->spin_ok) cands.push_back(ApplyTuning{0, 0, 0, 1});

@@ -70,17 +70,24 @@ _HUB_CASES = [I.hubbard12(),
               I.Problem(I.random_hubbard_model(np.random.default_rng(78), 10, n_bonds=12), I.Cut("updn"), 3, 5)]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
-@pytest.mark.parametrize("order", [0, 2, 4, 7])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("order", [0, 2, 4, 7, 9])
 def test_hubbard_kernel_variants_and_orders(dev, variant, order):
     """Every Hubbard kernel (class tiles with the uniform-chain fast path,
-    whole rows, generic class tiles) under several work orders agrees with
-    the oracle; uniform chains and random long-range couplings."""
+    whole rows in LDS, generic class tiles, two passes, whole rows with
+    16-byte access and ranked hops) under several work orders agrees with
+    the oracle; uniform chains and random long-range couplings (fermion
+    signs), even and odd row lengths."""
     for k, p in enumerate(_HUB_CASES):
         s = O.Sector(p.model, p.n_up, p.n_dn)
         psi = I.psi(500 + k, s.n)
         y_ref = s.apply(psi)
         S = _ecut().Sectors.from_problem(p)
+        if variant == 4 and not S.info.kernel_flags & 8:
+            assert math.comb(p.model.n_sites, p.n_dn) % 2 == 1
+            with pytest.raises(_ecut().EcutError):
+                S.set_tuning(0, 1, order, variant)
+            continue
         if variant == 3 and not S.info.kernel_flags & 2:
             with pytest.raises(_ecut().EcutError):
                 S.set_tuning(0, 1, order, variant)
@@ -126,6 +133,11 @@ def test_apply_full_size_sampled_vs_oracle(dev, name):
     lhs = torch.dot(pb, S.apply(xb)).item()
     rhs = torch.dot(S.apply(pb), xb).item()
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    if name == "hubbard16":
+        # the whole-row kernel at full size agrees with the default kernel
+        S.set_tuning(0, 1, 1, 4)
+        y4 = _gpu_apply_canonical(S, psi, dev)
+        assert np.linalg.norm(y4 - y) / np.linalg.norm(y) <= RTOL
 
 
 def test_apply_is_deterministic_and_batch_bit_exact(dev):
