@@ -20,10 +20,12 @@ constexpr int HUB2_NB = 8;                   // left-operator neighbour loads is
 constexpr int HUB3_M = 12;                   // element slots per thread and item in the fast kernel
 constexpr int SLAB_W = 16;                   // columns per slab of the left-operator pass (one 128-byte line)
 constexpr int SLAB_THREADS = 256;
-constexpr int SPIN_THREADS = 1024;
-constexpr int SPIN_M = 7;                    // element slots per thread of the spin kernel
+constexpr int SPIN_THREADS = 512;
+constexpr int SPIN_M = 13;                   // element slots per thread of the spin kernel
 constexpr int SPIN_TILE = SPIN_THREADS * SPIN_M;
 constexpr int SPIN_MAX_FLIP = 64;            // flip-flop terms inside the right part
+constexpr int SPIN_MANY_THREADS = 256;       // kernel for items of several short rows
+constexpr int SPIN_MANY_TILE = 512;          // amplitudes per such item (small: many groups for small problems)
 constexpr int HUBROW_THREADS = 1024;
 constexpr int HUBROW_P = 7;                  // column pairs per thread of the whole-row Hubbard kernel
 constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;

@@ -634,9 +634,12 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // ------------------------------------------------------------------------
 
 // One-row item: every per-row quantity (left word, left CSR, source rows of
-// the cross terms) is uniform across the work group.
+// the cross terms) is uniform across the work group.  One LDS buffer: it
+// first holds the source rows of the cross terms (one per left site), then
+// the item's own row for the right operator.
+template <int NT, int M>
 __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
-                                             double *xs2, const int32_t *rl, const int32_t *rh, const uint32_t *fm,
+                                             const int32_t *rl, const int32_t *rh, const uint32_t *fm,
                                              const double *fc, int n_flip, double *red) {
     const int tid = threadIdx.x;
     const int dR = B.d_r;
@@ -645,24 +648,13 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
     const uint32_t lw = P.lwords[gl];
     const double *__restrict__ xblk = P.x + B.offset;
     const double *__restrict__ xt = xblk + (int64_t)l * dR;
-    double acc[SPIN_M];
-    uint32_t wr[SPIN_M];
-    {
-        double xv[SPIN_M];
+    double acc[M];
+    uint32_t wr[M];
 #pragma unroll
-        for (int m = 0; m < SPIN_M; ++m) {
-            const int e = tid + m * SPIN_THREADS;
-            const bool ok = e < dR;
-            xv[m] = ok ? xt[e] : 0.0;
-            wr[m] = ok ? P.rwords[B.rbase + e] : 0u;
-            acc[m] = 0.0;
-        }
-        __syncthreads();   // the previous item's readers of xs / xs2 are done
-#pragma unroll
-        for (int m = 0; m < SPIN_M; ++m) {
-            const int e = tid + m * SPIN_THREADS;
-            if (e < dR) xs[e] = xv[m];
-        }
+    for (int m = 0; m < M; ++m) {
+        const int e = tid + m * NT;
+        wr[m] = e < dR ? P.rwords[B.rbase + e] : 0u;
+        acc[m] = 0.0;
     }
     // left operator: neighbour rows of the same block at the same columns
     {
@@ -670,18 +662,18 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
         for (int q = P.hl_ptr[gl]; q < q1; ++q) {
             const double c = P.hl_val[q];
             const double *__restrict__ xn = xblk + (int64_t)P.hl_col[q] * dR;
-            double v[SPIN_M];
+            double v[M];
 #pragma unroll
-            for (int m = 0; m < SPIN_M; ++m) {
-                const int e = tid + m * SPIN_THREADS;
+            for (int m = 0; m < M; ++m) {
+                const int e = tid + m * NT;
                 v[m] = e < dR ? xn[e] : 0.0;
             }
 #pragma unroll
-            for (int m = 0; m < SPIN_M; ++m) acc[m] += c * v[m];
+            for (int m = 0; m < M; ++m) acc[m] += c * v[m];
         }
     }
     // cross-cut flip-flops, grouped by left site: the source row (one per
-    // left site) is staged in xs2, then every bond of the group gathers from it
+    // left site) is staged in xs, then every bond of the group gathers from it
     const int nx = P.n_xbond;
     int k = 0;
     while (k < nx) {
@@ -694,28 +686,43 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
         if (lp >= 0) {
             const BlockDev S = P.blocks[src];
             const double *__restrict__ srow = P.x + S.offset + (int64_t)lp * S.d_r;
-            __syncthreads();   // earlier readers of xs2 are done
-            for (int e = tid; e < S.d_r; e += SPIN_THREADS) xs2[e] = srow[e];
+            __syncthreads();   // earlier readers of xs are done
+            for (int e = tid; e < S.d_r; e += NT) xs[e] = srow[e];
             __syncthreads();
             for (int kk = k; kk < k1; ++kk) {
                 const int rj = P.xbond[kk].rj;
                 const double c = P.xbond[kk].coef;
 #pragma unroll
-                for (int m = 0; m < SPIN_M; ++m) {
-                    const int e = tid + m * SPIN_THREADS;
-                    if (e < dR && ((wr[m] >> rj) & 1u) != bl) acc[m] += c * xs2[rank16(wr[m] ^ (1u << rj), rl, rh)];
+                for (int m = 0; m < M; ++m) {
+                    const int e = tid + m * NT;
+                    if (e < dR && ((wr[m] >> rj) & 1u) != bl) acc[m] += c * xs[rank16(wr[m] ^ (1u << rj), rl, rh)];
                 }
             }
         }
         k = k1;
     }
-    __syncthreads();   // xs complete
+    // the item's own row
+    {
+        double xv[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = tid + m * NT;
+            xv[m] = e < dR ? xt[e] : 0.0;
+        }
+        __syncthreads();   // readers of the last source row are done
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = tid + m * NT;
+            if (e < dR) xs[e] = xv[m];
+        }
+        __syncthreads();
+    }
     // right operator from the staged row, diagonal, epilogue
     double dgl = P.diag_l[gl];
     double part = 0.0;
 #pragma unroll
-    for (int m = 0; m < SPIN_M; ++m) {
-        const int e = tid + m * SPIN_THREADS;
+    for (int m = 0; m < M; ++m) {
+        const int e = tid + m * NT;
         if (e >= dR) continue;
         const uint32_t w = wr[m];
         double a = 0.0;
@@ -743,6 +750,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
 
 // Item of several short rows: per-element rows, cross terms gathered from
 // global memory (these blocks are small).
+template <int NT, int M>
 __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                                const int32_t *rl, const int32_t *rh, const uint32_t *fm,
                                                const double *fc, int n_flip, double *red) {
@@ -752,33 +760,35 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
     const float inv_d = 1.0f / (float)dR;
     const double *__restrict__ xblk = P.x + B.offset;
     const double *__restrict__ xt = xblk + (int64_t)W.row0 * dR;
-    double acc[SPIN_M];
-    uint32_t wr[SPIN_M];
-    int lrow[SPIN_M];   // row within the item (exact: e, dR < 2^13, so the float quotient never rounds across an integer)
+    // row of element e within the item: (e + 0.5) / dR in single precision is
+    // exact after truncation for e, dR < 2^13 (the quotient's rounding error
+    // stays below the distance to the next integer)
+    auto row_of = [&](int e) { return (int)(((float)e + 0.5f) * inv_d); };
+    double acc[M];
+    uint32_t wr[M];
     {
-        double xv[SPIN_M];
+        double xv[M];
 #pragma unroll
-        for (int m = 0; m < SPIN_M; ++m) {
-            const int e = tid + m * SPIN_THREADS;
+        for (int m = 0; m < M; ++m) {
+            const int e = tid + m * NT;
             const bool ok = e < n;
-            const int lr = (int)(((float)e + 0.5f) * inv_d);
-            lrow[m] = lr;
+            const int lr = row_of(e);
             xv[m] = ok ? xt[e] : 0.0;
             wr[m] = ok ? P.rwords[B.rbase + e - lr * dR] : 0u;
             acc[m] = 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < SPIN_M; ++m) {
-            const int e = tid + m * SPIN_THREADS;
+        for (int m = 0; m < M; ++m) {
+            const int e = tid + m * NT;
             if (e < n) xs[e] = xv[m];
         }
     }
 #pragma unroll
-    for (int m = 0; m < SPIN_M; ++m) {
-        const int e = tid + m * SPIN_THREADS;
+    for (int m = 0; m < M; ++m) {
+        const int e = tid + m * NT;
         if (e >= n) continue;
-        const int lr = lrow[m];
+        const int lr = row_of(e);
         const int r = e - lr * dR;
         const int gl = B.lbase + W.row0 + lr;
         const uint32_t lw = P.lwords[gl];
@@ -801,10 +811,10 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
     __syncthreads();
     double part = 0.0;
 #pragma unroll
-    for (int m = 0; m < SPIN_M; ++m) {
-        const int e = tid + m * SPIN_THREADS;
+    for (int m = 0; m < M; ++m) {
+        const int e = tid + m * NT;
         if (e >= n) continue;
-        const int lr = lrow[m];
+        const int lr = row_of(e);
         const int r = e - lr * dR;
         const int gl = B.lbase + W.row0 + lr;
         const uint32_t w = wr[m];
@@ -833,39 +843,43 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
     }
 }
 
-// xs: the item's tile (max_tile doubles); xs2 (one-row items): a source row
-// of the cross terms (max_src doubles, the largest d_r of the launch).
-__global__ __launch_bounds__(SPIN_THREADS, 4) void k_spin(const ProblemDev *__restrict__ probs,
-                                                          const ProblemDev single, const ItemDev *__restrict__ items,
-                                                          int n_items, int max_tile) {
+// ONE: items of one row (NT = SPIN_THREADS, M = SPIN_M; xs holds max(d_r)
+// doubles: first the cross-term source rows, then the row); otherwise items
+// of several short rows (xs holds the tile, at most SPIN_MANY_TILE).  Each
+// kernel skips the other kind of item, so both run over the same list.
+template <bool ONE>
+__global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, ONE ? 4 : 2) void k_spin(
+    const ProblemDev *__restrict__ probs, const ProblemDev single, const ItemDev *__restrict__ items, int n_items) {
+    constexpr int NT = ONE ? SPIN_THREADS : SPIN_MANY_THREADS;
+    constexpr int M = ONE ? SPIN_M : SPIN_MANY_TILE / SPIN_MANY_THREADS;
     extern __shared__ __align__(16) double xs[];
-    __shared__ double red[SPIN_THREADS / 64];
+    __shared__ double red[NT / 64];
     __shared__ int32_t rl[256];
     __shared__ int32_t rh[256 * 9];
     __shared__ uint32_t fm[SPIN_MAX_FLIP];
     __shared__ double fc[SPIN_MAX_FLIP];
     const int tid = threadIdx.x;
-    double *xs2 = xs + ((max_tile + 1) & ~1);
-    for (int i = tid; i < 256; i += SPIN_THREADS) rl[i] = single.rank_lo[i];
-    for (int i = tid; i < 256 * 9; i += SPIN_THREADS) rh[i] = single.rank_hi[i];
+    for (int i = tid; i < 256; i += NT) rl[i] = single.rank_lo[i];
+    for (int i = tid; i < 256 * 9; i += NT) rh[i] = single.rank_hi[i];
     int loaded = -1;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const ItemDev W = items[it];
+        if ((W.row1 - W.row0 == 1) != ONE) continue;
         const ProblemDev &P = probs ? probs[W.prob] : single;
         const int n_flip = P.n_rflip;
         if (W.prob != loaded) {
             __syncthreads();
-            for (int i = tid; i < n_flip; i += SPIN_THREADS) {
+            for (int i = tid; i < n_flip; i += NT) {
                 fm[i] = P.rflip_mask[i];
                 fc[i] = P.rflip_coef[i];
             }
             loaded = W.prob;
         }
         const BlockDev B = P.blocks[W.block];
-        if (W.row1 - W.row0 == 1)
-            spin_one_row(P, B, W, xs, xs2, rl, rh, fm, fc, n_flip, red);
+        if (ONE)
+            spin_one_row<NT, M>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
         else
-            spin_many_rows(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
+            spin_many_rows<NT, M>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
     }
 }
 
@@ -1364,10 +1378,13 @@ hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, cons
                        int max_tile_elems, int max_src, hipStream_t st) {
     if (n_items <= 0) return hipSuccess;
     if (max_tile_elems > SPIN_TILE || max_src > SPIN_TILE) return hipErrorInvalidValue;
-    const int grid = n_items < 65536 ? n_items : 65536;
-    const int tile = std::max(max_tile_elems, 1);
-    const size_t lds = ((size_t)((tile + 1) & ~1) + (size_t)std::max(max_src, 1)) * 8;
-    hipLaunchKernelGGL(k_spin, dim3(grid), dim3(SPIN_THREADS), lds, st, probs_d, single, items_d, n_items, tile);
+    const int grid = n_items < 2048 ? n_items : 2048;   // persistent groups walk the list
+    // one-row items: the row and the cross-term source rows; then the items of
+    // several short rows (their tiles are at most SPIN_MANY_TILE)
+    const size_t lds1 = (size_t)std::max(std::max(max_tile_elems, max_src), 1) * 8;
+    hipLaunchKernelGGL(k_spin<true>, dim3(grid), dim3(SPIN_THREADS), lds1, st, probs_d, single, items_d, n_items);
+    const size_t lds2 = (size_t)SPIN_MANY_TILE * 8;
+    hipLaunchKernelGGL(k_spin<false>, dim3(grid), dim3(SPIN_MANY_THREADS), lds2, st, probs_d, single, items_d, n_items);
     return hipGetLastError();
 }
 
@@ -1393,7 +1410,7 @@ hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32
 hipError_t set_hub_lds_limits(size_t bytes) {
     hipError_t e = hipSuccess;
     const int b = (int)bytes;
-    e = hipFuncSetAttribute((const void *)k_spin, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * SPIN_TILE * 8 + 16);
+    e = hipFuncSetAttribute((const void *)k_spin<true>, hipFuncAttributeMaxDynamicSharedMemorySize, SPIN_TILE * 8);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hubrow, hipFuncAttributeMaxDynamicSharedMemorySize, HUBROW_COLS * 8);
     if (e != hipSuccess) return e;

@@ -687,8 +687,22 @@ static void build_spin_tables(ecut_sectors *s) {
     if (s->kind != ECUT_SPIN_HALF) return;
     if (s->lsites.size() > 16 || s->rsites.size() > 16) return;
     if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP) return;
-    for (const ItemDev &it : s->items)
-        if ((int64_t)(it.row1 - it.row0) * s->blocks[it.block].d_r > SPIN_TILE) return;
+    if (s->max_d_r > SPIN_TILE) return;
+    // work items of the spin kernel: rows of at least 1024 amplitudes alone
+    // (their cross-term source rows are staged in LDS), shorter rows packed
+    // up to 2048 amplitudes; largest first
+    s->items.clear();
+    for (int b = 0; b < (int)s->blocks.size(); ++b) {
+        const BlockDev &B = s->blocks[b];
+        const int32_t rpt =
+            B.d_r >= 1024 ? 1 : std::max<int32_t>(1, std::min<int32_t>(B.d_l, SPIN_MANY_TILE / std::max(B.d_r, 1)));
+        for (int32_t r0 = 0; r0 < B.d_l; r0 += rpt)
+            s->items.push_back(ItemDev{0, b, r0, std::min(B.d_l, r0 + rpt), 0, 0});
+    }
+    std::stable_sort(s->items.begin(), s->items.end(), [&](const ItemDev &a, const ItemDev &b) {
+        return (int64_t)(a.row1 - a.row0) * s->blocks[a.block].d_r > (int64_t)(b.row1 - b.row0) * s->blocks[b.block].d_r;
+    });
+    for (size_t k = 0; k < s->items.size(); ++k) s->items[k].slot = (int32_t)k;
     make_rank_tables(s);
     s->spin_ok = true;
 }
