@@ -135,7 +135,7 @@ def kernel_name(S):
         v = t["variant"]
         if v == 0:
             return "k_hub3" if info.kernel_flags & 2 else "k_hub2"
-        return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3"}[v]
+        return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3", 4: "k_hubrow"}[v]
     return "k_spin" if (info.kernel_flags & 4 and t["variant"] == 0) else "k_rows"
 
 
@@ -237,19 +237,23 @@ def summarize_profiles(workload, kernel, copy_bytes, trace_dir, fetch_dir, write
     out = {"kernel": kernel, "workload": workload, "kernel_hash": kernel_source_hash(), "copy_bytes": copy_bytes,
            "commands": commands}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
-        ks, cs = [], []
+        # an apply may be several launches (e.g. k_spin<true> + k_spin<false>):
+        # sum every launch of the kernel family, divide by the number of applies
+        per_name, cs = {}, []
         for r in _csv_rows(d):
             if r.get("Counter_Name") != name:
                 continue
             kn = r["Kernel_Name"]
             v = float(r["Counter_Value"]) * 1024.0
-            if f"ecut::{kernel}" in kn:
-                ks.append(v)
+            if any(f"ecut::{k}" in kn for k in kernel.split("+")):
+                per_name.setdefault(kn, []).append(v)
             elif "copyBuffer" in kn:
                 cs.append(v)
+        n_apply = max((len(v) for v in per_name.values()), default=0)
         big = [c for c in cs if c > 0.25 * copy_bytes / 2]
         scale = copy_bytes / statistics.mean(big) if big else None
-        out[name] = {"kernel_raw_bytes_per_launch": statistics.mean(ks) if ks else None,
+        out[name] = {"kernel_raw_bytes_per_launch": sum(sum(v) for v in per_name.values()) / n_apply if n_apply else None,
+                     "launches": {k: len(v) for k, v in per_name.items()},
                      "copy_raw_bytes": statistics.mean(big) if big else None, "scale": scale}
     f_, w_ = out["FETCH_SIZE"], out["WRITE_SIZE"]
     if f_["kernel_raw_bytes_per_launch"] and f_["scale"] and w_["kernel_raw_bytes_per_launch"] and w_["scale"]:

@@ -130,3 +130,18 @@ def test_error_paths():
     S = E.Sectors(m, I.Cut("spatial", 0b111), 3, host_only=True)
     st = E.lib().ecut_apply_H(S.h, None, None, None)
     assert st == E.ECUT_EINVAL
+
+
+def test_bench_names_every_kernel_variant():
+    # the benchmark names the kernel of every tuning the autotuner may choose
+    import bench
+    S3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)
+    names = set()
+    for v in range(5):
+        S3.set_tuning(0, 1, 0, v)
+        names.add(bench.kernel_name(S3))
+    assert names == {"k_hub3", "k_hub", "k_hub2", "k_upslab+k_hub3", "k_hubrow"}
+    S4 = E.Sectors.from_problem(I.j1j2_6x5(), host_only=True)
+    for v, want in ((0, "k_spin"), (1, "k_rows")):
+        S4.set_tuning(0, 0, 0, v)
+        assert bench.kernel_name(S4) == want
