@@ -249,10 +249,14 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
 typedef struct ecut_lanczos_opts {
     int32_t max_steps;        /* Krylov steps per restart cycle, >= 1 */
     int32_t max_restarts;     /* explicit restarts from the current Ritz vector (needs reorth) */
-    int32_t reorth;           /* 0: three-term recurrence; 1: full reorthogonalisation (CGS2) */
+    int32_t reorth;           /* 0: three-term recurrence; 1: full reorthogonalisation (classical
+                                 Gram-Schmidt, a second pass when the first removes over half the
+                                 squared norm) */
     int32_t fixed_steps;      /* 1: run exactly max_steps (no convergence test) */
-    double tol;               /* stop when the Ritz residual beta_j |s_j| <= tol and the lowest
-                                 Ritz value moved by <= tol over the last step */
+    double tol;               /* energy tolerance: stop when the lowest Ritz value moved by <= tol
+                                 over the last step and its residual beta_j |s_j| <= 0.01 sqrt(tol)
+                                 (the energy error of a Ritz value is of the order of the squared
+                                 residual over the spectral gap) */
 } ecut_lanczos_opts;
 
 typedef struct ecut_lanczos_stats {
@@ -268,8 +272,9 @@ typedef struct ecut_lanczos_stats {
  * Lowest eigenvalue of H in this sector by Lanczos (the Krylov core the
  * paper's H*psi serves).  Per step: u = H v_j - beta_{j-1} v_{j-1} with
  * alpha_j = <v_j,u> fused into the H*psi kernel, w = u - alpha_j v_j,
- * optional CGS2 against all stored vectors, beta_j = |w|; the tridiagonal
- * eigenproblem is solved on the host by implicit QL.
+ * optional reorthogonalisation against all stored vectors, beta_j = |w|; on
+ * the host the lowest Ritz value is updated every step by Sturm bisection and
+ * the returned energy is cross-checked by implicit QL on the final matrix.
  *   v0_d:    start vector (dim), not modified; must not be zero.
  *   basis_d: caller-owned device workspace of ecut_lanczos_workspace(s, opts)
  *            doubles.

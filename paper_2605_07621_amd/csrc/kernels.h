@@ -32,7 +32,7 @@ constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;
 constexpr int HUBROW_MAX_BOND = 64;
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
-constexpr int MAX_BASIS = 1024;              // CGS2: vectors per projection call
+constexpr int MAX_BASIS = 1024;              // reorthogonalisation: vectors per projection call
 
 // One vector job of the batched Lanczos kernels.
 struct VecJob {
@@ -74,12 +74,16 @@ hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const Blo
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);
 hipError_t launch_axpy_norm(const VecJob *jobs_d, const int32_t *chunk_job_d, const int32_t *chunk_idx_d, int n_chunks,
                             hipStream_t st);
+// gate (nullable, device): when *gate == 0.0 the launch does nothing
 hipError_t launch_multidot(const double *basis, int64_t ld, int nvec, const double *y, int64_t n, double *partials,
-                           int n_chunks, hipStream_t st);
+                           int n_chunks, hipStream_t st, const double *gate = nullptr);
 hipError_t launch_multidot_reduce(const double *partials, int n_chunks, int nvec, const double *scale, double *coef,
-                                  hipStream_t st);
+                                  hipStream_t st, const double *gate = nullptr);
 hipError_t launch_multiaxpy(const double *basis, int64_t ld, int nvec, const double *coef, const double *scale,
-                            double *y, int64_t n, double *partials, int n_chunks, double sign, hipStream_t st);
+                            double *y, int64_t n, double *partials, int n_chunks, double sign, hipStream_t st,
+                            const double *gate = nullptr);
+// scal[4] = 1 if scal[3] < scal[2] / 2 else 0 (second reorthogonalisation pass needed)
+hipError_t launch_dgks_gate(double *scal, hipStream_t st);
 hipError_t launch_scale_copy(const double *x, double *y, int64_t n, double a, hipStream_t st);
 hipError_t launch_fill_normal(double *y, int64_t n, uint64_t seed, hipStream_t st);
 

@@ -1267,9 +1267,13 @@ __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restr
 }
 
 // Classical Gram-Schmidt, dot phase: partials[k * n_chunks + chunk] = <w_k, y> over the chunk.
+// gate (nullable): when it points to 0.0 the kernel does nothing (the
+// conditional second pass of the reorthogonalisation)
 __global__ __launch_bounds__(VEC_THREADS) void k_multidot(const double *__restrict__ basis, int64_t ld, int nvec,
                                                           const double *__restrict__ y, int64_t n,
-                                                          double *__restrict__ partials, int n_chunks) {
+                                                          double *__restrict__ partials, int n_chunks,
+                                                          const double *__restrict__ gate) {
+    if (gate && *gate == 0.0) return;
     __shared__ double red[VEC_THREADS / 64];
     for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const int64_t i0 = (int64_t)c * VEC_CHUNK;
@@ -1297,7 +1301,9 @@ __global__ __launch_bounds__(VEC_THREADS) void k_multidot(const double *__restri
 
 // coef[k] = scale_k * sum_chunks partials[k][*]  (fixed order)
 __global__ __launch_bounds__(VEC_THREADS) void k_multidot_reduce(const double *__restrict__ partials, int n_chunks,
-                                                                 const double *__restrict__ scale, double *__restrict__ coef) {
+                                                                 const double *__restrict__ scale, double *__restrict__ coef,
+                                                                 const double *__restrict__ gate) {
+    if (gate && *gate == 0.0) return;
     __shared__ double red[VEC_THREADS / 64];
     const int k = blockIdx.x;
     double s = 0.0;
@@ -1310,7 +1316,8 @@ __global__ __launch_bounds__(VEC_THREADS) void k_multidot_reduce(const double *_
 __global__ __launch_bounds__(VEC_THREADS) void k_multiaxpy(const double *__restrict__ basis, int64_t ld, int nvec,
                                                            const double *__restrict__ coef, const double *__restrict__ scale,
                                                            double *__restrict__ y, int64_t n, double *__restrict__ partials,
-                                                           int n_chunks, double sign) {
+                                                           int n_chunks, double sign, const double *__restrict__ gate) {
+    if (gate && *gate == 0.0) return;
     __shared__ double red[VEC_THREADS / 64];
     __shared__ double cs[MAX_BASIS];
     for (int k = threadIdx.x; k < nvec; k += blockDim.x) cs[k] = coef[k] * scale[k];
@@ -1331,6 +1338,19 @@ __global__ __launch_bounds__(VEC_THREADS) void k_multiaxpy(const double *__restr
             if (threadIdx.x == 0) partials[c] = s;
         }
     }
+}
+
+// Second-pass test of the reorthogonalisation (Daniel, Gragg, Kaufman and
+// Stewart, 1976): project again only when the first projection removed more
+// than half of the squared norm, ||w'||^2 < ||w||^2 / 2.
+// s[2] = ||w||^2 before, s[3] = ||w'||^2 after the first pass; s[4] = gate.
+__global__ void k_dgks_gate(double *s) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) s[4] = (s[3] < 0.5 * s[2]) ? 1.0 : 0.0;
+}
+
+hipError_t launch_dgks_gate(double *scal, hipStream_t st) {
+    hipLaunchKernelGGL(k_dgks_gate, dim3(1), dim3(64), 0, st, scal);
+    return hipGetLastError();
 }
 
 // y <- a * x (a from scalars[idx] or host value when scalars == NULL)
@@ -1466,23 +1486,25 @@ hipError_t launch_axpy_norm(const VecJob *jobs_d, const int32_t *chunk_job_d, co
 }
 
 hipError_t launch_multidot(const double *basis, int64_t ld, int nvec, const double *y, int64_t n, double *partials,
-                           int n_chunks, hipStream_t st) {
+                           int n_chunks, hipStream_t st, const double *gate) {
     int grid = n_chunks < 8192 ? n_chunks : 8192;
-    hipLaunchKernelGGL(k_multidot, dim3(grid), dim3(VEC_THREADS), 0, st, basis, ld, nvec, y, n, partials, n_chunks);
+    hipLaunchKernelGGL(k_multidot, dim3(grid), dim3(VEC_THREADS), 0, st, basis, ld, nvec, y, n, partials, n_chunks,
+                       gate);
     return hipGetLastError();
 }
 
 hipError_t launch_multidot_reduce(const double *partials, int n_chunks, int nvec, const double *scale, double *coef,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(VEC_THREADS), 0, st, partials, n_chunks, scale, coef);
+                                  hipStream_t st, const double *gate) {
+    hipLaunchKernelGGL(k_multidot_reduce, dim3(nvec), dim3(VEC_THREADS), 0, st, partials, n_chunks, scale, coef, gate);
     return hipGetLastError();
 }
 
 hipError_t launch_multiaxpy(const double *basis, int64_t ld, int nvec, const double *coef, const double *scale,
-                            double *y, int64_t n, double *partials, int n_chunks, double sign, hipStream_t st) {
+                            double *y, int64_t n, double *partials, int n_chunks, double sign, hipStream_t st,
+                            const double *gate) {
     int grid = n_chunks < 8192 ? n_chunks : 8192;
     hipLaunchKernelGGL(k_multiaxpy, dim3(grid), dim3(VEC_THREADS), 0, st, basis, ld, nvec, coef, scale, y, n, partials,
-                       n_chunks, sign);
+                       n_chunks, sign, gate);
     return hipGetLastError();
 }
 

@@ -1,11 +1,14 @@
 // Lanczos ground-state solver on the device (Paige's ordering):
 //   u = H v_j - beta_{j-1} v_{j-1}, alpha_j = <v_j, u>   (fused into H*psi)
 //   w = u - alpha_j v_j, beta_j = |w|                    (one fused pass)
-//   optional CGS2 against all stored vectors
+//   optional classical Gram-Schmidt against all stored vectors, with a
+//   second pass when the first loses more than half the squared norm
 // Vectors are kept unnormalised (v_j = s_j w_j) so no scaling pass is needed;
-// the scales enter the next H*psi and the updates as factors.  The tridiagonal
-// eigenproblem is solved on the host every step (implicit QL + inverse
-// iteration) for the lowest Ritz value and its residual beta_j |u_j|.
+// the scales enter the next H*psi and the updates as factors.  On the host,
+// every step takes the lowest Ritz value of the tridiagonal matrix by Sturm
+// bisection from the previous one (O(m)) and its eigenvector by inverse
+// iteration for the residual beta_j |u_j|; implicit QL on the final matrix
+// cross-checks the energy.
 #include "lanczos.h"
 
 #include <algorithm>
@@ -274,9 +277,22 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
     }
     Pack P;
     const size_t o_ja = P.put(ja), o_jx = P.put(jx), o_jb = P.put(jb), o_cj = P.put(cj), o_ci = P.put(ci);
-    size_t o_sc = 0;
+    size_t o_sc = 0, o_n0 = 0, o_n1 = 0;
     LzSolve *R = (act.size() == 1 && act[0]->reorth) ? act[0] : nullptr;
-    if (R) o_sc = P.put(R->sc);
+    if (R) {
+        o_sc = P.put(R->sc);
+        // squared norm of w before (scal[2]) and after (scal[3]) the first projection
+        std::vector<VecJob> n0(1), n1(1);
+        n0[0].partials = R->part_norm;
+        n0[0].n_partials = R->n_chunks;
+        n0[0].mode = 1;
+        n0[0].scalars = R->scal;
+        n0[0].out = 2;
+        n1[0] = n0[0];
+        n1[0].out = 3;
+        o_n0 = P.put(n0);
+        o_n1 = P.put(n1);
+    }
     ecut_status rs = stg.reserve(P.buf.size());
     if (rs != ECUT_OK) return rs;
     rs = stg.wait();
@@ -291,18 +307,27 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
                              (int)cj.size(), st);
     if (e != hipSuccess) return hip_fail(e, "lanczos update");
     if (R) {
-        // CGS2 against w_0..w_j (v_k = s_k w_k)
+        // classical Gram-Schmidt against w_0..w_j (v_k = s_k w_k); the second
+        // pass runs only when the first one removed more than half of the
+        // squared norm (decided on the device).  Every pass leaves the norm
+        // partials of its result in part_norm, so beta^2 below is the norm of
+        // the vector actually kept.
         const int nv = R->j + 1;
         if (nv > MAX_BASIS) return fail(ECUT_EUNSUPPORTED, "too many basis vectors");
         e = hipMemcpyAsync(R->dscale, d + o_sc, sizeof(double) * R->sc.size(), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = launch_reduce((const VecJob *)(d + o_n0), 1, st);
+        const double *gate = R->scal + 4;
         for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
-            e = launch_multidot(R->basis, basis_ld(*R), nv, yvec(*R), R->n, R->part_cgs, R->n_chunks, st);
-            if (e == hipSuccess) e = launch_multidot_reduce(R->part_cgs, R->n_chunks, nv, R->dscale, R->dcoef, st);
+            const double *g = pass == 1 ? gate : nullptr;
+            e = launch_multidot(R->basis, basis_ld(*R), nv, yvec(*R), R->n, R->part_cgs, R->n_chunks, st, g);
+            if (e == hipSuccess) e = launch_multidot_reduce(R->part_cgs, R->n_chunks, nv, R->dscale, R->dcoef, st, g);
             if (e == hipSuccess)
-                e = launch_multiaxpy(R->basis, basis_ld(*R), nv, R->dcoef, R->dscale, yvec(*R), R->n,
-                                     pass == 1 ? R->part_norm : nullptr, R->n_chunks, 1.0, st);
+                e = launch_multiaxpy(R->basis, basis_ld(*R), nv, R->dcoef, R->dscale, yvec(*R), R->n, R->part_norm,
+                                     R->n_chunks, 1.0, st, g);
+            if (e == hipSuccess && pass == 0) e = launch_reduce((const VecJob *)(d + o_n1), 1, st);
+            if (e == hipSuccess && pass == 0) e = launch_dgks_gate(R->scal, st);
         }
-        if (e != hipSuccess) return hip_fail(e, "CGS2");
+        if (e != hipSuccess) return hip_fail(e, "reorthogonalisation");
     }
     e = launch_reduce((const VecJob *)(d + o_jb), (int)jb.size(), st);
     if (e != hipSuccess) return hip_fail(e, "lanczos beta");
