@@ -68,7 +68,7 @@ hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, in
 int hub_blocks_per_cu(int which, size_t lds);
 // whole-row Hubbard kernel: rows_d lists the rows in processing order
 hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
-                         hipStream_t st);
+                         int n_xcd, hipStream_t st);
 hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
                        double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);

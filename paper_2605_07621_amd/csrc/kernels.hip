@@ -495,8 +495,12 @@ __device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32
 //  - diagonal U_i n_i,up n_i,dn from the two words;
 //  - 16-byte stores of y = xscale H x - zcoef z, one partial <x, y> per row.
 // ------------------------------------------------------------------------
+// n_xcd == 8: work group b runs on XCD b % 8 and walks the b % 8-th
+// contiguous chunk of the row order, so the rows in flight on one XCD are
+// neighbours in that order (their shared neighbour rows can hit its L2);
+// n_xcd == 1: plain grid stride.
 __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P, const int32_t *__restrict__ rows,
-                                                              int n_rows, int dR) {
+                                                              int n_rows, int dR, int n_xcd) {
     extern __shared__ __align__(16) double xs[];
     __shared__ int32_t rl[256];
     __shared__ int32_t rh[256 * 9];
@@ -516,7 +520,10 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
     const int np = dR >> 1;
     double2 *xs2 = (double2 *)xs;
     const uint32_t *__restrict__ wpairs = (const uint32_t *)H.rwords16;   // two 16-bit words per column pair
-    for (int k = blockIdx.x; k < n_rows; k += gridDim.x) {
+    const int xcd = blockIdx.x % n_xcd, slot = blockIdx.x / n_xcd, n_slot = gridDim.x / n_xcd;
+    const int per = (n_rows + n_xcd - 1) / n_xcd;
+    const int k_end = min(n_rows, (xcd + 1) * per);
+    for (int k = xcd * per + slot; k < k_end; k += n_slot) {
         const int a = rows[k];
         const double2 *__restrict__ xr = (const double2 *)(P.x + (int64_t)a * dR);
         double2 acc[HUBROW_P];
@@ -610,10 +617,13 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
 }
 
 hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
-                         hipStream_t st) {
+                         int n_xcd, hipStream_t st) {
     const int dR = s->blocks[0].d_r;
     if (dR % 2 != 0 || dR > HUBROW_COLS || !prob.hub.rwords16) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_hubrow, dim3(grid), dim3(HUBROW_THREADS), (size_t)dR * 8, st, prob, rows_d, n_rows, dR);
+    if (n_xcd != 8) n_xcd = 1;
+    grid = std::max(n_xcd, (grid / n_xcd) * n_xcd);
+    hipLaunchKernelGGL(k_hubrow, dim3(grid), dim3(HUBROW_THREADS), (size_t)dR * 8, st, prob, rows_d, n_rows, dR,
+                       n_xcd);
     return hipGetLastError();
 }
 

@@ -145,7 +145,8 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
         for (int order : {0, 2})
             for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 1});
         if (s->hubrow_ok)
-            for (int order : {0, 1, 2}) cands.push_back(ApplyTuning{0, 1, order, 4});
+            for (int order : {0, 1, 2, 9})
+                for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 4});
     } else {
         cands.push_back(ApplyTuning{0, 0, 0, 0});
         if (s->spin_ok) cands.push_back(ApplyTuning{0, 0, 0, 1});
