@@ -100,9 +100,9 @@ def _lat_stats(out, start):
 
 def serving_bench(n_requests, budget_gb):
     """Mixed ground-state requests (seeded XXZ and Hubbard chains, Sz=0 / half
-    filling, tol 1e-10): sequential one-at-a-time solves vs continuous batching,
-    closed loop (all at t=0) and Poisson arrivals at 0.5x and 2x the
-    sequential rate."""
+    filling, tol 1e-10): sequential one-at-a-time solves vs continuous batching
+    (every admitted request active, and at most 32 active), closed loop (all at
+    t=0) and Poisson arrivals at 0.5x and 2x the sequential rate."""
     import numpy as np
     from paper_2605_07621_amd import inputs as I
     reqs = I.serving_requests(n_requests, seed=2026)
@@ -113,19 +113,25 @@ def serving_bench(n_requests, budget_gb):
     s_seq = _lat_stats(seq, min(r["t_submit"] for r in seq))
     bat = _run_server(reqs, zeros, budget, 0, False)
     s_bat = _lat_stats(bat, min(r["t_submit"] for r in bat))
-    de = max(abs(a["energy"] - b["energy"]) for a, b in zip(seq, bat))
-    out = {"requests": len(reqs), "tol": 1e-10, "closed_loop": {"sequential": s_seq, "batched": s_bat},
+    cap = _run_server(reqs, zeros, budget, 32, False)
+    s_cap = _lat_stats(cap, min(r["t_submit"] for r in cap))
+    de = max(max(abs(a["energy"] - b["energy"]), abs(a["energy"] - c["energy"])) for a, b, c in zip(seq, bat, cap))
+    out = {"requests": len(reqs), "tol": 1e-10,
+           "closed_loop": {"sequential": s_seq, "batched": s_bat, "batched_max32": s_cap},
            "max_energy_diff_batched_vs_sequential": de,
-           "speedup_solves_per_s": round(s_bat["solves_per_s"] / s_seq["solves_per_s"], 3)}
+           "speedup_solves_per_s": round(s_bat["solves_per_s"] / s_seq["solves_per_s"], 3),
+           "speedup_solves_per_s_max32": round(s_cap["solves_per_s"] / s_seq["solves_per_s"], 3)}
     mu = s_seq["solves_per_s"]
     for rho in (0.5, 2.0):
         arr = I.poisson_arrivals(len(reqs), rho * mu)
         r_seq = _run_server(reqs, arr, budget, 1, True)
         r_bat = _run_server(reqs, arr, budget, 0, False)
+        r_cap = _run_server(reqs, arr, budget, 32, False)
         progress(f"serving: poisson rho={rho} done")
         out[f"poisson_rho{rho}"] = {"rate_per_s": round(rho * mu, 3),
                                     "sequential": _lat_stats(r_seq, min(r["t_submit"] for r in r_seq)),
-                                    "batched": _lat_stats(r_bat, min(r["t_submit"] for r in r_bat))}
+                                    "batched": _lat_stats(r_bat, min(r["t_submit"] for r in r_bat)),
+                                    "batched_max32": _lat_stats(r_cap, min(r["t_submit"] for r in r_cap))}
     return out
 
 

@@ -305,7 +305,9 @@ typedef struct ecut_server_opts {
     int32_t max_steps;        /* per request */
     double tol;               /* energy tolerance per request (as ecut_lanczos_opts.tol) */
     int32_t sequential;       /* 1: one request at a time through ecut_lanczos_ground_state (baseline) */
-    int32_t use_graph;        /* 1: replay the step as a captured HIP graph when the batch is unchanged */
+    int32_t use_graph;        /* must be 0: replaying the step as a captured HIP graph is not built
+                                 (the vectors of a solve rotate every step, so the arguments change);
+                                 1 gives ECUT_EUNSUPPORTED */
 } ecut_server_opts;
 
 typedef struct ecut_result {

@@ -271,6 +271,7 @@ ecut_status ecut_server_create(size_t hbm_budget, const ecut_server_opts *opts, 
     *out = nullptr;
     if (hbm_budget < 4096) return fail(ECUT_EINVAL, "budget too small");
     if (opts->max_steps < 2 || !(opts->tol > 0.0)) return fail(ECUT_EINVAL, "bad server options");
+    if (opts->use_graph != 0) return fail(ECUT_EUNSUPPORTED, "graph replay of the serving step is not built");
     auto *S = new (std::nothrow) ecut_server();
     if (!S) return fail(ECUT_ENOMEM, "host allocation");
     S->budget = hbm_budget;

@@ -291,8 +291,8 @@ def apply_batch(sectors, psis, ys, stream=None):
 class Server:
     """Continuous-batching ground-state server (ecut_server_*)."""
 
-    def __init__(self, hbm_budget, max_active=0, max_steps=400, tol=1e-10, sequential=False, use_graph=False):
-        o = ServerOpts(int(max_active), int(max_steps), float(tol), int(bool(sequential)), int(bool(use_graph)))
+    def __init__(self, hbm_budget, max_active=0, max_steps=400, tol=1e-10, sequential=False):
+        o = ServerOpts(int(max_active), int(max_steps), float(tol), int(bool(sequential)), 0)
         h = _vp()
         _check(lib().ecut_server_create(int(hbm_budget), ctypes.byref(o), ctypes.byref(h)))
         self.h = h

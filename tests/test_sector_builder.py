@@ -145,3 +145,13 @@ def test_bench_names_every_kernel_variant():
     for v, want in ((0, "k_spin"), (1, "k_rows")):
         S4.set_tuning(0, 0, 0, v)
         assert bench.kernel_name(S4) == want
+
+
+def test_server_rejects_graph_replay_option():
+    # graph replay of the serving step is not built: the option is refused
+    # before any device work (so this runs without a GPU)
+    import ctypes
+    o = E.ServerOpts(0, 100, 1e-10, 0, 1)
+    h = ctypes.c_void_p()
+    assert E.lib().ecut_server_create(1 << 20, ctypes.byref(o), ctypes.byref(h)) == E.ECUT_EUNSUPPORTED
+    assert not h.value
