@@ -26,7 +26,8 @@
  *   - Every call returns an ecut_status and never throws.  Argument errors
  *     are reported before any device work is queued.  A message for the last
  *     failure of the calling thread is available from ecut_last_error().
- *   - Handles are immutable after ecut_build_sectors and may be used from
+ *   - Apart from their launch tuning (ecut_set_tuning, ecut_autotune),
+ *     handles are immutable after ecut_build_sectors and may be used from
  *     several streams and threads at once for ecut_apply_H.
  */
 #ifndef ECUT_H
@@ -172,14 +173,18 @@ ecut_status ecut_export(const ecut_sectors *s, const double *bip_d, double *cano
  *            + Psi_q[l,:] H_R^T                        (right operator, in-row gather)
  *            + (d_L[l] + d_R[r] + diagonal cross terms) Psi_q[l,r]
  *            + sum_m A_m Psi_k B_m^T                    (sector-changing cross terms)
- * psi_d, y_d: dim doubles each, must not overlap.  Asynchronous on stream.
+ * psi_d, y_d: dim doubles each, must not overlap; with the whole-row
+ * Hubbard kernel (tuning variant 4) both must be 16-byte aligned (else
+ * ECUT_EINVAL).  Asynchronous on stream.
  */
 ecut_status ecut_apply_H(const ecut_sectors *s, const double *psi_d, double *y_d, void *stream);
 
 /*
- * One launch for n independent applications y_k = H_k psi_k (the sector
- * work queue over (problem, block, row tile), largest tiles first).  Each
- * output equals what ecut_apply_H gives for that problem alone, bit for bit.
+ * n independent applications y_k = H_k psi_k.  Spin and generic problems
+ * share one work queue over (problem, block, row tile), largest tiles first
+ * (one launch of the spin kernel pair and/or one of the generic row kernel);
+ * Hubbard up/down problems run their own tuned kernels.  Each output equals
+ * what ecut_apply_H gives for that problem alone, bit for bit.
  * s, psi_d, y_d: host arrays of n entries.  Uses an internal device
  * descriptor buffer that the library allocates on first use and grows;
  * the call synchronises the stream before reusing it.

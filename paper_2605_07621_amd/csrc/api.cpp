@@ -614,6 +614,8 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
         ecut_status st = check_dev(s[k]);
         if (st != ECUT_OK) return st;
         if (!psi_d[k] || !y_d[k] || psi_d[k] == y_d[k]) return fail(ECUT_EINVAL, "bad vector in batch");
+    }
+    for (int32_t k = 0; k < n; ++k) {
         probs[k] = s[k]->prob;
         probs[k].x = psi_d[k];
         probs[k].y = y_d[k];
@@ -621,9 +623,16 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
         probs[k].xscale = 1.0;
         probs[k].zcoef = 0.0;
         probs[k].partials = nullptr;
-        for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
         tiles[k] = max_tile_elems(s[k]);
+        if (s[k]->kernel == 1) {
+            // Hubbard up/down problems keep their own tuned kernels
+            ecut_status st = launch_apply(s[k], probs[k], (hipStream_t)stream);
+            if (st != ECUT_OK) return st;
+            continue;
+        }
+        for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
     }
+    if (items.empty()) return ECUT_OK;
     // one queue over all problems, largest tiles first (stable: problem order breaks ties)
     std::stable_sort(items.begin(), items.end(), [&](const ItemDev &a, const ItemDev &b) {
         const int64_t wa = (int64_t)(a.row1 - a.row0) * s[a.prob]->blocks[a.block].d_r;
