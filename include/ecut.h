@@ -329,9 +329,10 @@ typedef struct ecut_result {
 ecut_status ecut_server_create(size_t hbm_budget, const ecut_server_opts *opts, ecut_server **out);
 
 /* Queue one request.  not_before: earliest admission time on the server
- * clock (seconds since create; <= 0 = now).  v0 is a seeded N(0,1) vector in
- * canonical order drawn by the server from `seed` (splitmix64 + Box-Muller,
- * see DESIGN).  The model arrays are copied.  Thread-safe. */
+ * clock (seconds since create; <= 0 = now).  The start vector is drawn on the
+ * device directly in the bipartite layout: entry i is a Box-Muller normal from
+ * two splitmix64 values of (seed, 2i) and (seed, 2i+1), so a request gets the
+ * same vector alone or in a mix.  The model arrays are copied.  Thread-safe. */
 ecut_status ecut_server_submit(ecut_server *srv, const ecut_model_desc *model, const ecut_cut_desc *cut,
                                ecut_qnum q, uint64_t seed, double not_before, uint64_t *req_id);
 

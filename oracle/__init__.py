@@ -34,9 +34,11 @@ class _Model(ctypes.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        # ORACLE_LIB: another build of oracle.c (the planted-mistake test)
+        path = os.environ.get("ORACLE_LIB") or _build.LIB
+        if path == _build.LIB and not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        L = ctypes.CDLL(path)
         i64, i32, vp, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_sector_size.restype = i64

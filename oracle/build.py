@@ -11,15 +11,18 @@ SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp"
+def build(force: bool = True, out: str = LIB, plant: int = 0) -> str:
+    """Compile oracle.c into `out`.  plant != 0 builds the variant with one
+    deliberate mistake (ORC_PLANT, see oracle.c) for the planted-mistake test;
+    the library the tests normally load is always built with plant = 0."""
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(SRC):
+        return out
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-Wno-unused-parameter", "-o", tmp, SRC, "-lm"]
+           "-Wno-unused-parameter", f"-DORC_PLANT={int(plant)}", "-o", tmp, SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -10,7 +10,7 @@
  * What it computes (all in the full occupation basis of one symmetry sector,
  * never in the bipartite form the GPU path uses):
  *   - the sector basis: every occupation word with the requested particle
- *     numbers, in increasing integer order (Sec. "symmetry blocks", Eq. 1);
+ *     numbers, in increasing integer order (the symmetry sectors of Eq. 1);
  *   - rows of the K-local Hamiltonian of Eq. (1) for two model families:
  *       spin-1/2:  H = sum_b jxy_b (Sx_i Sx_j + Sy_i Sy_j) + jz_b Sz_i Sz_j,
  *                  S = sigma/2, site i = bit i, spin up = bit set;
@@ -29,8 +29,12 @@
  *     repeated classical Gram-Schmidt, and eigenvalues of the tridiagonal
  *     matrix by Sturm-sequence bisection.
  *
- * Parity status of every function is stated in the design doc's oracle section;
- * the pins live in tests/test_oracle_pins.py.
+ * Pins: tests/test_oracle_pins.py checks every function against what the
+ * paper and the mathematics fix (dense Kronecker-product Hamiltonians on tiny
+ * lattices, closed-form energies, brute-force enumeration, Hermiticity, the
+ * Vec/Kronecker identity of the cross term, Sturm bisection against LAPACK),
+ * and tests/test_oracle_plants.py shows those pins fail for planted mistakes
+ * (compile-time ORC_PLANT, never set in the normal build).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -55,6 +59,16 @@ typedef struct {
 } orc_model;
 
 #define ORC_MAX_ROW 1024
+
+/* ORC_PLANT selects one deliberate mistake for the test that shows the pins
+ * catch it (tests/test_oracle_plants.py builds each variant into a separate
+ * library); the normal build leaves it 0.
+ *   1: drop the on-site U term        2: drop the fermion sign of hops
+ *   3: flip amplitude jxy, not jxy/2  4: Sz Sz with the first site twice
+ *   5: only the down spins hop        6: wrong sign of the beta term in Lanczos */
+#ifndef ORC_PLANT
+#define ORC_PLANT 0
+#endif
 
 int orc_num_threads(void)
 {
@@ -184,6 +198,9 @@ static int apply_hop(uint64_t w, int L, int a, int b, uint64_t *w_out, int *sign
     uint64_t w1 = w & ~(1ull << mode_bit(L, b));
     if (mode_occupied(w1, L, a)) return 0;
     s *= (occupied_before(w1, L, a) & 1) ? -1 : 1;
+#if ORC_PLANT == 2
+    s = 1;
+#endif
     *w_out = w1 | (1ull << mode_bit(L, a));
     *sign = s;
     return 1;
@@ -199,6 +216,9 @@ static int model_row(const orc_model *m, uint64_t w, uint64_t *cw, double *cv)
         for (int b = 0; b < m->n_bonds; ++b) {
             int i = m->bi[b], j = m->bj[b];
             int ni = (int)((w >> i) & 1u), nj = (int)((w >> j) & 1u);
+#if ORC_PLANT == 4
+            nj = ni;
+#endif
             double si = ni ? 0.5 : -0.5, sj = nj ? 0.5 : -0.5;
             diag += m->jz[b] * si * sj;
             /* jxy (SxSx + SySy) = jxy/2 (S+_i S-_j + S-_i S+_j): flips an
@@ -206,18 +226,22 @@ static int model_row(const orc_model *m, uint64_t w, uint64_t *cw, double *cv)
             if (ni != nj && m->jxy[b] != 0.0) {
                 if (n >= ORC_MAX_ROW - 1) return -1;
                 cw[n] = w ^ ((1ull << i) | (1ull << j));
+#if ORC_PLANT == 3
+                cv[n] = m->jxy[b];
+#else
                 cv[n] = 0.5 * m->jxy[b];
+#endif
                 ++n;
             }
         }
     } else {
         int L = m->n_sites;
-        if (m->u)
+        if (m->u && ORC_PLANT != 1)
             for (int s = 0; s < L; ++s)
                 if (((w >> (L + s)) & 1u) && ((w >> s) & 1u)) diag += m->u[s];
         for (int b = 0; b < m->n_bonds; ++b) {
             if (m->t[b] == 0.0) continue;
-            for (int spin = 0; spin < 2; ++spin) {
+            for (int spin = ORC_PLANT == 5 ? 1 : 0; spin < 2; ++spin) {
                 int mi = spin * L + m->bi[b], mj = spin * L + m->bj[b];
                 uint64_t w2; int sg;
                 if (apply_hop(w, L, mi, mj, &w2, &sg)) {
@@ -501,7 +525,7 @@ int orc_lanczos(const orc_model *m, const uint64_t *words, int64_t n,
         if (row_ptr) orc_spmv_csr(n, row_ptr, col, val, v, u);
         else err = orc_apply_full(m, words, n, v, u);
         if (err) { steps = -3; break; }
-        for (int64_t i = 0; i < n; ++i) u[i] -= beta_prev * vp[i];
+        for (int64_t i = 0; i < n; ++i) u[i] -= (ORC_PLANT == 6 ? -beta_prev : beta_prev) * vp[i];
         double a = dot(v, u, n);
         for (int64_t i = 0; i < n; ++i) u[i] -= a * v[i];
         if (reorth) {
