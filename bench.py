@@ -179,6 +179,33 @@ def other_workloads(names, stream):
         alg = 2 * S.dim * 8 + int(S.info.device_bytes)
         out[name] = {"dim": S.dim, "blocks": int(S.info.n_blocks), "kernel": kernel_name(S), "ms": round(ms, 4),
                      "applies_per_s": round(1e3 / ms, 2), "algorithmic_GBps": round(alg / (ms * 1e-3) / 1e9, 1)}
+        steps = p.meta.get("lanczos_steps")
+        if name == "j1j2_6x5":
+            # Lanczos energy of the 6x5 lattice to 1e-10 (three-term recurrence);
+            # there is no oracle value at this size (parity unpinned)
+            v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to("cuda:0"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, st, _ = S.lanczos(v0, 600, tol=1e-10, allow_notconv=True)
+            out[name]["lanczos"] = {"steps": st["steps"], "converged": bool(st["converged"]),
+                                    "seconds": round(time.perf_counter() - t0, 3), "energy": e, "tol": 1e-10}
+            del v0
+        if steps:
+            # the configuration's fixed-step Lanczos energy (start vector: seed + 1)
+            v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to("cuda:0"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e, st, _ = S.lanczos(v0, steps, fixed_steps=True)
+            dt = time.perf_counter() - t0
+            lz = {"steps": st["steps"], "seconds": round(dt, 4), "energy": e}
+            gold = os.path.join(ROOT, "tests", "golden", f"{name}_energy.json")
+            if os.path.exists(gold):
+                with open(gold) as f:
+                    ref = json.load(f)["energy"]
+                lz["oracle_energy"] = ref
+                lz["abs_diff_vs_oracle"] = abs(e - ref)
+            out[name]["lanczos"] = lz
+            del v0
         del S, x, y
     torch.cuda.empty_cache()
     return out
