@@ -63,6 +63,34 @@ def test_apply_small_vs_oracle(dev, k):
     _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} n_up={p.n_up}")
 
 
+_WIDE = [
+    # Hubbard beyond the up/down kernels' 20-site tables: the generic row kernel
+    I.Problem(I.hubbard_chain(22, 1.0, 3.0, periodic=True), I.Cut("updn"), 2, 1),
+    I.Problem(I.random_hubbard_model(np.random.default_rng(31), 24, n_bonds=40), I.Cut("updn"), 1, 2),
+    # Hubbard with class tiles but no whole-row kernel (more than 16 sites)
+    I.Problem(I.hubbard_chain(18, 0.8, 5.0), I.Cut("updn"), 2, 3),
+    # spin models with a side wider than 16 sites (generic row kernel)
+    I.Problem(I.xxz_chain(40, 1.0, 0.7, periodic=True), I.Cut("spatial", (1 << 20) - 1), 2),
+    I.Problem(I.random_spin_model(np.random.default_rng(32), 34, n_bonds=50), I.Cut("spatial", (1 << 17) - 1), 3),
+]
+
+
+@pytest.mark.parametrize("k", range(len(_WIDE)))
+def test_apply_wide_lattices_vs_oracle(dev, k):
+    """Lattices wider than the specialised kernels take (and must agree on)
+    the generic paths; the whole-row Hubbard kernel is refused there."""
+    p = _WIDE[k]
+    s = O.Sector(p.model, p.n_up, p.n_dn)
+    psi = I.psi(800 + k, s.n)
+    y_ref = s.apply(psi)
+    S = _ecut().Sectors.from_problem(p)
+    assert not S.info.kernel_flags & (4 | 8)
+    if p.model.kind == "hubbard" and S.info.kernel == 1:
+        with pytest.raises(_ecut().EcutError):
+            S.set_tuning(0, 1, 0, 4)
+    _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} n_up={p.n_up} n_dn={p.n_dn}")
+
+
 _HUB_CASES = [I.hubbard12(),
               I.Problem(I.hubbard_chain(10, 1.0, 2.5), I.Cut("updn"), 5, 4),
               I.Problem(I.hubbard_chain(11, 0.7, 6.0), I.Cut("updn"), 6, 3),
