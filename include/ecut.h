@@ -15,7 +15,13 @@
  *     same memory), blocks by ascending q_l, contiguous, no padding.
  *     Position of (q, l, r) = offset[q] + l * d_R[q] + r, where l and r are
  *     the colex ranks (= rank in increasing integer order) of the left and
- *     right subsystem words.
+ *     right subsystem words.  Exception: when the Hubbard up/down kernels
+ *     apply (ecut_sectors_info.kernel == 1) the columns are in class-major
+ *     order -- down words sorted by the popcount of their high half (sites
+ *     n/2..n-1), then by the high half, then by the low half -- so that every
+ *     class of down words closed under all hops but the one across n/2 is a
+ *     contiguous run; ecut_sectors_words returns the down words in column
+ *     order and ecut_canonical_positions gives the map.
  *
  * Conventions shared by every entry point:
  *   - Device pointers (suffix _d) are caller-owned device memory on the
@@ -151,8 +157,9 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
 /* blocks: host int64 array of n_blocks x 5 entries (q_l, q_r, d_L, d_R, offset). */
 ecut_status ecut_sectors_blocks(const ecut_sectors *s, int64_t *blocks);
 
-/* Subsystem words of one block in rank order: l_words[d_L], r_words[d_R]
- * (host arrays; either may be NULL). */
+/* Subsystem words of one block in row and column order: l_words[d_L],
+ * r_words[d_R] (host arrays; either may be NULL).  Row and column order is
+ * the colex rank, except for the class-major columns described above. */
 ecut_status ecut_sectors_words(const ecut_sectors *s, int32_t block,
                                uint32_t *l_words, uint32_t *r_words);
 

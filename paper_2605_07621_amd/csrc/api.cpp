@@ -125,7 +125,7 @@ ecut_status upload(ecut_sectors *s) {
     const size_t o_xd = A.add(s->xdiag), o_xb = A.add(s->xbond), o_maps = A.add(s->maps);
     const size_t o_items = A.add(s->items);
     size_t o_lc = 0, o_le = 0, o_lr = 0, o_hc = 0, o_he = 0, o_seg = 0, o_xbh = 0, o_cf = 0, o_u = 0, o_rw16 = 0,
-           o_order = 0;
+           o_rw32 = 0, o_cor = 0, o_order = 0;
     if (s->hub_ok) {
         o_lc = A.add(s->hub_lo_cnt);
         o_le = A.add(s->hub_lo_ent);
@@ -137,6 +137,8 @@ ecut_status upload(ecut_sectors *s) {
         o_cf = A.add(s->hub_coef);
         o_u = A.add(s->hub_u);
         o_rw16 = A.add(s->hub_rw16);
+        o_rw32 = A.add(s->hub_rw32);
+        o_cor = A.add(s->hub_col_of_rank);
         o_order = A.add(s->row_order);
     }
     size_t o_hcc = 0, o_hsc = 0, o_hhw = 0, o_hhc = 0, o_hhe = 0, o_hlw = 0, o_hlcn = 0, o_hle = 0, o_hit = 0;
@@ -240,7 +242,8 @@ ecut_status upload(ecut_sectors *s) {
             H.rank_lo = (const int32_t *)(b + o_srl);
             H.rank_hi = (const int32_t *)(b + o_srh);
         }
-        H.rwords32 = P.rwords + s->blocks[0].rbase;
+        H.rwords32 = (const uint32_t *)(b + o_rw32);
+        H.col_of_rank = (const int32_t *)(b + o_cor);
         s->dev_row_order = (int32_t *)(b + o_order);
         H.cls = (const int32_t *)(b + o_hcc);
         H.cls_segcol = (const int32_t *)(b + o_hsc);
@@ -530,14 +533,19 @@ ecut_status ecut_sectors_words(const ecut_sectors *s, int32_t block, uint32_t *l
     if (block < 0 || block >= (int32_t)s->blocks.size()) return fail(ECUT_EINVAL, "block out of range");
     const BlockDev &B = s->blocks[block];
     if (l_words) std::memcpy(l_words, s->lwords.data() + B.lbase, sizeof(uint32_t) * (size_t)B.d_l);
-    if (r_words) std::memcpy(r_words, s->rwords.data() + B.rbase, sizeof(uint32_t) * (size_t)B.d_r);
+    if (r_words) {
+        if (s->hub_ok) std::memcpy(r_words, s->hub_rw32.data(), sizeof(uint32_t) * (size_t)B.d_r);   // column order
+        else std::memcpy(r_words, s->rwords.data() + B.rbase, sizeof(uint32_t) * (size_t)B.d_r);
+    }
     return ECUT_OK;
 }
 
 ecut_status ecut_canonical_positions(const ecut_sectors *s, int64_t *pos) {
     if (!s || !pos) return fail(ECUT_EINVAL, "null argument");
     if (s->kind == ECUT_HUBBARD) {
-        for (int64_t i = 0; i < s->dim; ++i) pos[i] = i;
+        // canonical index = up rank * d_R + down rank (up-major integer order)
+        const int64_t dR = s->blocks[0].d_r;
+        for (int64_t i = 0; i < s->dim; ++i) pos[i] = (i / dR) * dR + hub_column(s, i % dR);
         return ECUT_OK;
     }
     const int qmin = s->blocks[0].q_l;
@@ -568,7 +576,9 @@ static ecut_status permute(const ecut_sectors *s, const double *in, double *out,
     if (in == out) return fail(ECUT_EINVAL, "in and out must differ");
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e;
-    if (s->kind == ECUT_HUBBARD) {
+    if (s->kind == ECUT_HUBBARD && s->hub_ok) {
+        e = launch_perm_cols(s->prob.hub.col_of_rank, s->blocks[0].d_l, s->blocks[0].d_r, in, out, to_bip, hs);
+    } else if (s->kind == ECUT_HUBBARD) {
         e = hipMemcpyAsync(out, in, sizeof(double) * (size_t)s->dim, hipMemcpyDeviceToDevice, hs);
     } else {
         const uint64_t *bt = nullptr;

@@ -81,8 +81,9 @@ struct HubDev {
     const int32_t *xb;           // [n_xb][4]: lo bit, hi bit (relative to h), coef_idx, pad
     const double *coef;          // [n_coef] hop values (-t_b)
     const double *u;             // [n_sites] U_i
-    const uint16_t *rwords16;    // [d_r] down words (n_r <= 16) or NULL
-    const uint32_t *rwords32;    // [d_r] down words
+    const uint16_t *rwords16;    // [d_r] down word of each column (n_r <= 16) or NULL
+    const uint32_t *rwords32;    // [d_r] down word of each column
+    const int32_t *col_of_rank;  // [d_r] column of the down word of canonical rank r
     // whole-row kernel: down-spin hops by ranking the hopped word
     int32_t n_dbond;             // bonds with t != 0
     int32_t dbond_pad_;
@@ -224,7 +225,9 @@ struct ecut_sectors {
     ecut::HubDev hub{};
     std::vector<int32_t> hub_lo_cnt, hub_lo_ent, hub_lo_rank, hub_hi_cnt, hub_hi_ent, hub_seg_off, hub_xb;
     std::vector<double> hub_coef, hub_u;
-    std::vector<uint16_t> hub_rw16;
+    std::vector<uint16_t> hub_rw16;          // down word of each column (n <= 16)
+    std::vector<uint32_t> hub_rw32;          // down word of each column
+    std::vector<int32_t> hub_col_of_rank;    // column of the down word of canonical (colex) rank r
     std::vector<int32_t> hc_cls, hc_segcol, hc_hiw, hc_hicnt, hc_hient, hc_low, hc_locnt, hc_loent;
     std::vector<ecut::HubItem> hub_items;         // class-tile items, slot order
     std::vector<ecut::HubItem> hub_items_ord;     // class-tile items, processing order
@@ -262,5 +265,6 @@ void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out)
 // row order used by work order `order` (0..10) of the Hubbard kernels
 inline int row_order_kind(int order) { return order >= 9 ? 3 : order % 3; }
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
+int32_t hub_column(const ecut_sectors *s, int64_t r);
 void release_device(ecut_sectors *s);
 }  // namespace ecut

@@ -69,6 +69,9 @@ int hub_blocks_per_cu(int which, size_t lds);
 // whole-row Hubbard kernel: rows_d lists the rows in processing order
 hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
                          int n_xcd, hipStream_t st);
+// Hubbard block whose columns are a permutation of the canonical down ranks
+hipError_t launch_perm_cols(const int32_t *col_d, int64_t n_rows, int dR, const double *in, double *out, bool to_bip,
+                            hipStream_t st);
 hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
                        double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);

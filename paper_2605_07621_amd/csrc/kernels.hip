@@ -490,8 +490,9 @@ __device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32
 //  - up-spin hops: the neighbour rows of the left CSR (wave-uniform), read
 //    at the same column pairs, two rows in flight per thread;
 //  - down-spin hops: for every bond whose two sites hold one particle, the
-//    hopped word is ranked with the colex byte tables and its amplitude read
-//    from the staged row; sign (-1)^(particles strictly between the sites);
+//    hopped word is ranked with the colex byte tables, the rank mapped to its
+//    column (class-major order, table in LDS) and the amplitude read from the
+//    staged row; sign (-1)^(particles strictly between the sites);
 //  - diagonal U_i n_i,up n_i,dn from the two words;
 //  - 16-byte stores of y = xscale H x - zcoef z, one partial <x, y> per row.
 // ------------------------------------------------------------------------
@@ -519,6 +520,8 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
     }
     const int np = dR >> 1;
     double2 *xs2 = (double2 *)xs;
+    uint16_t *colmap = (uint16_t *)(xs + dR);   // column of each canonical down rank
+    for (int i = tid; i < dR; i += HUBROW_THREADS) colmap[i] = (uint16_t)H.col_of_rank[i];
     const uint32_t *__restrict__ wpairs = (const uint32_t *)H.rwords16;   // two 16-bit words per column pair
     const int xcd = blockIdx.x % n_xcd, slot = blockIdx.x / n_xcd, n_slot = gridDim.x / n_xcd;
     const int per = (n_rows + n_xcd - 1) / n_xcd;
@@ -584,7 +587,7 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
                 for (int b = 0; b < n_bond; ++b) {
                     const uint32_t msk = bm[b];
                     if (__popc(w & msk) != 1) continue;
-                    const double v = xs[rank16(w ^ msk, rl, rh)];
+                    const double v = xs[colmap[rank16(w ^ msk, rl, rh)]];
                     d += (__popc(w & bb[b]) & 1) ? -bc[b] * v : bc[b] * v;
                 }
                 double dg;
@@ -619,11 +622,12 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
 hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
                          int n_xcd, hipStream_t st) {
     const int dR = s->blocks[0].d_r;
-    if (dR % 2 != 0 || dR > HUBROW_COLS || !prob.hub.rwords16) return hipErrorInvalidValue;
+    if (dR % 2 != 0 || dR > HUBROW_COLS || !prob.hub.rwords16 || !prob.hub.col_of_rank) return hipErrorInvalidValue;
     if (n_xcd != 8) n_xcd = 1;
     grid = std::max(n_xcd, (grid / n_xcd) * n_xcd);
-    hipLaunchKernelGGL(k_hubrow, dim3(grid), dim3(HUBROW_THREADS), (size_t)dR * 8, st, prob, rows_d, n_rows, dR,
-                       n_xcd);
+    // the staged row, then the 16-bit rank -> column table
+    const size_t lds = (size_t)dR * 8 + (size_t)dR * 2;
+    hipLaunchKernelGGL(k_hubrow, dim3(grid), dim3(HUBROW_THREADS), lds, st, prob, rows_d, n_rows, dR, n_xcd);
     return hipGetLastError();
 }
 
@@ -1236,6 +1240,29 @@ __global__ void k_export(PermDev D, const double *__restrict__ bip, double *__re
         canon[i] = bip[d_canon_to_pos(D, i)];
 }
 
+// Hubbard block with permuted columns: canonical index i = a * dR + r (up
+// rank a, down rank r) sits at a * dR + col[r].
+__global__ void k_perm_cols(const int32_t *__restrict__ col, int64_t n_rows, int dR, const double *__restrict__ in,
+                            double *__restrict__ out, int to_bip) {
+    const int64_t n = n_rows * dR;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = i / dR;
+        const int64_t p = a * dR + col[i - a * dR];
+        if (to_bip) out[p] = in[i];
+        else out[i] = in[p];
+    }
+}
+
+hipError_t launch_perm_cols(const int32_t *col_d, int64_t n_rows, int dR, const double *in, double *out, bool to_bip,
+                            hipStream_t st) {
+    const int64_t n = n_rows * dR;
+    int grid = (int)((n + 255) / 256);
+    if (grid > 65536) grid = 65536;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_perm_cols, dim3(grid), dim3(256), 0, st, col_d, n_rows, dR, in, out, to_bip ? 1 : 0);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------
 // Lanczos vector kernels.  A "segment set" describes one vector per problem
 // for batched launches: seg k covers [0, n_k) of vectors x_k, y_k.
@@ -1442,7 +1469,7 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     const int b = (int)bytes;
     e = hipFuncSetAttribute((const void *)k_spin<true>, hipFuncAttributeMaxDynamicSharedMemorySize, SPIN_TILE * 8);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hubrow, hipFuncAttributeMaxDynamicSharedMemorySize, HUBROW_COLS * 8);
+    e = hipFuncSetAttribute((const void *)k_hubrow, hipFuncAttributeMaxDynamicSharedMemorySize, HUBROW_COLS * 10);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;

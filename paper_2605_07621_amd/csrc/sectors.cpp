@@ -380,13 +380,18 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     std::vector<int32_t> lo_rank(nlo), seg_off(nhi, -1);
     for (int v = 0; v < nlo; ++v) lo_rank[v] = (int32_t)ecut::colex_rank((uint64_t)v);
     {
+        // class-major column order: segments grouped by popc(hi), then by hi;
+        // every class (all segments of one popc(hi)) is one contiguous run of
+        // columns, so a class tile of a row is contiguous memory
         int32_t acc = 0;
-        for (int u = 0; u < nhi; ++u) {
-            int k = c - __builtin_popcount(u);
-            if (k < 0 || k > h) continue;
-            seg_off[u] = acc;
-            acc += (int32_t)ecut::binom(h, k);
-        }
+        for (int kh = 0; kh <= n - h; ++kh)
+            for (int u = 0; u < nhi; ++u) {
+                if (__builtin_popcount(u) != kh) continue;
+                int k = c - kh;
+                if (k < 0 || k > h) continue;
+                seg_off[u] = acc;
+                acc += (int32_t)ecut::binom(h, k);
+            }
         if (acc != B.d_r) return;   // cannot happen; keeps the kernel honest
     }
     auto pack = [](int32_t delta, int neg, int ci) { return (int32_t)(((uint32_t)delta << 9) | (uint32_t)(neg << 8) | (uint32_t)ci); };
@@ -453,9 +458,18 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     H.u0 = s->hub_u[0];
     for (int i = 1; i < n; ++i)
         if (s->hub_u[i] != H.u0) H.uniform_u = 0;
+    // canonical (colex) rank of a down word -> its column; down words by column
+    s->hub_col_of_rank.assign(B.d_r, 0);
+    s->hub_rw32.assign(B.d_r, 0);
     s->hub_rw16.clear();
-    if (n <= 16)
-        for (int32_t r = 0; r < B.d_r; ++r) s->hub_rw16.push_back((uint16_t)s->rwords[B.rbase + r]);
+    if (n <= 16) s->hub_rw16.assign(B.d_r, 0);
+    for (int32_t r = 0; r < B.d_r; ++r) {
+        const uint32_t w = s->rwords[B.rbase + r];
+        const int32_t col = seg_off[w >> h] + lo_rank[w & ((1u << h) - 1u)];
+        s->hub_col_of_rank[r] = col;
+        s->hub_rw32[col] = w;
+        if (n <= 16) s->hub_rw16[col] = (uint16_t)w;
+    }
     build_hubrow_tables(s, m);
     make_row_order(s, 0, s->row_order);
 
@@ -630,6 +644,12 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     }
     s->hub_ok = true;
     s->kernel = 1;
+}
+
+// Column of the down word of canonical rank r in the block (identity unless
+// the Hubbard up/down kernels, which use the class-major column order, apply).
+int32_t hub_column(const ecut_sectors *s, int64_t r) {
+    return s->hub_ok ? s->hub_col_of_rank[(size_t)r] : (int32_t)r;
 }
 
 static void make_rank_tables(ecut_sectors *s) {

@@ -48,6 +48,19 @@ CASES = [
 ]
 
 
+def _class_major(words, n_sites):
+    """Column order of the down words under the Hubbard up/down kernels:
+    by popcount of the high half (sites n/2..n-1), then the high half, then
+    the low half (the class-major order, so every class is contiguous).
+    Returns (words in column order, column of the word of canonical rank r)."""
+    h = n_sites // 2
+    w = [int(v) for v in words]
+    order = sorted(range(len(w)), key=lambda r: (bin(w[r] >> h).count("1"), w[r] >> h, w[r] & ((1 << h) - 1)))
+    col = np.empty(len(w), dtype=np.int64)
+    col[order] = np.arange(len(w))
+    return np.asarray([w[r] for r in order], dtype=np.uint64), col
+
+
 @pytest.mark.parametrize("p", CASES, ids=lambda p: f"{p.model.name}-{p.cut.kind}-{p.n_up}-{p.n_dn}")
 def test_blocks_words_positions_bit_exact(p):
     S = E.Sectors.from_problem(p, host_only=True)
@@ -59,6 +72,12 @@ def test_blocks_words_positions_bit_exact(p):
     np.testing.assert_array_equal(blocks[:, 2], oblocks[:, 1])   # d_L
     np.testing.assert_array_equal(blocks[:, 3], oblocks[:, 2])   # d_R
     np.testing.assert_array_equal(blocks[:, 4], oblocks[:, 3])   # offsets
+    class_major = p.cut.kind == "updn" and S.info.kernel == 1
+    if class_major:
+        # the oracle's positions with the down index replaced by its column
+        dR = int(blocks[0, 3])
+        _, col = _class_major(O.enumerate_bruteforce(p.model.n_sites, p.n_dn), p.model.n_sites)
+        pos = (pos // dR) * dR + col[pos % dR]
     np.testing.assert_array_equal(S.canonical_positions(), pos)
     for b in range(blocks.shape[0]):
         lw, rw = S.words(b)
@@ -68,8 +87,11 @@ def test_blocks_words_positions_bit_exact(p):
         else:
             n_left = n_right = p.model.n_sites
         ql, qr = int(blocks[b, 0]), int(blocks[b, 1])
+        want_r = O.enumerate_bruteforce(n_right, qr) if n_right else np.asarray([0], dtype=np.uint64)
+        if class_major:
+            want_r = _class_major(want_r, p.model.n_sites)[0]
         np.testing.assert_array_equal(lw.astype(np.uint64), O.enumerate_bruteforce(n_left, ql) if n_left else [0])
-        np.testing.assert_array_equal(rw.astype(np.uint64), O.enumerate_bruteforce(n_right, qr) if n_right else [0])
+        np.testing.assert_array_equal(rw.astype(np.uint64), want_r)
 
 
 def test_workload_block_structure():
