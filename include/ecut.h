@@ -232,15 +232,29 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
  *              Spin and generic problems (kernel 2) take variant 0 (the
  *              ranking-table spin kernel when kernel_flags bit 2 is set, else
  *              the generic row kernel) or 1 (the generic row kernel, which
- *              reads the right operator's CSR); other fields are ignored.
- * ecut_set_tuning re-uploads the row order (synchronous).  Not to be called
- * while an ecut_apply_H on the same handle is in flight.
+ *              reads the right operator's CSR); n_xcd and row_order are
+ *              ignored for them;
+ *   tile:      spin problems (kernel_flags bit 2) only, else it must be 0:
+ *              the work items of the sector queue are single rows for rows
+ *              longer than tile/2 amplitudes, and runs of shorter rows of at
+ *              most `tile` amplitudes otherwise (0 = 512, at most 512).
+ *              Smaller tiles give more, smaller items; the Lanczos
+ *              workspace (ecut_lanczos_workspace) holds the per-item partial
+ *              sums of the smallest tile, so it does not change with tuning.  For the spin kernel, grid is
+ *              the number of work groups that stride through the item queue
+ *              (0 = min(items, 2048)); the generic row kernel ignores it.
+ * ecut_set_tuning re-uploads the row order or the work items (synchronous).
+ * Not to be called while an ecut_apply_H on the same handle is in flight.
+ * Results of different tunings agree to rounding (the terms of an amplitude
+ * are summed in the same order by every spin tiling; the Lanczos partial sums
+ * follow the item split).
  */
 typedef struct ecut_tuning {
     int32_t grid;
     int32_t n_xcd;
     int32_t row_order;
     int32_t variant;
+    int32_t tile;
 } ecut_tuning;
 
 ecut_status ecut_get_tuning(const ecut_sectors *s, ecut_tuning *t);
@@ -248,7 +262,8 @@ ecut_status ecut_set_tuning(ecut_sectors *s, const ecut_tuning *t);
 
 /*
  * Autotuner: times ecut_apply_H(x_d -> y_d) for each candidate launch tuning
- * (grid, XCD chunking, row order) with HIP events on `stream`, keeps the
+ * (Hubbard: kernel variant, row order, XCD chunking; spin: short-row tile and
+ * grid, then the generic row kernel) with HIP events on `stream`, keeps the
  * fastest on the handle and returns it in *best (nullable).  x_d, y_d: dim
  * doubles each (contents of y_d are overwritten).  If the environment
  * variable ECUT_TUNE_CACHE names a JSON file, results are read from and

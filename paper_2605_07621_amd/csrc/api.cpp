@@ -123,7 +123,9 @@ ecut_status upload(ecut_sectors *s) {
     const size_t o_hrp = A.add(s->hr_ptr), o_hrc = A.add(s->hr_col), o_hrv = A.add(s->hr_val);
     const size_t o_dl = A.add(s->diag_l), o_dr = A.add(s->diag_r);
     const size_t o_xd = A.add(s->xdiag), o_xb = A.add(s->xbond), o_maps = A.add(s->maps);
-    const size_t o_items = A.add(s->items);
+    std::vector<ItemDev> row_items(std::max(s->items_cap, s->items.size()), ItemDev{0, 0, 0, 0, 0, 0});
+    std::copy(s->items.begin(), s->items.end(), row_items.begin());   // capacity for any tile size
+    const size_t o_items = A.add(row_items);
     size_t o_lc = 0, o_le = 0, o_lr = 0, o_hc = 0, o_he = 0, o_seg = 0, o_xbh = 0, o_cf = 0, o_u = 0, o_rw16 = 0,
            o_rw32 = 0, o_cor = 0, o_order = 0;
     if (s->hub_ok) {
@@ -334,7 +336,8 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
         }
     } else if (P.spin_ok) {
-        e = launch_spin(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), s->max_d_r, st);
+        e = launch_spin(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), s->max_d_r, s->tune.grid,
+                        st);
     } else {
         e = launch_rows(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
     }
@@ -353,7 +356,7 @@ int32_t apply_partial_slots(const ecut_sectors *s) {
 // workspace size: either Hubbard variant may run on the same workspace
 int32_t apply_partial_slots_max(const ecut_sectors *s) {
     return s->kernel == 1 ? std::max<int32_t>(s->blocks[0].d_l, (int32_t)s->hub_items.size())
-                          : (int32_t)s->items.size();
+                          : (int32_t)std::max(s->items_cap, s->items.size());
 }
 
 // ---------------------------------------------------------------- staging buffers
@@ -447,7 +450,7 @@ ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::v
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
     const ProblemDev *probs_d = (const ProblemDev *)S.dev;
     const ItemDev *items_d = (const ItemDev *)((char *)S.dev + pb);
-    if (n_spin > 0) e = launch_spin(probs_d, probs[first_spin], items_d, (int)n_spin, spin_tile, spin_src, st);
+    if (n_spin > 0) e = launch_spin(probs_d, probs[first_spin], items_d, (int)n_spin, spin_tile, spin_src, 0, st);
     if (e == hipSuccess && n_spin < items.size())
         e = launch_rows(probs_d, probs[0], items_d + n_spin, (int)(items.size() - n_spin), rows_tile, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");

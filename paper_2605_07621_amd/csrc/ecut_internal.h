@@ -183,6 +183,7 @@ struct ApplyTuning {
     int32_t n_xcd;    // XCD-contiguous work chunks (0 = 8)
     int32_t order;    // row order: 0 increasing, 1 by inversion level, 2 segment-major by level
     int32_t variant;  // Hubbard kernel: 0 class tiles, 1 whole rows
+    int32_t tile;     // spin kernel: amplitudes per item of several short rows (0 = default)
 };
 
 // Work item: rows [row0, row1) of block `block` of problem `prob`; `slot`
@@ -241,8 +242,9 @@ struct ecut_sectors {
     std::vector<int32_t> spin_rank_lo, spin_rank_hi;
     std::vector<uint32_t> spin_fmask;
     std::vector<double> spin_fcoef;
-    // default work items of a single application
+    // work items of a single application
     std::vector<ecut::ItemDev> items;
+    size_t items_cap = 0;                 // device capacity for any spin tile size
     std::vector<int32_t> row_order;       // Hubbard kernel: row processing order
     int32_t kernel = 2;
     ecut::ApplyTuning tune{};
@@ -266,5 +268,7 @@ void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out)
 inline int row_order_kind(int order) { return order >= 9 ? 3 : order % 3; }
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 int32_t hub_column(const ecut_sectors *s, int64_t r);
+// work items of the spin kernel for a short-row tile of `tile` amplitudes
+void make_spin_items(const ecut_sectors *s, int32_t tile, std::vector<ItemDev> &out);
 void release_device(ecut_sectors *s);
 }  // namespace ecut

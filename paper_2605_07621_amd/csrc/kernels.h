@@ -55,8 +55,9 @@ hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, cons
                        int max_tile_elems, hipStream_t st);
 // spin kernel with ranking tables; every problem of the launch must have
 // spin_ok.  max_src: largest d_r of any block of the launch's problems.
+// grid: work groups of each of the two launches (0 = min(n_items, 2048)).
 hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
-                       int max_tile_elems, int max_src, hipStream_t st);
+                       int max_tile_elems, int max_src, int grid, hipStream_t st);
 hipError_t launch_hub(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
                       int n_xcd, hipStream_t st);
 size_t hub2_lds_bytes(const ecut_sectors *s);

@@ -1432,10 +1432,11 @@ hipError_t launch_rows(const ProblemDev *probs_d, const ProblemDev &single, cons
 }
 
 hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, const ItemDev *items_d, int n_items,
-                       int max_tile_elems, int max_src, hipStream_t st) {
+                       int max_tile_elems, int max_src, int grid, hipStream_t st) {
     if (n_items <= 0) return hipSuccess;
     if (max_tile_elems > SPIN_TILE || max_src > SPIN_TILE) return hipErrorInvalidValue;
-    const int grid = n_items < 2048 ? n_items : 2048;   // persistent groups walk the list
+    if (grid <= 0) grid = 2048;
+    if (grid > n_items) grid = n_items;   // groups walk the list with a stride of the grid
     // one-row items: the row and the cross-term source rows; then the items of
     // several short rows (their tiles are at most SPIN_MANY_TILE)
     const size_t lds1 = (size_t)std::max(std::max(max_tile_elems, max_src), 1) * 8;

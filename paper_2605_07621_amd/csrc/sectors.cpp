@@ -337,6 +337,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
         return wa > wb;
     });
     for (size_t k = 0; k < s->items.size(); ++k) s->items[k].slot = (int32_t)k;
+    s->items_cap = s->items.size();
 
     s->hub_ok = false;
     s->kernel = 2;
@@ -708,23 +709,30 @@ static void build_spin_tables(ecut_sectors *s) {
     if (s->lsites.size() > 16 || s->rsites.size() > 16) return;
     if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP) return;
     if (s->max_d_r > SPIN_TILE) return;
-    // work items of the spin kernel: rows of at least 1024 amplitudes alone
-    // (their cross-term source rows are staged in LDS), shorter rows packed
-    // up to 2048 amplitudes; largest first
-    s->items.clear();
-    for (int b = 0; b < (int)s->blocks.size(); ++b) {
-        const BlockDev &B = s->blocks[b];
-        const int32_t rpt =
-            B.d_r >= 1024 ? 1 : std::max<int32_t>(1, std::min<int32_t>(B.d_l, SPIN_MANY_TILE / std::max(B.d_r, 1)));
-        for (int32_t r0 = 0; r0 < B.d_l; r0 += rpt)
-            s->items.push_back(ItemDev{0, b, r0, std::min(B.d_l, r0 + rpt), 0, 0});
-    }
-    std::stable_sort(s->items.begin(), s->items.end(), [&](const ItemDev &a, const ItemDev &b) {
-        return (int64_t)(a.row1 - a.row0) * s->blocks[a.block].d_r > (int64_t)(b.row1 - b.row0) * s->blocks[b.block].d_r;
-    });
-    for (size_t k = 0; k < s->items.size(); ++k) s->items[k].slot = (int32_t)k;
+    make_spin_items(s, SPIN_MANY_TILE, s->items);
+    // every item holds at least one row, so no tile size gives more items
+    // than there are rows
+    size_t rows = 0;
+    for (const BlockDev &B : s->blocks) rows += (size_t)B.d_l;
+    s->items_cap = std::max(s->items.size(), rows);
     make_rank_tables(s);
     s->spin_ok = true;
+}
+
+// Work items of the spin kernel: a row longer than half the tile is an item of
+// its own (its cross-term source rows are staged in LDS), shorter rows are
+// packed into items of at most `tile` amplitudes; largest first.
+void make_spin_items(const ecut_sectors *s, int32_t tile, std::vector<ItemDev> &out) {
+    out.clear();
+    for (int b = 0; b < (int)s->blocks.size(); ++b) {
+        const BlockDev &B = s->blocks[b];
+        const int32_t rpt = std::max<int32_t>(1, std::min<int32_t>(B.d_l, tile / std::max(B.d_r, 1)));
+        for (int32_t r0 = 0; r0 < B.d_l; r0 += rpt) out.push_back(ItemDev{0, b, r0, std::min(B.d_l, r0 + rpt), 0, 0});
+    }
+    std::stable_sort(out.begin(), out.end(), [&](const ItemDev &a, const ItemDev &b) {
+        return (int64_t)(a.row1 - a.row0) * s->blocks[a.block].d_r > (int64_t)(b.row1 - b.row0) * s->blocks[b.block].d_r;
+    });
+    for (size_t k = 0; k < out.size(); ++k) out[k].slot = (int32_t)k;
 }
 
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out) {

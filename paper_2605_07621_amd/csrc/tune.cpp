@@ -32,7 +32,8 @@ std::string shape_key(const ecut_sectors *s) {
     return k.str();
 }
 
-// The cache file is a flat JSON object {"key": [grid, n_xcd, row_order], ...}.
+// The cache file is a flat JSON object {"key": [grid, n_xcd, row_order, variant, tile], ...};
+// entries without the tile take the default tile.
 std::map<std::string, ApplyTuning> read_cache(const char *path) {
     std::map<std::string, ApplyTuning> out;
     std::ifstream f(path);
@@ -48,9 +49,9 @@ std::map<std::string, ApplyTuning> read_cache(const char *path) {
         const size_t a = t.find('[', q), b = t.find(']', q);
         if (a == std::string::npos || b == std::string::npos) break;
         ApplyTuning T{};
-        if (std::sscanf(t.substr(a + 1, b - a - 1).c_str(), "%d , %d , %d , %d", &T.grid, &T.n_xcd, &T.order,
-                        &T.variant) == 4)
-            out[key] = T;
+        const int got = std::sscanf(t.substr(a + 1, b - a - 1).c_str(), "%d , %d , %d , %d , %d", &T.grid, &T.n_xcd,
+                                    &T.order, &T.variant, &T.tile);
+        if (got == 4 || got == 5) out[key] = T;
         p = b;
     }
     return out;
@@ -62,7 +63,7 @@ void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) 
     size_t k = 0;
     for (auto &kv : m) {
         f << "  \"" << kv.first << "\": [" << kv.second.grid << ", " << kv.second.n_xcd << ", " << kv.second.order
-          << ", " << kv.second.variant << "]" << (++k < m.size() ? "," : "") << "\n";
+          << ", " << kv.second.variant << ", " << kv.second.tile << "]" << (++k < m.size() ? "," : "") << "\n";
     }
     f << "}\n";
 }
@@ -71,6 +72,8 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 4)
         return fail(ECUT_EINVAL, "bad tuning");
     if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
+    if (T.tile < 0 || T.tile > SPIN_MANY_TILE) return fail(ECUT_EINVAL, "tile must lie in 0..512");
+    if (T.tile != 0 && !s->spin_ok) return fail(ECUT_EUNSUPPORTED, "the tile size applies to the spin kernel only");
     if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
         return fail(ECUT_EUNSUPPORTED, "class tiles not available");
     if (T.variant == 3 && s->kernel == 1 && !s->hub3_ok) return fail(ECUT_EUNSUPPORTED, "split passes not available");
@@ -88,6 +91,18 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
                               hipMemcpyHostToDevice);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work order)");
         }
+    }
+    const int32_t tile = T.tile > 0 ? T.tile : SPIN_MANY_TILE, cur = s->tune.tile > 0 ? s->tune.tile : SPIN_MANY_TILE;
+    if (s->spin_ok && tile != cur) {
+        std::vector<ItemDev> items;
+        make_spin_items(s, tile, items);
+        if (items.size() > s->items_cap) return fail(ECUT_EINVAL, "work list exceeds its buffer");
+        if (s->on_device && s->dev_items) {
+            hipError_t e =
+                hipMemcpy(s->dev_items, items.data(), items.size() * sizeof(ItemDev), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work items)");
+        }
+        s->items.swap(items);
     }
     s->tune = T;
     if (s->kernel != 1) s->prob.spin_ok = (s->spin_ok && s->on_device && T.variant == 0) ? 1 : 0;
@@ -107,12 +122,13 @@ ecut_status ecut_get_tuning(const ecut_sectors *s, ecut_tuning *t) {
     t->n_xcd = s->tune.n_xcd;
     t->row_order = s->tune.order;
     t->variant = s->tune.variant;
+    t->tile = s->tune.tile;
     return ECUT_OK;
 }
 
 ecut_status ecut_set_tuning(ecut_sectors *s, const ecut_tuning *t) {
     if (!s || !t) return fail(ECUT_EINVAL, "bad argument");
-    ApplyTuning T{t->grid, t->n_xcd, t->row_order, t->variant};
+    ApplyTuning T{t->grid, t->n_xcd, t->row_order, t->variant, t->tile};
     return apply_tuning(s, T);
 }
 
@@ -147,9 +163,13 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
         if (s->hubrow_ok)
             for (int order : {0, 1, 2, 9})
                 for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 4});
+    } else if (s->spin_ok) {
+        // spin kernel: short-row tile and grid; then the generic row kernel
+        for (int tile : {128, 256, 512})
+            for (int grid : {0, 512, 1024}) cands.push_back(ApplyTuning{grid, 0, 0, 0, tile});
+        cands.push_back(ApplyTuning{0, 0, 0, 1, 0});
     } else {
-        cands.push_back(ApplyTuning{0, 0, 0, 0});
-        if (s->spin_ok) cands.push_back(ApplyTuning{0, 0, 0, 1});
+        cands.push_back(ApplyTuning{0, 0, 0, 0, 0});
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

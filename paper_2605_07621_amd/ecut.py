@@ -63,7 +63,11 @@ class LanczosStats(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("grid", _i32), ("n_xcd", _i32), ("row_order", _i32), ("variant", _i32)]
+    _fields_ = [("grid", _i32), ("n_xcd", _i32), ("row_order", _i32), ("variant", _i32), ("tile", _i32)]
+
+
+def _tuning_dict(t):
+    return dict(grid=t.grid, n_xcd=t.n_xcd, row_order=t.row_order, variant=t.variant, tile=t.tile)
 
 
 class ServerOpts(ctypes.Structure):
@@ -243,17 +247,17 @@ class Sectors:
     def get_tuning(self):
         t = Tuning()
         _check(lib().ecut_get_tuning(self.h, ctypes.byref(t)))
-        return dict(grid=t.grid, n_xcd=t.n_xcd, row_order=t.row_order, variant=t.variant)
+        return _tuning_dict(t)
 
-    def set_tuning(self, grid=0, n_xcd=0, row_order=0, variant=0):
-        t = Tuning(int(grid), int(n_xcd), int(row_order), int(variant))
+    def set_tuning(self, grid=0, n_xcd=0, row_order=0, variant=0, tile=0):
+        t = Tuning(int(grid), int(n_xcd), int(row_order), int(variant), int(tile))
         _check(lib().ecut_set_tuning(self.h, ctypes.byref(t)))
 
     def autotune(self, x, y, stream=None):
         t = Tuning()
         _check(lib().ecut_autotune(self.h, _dptr(x, self.dim, "x"), _dptr(y, self.dim, "y"), _stream(stream),
                                    ctypes.byref(t)))
-        return dict(grid=t.grid, n_xcd=t.n_xcd, row_order=t.row_order, variant=t.variant)
+        return _tuning_dict(t)
 
     def lanczos_workspace(self, max_steps, reorth=False, max_restarts=0, tol=1e-10, fixed_steps=False):
         o = LanczosOpts(int(max_steps), int(max_restarts), int(bool(reorth)), int(bool(fixed_steps)), float(tol))

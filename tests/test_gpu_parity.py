@@ -235,6 +235,53 @@ def test_spin_kernel_full_size_variants_agree(dev):
     del y0, y1, x
 
 
+_TILE_CASES = ((1, 0), (64, 7), (128, 1024), (256, 4096), (512, 1), (300, 0))
+
+
+def test_spin_tile_tunings_bit_exact(dev):
+    """Every short-row tile and grid of the spin kernel's sector queue gives
+    the same vector bit for bit (each amplitude sums its terms in the same
+    order however the rows are grouped), and it matches the oracle."""
+    import torch
+    cases = [p for p in _SPIN_CASES] + [I.heisenberg16()]
+    n_run = 0
+    for k, p in enumerate(cases):
+        S = _ecut().Sectors.from_problem(p)
+        if not S.info.kernel_flags & 4:
+            continue
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        psi = I.psi(1300 + k, s.n)
+        x = S.import_(torch.from_numpy(psi).to(dev))
+        S.set_tuning(0, 0, 0, 0, 0)
+        y0 = S.apply(x)
+        for tile, grid in _TILE_CASES:
+            S.set_tuning(grid, 0, 0, 0, tile)
+            y = S.apply(x)
+            torch.cuda.synchronize()
+            assert torch.equal(y, y0), f"{p.model.name} n_up={p.n_up} tile {tile} grid {grid}"
+        S.set_tuning(0, 0, 0, 0, 64)
+        _compare(_gpu_apply_canonical(S, psi, dev), s.apply(psi), f"{p.model.name} n_up={p.n_up} tile 64")
+        n_run += 1
+    assert n_run >= 4
+
+
+def test_spin_tile_tunings_full_size(dev):
+    """6x5 J1-J2 (155M amplitudes, 16 blocks): the tile and grid candidates of
+    the autotuner give the default tuning's vector bit for bit."""
+    import torch
+    p = I.j1j2_6x5()
+    S = _ecut().Sectors.from_problem(p)
+    x = torch.from_numpy(I.psi(p.meta["seed"] + 5, S.dim)).to(dev)
+    y0 = S.apply(x)
+    y = torch.empty_like(x)
+    for tile, grid in ((128, 1024), (256, 4096), (1, 0)):
+        S.set_tuning(grid, 0, 0, 0, tile)
+        S.apply(x, out=y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0), (tile, grid)
+    del x, y, y0
+
+
 def test_batch_mixed_kernels_bit_exact(dev):
     """A batch that mixes spin-kernel problems, generic-kernel problems and
     a spin problem tuned to the generic kernel runs each on its own kernel."""
@@ -282,6 +329,14 @@ def test_lanczos_heisenberg16_vs_oracle(dev):
     assert abs(e - e_ref) <= 1e-10
     e2, st2, _ = S.lanczos(v0, 400, tol=1e-10)
     assert abs(e2 - e_ref) <= 1e-10 and st2["converged"] == 1
+    for tile in (1, 64):
+        # more, smaller work items: the per-item partial sums of the fused
+        # Lanczos epilogue follow the split; a NaN workspace shows that every
+        # slot the solver reads is written first
+        S.set_tuning(0, 0, 0, 0, tile)
+        ws = torch.full((S.lanczos_workspace(100),), float("nan"), dtype=torch.float64, device=dev)
+        e3, st3, _ = S.lanczos(v0, 100, fixed_steps=True, workspace=ws)
+        assert st3["steps"] == 100 and abs(e3 - e_ref) <= 1e-10, (tile, e3, e_ref)
 
 
 def test_lanczos_hubbard12_vs_oracle(dev):

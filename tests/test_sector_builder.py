@@ -177,3 +177,24 @@ def test_server_rejects_graph_replay_option():
     h = ctypes.c_void_p()
     assert E.lib().ecut_server_create(1 << 20, ctypes.byref(o), ctypes.byref(h)) == E.ECUT_EUNSUPPORTED
     assert not h.value
+
+
+def test_spin_tile_tuning_host():
+    # the short-row tile of the spin kernel is a tuning field: validated, kept
+    # on the handle, and it leaves the Lanczos workspace size unchanged
+    S = E.Sectors.from_problem(I.j1j2_6x5(), host_only=True)
+    assert S.info.kernel_flags & 4
+    ws = S.lanczos_workspace(40)
+    for tile in (1, 64, 128, 256, 512, 0):
+        S.set_tuning(0, 0, 0, 0, tile)
+        assert S.get_tuning()["tile"] == tile
+        assert S.lanczos_workspace(40) == ws
+    for bad in (-1, 513, 4096):
+        assert _status(lambda: S.set_tuning(0, 0, 0, 0, bad)) == E.ECUT_EINVAL
+    assert S.get_tuning()["tile"] == 0          # a rejected tuning changes nothing
+    # problems that do not run the spin kernel take no tile
+    H = E.Sectors.from_problem(I.hubbard12(), host_only=True)
+    assert _status(lambda: H.set_tuning(0, 1, 0, 0, 128)) == E.ECUT_EUNSUPPORTED
+    G = E.Sectors.from_problem(I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", 0b111), 10), host_only=True)
+    assert not G.info.kernel_flags & 4
+    assert _status(lambda: G.set_tuning(0, 0, 0, 0, 64)) == E.ECUT_EUNSUPPORTED
