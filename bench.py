@@ -142,7 +142,7 @@ def kernel_name(S):
         v = t["variant"]
         if v == 0:
             return "k_hub3" if info.kernel_flags & 2 else "k_hub2"
-        return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3", 4: "k_hubrow"}[v]
+        return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3", 4: "k_hubrow", 5: "k_hubseg"}[v]
     return "k_spin" if (info.kernel_flags & 4 and t["variant"] == 0) else "k_rows"
 
 

@@ -128,7 +128,9 @@ typedef struct ecut_sectors_info {
                                  ranking-table kernel available (both parts <= 16 sites, row
                                  tiles <= 7168 amplitudes, <= 64 flip-flop terms in the right part);
                                  Hubbard: bit 3 the whole-row kernel available (<= 16 sites, even
-                                 row length <= 14336, <= 64 bonds) */
+                                 row length <= 14336, <= 64 bonds); bit 4 the segment-tile kernel
+                                 available (as bit 1, and every tile fits 512 threads x 10
+                                 slots and 48 KB of LDS) */
     int32_t reserved;
     int64_t device_bytes;     /* device metadata held by the handle */
     double n_eff;             /* 1 / sum_q w_q^2 with w_q = d_L d_R / dim (block-size participation number) */
@@ -228,7 +230,14 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
  *              then the right operator and diagonal on class tiles,
  *              4 whole rows with 16-byte access: the row in LDS, down-spin
  *              hops found by ranking the hopped word (any hopping graph;
- *              needs kernel_flags bit 3 and 16-byte aligned vectors).
+ *              needs kernel_flags bit 3 and 16-byte aligned vectors),
+ *              5 segment tiles: (up segment) x (down segment) tiles, where a
+ *              segment is the words sharing the high half, so hops inside
+ *              either low half are read from LDS; the tiles of one panel
+ *              (up segment x down class) run together on one XCD so the
+ *              down high-half hops find their source in L2 (needs
+ *              kernel_flags bit 4; row_order ignored; n_xcd 1 = plain grid
+ *              stride, else 8 XCD chunks).
  *              Spin and generic problems (kernel 2) take variant 0 (the
  *              ranking-table spin kernel when kernel_flags bit 2 is set, else
  *              the generic row kernel) or 1 (the generic row kernel, which

@@ -180,6 +180,14 @@ ecut_status upload(ecut_sectors *s) {
         o_3hn = A.add(s->h3_hnb);
         o_3hc = A.add(s->h3_hcnt);
     }
+    size_t o_5us = 0, o_5uh = 0, o_5ul = 0, o_5ux = 0, o_5it = 0;
+    if (s->hubseg_ok) {
+        o_5us = A.add(s->hs_useg);
+        o_5uh = A.add(s->hs_uhnb);
+        o_5ul = A.add(s->hs_ulo);
+        o_5ux = A.add(s->hs_ucross);
+        o_5it = A.add(s->hs_items);
+    }
     void *mem = nullptr;
     hipError_t e = hipMalloc(&mem, A.off);
     if (e != hipSuccess) return fail(ECUT_ENOMEM, std::string("hipMalloc(sector tables): ") + hipGetErrorString(e));
@@ -281,6 +289,29 @@ ecut_status upload(ecut_sectors *s) {
         A3.max_tile = s->h3_max_tile;
         A3.max_nseg = s->hub.max_nseg;
     }
+    if (s->hubseg_ok) {
+        HubSegArgs &G = s->hseg;
+        G = HubSegArgs{};
+        G.hop = s->hub.hop0;
+        G.u0 = s->hub.u0;
+        G.lwords = P.lwords;
+        G.cls = P.hub.cls;
+        G.seginfo = (const int4 *)(b + o_3si);
+        G.loinfo = (const int4 *)(b + o_3li);
+        G.looff = (const int32_t *)(b + o_3lo);
+        G.hnb = (const int32_t *)(b + o_3hn);
+        G.hcnt = (const int32_t *)(b + o_3hc);
+        G.useg = (const int4 *)(b + o_5us);
+        G.uhnb = (const int32_t *)(b + o_5uh);
+        G.ulo = (const int32_t *)(b + o_5ul);
+        G.ucross = (const int32_t *)(b + o_5ux);
+        G.items = (const HubSegItem *)(b + o_5it);
+        G.n_items = (int32_t)s->hs_items.size();
+        G.dR = s->blocks[0].d_r;
+        G.h = s->hub.h;
+        G.hs = s->h3_hs;
+        G.uhs = s->hs_uhs;
+    }
     s->dev_mem = mem;
     s->dev_bytes = A.off;
     s->device = dev;
@@ -319,6 +350,18 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             A3.zcoef = P.zcoef;
             const int slab_grid = 8 * std::max(1, (n_cu / 8) * hub_blocks_per_cu(4, 0));
             e = launch_hub3(s, A3, grid, n_xcd, T.variant == 3, slab_grid, st);
+        } else if (T.variant == 5 && s->hubseg_ok) {
+            const size_t lds = (size_t)s->hs_max_tile * 8;
+            if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "segment tiles exceed the device's LDS per work group");
+            const int grid = T.grid > 0 ? T.grid : n_cu * hub_blocks_per_cu(5, lds);
+            HubSegArgs G = s->hseg;
+            G.x = P.x;
+            G.y = P.y;
+            G.z = P.z;
+            G.partials = P.partials;
+            G.xscale = P.xscale;
+            G.zcoef = P.zcoef;
+            e = launch_hubseg(s, G, grid, n_xcd == 1 ? 1 : 8, st);
         } else if (T.variant == 4 && s->hubrow_ok) {
             if (((uintptr_t)P.x | (uintptr_t)P.y | (uintptr_t)P.z) & 15)
                 return fail(ECUT_EINVAL, "the whole-row kernel needs 16-byte aligned vectors");
@@ -348,6 +391,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
 // number of partial slots the apply kernel writes
 int32_t apply_partial_slots(const ecut_sectors *s) {
     if (s->kernel != 1) return (int32_t)s->items.size();
+    if (s->tune.variant == 5 && s->hubseg_ok) return s->hs_n_slots;
     const bool tiles = ((s->tune.variant == 0 || s->tune.variant == 3) && (s->hub3_ok || s->hub2_ok)) ||
                        (s->tune.variant == 2 && s->hub2_ok);   // variants 1 and 4: one slot per row
     return tiles ? (int32_t)s->hub_items.size() : s->blocks[0].d_l;
@@ -355,7 +399,8 @@ int32_t apply_partial_slots(const ecut_sectors *s) {
 
 // workspace size: either Hubbard variant may run on the same workspace
 int32_t apply_partial_slots_max(const ecut_sectors *s) {
-    return s->kernel == 1 ? std::max<int32_t>(s->blocks[0].d_l, (int32_t)s->hub_items.size())
+    return s->kernel == 1 ? std::max<int32_t>(std::max<int32_t>(s->blocks[0].d_l, (int32_t)s->hub_items.size()),
+                                              s->hubseg_ok ? s->hs_n_slots : 0)
                           : (int32_t)std::max(s->items_cap, s->items.size());
 }
 
@@ -511,7 +556,8 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
     I.n_cross_offdiag = 2 * (int32_t)s->xbond.size();
     I.n_cross_diag = (int32_t)s->xdiag.size();
     I.kernel = s->kernel;
-    I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0) | (s->hubrow_ok ? 8 : 0);
+    I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0) | (s->hubrow_ok ? 8 : 0) |
+                     (s->hubseg_ok ? 16 : 0);
     I.device_bytes = (int64_t)s->dev_bytes;
     I.n_eff = s->n_eff;
     *info = I;

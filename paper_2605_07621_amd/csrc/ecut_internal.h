@@ -138,6 +138,39 @@ struct Hub3Args {
     int32_t h, hs, max_tile, max_nseg;
 };
 
+// Segment-tile kernel: a tile is (up segment) x (down segment), where a
+// segment is the set of words that share the high half.  Up segments are
+// contiguous row ranges (rows are in increasing word order), down segments
+// contiguous column runs (class-major columns).
+struct HubSegArgs {
+    const double *x;
+    double *y;
+    const double *z;
+    double *partials;
+    double xscale, zcoef, hop, u0;
+    const uint32_t *lwords;           // up words
+    const int32_t *cls;               // [n_cls][8] as HubDev::cls (down classes)
+    const int4 *seginfo;              // down segments, as Hub3Args
+    const int4 *loinfo;               // down low words, as Hub3Args
+    const int32_t *looff;             // down low-hop offsets, as Hub3Args
+    const int32_t *hnb;               // down high-hop neighbours (segment index within the class)
+    const int32_t *hcnt;              // down high-hop counts
+    const int4 *useg;                 // up segments: first row, rows, up low-table base, high hops
+    const int32_t *uhnb;              // [up segment][uhs]: first row of each high-hop neighbour segment
+    const int32_t *ulo;               // [up low word][9]: hop count, then row offsets i' - i
+    const int32_t *ucross;            // [row]: source row of the crossing-bond hop, -1 if none
+    const struct HubSegItem *items;
+    int32_t n_items, n_xcd, per_xcd, dR;
+    int32_t h, hs, uhs, pad_;
+};
+
+// Work item of the segment-tile kernel: up segment, down segment (global
+// index), down class; slot = index in the order-independent item list.
+// useg < 0 marks padding.
+struct HubSegItem {
+    int32_t useg, dseg, cls, slot;
+};
+
 // Work item of the class-tile kernel: rows [row0, row0 + nrows) of one class;
 // slot is the item's index in the order-independent item list.
 struct HubItem {
@@ -223,6 +256,12 @@ struct ecut_sectors {
     std::vector<int32_t> h3_seginfo, h3_loinfo, h3_looff, h3_hnb, h3_hcnt;
     int32_t h3_hs = 1, h3_max_tile = 0;
     ecut::Hub3Args h3{};                 // device pointers (launch fields filled per call)
+    // segment-tile kernel
+    bool hubseg_ok = false;
+    std::vector<int32_t> hs_useg, hs_uhnb, hs_ulo, hs_ucross;
+    std::vector<ecut::HubSegItem> hs_items;   // processing order, padded to 8 equal XCD chunks
+    int32_t hs_uhs = 1, hs_n_slots = 0, hs_max_tile = 0;
+    ecut::HubSegArgs hseg{};
     ecut::HubDev hub{};
     std::vector<int32_t> hub_lo_cnt, hub_lo_ent, hub_lo_rank, hub_hi_cnt, hub_hi_ent, hub_seg_off, hub_xb;
     std::vector<double> hub_coef, hub_u;

@@ -18,6 +18,8 @@ constexpr int HUB2_M = 16;                   // element passes per thread and it
 constexpr int HUB2_LOREG = 8;                // low-hop entries kept in registers
 constexpr int HUB2_NB = 8;                   // left-operator neighbour loads issued together per element
 constexpr int HUB3_M = 12;                   // element slots per thread and item in the fast kernel
+constexpr int HUBSEG_THREADS = 512;
+constexpr int HUBSEG_M = 10;                 // element slots per thread and item in the segment-tile kernel
 constexpr int SLAB_W = 16;                   // columns per slab of the left-operator pass (one 128-byte line)
 constexpr int SLAB_THREADS = 256;
 constexpr int SPIN_THREADS = 512;
@@ -64,6 +66,8 @@ size_t hub2_lds_bytes(const ecut_sectors *s);
 hipError_t launch_hub2(const ecut_sectors *s, const ProblemDev &prob, const HubItem *items_d, int n_items, int grid,
                        int n_xcd, hipStream_t st);
 size_t hub3_lds_bytes(const ecut_sectors *s);
+// segment tiles: grid work groups, n_xcd = 8 (items in 8 XCD chunks) or 1
+hipError_t launch_hubseg(const ecut_sectors *s, const HubSegArgs &args, int grid, int n_xcd, hipStream_t st);
 hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, bool split, int slab_grid,
                        hipStream_t st);
 int hub_blocks_per_cu(int which, size_t lds);

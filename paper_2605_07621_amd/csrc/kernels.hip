@@ -1112,6 +1112,152 @@ __global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
     }
 }
 
+// ------------------------------------------------------------------------
+// Segment-tile kernel for uniform, sign-free hopping.  A segment is the set
+// of words that share the high half; a tile is Psi[a][b] for a in one up
+// segment (a contiguous run of rows) and b in one down segment (a contiguous
+// run of columns).  Hops inside the low half of either word stay in the tile
+// and are read from LDS.  The other hops read global memory:
+//  - up high-half hops: the same columns of the neighbour segment's rows;
+//  - down high-half hops: the same rows at the neighbour segment's columns;
+//  - the bond across the split, for either spin: one gathered element.
+// Items come grouped by panel (one up segment x one down class), and the
+// panels are dealt to 8 XCD chunks, so all work groups of an XCD work on one
+// or two panels at a time: the down high-hop sources are the other tiles of
+// the same panel, fetched into that XCD's L2 by their own item.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(HUBSEG_THREADS, 4) void k_hubseg(const HubSegArgs A) {
+    extern __shared__ __align__(16) double xt[];
+    __shared__ double red[HUBSEG_THREADS / 64];
+    constexpr int M = HUBSEG_M;
+    const int tid = threadIdx.x;
+    const int dR = A.dR;
+    const int xcd = blockIdx.x % A.n_xcd;
+    const int wslot = blockIdx.x / A.n_xcd;
+    const int nslot = gridDim.x / A.n_xcd;
+    for (int k = wslot; k < A.per_xcd; k += nslot) {
+        const int idx = xcd * A.per_xcd + k;
+        if (idx >= A.n_items) break;
+        const HubSegItem it = A.items[idx];
+        if (it.useg < 0) continue;
+        const int4 U = A.useg[it.useg];   // first row, rows, up low-table base, high hops
+        const int32_t *cd = A.cls + 8 * it.cls;
+        const int L = cd[0], seg_base = cd[2], lo_base = cd[3];
+        const int4 S = A.seginfo[it.dseg];   // first column, high word, crossing column, crossing bit
+        const int Lp = L + 1;
+        const int per_pass = HUBSEG_THREADS / L;
+        const int p = tid / L;
+        const int j = tid - p * L;
+        const bool active = p < per_pass;
+        int4 li = make_int4(0, 0, 2, 0);
+        int lof[8];
+        if (active) {
+            li = A.loinfo[lo_base + j];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lof[q] = A.looff[(lo_base + j) * 8 + q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lof[q] = 0;
+        }
+        // element (i, j) of the tile lives at offset (U.x + i) * dR + S.x + j
+        int off[M];
+        double x0[M], acc[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int i = p + m * per_pass;
+            off[m] = (active && i < U.y) ? (U.x + i) * dR + S.x + j : -1;
+            acc[m] = 0.0;
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) x0[m] = off[m] >= 0 ? A.x[off[m]] : 0.0;
+        // up high-half hops: row i of the neighbour segment, same column
+        for (int q = 0; q < U.w; ++q) {
+            const int d = (A.uhnb[it.useg * A.uhs + q] - U.x) * dR;
+            double v[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) v[m] = off[m] >= 0 ? A.x[off[m] + d] : 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] += v[m];
+        }
+        // down high-half hops: same row, the neighbour segment's column
+        const int nd = A.hcnt[it.dseg];
+        for (int q = 0; q < nd; ++q) {
+            const int d = A.seginfo[seg_base + A.hnb[it.dseg * A.hs + q]].x - S.x;
+            double v[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) v[m] = off[m] >= 0 ? A.x[off[m] + d] : 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] += v[m];
+        }
+        // the bond across the split: up (source row per row), down (source
+        // column in the neighbouring class, per column)
+        {
+            const bool dx = (li.z ^ S.w) == 1;
+            const int dd = S.z + li.y - (S.x + j);
+            double v[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                v[m] = 0.0;
+                if (off[m] >= 0) {
+                    const int a = U.x + p + m * per_pass;
+                    const int r = A.ucross[a];
+                    if (r >= 0) v[m] = A.x[off[m] + (r - a) * dR];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] += v[m];
+#pragma unroll
+            for (int m = 0; m < M; ++m) v[m] = (off[m] >= 0 && dx) ? A.x[off[m] + dd] : 0.0;
+#pragma unroll
+            for (int m = 0; m < M; ++m) acc[m] += v[m];
+        }
+        // stage the tile (row stride L + 1, zero in the pad column)
+        __syncthreads();   // readers of the previous tile are done
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (off[m] >= 0) xt[(p + m * per_pass) * Lp + j] = x0[m];
+        for (int r = tid; r < U.y; r += HUBSEG_THREADS) xt[r * Lp + L] = 0.0;
+        __syncthreads();
+        // low-half hops of both spins from the tile, diagonal, epilogue
+        const uint32_t bw = ((uint32_t)S.y << A.h) | (uint32_t)li.x;
+        double part = 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            if (off[m] < 0) continue;
+            const int i = p + m * per_pass;
+            const int rb = i * Lp + j;
+            double dn = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dn += xt[rb + lof[q]];
+            const int32_t *ul = A.ulo + (U.z + i) * 9;
+            const int nu = ul[0];
+            for (int q = 0; q < nu; ++q) dn += xt[rb + ul[1 + q] * Lp];
+            const uint32_t aw = A.lwords[U.x + i];
+            const double dg = A.u0 * (double)__popc(aw & bw);
+            double y = A.xscale * (A.hop * (acc[m] + dn) + dg * x0[m]);
+            if (A.z) y -= A.zcoef * A.z[off[m]];
+            A.y[off[m]] = y;
+            part += x0[m] * y;
+        }
+        if (A.partials) {
+            const double sum = block_sum(part, red);
+            if (tid == 0) A.partials[it.slot] = sum;
+        }
+    }
+}
+
+hipError_t launch_hubseg(const ecut_sectors *s, const HubSegArgs &args, int grid, int n_xcd, hipStream_t st) {
+    HubSegArgs A = args;
+    if (n_xcd != 1) n_xcd = 8;
+    if (grid % n_xcd) grid = (grid / n_xcd) * n_xcd;
+    if (grid < n_xcd) grid = n_xcd;
+    A.n_xcd = n_xcd;
+    A.per_xcd = (A.n_items + n_xcd - 1) / n_xcd;
+    const size_t lds = (size_t)s->hs_max_tile * 8;
+    hipLaunchKernelGGL(k_hubseg, dim3(grid), dim3(HUBSEG_THREADS), lds, st, A);
+    return hipGetLastError();
+}
+
 size_t hub3_lds_bytes(const ecut_sectors *s) {
     auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
     const int mns = s->hub.max_nseg;
@@ -1141,6 +1287,7 @@ int hub_blocks_per_cu(int which, size_t lds) {
     hipError_t e = hipSuccess;
     if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3<true>, HUB2_THREADS, lds);
     else if (which == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_upslab, SLAB_THREADS, 0);
+    else if (which == 5) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hubseg, HUBSEG_THREADS, lds);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub2<true, true>, HUB2_THREADS, lds);
     if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -138,6 +138,7 @@ inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
 
 static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
 static void build_spin_tables(ecut_sectors *s);
+static void build_hubseg_tables(ecut_sectors *s);
 static void make_rank_tables(ecut_sectors *s);
 static void build_hubrow_tables(ecut_sectors *s, const ecut_model_desc *m);
 void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
@@ -485,7 +486,6 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
             std::vector<std::vector<int32_t>> hient, loent;
         };
         std::vector<Cls> cl;
-        int max_size = 0;
         for (int k = 0; k <= nh; ++k) {
             const int lc = c - k;
             if (lc < 0 || lc > h) continue;
@@ -523,7 +523,6 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
                     }
                 }
             }
-            max_size = std::max(max_size, C.L * C.nseg);
             cl.push_back(std::move(C));
         }
         size_t hs2 = 1, ls2 = 1;
@@ -531,7 +530,11 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
             for (auto &v : C.hient) hs2 = std::max(hs2, v.size());
             for (auto &v : C.loent) ls2 = std::max(ls2, v.size());
         }
-        const int tile = std::max(max_size, 2048);
+        // rows per item: the padded tile (row stride L + 1 in the fast
+        // kernel) of every class stays within the largest one-row class tile,
+        // so one-column classes do not double the LDS of a work group
+        int tile_pad = 2048;
+        for (auto &C : cl) tile_pad = std::max(tile_pad, C.nseg * (C.L + 1));
         s->hc_cls.clear();
         s->hc_segcol.clear();
         s->hc_hiw.clear();
@@ -546,7 +549,7 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
             Cls &C = cl[ci];
             const int seg_base = (int)s->hc_segcol.size(), lo_base = (int)s->hc_low.size();
             const int S = C.L * C.nseg;
-            const int rpi = std::max(1, std::min(B.d_l, tile / S));
+            const int rpi = std::max(1, std::min(B.d_l, tile_pad / (C.nseg * (C.L + 1))));
             s->hc_cls.insert(s->hc_cls.end(), {C.L, C.nseg, seg_base, lo_base, rpi, S, C.k, 0});
             for (int si = 0; si < C.nseg; ++si) {
                 s->hc_segcol.push_back(C.segcol[si]);
@@ -632,6 +635,7 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
             if ((size_t)mt * 8 + (size_t)max_nseg * (16 + 4 * hs2 + 4) + 2048 > 150 * 1024) fast = false;
         }
         s->hub3_ok = fast;
+        build_hubseg_tables(s);
         H.cls_lo_stride = (int32_t)ls2;
         H.cls_hi_stride = (int32_t)hs2;
         H.max_tile = max_tile;
@@ -645,6 +649,118 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     }
     s->hub_ok = true;
     s->kernel = 1;
+}
+
+// Tables of the segment-tile kernel (uniform, sign-free hopping, as the fast
+// class-tile kernel).  The down side reuses that kernel's segment and
+// low-word tables.  The up side is read off the up-hopping CSR: a hop that
+// keeps the high half of the up word is a low-half hop inside the segment (a
+// row offset), one that keeps the low half moves to the same row of a
+// neighbour segment, any other is the crossing-bond hop (at most one per
+// row).  Anything that does not fit this shape leaves the kernel off.
+static void build_hubseg_tables(ecut_sectors *s) {
+    s->hubseg_ok = false;
+    s->hs_useg.clear();
+    s->hs_uhnb.clear();
+    s->hs_ulo.clear();
+    s->hs_ucross.clear();
+    s->hs_items.clear();
+    if (!s->hub3_ok) return;
+    const BlockDev &B = s->blocks[0];
+    if (B.lbase != 0 || (int64_t)B.d_l * B.d_r >= (1ll << 31)) return;
+    const int h = s->hub.h;
+    const uint32_t lomask = (1u << h) - 1u;
+    const int32_t nr = B.d_l;
+    // up segments: maximal runs of rows with the same high half
+    std::vector<int32_t> seg_of_row(nr), seg_row0, seg_rows;
+    std::map<uint32_t, int32_t> seg_of_hi;
+    for (int32_t a = 0; a < nr; ++a) {
+        const uint32_t hi = s->lwords[a] >> h;
+        if (a == 0 || hi != (s->lwords[a - 1] >> h)) {
+            if (seg_of_hi.count(hi)) return;   // not contiguous
+            seg_of_hi[hi] = (int32_t)seg_row0.size();
+            seg_row0.push_back(a);
+            seg_rows.push_back(0);
+        }
+        seg_of_row[a] = (int32_t)seg_row0.size() - 1;
+        ++seg_rows.back();
+    }
+    const int32_t ns = (int32_t)seg_row0.size();
+    std::vector<std::vector<int32_t>> hnb(ns);
+    s->hs_ulo.assign((size_t)nr * 9, 0);
+    s->hs_ucross.assign(nr, -1);
+    for (int32_t a = 0; a < nr; ++a) {
+        const uint32_t w = s->lwords[a];
+        const int32_t g = seg_of_row[a], i = a - seg_row0[g];
+        std::vector<int32_t> his;
+        int nlo = 0;
+        for (int32_t q = s->hl_ptr[a]; q < s->hl_ptr[a + 1]; ++q) {
+            const int32_t a2 = s->hl_col[q];
+            if (a2 == a || a2 < 0 || a2 >= nr) return;
+            const uint32_t w2 = s->lwords[a2];
+            if ((w2 >> h) == (w >> h)) {
+                if (nlo == 8) return;
+                s->hs_ulo[(size_t)a * 9 + 1 + nlo++] = a2 - a;
+            } else if ((w2 & lomask) == (w & lomask)) {
+                const int32_t g2 = seg_of_row[a2];
+                if (a2 - seg_row0[g2] != i || seg_rows[g2] != seg_rows[g]) return;
+                his.push_back(seg_row0[g2]);
+            } else {
+                if (s->hs_ucross[a] >= 0) return;
+                s->hs_ucross[a] = a2;
+            }
+        }
+        s->hs_ulo[(size_t)a * 9] = nlo;
+        std::sort(his.begin(), his.end());
+        if (i == 0) hnb[g] = his;
+        else if (his != hnb[g]) return;   // the high-half hops must not depend on the low half
+    }
+    size_t uhs = 1;
+    for (auto &v : hnb) uhs = std::max(uhs, v.size());
+    for (int32_t g = 0; g < ns; ++g) {
+        s->hs_useg.insert(s->hs_useg.end(), {seg_row0[g], seg_rows[g], seg_row0[g], (int32_t)hnb[g].size()});
+        for (size_t q = 0; q < uhs; ++q) s->hs_uhnb.push_back(q < hnb[g].size() ? hnb[g][q] : seg_row0[g]);
+    }
+    s->hs_uhs = (int32_t)uhs;
+    // items: panels (up segment x down class), heaviest first, dealt to 8
+    // equal XCD chunks padded with empty items
+    const int n_cls = (int)(s->hc_cls.size() / 8);
+    struct Panel {
+        int64_t size;
+        int32_t g, ci;
+    };
+    std::vector<Panel> panels;
+    int32_t max_tile = 1;
+    for (int32_t g = 0; g < ns; ++g)
+        for (int ci = 0; ci < n_cls; ++ci) {
+            const int L = s->hc_cls[8 * ci], nseg = s->hc_cls[8 * ci + 1];
+            const int per_pass = HUBSEG_THREADS / L;
+            if (per_pass < 1 || (seg_rows[g] + per_pass - 1) / per_pass > HUBSEG_M) return;
+            max_tile = std::max(max_tile, seg_rows[g] * (L + 1));
+            panels.push_back(Panel{(int64_t)seg_rows[g] * L * nseg, g, ci});
+        }
+    if ((size_t)max_tile * 8 > 48 * 1024) return;
+    std::stable_sort(panels.begin(), panels.end(), [](const Panel &x, const Panel &y) { return x.size > y.size; });
+    const int n_chunks = 8;
+    std::vector<std::vector<HubSegItem>> ch(n_chunks);
+    std::vector<int64_t> load(n_chunks, 0);
+    int32_t slot = 0;
+    for (const Panel &P : panels) {
+        // the least loaded chunk takes the next panel
+        const int c = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[c] += P.size;
+        const int nseg = s->hc_cls[8 * P.ci + 1], seg_base = s->hc_cls[8 * P.ci + 2];
+        for (int si = 0; si < nseg; ++si) ch[c].push_back(HubSegItem{P.g, seg_base + si, P.ci, slot++});
+    }
+    size_t len = 0;
+    for (auto &c : ch) len = std::max(len, c.size());
+    for (auto &c : ch) {
+        s->hs_items.insert(s->hs_items.end(), c.begin(), c.end());
+        for (size_t k = c.size(); k < len; ++k) s->hs_items.push_back(HubSegItem{-1, 0, 0, 0});
+    }
+    s->hs_n_slots = slot;
+    s->hs_max_tile = max_tile;
+    s->hubseg_ok = true;
 }
 
 // Column of the down word of canonical rank r in the block (identity unless

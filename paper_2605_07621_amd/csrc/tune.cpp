@@ -69,7 +69,7 @@ void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) 
 }
 
 ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
-    if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 4)
+    if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 5)
         return fail(ECUT_EINVAL, "bad tuning");
     if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
     if (T.tile < 0 || T.tile > SPIN_MANY_TILE) return fail(ECUT_EINVAL, "tile must lie in 0..512");
@@ -77,6 +77,8 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
         return fail(ECUT_EUNSUPPORTED, "class tiles not available");
     if (T.variant == 3 && s->kernel == 1 && !s->hub3_ok) return fail(ECUT_EUNSUPPORTED, "split passes not available");
+    if (T.variant == 5 && s->kernel == 1 && !s->hubseg_ok)
+        return fail(ECUT_EUNSUPPORTED, "segment tiles not available (needs uniform, sign-free hopping, <= 16 sites)");
     if (T.variant == 4 && s->kernel == 1 && !s->hubrow_ok)
         return fail(ECUT_EUNSUPPORTED, "whole-row kernel not available (more than 16 sites, odd or too long rows)");
     if (s->kernel == 1 && (T.order != s->tune.order || T.variant != s->tune.variant)) {
@@ -163,6 +165,8 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
         if (s->hubrow_ok)
             for (int order : {0, 1, 2, 9})
                 for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 4});
+        if (s->hubseg_ok)
+            for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, 0, 5});
     } else if (s->spin_ok) {
         // spin kernel: short-row tile and grid; then the generic row kernel
         for (int tile : {128, 256, 512})

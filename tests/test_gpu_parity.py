@@ -98,14 +98,14 @@ _HUB_CASES = [I.hubbard12(),
               I.Problem(I.random_hubbard_model(np.random.default_rng(78), 10, n_bonds=12), I.Cut("updn"), 3, 5)]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("order", [0, 2, 4, 7, 9])
 def test_hubbard_kernel_variants_and_orders(dev, variant, order):
     """Every Hubbard kernel (class tiles with the uniform-chain fast path,
     whole rows in LDS, generic class tiles, two passes, whole rows with
-    16-byte access and ranked hops) under several work orders agrees with
-    the oracle; uniform chains and random long-range couplings (fermion
-    signs), even and odd row lengths."""
+    16-byte access and ranked hops, segment tiles) under several work orders
+    agrees with the oracle; uniform chains and random long-range couplings
+    (fermion signs), even and odd row lengths."""
     for k, p in enumerate(_HUB_CASES):
         s = O.Sector(p.model, p.n_up, p.n_dn)
         psi = I.psi(500 + k, s.n)
@@ -117,6 +117,11 @@ def test_hubbard_kernel_variants_and_orders(dev, variant, order):
                 S.set_tuning(0, 1, order, variant)
             continue
         if variant == 3 and not S.info.kernel_flags & 2:
+            with pytest.raises(_ecut().EcutError):
+                S.set_tuning(0, 1, order, variant)
+            continue
+        if variant == 5 and not S.info.kernel_flags & 16:
+            assert not S.info.kernel_flags & 2    # segment tiles cover every uniform sign-free chain here
             with pytest.raises(_ecut().EcutError):
                 S.set_tuning(0, 1, order, variant)
             continue
@@ -167,7 +172,7 @@ def test_apply_full_size_sampled_vs_oracle(dev, name):
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
     if name == "hubbard16":
         # every Hubbard kernel at full size agrees with the autotuned one
-        for t in ((0, 8, 8, 0), (0, 1, 1, 4), (0, 8, 2, 4)):
+        for t in ((0, 8, 8, 0), (0, 1, 1, 4), (0, 8, 2, 4), (0, 8, 0, 5), (0, 1, 0, 5)):
             S.set_tuning(*t)
             yt = _gpu_apply_canonical(S, psi, dev)
             assert np.linalg.norm(yt - y) / np.linalg.norm(y) <= RTOL, t
@@ -346,7 +351,7 @@ def test_lanczos_hubbard12_vs_oracle(dev):
     e_ref = s.lanczos(I.psi(p.meta["seed"] + 1, s.n), 400, tol=1e-13)[0][-1]
     S = _ecut().Sectors.from_problem(p)
     v0 = torch.from_numpy(I.psi(p.meta["seed"] + 1, s.n)).to(dev)
-    for variant in (0, 1, 3):
+    for variant in (0, 1, 3, 5):
         # a workspace full of NaN: every partial slot the solver reads must be written first
         S.set_tuning(0, 8, 0, variant)
         ws = torch.full((S.lanczos_workspace(200),), float("nan"), dtype=torch.float64, device=dev)

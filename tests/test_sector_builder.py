@@ -105,7 +105,7 @@ def test_workload_block_structure():
     # a straight cut between x=2 and x=3 of the 6x5 lattice crosses 5 J1 and 8 J2 bonds
     assert S4.info.n_cut_bonds == 13 and S4.info.n_cross_offdiag == 26 and S4.info.n_cross_diag == 13
     S3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)
-    assert S3.dim == 165636900 and S3.info.kernel == 1 and S3.info.kernel_flags == 1 | 2 | 8
+    assert S3.dim == 165636900 and S3.info.kernel == 1 and S3.info.kernel_flags == 1 | 2 | 8 | 16
     assert S3.info.n_eff == pytest.approx(1.0)
 
 
@@ -159,10 +159,11 @@ def test_bench_names_every_kernel_variant():
     import bench
     S3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)
     names = set()
-    for v in range(5):
+    assert S3.info.kernel_flags & 16
+    for v in range(6):
         S3.set_tuning(0, 1, 0, v)
         names.add(bench.kernel_name(S3))
-    assert names == {"k_hub3", "k_hub", "k_hub2", "k_upslab+k_hub3", "k_hubrow"}
+    assert names == {"k_hub3", "k_hub", "k_hub2", "k_upslab+k_hub3", "k_hubrow", "k_hubseg"}
     S4 = E.Sectors.from_problem(I.j1j2_6x5(), host_only=True)
     for v, want in ((0, "k_spin"), (1, "k_rows")):
         S4.set_tuning(0, 0, 0, v)
