@@ -379,8 +379,9 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
         }
     } else if (P.spin_ok) {
-        e = launch_spin(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), s->max_d_r, s->tune.grid,
-                        st);
+        int grid = s->tune.grid;
+        if (s->tune.order == 1) grid = std::max(8, ((grid > 0 ? grid : 2048) / 8) * 8);   // keeps chunk c on XCD c
+        e = launch_spin(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), s->max_d_r, grid, st);
     } else {
         e = launch_rows(nullptr, P, s->dev_items, (int)s->items.size(), max_tile_elems(s), st);
     }
@@ -390,7 +391,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
 
 // number of partial slots the apply kernel writes
 int32_t apply_partial_slots(const ecut_sectors *s) {
-    if (s->kernel != 1) return (int32_t)s->items.size();
+    if (s->kernel != 1) return s->item_slots;
     if (s->tune.variant == 5 && s->hubseg_ok) return s->hs_n_slots;
     const bool tiles = ((s->tune.variant == 0 || s->tune.variant == 3) && (s->hub3_ok || s->hub2_ok)) ||
                        (s->tune.variant == 2 && s->hub2_ok);   // variants 1 and 4: one slot per row
@@ -401,7 +402,7 @@ int32_t apply_partial_slots(const ecut_sectors *s) {
 int32_t apply_partial_slots_max(const ecut_sectors *s) {
     return s->kernel == 1 ? std::max<int32_t>(std::max<int32_t>(s->blocks[0].d_l, (int32_t)s->hub_items.size()),
                                               s->hubseg_ok ? s->hs_n_slots : 0)
-                          : (int32_t)std::max(s->items_cap, s->items.size());
+                          : std::max(s->item_slots_cap, s->item_slots);
 }
 
 // ---------------------------------------------------------------- staging buffers

@@ -281,9 +281,12 @@ struct ecut_sectors {
     std::vector<int32_t> spin_rank_lo, spin_rank_hi;
     std::vector<uint32_t> spin_fmask;
     std::vector<double> spin_fcoef;
-    // work items of a single application
+    // work items of a single application (spin problems: may hold padding
+    // items with row1 == row0 and slot -1)
     std::vector<ecut::ItemDev> items;
-    size_t items_cap = 0;                 // device capacity for any spin tile size
+    size_t items_cap = 0;                 // device capacity for any spin tile size and order
+    int32_t item_slots = 0;               // partial-sum slots of `items` (its non-padding items)
+    int32_t item_slots_cap = 0;           // most slots any spin tiling can use
     std::vector<int32_t> row_order;       // Hubbard kernel: row processing order
     int32_t kernel = 2;
     ecut::ApplyTuning tune{};
@@ -307,7 +310,9 @@ void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out)
 inline int row_order_kind(int order) { return order >= 9 ? 3 : order % 3; }
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 int32_t hub_column(const ecut_sectors *s, int64_t r);
-// work items of the spin kernel for a short-row tile of `tile` amplitudes
-void make_spin_items(const ecut_sectors *s, int32_t tile, std::vector<ItemDev> &out);
+// work items of the spin kernel for a short-row tile of `tile` amplitudes;
+// order 0 largest first, 1 segments dealt to 8 XCD chunks (padded list);
+// returns the number of partial-sum slots
+int32_t make_spin_items(const ecut_sectors *s, int32_t tile, int32_t order, std::vector<ItemDev> &out);
 void release_device(ecut_sectors *s);
 }  // namespace ecut

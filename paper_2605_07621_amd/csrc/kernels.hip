@@ -58,6 +58,7 @@ __global__ __launch_bounds__(ROWS_THREADS) void k_rows(const ProblemDev *__restr
     __shared__ double red[ROWS_THREADS / 64];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const ItemDev W = items[it];
+        if (W.row1 <= W.row0) continue;   // padding of an XCD-dealt list
         const ProblemDev &P = probs ? probs[W.prob] : single;
         const BlockDev B = P.blocks[W.block];
         const int dR = B.d_r;
@@ -878,7 +879,7 @@ __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, ONE ? 4 : 2
     int loaded = -1;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const ItemDev W = items[it];
-        if ((W.row1 - W.row0 == 1) != ONE) continue;
+        if (W.row1 <= W.row0 || (W.row1 - W.row0 == 1) != ONE) continue;   // padding, or the other kernel's item
         const ProblemDev &P = probs ? probs[W.prob] : single;
         const int n_flip = P.n_rflip;
         if (W.prob != loaded) {
@@ -951,9 +952,9 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_upslab(const double *__restric
 // into a per-segment and a per-lane part that are both precomputed.
 // ------------------------------------------------------------------------
 template <bool UP>
-__global__ __launch_bounds__(HUB2_THREADS, 4) void k_hub3(const Hub3Args A) {
+__global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const Hub3Args A) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[HUB2_THREADS / 64];
+    __shared__ double red[HUB3_THREADS / 64];
     const int hs = A.hs;
     double *xs = (double *)smem;
     int4 *sinf = (int4 *)(smem + (((size_t)A.max_tile * 8 + 15) & ~(size_t)15));
@@ -1275,9 +1276,9 @@ hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, in
         // pass 1: left operator over column slabs held in L2; pass 2: tiles
         hipLaunchKernelGGL(k_upslab, dim3(slab_grid), dim3(SLAB_THREADS), 0, st, A.x, A.y, A.hl_ptr, A.hl_col, A.hl_val,
                            A.n_rows, A.dR, slab_grid / 8);
-        hipLaunchKernelGGL(k_hub3<false>, dim3(grid), dim3(HUB2_THREADS), hub3_lds_bytes(s), st, A);
+        hipLaunchKernelGGL(k_hub3<false>, dim3(grid), dim3(HUB3_THREADS), hub3_lds_bytes(s), st, A);
     } else {
-        hipLaunchKernelGGL(k_hub3<true>, dim3(grid), dim3(HUB2_THREADS), hub3_lds_bytes(s), st, A);
+        hipLaunchKernelGGL(k_hub3<true>, dim3(grid), dim3(HUB3_THREADS), hub3_lds_bytes(s), st, A);
     }
     return hipGetLastError();
 }
@@ -1285,7 +1286,7 @@ hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, in
 int hub_blocks_per_cu(int which, size_t lds) {
     int n = 0;
     hipError_t e = hipSuccess;
-    if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3<true>, HUB2_THREADS, lds);
+    if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3<true>, HUB3_THREADS, lds);
     else if (which == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_upslab, SLAB_THREADS, 0);
     else if (which == 5) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hubseg, HUBSEG_THREADS, lds);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub2<true, true>, HUB2_THREADS, lds);

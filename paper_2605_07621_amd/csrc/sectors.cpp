@@ -339,6 +339,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
     });
     for (size_t k = 0; k < s->items.size(); ++k) s->items[k].slot = (int32_t)k;
     s->items_cap = s->items.size();
+    s->item_slots = s->item_slots_cap = (int32_t)s->items.size();
 
     s->hub_ok = false;
     s->kernel = 2;
@@ -626,10 +627,11 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
             }
             s->h3_hs = (int32_t)hs2;
             s->h3_max_tile = mt;
-            // every item must fit HUB3_M (12) element slots per thread of 512
+            // every item must fit HUB3_M element slots per thread of HUB3_THREADS
             for (size_t ci = 0; ci < cl.size(); ++ci) {
                 const int L = s->hc_cls[8 * ci], nseg = s->hc_cls[8 * ci + 1], rpi = s->hc_cls[8 * ci + 4];
-                if ((rpi * nseg + 512 / L - 1) / (512 / L) > 12) fast = false;
+                const int per_pass = HUB3_THREADS / L;
+                if (per_pass < 1 || (rpi * nseg + per_pass - 1) / per_pass > HUB3_M) fast = false;
                 if ((int64_t)rpi * s->blocks[0].d_r > (1ll << 31) / 2) fast = false;
             }
             if ((size_t)mt * 8 + (size_t)max_nseg * (16 + 4 * hs2 + 4) + 2048 > 150 * 1024) fast = false;
@@ -825,12 +827,14 @@ static void build_spin_tables(ecut_sectors *s) {
     if (s->lsites.size() > 16 || s->rsites.size() > 16) return;
     if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP) return;
     if (s->max_d_r > SPIN_TILE) return;
-    make_spin_items(s, SPIN_MANY_TILE, s->items);
-    // every item holds at least one row, so no tile size gives more items
-    // than there are rows
+    s->item_slots = make_spin_items(s, SPIN_MANY_TILE, 0, s->items);
+    // every item holds at least one row, so no tile size gives more slots
+    // than there are rows; an XCD-dealt list pads each of its 8 chunks to the
+    // longest, at most 8 times the items
     size_t rows = 0;
     for (const BlockDev &B : s->blocks) rows += (size_t)B.d_l;
-    s->items_cap = std::max(s->items.size(), rows);
+    s->item_slots_cap = (int32_t)std::max(s->items.size(), rows);
+    s->items_cap = 8 * (size_t)s->item_slots_cap;
     make_rank_tables(s);
     s->spin_ok = true;
 }
@@ -838,17 +842,57 @@ static void build_spin_tables(ecut_sectors *s) {
 // Work items of the spin kernel: a row longer than half the tile is an item of
 // its own (its cross-term source rows are staged in LDS), shorter rows are
 // packed into items of at most `tile` amplitudes; largest first.
-void make_spin_items(const ecut_sectors *s, int32_t tile, std::vector<ItemDev> &out) {
-    out.clear();
+//
+// Order 1 deals the items to 8 chunks, one per XCD: the one-row items of a
+// block in runs that share the high half of the left word (a segment, whose
+// rows are each other's neighbours under the left bonds inside the low half),
+// every run to the chunk with the least work so far.  The chunks are padded
+// to one length with empty items and interleaved, position 8 k + c holding
+// item k of chunk c, so a grid-stride walk with a grid that is a multiple of
+// 8 runs chunk c on XCD c (work group w runs on XCD w % 8).
+int32_t make_spin_items(const ecut_sectors *s, int32_t tile, int32_t order, std::vector<ItemDev> &out) {
+    std::vector<ItemDev> base;
     for (int b = 0; b < (int)s->blocks.size(); ++b) {
         const BlockDev &B = s->blocks[b];
         const int32_t rpt = std::max<int32_t>(1, std::min<int32_t>(B.d_l, tile / std::max(B.d_r, 1)));
-        for (int32_t r0 = 0; r0 < B.d_l; r0 += rpt) out.push_back(ItemDev{0, b, r0, std::min(B.d_l, r0 + rpt), 0, 0});
+        for (int32_t r0 = 0; r0 < B.d_l; r0 += rpt) base.push_back(ItemDev{0, b, r0, std::min(B.d_l, r0 + rpt), 0, 0});
     }
-    std::stable_sort(out.begin(), out.end(), [&](const ItemDev &a, const ItemDev &b) {
-        return (int64_t)(a.row1 - a.row0) * s->blocks[a.block].d_r > (int64_t)(b.row1 - b.row0) * s->blocks[b.block].d_r;
-    });
-    for (size_t k = 0; k < out.size(); ++k) out[k].slot = (int32_t)k;
+    auto work = [&](const ItemDev &a) { return (int64_t)(a.row1 - a.row0) * s->blocks[a.block].d_r; };
+    std::stable_sort(base.begin(), base.end(), [&](const ItemDev &a, const ItemDev &b) { return work(a) > work(b); });
+    for (size_t k = 0; k < base.size(); ++k) base[k].slot = (int32_t)k;
+    const int32_t n_slots = (int32_t)base.size();
+    if (order != 1) {
+        out.swap(base);
+        return n_slots;
+    }
+    const int n_chunks = 8;
+    const int hshift = ((int)s->lsites.size() + 1) / 2;
+    std::vector<std::vector<ItemDev>> ch(n_chunks);
+    std::vector<int64_t> load(n_chunks, 0);
+    size_t k = 0;
+    while (k < base.size()) {
+        const ItemDev &a = base[k];
+        size_t k1 = k + 1;
+        if (a.row1 - a.row0 == 1) {
+            const BlockDev &B = s->blocks[a.block];
+            const uint32_t seg = s->lwords[B.lbase + a.row0] >> hshift;
+            while (k1 < base.size() && base[k1].block == a.block && base[k1].row1 - base[k1].row0 == 1 &&
+                   (s->lwords[B.lbase + base[k1].row0] >> hshift) == seg)
+                ++k1;
+        }
+        const int c = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (size_t q = k; q < k1; ++q) {
+            ch[c].push_back(base[q]);
+            load[c] += work(base[q]);
+        }
+        k = k1;
+    }
+    size_t len = 0;
+    for (auto &c : ch) len = std::max(len, c.size());
+    out.assign(len * n_chunks, ItemDev{0, 0, 0, 0, -1, 0});
+    for (int c = 0; c < n_chunks; ++c)
+        for (size_t i = 0; i < ch[c].size(); ++i) out[i * n_chunks + c] = ch[c][i];
+    return n_slots;
 }
 
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out) {

@@ -74,6 +74,7 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
     if (T.tile < 0 || T.tile > SPIN_MANY_TILE) return fail(ECUT_EINVAL, "tile must lie in 0..512");
     if (T.tile != 0 && !s->spin_ok) return fail(ECUT_EUNSUPPORTED, "the tile size applies to the spin kernel only");
+    if (s->spin_ok && T.order > 1) return fail(ECUT_EINVAL, "spin problems take row order 0 or 1");
     if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
         return fail(ECUT_EUNSUPPORTED, "class tiles not available");
     if (T.variant == 3 && s->kernel == 1 && !s->hub3_ok) return fail(ECUT_EUNSUPPORTED, "split passes not available");
@@ -95,16 +96,18 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
         }
     }
     const int32_t tile = T.tile > 0 ? T.tile : SPIN_MANY_TILE, cur = s->tune.tile > 0 ? s->tune.tile : SPIN_MANY_TILE;
-    if (s->spin_ok && tile != cur) {
+    if (s->spin_ok && (tile != cur || T.order != s->tune.order)) {
         std::vector<ItemDev> items;
-        make_spin_items(s, tile, items);
-        if (items.size() > s->items_cap) return fail(ECUT_EINVAL, "work list exceeds its buffer");
+        const int32_t slots = make_spin_items(s, tile, T.order, items);
+        if (items.size() > s->items_cap || slots > s->item_slots_cap)
+            return fail(ECUT_EINVAL, "work list exceeds its buffer");
         if (s->on_device && s->dev_items) {
             hipError_t e =
                 hipMemcpy(s->dev_items, items.data(), items.size() * sizeof(ItemDev), hipMemcpyHostToDevice);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work items)");
         }
         s->items.swap(items);
+        s->item_slots = slots;
     }
     s->tune = T;
     if (s->kernel != 1) s->prob.spin_ok = (s->spin_ok && s->on_device && T.variant == 0) ? 1 : 0;
@@ -169,8 +172,9 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
             for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, 0, 5});
     } else if (s->spin_ok) {
         // spin kernel: short-row tile and grid; then the generic row kernel
-        for (int tile : {128, 256, 512})
-            for (int grid : {0, 512, 1024}) cands.push_back(ApplyTuning{grid, 0, 0, 0, tile});
+        for (int order : {0, 1})
+            for (int tile : {128, 256, 512})
+                for (int grid : {0, 512, 1024}) cands.push_back(ApplyTuning{grid, 0, order, 0, tile});
         cands.push_back(ApplyTuning{0, 0, 0, 1, 0});
     } else {
         cands.push_back(ApplyTuning{0, 0, 0, 0, 0});

@@ -240,7 +240,9 @@ def test_spin_kernel_full_size_variants_agree(dev):
     del y0, y1, x
 
 
-_TILE_CASES = ((1, 0), (64, 7), (128, 1024), (256, 4096), (512, 1), (300, 0))
+# (tile, grid, row order): order 1 deals segments of rows to the 8 XCDs
+_TILE_CASES = ((1, 0, 0), (64, 7, 0), (128, 1024, 0), (256, 4096, 0), (512, 1, 0), (300, 0, 0),
+               (512, 0, 1), (1, 0, 1), (128, 13, 1), (256, 2048, 1))
 
 
 def test_spin_tile_tunings_bit_exact(dev):
@@ -259,11 +261,11 @@ def test_spin_tile_tunings_bit_exact(dev):
         x = S.import_(torch.from_numpy(psi).to(dev))
         S.set_tuning(0, 0, 0, 0, 0)
         y0 = S.apply(x)
-        for tile, grid in _TILE_CASES:
-            S.set_tuning(grid, 0, 0, 0, tile)
+        for tile, grid, order in _TILE_CASES:
+            S.set_tuning(grid, 0, order, 0, tile)
             y = S.apply(x)
             torch.cuda.synchronize()
-            assert torch.equal(y, y0), f"{p.model.name} n_up={p.n_up} tile {tile} grid {grid}"
+            assert torch.equal(y, y0), f"{p.model.name} n_up={p.n_up} tile {tile} grid {grid} order {order}"
         S.set_tuning(0, 0, 0, 0, 64)
         _compare(_gpu_apply_canonical(S, psi, dev), s.apply(psi), f"{p.model.name} n_up={p.n_up} tile 64")
         n_run += 1
@@ -279,11 +281,16 @@ def test_spin_tile_tunings_full_size(dev):
     x = torch.from_numpy(I.psi(p.meta["seed"] + 5, S.dim)).to(dev)
     y0 = S.apply(x)
     y = torch.empty_like(x)
-    for tile, grid in ((128, 1024), (256, 4096), (1, 0)):
-        S.set_tuning(grid, 0, 0, 0, tile)
+    for tile, grid, order in ((128, 1024, 0), (256, 4096, 0), (1, 0, 0), (512, 0, 1), (128, 512, 1), (512, 0, 1)):
+        S.set_tuning(grid, 0, order, 0, tile)
         S.apply(x, out=y)
         torch.cuda.synchronize()
-        assert torch.equal(y, y0), (tile, grid)
+        assert torch.equal(y, y0), (tile, grid, order)
+    # the generic row kernel walks the padded list of order 1 too
+    S.set_tuning(0, 0, 1, 1, 0)
+    S.apply(x, out=y)
+    torch.cuda.synchronize()
+    assert (torch.linalg.vector_norm(y - y0) / torch.linalg.vector_norm(y0)).item() <= RTOL
     del x, y, y0
 
 
@@ -334,14 +341,15 @@ def test_lanczos_heisenberg16_vs_oracle(dev):
     assert abs(e - e_ref) <= 1e-10
     e2, st2, _ = S.lanczos(v0, 400, tol=1e-10)
     assert abs(e2 - e_ref) <= 1e-10 and st2["converged"] == 1
-    for tile in (1, 64):
-        # more, smaller work items: the per-item partial sums of the fused
-        # Lanczos epilogue follow the split; a NaN workspace shows that every
-        # slot the solver reads is written first
-        S.set_tuning(0, 0, 0, 0, tile)
+    for tile, order in ((1, 0), (64, 0), (64, 1)):
+        # more, smaller work items, and the padded XCD-dealt list: the
+        # per-item partial sums of the fused Lanczos epilogue follow the split;
+        # a NaN workspace shows that every slot the solver reads is written
+        # first and that padding writes none
+        S.set_tuning(0, 0, order, 0, tile)
         ws = torch.full((S.lanczos_workspace(100),), float("nan"), dtype=torch.float64, device=dev)
         e3, st3, _ = S.lanczos(v0, 100, fixed_steps=True, workspace=ws)
-        assert st3["steps"] == 100 and abs(e3 - e_ref) <= 1e-10, (tile, e3, e_ref)
+        assert st3["steps"] == 100 and abs(e3 - e_ref) <= 1e-10, (tile, order, e3, e_ref)
 
 
 def test_lanczos_hubbard12_vs_oracle(dev):

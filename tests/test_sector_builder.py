@@ -192,6 +192,10 @@ def test_spin_tile_tuning_host():
         assert S.lanczos_workspace(40) == ws
     for bad in (-1, 513, 4096):
         assert _status(lambda: S.set_tuning(0, 0, 0, 0, bad)) == E.ECUT_EINVAL
+    S.set_tuning(0, 0, 1, 0, 128)                # segments dealt to the XCDs
+    assert S.get_tuning()["row_order"] == 1 and S.lanczos_workspace(40) == ws
+    assert _status(lambda: S.set_tuning(0, 0, 2, 0, 0)) == E.ECUT_EINVAL
+    S.set_tuning(0, 0, 0, 0, 0)
     assert S.get_tuning()["tile"] == 0          # a rejected tuning changes nothing
     # problems that do not run the spin kernel take no tile
     H = E.Sectors.from_problem(I.hubbard12(), host_only=True)
