@@ -29,7 +29,7 @@ constexpr int SPIN_M = 13;                   // element slots per thread of the 
 constexpr int SPIN_TILE = SPIN_THREADS * SPIN_M;
 constexpr int SPIN_MAX_FLIP = 64;            // flip-flop terms inside the right part
 constexpr int SPIN_MANY_THREADS = 256;       // kernel for items of several short rows
-constexpr int SPIN_MANY_TILE = 512;          // amplitudes per such item (small: many groups for small problems)
+constexpr int SPIN_MANY_TILE = 512;          // most amplitudes per such item: the default and largest tile
 constexpr int HUBROW_THREADS = 1024;
 constexpr int HUBROW_P = 7;                  // column pairs per thread of the whole-row Hubbard kernel
 constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;
