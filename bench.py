@@ -29,9 +29,12 @@ PEAK_HBM_GBS = 8000.0
 
 
 def kernel_source_hash():
+    """Hash of the sources that decide what a profiled kernel does: the
+    kernels, their constants and argument structs, and the work lists."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2605_07621_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("kernels.hip", "kernels.h", "ecut_internal.h", "sectors.cpp"):
+        with open(os.path.join(ROOT, "paper_2605_07621_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
