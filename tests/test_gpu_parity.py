@@ -295,15 +295,18 @@ def test_spin_tile_tunings_full_size(dev):
 
 
 def test_batch_mixed_kernels_bit_exact(dev):
-    """A batch that mixes spin-kernel problems, generic-kernel problems and
-    a spin problem tuned to the generic kernel runs each on its own kernel."""
+    """A batch that mixes spin-kernel problems, generic-kernel problems, a
+    spin problem tuned to the generic kernel, one on a padded XCD-dealt item
+    list and a Hubbard problem on segment tiles runs each on its own kernel."""
     import torch
     ecut = _ecut()
     probs = [I.heisenberg16(), I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", 0b111), 10),
-             _SPIN_CASES[-1], SMALL[3]]
+             _SPIN_CASES[-1], SMALL[3], I.heisenberg16(), I.hubbard12()]
     Ss = [ecut.Sectors.from_problem(p) for p in probs]
     assert Ss[0].info.kernel_flags & 4 and not Ss[1].info.kernel_flags & 4
     Ss[3].set_tuning(0, 0, 0, 1)
+    Ss[4].set_tuning(0, 0, 1, 0, 64)     # padded XCD-dealt item list, small tile
+    Ss[5].set_tuning(0, 8, 0, 5)         # Hubbard on segment tiles
     xs = [torch.from_numpy(I.psi(900 + k, S.dim)).to(dev) for k, S in enumerate(Ss)]
     alone = [S.apply(x) for S, x in zip(Ss, xs)]
     ys = [torch.empty_like(x) for x in xs]
