@@ -178,6 +178,65 @@ def test_apply_full_size_sampled_vs_oracle(dev, name):
             assert np.linalg.norm(yt - y) / np.linalg.norm(y) <= RTOL, t
 
 
+def test_cut_invariance_heisenberg16(dev):
+    """H*psi brought back to canonical order does not depend on where the
+    chain is cut: every cut 1|15 ... 15|1 gives the oracle's vector."""
+    p = I.heisenberg16()
+    s = O.Sector(p.model, p.n_up)
+    psi = I.psi(p.meta["seed"], s.n)
+    y_ref = s.apply(psi)
+    for k in range(1, 16):
+        S = _ecut().Sectors.from_problem(I.Problem(p.model, I.Cut("spatial", (1 << k) - 1), p.n_up))
+        _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"cut {k}|{16 - k}")
+
+
+def test_cut_invariance_j1j2_6x5_full_size(dev):
+    """At full size (155M amplitudes) the 6x5 J1-J2 apply gives the same
+    canonical vector for the x<=2 | x>=3 cut, its mirror, and a checkerboard
+    cut whose 49 nearest-neighbour bonds all cross it."""
+    import torch
+    p = I.j1j2_6x5()
+    full = (1 << 30) - 1
+    checker = sum(1 << (5 * x + y) for x in range(6) for y in range(5) if (x + y) % 2 == 0)
+    x = torch.from_numpy(I.psi(p.meta["seed"] + 9, math.comb(30, 15))).to(dev)
+    ref = None
+    for mask in (p.cut.left_mask, full ^ p.cut.left_mask, checker):
+        S = _ecut().Sectors.from_problem(I.Problem(p.model, I.Cut("spatial", mask), p.n_up))
+        assert S.info.kernel_flags & 4
+        xt = S.import_(x)
+        S.autotune(xt, torch.empty_like(xt))
+        y = S.export(S.apply(xt))
+        del xt
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = y
+            continue
+        err = (torch.linalg.vector_norm(y - ref) / torch.linalg.vector_norm(ref)).item()
+        assert err <= RTOL, (hex(mask), err)
+        del y
+
+
+def test_hubbard16_spin_flip_symmetry_full_size(dev):
+    """With N_up = N_dn the Hamiltonian is symmetric under exchanging the
+    spins, so H (Psi^T) = (H Psi)^T for the 12,870 x 12,870 canonical
+    amplitude matrix, in the autotuned launch configuration."""
+    import torch
+    p = I.hubbard16()
+    S = _ecut().Sectors.from_problem(p)
+    n = math.comb(16, 8)
+    x = torch.from_numpy(I.psi(p.meta["seed"] + 7, S.dim)).to(dev)
+    xi = S.import_(x)
+    S.autotune(xi, torch.empty_like(xi))
+    y = S.export(S.apply(xi)).view(n, n)
+    del xi
+    xt = x.view(n, n).t().contiguous().view(-1)
+    del x
+    yt = S.export(S.apply(S.import_(xt))).view(n, n)
+    torch.cuda.synchronize()
+    err = (torch.linalg.vector_norm(yt - y.t()) / torch.linalg.vector_norm(y)).item()
+    assert err <= RTOL, err
+
+
 def test_apply_is_deterministic_and_batch_bit_exact(dev):
     import torch
     ecut = _ecut()
