@@ -348,6 +348,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             A3.n_items = (int32_t)s->hub_items_ord.size();
             A3.xscale = P.xscale;
             A3.zcoef = P.zcoef;
+            A3.dscale = P.dscale;
             const int slab_grid = 8 * std::max(1, (n_cu / 8) * hub_blocks_per_cu(4, 0));
             e = launch_hub3(s, A3, grid, n_xcd, T.variant == 3, slab_grid, st);
         } else if (T.variant == 5 && s->hubseg_ok) {
@@ -361,6 +362,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             G.partials = P.partials;
             G.xscale = P.xscale;
             G.zcoef = P.zcoef;
+            G.dscale = P.dscale;
             e = launch_hubseg(s, G, grid, n_xcd == 1 ? 1 : 8, st);
         } else if (T.variant == 4 && s->hubrow_ok) {
             if (((uintptr_t)P.x | (uintptr_t)P.y | (uintptr_t)P.z) & 15)
@@ -413,6 +415,8 @@ ecut_status Staging::reserve(size_t bytes) {
     if (bytes <= cap && dev) return ECUT_OK;
     ecut_status st = wait();
     if (st != ECUT_OK) return st;
+    // kernels launched earlier may still read the old descriptors
+    if (dev && hipDeviceSynchronize() != hipSuccess) return fail(ECUT_EDEVICE, "hipDeviceSynchronize(descriptor buffer)");
     if (dev) hipFree(dev);
     if (host) hipHostFree(host);
     dev = host = nullptr;

@@ -123,6 +123,7 @@ struct Hub3Args {
     const double *z;
     double *partials;
     double xscale, zcoef, hop, u0;
+    const double *dscale;             // nullable: xscale = dscale[0], zcoef = dscale[1]
     const int32_t *hl_ptr, *hl_col;   // up-spin hop rows
     const double *hl_val;
     int32_t n_rows, pad_;
@@ -148,6 +149,7 @@ struct HubSegArgs {
     const double *z;
     double *partials;
     double xscale, zcoef, hop, u0;
+    const double *dscale;             // nullable: xscale = dscale[0], zcoef = dscale[1]
     const uint32_t *lwords;           // up words
     const int32_t *cls;               // [n_cls][8] as HubDev::cls (down classes)
     const int4 *seginfo;              // down segments, as Hub3Args
@@ -207,6 +209,7 @@ struct ProblemDev {
     const double *z;             // Lanczos: previous vector (nullable)
     double xscale;               // y = xscale * H x - zcoef * z
     double zcoef;
+    const double *dscale;        // nullable: the two factors are read from dscale[0], dscale[1]
     double *partials;            // Lanczos: per-item partial <x, y> (nullable)
 };
 

@@ -46,6 +46,12 @@ __device__ double block_sum(double v, double *red) {
 
 }  // namespace
 
+// Epilogue factors y = xscale H x - zcoef z: from the descriptor, or from
+// device memory when the Lanczos driver keeps them there.
+__device__ __forceinline__ double2 epi_factors(const double *dscale, double xscale, double zcoef) {
+    return dscale ? make_double2(dscale[0], dscale[1]) : make_double2(xscale, zcoef);
+}
+
 // ------------------------------------------------------------------------
 // Generic row-tile kernel: any cut, sector-changing cross terms, batches of
 // problems.  One work item = rows [row0,row1) of one block, staged in LDS
@@ -60,6 +66,7 @@ __global__ __launch_bounds__(ROWS_THREADS) void k_rows(const ProblemDev *__restr
         const ItemDev W = items[it];
         if (W.row1 <= W.row0) continue;   // padding of an XCD-dealt list
         const ProblemDev &P = probs ? probs[W.prob] : single;
+        const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
         const BlockDev B = P.blocks[W.block];
         const int dR = B.d_r;
         const int nrows = W.row1 - W.row0;
@@ -107,9 +114,9 @@ __global__ __launch_bounds__(ROWS_THREADS) void k_rows(const ProblemDev *__restr
                     acc += X.coef * P.x[S.offset + (int64_t)lp * S.d_r + rp];
                 }
             }
-            double yv = P.xscale * acc;
+            double yv = ef.x * acc;
             const int64_t gi = B.offset + (int64_t)l * dR + r;
-            if (P.z) yv -= P.zcoef * P.z[gi];
+            if (P.z) yv -= ef.y * P.z[gi];
             P.y[gi] = yv;
             part += xv * yv;
         }
@@ -133,6 +140,7 @@ __global__ __launch_bounds__(ROWS_THREADS) void k_rows(const ProblemDev *__restr
 template <bool UU, bool UT, bool W16>
 __global__ __launch_bounds__(HUB_THREADS) void k_hub(const ProblemDev P, const int32_t *__restrict__ rows, int n_rows,
                                                      int n_xcd, int per_xcd) {
+    const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[HUB_THREADS / 64];
     const HubDev &H = P.hub;
@@ -260,8 +268,8 @@ __global__ __launch_bounds__(HUB_THREADS) void k_hub(const ProblemDev P, const i
                     }
                 }
                 const int64_t gi = (int64_t)a * dR + r;
-                double y = P.xscale * (acc[c] + s);
-                if (P.z) y -= P.zcoef * P.z[gi];
+                double y = ef.x * (acc[c] + s);
+                if (P.z) y -= ef.y * P.z[gi];
                 P.y[gi] = y;
                 part += xv * y;
             }
@@ -293,6 +301,7 @@ __global__ __launch_bounds__(HUB_THREADS) void k_hub(const ProblemDev P, const i
 template <bool UU, bool UT>
 __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const HubItem *__restrict__ items,
                                                        int n_items, int n_xcd, int per_xcd) {
+    const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[HUB2_THREADS / 64];
     const HubDev &H = P.hub;
@@ -463,8 +472,8 @@ __global__ __launch_bounds__(HUB2_THREADS) void k_hub2(const ProblemDev P, const
                     }
                 }
                 const int64_t gi = (int64_t)row * dR + colv[u];
-                double y = P.xscale * (a + dg * xv);
-                if (P.z) y -= P.zcoef * P.z[gi];
+                double y = ef.x * (a + dg * xv);
+                if (P.z) y -= ef.y * P.z[gi];
                 P.y[gi] = y;
                 part += xv * y;
             }
@@ -503,6 +512,7 @@ __device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32
 // n_xcd == 1: plain grid stride.
 __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P, const int32_t *__restrict__ rows,
                                                               int n_rows, int dR, int n_xcd) {
+    const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
     extern __shared__ __align__(16) double xs[];
     __shared__ int32_t rl[256];
     __shared__ int32_t rh[256 * 9];
@@ -602,13 +612,13 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
                         both &= both - 1u;
                     }
                 }
-                yv[e] = P.xscale * ((e ? acc[m].y : acc[m].x) + d + dg * x0[e]);
+                yv[e] = ef.x * ((e ? acc[m].y : acc[m].x) + d + dg * x0[e]);
             }
             const int64_t gp = (int64_t)a * np + p;
             if (P.z) {
                 const double2 zz = ((const double2 *)P.z)[gp];
-                yv[0] -= P.zcoef * zz.x;
-                yv[1] -= P.zcoef * zz.y;
+                yv[0] -= ef.y * zz.x;
+                yv[1] -= ef.y * zz.y;
             }
             ((double2 *)P.y)[gp] = make_double2(yv[0], yv[1]);
             part += x0[0] * yv[0] + x0[1] * yv[1];
@@ -656,6 +666,7 @@ template <int NT, int M>
 __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                              const int32_t *rl, const int32_t *rh, const uint32_t *fm,
                                              const double *fc, int n_flip, double *red) {
+    const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
     const int tid = threadIdx.x;
     const int dR = B.d_r;
     const int l = W.row0;
@@ -751,9 +762,9 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
         }
         const double x0 = xs[e];
-        double yv = P.xscale * (acc[m] + a + dg * x0);
+        double yv = ef.x * (acc[m] + a + dg * x0);
         const int64_t gi = B.offset + (int64_t)l * dR + e;
-        if (P.z) yv -= P.zcoef * P.z[gi];
+        if (P.z) yv -= ef.y * P.z[gi];
         P.y[gi] = yv;
         part += x0 * yv;
     }
@@ -769,6 +780,7 @@ template <int NT, int M>
 __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                                const int32_t *rl, const int32_t *rh, const uint32_t *fm,
                                                const double *fc, int n_flip, double *red) {
+    const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
     const int tid = threadIdx.x;
     const int dR = B.d_r;
     const int n = (W.row1 - W.row0) * dR;
@@ -846,9 +858,9 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
             dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
         }
         const double x0 = xs[e];
-        double yv = P.xscale * (acc[m] + a + dg * x0);
+        double yv = ef.x * (acc[m] + a + dg * x0);
         const int64_t gi = B.offset + (int64_t)W.row0 * dR + e;
-        if (P.z) yv -= P.zcoef * P.z[gi];
+        if (P.z) yv -= ef.y * P.z[gi];
         P.y[gi] = yv;
         part += x0 * yv;
     }
@@ -953,6 +965,7 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_upslab(const double *__restric
 // ------------------------------------------------------------------------
 template <bool UP>
 __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const Hub3Args A) {
+    const double2 ef = epi_factors(A.dscale, A.xscale, A.zcoef);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[HUB3_THREADS / 64];
     const int hs = A.hs;
@@ -1099,8 +1112,8 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
             const uint32_t bw = ((uint32_t)sinf[s].y << A.h) | (uint32_t)li.x;
             const double dg = A.u0 * (double)__popc(aw & bw);
             const int64_t gi = (int64_t)it.row0 * dR + col_m[m];
-            double y = UP ? A.xscale * (A.hop * (acc[m] + dn) + dg * x0) : A.xscale * (acc[m] + A.hop * dn + dg * x0);
-            if (A.z) y -= A.zcoef * A.z[gi];
+            double y = UP ? ef.x * (A.hop * (acc[m] + dn) + dg * x0) : ef.x * (acc[m] + A.hop * dn + dg * x0);
+            if (A.z) y -= ef.y * A.z[gi];
             A.y[gi] = y;
             part += x0 * y;
         }
@@ -1128,6 +1141,7 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
 // the same panel, fetched into that XCD's L2 by their own item.
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(HUBSEG_THREADS, 4) void k_hubseg(const HubSegArgs A) {
+    const double2 ef = epi_factors(A.dscale, A.xscale, A.zcoef);
     extern __shared__ __align__(16) double xt[];
     __shared__ double red[HUBSEG_THREADS / 64];
     constexpr int M = HUBSEG_M;
@@ -1235,8 +1249,8 @@ __global__ __launch_bounds__(HUBSEG_THREADS, 4) void k_hubseg(const HubSegArgs A
             for (int q = 0; q < nu; ++q) dn += xt[rb + ul[1 + q] * Lp];
             const uint32_t aw = A.lwords[U.x + i];
             const double dg = A.u0 * (double)__popc(aw & bw);
-            double y = A.xscale * (A.hop * (acc[m] + dn) + dg * x0[m]);
-            if (A.z) y -= A.zcoef * A.z[off[m]];
+            double y = ef.x * (A.hop * (acc[m] + dn) + dg * x0[m]);
+            if (A.z) y -= ef.y * A.z[off[m]];
             A.y[off[m]] = y;
             part += x0[m] * y;
         }
@@ -1425,7 +1439,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_reduce(const VecJob *__restrict
     for (int i = threadIdx.x; i < J.n_partials; i += blockDim.x) s += J.partials[i];
     s = block_sum(s, red);
     if (threadIdx.x == 0) {
-        if (J.mode == 0) J.scalars[J.out] = J.scale * s;
+        if (J.mode == 0) J.scalars[J.out] = (J.dscale ? J.dscale[0] : J.scale) * s;
         else J.scalars[J.out] = s;
     }
 }
@@ -1439,7 +1453,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restr
         const int ci = chunk_idx[c];
         const int64_t i0 = (int64_t)ci * VEC_CHUNK;
         const int64_t i1 = i0 + VEC_CHUNK < J.n ? i0 + VEC_CHUNK : J.n;
-        const double a = J.scalars[J.coef_idx] * J.coef_mul;
+        const double a = J.scalars[J.coef_idx] * (J.dscale ? J.dscale[0] : J.coef_mul);
         double s = 0.0;
         for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
             const double v = J.y[i] - a * J.x[i];
@@ -1449,6 +1463,32 @@ __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restr
         s = block_sum(s, red);
         if (threadIdx.x == 0) J.partials[ci] = s;
     }
+}
+
+// Next-step factors of the Lanczos recurrence, one thread per solve: with
+// beta = |w| the next vector is w / beta, so the next apply scales by 1/beta
+// and subtracts beta s_j w_j.  A zero or non-finite beta makes the factors
+// non-finite; the host sees the breakdown in the copied scalars and stops the
+// solve.
+__global__ __launch_bounds__(64) void k_lz_next(const LzNextJob *__restrict__ jobs, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const LzNextJob J = jobs[i];
+    double *s = J.scal;
+    const double a = s[0], b2 = s[1];
+    const double beta = sqrt(b2 > 0.0 ? b2 : 0.0);
+    const double inv = 1.0 / beta;
+    s[LZ_Z] = J.start ? 0.0 : beta * s[LZ_S];
+    s[LZ_S] = inv;
+    if (J.scales) J.scales[J.slot] = inv;
+    J.out2[0] = a;
+    J.out2[1] = b2;
+}
+
+hipError_t launch_lz_next(const LzNextJob *jobs, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lz_next, dim3((n + 63) / 64), dim3(64), 0, st, jobs, n);
+    return hipGetLastError();
 }
 
 // Classical Gram-Schmidt, dot phase: partials[k * n_chunks + chunk] = <w_k, y> over the chunk.

@@ -94,11 +94,42 @@ struct Pack {
 };
 }  // namespace
 
-static ecut_status run_norm_jobs(std::vector<LzSolve *> &act, const std::vector<double *> &vecs, hipStream_t st,
-                                 Staging &stg) {
-    // scal[1] <- |v|^2 for each solve via an axpy with zero coefficient
+LzPipe::~LzPipe() {
+    for (Step &S : steps) {
+        if (S.ev) {
+            (void)hipEventSynchronize(S.ev);
+            (void)hipEventDestroy(S.ev);
+        }
+        if (S.dev) (void)hipFree(S.dev);
+        if (S.host) (void)hipHostFree(S.host);
+    }
+}
+
+// room for n solves in a free step slot (its previous copy has completed)
+static ecut_status step_reserve(LzPipe::Step &S, size_t n) {
+    if (!S.ev && hipEventCreateWithFlags(&S.ev, hipEventDisableTiming) != hipSuccess)
+        return fail(ECUT_EDEVICE, "hipEventCreate (lanczos step)");
+    if (n <= S.cap) return ECUT_OK;
+    if (S.dev) (void)hipFree(S.dev);
+    if (S.host) (void)hipHostFree(S.host);
+    S.dev = S.host = nullptr;
+    S.cap = 0;
+    size_t c = 64;
+    while (c < n) c *= 2;
+    if (hipMalloc(&S.dev, c * 2 * sizeof(double)) != hipSuccess) return fail(ECUT_ENOMEM, "hipMalloc(lanczos scalars)");
+    if (hipHostMalloc(&S.host, c * 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return fail(ECUT_ENOMEM, "hipHostMalloc(lanczos scalars)");
+    S.cap = c;
+    return ECUT_OK;
+}
+
+// |v|^2 of each start vector into scal[1], then the first scale 1/|v| and a
+// zero previous-vector coefficient on the device (k_lz_next, start mode)
+static ecut_status run_start_jobs(std::vector<LzSolve *> &act, const std::vector<double *> &vecs, hipStream_t st,
+                                  Staging &stg) {
     std::vector<VecJob> jn, jr;
     std::vector<int32_t> cj, ci;
+    std::vector<LzNextJob> jl;
     for (size_t k = 0; k < act.size(); ++k) {
         LzSolve &L = *act[k];
         VecJob J{};
@@ -118,9 +149,10 @@ static ecut_status run_norm_jobs(std::vector<LzSolve *> &act, const std::vector<
         R.scalars = L.scal;
         R.out = 1;
         jr.push_back(R);
+        jl.push_back(LzNextJob{L.scal, L.scal + 8, L.reorth ? L.dscale : nullptr, 0, 1});
     }
     Pack P;
-    size_t o_jn = P.put(jn), o_jr = P.put(jr), o_cj = P.put(cj), o_ci = P.put(ci);
+    size_t o_jn = P.put(jn), o_jr = P.put(jr), o_cj = P.put(cj), o_ci = P.put(ci), o_jl = P.put(jl);
     ecut_status rs = stg.reserve(P.buf.size());
     if (rs != ECUT_OK) return rs;
     rs = stg.wait();
@@ -132,19 +164,13 @@ static ecut_status run_norm_jobs(std::vector<LzSolve *> &act, const std::vector<
     hipError_t e = launch_axpy_norm((const VecJob *)(d + o_jn), (const int32_t *)(d + o_cj), (const int32_t *)(d + o_ci),
                                     (int)cj.size(), st);
     if (e == hipSuccess) e = launch_reduce((const VecJob *)(d + o_jr), (int)jr.size(), st);
-    if (e != hipSuccess) return hip_fail(e, "lanczos norm");
-    for (LzSolve *L : act) {
-        e = hipMemcpyAsync(L->host_scal, L->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(scalars)");
-    }
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (lanczos norm)");
-    stg.pending = false;
+    if (e == hipSuccess) e = launch_lz_next((const LzNextJob *)(d + o_jl), (int)jl.size(), st);
+    if (e != hipSuccess) return hip_fail(e, "lanczos start");
     return ECUT_OK;
 }
 
 ecut_status lz_start(std::vector<LzSolve *> &solves, const std::vector<const double *> &v0, hipStream_t st,
-                     Staging &stg) {
+                     Staging &stg, bool host_norm) {
     std::vector<double *> xs;
     std::vector<LzSolve *> act;
     for (size_t k = 0; k < solves.size(); ++k) {
@@ -158,25 +184,26 @@ ecut_status lz_start(std::vector<LzSolve *> &solves, const std::vector<const dou
             hipError_t e = hipMemcpyAsync(x0, v0[k], sizeof(double) * (size_t)L.n, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(v0)");
         }
-        static const double zero[2] = {0.0, 0.0};
-        hipError_t e = hipMemcpyAsync(L.scal, zero, sizeof(zero), hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(scal init)");
+        // alpha must read as zero in the norm pass (coefficient 0 * scal[0])
+        hipError_t e = hipMemsetAsync(L.scal, 0, 16 * sizeof(double), st);
+        if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(scal init)");
         xs.push_back(x0);
         act.push_back(&L);
     }
-    ecut_status rs = run_norm_jobs(act, xs, st, stg);
-    if (rs != ECUT_OK) return rs;
+    ecut_status rs = run_start_jobs(act, xs, st, stg);
+    if (rs != ECUT_OK || !host_norm) return rs;
     for (LzSolve *L : act) {
-        const double nrm = std::sqrt(L->host_scal[1]);
+        double h[2] = {0.0, 0.0};
+        hipError_t e = hipMemcpyAsync(h, L->scal + 8, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "lanczos start norm");
+        const double nrm = std::sqrt(std::max(h[1], 0.0));
         if (!(nrm > 0.0) || !std::isfinite(nrm)) {
             L->done = true;
             L->status = fail(ECUT_EINVAL, "start vector is zero or not finite");
             continue;
         }
-        L->s_cur = 1.0 / nrm;
-        L->s_prev = 0.0;
-        L->beta_prev = 0.0;
-        L->sc.push_back(L->s_cur);
+        L->sc.push_back(1.0 / nrm);   // the scale k_lz_next set on the device
     }
     return ECUT_OK;
 }
@@ -204,12 +231,24 @@ ecut_status lz_ritz_vector(LzSolve &L, double *out, hipStream_t st, Staging &stg
     return ECUT_OK;
 }
 
-ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg) {
+bool lz_can_launch(const LzSolve &L) {
+    if (L.done) return false;
+    if (L.reorth && L.pending > 0) return false;   // a restart may follow each step
+    const int limit = L.fixed ? L.max_steps : L.max_steps * (L.max_restarts + 1);
+    return L.total + L.pending < limit;
+}
+
+ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t st, Staging &stg) {
+    if (pipe.n >= LzPipe::DEPTH) return fail(ECUT_EINVAL, "Lanczos pipe full");
     std::vector<LzSolve *> act;
     for (LzSolve *L : solves)
-        if (!L->done) act.push_back(L);
+        if (lz_can_launch(*L)) act.push_back(L);
     if (act.empty()) return ECUT_OK;
-    // 1. u = s_j H w_j - beta_{j-1} s_{j-1} w_{j-1}, alpha partials
+    LzPipe::Step &S = pipe.steps[(pipe.head + pipe.n) % LzPipe::DEPTH];
+    ecut_status rs = step_reserve(S, act.size());
+    if (rs != ECUT_OK) return rs;
+    // 1. u = s_j H w_j - beta_{j-1} s_{j-1} w_{j-1}, alpha partials; the two
+    //    factors are read on the device from scal[LZ_S], scal[LZ_Z]
     std::vector<ProblemDev> rows_probs;
     std::vector<const ecut_sectors *> rows_s;
     std::vector<ItemDev> rows_items;
@@ -219,11 +258,10 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         P.x = xvec(*L);
         P.y = yvec(*L);
         P.z = zvec(*L);
-        P.xscale = L->s_cur;
-        P.zcoef = L->beta_prev * L->s_prev;
+        P.dscale = L->scal + LZ_S;
         P.partials = L->part_apply;
         if (L->s->kernel == 1 || act.size() == 1) {
-            ecut_status rs = launch_apply(L->s, P, st);
+            rs = launch_apply(L->s, P, st);
             if (rs != ECUT_OK) return rs;
         } else {
             const int32_t pi = (int32_t)rows_probs.size();
@@ -240,12 +278,13 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
             const int64_t wb = (int64_t)(b.row1 - b.row0) * rows_s[b.prob]->blocks[b.block].d_r;
             return wa > wb;
         });
-        ecut_status rs = batch_launch_rows(rows_probs, rows_items, rows_tiles, st);
+        rs = batch_launch_rows(rows_probs, rows_items, rows_tiles, st);
         if (rs != ECUT_OK) return rs;
     }
-    // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2
+    // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2; 5. next factors
     std::vector<VecJob> ja, jx, jb;
     std::vector<int32_t> cj, ci;
+    std::vector<LzNextJob> jl;
     for (size_t k = 0; k < act.size(); ++k) {
         LzSolve &L = *act[k];
         VecJob A{};
@@ -255,7 +294,7 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         A.mode = 0;
         A.scalars = L.scal;
         A.out = 0;
-        A.scale = L.s_cur;
+        A.dscale = L.scal + LZ_S;
         ja.push_back(A);
         VecJob X{};
         X.x = xvec(L);
@@ -264,7 +303,7 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         X.partials = L.part_norm;
         X.scalars = L.scal;
         X.coef_idx = 0;
-        X.coef_mul = L.s_cur;
+        X.dscale = L.scal + LZ_S;
         jx.push_back(X);
         for (int32_t c = 0; c < L.n_chunks; ++c) { cj.push_back((int32_t)k); ci.push_back(c); }
         VecJob B{};
@@ -274,13 +313,14 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         B.scalars = L.scal;
         B.out = 1;
         jb.push_back(B);
+        jl.push_back(LzNextJob{L.scal, S.dev + 2 * k, L.reorth ? L.dscale : nullptr, L.j + 1, 0});
     }
     Pack P;
-    const size_t o_ja = P.put(ja), o_jx = P.put(jx), o_jb = P.put(jb), o_cj = P.put(cj), o_ci = P.put(ci);
-    size_t o_sc = 0, o_n0 = 0, o_n1 = 0;
+    const size_t o_ja = P.put(ja), o_jx = P.put(jx), o_jb = P.put(jb), o_cj = P.put(cj), o_ci = P.put(ci),
+                 o_jl = P.put(jl);
+    size_t o_n0 = 0, o_n1 = 0;
     LzSolve *R = (act.size() == 1 && act[0]->reorth) ? act[0] : nullptr;
     if (R) {
-        o_sc = P.put(R->sc);
         // squared norm of w before (scal[2]) and after (scal[3]) the first projection
         std::vector<VecJob> n0(1), n1(1);
         n0[0].partials = R->part_norm;
@@ -293,7 +333,7 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         o_n0 = P.put(n0);
         o_n1 = P.put(n1);
     }
-    ecut_status rs = stg.reserve(P.buf.size());
+    rs = stg.reserve(P.buf.size());
     if (rs != ECUT_OK) return rs;
     rs = stg.wait();
     if (rs != ECUT_OK) return rs;
@@ -307,15 +347,14 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
                              (int)cj.size(), st);
     if (e != hipSuccess) return hip_fail(e, "lanczos update");
     if (R) {
-        // classical Gram-Schmidt against w_0..w_j (v_k = s_k w_k); the second
-        // pass runs only when the first one removed more than half of the
-        // squared norm (decided on the device).  Every pass leaves the norm
-        // partials of its result in part_norm, so beta^2 below is the norm of
-        // the vector actually kept.
+        // classical Gram-Schmidt against w_0..w_j (v_k = s_k w_k, the scales
+        // kept on the device by k_lz_next); the second pass runs only when the
+        // first one removed more than half of the squared norm (decided on
+        // the device).  Every pass leaves the norm partials of its result in
+        // part_norm, so beta^2 below is the norm of the vector actually kept.
         const int nv = R->j + 1;
         if (nv > MAX_BASIS) return fail(ECUT_EUNSUPPORTED, "too many basis vectors");
-        e = hipMemcpyAsync(R->dscale, d + o_sc, sizeof(double) * R->sc.size(), hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = launch_reduce((const VecJob *)(d + o_n0), 1, st);
+        e = launch_reduce((const VecJob *)(d + o_n0), 1, st);
         const double *gate = R->scal + 4;
         for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
             const double *g = pass == 1 ? gate : nullptr;
@@ -330,18 +369,35 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
         if (e != hipSuccess) return hip_fail(e, "reorthogonalisation");
     }
     e = launch_reduce((const VecJob *)(d + o_jb), (int)jb.size(), st);
+    if (e == hipSuccess) e = launch_lz_next((const LzNextJob *)(d + o_jl), (int)jl.size(), st);
+    if (e == hipSuccess) e = hipMemcpyAsync(S.host, S.dev, 2 * sizeof(double) * act.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(S.ev, st);
     if (e != hipSuccess) return hip_fail(e, "lanczos beta");
+    S.solves = act;
     for (LzSolve *L : act) {
-        e = hipMemcpyAsync(L->host_scal, L->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(scalars)");
+        ++L->pending;
+        ++L->j;
     }
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize (lanczos step)");
-    stg.pending = false;
-    // 5. host: tridiagonal eigenproblem and convergence
-    for (LzSolve *L : act) {
-        const double alpha = L->host_scal[0];
-        const double beta = std::sqrt(std::max(L->host_scal[1], 0.0));
+    ++pipe.n;
+    return ECUT_OK;
+}
+
+ecut_status lz_finish(LzPipe &pipe, hipStream_t st, Staging &stg) {
+    if (pipe.n == 0) return ECUT_OK;
+    LzPipe::Step &S = pipe.steps[pipe.head];
+    hipError_t e = hipEventSynchronize(S.ev);
+    pipe.head = (pipe.head + 1) % LzPipe::DEPTH;
+    --pipe.n;
+    std::vector<LzSolve *> act;
+    act.swap(S.solves);
+    for (LzSolve *L : act) --L->pending;
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize (lanczos step)");
+    // host: tridiagonal eigenproblem and convergence
+    for (size_t k = 0; k < act.size(); ++k) {
+        LzSolve *L = act[k];
+        if (L->done) continue;   // a step launched before the solve was seen to stop
+        const double alpha = S.host[2 * k];
+        const double beta = std::sqrt(std::max(S.host[2 * k + 1], 0.0));
         if (!std::isfinite(alpha) || !std::isfinite(beta)) {
             L->done = true;
             L->status = fail(ECUT_EDEVICE, "non-finite Lanczos coefficient");
@@ -382,17 +438,19 @@ ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg
             ++L->restarts;
             std::vector<LzSolve *> one{L};
             std::vector<const double *> v0{slot(*L, 0)};
-            r2 = lz_start(one, v0, st, stg);
+            r2 = lz_start(one, v0, st, stg, true);
             if (r2 != ECUT_OK) return r2;
             continue;
         }
-        L->s_prev = L->s_cur;
-        L->s_cur = 1.0 / beta;
-        L->beta_prev = beta;
-        L->sc.push_back(L->s_cur);
-        ++L->j;
+        if (L->reorth) L->sc.push_back(1.0 / beta);   // the scale k_lz_next set on the device
     }
     return ECUT_OK;
+}
+
+ecut_status lz_step(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t st, Staging &stg) {
+    ecut_status rs = lz_launch(solves, pipe, st, stg);
+    while (rs == ECUT_OK && pipe.n > 0) rs = lz_finish(pipe, st, stg);
+    return rs;
 }
 
 // Final energy: all eigenvalues of T by implicit QL; the per-step bisection
@@ -438,12 +496,28 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
     L.tol = opts->tol;
     std::vector<LzSolve *> v{&L};
     std::vector<const double *> v0{v0_d};
-    ecut_status rs = lz_start(v, v0, st, stg);
+    ecut_status rs = lz_start(v, v0, st, stg, true);
     if (rs != ECUT_OK) return rs;
     if (L.done) return L.status;
-    while (!L.done) {
-        rs = lz_step(v, st, stg);
-        if (rs != ECUT_OK) return rs;
+    // three-term solves keep two steps in flight: the host processes step j
+    // while the device runs step j + 1 (its factors are set on the device),
+    // so a converged solve runs one extra step whose result is dropped
+    {
+        LzPipe pipe;
+        while (!L.done || pipe.n > 0) {
+            if (!L.done && pipe.n < LzPipe::DEPTH && lz_can_launch(L)) {
+                rs = lz_launch(v, pipe, st, stg);
+            } else if (pipe.n > 0) {
+                rs = lz_finish(pipe, st, stg);
+            } else {
+                L.done = true;   // no step left to launch: the budget ends the solve
+                L.status = L.fixed ? ECUT_OK : ECUT_ENOTCONV;
+            }
+            if (rs != ECUT_OK) {
+                (void)hipStreamSynchronize(st);
+                return rs;
+            }
+        }
     }
     if (L.status != ECUT_OK && L.status != ECUT_ENOTCONV) return L.status;
     *energy = final_energy(L);

@@ -25,28 +25,52 @@ struct LzSolve {
     double *part_cgs = nullptr;   // reorth: keep x n_chunks
     double *dcoef = nullptr;      // reorth: MAX_BASIS
     double *dscale = nullptr;     // reorth: MAX_BASIS
-    double *scal = nullptr;       // device: alpha, beta^2
+    double *scal = nullptr;       // device scalars, see LZ_S / LZ_Z in kernels.h
     // host state
     int j = 0, total = 0, restarts = 0, max_steps = 0, max_restarts = 0;
+    int pending = 0;              // launched steps not yet processed
     bool fixed = false;
     double tol = 0.0;
-    double s_cur = 1.0, s_prev = 0.0, beta_prev = 0.0;
-    std::vector<double> a, b, sc;
+    std::vector<double> a, b, sc; // tridiagonal matrix; sc: scales of the basis vectors (reorth)
     double energy = 0.0, e_prev = 0.0, residual = 0.0;
     bool done = false;
     ecut_status status = ECUT_OK;
-    double host_scal[2] = {0.0, 0.0};
+};
+
+// Steps in flight: each holds the solves it advanced and pinned host room for
+// their alpha, |w|^2, filled by one device-to-host copy and marked by an event.
+struct LzPipe {
+    struct Step {
+        std::vector<LzSolve *> solves;
+        double *dev = nullptr;    // 2 doubles per solve, written by k_lz_next
+        double *host = nullptr;   // pinned copy
+        size_t cap = 0;           // solves
+        hipEvent_t ev = nullptr;
+    };
+    static constexpr int DEPTH = 2;
+    Step steps[DEPTH];
+    int head = 0, n = 0;          // oldest in-flight step, steps in flight
+    ~LzPipe();
 };
 
 // doubles of device workspace for one solve
 size_t lz_workspace_doubles(const ecut_sectors *s, bool reorth, int keep);
 // carve the workspace (ws: lz_workspace_doubles doubles)
 void lz_carve(LzSolve &L, const ecut_sectors *s, bool reorth, int keep, double *ws);
-// start: x slot <- v0 (device, dim), computes the first scale; synchronises st
+// start: x slot <- v0 (device, dim); the first scale 1/|v0| is set on the
+// device.  host_norm: also synchronise st and check |v0| on the host (needed
+// for the reorthogonalisation scales and to reject a zero start vector).
 ecut_status lz_start(std::vector<LzSolve *> &solves, const std::vector<const double *> &v0, hipStream_t st,
-                     Staging &stg);
-// one Lanczos step for every solve that is not done; synchronises st
-ecut_status lz_step(std::vector<LzSolve *> &solves, hipStream_t st, Staging &stg);
+                     Staging &stg, bool host_norm);
+// true while a solve may take another step (not done, step budget left)
+bool lz_can_launch(const LzSolve &L);
+// enqueue one step for every solve that may take one (needs a free pipe slot)
+ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t st, Staging &stg);
+// wait for the oldest step in flight and process its scalars on the host
+// (convergence, breakdown, restarts); solves already done ignore it
+ecut_status lz_finish(LzPipe &pipe, hipStream_t st, Staging &stg);
+// one step, launched and finished (synchronises st)
+ecut_status lz_step(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t st, Staging &stg);
 // lowest eigenvalue of the final tridiagonal matrix by implicit QL
 double final_energy(const LzSolve &L);
 // ground-state Ritz vector of the current cycle into out (reorth only)

@@ -150,6 +150,7 @@ static size_t footprint(const ecut_sectors *s) { return lz_workspace_doubles(s, 
 void ecut_server::run() {
     hipSetDevice(device);
     std::vector<std::unique_ptr<Active>> active;
+    LzPipe pipe;   // batched steps in flight (two: the host processes one while the device runs the next)
     const int max_active = opts.max_active > 0 ? opts.max_active : 1 << 30;
     while (true) {
         // ---- admission
@@ -223,24 +224,35 @@ void ecut_server::run() {
                 ls.push_back(&A->L);
                 v0.push_back(A->L.ring[0]);
             }
-            if (st == ECUT_OK) st = lz_start(ls, v0, stream, stg);
+            if (st == ECUT_OK) st = lz_start(ls, v0, stream, stg, false);
         }
-        // ---- one batched step
+        // ---- one batched step launched, the oldest one in flight processed
         if (st == ECUT_OK && !active.empty()) {
             std::vector<LzSolve *> ls;
-            for (auto &A : active) ls.push_back(&A->L);
-            st = lz_step(ls, stream, stg);
+            bool any = false;
+            for (auto &A : active) {
+                ls.push_back(&A->L);
+                any = any || lz_can_launch(A->L);
+            }
+            const int before = pipe.n;
+            if (any && pipe.n < LzPipe::DEPTH) st = lz_launch(ls, pipe, stream, stg);
+            if (st == ECUT_OK && (pipe.n == LzPipe::DEPTH || (pipe.n == before && pipe.n > 0))) st = lz_finish(pipe, stream, stg);
+            if (st == ECUT_OK && pipe.n == 0)
+                for (auto &A : active)
+                    if (!A->L.done && !lz_can_launch(A->L)) A->L.done = true, A->L.status = ECUT_ENOTCONV;
         }
         if (st != ECUT_OK) {
+            (void)hipStreamSynchronize(stream);
+            while (pipe.n > 0) (void)lz_finish(pipe, stream, stg);
             std::lock_guard<std::mutex> g(mu);
             worker_status = st;
-            for (auto &A : active) A->L.done = true, A->L.status = st;
+            for (auto &A : active) A->L.done = true, A->L.status = st, A->L.pending = 0;
         }
         // ---- retire
         std::vector<ecut_result> out;
         for (auto it = active.begin(); it != active.end();) {
             Active &A = **it;
-            if (!A.L.done) { ++it; continue; }
+            if (!A.L.done || A.L.pending > 0) { ++it; continue; }   // retire once no step of it is in flight
             ecut_result r{};
             r.req_id = A.req->id;
             r.status = A.L.status;
