@@ -296,7 +296,9 @@ typedef struct ecut_lanczos_opts {
 } ecut_lanczos_opts;
 
 typedef struct ecut_lanczos_stats {
-    int32_t steps;            /* total matvecs */
+    int32_t steps;            /* steps in the tridiagonal matrix (one matvec each); with tol and
+                                 no reorthogonalisation one more matvec runs after convergence
+                                 and is not counted */
     int32_t restarts;
     int32_t converged;
     int32_t reserved;
@@ -316,7 +318,13 @@ typedef struct ecut_lanczos_stats {
  *            doubles.
  *   gs_d:    optional (nullable) output ground-state vector (dim); needs reorth=1.
  *   energy:  host output.  stats: nullable host output.
- * Synchronises the stream (one small device-to-host copy per step).
+ * The factors of each step (1/beta_j for the next vector, beta_j s_j for the
+ * previous one, with v_j = s_j w_j kept unnormalised) are computed on the
+ * device.  Without reorthogonalisation two steps are in flight: the host
+ * reads alpha_j, beta_j of step j (one small device-to-host copy per step)
+ * while the device runs step j + 1, and drops that step if step j ends the
+ * solve.  With reorthogonalisation one step is in flight (a restart may
+ * follow).  Synchronises the stream before returning.
  * Returns ECUT_ENOTCONV (with energy set) if tol was not reached.
  */
 size_t ecut_lanczos_workspace(const ecut_sectors *s, const ecut_lanczos_opts *opts);
@@ -331,8 +339,10 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
  * Requests are admitted when their footprint (sector metadata + Lanczos
  * vectors) fits the free arena and a slot is free; all admitted solves
  * advance together, one batched H*psi launch and one batched vector-update
- * launch per step; a solve leaves the batch when converged (tol) or at
- * max_steps, freeing its memory for the next admission.
+ * launch per step, with two steps in flight (the host checks the solves of
+ * step j while the device runs step j + 1); a solve leaves the batch when
+ * converged (tol) or at max_steps, freeing its memory for the next admission
+ * once no step of it is in flight.
  * ------------------------------------------------------------------------- */
 typedef struct ecut_server ecut_server;
 
@@ -340,7 +350,8 @@ typedef struct ecut_server_opts {
     int32_t max_active;       /* slots; 0 = unlimited */
     int32_t max_steps;        /* per request */
     double tol;               /* energy tolerance per request (as ecut_lanczos_opts.tol) */
-    int32_t sequential;       /* 1: one request at a time through ecut_lanczos_ground_state (baseline) */
+    int32_t sequential;       /* 1: one request at a time (max_active forced to 1), the
+                                 one-at-a-time baseline on the same engine */
     int32_t use_graph;        /* must be 0: replaying the step as a captured HIP graph is not built
                                  (the vectors of a solve rotate every step, so the arguments change);
                                  1 gives ECUT_EUNSUPPORTED */

@@ -4,7 +4,10 @@
 //   optional classical Gram-Schmidt against all stored vectors, with a
 //   second pass when the first loses more than half the squared norm
 // Vectors are kept unnormalised (v_j = s_j w_j) so no scaling pass is needed;
-// the scales enter the next H*psi and the updates as factors.  On the host,
+// the scales enter the next H*psi and the updates as factors, which a small
+// kernel derives from beta_j on the device, so the host need not answer
+// before the next step is launched: three-term solves keep two steps in
+// flight and the host processes step j while step j + 1 runs.  On the host,
 // every step takes the lowest Ritz value of the tridiagonal matrix by Sturm
 // bisection from the previous one (O(m)) and its eigenvector by inverse
 // iteration for the residual beta_j |u_j|; implicit QL on the final matrix

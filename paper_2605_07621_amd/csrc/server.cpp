@@ -4,14 +4,18 @@
 // bytes.  Each step it
 //   1. admits queued requests (FIFO, arrival time reached) while a slot is
 //      free and the request's Lanczos workspace fits the free arena;
-//   2. advances every admitted solve by one Lanczos step: one batched H*psi
+//   2. launches one Lanczos step of every admitted solve: one batched H*psi
 //      launch over the sector work queue of all generic-kernel problems (plus
 //      the Hubbard up/down kernel per Hubbard problem), one batched alpha
-//      reduction, one batched update+norm pass and one batched beta
-//      reduction, then one synchronisation for all alpha/beta values;
-//   3. retires converged solves, freeing their arena space and slot.
+//      reduction, one batched update+norm pass, one batched beta reduction
+//      and the next step's factors, all on the device, then one copy of all
+//      alpha/beta values to pinned host memory;
+//   3. with two steps in flight, waits for the older one and checks its
+//      solves (convergence, breakdown) while the device runs the newer one;
+//   4. retires finished solves once no step of theirs is in flight, freeing
+//      their arena space and slot.
 // With max_active = 1 the same loop is the sequential baseline: one request
-// at a time on the plain single-solve path.
+// at a time on the same engine.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
