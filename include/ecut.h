@@ -293,6 +293,11 @@ typedef struct ecut_lanczos_opts {
                                  over the last step and its residual beta_j |s_j| <= 0.01 sqrt(tol)
                                  (the energy error of a Ritz value is of the order of the squared
                                  residual over the spectral gap) */
+    int32_t use_graph;        /* 1: replay the steps of a three-term solve (after the first) from
+                                 HIP graphs captured once per ring phase, so a step costs one graph
+                                 launch on the host; 0: launch every kernel each step.  Same results
+                                 bit for bit.  With the null stream the solve runs on a private
+                                 stream ordered after the caller's work */
 } ecut_lanczos_opts;
 
 typedef struct ecut_lanczos_stats {
@@ -352,9 +357,10 @@ typedef struct ecut_server_opts {
     double tol;               /* energy tolerance per request (as ecut_lanczos_opts.tol) */
     int32_t sequential;       /* 1: one request at a time (max_active forced to 1), the
                                  one-at-a-time baseline on the same engine */
-    int32_t use_graph;        /* must be 0: replaying the step as a captured HIP graph is not built
-                                 (the vectors of a solve rotate every step, so the arguments change);
-                                 1 gives ECUT_EUNSUPPORTED */
+    int32_t use_graph;        /* 1: while the set of active solves stays the same, replay each
+                                 batched step from a HIP graph captured once per ring phase (a new
+                                 set drops the graphs); 0: launch every kernel each step.  Same
+                                 results bit for bit */
 } ecut_server_opts;
 
 typedef struct ecut_result {

@@ -466,43 +466,59 @@ void Staging::release() {
     device = -1;
 }
 
-ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items_in,
-                              const std::vector<int32_t> &tiles, hipStream_t st) {
-    static thread_local Staging S;
+void make_rows_batch(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items_in,
+                     const std::vector<int32_t> &tiles, RowsBatch &b) {
     // the spin kernel takes the problems whose tuning selects it (as their
     // own ecut_apply_H does), the generic row kernel the others; the order
     // of the queue is kept within each group
     std::vector<ItemDev> items;
     items.reserve(items_in.size());
-    int spin_tile = 0, spin_src = 0, rows_tile = 0, first_spin = -1;
+    b = RowsBatch{};
     for (const ItemDev &it : items_in)
         if (probs[it.prob].spin_ok) {
             items.push_back(it);
-            spin_tile = std::max(spin_tile, tiles[it.prob]);
-            spin_src = std::max(spin_src, probs[it.prob].max_d_r);
-            if (first_spin < 0) first_spin = it.prob;
+            b.spin_tile = std::max(b.spin_tile, tiles[it.prob]);
+            b.spin_src = std::max(b.spin_src, probs[it.prob].max_d_r);
+            if (b.first_spin < 0) b.first_spin = it.prob;
         }
-    const size_t n_spin = items.size();
+    b.n_spin = (int)items.size();
     for (const ItemDev &it : items_in)
         if (!probs[it.prob].spin_ok) {
             items.push_back(it);
-            rows_tile = std::max(rows_tile, tiles[it.prob]);
+            b.rows_tile = std::max(b.rows_tile, tiles[it.prob]);
         }
-    const size_t pb = (probs.size() * sizeof(ProblemDev) + 255) & ~(size_t)255;
-    const size_t bytes = pb + items.size() * sizeof(ItemDev);
-    ecut_status rs = S.reserve(bytes);
+    b.n_items = (int)items.size();
+    b.pb = (probs.size() * sizeof(ProblemDev) + 255) & ~(size_t)255;
+    b.buf.assign(b.pb + items.size() * sizeof(ItemDev), 0);
+    std::memcpy(b.buf.data(), probs.data(), probs.size() * sizeof(ProblemDev));
+    std::memcpy(b.buf.data() + b.pb, items.data(), items.size() * sizeof(ItemDev));
+    if (b.first_spin >= 0) b.spin_single = probs[b.first_spin];
+    if (!probs.empty()) b.rows_single = probs[0];
+}
+
+hipError_t launch_rows_batch(const RowsBatch &b, const void *dev, hipStream_t st) {
+    const ProblemDev *probs_d = (const ProblemDev *)dev;
+    const ItemDev *items_d = (const ItemDev *)((const char *)dev + b.pb);
+    hipError_t e = hipSuccess;
+    if (b.n_spin > 0) e = launch_spin(probs_d, b.spin_single, items_d, b.n_spin, b.spin_tile, b.spin_src, 0, st);
+    if (e == hipSuccess && b.n_spin < b.n_items)
+        e = launch_rows(probs_d, b.rows_single, items_d + b.n_spin, b.n_items - b.n_spin, b.rows_tile, st);
+    return e;
+}
+
+ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items_in,
+                              const std::vector<int32_t> &tiles, hipStream_t st) {
+    static thread_local Staging S;
+    RowsBatch b;
+    make_rows_batch(probs, items_in, tiles, b);
+    ecut_status rs = S.reserve(b.buf.size());
     if (rs != ECUT_OK) return rs;
     rs = S.wait();
     if (rs != ECUT_OK) return rs;
-    std::memcpy(S.host, probs.data(), probs.size() * sizeof(ProblemDev));
-    std::memcpy((char *)S.host + pb, items.data(), items.size() * sizeof(ItemDev));
-    hipError_t e = hipMemcpyAsync(S.dev, S.host, bytes, hipMemcpyHostToDevice, st);
+    std::memcpy(S.host, b.buf.data(), b.buf.size());
+    hipError_t e = hipMemcpyAsync(S.dev, S.host, b.buf.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
-    const ProblemDev *probs_d = (const ProblemDev *)S.dev;
-    const ItemDev *items_d = (const ItemDev *)((char *)S.dev + pb);
-    if (n_spin > 0) e = launch_spin(probs_d, probs[first_spin], items_d, (int)n_spin, spin_tile, spin_src, 0, st);
-    if (e == hipSuccess && n_spin < items.size())
-        e = launch_rows(probs_d, probs[0], items_d + n_spin, (int)(items.size() - n_spin), rows_tile, st);
+    e = launch_rows_batch(b, S.dev, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");
     e = hipEventRecord(S.ev, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");

@@ -15,6 +15,7 @@
 #include "lanczos.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -41,6 +42,8 @@ size_t lz_workspace_doubles(const ecut_sectors *s, bool reorth, int keep) {
 }
 
 void lz_carve(LzSolve &L, const ecut_sectors *s, bool reorth, int keep, double *ws) {
+    static std::atomic<uint64_t> next_uid{1};
+    L.uid = next_uid++;
     const int64_t n = s->dim;
     const int64_t nc = n_chunks_of(n);
     auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
@@ -241,15 +244,24 @@ bool lz_can_launch(const LzSolve &L) {
     return L.total + L.pending < limit;
 }
 
-ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t st, Staging &stg) {
-    if (pipe.n >= LzPipe::DEPTH) return fail(ECUT_EINVAL, "Lanczos pipe full");
+// Everything one step launches, with its descriptors packed in one buffer.
+namespace {
+struct StepPlan {
     std::vector<LzSolve *> act;
-    for (LzSolve *L : solves)
-        if (lz_can_launch(*L)) act.push_back(L);
-    if (act.empty()) return ECUT_OK;
-    LzPipe::Step &S = pipe.steps[(pipe.head + pipe.n) % LzPipe::DEPTH];
-    ecut_status rs = step_reserve(S, act.size());
-    if (rs != ECUT_OK) return rs;
+    std::vector<ProblemDev> own;              // problems launched on their own kernels
+    std::vector<const ecut_sectors *> own_s;
+    RowsBatch rows;                           // the others, one row-kernel queue
+    bool has_rows = false;
+    Pack P;
+    size_t o_rows = 0, o_ja = 0, o_jx = 0, o_jb = 0, o_cj = 0, o_ci = 0, o_jl = 0, o_n0 = 0, o_n1 = 0;
+    int n_ja = 0, n_cj = 0, n_jl = 0;
+    LzSolve *R = nullptr;                     // the one solve with reorthogonalisation, if any
+};
+}  // namespace
+
+// out2: device room for alpha, |w|^2 of every solve of the step
+static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan &pl) {
+    pl.act = act;
     // 1. u = s_j H w_j - beta_{j-1} s_{j-1} w_{j-1}, alpha partials; the two
     //    factors are read on the device from scal[LZ_S], scal[LZ_Z]
     std::vector<ProblemDev> rows_probs;
@@ -264,8 +276,8 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
         P.dscale = L->scal + LZ_S;
         P.partials = L->part_apply;
         if (L->s->kernel == 1 || act.size() == 1) {
-            rs = launch_apply(L->s, P, st);
-            if (rs != ECUT_OK) return rs;
+            pl.own.push_back(P);
+            pl.own_s.push_back(L->s);
         } else {
             const int32_t pi = (int32_t)rows_probs.size();
             rows_probs.push_back(P);
@@ -281,8 +293,9 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
             const int64_t wb = (int64_t)(b.row1 - b.row0) * rows_s[b.prob]->blocks[b.block].d_r;
             return wa > wb;
         });
-        rs = batch_launch_rows(rows_probs, rows_items, rows_tiles, st);
-        if (rs != ECUT_OK) return rs;
+        make_rows_batch(rows_probs, rows_items, rows_tiles, pl.rows);
+        pl.has_rows = true;
+        pl.o_rows = pl.P.put(pl.rows.buf);
     }
     // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2; 5. next factors
     std::vector<VecJob> ja, jx, jb;
@@ -316,40 +329,49 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
         B.scalars = L.scal;
         B.out = 1;
         jb.push_back(B);
-        jl.push_back(LzNextJob{L.scal, S.dev + 2 * k, L.reorth ? L.dscale : nullptr, L.j + 1, 0});
+        jl.push_back(LzNextJob{L.scal, out2 + 2 * k, L.reorth ? L.dscale : nullptr, L.j + 1, 0});
     }
-    Pack P;
-    const size_t o_ja = P.put(ja), o_jx = P.put(jx), o_jb = P.put(jb), o_cj = P.put(cj), o_ci = P.put(ci),
-                 o_jl = P.put(jl);
-    size_t o_n0 = 0, o_n1 = 0;
-    LzSolve *R = (act.size() == 1 && act[0]->reorth) ? act[0] : nullptr;
-    if (R) {
+    pl.o_ja = pl.P.put(ja);
+    pl.o_jx = pl.P.put(jx);
+    pl.o_jb = pl.P.put(jb);
+    pl.o_cj = pl.P.put(cj);
+    pl.o_ci = pl.P.put(ci);
+    pl.o_jl = pl.P.put(jl);
+    pl.n_ja = (int)ja.size();
+    pl.n_cj = (int)cj.size();
+    pl.n_jl = (int)jl.size();
+    pl.R = (act.size() == 1 && act[0]->reorth) ? act[0] : nullptr;
+    if (pl.R) {
         // squared norm of w before (scal[2]) and after (scal[3]) the first projection
         std::vector<VecJob> n0(1), n1(1);
-        n0[0].partials = R->part_norm;
-        n0[0].n_partials = R->n_chunks;
+        n0[0].partials = pl.R->part_norm;
+        n0[0].n_partials = pl.R->n_chunks;
         n0[0].mode = 1;
-        n0[0].scalars = R->scal;
+        n0[0].scalars = pl.R->scal;
         n0[0].out = 2;
         n1[0] = n0[0];
         n1[0].out = 3;
-        o_n0 = P.put(n0);
-        o_n1 = P.put(n1);
+        pl.o_n0 = pl.P.put(n0);
+        pl.o_n1 = pl.P.put(n1);
     }
-    rs = stg.reserve(P.buf.size());
-    if (rs != ECUT_OK) return rs;
-    rs = stg.wait();
-    if (rs != ECUT_OK) return rs;
-    std::memcpy(stg.host, P.buf.data(), P.buf.size());
-    rs = stg.upload(P.buf.size(), st);
-    if (rs != ECUT_OK) return rs;
-    char *d = (char *)stg.dev;
-    hipError_t e = launch_reduce((const VecJob *)(d + o_ja), (int)ja.size(), st);
+}
+
+// launches of a step; dev: a device copy of pl.P.buf
+static ecut_status enqueue_plan(const StepPlan &pl, const void *dev, hipStream_t st) {
+    for (size_t k = 0; k < pl.own.size(); ++k) {
+        ecut_status rs = launch_apply(pl.own_s[k], pl.own[k], st);
+        if (rs != ECUT_OK) return rs;
+    }
+    const char *d = (const char *)dev;
+    hipError_t e = hipSuccess;
+    if (pl.has_rows) e = launch_rows_batch(pl.rows, d + pl.o_rows, st);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");
+    e = launch_reduce((const VecJob *)(d + pl.o_ja), pl.n_ja, st);
     if (e == hipSuccess)
-        e = launch_axpy_norm((const VecJob *)(d + o_jx), (const int32_t *)(d + o_cj), (const int32_t *)(d + o_ci),
-                             (int)cj.size(), st);
+        e = launch_axpy_norm((const VecJob *)(d + pl.o_jx), (const int32_t *)(d + pl.o_cj), (const int32_t *)(d + pl.o_ci),
+                             pl.n_cj, st);
     if (e != hipSuccess) return hip_fail(e, "lanczos update");
-    if (R) {
+    if (LzSolve *R = pl.R) {
         // classical Gram-Schmidt against w_0..w_j (v_k = s_k w_k, the scales
         // kept on the device by k_lz_next); the second pass runs only when the
         // first one removed more than half of the squared norm (decided on
@@ -357,7 +379,7 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
         // part_norm, so beta^2 below is the norm of the vector actually kept.
         const int nv = R->j + 1;
         if (nv > MAX_BASIS) return fail(ECUT_EUNSUPPORTED, "too many basis vectors");
-        e = launch_reduce((const VecJob *)(d + o_n0), 1, st);
+        e = launch_reduce((const VecJob *)(d + pl.o_n0), 1, st);
         const double *gate = R->scal + 4;
         for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
             const double *g = pass == 1 ? gate : nullptr;
@@ -366,16 +388,109 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
             if (e == hipSuccess)
                 e = launch_multiaxpy(R->basis, basis_ld(*R), nv, R->dcoef, R->dscale, yvec(*R), R->n, R->part_norm,
                                      R->n_chunks, 1.0, st, g);
-            if (e == hipSuccess && pass == 0) e = launch_reduce((const VecJob *)(d + o_n1), 1, st);
+            if (e == hipSuccess && pass == 0) e = launch_reduce((const VecJob *)(d + pl.o_n1), 1, st);
             if (e == hipSuccess && pass == 0) e = launch_dgks_gate(R->scal, st);
         }
         if (e != hipSuccess) return hip_fail(e, "reorthogonalisation");
     }
-    e = launch_reduce((const VecJob *)(d + o_jb), (int)jb.size(), st);
-    if (e == hipSuccess) e = launch_lz_next((const LzNextJob *)(d + o_jl), (int)jl.size(), st);
-    if (e == hipSuccess) e = hipMemcpyAsync(S.host, S.dev, 2 * sizeof(double) * act.size(), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipEventRecord(S.ev, st);
+    e = launch_reduce((const VecJob *)(d + pl.o_jb), (int)pl.act.size(), st);
+    if (e == hipSuccess) e = launch_lz_next((const LzNextJob *)(d + pl.o_jl), pl.n_jl, st);
     if (e != hipSuccess) return hip_fail(e, "lanczos beta");
+    return ECUT_OK;
+}
+
+LzGraph::~LzGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (dev) (void)hipFreeAsync(dev, st);
+    if (dev_out) (void)hipFreeAsync(dev_out, st);
+}
+
+// capture one step of act (its current ring phases) as a graph
+static ecut_status capture_step(const std::vector<LzSolve *> &act, hipStream_t st, std::shared_ptr<LzGraph> &out) {
+    auto g = std::make_shared<LzGraph>();
+    g->st = st;
+    hipError_t e = hipMallocAsync((void **)&g->dev_out, 2 * sizeof(double) * act.size(), st);
+    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(graph scalars)");
+    StepPlan pl;
+    build_plan(act, g->dev_out, pl);
+    e = hipMallocAsync(&g->dev, pl.P.buf.size(), st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->dev, pl.P.buf.data(), pl.P.buf.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);   // the pageable source is released on return
+    if (e != hipSuccess) return hip_fail(e, "graph descriptors");
+    e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    ecut_status rs = enqueue_plan(pl, g->dev, st);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (rs != ECUT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rs;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    out = g;
+    return ECUT_OK;
+}
+
+ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t st, Staging &stg) {
+    if (pipe.n >= LzPipe::DEPTH) return fail(ECUT_EINVAL, "Lanczos pipe full");
+    std::vector<LzSolve *> act;
+    for (LzSolve *L : solves)
+        if (lz_can_launch(*L)) act.push_back(L);
+    if (act.empty()) return ECUT_OK;
+    LzPipe::Step &S = pipe.steps[(pipe.head + pipe.n) % LzPipe::DEPTH];
+    ecut_status rs = step_reserve(S, act.size());
+    if (rs != ECUT_OK) return rs;
+    // graph replay: three-term solves past their first step, launched by the
+    // previous step too (a new set of solves drops the captured graphs)
+    std::vector<uint64_t> who, key;
+    bool graph = pipe.use_graph && st != nullptr;
+    for (LzSolve *L : act) {
+        who.push_back(L->uid);
+        key.push_back(L->uid);
+        key.push_back((uint64_t)(L->j % 3));
+        graph = graph && !L->reorth && L->j >= 1;
+    }
+    if (who != pipe.last) {
+        pipe.graphs.clear();   // graphs of a launch still in flight live on in its step
+        pipe.last = who;
+        pipe.same = 0;
+    } else {
+        ++pipe.same;
+    }
+    graph = graph && pipe.same >= LzPipe::GRAPH_AFTER;
+    hipError_t e;
+    if (graph) {
+        std::shared_ptr<LzGraph> &g = pipe.graphs[key];
+        if (!g) {
+            rs = capture_step(act, st, g);
+            if (rs != ECUT_OK) return rs;
+            ++pipe.graph_captures;
+        }
+        ++pipe.graph_replays;
+        e = hipGraphLaunch(g->exec, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(S.host, g->dev_out, 2 * sizeof(double) * act.size(), hipMemcpyDeviceToHost, st);
+        S.graph = g;
+    } else {
+        StepPlan pl;
+        build_plan(act, S.dev, pl);
+        rs = stg.reserve(pl.P.buf.size());
+        if (rs != ECUT_OK) return rs;
+        rs = stg.wait();
+        if (rs != ECUT_OK) return rs;
+        std::memcpy(stg.host, pl.P.buf.data(), pl.P.buf.size());
+        rs = stg.upload(pl.P.buf.size(), st);
+        if (rs != ECUT_OK) return rs;
+        rs = enqueue_plan(pl, stg.dev, st);
+        if (rs != ECUT_OK) return rs;
+        e = hipMemcpyAsync(S.host, S.dev, 2 * sizeof(double) * act.size(), hipMemcpyDeviceToHost, st);
+        S.graph.reset();
+    }
+    if (e == hipSuccess) e = hipEventRecord(S.ev, st);
+    if (e != hipSuccess) return hip_fail(e, "lanczos step");
     S.solves = act;
     for (LzSolve *L : act) {
         ++L->pending;
@@ -393,6 +508,7 @@ ecut_status lz_finish(LzPipe &pipe, hipStream_t st, Staging &stg) {
     --pipe.n;
     std::vector<LzSolve *> act;
     act.swap(S.solves);
+    S.graph.reset();
     for (LzSolve *L : act) --L->pending;
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize (lanczos step)");
     // host: tridiagonal eigenproblem and convergence
@@ -491,6 +607,19 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
     static thread_local Staging stg;
+    if (opts->use_graph && !st) {
+        // graphs are captured on a stream of our own, ordered after the
+        // caller's work on the null stream; the call is synchronous anyway
+        static thread_local hipStream_t priv = nullptr;
+        static thread_local hipEvent_t after = nullptr;
+        hipError_t e = hipSuccess;
+        if (!priv) e = hipStreamCreateWithFlags(&priv, hipStreamNonBlocking);
+        if (e == hipSuccess && !after) e = hipEventCreateWithFlags(&after, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(after, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(priv, after, 0);
+        if (e != hipSuccess) return hip_fail(e, "lanczos stream");
+        st = priv;
+    }
     LzSolve L;
     lz_carve(L, s, opts->reorth != 0, opts->reorth ? opts->max_steps : 0, basis_d);
     L.max_steps = opts->max_steps;
@@ -507,6 +636,7 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
     // so a converged solve runs one extra step whose result is dropped
     {
         LzPipe pipe;
+        pipe.use_graph = opts->use_graph != 0;
         while (!L.done || pipe.n > 0) {
             if (!L.done && pipe.n < LzPipe::DEPTH && lz_can_launch(L)) {
                 rs = lz_launch(v, pipe, st, stg);

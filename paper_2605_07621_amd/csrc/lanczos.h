@@ -4,6 +4,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <map>
+#include <memory>
 #include <vector>
 
 #include "ecut_internal.h"
@@ -12,6 +15,7 @@
 namespace ecut {
 
 struct LzSolve {
+    uint64_t uid = 0;             // unique per carved solve, never reused (keys captured graphs)
     const ecut_sectors *s = nullptr;
     int64_t n = 0;
     bool reorth = false;
@@ -37,19 +41,41 @@ struct LzSolve {
     ecut_status status = ECUT_OK;
 };
 
+// One step of a fixed set of three-term solves at fixed ring phases, captured
+// as a HIP graph with its descriptors in device memory of its own; replaying
+// it needs no host work but the launch.
+struct LzGraph {
+    hipGraphExec_t exec = nullptr;
+    void *dev = nullptr;          // descriptors
+    double *dev_out = nullptr;    // alpha, |w|^2 per solve
+    hipStream_t st = nullptr;     // allocations are stream ordered on it
+    ~LzGraph();
+};
+
 // Steps in flight: each holds the solves it advanced and pinned host room for
 // their alpha, |w|^2, filled by one device-to-host copy and marked by an event.
 struct LzPipe {
     struct Step {
         std::vector<LzSolve *> solves;
-        double *dev = nullptr;    // 2 doubles per solve, written by k_lz_next
+        double *dev = nullptr;    // 2 doubles per solve, written by k_lz_next (eager steps)
         double *host = nullptr;   // pinned copy
         size_t cap = 0;           // solves
         hipEvent_t ev = nullptr;
+        std::shared_ptr<LzGraph> graph;   // a replayed step keeps its graph alive until finished
     };
     static constexpr int DEPTH = 2;
     Step steps[DEPTH];
     int head = 0, n = 0;          // oldest in-flight step, steps in flight
+    // graph replay of steps whose solves stayed the same for GRAPH_AFTER
+    // launches in a row; key: (solve uid, ring phase) of every solve of the
+    // step.  A solve's uid is never reused, so a graph can never be replayed
+    // for another solve that took the place (and address) of a retired one.
+    static constexpr int GRAPH_AFTER = 3;
+    bool use_graph = false;
+    std::map<std::vector<uint64_t>, std::shared_ptr<LzGraph>> graphs;
+    std::vector<uint64_t> last;   // solves of the previous launch
+    int same = 0;                 // launches in a row with those solves
+    int graph_captures = 0, graph_replays = 0;
     ~LzPipe();
 };
 

@@ -16,6 +16,18 @@ int32_t apply_partial_slots(const ecut_sectors *s);        // slots the current 
 int32_t apply_partial_slots_max(const ecut_sectors *s);    // slots any variant may write
 int32_t max_tile_elems(const ecut_sectors *s);
 
+// A batched row-kernel launch over several problems: the problems (padded to
+// 256 bytes), then the work items, spin-kernel items first.
+struct RowsBatch {
+    std::vector<char> buf;
+    size_t pb = 0;
+    int n_spin = 0, n_items = 0, spin_tile = 0, spin_src = 0, rows_tile = 0, first_spin = -1;
+    ProblemDev spin_single{}, rows_single{};
+};
+void make_rows_batch(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items,
+                     const std::vector<int32_t> &tiles, RowsBatch &b);
+// launch with dev = a device copy of b.buf
+hipError_t launch_rows_batch(const RowsBatch &b, const void *dev, hipStream_t st);
 // One row-kernel launch over the work items of several problems (two when
 // spin-kernel and generic problems are mixed): copies the problem
 // descriptors and the work items to a per-thread device buffer (pinned

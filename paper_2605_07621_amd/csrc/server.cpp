@@ -155,6 +155,7 @@ void ecut_server::run() {
     hipSetDevice(device);
     std::vector<std::unique_ptr<Active>> active;
     LzPipe pipe;   // batched steps in flight (two: the host processes one while the device runs the next)
+    pipe.use_graph = opts.use_graph != 0;
     const int max_active = opts.max_active > 0 ? opts.max_active : 1 << 30;
     while (true) {
         // ---- admission
@@ -287,7 +288,6 @@ ecut_status ecut_server_create(size_t hbm_budget, const ecut_server_opts *opts, 
     *out = nullptr;
     if (hbm_budget < 4096) return fail(ECUT_EINVAL, "budget too small");
     if (opts->max_steps < 2 || !(opts->tol > 0.0)) return fail(ECUT_EINVAL, "bad server options");
-    if (opts->use_graph != 0) return fail(ECUT_EUNSUPPORTED, "graph replay of the serving step is not built");
     auto *S = new (std::nothrow) ecut_server();
     if (!S) return fail(ECUT_ENOMEM, "host allocation");
     S->budget = hbm_budget;

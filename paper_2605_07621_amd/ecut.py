@@ -54,7 +54,8 @@ class SectorsInfo(ctypes.Structure):
 
 
 class LanczosOpts(ctypes.Structure):
-    _fields_ = [("max_steps", _i32), ("max_restarts", _i32), ("reorth", _i32), ("fixed_steps", _i32), ("tol", _dbl)]
+    _fields_ = [("max_steps", _i32), ("max_restarts", _i32), ("reorth", _i32), ("fixed_steps", _i32), ("tol", _dbl),
+                ("use_graph", _i32)]
 
 
 class LanczosStats(ctypes.Structure):
@@ -264,10 +265,11 @@ class Sectors:
         return int(lib().ecut_lanczos_workspace(self.h, ctypes.byref(o)))
 
     def lanczos(self, v0, max_steps, tol=1e-10, reorth=False, fixed_steps=False, max_restarts=0,
-                want_gs=False, workspace=None, stream=None, allow_notconv=False):
+                want_gs=False, workspace=None, stream=None, allow_notconv=False, use_graph=False):
         """Returns (energy, stats dict, ground state or None)."""
         import torch
-        o = LanczosOpts(int(max_steps), int(max_restarts), int(bool(reorth)), int(bool(fixed_steps)), float(tol))
+        o = LanczosOpts(int(max_steps), int(max_restarts), int(bool(reorth)), int(bool(fixed_steps)), float(tol),
+                        int(bool(use_graph)))
         nws = int(lib().ecut_lanczos_workspace(self.h, ctypes.byref(o)))
         ws = torch.empty(nws, dtype=torch.float64, device=v0.device) if workspace is None else workspace
         gs = torch.empty(self.dim, dtype=torch.float64, device=v0.device) if want_gs else None
@@ -295,8 +297,8 @@ def apply_batch(sectors, psis, ys, stream=None):
 class Server:
     """Continuous-batching ground-state server (ecut_server_*)."""
 
-    def __init__(self, hbm_budget, max_active=0, max_steps=400, tol=1e-10, sequential=False):
-        o = ServerOpts(int(max_active), int(max_steps), float(tol), int(bool(sequential)), 0)
+    def __init__(self, hbm_budget, max_active=0, max_steps=400, tol=1e-10, sequential=False, use_graph=False):
+        o = ServerOpts(int(max_active), int(max_steps), float(tol), int(bool(sequential)), int(bool(use_graph)))
         h = _vp()
         _check(lib().ecut_server_create(int(hbm_budget), ctypes.byref(o), ctypes.byref(h)))
         self.h = h

@@ -414,6 +414,29 @@ def test_lanczos_heisenberg16_vs_oracle(dev):
         assert st3["steps"] == 100 and abs(e3 - e_ref) <= 1e-10, (tile, order, e3, e_ref)
 
 
+@pytest.mark.parametrize("name", ["heisenberg16", "hubbard12"])
+def test_lanczos_graph_replay_matches_eager(dev, name):
+    """Three-term solves replayed from captured HIP graphs (one per ring phase)
+    give the eagerly launched solve's energy and step count exactly: fixed-step
+    runs (many replays of each graph) and runs to a tolerance, on the null
+    stream (private capture stream) and on a stream of the caller's."""
+    import torch
+    p = I.WORKLOADS[name]()
+    S = _ecut().Sectors.from_problem(p)
+    v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to(dev))
+    side = torch.cuda.Stream()
+    for kw in (dict(max_steps=150, fixed_steps=True), dict(max_steps=400, tol=1e-10)):
+        e0, s0, _ = S.lanczos(v0, **kw)
+        for stream in (None, side):
+            e1, s1, _ = S.lanczos(v0, stream=stream, use_graph=True, **kw)
+            torch.cuda.synchronize()
+            assert e1 == e0 and s1["steps"] == s0["steps"], (kw, stream, e0, e1, s0["steps"], s1["steps"])
+            # eager work between replays of the graphs of another solve
+            y = S.apply(v0)
+            torch.cuda.synchronize()
+            del y
+
+
 def test_lanczos_hubbard12_vs_oracle(dev):
     import torch
     p = I.hubbard12()
@@ -531,9 +554,13 @@ def test_server_batched_vs_alone_vs_oracle(dev):
         s = O.Sector(p.model, p.n_up, p.n_dn)
         refs.append(s.lanczos(I.psi(3, s.n), 600, tol=1e-14)[0][-1])
     results = {}
-    for mode in ("alone", "mix"):
-        srv = ecut.Server(2 << 30, max_active=(1 if mode == "alone" else 0), max_steps=600, tol=1e-10,
-                          sequential=(mode == "alone"))
+    # alone_graph: one request at a time with graph replay; each request takes
+    # the slot (and the host address) of the one before, so a replay must
+    # never pick up the graphs of a retired request
+    for mode in ("alone", "mix", "mix_graph", "alone_graph"):
+        alone = mode.startswith("alone")
+        srv = ecut.Server(2 << 30, max_active=(1 if alone else 0), max_steps=600, tol=1e-10,
+                          sequential=alone, use_graph=mode.endswith("graph"))
         ids = [srv.submit(p, seed=1000 + k) for k, p in enumerate(reqs)]
         srv.drain()
         res = {r["req_id"]: r for r in srv.poll()}
@@ -546,6 +573,11 @@ def test_server_batched_vs_alone_vs_oracle(dev):
         assert abs(m["energy"] - refs[k]) <= 1e-10, (k, m["energy"], refs[k])
         assert abs(a["energy"] - m["energy"]) <= 1e-10
         assert a["steps"] == m["steps"]
+        # graph replay of the step changes nothing
+        g = results["mix_graph"][k]
+        assert g["status"] == 0 and g["energy"] == m["energy"] and g["steps"] == m["steps"]
+        g = results["alone_graph"][k]
+        assert g["status"] == 0 and g["energy"] == a["energy"] and g["steps"] == a["steps"]
 
 
 def test_server_budget_admission(dev):

@@ -170,14 +170,18 @@ def test_bench_names_every_kernel_variant():
         assert bench.kernel_name(S4) == want
 
 
-def test_server_rejects_graph_replay_option():
-    # graph replay of the serving step is not built: the option is refused
-    # before any device work (so this runs without a GPU)
+def test_option_structs_match_header():
+    # the binding's ctypes structs follow the header's field order and types
     import ctypes
-    o = E.ServerOpts(0, 100, 1e-10, 0, 1)
-    h = ctypes.c_void_p()
-    assert E.lib().ecut_server_create(1 << 20, ctypes.byref(o), ctypes.byref(h)) == E.ECUT_EUNSUPPORTED
-    assert not h.value
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "ecut.h")).read()
+    ctype = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "uint64_t": ctypes.c_uint64}
+    for cname, py in (("ecut_lanczos_opts", E.LanczosOpts), ("ecut_server_opts", E.ServerOpts),
+                      ("ecut_tuning", E.Tuning), ("ecut_lanczos_stats", E.LanczosStats), ("ecut_result", E.Result)):
+        body = re.search(r"typedef struct " + cname + r" \{(.*?)\} " + cname + ";", hdr, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        fields = re.findall(r"(int32_t|double|uint64_t)\s+(\w+);", body)
+        assert [f for f, _ in py._fields_] == [n for _, n in fields], cname
+        assert [t for _, t in py._fields_] == [ctype[ty] for ty, _ in fields], cname
 
 
 def test_spin_tile_tuning_host():
