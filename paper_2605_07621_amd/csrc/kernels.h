@@ -39,6 +39,24 @@ constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
 constexpr int MAX_BASIS = 1024;              // reorthogonalisation: vectors per projection call
 
 // One vector job of the batched Lanczos kernels.
+// Lanczos scalars kept on the device, per solve (scal[]): 0 alpha, 1 |w|^2,
+// 2-4 reorthogonalisation norms and gate, LZ_S the scale s_j of the current
+// vector (v_j = s_j w_j), LZ_Z the coefficient beta_{j-1} s_{j-1} of the
+// previous one.  The apply kernels and vector jobs read them through their
+// dscale pointers (scal + LZ_S).
+constexpr int LZ_S = 6, LZ_Z = 7;
+
+// Next-step job of a solve, run by k_reduce right after it wrote |w|^2 of a
+// step (or of the start vector) to scal[1]: set the factors of the next step
+// and copy alpha, |w|^2 to out2.
+struct LzNextJob {
+    double *scal;
+    double *out2;            // 2 doubles for the host
+    double *scales;          // nullable: scales[slot] <- new scale (reorthogonalisation basis)
+    int32_t slot;
+    int32_t start;           // 1: start vector (no previous vector)
+};
+
 struct VecJob {
     const double *x;
     double *y;
@@ -52,25 +70,8 @@ struct VecJob {
     double scale;
     double coef_mul;
     const double *dscale;    // nullable: scale and coef_mul are read from dscale[0]
+    LzNextJob next;          // k_reduce, next.scal non-null: after the sum, k_lz_next's work for it
 };
-
-// Lanczos scalars kept on the device, per solve (scal[]): 0 alpha, 1 |w|^2,
-// 2-4 reorthogonalisation norms and gate, LZ_S the scale s_j of the current
-// vector (v_j = s_j w_j), LZ_Z the coefficient beta_{j-1} s_{j-1} of the
-// previous one.  The apply kernels and vector jobs read them through their
-// dscale pointers (scal + LZ_S).
-constexpr int LZ_S = 6, LZ_Z = 7;
-
-// One job of k_lz_next: after |w|^2 of a step (or of the start vector) is in
-// scal[1], set the factors of the next step and copy alpha, |w|^2 to out2.
-struct LzNextJob {
-    double *scal;
-    double *out2;            // 2 doubles for the host
-    double *scales;          // nullable: scales[slot] <- new scale (reorthogonalisation basis)
-    int32_t slot;
-    int32_t start;           // 1: start vector (no previous vector)
-};
-hipError_t launch_lz_next(const LzNextJob *jobs, int n, hipStream_t st);
 
 size_t hub_lds_bytes(const ecut_sectors *s);
 hipError_t set_hub_lds_limits(size_t bytes);

@@ -1429,6 +1429,24 @@ hipError_t launch_perm_cols(const int32_t *col_d, int64_t n_rows, int dR, const 
 // Lanczos vector kernels.  A "segment set" describes one vector per problem
 // for batched launches: seg k covers [0, n_k) of vectors x_k, y_k.
 // ------------------------------------------------------------------------
+// Next-step factors of the Lanczos recurrence, done by the thread that
+// finishes the |w|^2 reduction of a solve (VecJob::next): with
+// beta = |w| the next vector is w / beta, so the next apply scales by 1/beta
+// and subtracts beta s_j w_j.  A zero or non-finite beta makes the factors
+// non-finite; the host sees the breakdown in the copied scalars and stops the
+// solve.
+__device__ __forceinline__ void lz_next(const LzNextJob &J) {
+    double *s = J.scal;
+    const double a = s[0], b2 = s[1];
+    const double beta = sqrt(b2 > 0.0 ? b2 : 0.0);
+    const double inv = 1.0 / beta;
+    s[LZ_Z] = J.start ? 0.0 : beta * s[LZ_S];
+    s[LZ_S] = inv;
+    if (J.scales) J.scales[J.slot] = inv;
+    J.out2[0] = a;
+    J.out2[1] = b2;
+}
+
 __global__ __launch_bounds__(VEC_THREADS) void k_reduce(const VecJob *__restrict__ jobs, int n_jobs) {
     __shared__ double red[VEC_THREADS / 64];
     const int j = blockIdx.x;
@@ -1441,6 +1459,7 @@ __global__ __launch_bounds__(VEC_THREADS) void k_reduce(const VecJob *__restrict
     if (threadIdx.x == 0) {
         if (J.mode == 0) J.scalars[J.out] = (J.dscale ? J.dscale[0] : J.scale) * s;
         else J.scalars[J.out] = s;
+        if (J.next.scal) lz_next(J.next);
     }
 }
 
@@ -1463,32 +1482,6 @@ __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restr
         s = block_sum(s, red);
         if (threadIdx.x == 0) J.partials[ci] = s;
     }
-}
-
-// Next-step factors of the Lanczos recurrence, one thread per solve: with
-// beta = |w| the next vector is w / beta, so the next apply scales by 1/beta
-// and subtracts beta s_j w_j.  A zero or non-finite beta makes the factors
-// non-finite; the host sees the breakdown in the copied scalars and stops the
-// solve.
-__global__ __launch_bounds__(64) void k_lz_next(const LzNextJob *__restrict__ jobs, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const LzNextJob J = jobs[i];
-    double *s = J.scal;
-    const double a = s[0], b2 = s[1];
-    const double beta = sqrt(b2 > 0.0 ? b2 : 0.0);
-    const double inv = 1.0 / beta;
-    s[LZ_Z] = J.start ? 0.0 : beta * s[LZ_S];
-    s[LZ_S] = inv;
-    if (J.scales) J.scales[J.slot] = inv;
-    J.out2[0] = a;
-    J.out2[1] = b2;
-}
-
-hipError_t launch_lz_next(const LzNextJob *jobs, int n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lz_next, dim3((n + 63) / 64), dim3(64), 0, st, jobs, n);
-    return hipGetLastError();
 }
 
 // Classical Gram-Schmidt, dot phase: partials[k * n_chunks + chunk] = <w_k, y> over the chunk.

@@ -106,7 +106,6 @@ LzPipe::~LzPipe() {
             (void)hipEventSynchronize(S.ev);
             (void)hipEventDestroy(S.ev);
         }
-        if (S.dev) (void)hipFree(S.dev);
         if (S.host) (void)hipHostFree(S.host);
     }
 }
@@ -116,15 +115,16 @@ static ecut_status step_reserve(LzPipe::Step &S, size_t n) {
     if (!S.ev && hipEventCreateWithFlags(&S.ev, hipEventDisableTiming) != hipSuccess)
         return fail(ECUT_EDEVICE, "hipEventCreate (lanczos step)");
     if (n <= S.cap) return ECUT_OK;
-    if (S.dev) (void)hipFree(S.dev);
     if (S.host) (void)hipHostFree(S.host);
-    S.dev = S.host = nullptr;
+    S.host = S.host_dev = nullptr;
     S.cap = 0;
     size_t c = 64;
     while (c < n) c *= 2;
-    if (hipMalloc(&S.dev, c * 2 * sizeof(double)) != hipSuccess) return fail(ECUT_ENOMEM, "hipMalloc(lanczos scalars)");
-    if (hipHostMalloc(&S.host, c * 2 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    // coherent, mapped: the reduction kernel writes alpha, |w|^2 here directly
+    if (hipHostMalloc(&S.host, c * 2 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
         return fail(ECUT_ENOMEM, "hipHostMalloc(lanczos scalars)");
+    if (hipHostGetDevicePointer((void **)&S.host_dev, S.host, 0) != hipSuccess)
+        return fail(ECUT_EDEVICE, "hipHostGetDevicePointer(lanczos scalars)");
     S.cap = c;
     return ECUT_OK;
 }
@@ -135,7 +135,6 @@ static ecut_status run_start_jobs(std::vector<LzSolve *> &act, const std::vector
                                   Staging &stg) {
     std::vector<VecJob> jn, jr;
     std::vector<int32_t> cj, ci;
-    std::vector<LzNextJob> jl;
     for (size_t k = 0; k < act.size(); ++k) {
         LzSolve &L = *act[k];
         VecJob J{};
@@ -154,11 +153,11 @@ static ecut_status run_start_jobs(std::vector<LzSolve *> &act, const std::vector
         R.mode = 1;
         R.scalars = L.scal;
         R.out = 1;
+        R.next = LzNextJob{L.scal, L.scal + 8, L.reorth ? L.dscale : nullptr, 0, 1};
         jr.push_back(R);
-        jl.push_back(LzNextJob{L.scal, L.scal + 8, L.reorth ? L.dscale : nullptr, 0, 1});
     }
     Pack P;
-    size_t o_jn = P.put(jn), o_jr = P.put(jr), o_cj = P.put(cj), o_ci = P.put(ci), o_jl = P.put(jl);
+    size_t o_jn = P.put(jn), o_jr = P.put(jr), o_cj = P.put(cj), o_ci = P.put(ci);
     ecut_status rs = stg.reserve(P.buf.size());
     if (rs != ECUT_OK) return rs;
     rs = stg.wait();
@@ -170,7 +169,6 @@ static ecut_status run_start_jobs(std::vector<LzSolve *> &act, const std::vector
     hipError_t e = launch_axpy_norm((const VecJob *)(d + o_jn), (const int32_t *)(d + o_cj), (const int32_t *)(d + o_ci),
                                     (int)cj.size(), st);
     if (e == hipSuccess) e = launch_reduce((const VecJob *)(d + o_jr), (int)jr.size(), st);
-    if (e == hipSuccess) e = launch_lz_next((const LzNextJob *)(d + o_jl), (int)jl.size(), st);
     if (e != hipSuccess) return hip_fail(e, "lanczos start");
     return ECUT_OK;
 }
@@ -253,8 +251,8 @@ struct StepPlan {
     RowsBatch rows;                           // the others, one row-kernel queue
     bool has_rows = false;
     Pack P;
-    size_t o_rows = 0, o_ja = 0, o_jx = 0, o_jb = 0, o_cj = 0, o_ci = 0, o_jl = 0, o_n0 = 0, o_n1 = 0;
-    int n_ja = 0, n_cj = 0, n_jl = 0;
+    size_t o_rows = 0, o_ja = 0, o_jx = 0, o_jb = 0, o_cj = 0, o_ci = 0, o_n0 = 0, o_n1 = 0;
+    int n_ja = 0, n_cj = 0;
     LzSolve *R = nullptr;                     // the one solve with reorthogonalisation, if any
 };
 }  // namespace
@@ -300,7 +298,6 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
     // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2; 5. next factors
     std::vector<VecJob> ja, jx, jb;
     std::vector<int32_t> cj, ci;
-    std::vector<LzNextJob> jl;
     for (size_t k = 0; k < act.size(); ++k) {
         LzSolve &L = *act[k];
         VecJob A{};
@@ -328,18 +325,16 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
         B.mode = 1;
         B.scalars = L.scal;
         B.out = 1;
+        B.next = LzNextJob{L.scal, out2 + 2 * k, L.reorth ? L.dscale : nullptr, L.j + 1, 0};
         jb.push_back(B);
-        jl.push_back(LzNextJob{L.scal, out2 + 2 * k, L.reorth ? L.dscale : nullptr, L.j + 1, 0});
     }
     pl.o_ja = pl.P.put(ja);
     pl.o_jx = pl.P.put(jx);
     pl.o_jb = pl.P.put(jb);
     pl.o_cj = pl.P.put(cj);
     pl.o_ci = pl.P.put(ci);
-    pl.o_jl = pl.P.put(jl);
     pl.n_ja = (int)ja.size();
     pl.n_cj = (int)cj.size();
-    pl.n_jl = (int)jl.size();
     pl.R = (act.size() == 1 && act[0]->reorth) ? act[0] : nullptr;
     if (pl.R) {
         // squared norm of w before (scal[2]) and after (scal[3]) the first projection
@@ -393,8 +388,7 @@ static ecut_status enqueue_plan(const StepPlan &pl, const void *dev, hipStream_t
         }
         if (e != hipSuccess) return hip_fail(e, "reorthogonalisation");
     }
-    e = launch_reduce((const VecJob *)(d + pl.o_jb), (int)pl.act.size(), st);
-    if (e == hipSuccess) e = launch_lz_next((const LzNextJob *)(d + pl.o_jl), pl.n_jl, st);
+    e = launch_reduce((const VecJob *)(d + pl.o_jb), (int)pl.act.size(), st);   // and the next factors
     if (e != hipSuccess) return hip_fail(e, "lanczos beta");
     return ECUT_OK;
 }
@@ -476,7 +470,7 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
         S.graph = g;
     } else {
         StepPlan pl;
-        build_plan(act, S.dev, pl);
+        build_plan(act, S.host_dev, pl);   // alpha, |w|^2 go straight to pinned host memory
         rs = stg.reserve(pl.P.buf.size());
         if (rs != ECUT_OK) return rs;
         rs = stg.wait();
@@ -486,7 +480,7 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
         if (rs != ECUT_OK) return rs;
         rs = enqueue_plan(pl, stg.dev, st);
         if (rs != ECUT_OK) return rs;
-        e = hipMemcpyAsync(S.host, S.dev, 2 * sizeof(double) * act.size(), hipMemcpyDeviceToHost, st);
+        e = hipSuccess;
         S.graph.reset();
     }
     if (e == hipSuccess) e = hipEventRecord(S.ev, st);

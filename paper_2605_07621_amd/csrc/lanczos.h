@@ -57,8 +57,8 @@ struct LzGraph {
 struct LzPipe {
     struct Step {
         std::vector<LzSolve *> solves;
-        double *dev = nullptr;    // 2 doubles per solve, written by k_lz_next (eager steps)
-        double *host = nullptr;   // pinned copy
+        double *host = nullptr;       // 2 doubles per solve: coherent pinned host memory
+        double *host_dev = nullptr;   // its device address (eager steps write it directly)
         size_t cap = 0;           // solves
         hipEvent_t ev = nullptr;
         std::shared_ptr<LzGraph> graph;   // a replayed step keeps its graph alive until finished
