@@ -70,7 +70,9 @@ struct VecJob {
     double scale;
     double coef_mul;
     const double *dscale;    // nullable: scale and coef_mul are read from dscale[0]
-    LzNextJob next;          // k_reduce, next.scal non-null: after the sum, k_lz_next's work for it
+    LzNextJob next;          // k_reduce, next.scal non-null: after the sum, the next-step job of its solve
+    const double *a_partials;   // k_axpy_norm, nullable: form scalars[coef_idx] itself as
+    int32_t a_n;                //   dscale[0] * sum of a_n partials (k_reduce's order and result)
 };
 
 size_t hub_lds_bytes(const ecut_sectors *s);

@@ -1467,12 +1467,29 @@ __global__ __launch_bounds__(VEC_THREADS) void k_reduce(const VecJob *__restrict
 __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restrict__ jobs, const int32_t *__restrict__ chunk_job,
                                                            const int32_t *__restrict__ chunk_idx, int n_chunks) {
     __shared__ double red[VEC_THREADS / 64];
+    __shared__ double bcast;
     for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const VecJob J = jobs[chunk_job[c]];
         const int ci = chunk_idx[c];
         const int64_t i0 = (int64_t)ci * VEC_CHUNK;
         const int64_t i1 = i0 + VEC_CHUNK < J.n ? i0 + VEC_CHUNK : J.n;
-        const double a = J.scalars[J.coef_idx] * (J.dscale ? J.dscale[0] : J.coef_mul);
+        double sc = J.dscale ? J.dscale[0] : J.coef_mul;
+        double a;
+        if (J.a_partials) {
+            // the coefficient's reduction, done here in k_reduce's order so
+            // every block (and the stored value) gets k_reduce's result
+            double t = 0.0;
+            for (int i = threadIdx.x; i < J.a_n; i += blockDim.x) t += J.a_partials[i];
+            t = block_sum(t, red);   // the sum in thread 0, after a barrier
+            if (threadIdx.x == 0) bcast = t;
+            __syncthreads();
+            t = bcast;               // read before the norm's block_sum barriers below
+            const double coef = (J.dscale ? J.dscale[0] : J.scale) * t;
+            if (ci == 0 && threadIdx.x == 0) J.scalars[J.coef_idx] = coef;
+            a = coef * sc;
+        } else {
+            a = J.scalars[J.coef_idx] * sc;
+        }
         double s = 0.0;
         for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
             const double v = J.y[i] - a * J.x[i];

@@ -130,7 +130,7 @@ static ecut_status step_reserve(LzPipe::Step &S, size_t n) {
 }
 
 // |v|^2 of each start vector into scal[1], then the first scale 1/|v| and a
-// zero previous-vector coefficient on the device (k_lz_next, start mode)
+// zero previous-vector coefficient, set on the device by the reduction (start mode)
 static ecut_status run_start_jobs(std::vector<LzSolve *> &act, const std::vector<double *> &vecs, hipStream_t st,
                                   Staging &stg) {
     std::vector<VecJob> jn, jr;
@@ -207,7 +207,7 @@ ecut_status lz_start(std::vector<LzSolve *> &solves, const std::vector<const dou
             L->status = fail(ECUT_EINVAL, "start vector is zero or not finite");
             continue;
         }
-        L->sc.push_back(1.0 / nrm);   // the scale k_lz_next set on the device
+        L->sc.push_back(1.0 / nrm);   // the scale set on the device
     }
     return ECUT_OK;
 }
@@ -250,6 +250,7 @@ struct StepPlan {
     std::vector<const ecut_sectors *> own_s;
     RowsBatch rows;                           // the others, one row-kernel queue
     bool has_rows = false;
+    bool fuse_alpha = false;                  // alpha formed inside the update pass
     Pack P;
     size_t o_rows = 0, o_ja = 0, o_jx = 0, o_jb = 0, o_cj = 0, o_ci = 0, o_n0 = 0, o_n1 = 0;
     int n_ja = 0, n_cj = 0;
@@ -295,9 +296,14 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
         pl.has_rows = true;
         pl.o_rows = pl.P.put(pl.rows.buf);
     }
-    // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2; 5. next factors
+    // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2; 5. next factors.
+    // When every block of the update pass can afford to re-add the alpha
+    // partials (at most 4M reads in all), it does so and alpha needs no launch.
     std::vector<VecJob> ja, jx, jb;
     std::vector<int32_t> cj, ci;
+    int64_t alpha_reads = 0;
+    for (LzSolve *L : act) alpha_reads += (int64_t)apply_partial_slots(L->s) * L->n_chunks;
+    pl.fuse_alpha = alpha_reads <= (int64_t)1 << 22;
     for (size_t k = 0; k < act.size(); ++k) {
         LzSolve &L = *act[k];
         VecJob A{};
@@ -317,6 +323,10 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
         X.scalars = L.scal;
         X.coef_idx = 0;
         X.dscale = L.scal + LZ_S;
+        if (pl.fuse_alpha) {
+            X.a_partials = L.part_apply;
+            X.a_n = L.n_apply;
+        }
         jx.push_back(X);
         for (int32_t c = 0; c < L.n_chunks; ++c) { cj.push_back((int32_t)k); ci.push_back(c); }
         VecJob B{};
@@ -361,14 +371,14 @@ static ecut_status enqueue_plan(const StepPlan &pl, const void *dev, hipStream_t
     hipError_t e = hipSuccess;
     if (pl.has_rows) e = launch_rows_batch(pl.rows, d + pl.o_rows, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");
-    e = launch_reduce((const VecJob *)(d + pl.o_ja), pl.n_ja, st);
+    if (!pl.fuse_alpha) e = launch_reduce((const VecJob *)(d + pl.o_ja), pl.n_ja, st);
     if (e == hipSuccess)
         e = launch_axpy_norm((const VecJob *)(d + pl.o_jx), (const int32_t *)(d + pl.o_cj), (const int32_t *)(d + pl.o_ci),
                              pl.n_cj, st);
     if (e != hipSuccess) return hip_fail(e, "lanczos update");
     if (LzSolve *R = pl.R) {
         // classical Gram-Schmidt against w_0..w_j (v_k = s_k w_k, the scales
-        // kept on the device by k_lz_next); the second pass runs only when the
+        // kept on the device by the reductions); the second pass runs only when the
         // first one removed more than half of the squared norm (decided on
         // the device).  Every pass leaves the norm partials of its result in
         // part_norm, so beta^2 below is the norm of the vector actually kept.
@@ -555,7 +565,7 @@ ecut_status lz_finish(LzPipe &pipe, hipStream_t st, Staging &stg) {
             if (r2 != ECUT_OK) return r2;
             continue;
         }
-        if (L->reorth) L->sc.push_back(1.0 / beta);   // the scale k_lz_next set on the device
+        if (L->reorth) L->sc.push_back(1.0 / beta);   // the scale set on the device
     }
     return ECUT_OK;
 }
