@@ -73,6 +73,7 @@ struct VecJob {
     LzNextJob next;          // k_reduce, next.scal non-null: after the sum, the next-step job of its solve
     const double *a_partials;   // k_axpy_norm, nullable: form scalars[coef_idx] itself as
     int32_t a_n;                //   dscale[0] * sum of a_n partials (k_reduce's order and result)
+    int64_t chunk;              // k_axpy_norm: elements per partial (0 = VEC_CHUNK)
 };
 
 size_t hub_lds_bytes(const ecut_sectors *s);

@@ -1471,8 +1471,9 @@ __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restr
     for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const VecJob J = jobs[chunk_job[c]];
         const int ci = chunk_idx[c];
-        const int64_t i0 = (int64_t)ci * VEC_CHUNK;
-        const int64_t i1 = i0 + VEC_CHUNK < J.n ? i0 + VEC_CHUNK : J.n;
+        const int64_t ck = J.chunk > 0 ? J.chunk : VEC_CHUNK;
+        const int64_t i0 = (int64_t)ci * ck;
+        const int64_t i1 = i0 + ck < J.n ? i0 + ck : J.n;
         double sc = J.dscale ? J.dscale[0] : J.coef_mul;
         double a;
         if (J.a_partials) {

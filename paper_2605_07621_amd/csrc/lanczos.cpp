@@ -26,11 +26,23 @@
 
 namespace ecut {
 
-static int64_t n_chunks_of(int64_t n) { return (n + VEC_CHUNK - 1) / VEC_CHUNK; }
+// Elements per norm partial: VEC_CHUNK with reorthogonalisation (its kernels
+// share that layout); for three-term solves smaller, down to 1024, so a
+// short vector's update pass still spreads over many work groups.
+static int64_t chunk_of(int64_t n, bool reorth) {
+    if (reorth) return VEC_CHUNK;
+    int64_t c = 1024;
+    while (c < VEC_CHUNK && c * 2048 < n) c *= 2;
+    return c;
+}
+static int64_t n_chunks_of(int64_t n, bool reorth) {
+    const int64_t c = chunk_of(n, reorth);
+    return (n + c - 1) / c;
+}
 
 size_t lz_workspace_doubles(const ecut_sectors *s, bool reorth, int keep) {
     const int64_t n = s->dim;
-    const int64_t nc = n_chunks_of(n);
+    const int64_t nc = n_chunks_of(n, reorth);
     auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
     int64_t d = 0;
     d += reorth ? al(n) * (keep + 1) : al(n) * 3;
@@ -45,8 +57,9 @@ void lz_carve(LzSolve &L, const ecut_sectors *s, bool reorth, int keep, double *
     static std::atomic<uint64_t> next_uid{1};
     L.uid = next_uid++;
     const int64_t n = s->dim;
-    const int64_t nc = n_chunks_of(n);
+    const int64_t nc = n_chunks_of(n, reorth);
     auto al = [](int64_t v) { return (v + 31) & ~(int64_t)31; };
+    L.chunk = chunk_of(n, reorth);
     L.s = s;
     L.n = n;
     L.reorth = reorth;
@@ -145,6 +158,7 @@ static ecut_status run_start_jobs(std::vector<LzSolve *> &act, const std::vector
         J.scalars = L.scal;
         J.coef_idx = 0;
         J.coef_mul = 0.0;
+        J.chunk = L.chunk;
         jn.push_back(J);
         for (int32_t c = 0; c < L.n_chunks; ++c) { cj.push_back((int32_t)k); ci.push_back(c); }
         VecJob R{};
@@ -323,6 +337,7 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
         X.scalars = L.scal;
         X.coef_idx = 0;
         X.dscale = L.scal + LZ_S;
+        X.chunk = L.chunk;
         if (pl.fuse_alpha) {
             X.a_partials = L.part_apply;
             X.a_n = L.n_apply;

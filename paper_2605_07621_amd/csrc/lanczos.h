@@ -26,6 +26,7 @@ struct LzSolve {
     int32_t n_apply = 0;
     double *part_norm = nullptr;
     int32_t n_chunks = 0;
+    int64_t chunk = 0;            // elements per norm partial
     double *part_cgs = nullptr;   // reorth: keep x n_chunks
     double *dcoef = nullptr;      // reorth: MAX_BASIS
     double *dscale = nullptr;     // reorth: MAX_BASIS
