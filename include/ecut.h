@@ -361,6 +361,11 @@ typedef struct ecut_server_opts {
                                  batched step from a HIP graph captured once per ring phase (a new
                                  set drops the graphs); 0: launch every kernel each step.  Same
                                  results bit for bit */
+    int32_t autotune;         /* 1: the first request of each problem shape (device architecture,
+                                 sites, particle numbers, blocks, dimension) is autotuned on its own
+                                 workspace (ecut_autotune); the tuning is kept for the life of the
+                                 process and applied to every later request of that shape, in any
+                                 server.  0: default launch tuning */
 } ecut_server_opts;
 
 typedef struct ecut_result {

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 #include "ecut_internal.h"
@@ -15,6 +16,8 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
 int32_t apply_partial_slots(const ecut_sectors *s);        // slots the current launch writes
 int32_t apply_partial_slots_max(const ecut_sectors *s);    // slots any variant may write
 int32_t max_tile_elems(const ecut_sectors *s);
+// key of a problem's launch tuning: device architecture and problem shape
+std::string tune_shape_key(const ecut_sectors *s);
 
 // A batched row-kernel launch over several problems: the problems (padded to
 // 256 bytes), then the work items, spin-kernel items first.

@@ -27,6 +27,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -151,6 +152,27 @@ struct ecut_server {
 
 static size_t footprint(const ecut_sectors *s) { return lz_workspace_doubles(s, false, 0) * sizeof(double); }
 
+// Launch tuning of each problem shape, measured once per process (on the
+// first request of the shape, x = its start vector, y = a ring vector the
+// solve overwrites later) and reused for every later request of the shape.
+static std::mutex g_tune_mu;
+static std::map<std::string, ecut_tuning> g_tunings;
+
+static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStream_t st) {
+    const std::string key = tune_shape_key(s);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tunings.find(key);
+        if (it != g_tunings.end() && ecut_set_tuning(s, &it->second) == ECUT_OK) return ECUT_OK;
+    }
+    ecut_tuning best{};
+    ecut_status rs = ecut_autotune(s, x, y, st, &best);
+    if (rs != ECUT_OK) return rs;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tunings.emplace(key, best);
+    return ECUT_OK;
+}
+
 void ecut_server::run() {
     hipSetDevice(device);
     std::vector<std::unique_ptr<Active>> active;
@@ -226,6 +248,7 @@ void ecut_server::run() {
             for (Active *A : fresh) {
                 hipError_t e = launch_fill_normal(A->L.ring[0], A->L.n, A->req->seed, stream);
                 if (e != hipSuccess) st = hip_fail(e, "seeded start vector");
+                if (st == ECUT_OK && opts.autotune) st = tune_once(A->s, A->L.ring[0], A->L.ring[1], stream);
                 ls.push_back(&A->L);
                 v0.push_back(A->L.ring[0]);
             }

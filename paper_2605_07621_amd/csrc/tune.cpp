@@ -18,7 +18,9 @@ namespace {
 
 std::mutex g_cache_mu;
 
-std::string shape_key(const ecut_sectors *s) {
+}  // namespace
+
+std::string tune_shape_key(const ecut_sectors *s) {
     hipDeviceProp_t prop;
     int dev = 0;
     hipGetDevice(&dev);
@@ -31,6 +33,8 @@ std::string shape_key(const ecut_sectors *s) {
       << s->blocks.size() << "/dim" << s->dim;
     return k.str();
 }
+
+namespace {
 
 // The cache file is a flat JSON object {"key": [grid, n_xcd, row_order, variant, tile], ...};
 // entries without the tile take the default tile.
@@ -142,14 +146,14 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
     if (!s->on_device) return fail(ECUT_EINVAL, "handle was built with ECUT_BUILD_HOST_ONLY");
     hipStream_t st = (hipStream_t)stream;
     const char *cache_path = std::getenv("ECUT_TUNE_CACHE");
-    const std::string key = shape_key(s);
+    const std::string key = tune_shape_key(s);
     if (cache_path) {
         std::lock_guard<std::mutex> g(g_cache_mu);
         auto m = read_cache(cache_path);
         auto it = m.find(key);
-        if (it != m.end()) {
-            ecut_status rs = apply_tuning(s, it->second);
-            if (rs != ECUT_OK) return rs;
+        // an entry this problem cannot take (another model of the same
+        // shape) is timed afresh
+        if (it != m.end() && apply_tuning(s, it->second) == ECUT_OK) {
             if (best) ecut_get_tuning(s, best);
             return ECUT_OK;
         }

@@ -559,8 +559,9 @@ def test_server_batched_vs_alone_vs_oracle(dev):
     # never pick up the graphs of a retired request
     for mode in ("alone", "mix", "mix_graph", "alone_graph"):
         alone = mode.startswith("alone")
+        # every server tunes each new problem shape once (shared by all of them)
         srv = ecut.Server(2 << 30, max_active=(1 if alone else 0), max_steps=600, tol=1e-10,
-                          sequential=alone, use_graph=mode.endswith("graph"))
+                          sequential=alone, use_graph=mode.endswith("graph"), autotune=True)
         ids = [srv.submit(p, seed=1000 + k) for k, p in enumerate(reqs)]
         srv.drain()
         res = {r["req_id"]: r for r in srv.poll()}
