@@ -326,6 +326,62 @@ def summarize_profiles(workload, kernel, copy_bytes, trace_dir, fetch_dir, write
     return out
 
 
+def serving_trace(n_requests, budget_gb):
+    """The batched closed-loop serving run (at most 32 active) alone, after
+    the tuning warm-up, for a kernel trace: prints its statistics and its
+    timed window on the monotonic clock (the clock of rocprofv3's stamps)."""
+    import numpy as np
+    from paper_2605_07621_amd import inputs as I
+    reqs = I.serving_requests(n_requests, seed=2026)
+    budget = budget_gb * 2**30
+    _warm_tunings(reqs, budget)
+    t0 = time.monotonic_ns()
+    out = _run_server(reqs, np.zeros(len(reqs)), budget, 32, False)
+    t1 = time.monotonic_ns()
+    return dict(run="batched_max32_closed_loop", requests=n_requests, window_ns=[t0, t1],
+                **_lat_stats(out, min(r["t_submit"] for r in out)))
+
+
+def summarize_serving(trace_dir, window, command):
+    """profiles/serving_c5_batched32_trace.txt: the kernels of the timed
+    serving window from a rocprofv3 kernel trace, and how busy the GPU was."""
+    import csv
+    t0, t1 = window
+    rows = []
+    for fn in os.listdir(trace_dir):
+        if fn.endswith("kernel_trace.csv"):
+            with open(os.path.join(trace_dir, fn)) as f:
+                rows += [r for r in csv.DictReader(f) if t0 <= int(r["Start_Timestamp"]) <= t1]
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    busy, cs, ce = 0, None, None
+    for s, e in iv:
+        if ce is None or s > ce:
+            busy += 0 if ce is None else ce - cs
+            cs, ce = s, e
+        else:
+            ce = max(ce, e)
+    if ce is not None:
+        busy += ce - cs
+    span = t1 - t0
+    per = {}
+    for r in rows:
+        k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        n, tot = per.get(k, (0, 0))
+        per[k] = (n + 1, tot + int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    lines = ["# rocprofv3 kernel trace: 256 mixed serving requests, batched closed loop (at most 32 active)", "",
+             "command (from the repository root):", "  cd /tmp && export TMPDIR=/tmp && cd -", "  " + command, "",
+             f"timed window {span / 1e9:.3f} s, {len(rows)} kernels, GPU busy {busy / 1e9:.3f} s "
+             f"({100.0 * busy / span:.1f}% of the window; kernels of different queues overlap, so the",
+             "shares, of the busy time, can sum above 100%: uploads of sector tables run beside the steps)", "",
+             f"{'kernel':60s} {'calls':>8s} {'total_ms':>10s} {'share':>7s}"]
+    for k, (n, tot) in sorted(per.items(), key=lambda kv: -kv[1][1])[:16]:
+        lines.append(f"{k[:60]:60s} {n:8d} {tot / 1e6:10.1f} {100.0 * tot / max(busy, 1):6.1f}%")
+    path = os.path.join(ROOT, "profiles", "serving_c5_batched32_trace.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,7 +404,18 @@ def main():
     ap.add_argument("--kernel", default="k_hub3", help="kernel named in --summarize")
     ap.add_argument("--commands", default=None, help="JSON of the profiling commands, for --summarize")
     ap.add_argument("--serving-budget-gb", type=float, default=24.0)
+    ap.add_argument("--serving-trace", action="store_true",
+                    help="run only the batched serving closed loop (for a kernel trace) and print its window")
+    ap.add_argument("--summarize-serving", nargs=2, metavar=("TRACE_DIR", "WINDOW_JSON"),
+                    help="write profiles/serving_c5_batched32_trace.txt from a --serving-trace kernel trace")
     args = ap.parse_args()
+    if args.summarize_serving:
+        w = json.loads(open(args.summarize_serving[1]).read().strip().splitlines()[-1])
+        print(summarize_serving(args.summarize_serving[0], w["window_ns"], args.commands or ""))
+        return
+    if args.serving_trace:
+        print(json.dumps(serving_trace(args.serving, args.serving_budget_gb)), flush=True)
+        return
     if args.summarize:
         from paper_2605_07621_amd import inputs as I
         p = I.WORKLOADS[args.workload]()

@@ -340,8 +340,10 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
 
 /* ---------------------------------------------------------------------------
  * Continuous-batching ground-state server.
- * A worker thread owns one stream and a device arena of hbm_budget bytes.
- * Requests are admitted when their footprint (sector metadata + Lanczos
+ * A worker thread owns one stream and a device arena of hbm_budget bytes;
+ * a helper thread builds the sector tables of arrived requests (up to 16
+ * ahead of the queue head, in arrival order) and frees those of retired
+ * solves.  Requests are admitted when their footprint (sector metadata + Lanczos
  * vectors) fits the free arena and a slot is free; all admitted solves
  * advance together, one batched H*psi launch and one batched vector-update
  * launch per step, with two steps in flight (the host checks the solves of
@@ -392,7 +394,9 @@ ecut_status ecut_server_submit(ecut_server *srv, const ecut_model_desc *model, c
 /* Copy up to max finished results; *n_done = number copied (0 -> ECUT_EAGAIN). */
 ecut_status ecut_server_poll(ecut_server *srv, ecut_result *out, int32_t max, int32_t *n_done);
 
-/* Block until every submitted request has finished. */
+/* Block until every submitted request has finished.  A failure of the
+ * server's own threads (not of a single request) is returned here and by
+ * ecut_server_poll, with the worker's message in ecut_last_error(). */
 ecut_status ecut_server_drain(ecut_server *srv);
 
 /* Server clock (seconds since create). */

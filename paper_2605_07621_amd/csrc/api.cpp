@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -41,7 +42,7 @@ std::mutex g_dev_mu;
 std::map<int, DevRes> g_dev;
 }  // namespace
 
-static size_t g_last_max_lds = 0;
+static std::atomic<size_t> g_last_max_lds{0};   // read by launches on any thread
 
 ecut_status device_res(int *dev_out, const uint64_t **binom_out, int *n_cu_out) {
     int dev = 0;

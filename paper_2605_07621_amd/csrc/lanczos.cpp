@@ -424,6 +424,11 @@ LzGraph::~LzGraph() {
     if (dev_out) (void)hipFreeAsync(dev_out, st);
 }
 
+std::mutex &lz_capture_mutex() {
+    static std::mutex m;
+    return m;
+}
+
 // capture one step of act (its current ring phases) as a graph
 static ecut_status capture_step(const std::vector<LzSolve *> &act, hipStream_t st, std::shared_ptr<LzGraph> &out) {
     auto g = std::make_shared<LzGraph>();
@@ -436,11 +441,15 @@ static ecut_status capture_step(const std::vector<LzSolve *> &act, hipStream_t s
     if (e == hipSuccess) e = hipMemcpyAsync(g->dev, pl.P.buf.data(), pl.P.buf.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);   // the pageable source is released on return
     if (e != hipSuccess) return hip_fail(e, "graph descriptors");
-    e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    ecut_status rs = enqueue_plan(pl, g->dev, st);
+    ecut_status rs;
     hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(st, &graph);
+    {
+        std::lock_guard<std::mutex> cg(lz_capture_mutex());
+        e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        rs = enqueue_plan(pl, g->dev, st);
+        e = hipStreamEndCapture(st, &graph);
+    }
     if (rs != ECUT_OK) {
         if (graph) (void)hipGraphDestroy(graph);
         return rs;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "ecut_internal.h"
@@ -96,6 +97,10 @@ ecut_status lz_launch(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t 
 // wait for the oldest step in flight and process its scalars on the host
 // (convergence, breakdown, restarts); solves already done ignore it
 ecut_status lz_finish(LzPipe &pipe, hipStream_t st, Staging &stg);
+// held while a step is being captured: another host thread of the process
+// holds it around its own HIP calls (allocation, upload, free), which a
+// stream capture in progress on the device would otherwise reject
+std::mutex &lz_capture_mutex();
 // one step, launched and finished (synchronises st)
 ecut_status lz_step(std::vector<LzSolve *> &solves, LzPipe &pipe, hipStream_t st, Staging &stg);
 // lowest eigenvalue of the final tridiagonal matrix by implicit QL

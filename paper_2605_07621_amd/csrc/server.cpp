@@ -93,7 +93,11 @@ struct Request {
     double not_before = 0.0, t_submit = 0.0;
     std::vector<int32_t> bi, bj;
     std::vector<double> jxy, jz, t, u;
-    ecut_sectors *built = nullptr;   // sectors built while waiting for memory
+    // sectors built ahead of admission by the helper thread (or kept while
+    // the request waits for memory); state 0 not built, 1 building, 2 built
+    ecut_sectors *built = nullptr;
+    int state = 0;
+    ecut_status build_status = ECUT_OK;
     ~Request() {
         if (built) ecut_sectors_free(built);
     }
@@ -135,9 +139,10 @@ struct ecut_server {
     ArenaAlloc alloc;
     hipStream_t stream = nullptr;
     Staging stg;
-    std::thread worker;
+    std::thread worker, helper;
     std::mutex mu;
-    std::condition_variable cv, cv_done;
+    std::condition_variable cv, cv_done, cv_help;
+    std::vector<ecut_sectors *> graveyard;   // retired handles, freed by the helper
     std::deque<std::unique_ptr<Request>> queue;
     std::vector<ecut_result> finished;
     uint64_t next_id = 1;
@@ -145,9 +150,11 @@ struct ecut_server {
     bool stop = false;
     std::chrono::steady_clock::time_point t0;
     ecut_status worker_status = ECUT_OK;
+    std::string worker_msg;   // the worker's error message (error messages are per thread)
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
     void run();
+    void help();
 };
 
 static size_t footprint(const ecut_sectors *s) { return lz_workspace_doubles(s, false, 0) * sizeof(double); }
@@ -173,6 +180,58 @@ static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStr
     return ECUT_OK;
 }
 
+// Helper thread: builds the sectors of arrived requests near the head of the
+// queue (at most LOOKAHEAD of them) before the worker admits them, and frees
+// the handles of retired solves, so that neither the host work of a build
+// nor the device wait inside hipFree sits between two batched steps.
+static constexpr int LOOKAHEAD = 16;
+
+void ecut_server::help() {
+    hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        if (!graveyard.empty()) {
+            std::vector<ecut_sectors *> g;
+            g.swap(graveyard);
+            lk.unlock();
+            {
+                std::lock_guard<std::mutex> cg(lz_capture_mutex());
+                for (ecut_sectors *s : g) ecut_sectors_free(s);
+            }
+            lk.lock();
+            continue;
+        }
+        if (stop) break;
+        Request *R = nullptr;
+        int k = 0;
+        const double t = now();
+        for (auto &q : queue) {
+            if (k++ >= LOOKAHEAD || q->not_before > t) break;   // never ahead of arrival
+            if (q->state == 0) {
+                R = q.get();
+                break;
+            }
+        }
+        if (!R) {
+            cv_help.wait_for(lk, std::chrono::milliseconds(2));
+            continue;
+        }
+        R->state = 1;
+        lk.unlock();
+        ecut_sectors *s = nullptr;
+        ecut_status st;
+        {
+            std::lock_guard<std::mutex> cg(lz_capture_mutex());
+            st = ecut_build_sectors(&R->model, &R->cut, R->q, 0, &s);
+        }
+        lk.lock();
+        R->built = s;
+        R->build_status = st;
+        R->state = 2;
+        cv.notify_all();
+    }
+}
+
 void ecut_server::run() {
     hipSetDevice(device);
     std::vector<std::unique_ptr<Active>> active;
@@ -187,19 +246,21 @@ void ecut_server::run() {
             while (!stop && active.empty()) {
                 if (!queue.empty()) {
                     const double wait = queue.front()->not_before - now();
-                    if (wait <= 0) break;
-                    cv.wait_for(lk, std::chrono::duration<double>(std::min(wait, 0.05)));
+                    if (wait <= 0 && queue.front()->state == 2) break;
+                    // not arrived yet, or the helper is still building it
+                    cv.wait_for(lk, std::chrono::duration<double>(wait > 0 ? std::min(wait, 0.05) : 0.05));
                 } else {
                     cv.wait_for(lk, std::chrono::milliseconds(50));
                 }
             }
             if (stop && active.empty()) break;
-            while (!queue.empty() && (int)active.size() < max_active && queue.front()->not_before <= now()) {
+            while (!queue.empty() && (int)active.size() < max_active && queue.front()->not_before <= now() &&
+                   queue.front()->state == 2) {
                 Request &R = *queue.front();
                 lk.unlock();
                 ecut_sectors *s = R.built;
                 R.built = nullptr;
-                ecut_status st = s ? ECUT_OK : ecut_build_sectors(&R.model, &R.cut, R.q, 0, &s);
+                ecut_status st = R.build_status;
                 size_t off = 0, bytes = 0;
                 bool fits = false;
                 if (st == ECUT_OK) {
@@ -226,6 +287,7 @@ void ecut_server::run() {
                     R.built = s;
                     break;
                 }
+                cv_help.notify_one();   // the look-ahead window moves on
                 auto A = std::make_unique<Active>();
                 A->req = std::move(queue.front());
                 queue.pop_front();
@@ -274,10 +336,12 @@ void ecut_server::run() {
             while (pipe.n > 0) (void)lz_finish(pipe, stream, stg);
             std::lock_guard<std::mutex> g(mu);
             worker_status = st;
+            worker_msg = ecut_last_error();
             for (auto &A : active) A->L.done = true, A->L.status = st, A->L.pending = 0;
         }
         // ---- retire
         std::vector<ecut_result> out;
+        std::vector<ecut_sectors *> retired;
         for (auto it = active.begin(); it != active.end();) {
             Active &A = **it;
             if (!A.L.done || A.L.pending > 0) { ++it; continue; }   // retire once no step of it is in flight
@@ -292,8 +356,14 @@ void ecut_server::run() {
             r.t_done = now();
             out.push_back(r);
             alloc.release(A.off, A.bytes);
-            ecut_sectors_free(A.s);
+            retired.push_back(A.s);   // freed by the helper: hipFree waits for the device
             it = active.erase(it);
+        }
+        if (!retired.empty()) {
+            std::lock_guard<std::mutex> g(mu);
+            graveyard.insert(graveyard.end(), retired.begin(), retired.end());
+            retired.clear();
+            cv_help.notify_one();
         }
         if (!out.empty()) {
             std::lock_guard<std::mutex> g(mu);
@@ -338,6 +408,7 @@ ecut_status ecut_server_create(size_t hbm_budget, const ecut_server_opts *opts, 
     S->alloc.init(hbm_budget);
     S->t0 = std::chrono::steady_clock::now();
     S->worker = std::thread([S] { S->run(); });
+    S->helper = std::thread([S] { S->help(); });
     *out = S;
     return ECUT_OK;
 }
@@ -365,6 +436,7 @@ ecut_status ecut_server_submit(ecut_server *srv, const ecut_model_desc *model, c
     srv->queue.insert(it, std::move(R));
     ++srv->n_submitted;
     srv->cv.notify_all();
+    srv->cv_help.notify_one();
     return ECUT_OK;
 }
 
@@ -375,7 +447,8 @@ ecut_status ecut_server_poll(ecut_server *srv, ecut_result *out, int32_t max, in
     for (int32_t k = 0; k < n; ++k) out[k] = srv->finished[k];
     srv->finished.erase(srv->finished.begin(), srv->finished.begin() + n);
     *n_done = n;
-    if (srv->worker_status != ECUT_OK && n == 0) return fail(srv->worker_status, "server worker failed");
+    if (srv->worker_status != ECUT_OK && n == 0)
+        return fail(srv->worker_status, "server worker failed: " + srv->worker_msg);
     return n > 0 ? ECUT_OK : ECUT_EAGAIN;
 }
 
@@ -383,20 +456,33 @@ ecut_status ecut_server_drain(ecut_server *srv) {
     if (!srv) return fail(ECUT_EINVAL, "null argument");
     std::unique_lock<std::mutex> lk(srv->mu);
     srv->cv_done.wait(lk, [&] { return srv->n_finished >= srv->n_submitted || srv->worker_status != ECUT_OK; });
-    return srv->worker_status;
+    if (srv->worker_status != ECUT_OK) return fail(srv->worker_status, "server worker failed: " + srv->worker_msg);
+    return ECUT_OK;
 }
 
 double ecut_server_now(const ecut_server *srv) { return srv ? srv->now() : 0.0; }
 
 void ecut_server_destroy(ecut_server *srv) {
     if (!srv) return;
+    // queued requests are dropped; the helper may be building one of them,
+    // so they stay alive (out of the queue) until both threads have ended
+    std::deque<std::unique_ptr<Request>> dropped;
     {
         std::lock_guard<std::mutex> g(srv->mu);
         srv->stop = true;
-        srv->queue.clear();
+        dropped.swap(srv->queue);
         srv->cv.notify_all();
+        srv->cv_help.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
+    {
+        std::lock_guard<std::mutex> g(srv->mu);
+        srv->cv_help.notify_all();
+    }
+    if (srv->helper.joinable()) srv->helper.join();
+    for (ecut_sectors *s : srv->graveyard) ecut_sectors_free(s);
+    srv->graveyard.clear();
+    dropped.clear();
     srv->stg.release();
     hipStreamSynchronize(srv->stream);
     hipStreamDestroy(srv->stream);

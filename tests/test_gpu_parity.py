@@ -562,6 +562,7 @@ def test_server_batched_vs_alone_vs_oracle(dev):
         # every server tunes each new problem shape once (shared by all of them)
         srv = ecut.Server(2 << 30, max_active=(1 if alone else 0), max_steps=600, tol=1e-10,
                           sequential=alone, use_graph=mode.endswith("graph"), autotune=True)
+        print(f"[server] mode {mode}", flush=True)
         ids = [srv.submit(p, seed=1000 + k) for k, p in enumerate(reqs)]
         srv.drain()
         res = {r["req_id"]: r for r in srv.poll()}
