@@ -382,6 +382,58 @@ def summarize_serving(trace_dir, window, command):
     return path
 
 
+def summarize_solve(trace_dir, bench_json, command):
+    """profiles/lanczos_reorth_hubbard16_trace.txt: the kernels of the
+    ground-state solve (full reorthogonalisation) from a rocprofv3 kernel trace
+    of a bench run, and the streaming rate of the projection kernels.  Their
+    first pass at step j reads j + 1 basis vectors, so the median growth of
+    the launch time from one step to the next is the time of one vector."""
+    import csv
+    import numpy as np
+    res = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    gs, dim = res["ground_state"], res["config"]["dim"]
+    rows = []
+    for fn in os.listdir(trace_dir):
+        if fn.endswith("kernel_trace.csv"):
+            with open(os.path.join(trace_dir, fn)) as f:
+                rows += list(csv.DictReader(f))
+    for r in rows:
+        r["k"] = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        r["t0"], r["t1"] = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+    proj = [r for r in rows if r["k"].startswith(("ecut::k_multidot<", "ecut::k_multiaxpy<"))]
+    t0, t1 = min(r["t0"] for r in proj), max(r["t1"] for r in proj)
+    win = [r for r in rows if t0 <= r["t0"] <= t1]
+    per = {}
+    for r in win:
+        n, tot = per.get(r["k"], (0, 0))
+        per[r["k"]] = (n + 1, tot + r["t1"] - r["t0"])
+    busy = sum(v[1] for v in per.values())
+    vec_bytes = 8.0 * dim
+    lines = ["# rocprofv3 kernel trace: ground-state solve, 16-site Hubbard chain (dim 165,636,900), "
+             f"full reorthogonalisation over at most {gs['n_keep']} vectors", "",
+             "command (from the repository root):", "  cd /tmp && export TMPDIR=/tmp && cd -", "  " + command, "",
+             f"solve: {gs['steps']} steps, {gs['restarts']} restart(s), {gs['seconds']} s (bench clock), "
+             f"|E - E_oracle| = {gs.get('abs_diff_vs_oracle')}",
+             f"kernels between the first and last projection launch: {len(win)}, {busy / 1e9:.3f} s of kernel time", "",
+             f"{'kernel':40s} {'calls':>7s} {'total_ms':>10s} {'share':>7s}  per added basis vector"]
+    for k, (n, tot) in sorted(per.items(), key=lambda kv: -kv[1][1])[:10]:
+        extra = ""
+        if k in ("ecut::k_multidot<true>", "ecut::k_multiaxpy<true>"):
+            d = np.array([r["t1"] - r["t0"] for r in sorted((r for r in win if r["k"] == k), key=lambda r: r["t0"])],
+                         dtype=float)
+            d = d[d > 20e3]   # first passes (a skipped second pass returns at once)
+            inc = np.diff(d)
+            inc = inc[inc > 0]   # a restart shortens the basis
+            if len(inc):
+                m = float(np.median(inc))
+                extra = f"  {m / 1e3:.1f} us = {vec_bytes / m / 1e3:.2f} TB/s"
+        lines.append(f"{k[:40]:40s} {n:7d} {tot / 1e6:10.1f} {100.0 * tot / max(busy, 1):6.1f}%{extra}")
+    path = os.path.join(ROOT, "profiles", "lanczos_reorth_hubbard16_trace.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -406,9 +458,14 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=24.0)
     ap.add_argument("--serving-trace", action="store_true",
                     help="run only the batched serving closed loop (for a kernel trace) and print its window")
+    ap.add_argument("--summarize-solve", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="write profiles/lanczos_reorth_hubbard16_trace.txt from a kernel trace of a bench run")
     ap.add_argument("--summarize-serving", nargs=2, metavar=("TRACE_DIR", "WINDOW_JSON"),
                     help="write profiles/serving_c5_batched32_trace.txt from a --serving-trace kernel trace")
     args = ap.parse_args()
+    if args.summarize_solve:
+        print(summarize_solve(args.summarize_solve[0], args.summarize_solve[1], args.commands or ""))
+        return
     if args.summarize_serving:
         w = json.loads(open(args.summarize_serving[1]).read().strip().splitlines()[-1])
         print(summarize_serving(args.summarize_serving[0], w["window_ns"], args.commands or ""))

@@ -1502,36 +1502,76 @@ __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restr
     }
 }
 
+// Reorthogonalisation kernels.  One work group per chunk of VEC_CHUNK
+// elements (512 threads x 16 elements); a thread's chunk of y stays in
+// registers while the basis vectors stream past it.  Element pair t of a
+// thread is (i0 + 2 (tid + 512 t), i0 + 2 (tid + 512 t) + 1); with V2 (every
+// vector 16-byte aligned, even ld) a pair is one 16-byte load.
+constexpr int CGS_THREADS = 512;
+constexpr int CGS_PAIRS = (int)(VEC_CHUNK / (2 * CGS_THREADS));
+static_assert(2 * CGS_THREADS * CGS_PAIRS == VEC_CHUNK, "one chunk per work group");
+
+template <bool V2>
+__device__ __forceinline__ void cgs_load(const double *__restrict__ p, int64_t i0, int64_t i1, double2 (&v)[CGS_PAIRS]) {
+#pragma unroll
+    for (int t = 0; t < CGS_PAIRS; ++t) {
+        const int64_t e = i0 + 2 * (int64_t)(threadIdx.x + CGS_THREADS * t);
+        if (e + 1 < i1)
+            v[t] = V2 ? *(const double2 *)(p + e) : make_double2(p[e], p[e + 1]);
+        else
+            v[t] = make_double2(e < i1 ? p[e] : 0.0, 0.0);
+    }
+}
+
 // Classical Gram-Schmidt, dot phase: partials[k * n_chunks + chunk] = <w_k, y> over the chunk.
 // gate (nullable): when it points to 0.0 the kernel does nothing (the
-// conditional second pass of the reorthogonalisation)
-__global__ __launch_bounds__(VEC_THREADS) void k_multidot(const double *__restrict__ basis, int64_t ld, int nvec,
+// conditional second pass of the reorthogonalisation).  The per-wave sums of
+// eight vectors are reduced across the group together, behind one barrier.
+template <bool V2>
+__global__ __launch_bounds__(CGS_THREADS) void k_multidot(const double *__restrict__ basis, int64_t ld, int nvec,
                                                           const double *__restrict__ y, int64_t n,
                                                           double *__restrict__ partials, int n_chunks,
                                                           const double *__restrict__ gate) {
     if (gate && *gate == 0.0) return;
-    __shared__ double red[VEC_THREADS / 64];
+    constexpr int NW = CGS_THREADS / 64;
+    __shared__ double red[2][8][NW];   // two buffers: a group writes one while the other is read
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const int64_t i0 = (int64_t)c * VEC_CHUNK;
         const int64_t i1 = i0 + VEC_CHUNK < n ? i0 + VEC_CHUNK : n;
-        for (int k = 0; k < nvec; k += 8) {
+        double2 yv[CGS_PAIRS];
+        cgs_load<V2>(y, i0, i1, yv);
+        int g = 0;
+        for (int k0 = 0; k0 < nvec; k0 += 8, g ^= 1) {
             double s[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) s[q] = 0.0;
-            for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-                const double yv = y[i];
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (k + q < nvec) s[q] += basis[(int64_t)(k + q) * ld + i] * yv;
-            }
-#pragma unroll
             for (int q = 0; q < 8; ++q) {
-                if (k + q < nvec) {
-                    const double t = block_sum(s[q], red);
-                    if (threadIdx.x == 0) partials[(int64_t)(k + q) * n_chunks + c] = t;
+                s[q] = 0.0;
+                if (k0 + q < nvec) {
+                    double2 b[CGS_PAIRS];
+                    cgs_load<V2>(basis + (int64_t)(k0 + q) * ld, i0, i1, b);
+#pragma unroll
+                    for (int t = 0; t < CGS_PAIRS; ++t) {
+                        s[q] += b[t].x * yv[t].x;
+                        s[q] += b[t].y * yv[t].y;
+                    }
                 }
             }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s[q] = wave_sum(s[q]);
+            if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) red[g][q][wid] = s[q];
+            }
+            __syncthreads();
+            if (threadIdx.x < 8 && k0 + (int)threadIdx.x < nvec) {
+                double r = 0.0;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) r += red[g][threadIdx.x][w];
+                partials[(int64_t)(k0 + threadIdx.x) * n_chunks + c] = r;
+            }
         }
+        __syncthreads();   // red is written again by the next chunk
     }
 }
 
@@ -1548,26 +1588,58 @@ __global__ __launch_bounds__(VEC_THREADS) void k_multidot_reduce(const double *_
     if (threadIdx.x == 0) coef[k] = s * scale[k];
 }
 
-// y <- y - sum_k coef[k] * scale_k * w_k ; optional norm partials
-__global__ __launch_bounds__(VEC_THREADS) void k_multiaxpy(const double *__restrict__ basis, int64_t ld, int nvec,
+// y <- y - sum_k coef[k] * scale_k * w_k (sign != 0), or y <- sum_k ... (sign
+// == 0); optional norm partials of the result per chunk.  Each element sums
+// its terms in order k = 0, 1, ...  Capped at four waves per SIMD (at most
+// 128 registers): the uncapped build holds more loads in flight but runs one
+// group per compute unit, and streams the basis about 25% slower.
+template <bool V2>
+__global__ __launch_bounds__(CGS_THREADS, 4) void k_multiaxpy(const double *__restrict__ basis, int64_t ld, int nvec,
                                                            const double *__restrict__ coef, const double *__restrict__ scale,
                                                            double *__restrict__ y, int64_t n, double *__restrict__ partials,
                                                            int n_chunks, double sign, const double *__restrict__ gate) {
     if (gate && *gate == 0.0) return;
-    __shared__ double red[VEC_THREADS / 64];
+    __shared__ double red[CGS_THREADS / 64];
     __shared__ double cs[MAX_BASIS];
     for (int k = threadIdx.x; k < nvec; k += blockDim.x) cs[k] = coef[k] * scale[k];
     __syncthreads();
     for (int c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const int64_t i0 = (int64_t)c * VEC_CHUNK;
         const int64_t i1 = i0 + VEC_CHUNK < n ? i0 + VEC_CHUNK : n;
+        double2 v[CGS_PAIRS];
+#pragma unroll
+        for (int t = 0; t < CGS_PAIRS; ++t) v[t] = make_double2(0.0, 0.0);
+#pragma unroll 1
+        for (int k = 0; k < nvec; ++k) {
+            double2 b[CGS_PAIRS];
+            cgs_load<V2>(basis + (int64_t)k * ld, i0, i1, b);
+            const double ck = cs[k];
+#pragma unroll
+            for (int t = 0; t < CGS_PAIRS; ++t) {
+                v[t].x += ck * b[t].x;
+                v[t].y += ck * b[t].y;
+            }
+        }
+        double2 yo[CGS_PAIRS];
+        if (sign != 0.0) cgs_load<V2>(y, i0, i1, yo);
         double s = 0.0;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-            double v = 0.0;
-            for (int k = 0; k < nvec; ++k) v += cs[k] * basis[(int64_t)k * ld + i];
-            const double yv = (sign != 0.0) ? y[i] - v : v;
-            y[i] = yv;
-            s += yv * yv;
+#pragma unroll
+        for (int t = 0; t < CGS_PAIRS; ++t) {
+            const int64_t e = i0 + 2 * (int64_t)(threadIdx.x + CGS_THREADS * t);
+            const double2 r = sign != 0.0 ? make_double2(yo[t].x - v[t].x, yo[t].y - v[t].y) : v[t];
+            if (e + 1 < i1) {
+                if (V2) {
+                    *(double2 *)(y + e) = r;
+                } else {
+                    y[e] = r.x;
+                    y[e + 1] = r.y;
+                }
+                s += r.x * r.x;
+                s += r.y * r.y;
+            } else if (e < i1) {
+                y[e] = r.x;
+                s += r.x * r.x;
+            }
         }
         if (partials) {
             s = block_sum(s, red);
@@ -1722,11 +1794,20 @@ hipError_t launch_axpy_norm(const VecJob *jobs_d, const int32_t *chunk_job_d, co
     return hipGetLastError();
 }
 
+// 16-byte loads need every vector (base + k ld) and y 16-byte aligned
+static bool cgs_aligned(const double *basis, int64_t ld, const double *y) {
+    return ((((uintptr_t)basis | (uintptr_t)y) & 15) == 0) && (ld & 1) == 0;
+}
+
 hipError_t launch_multidot(const double *basis, int64_t ld, int nvec, const double *y, int64_t n, double *partials,
                            int n_chunks, hipStream_t st, const double *gate) {
-    int grid = n_chunks < 8192 ? n_chunks : 8192;
-    hipLaunchKernelGGL(k_multidot, dim3(grid), dim3(VEC_THREADS), 0, st, basis, ld, nvec, y, n, partials, n_chunks,
-                       gate);
+    const int grid = n_chunks < 1 ? 1 : (n_chunks < 65536 ? n_chunks : 65536);
+    if (cgs_aligned(basis, ld, y))
+        hipLaunchKernelGGL(k_multidot<true>, dim3(grid), dim3(CGS_THREADS), 0, st, basis, ld, nvec, y, n, partials,
+                           n_chunks, gate);
+    else
+        hipLaunchKernelGGL(k_multidot<false>, dim3(grid), dim3(CGS_THREADS), 0, st, basis, ld, nvec, y, n, partials,
+                           n_chunks, gate);
     return hipGetLastError();
 }
 
@@ -1739,9 +1820,13 @@ hipError_t launch_multidot_reduce(const double *partials, int n_chunks, int nvec
 hipError_t launch_multiaxpy(const double *basis, int64_t ld, int nvec, const double *coef, const double *scale,
                             double *y, int64_t n, double *partials, int n_chunks, double sign, hipStream_t st,
                             const double *gate) {
-    int grid = n_chunks < 8192 ? n_chunks : 8192;
-    hipLaunchKernelGGL(k_multiaxpy, dim3(grid), dim3(VEC_THREADS), 0, st, basis, ld, nvec, coef, scale, y, n, partials,
-                       n_chunks, sign, gate);
+    const int grid = n_chunks < 1 ? 1 : (n_chunks < 65536 ? n_chunks : 65536);
+    if (cgs_aligned(basis, ld, y))
+        hipLaunchKernelGGL(k_multiaxpy<true>, dim3(grid), dim3(CGS_THREADS), 0, st, basis, ld, nvec, coef, scale, y, n,
+                           partials, n_chunks, sign, gate);
+    else
+        hipLaunchKernelGGL(k_multiaxpy<false>, dim3(grid), dim3(CGS_THREADS), 0, st, basis, ld, nvec, coef, scale, y,
+                           n, partials, n_chunks, sign, gate);
     return hipGetLastError();
 }
 

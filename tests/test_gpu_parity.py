@@ -506,6 +506,32 @@ def test_lanczos_reorth_ground_state_vector(dev):
     assert np.linalg.norm(hg - e * g) <= 1e-6
 
 
+def test_lanczos_reorth_unaligned_workspace_odd_dim(dev):
+    """Full reorthogonalisation on a workspace that is 8- but not 16-byte
+    aligned (the projection kernels then take their scalar-load path), on a
+    sector of odd dimension (a one-element tail in the last chunk): the same
+    energy, steps and ground state bit for bit as on an aligned workspace, and
+    the oracle's energy."""
+    import torch
+    p = I.Problem(I.xxz_chain(15, 1.0, 0.6), I.Cut("spatial", I.left_mask_first(7)), 7)
+    s = O.Sector(p.model, 7)
+    assert s.n % 2 == 1
+    ref = s.lanczos(I.psi(3, s.n), 600, tol=1e-14)[0][-1]
+    S = _ecut().Sectors.from_problem(p)
+    v0 = torch.from_numpy(I.psi(9, s.n)).to(dev)
+    nws = S.lanczos_workspace(80, reorth=True, max_restarts=4, tol=1e-11)
+    buf = torch.full((nws + 2,), float("nan"), dtype=torch.float64, device=dev)
+    out = []
+    for off in (0, 1):
+        ws = buf[off:off + nws]
+        assert (ws.data_ptr() % 16 == 0) == (off == 0)
+        e, st, gs = S.lanczos(v0, 80, tol=1e-11, reorth=True, max_restarts=4, want_gs=True, workspace=ws)
+        out.append((e, st["steps"], S.export(gs).cpu().numpy()))
+    assert out[0][0] == out[1][0] and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
+    assert abs(out[0][0] - ref) <= 1e-10
+
+
 def test_lanczos_u0_hubbard16_closed_form(dev):
     """16-site chain at U=0 (the headline geometry): free-fermion energy."""
     import torch
