@@ -410,6 +410,32 @@ const char *ecut_last_error(void);
 /* Library version string. */
 const char *ecut_version(void);
 
+/* ---------------------------------------------------------------------------
+ * Device memory for the sector tables.
+ * Each handle keeps its tables (basis words, operator CSR, work lists, rank
+ * tables) in one block of device memory the library allocates, with
+ * hipMalloc unless the caller installs an allocator here: for instance one
+ * backed by torch's caching allocator, so that the tables share its pool.
+ *   alloc(bytes, device, user): at least `bytes` of device memory on HIP
+ *     device `device` (the current device at the call), 256-byte aligned, or
+ *     NULL.  NULL fails the building call with ECUT_ENOMEM; a misaligned
+ *     block is handed back to free and the call fails with ECUT_EINVAL.
+ *   free(ptr, bytes, device, user): releases a block alloc returned.  The
+ *     library synchronises the device first, so no kernel still reads it.
+ * Each block is released through the pair that made it: the pair may be
+ * replaced at any time, but must stay callable while any block it made is
+ * alive.  Both may be called from any thread, including the server's own.
+ * Passing NULL, NULL restores hipMalloc / hipFree.  Not covered: the
+ * server's arena (one hipMalloc of hbm_budget at create), the library's
+ * per-device constant tables (kept until the process ends), its
+ * launch-descriptor buffers (kept per thread and per server), and the
+ * caller's own vectors and workspaces.
+ * Errors: ECUT_EINVAL if exactly one of alloc and free is NULL.
+ * ------------------------------------------------------------------------- */
+typedef void *(*ecut_alloc_fn)(size_t bytes, int32_t device, void *user);
+typedef void (*ecut_free_fn)(void *ptr, size_t bytes, int32_t device, void *user);
+ecut_status ecut_set_allocator(ecut_alloc_fn alloc, ecut_free_fn free_fn, void *user);
+
 #ifdef __cplusplus
 }
 #endif

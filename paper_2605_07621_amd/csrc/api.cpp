@@ -101,12 +101,71 @@ struct Arena {
 };
 }  // namespace
 
+// ---------------------------------------------------------------- table memory
+// The sector tables of a handle come from the caller's allocator when one is
+// set (ecut_set_allocator), else from hipMalloc.  Each allocation remembers
+// the pair that made it, so it is released through that pair even after the
+// caller installs another one.
+namespace {
+struct MetaAlloc {
+    ecut_alloc_fn alloc = nullptr;
+    ecut_free_fn free = nullptr;
+    void *user = nullptr;
+};
+std::mutex g_alloc_mu;
+MetaAlloc g_alloc;
+std::map<void *, std::pair<MetaAlloc, size_t>> g_alloc_owner;   // live allocations of callers' allocators
+}  // namespace
+
+static ecut_status table_alloc(void **p, size_t bytes, int device) {
+    MetaAlloc a;
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        a = g_alloc;
+    }
+    if (!a.alloc) {
+        const hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) return fail(ECUT_ENOMEM, std::string("hipMalloc(sector tables): ") + hipGetErrorString(e));
+        return ECUT_OK;
+    }
+    void *m = a.alloc(bytes, device, a.user);
+    if (!m) return fail(ECUT_ENOMEM, "the caller's allocator returned NULL for the sector tables");
+    if ((uintptr_t)m & 255) {
+        a.free(m, bytes, device, a.user);
+        return fail(ECUT_EINVAL, "the caller's allocator returned memory that is not 256-byte aligned");
+    }
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc_owner[m] = {a, bytes};
+    *p = m;
+    return ECUT_OK;
+}
+
+static void table_free(void *p, int device) {
+    MetaAlloc a;
+    size_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> g(g_alloc_mu);
+        auto it = g_alloc_owner.find(p);
+        if (it == g_alloc_owner.end()) {
+            (void)hipFree(p);
+            return;
+        }
+        a = it->second.first;
+        bytes = it->second.second;
+        g_alloc_owner.erase(it);
+    }
+    // hipFree waits for the device; a caller's free may hand the memory out
+    // again at once, so kernels still reading the tables must finish first
+    (void)hipDeviceSynchronize();
+    a.free(p, bytes, device, a.user);
+}
+
 void release_device(ecut_sectors *s) {
     if (s->dev_mem) {
         int cur = 0;
         hipGetDevice(&cur);
         if (s->device >= 0 && s->device != cur) (void)hipSetDevice(s->device);
-        (void)hipFree(s->dev_mem);
+        table_free(s->dev_mem, s->device >= 0 ? s->device : cur);
         if (s->device >= 0 && s->device != cur) (void)hipSetDevice(cur);
     }
     s->dev_mem = nullptr;
@@ -190,12 +249,13 @@ ecut_status upload(ecut_sectors *s) {
         o_5it = A.add(s->hs_items);
     }
     void *mem = nullptr;
-    hipError_t e = hipMalloc(&mem, A.off);
-    if (e != hipSuccess) return fail(ECUT_ENOMEM, std::string("hipMalloc(sector tables): ") + hipGetErrorString(e));
+    st = table_alloc(&mem, A.off, dev);
+    if (st != ECUT_OK) return st;
+    hipError_t e = hipSuccess;
     for (auto &p : A.pieces) {
         e = hipMemcpy((char *)mem + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            hipFree(mem);
+            table_free(mem, dev);
             return hip_fail(e, "hipMemcpy(sector tables)");
         }
     }
@@ -537,6 +597,13 @@ extern "C" {
 const char *ecut_last_error(void) { return g_err.c_str(); }
 
 const char *ecut_version(void) { return "ecut 0.1 (gfx950)"; }
+
+ecut_status ecut_set_allocator(ecut_alloc_fn alloc, ecut_free_fn free_fn, void *user) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(ECUT_EINVAL, "alloc and free must both be set or both be NULL");
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    g_alloc = MetaAlloc{alloc, free_fn, user};
+    return ECUT_OK;
+}
 
 ecut_status ecut_build_sectors(const ecut_model_desc *model, const ecut_cut_desc *cut, ecut_qnum q, uint32_t flags,
                                ecut_sectors **out) {

@@ -82,6 +82,10 @@ class Result(ctypes.Structure):
 
 
 # (name, restype, argtypes) of every entry point declared in include/ecut.h
+# ecut_alloc_fn / ecut_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(_vp, _sz, _i32, _vp)
+FREE_FN = ctypes.CFUNCTYPE(None, _vp, _sz, _i32, _vp)
+
 SYMBOLS = [
     ("ecut_build_sectors", _i32, [ctypes.POINTER(ModelDesc), ctypes.POINTER(CutDesc), QNum, _u32, ctypes.POINTER(_vp)]),
     ("ecut_sectors_free", None, [_vp]),
@@ -106,11 +110,13 @@ SYMBOLS = [
     ("ecut_server_drain", _i32, [_vp]),
     ("ecut_server_now", _dbl, [_vp]),
     ("ecut_server_destroy", None, [_vp]),
+    ("ecut_set_allocator", _i32, [ALLOC_FN, FREE_FN, _vp]),
     ("ecut_last_error", ctypes.c_char_p, []),
     ("ecut_version", ctypes.c_char_p, []),
 ]
 
 _lib = None
+_allocators = []   # every pair ever installed: blocks they made are released through them
 
 
 def lib():
@@ -284,6 +290,36 @@ class Sectors:
         stats = dict(steps=stt.steps, restarts=stt.restarts, converged=stt.converged, residual=stt.residual,
                      seconds=stt.seconds, status=st)
         return e.value, stats, gs
+
+
+def set_allocator(alloc=None, free=None):
+    """ecut_set_allocator: alloc(nbytes, device) -> device address (int, 0 on
+    failure) and free(ptr, nbytes, device) back the sector tables of handles
+    built from now on; set_allocator() restores hipMalloc / hipFree.  The
+    callbacks are kept alive for the life of the process."""
+    if (alloc is None) != (free is None):
+        raise ValueError("alloc and free must both be given or both be None")
+    if alloc is None:
+        _check(lib().ecut_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+    a = ALLOC_FN(lambda nbytes, device, user: alloc(nbytes, device) or None)
+    f = FREE_FN(lambda ptr, nbytes, device, user: free(ptr, nbytes, device))
+    _allocators.append((a, f))
+    _check(lib().ecut_set_allocator(a, f, None))
+
+
+def torch_allocator():
+    """An (alloc, free) pair for set_allocator backed by torch's CUDA caching
+    allocator (on the current stream of the device at allocation)."""
+    import torch
+
+    def alloc(nbytes, device):
+        return torch.cuda.caching_allocator_alloc(nbytes, device)
+
+    def free(ptr, nbytes, device):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
 
 
 def apply_batch(sectors, psis, ys, stream=None):

@@ -624,3 +624,62 @@ def test_server_budget_admission(dev):
     assert res[ids[3]]["status"] == ecut.ECUT_ENOMEM
     e = [res[i]["energy"] for i in ids[:3]]
     assert max(e) - min(e) <= 1e-10
+
+
+def test_caller_allocator_backs_sector_tables(dev):
+    """ecut_set_allocator: sector tables taken from torch's caching allocator
+    give the same H*psi bit for bit; a server builds and frees its requests'
+    tables through the callbacks from its own threads; every block goes back
+    through the pair that made it; a block that is not 256-byte aligned is
+    refused and handed back."""
+    import torch
+    E = _ecut()
+    ta, tf = E.torch_allocator()
+    live, log = {}, []
+
+    def alloc(n, d):
+        ptr = ta(n, d)
+        live[ptr] = n
+        log.append("a")
+        return ptr
+
+    def free(ptr, n, d):
+        assert live.pop(ptr) == n
+        log.append("f")
+        tf(ptr, n, d)
+
+    probs = [I.Problem(I.xxz_chain(12, 1.0, 0.7), I.Cut("spatial", I.left_mask_first(6)), 6),
+             I.Problem(I.hubbard_chain(8, 1.0, 6.0), I.Cut("updn"), 4, 4)]
+    refs = []
+    for p in probs:
+        S = E.Sectors.from_problem(p)
+        x = torch.from_numpy(I.psi(5, S.dim)).to(dev)
+        refs.append((x, S.apply(x).cpu()))
+        S.close()
+    E.set_allocator(alloc, free)
+    try:
+        for p, (x, yref) in zip(probs, refs):
+            S = E.Sectors.from_problem(p)
+            assert len(live) == 1
+            y = S.apply(x).cpu()
+            S.close()
+            assert torch.equal(y, yref)
+        assert not live
+        srv = E.Server(1 << 30, max_steps=300, tol=1e-10)
+        ids = [srv.submit(p, seed=7 + k) for k, p in enumerate(probs)]
+        srv.drain()
+        res = srv.poll()
+        srv.close()
+        assert sorted(r["req_id"] for r in res) == sorted(ids)
+        assert all(r["status"] == 0 for r in res)
+        assert not live and log.count("a") == log.count("f") == 4
+        E.set_allocator(lambda n, d: ta(n + 256, d) + 8, lambda ptr, n, d: tf(ptr - 8, n, d))
+        with pytest.raises(E.EcutError) as err:
+            E.Sectors.from_problem(probs[0])
+        assert err.value.status == E.ECUT_EINVAL
+    finally:
+        E.set_allocator()
+    S = E.Sectors.from_problem(probs[0])
+    y = S.apply(refs[0][0]).cpu()
+    S.close()
+    assert torch.equal(y, refs[0][1])

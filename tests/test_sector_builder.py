@@ -29,6 +29,19 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in L.ecut_version()
 
 
+def test_set_allocator_argument_checks():
+    """ecut_set_allocator takes both callbacks or neither (no device work)."""
+    L = E.lib()
+    assert L.ecut_set_allocator(E.ALLOC_FN(lambda n, d, u: None), E.FREE_FN(), None) == E.ECUT_EINVAL
+    assert b"both" in L.ecut_last_error()
+    assert L.ecut_set_allocator(E.ALLOC_FN(), E.FREE_FN(lambda p, n, d, u: None), None) == E.ECUT_EINVAL
+    assert L.ecut_set_allocator(E.ALLOC_FN(), E.FREE_FN(), None) == E.ECUT_OK
+    with pytest.raises(ValueError):
+        E.set_allocator(lambda n, d: 0, None)
+    E.set_allocator(lambda n, d: 0, lambda p, n, d: None)
+    E.set_allocator()
+
+
 def _oracle_blocks_and_pos(p):
     s = O.Sector(p.model, p.n_up, p.n_dn)
     pos, blocks = s.bipartite(p.cut.kind, p.cut.left_mask)
