@@ -712,8 +712,20 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
         if (lp >= 0) {
             const BlockDev S = P.blocks[src];
             const double *__restrict__ srow = P.x + S.offset + (int64_t)lp * S.d_r;
+            // every row of a problem on this kernel fits NT * M elements; all
+            // loads of the row are in flight before the barrier
+            double sv[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int e = tid + m * NT;
+                sv[m] = e < S.d_r ? srow[e] : 0.0;
+            }
             __syncthreads();   // earlier readers of xs are done
-            for (int e = tid; e < S.d_r; e += NT) xs[e] = srow[e];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int e = tid + m * NT;
+                if (e < S.d_r) xs[e] = sv[m];
+            }
             __syncthreads();
             for (int kk = k; kk < k1; ++kk) {
                 const int rj = P.xbond[kk].rj;
