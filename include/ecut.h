@@ -243,13 +243,20 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
  *              the generic row kernel) or 1 (the generic row kernel, which
  *              reads the right operator's CSR); n_xcd and row_order are
  *              ignored for them;
- *   tile:      spin problems (kernel_flags bit 2) only, else it must be 0:
- *              the work items of the sector queue are single rows for rows
+ *   tile:      Hubbard variant 4: threads per work group, 256, 512 or 1024
+ *              (0 = 1024); a row must fit 14 columns per thread (2 x 7
+ *              column pairs), and smaller groups put more rows in flight on a
+ *              CU.  For it, grid = work groups (0 = as many as fit on the
+ *              device).  Every group size sums the terms of an amplitude in
+ *              the same order, so the vector is the same bit for bit.
+ *              Spin problems (kernel_flags bit 2): the work items of the
+ *              sector queue are single rows for rows
  *              longer than tile/2 amplitudes, and runs of shorter rows of at
  *              most `tile` amplitudes otherwise (0 = 512, at most 512).
  *              Smaller tiles give more, smaller items; the Lanczos
  *              workspace (ecut_lanczos_workspace) holds the per-item partial
- *              sums of the smallest tile, so it does not change with tuning.  For the spin kernel, grid is
+ *              sums of the smallest tile, so it does not change with tuning.
+ *              Any other problem or variant takes tile 0.  For the spin kernel, grid is
  *              the number of work groups that stride through the item queue
  *              (0 = min(items, 2048)); the generic row kernel ignores it.
  * ecut_set_tuning re-uploads the row order or the work items (synchronous).

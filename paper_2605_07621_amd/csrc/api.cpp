@@ -428,8 +428,8 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
         } else if (T.variant == 4 && s->hubrow_ok) {
             if (((uintptr_t)P.x | (uintptr_t)P.y | (uintptr_t)P.z) & 15)
                 return fail(ECUT_EINVAL, "the whole-row kernel needs 16-byte aligned vectors");
-            const int grid = T.grid > 0 ? T.grid : n_cu;
-            e = launch_hubrow(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd == 8 ? 8 : 1, st);
+            e = launch_hubrow(s, P, s->dev_row_order, s->blocks[0].d_l, T.grid, n_xcd == 8 ? 8 : 1,
+                              T.tile > 0 ? T.tile : 1024, n_cu, st);
         } else if ((T.variant == 0 || T.variant == 2) && s->hub2_ok) {
             const size_t lds = hub2_lds_bytes(s);
             if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "class tiles exceed the device's LDS per work group");

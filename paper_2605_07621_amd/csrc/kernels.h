@@ -96,9 +96,11 @@ hipError_t launch_hubseg(const ecut_sectors *s, const HubSegArgs &args, int grid
 hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, bool split, int slab_grid,
                        hipStream_t st);
 int hub_blocks_per_cu(int which, size_t lds);
-// whole-row Hubbard kernel: rows_d lists the rows in processing order
+// whole-row Hubbard kernel: rows_d lists the rows in processing order;
+// threads per work group 256, 512 or 1024 (rows of at most 2 * HUBROW_P *
+// threads columns); grid 0 = as many groups as fit on n_cu compute units
 hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
-                         int n_xcd, hipStream_t st);
+                         int n_xcd, int threads, int n_cu, hipStream_t st);
 // Hubbard block whose columns are a permutation of the canonical down ranks
 hipError_t launch_perm_cols(const int32_t *col_d, int64_t n_rows, int dR, const double *in, double *out, bool to_bip,
                             hipStream_t st);

@@ -510,21 +510,22 @@ __device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32
 // contiguous chunk of the row order, so the rows in flight on one XCD are
 // neighbours in that order (their shared neighbour rows can hit its L2);
 // n_xcd == 1: plain grid stride.
-__global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P, const int32_t *__restrict__ rows,
-                                                              int n_rows, int dR, int n_xcd) {
+template <int NT>
+__global__ __launch_bounds__(NT, 4) void k_hubrow(const ProblemDev P, const int32_t *__restrict__ rows, int n_rows,
+                                                  int dR, int n_xcd) {
     const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
     extern __shared__ __align__(16) double xs[];
     __shared__ int32_t rl[256];
     __shared__ int32_t rh[256 * 9];
     __shared__ uint32_t bm[HUBROW_MAX_BOND], bb[HUBROW_MAX_BOND];
     __shared__ double bc[HUBROW_MAX_BOND];
-    __shared__ double red[HUBROW_THREADS / 64];
+    __shared__ double red[NT / 64];
     const HubDev &H = P.hub;
     const int tid = threadIdx.x;
     const int n_bond = H.n_dbond;
-    for (int i = tid; i < 256; i += HUBROW_THREADS) rl[i] = H.rank_lo[i];
-    for (int i = tid; i < 256 * 9; i += HUBROW_THREADS) rh[i] = H.rank_hi[i];
-    for (int i = tid; i < n_bond; i += HUBROW_THREADS) {
+    for (int i = tid; i < 256; i += NT) rl[i] = H.rank_lo[i];
+    for (int i = tid; i < 256 * 9; i += NT) rh[i] = H.rank_hi[i];
+    for (int i = tid; i < n_bond; i += NT) {
         bm[i] = H.dbond_mask[i];
         bb[i] = H.dbond_betw[i];
         bc[i] = H.dbond_coef[i];
@@ -532,7 +533,7 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
     const int np = dR >> 1;
     double2 *xs2 = (double2 *)xs;
     uint16_t *colmap = (uint16_t *)(xs + dR);   // column of each canonical down rank
-    for (int i = tid; i < dR; i += HUBROW_THREADS) colmap[i] = (uint16_t)H.col_of_rank[i];
+    for (int i = tid; i < dR; i += NT) colmap[i] = (uint16_t)H.col_of_rank[i];
     const uint32_t *__restrict__ wpairs = (const uint32_t *)H.rwords16;   // two 16-bit words per column pair
     const int xcd = blockIdx.x % n_xcd, slot = blockIdx.x / n_xcd, n_slot = gridDim.x / n_xcd;
     const int per = (n_rows + n_xcd - 1) / n_xcd;
@@ -545,14 +546,14 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
             double2 xv[HUBROW_P];
 #pragma unroll
             for (int m = 0; m < HUBROW_P; ++m) {
-                const int p = tid + m * HUBROW_THREADS;
+                const int p = tid + m * NT;
                 xv[m] = p < np ? xr[p] : make_double2(0.0, 0.0);
                 acc[m] = make_double2(0.0, 0.0);
             }
             __syncthreads();   // readers of the previous row are done (and the tables are loaded)
 #pragma unroll
             for (int m = 0; m < HUBROW_P; ++m) {
-                const int p = tid + m * HUBROW_THREADS;
+                const int p = tid + m * NT;
                 if (p < np) xs2[p] = xv[m];
             }
         }
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
                 double2 v0[HUBROW_P], v1[HUBROW_P];
 #pragma unroll
                 for (int m = 0; m < HUBROW_P; ++m) {
-                    const int p = tid + m * HUBROW_THREADS;
+                    const int p = tid + m * NT;
                     const bool ok = p < np;
                     v0[m] = ok ? n0[p] : make_double2(0.0, 0.0);
                     v1[m] = ok && two ? n1[p] : make_double2(0.0, 0.0);
@@ -584,7 +585,7 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
         double part = 0.0;
 #pragma unroll
         for (int m = 0; m < HUBROW_P; ++m) {
-            const int p = tid + m * HUBROW_THREADS;
+            const int p = tid + m * NT;
             if (p >= np) continue;
             const uint32_t wp = wpairs[p];
             double yv[2], x0[2];
@@ -631,14 +632,29 @@ __global__ __launch_bounds__(HUBROW_THREADS, 4) void k_hubrow(const ProblemDev P
 }
 
 hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const int32_t *rows_d, int n_rows, int grid,
-                         int n_xcd, hipStream_t st) {
+                         int n_xcd, int threads, int n_cu, hipStream_t st) {
     const int dR = s->blocks[0].d_r;
-    if (dR % 2 != 0 || dR > HUBROW_COLS || !prob.hub.rwords16 || !prob.hub.col_of_rank) return hipErrorInvalidValue;
+    if (threads != 256 && threads != 512 && threads != 1024) return hipErrorInvalidValue;
+    if (dR % 2 != 0 || dR > 2 * HUBROW_P * threads || !prob.hub.rwords16 || !prob.hub.col_of_rank)
+        return hipErrorInvalidValue;
     if (n_xcd != 8) n_xcd = 1;
-    grid = std::max(n_xcd, (grid / n_xcd) * n_xcd);
     // the staged row, then the 16-bit rank -> column table
     const size_t lds = (size_t)dR * 8 + (size_t)dR * 2;
-    hipLaunchKernelGGL(k_hubrow, dim3(grid), dim3(HUBROW_THREADS), lds, st, prob, rows_d, n_rows, dR, n_xcd);
+    const void *fn = threads == 256 ? (const void *)k_hubrow<256>
+                     : threads == 512 ? (const void *)k_hubrow<512> : (const void *)k_hubrow<1024>;
+    if (grid <= 0) {
+        int per_cu = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
+        if (e != hipSuccess) return e;
+        grid = std::max(1, per_cu) * n_cu;
+    }
+    grid = std::max(n_xcd, (grid / n_xcd) * n_xcd);
+    if (threads == 256)
+        hipLaunchKernelGGL(k_hubrow<256>, dim3(grid), dim3(256), lds, st, prob, rows_d, n_rows, dR, n_xcd);
+    else if (threads == 512)
+        hipLaunchKernelGGL(k_hubrow<512>, dim3(grid), dim3(512), lds, st, prob, rows_d, n_rows, dR, n_xcd);
+    else
+        hipLaunchKernelGGL(k_hubrow<1024>, dim3(grid), dim3(1024), lds, st, prob, rows_d, n_rows, dR, n_xcd);
     return hipGetLastError();
 }
 
@@ -1753,7 +1769,11 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     const int b = (int)bytes;
     e = hipFuncSetAttribute((const void *)k_spin<true>, hipFuncAttributeMaxDynamicSharedMemorySize, SPIN_TILE * 8);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hubrow, hipFuncAttributeMaxDynamicSharedMemorySize, HUBROW_COLS * 10);
+    e = hipFuncSetAttribute((const void *)k_hubrow<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * HUBROW_P * 1024 * 10);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hubrow<512>, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * HUBROW_P * 512 * 10);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hubrow<256>, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * HUBROW_P * 256 * 10);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;

@@ -187,7 +187,7 @@ static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStr
 static constexpr int LOOKAHEAD = 16;
 
 void ecut_server::help() {
-    hipSetDevice(device);
+    const hipError_t dev_err = hipSetDevice(device);   // a failure fails every build
     std::unique_lock<std::mutex> lk(mu);
     while (true) {
         if (!graveyard.empty()) {
@@ -222,7 +222,8 @@ void ecut_server::help() {
         ecut_status st;
         {
             std::lock_guard<std::mutex> cg(lz_capture_mutex());
-            st = ecut_build_sectors(&R->model, &R->cut, R->q, 0, &s);
+            st = dev_err != hipSuccess ? hip_fail(dev_err, "hipSetDevice (server helper)")
+                                       : ecut_build_sectors(&R->model, &R->cut, R->q, 0, &s);
         }
         lk.lock();
         R->built = s;

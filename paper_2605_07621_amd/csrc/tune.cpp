@@ -76,8 +76,18 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 5)
         return fail(ECUT_EINVAL, "bad tuning");
     if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
-    if (T.tile < 0 || T.tile > SPIN_MANY_TILE) return fail(ECUT_EINVAL, "tile must lie in 0..512");
-    if (T.tile != 0 && !s->spin_ok) return fail(ECUT_EUNSUPPORTED, "the tile size applies to the spin kernel only");
+    if (T.tile < 0) return fail(ECUT_EINVAL, "tile must not be negative");
+    if (s->spin_ok) {
+        if (T.tile > SPIN_MANY_TILE) return fail(ECUT_EINVAL, "tile must lie in 0..512");
+    } else if (s->kernel == 1 && T.variant == 4) {
+        // the whole-row Hubbard kernel: tile = threads per work group
+        if (T.tile != 0 && T.tile != 256 && T.tile != 512 && T.tile != 1024)
+            return fail(ECUT_EINVAL, "whole-row work groups take 256, 512 or 1024 threads");
+        if (T.tile != 0 && !s->blocks.empty() && s->blocks[0].d_r > 2 * HUBROW_P * T.tile)
+            return fail(ECUT_EUNSUPPORTED, "rows longer than 14 columns per thread of the work group");
+    } else if (T.tile != 0) {
+        return fail(ECUT_EUNSUPPORTED, "the tile applies to the spin kernel and the whole-row Hubbard kernel only");
+    }
     if (s->spin_ok && T.order > 1) return fail(ECUT_EINVAL, "spin problems take row order 0 or 1");
     if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
         return fail(ECUT_EUNSUPPORTED, "class tiles not available");
@@ -170,8 +180,10 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
         for (int order : {0, 2})
             for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 1});
         if (s->hubrow_ok)
-            for (int order : {0, 1, 2, 9})
-                for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 4});
+            for (int threads : {1024, 512, 256})
+                if (threads == 1024 || s->blocks[0].d_r <= 2 * HUBROW_P * threads)
+                    for (int order : {0, 1, 2, 9})
+                        for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 4, threads == 1024 ? 0 : threads});
         if (s->hubseg_ok)
             for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, 0, 5});
     } else if (s->spin_ok) {

@@ -130,6 +130,37 @@ def test_hubbard_kernel_variants_and_orders(dev, variant, order):
         _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} v{variant} o{order}")
 
 
+def test_hubbard_whole_row_group_sizes(dev):
+    """The whole-row kernel (variant 4) with 256-, 512- and 1024-thread work
+    groups gives the same vector bit for bit, the oracle's on the small cases;
+    the 14-site chain (rows of 3,432 columns) runs at every group size."""
+    import torch
+    E = _ecut()
+    cases = list(_HUB_CASES) + [I.Problem(I.hubbard_chain(14, 1.0, 4.0), I.Cut("updn"), 7, 7)]
+    for k, p in enumerate(cases):
+        S = E.Sectors.from_problem(p)
+        if not S.info.kernel_flags & 8:
+            continue
+        d_r = int(S.blocks()[0][3])
+        x = torch.from_numpy(I.psi(600 + k, S.dim)).to(dev)
+        ys = {}
+        for threads in (1024, 512, 256):
+            if d_r > 14 * threads:
+                with pytest.raises(E.EcutError):
+                    S.set_tuning(0, 8, 0, 4, threads)
+                continue
+            S.set_tuning(0, 8, 9 if threads == 256 else 0, 4, 0 if threads == 1024 else threads)
+            ys[threads] = S.apply(x).cpu()
+        assert 256 in ys or d_r > 14 * 256
+        for threads, y in ys.items():
+            assert torch.equal(y, ys[1024]), (p.model.name, threads)
+        if S.dim <= 1 << 20:
+            s = O.Sector(p.model, p.n_up, p.n_dn)
+            psi = I.psi(700 + k, s.n)
+            S.set_tuning(0, 1, 0, 4, 256 if d_r <= 14 * 256 else 0)
+            _compare(_gpu_apply_canonical(S, psi, dev), s.apply(psi), f"{p.model.name} whole rows, small groups")
+
+
 @pytest.mark.parametrize("name", ["heisenberg16", "hubbard12"])
 def test_apply_workload_full_vs_oracle(dev, name):
     p = I.WORKLOADS[name]()

@@ -220,3 +220,22 @@ def test_spin_tile_tuning_host():
     G = E.Sectors.from_problem(I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", 0b111), 10), host_only=True)
     assert not G.info.kernel_flags & 4
     assert _status(lambda: G.set_tuning(0, 0, 0, 0, 64)) == E.ECUT_EUNSUPPORTED
+
+
+def test_whole_row_group_size_tuning_host():
+    """Hubbard variant 4 takes its work-group size in the tile field: 256,
+    512 or 1024 threads, as long as a row fits 14 columns per thread."""
+    H = E.Sectors.from_problem(I.hubbard12(), host_only=True)      # rows of 924 columns
+    assert H.info.kernel_flags & 8
+    for tile in (256, 512, 1024, 0):
+        H.set_tuning(0, 8, 0, 4, tile)
+        assert H.get_tuning()["tile"] == tile and H.get_tuning()["variant"] == 4
+    for bad in (-1, 128, 300, 2048):
+        assert _status(lambda: H.set_tuning(0, 8, 0, 4, bad)) == E.ECUT_EINVAL
+    assert _status(lambda: H.set_tuning(0, 8, 0, 0, 256)) == E.ECUT_EUNSUPPORTED   # other variants: tile 0
+    C3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)      # rows of 12,870 columns
+    assert C3.info.kernel_flags & 8
+    for tile in (256, 512):
+        assert _status(lambda: C3.set_tuning(0, 8, 0, 4, tile)) == E.ECUT_EUNSUPPORTED
+    C3.set_tuning(0, 8, 0, 4, 1024)
+    assert C3.get_tuning()["tile"] == 1024
