@@ -32,6 +32,7 @@ constexpr int SPIN_MANY_THREADS = 256;       // kernel for items of several shor
 constexpr int SPIN_MANY_TILE = 512;          // most amplitudes per such item: the default and largest tile
 constexpr int HUBROW_THREADS = 1024;
 constexpr int HUBROW_P = 7;                  // column pairs per thread of the whole-row Hubbard kernel
+constexpr int HUBROW_P_SHORT = 4;            // the same for 512-thread groups on rows of <= 4096 columns
 constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;
 constexpr int HUBROW_MAX_BOND = 64;
 constexpr int VEC_THREADS = 256;

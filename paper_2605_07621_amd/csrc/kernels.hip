@@ -510,7 +510,7 @@ __device__ __forceinline__ int rank16(uint32_t w, const int32_t *rl, const int32
 // contiguous chunk of the row order, so the rows in flight on one XCD are
 // neighbours in that order (their shared neighbour rows can hit its L2);
 // n_xcd == 1: plain grid stride.
-template <int NT>
+template <int NT, int PP, int NB>
 __global__ __launch_bounds__(NT, 4) void k_hubrow(const ProblemDev P, const int32_t *__restrict__ rows, int n_rows,
                                                   int dR, int n_xcd) {
     const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
@@ -541,50 +541,57 @@ __global__ __launch_bounds__(NT, 4) void k_hubrow(const ProblemDev P, const int3
     for (int k = xcd * per + slot; k < k_end; k += n_slot) {
         const int a = rows[k];
         const double2 *__restrict__ xr = (const double2 *)(P.x + (int64_t)a * dR);
-        double2 acc[HUBROW_P];
+        double2 acc[PP];
         {
-            double2 xv[HUBROW_P];
+            double2 xv[PP];
 #pragma unroll
-            for (int m = 0; m < HUBROW_P; ++m) {
+            for (int m = 0; m < PP; ++m) {
                 const int p = tid + m * NT;
                 xv[m] = p < np ? xr[p] : make_double2(0.0, 0.0);
                 acc[m] = make_double2(0.0, 0.0);
             }
             __syncthreads();   // readers of the previous row are done (and the tables are loaded)
 #pragma unroll
-            for (int m = 0; m < HUBROW_P; ++m) {
+            for (int m = 0; m < PP; ++m) {
                 const int p = tid + m * NT;
                 if (p < np) xs2[p] = xv[m];
             }
         }
-        // up-spin hops: whole neighbour rows, two in flight
+        // up-spin hops: whole neighbour rows, NB in flight; each element adds
+        // them pair by pair, (c0 v0 + c1 v1), in list order, whatever NB is
         {
             const int q0 = P.hl_ptr[a], q1 = P.hl_ptr[a + 1];
-            for (int q = q0; q < q1; q += 2) {
-                const bool two = q + 1 < q1;
-                const double c0 = P.hl_val[q], c1 = two ? P.hl_val[q + 1] : 0.0;
-                const double2 *__restrict__ n0 = (const double2 *)(P.x + (int64_t)P.hl_col[q] * dR);
-                const double2 *__restrict__ n1 = two ? (const double2 *)(P.x + (int64_t)P.hl_col[q + 1] * dR) : n0;
-                double2 v0[HUBROW_P], v1[HUBROW_P];
+            for (int q = q0; q < q1; q += NB) {
+                double c[NB];
+                const double2 *__restrict__ nr[NB];
 #pragma unroll
-                for (int m = 0; m < HUBROW_P; ++m) {
-                    const int p = tid + m * NT;
-                    const bool ok = p < np;
-                    v0[m] = ok ? n0[p] : make_double2(0.0, 0.0);
-                    v1[m] = ok && two ? n1[p] : make_double2(0.0, 0.0);
+                for (int u = 0; u < NB; ++u) {
+                    const bool has = q + u < q1;
+                    c[u] = has ? P.hl_val[q + u] : 0.0;
+                    nr[u] = (const double2 *)(P.x + (int64_t)P.hl_col[has ? q + u : q] * dR);
                 }
+                double2 v[NB][PP];
 #pragma unroll
-                for (int m = 0; m < HUBROW_P; ++m) {
-                    acc[m].x += c0 * v0[m].x + c1 * v1[m].x;
-                    acc[m].y += c0 * v0[m].y + c1 * v1[m].y;
-                }
+                for (int u = 0; u < NB; ++u)
+#pragma unroll
+                    for (int m = 0; m < PP; ++m) {
+                        const int p = tid + m * NT;
+                        v[u][m] = p < np && q + u < q1 ? nr[u][p] : make_double2(0.0, 0.0);
+                    }
+#pragma unroll
+                for (int u = 0; u < NB; u += 2)
+#pragma unroll
+                    for (int m = 0; m < PP; ++m) {
+                        acc[m].x += c[u] * v[u][m].x + c[u + 1] * v[u + 1][m].x;
+                        acc[m].y += c[u] * v[u][m].y + c[u + 1] * v[u + 1][m].y;
+                    }
             }
         }
         __syncthreads();   // the row is staged
         const uint32_t aw = P.lwords[a];
         double part = 0.0;
 #pragma unroll
-        for (int m = 0; m < HUBROW_P; ++m) {
+        for (int m = 0; m < PP; ++m) {
             const int p = tid + m * NT;
             if (p >= np) continue;
             const uint32_t wp = wpairs[p];
@@ -640,8 +647,12 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
     if (n_xcd != 8) n_xcd = 1;
     // the staged row, then the 16-bit rank -> column table
     const size_t lds = (size_t)dR * 8 + (size_t)dR * 2;
-    const void *fn = threads == 256 ? (const void *)k_hubrow<256>
-                     : threads == 512 ? (const void *)k_hubrow<512> : (const void *)k_hubrow<1024>;
+    // rows that fit half the pairs per thread keep four neighbour rows in flight
+    const bool short_rows = threads == 512 && dR <= 2 * HUBROW_P_SHORT * 512;
+    const void *fn = threads == 256   ? (const void *)k_hubrow<256, HUBROW_P, 2>
+                     : short_rows     ? (const void *)k_hubrow<512, HUBROW_P_SHORT, 4>
+                     : threads == 512 ? (const void *)k_hubrow<512, HUBROW_P, 2>
+                                      : (const void *)k_hubrow<1024, HUBROW_P, 2>;
     if (grid <= 0) {
         int per_cu = 0;
         const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
@@ -650,11 +661,15 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
     }
     grid = std::max(n_xcd, (grid / n_xcd) * n_xcd);
     if (threads == 256)
-        hipLaunchKernelGGL(k_hubrow<256>, dim3(grid), dim3(256), lds, st, prob, rows_d, n_rows, dR, n_xcd);
+        hipLaunchKernelGGL((k_hubrow<256, HUBROW_P, 2>), dim3(grid), dim3(256), lds, st, prob, rows_d, n_rows, dR, n_xcd);
+    else if (short_rows)
+        hipLaunchKernelGGL((k_hubrow<512, HUBROW_P_SHORT, 4>), dim3(grid), dim3(512), lds, st, prob, rows_d, n_rows, dR,
+                           n_xcd);
     else if (threads == 512)
-        hipLaunchKernelGGL(k_hubrow<512>, dim3(grid), dim3(512), lds, st, prob, rows_d, n_rows, dR, n_xcd);
+        hipLaunchKernelGGL((k_hubrow<512, HUBROW_P, 2>), dim3(grid), dim3(512), lds, st, prob, rows_d, n_rows, dR, n_xcd);
     else
-        hipLaunchKernelGGL(k_hubrow<1024>, dim3(grid), dim3(1024), lds, st, prob, rows_d, n_rows, dR, n_xcd);
+        hipLaunchKernelGGL((k_hubrow<1024, HUBROW_P, 2>), dim3(grid), dim3(1024), lds, st, prob, rows_d, n_rows, dR,
+                           n_xcd);
     return hipGetLastError();
 }
 
@@ -1769,11 +1784,17 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     const int b = (int)bytes;
     e = hipFuncSetAttribute((const void *)k_spin<true>, hipFuncAttributeMaxDynamicSharedMemorySize, SPIN_TILE * 8);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hubrow<1024>, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * HUBROW_P * 1024 * 10);
+    e = hipFuncSetAttribute((const void *)k_hubrow<1024, HUBROW_P, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * HUBROW_P * 1024 * 10);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hubrow<512>, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * HUBROW_P * 512 * 10);
+    e = hipFuncSetAttribute((const void *)k_hubrow<512, HUBROW_P, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * HUBROW_P * 512 * 10);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hubrow<256>, hipFuncAttributeMaxDynamicSharedMemorySize, 2 * HUBROW_P * 256 * 10);
+    e = hipFuncSetAttribute((const void *)k_hubrow<512, HUBROW_P_SHORT, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * HUBROW_P_SHORT * 512 * 10);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hubrow<256, HUBROW_P, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * HUBROW_P * 256 * 10);
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub<true, true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
