@@ -1652,15 +1652,21 @@ __global__ __launch_bounds__(CGS_THREADS, 4) void k_multiaxpy(const double *__re
         double2 v[CGS_PAIRS];
 #pragma unroll
         for (int t = 0; t < CGS_PAIRS; ++t) v[t] = make_double2(0.0, 0.0);
-#pragma unroll 1
-        for (int k = 0; k < nvec; ++k) {
-            double2 b[CGS_PAIRS];
-            cgs_load<V2>(basis + (int64_t)k * ld, i0, i1, b);
-            const double ck = cs[k];
+        // eight vectors per unrolled group, as in the dot kernel, so that
+        // loads of later vectors can go out early
+        for (int k0 = 0; k0 < nvec; k0 += 8) {
 #pragma unroll
-            for (int t = 0; t < CGS_PAIRS; ++t) {
-                v[t].x += ck * b[t].x;
-                v[t].y += ck * b[t].y;
+            for (int q = 0; q < 8; ++q) {
+                if (k0 + q < nvec) {
+                    double2 b[CGS_PAIRS];
+                    cgs_load<V2>(basis + (int64_t)(k0 + q) * ld, i0, i1, b);
+                    const double ck = cs[k0 + q];
+#pragma unroll
+                    for (int t = 0; t < CGS_PAIRS; ++t) {
+                        v[t].x += ck * b[t].x;
+                        v[t].y += ck * b[t].y;
+                    }
+                }
             }
         }
         double2 yo[CGS_PAIRS];
