@@ -1534,11 +1534,28 @@ __global__ __launch_bounds__(VEC_THREADS) void k_axpy_norm(const VecJob *__restr
         } else {
             a = J.scalars[J.coef_idx] * sc;
         }
+        // eight elements per thread and pass, all loads before any store;
+        // each thread still takes i0 + tid, + blockDim, ... in order
+        const double *__restrict__ xp = J.x;
+        double *__restrict__ yp = J.y;
         double s = 0.0;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-            const double v = J.y[i] - a * J.x[i];
-            J.y[i] = v;
-            s += v * v;
+        for (int64_t base = i0 + threadIdx.x; base < i1; base += 8 * (int64_t)blockDim.x) {
+            double yv[8], xv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = base + (int64_t)u * blockDim.x;
+                yv[u] = i < i1 ? yp[i] : 0.0;
+                xv[u] = i < i1 ? xp[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t i = base + (int64_t)u * blockDim.x;
+                if (i < i1) {
+                    const double v = yv[u] - a * xv[u];
+                    yp[i] = v;
+                    s += v * v;
+                }
+            }
         }
         s = block_sum(s, red);
         if (threadIdx.x == 0) J.partials[ci] = s;
