@@ -37,6 +37,7 @@ constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;
 constexpr int HUBROW_MAX_BOND = 64;
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
+constexpr int64_t STREAM_STORE_MIN = (int64_t)32 << 20;   // elements: results of vectors this long bypass the cache
 constexpr int MAX_BASIS = 1024;              // reorthogonalisation: vectors per projection call
 
 // One vector job of the batched Lanczos kernels.

@@ -44,6 +44,19 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
+// Result stores.  A vector larger than the last-level cache is streamed past
+// it (non-temporal: its lines would only evict the source rows that later
+// work still gathers); a smaller one stays cacheable for the next kernel.
+// The choice is a compile-time one: with a run-time flag the compiler merges
+// the two stores of the branches into one plain store.
+template <bool STREAM>
+__device__ __forceinline__ void store_result(double *p, double v) {
+    if constexpr (STREAM)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 }  // namespace
 
 // Epilogue factors y = xscale H x - zcoef z: from the descriptor, or from
@@ -1006,7 +1019,7 @@ __global__ __launch_bounds__(SLAB_THREADS) void k_upslab(const double *__restric
 // per-lane address arithmetic; the crossing bond's source column splits
 // into a per-segment and a per-lane part that are both precomputed.
 // ------------------------------------------------------------------------
-template <bool UP>
+template <bool UP, bool STREAM>
 __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const Hub3Args A) {
     const double2 ef = epi_factors(A.dscale, A.xscale, A.zcoef);
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1157,7 +1170,7 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
             const int64_t gi = (int64_t)it.row0 * dR + col_m[m];
             double y = UP ? ef.x * (A.hop * (acc[m] + dn) + dg * x0) : ef.x * (acc[m] + A.hop * dn + dg * x0);
             if (A.z) y -= ef.y * A.z[gi];
-            A.y[gi] = y;
+            store_result<STREAM>(&A.y[gi], y);
             part += x0 * y;
         }
         if (A.partials) {
@@ -1333,17 +1346,24 @@ hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, in
         // pass 1: left operator over column slabs held in L2; pass 2: tiles
         hipLaunchKernelGGL(k_upslab, dim3(slab_grid), dim3(SLAB_THREADS), 0, st, A.x, A.y, A.hl_ptr, A.hl_col, A.hl_val,
                            A.n_rows, A.dR, slab_grid / 8);
-        hipLaunchKernelGGL(k_hub3<false>, dim3(grid), dim3(HUB3_THREADS), hub3_lds_bytes(s), st, A);
-    } else {
-        hipLaunchKernelGGL(k_hub3<true>, dim3(grid), dim3(HUB3_THREADS), hub3_lds_bytes(s), st, A);
     }
+    const bool stream = (int64_t)A.n_rows * A.dR >= STREAM_STORE_MIN;
+    const size_t lds = hub3_lds_bytes(s);
+    if (split && stream)
+        hipLaunchKernelGGL((k_hub3<false, true>), dim3(grid), dim3(HUB3_THREADS), lds, st, A);
+    else if (split)
+        hipLaunchKernelGGL((k_hub3<false, false>), dim3(grid), dim3(HUB3_THREADS), lds, st, A);
+    else if (stream)
+        hipLaunchKernelGGL((k_hub3<true, true>), dim3(grid), dim3(HUB3_THREADS), lds, st, A);
+    else
+        hipLaunchKernelGGL((k_hub3<true, false>), dim3(grid), dim3(HUB3_THREADS), lds, st, A);
     return hipGetLastError();
 }
 
 int hub_blocks_per_cu(int which, size_t lds) {
     int n = 0;
     hipError_t e = hipSuccess;
-    if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3<true>, HUB3_THREADS, lds);
+    if (which == 3) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub3<true, true>, HUB3_THREADS, lds);
     else if (which == 4) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_upslab, SLAB_THREADS, 0);
     else if (which == 5) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hubseg, HUBSEG_THREADS, lds);
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)k_hub2<true, true>, HUB2_THREADS, lds);
@@ -1831,9 +1851,13 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     if (e != hipSuccess) return e;
     e = hipFuncSetAttribute((const void *)k_hub2<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hub3<true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    e = hipFuncSetAttribute((const void *)k_hub3<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void *)k_hub3<false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    e = hipFuncSetAttribute((const void *)k_hub3<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub3<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void *)k_hub3<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void *)k_rows<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)ROWS_MAX_LDS);
 }
