@@ -251,13 +251,14 @@ ecut_status upload(ecut_sectors *s) {
     void *mem = nullptr;
     st = table_alloc(&mem, A.off, dev);
     if (st != ECUT_OK) return st;
-    hipError_t e = hipSuccess;
-    for (auto &p : A.pieces) {
-        e = hipMemcpy((char *)mem + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            table_free(mem, dev);
-            return hip_fail(e, "hipMemcpy(sector tables)");
-        }
+    // one host image of the whole block, one copy (each copy of pageable
+    // memory is a synchronous call with its own staging)
+    std::vector<char> image(A.off, 0);
+    for (auto &p : A.pieces) std::memcpy(image.data() + p.off, p.src, p.bytes);
+    hipError_t e = hipMemcpy(mem, image.data(), A.off, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        table_free(mem, dev);
+        return hip_fail(e, "hipMemcpy(sector tables)");
     }
     char *b = (char *)mem;
     ProblemDev &P = s->prob;
