@@ -639,6 +639,30 @@ def test_server_batched_vs_alone_vs_oracle(dev):
         assert g["status"] == 0 and g["energy"] == a["energy"] and g["steps"] == a["steps"]
 
 
+def test_server_failed_build_is_reported(dev):
+    """A request whose sectors cannot be built (checked only when the
+    server's builder thread reaches it) finishes with the builder's error,
+    and the requests around it are still solved, in order, to the oracle's
+    energies; with graph replay and without."""
+    ecut = _ecut()
+    good = _serving_mix()[:3]
+    bad = I.Problem(I.hubbard_chain(6, 1.0, 4.0), I.Cut("updn"), 7, 3)   # 7 > 6 sites
+    refs = [O.Sector(p.model, p.n_up, p.n_dn).lanczos(I.psi(3, O.Sector(p.model, p.n_up, p.n_dn).n), 600,
+                                                     tol=1e-14)[0][-1] for p in good]
+    for use_graph in (False, True):
+        srv = ecut.Server(1 << 30, max_steps=600, tol=1e-10, use_graph=use_graph)
+        ids = [srv.submit(good[0], seed=1), srv.submit(bad, seed=2), srv.submit(good[1], seed=3),
+               srv.submit(good[2], seed=4)]
+        srv.drain()
+        res = {r["req_id"]: r for r in srv.poll()}
+        srv.close()
+        assert sorted(res) == sorted(ids)
+        assert res[ids[1]]["status"] == ecut.ECUT_EINVAL
+        for k, i in zip((0, 1, 2), (ids[0], ids[2], ids[3])):
+            assert res[i]["status"] == 0
+            assert abs(res[i]["energy"] - refs[k]) <= 1e-10, (use_graph, k)
+
+
 def test_server_budget_admission(dev):
     """A budget that holds one request at a time still serves them all
     (admission waits for memory); a request larger than the budget fails."""
