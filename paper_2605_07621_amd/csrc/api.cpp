@@ -146,13 +146,15 @@ static void table_free(void *p, int device) {
     {
         std::lock_guard<std::mutex> g(g_alloc_mu);
         auto it = g_alloc_owner.find(p);
-        if (it == g_alloc_owner.end()) {
-            (void)hipFree(p);
-            return;
+        if (it != g_alloc_owner.end()) {
+            a = it->second.first;
+            bytes = it->second.second;
+            g_alloc_owner.erase(it);
         }
-        a = it->second.first;
-        bytes = it->second.second;
-        g_alloc_owner.erase(it);
+    }
+    if (!a.free) {   // made by hipMalloc (the wait inside hipFree happens outside the lock)
+        (void)hipFree(p);
+        return;
     }
     // hipFree waits for the device; a caller's free may hand the memory out
     // again at once, so kernels still reading the tables must finish first

@@ -234,7 +234,15 @@ void ecut_server::help() {
 }
 
 void ecut_server::run() {
-    hipSetDevice(device);
+    const hipError_t dev_err = hipSetDevice(device);
+    if (dev_err != hipSuccess) {   // nothing can run: drain and poll report it
+        const ecut_status st = hip_fail(dev_err, "hipSetDevice (server worker)");
+        std::lock_guard<std::mutex> g(mu);
+        worker_status = st;
+        worker_msg = ecut_last_error();
+        cv_done.notify_all();
+        return;
+    }
     std::vector<std::unique_ptr<Active>> active;
     LzPipe pipe;   // batched steps in flight (two: the host processes one while the device runs the next)
     pipe.use_graph = opts.use_graph != 0;
