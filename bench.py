@@ -39,16 +39,20 @@ def kernel_source_hash():
 
 
 def traffic_from_profile(kernel, workload, per_launch_alg):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    or None if there is none or the kernel source changed since."""
+    """HBM traffic per launch from the committed rocprofv3 counter summary
+    and the launch tuning the counters were taken with (grid,n_xcd,
+    row_order,variant), or (None, None) if there is none or the kernel
+    source changed since."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as f:
         d = json.load(f)
     if d.get("kernel_hash") != kernel_source_hash():
-        return None
-    return d.get("bytes_per_launch")
+        return None, None
+    words = d.get("commands", {}).get("fetch", "").split()
+    tuning = words[words.index("--tuning") + 1] if "--tuning" in words[:-1] else None
+    return d.get("bytes_per_launch"), tuning
 
 
 def cpu_baseline(p, seconds):
@@ -525,7 +529,7 @@ def main():
     alg_bytes = 2 * n * 8 + int(S.info.device_bytes)
     kernel = kernel_name(S)
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(kernel, args.workload, alg_bytes)
+    traffic, traffic_tuning = traffic_from_profile(kernel, args.workload, alg_bytes)
 
     # a few fused Lanczos steps (H*psi + alpha + update + beta) on the same input
     lz = None
@@ -554,7 +558,7 @@ def main():
                    "kernel": kernel, "tuning": tuning},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes": alg_bytes,
+                     "traffic": traffic, "traffic_tuning": traffic_tuning, "algorithmic_bytes": alg_bytes,
                      "kernel_ms": round(kern_ms, 5), "kernel": kernel},
         "lanczos": lz,
     }
