@@ -183,6 +183,30 @@ def test_bench_names_every_kernel_variant():
         assert bench.kernel_name(S4) == want
 
 
+def test_bench_traffic_lookup(tmp_path, monkeypatch):
+    """The benchmark takes HBM traffic from a counter summary only when the
+    summary was made from the current kernel source, and reports the launch
+    tuning of its counter runs beside it."""
+    import json
+    import bench
+    h = bench.kernel_source_hash()
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    assert bench.traffic_from_profile("k_x", "w", 0) == (None, None)
+    d = {"kernel_hash": h, "bytes_per_launch": 123.0,
+         "commands": {"fetch": "rocprofv3 --pmc FETCH_SIZE -o run -- python3 bench.py --tuning 0,8,8,0 --steps 3"}}
+    path = tmp_path / "profiles" / "k_x_w_traffic.json"
+    path.write_text(json.dumps(d))
+    assert bench.traffic_from_profile("k_x", "w", 0) == (123.0, "0,8,8,0")
+    d["commands"]["fetch"] = "rocprofv3 --pmc FETCH_SIZE -o run -- python3 bench.py"
+    path.write_text(json.dumps(d))
+    assert bench.traffic_from_profile("k_x", "w", 0) == (123.0, None)
+    d["kernel_hash"] = "0" * 16
+    path.write_text(json.dumps(d))
+    assert bench.traffic_from_profile("k_x", "w", 0) == (None, None)
+
+
 def test_option_structs_match_header():
     # the binding's ctypes structs follow the header's field order and types
     import ctypes
