@@ -1169,7 +1169,12 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
             const double dg = A.u0 * (double)__popc(aw & bw);
             const int64_t gi = (int64_t)it.row0 * dR + col_m[m];
             double y = UP ? ef.x * (A.hop * (acc[m] + dn) + dg * x0) : ef.x * (acc[m] + A.hop * dn + dg * x0);
-            if (A.z) y -= ef.y * A.z[gi];
+            if (A.z) {
+                if constexpr (STREAM)   // read once: kept out of the cache like the result
+                    y -= ef.y * __builtin_nontemporal_load(A.z + gi);
+                else
+                    y -= ef.y * A.z[gi];
+            }
             store_result<STREAM>(&A.y[gi], y);
             part += x0 * y;
         }
