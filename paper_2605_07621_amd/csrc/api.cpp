@@ -352,6 +352,8 @@ ecut_status upload(ecut_sectors *s) {
         A3.hs = s->h3_hs;
         A3.max_tile = s->h3_max_tile;
         A3.max_nseg = s->hub.max_nseg;
+        A3.max_l = 0;
+        for (size_t ci = 0; ci + 7 < s->hc_cls.size(); ci += 8) A3.max_l = std::max(A3.max_l, s->hc_cls[ci]);
     }
     if (s->hubseg_ok) {
         HubSegArgs &G = s->hseg;

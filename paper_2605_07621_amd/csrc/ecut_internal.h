@@ -126,7 +126,7 @@ struct Hub3Args {
     const double *dscale;             // nullable: xscale = dscale[0], zcoef = dscale[1]
     const int32_t *hl_ptr, *hl_col;   // up-spin hop rows
     const double *hl_val;
-    int32_t n_rows, pad_;
+    int32_t n_rows, max_l;            // rows; longest class (its low-hop tables are copied to LDS)
     const uint32_t *lwords;           // up words
     const int32_t *cls;               // [n_cls][8] as HubDev::cls
     const int4 *seginfo;              // [seg]: column, high word, crossing column, crossing bit (2 = none)

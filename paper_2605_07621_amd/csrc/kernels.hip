@@ -1029,6 +1029,11 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
     int4 *sinf = (int4 *)(smem + (((size_t)A.max_tile * 8 + 15) & ~(size_t)15));
     int32_t *hnb = (int32_t *)(sinf + A.max_nseg);
     int32_t *hcnt = hnb + A.max_nseg * hs;
+    // the class's per-lane low-hop tables: loinfo, then looff as two int4
+    const size_t lo_off = (((size_t)A.max_tile * 8 + 15) & ~(size_t)15) + (size_t)A.max_nseg * 16 +
+                          (((size_t)A.max_nseg * hs * 4 + 15) & ~(size_t)15) + (((size_t)A.max_nseg * 4 + 15) & ~(size_t)15);
+    int4 *linf = (int4 *)(smem + lo_off);
+    int4 *lofs = linf + A.max_l;
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
     const int dR = A.dR;
@@ -1050,6 +1055,12 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
                 hcnt[i] = A.hcnt[seg_base + i];
             }
             for (int i = tid; i < nseg * hs; i += NT) hnb[i] = A.hnb[seg_base * hs + i];
+            for (int i = tid; i < L; i += NT) {
+                linf[i] = A.loinfo[lo_base + i];
+                const int4 *src = (const int4 *)(A.looff + (size_t)(lo_base + i) * 8);
+                lofs[2 * i] = src[0];
+                lofs[2 * i + 1] = src[1];
+            }
             loaded = it.cls;
             __syncthreads();
         }
@@ -1120,9 +1131,10 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
         int4 li = make_int4(0, 0, 2, 0);
         int lof[8];
         if (active) {
-            li = A.loinfo[lo_base + j];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) lof[q] = A.looff[(lo_base + j) * 8 + q];
+            li = linf[j];
+            const int4 o0 = lofs[2 * j], o1 = lofs[2 * j + 1];
+            lof[0] = o0.x, lof[1] = o0.y, lof[2] = o0.z, lof[3] = o0.w;
+            lof[4] = o1.x, lof[5] = o1.y, lof[6] = o1.z, lof[7] = o1.w;
         } else {
 #pragma unroll
             for (int q = 0; q < 8; ++q) lof[q] = 0;
@@ -1337,7 +1349,8 @@ hipError_t launch_hubseg(const ecut_sectors *s, const HubSegArgs &args, int grid
 size_t hub3_lds_bytes(const ecut_sectors *s) {
     auto al = [](size_t b) { return (b + 15) & ~(size_t)15; };
     const int mns = s->hub.max_nseg;
-    return al((size_t)s->h3_max_tile * 8) + al((size_t)mns * 16) + al((size_t)mns * s->h3_hs * 4) + al((size_t)mns * 4);
+    return al((size_t)s->h3_max_tile * 8) + al((size_t)mns * 16) + al((size_t)mns * s->h3_hs * 4) + al((size_t)mns * 4) +
+           (size_t)s->h3.max_l * 48;
 }
 
 hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, bool split, int slab_grid,

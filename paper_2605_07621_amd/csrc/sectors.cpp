@@ -628,13 +628,15 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
             s->h3_hs = (int32_t)hs2;
             s->h3_max_tile = mt;
             // every item must fit HUB3_M element slots per thread of HUB3_THREADS
+            int max_l = 0;
             for (size_t ci = 0; ci < cl.size(); ++ci) {
                 const int L = s->hc_cls[8 * ci], nseg = s->hc_cls[8 * ci + 1], rpi = s->hc_cls[8 * ci + 4];
+                max_l = std::max(max_l, L);
                 const int per_pass = HUB3_THREADS / L;
                 if (per_pass < 1 || (rpi * nseg + per_pass - 1) / per_pass > HUB3_M) fast = false;
                 if ((int64_t)rpi * s->blocks[0].d_r > (1ll << 31) / 2) fast = false;
             }
-            if ((size_t)mt * 8 + (size_t)max_nseg * (16 + 4 * hs2 + 4) + 2048 > 150 * 1024) fast = false;
+            if ((size_t)mt * 8 + (size_t)max_nseg * (16 + 4 * hs2 + 4) + (size_t)max_l * 48 + 2048 > 150 * 1024) fast = false;
         }
         s->hub3_ok = fast;
         build_hubseg_tables(s);
