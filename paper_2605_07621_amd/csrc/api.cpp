@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ecut_internal.h"
@@ -250,6 +251,12 @@ ecut_status upload(ecut_sectors *s) {
         o_5ux = A.add(s->hs_ucross);
         o_5it = A.add(s->hs_items);
     }
+    size_t o_6k = 0, o_6v = 0, o_6r = 0;
+    if (s->hub6_ok) {
+        o_6k = A.add(s->h6_col);
+        o_6v = A.add(s->h6_val);
+        o_6r = A.add(s->level_rows);
+    }
     void *mem = nullptr;
     st = table_alloc(&mem, A.off, dev);
     if (st != ECUT_OK) return st;
@@ -378,6 +385,33 @@ ecut_status upload(ecut_sectors *s) {
         G.hs = s->h3_hs;
         G.uhs = s->hs_uhs;
     }
+    if (s->hub6_ok) {
+        const BlockDev &B0 = s->blocks[0];
+        HubUArgs &U = s->h6u;
+        U = HubUArgs{};
+        U.hl_ptr = P.hl_ptr;
+        U.hl_col = P.hl_col;
+        U.hl_val = P.hl_val;
+        U.rows = (const int32_t *)(b + o_6r);   // level order: a row's neighbours sit in the levels beside it
+        U.uniform = 1;
+        for (double v : s->hl_val) U.uniform = U.uniform && v == s->hl_val[0];
+        U.hop = s->hl_val.empty() ? 0.0 : s->hl_val[0];
+        U.n_rows = B0.d_l;
+        U.dR = B0.d_r;
+        HubDArgs &D = s->h6d;
+        D = HubDArgs{};
+        D.n_slots = s->h6_maxq;
+        D.col = (const int32_t *)(b + o_6k);
+        D.val = s->h6_uniform ? nullptr : (const double *)(b + o_6v);
+        D.hop = s->h6_hop;
+        D.lwords = P.lwords;
+        D.rwords = P.hub.rwords32;
+        D.u = P.hub.u;
+        D.u0 = s->hub.u0;
+        D.uniform_u = s->hub.uniform_u;
+        D.n_rows = B0.d_l;
+        D.dR = B0.d_r;
+    }
     s->dev_mem = mem;
     s->dev_bytes = A.off;
     s->device = dev;
@@ -389,6 +423,24 @@ int32_t max_tile_elems(const ecut_sectors *s) {
     int64_t m = 0;
     for (auto &it : s->items) m = std::max<int64_t>(m, (int64_t)(it.row1 - it.row0) * s->blocks[it.block].d_r);
     return (int32_t)m;
+}
+
+// Item counts of the two-pass kernels for the current tuning: the left pass
+// takes `grid` rows of the level order (0 = HUBU_ROWS) per item over slabs of
+// 64 lanes x 1 or 2 columns; the right pass `tile` rows (0 = HUBD_ROWS) x
+// HUBD_THREADS columns per item.
+static int32_t hub6_rows_d(const ecut_sectors *s) { return s->tune.tile > 0 ? s->tune.tile : HUBD_ROWS; }
+
+void hub6_shape(const ecut_sectors *s, HubUArgs &U, HubDArgs &D) {
+    const int32_t dR = s->blocks[0].d_r, nr = s->blocks[0].d_l;
+    const int32_t cols = (dR % 2 == 0 ? 2 : 1) * 64;
+    U.rows_per_item = s->tune.grid > 0 ? s->tune.grid : HUBU_ROWS;
+    U.n_rgroups = (nr + U.rows_per_item - 1) / U.rows_per_item;
+    U.n_slabs = (dR + cols - 1) / cols;
+    U.n_items = U.n_slabs * U.n_rgroups;
+    D.rows_per_item = hub6_rows_d(s);
+    D.n_chunks = (dR + HUBD_THREADS - 1) / HUBD_THREADS;
+    D.n_items = ((nr + D.rows_per_item - 1) / D.rows_per_item) * D.n_chunks;
 }
 
 // One application on a stream, with the Lanczos epilogue fields of `P`
@@ -417,6 +469,40 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             A3.dscale = P.dscale;
             const int slab_grid = 8 * std::max(1, (n_cu / 8) * hub_blocks_per_cu(4, 0));
             e = launch_hub3(s, A3, grid, n_xcd, T.variant == 3, slab_grid, st);
+        } else if ((T.variant == 6 && s->hub6_ok) || (T.variant == 7 && s->hub3_ok)) {
+            // left operator on flat slab items of `grid` rows (0 = HUBU_ROWS)
+            HubUArgs U = s->h6u;
+            HubDArgs D = s->h6d;
+            hub6_shape(s, U, D);
+            U.x = D.x = P.x;
+            U.y = D.y = P.y;
+            e = launch_hub6_left(U, n_xcd, st);
+            if (e == hipSuccess && T.variant == 6) {
+                D.z = P.z;
+                D.partials = P.partials;
+                D.xscale = P.xscale;
+                D.zcoef = P.zcoef;
+                D.dscale = P.dscale;
+                e = launch_hubD_only(D, n_xcd, st);
+            } else if (e == hipSuccess) {
+                // right operator, diagonal and epilogue on class tiles (the
+                // left operator's sum is already in y)
+                const size_t lds = hub3_lds_bytes(s);
+                if (e == hipSuccess && lds > g_last_max_lds)
+                    return fail(ECUT_EUNSUPPORTED, "class tiles exceed the device's LDS per work group");
+                Hub3Args A3 = s->h3;
+                A3.x = P.x;
+                A3.y = P.y;
+                A3.z = P.z;
+                A3.partials = P.partials;
+                A3.items = s->dev_hub_items;
+                A3.n_items = (int32_t)s->hub_items_ord.size();
+                A3.xscale = P.xscale;
+                A3.zcoef = P.zcoef;
+                A3.dscale = P.dscale;
+                const int grid = n_cu * hub_blocks_per_cu(3, lds);
+                if (e == hipSuccess) e = launch_hub3(s, A3, grid, n_xcd, true, 0, st);
+            }
         } else if (T.variant == 5 && s->hubseg_ok) {
             const size_t lds = (size_t)s->hs_max_tile * 8;
             if (lds > g_last_max_lds) return fail(ECUT_EUNSUPPORTED, "segment tiles exceed the device's LDS per work group");
@@ -461,6 +547,13 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
 int32_t apply_partial_slots(const ecut_sectors *s) {
     if (s->kernel != 1) return s->item_slots;
     if (s->tune.variant == 5 && s->hubseg_ok) return s->hs_n_slots;
+    if (s->tune.variant == 7 && s->hub3_ok) return (int32_t)s->hub_items.size();
+    if (s->tune.variant == 6 && s->hub6_ok) {
+        HubUArgs U{};
+        HubDArgs D{};
+        hub6_shape(s, U, D);
+        return D.n_items;
+    }
     const bool tiles = ((s->tune.variant == 0 || s->tune.variant == 3) && (s->hub3_ok || s->hub2_ok)) ||
                        (s->tune.variant == 2 && s->hub2_ok);   // variants 1 and 4: one slot per row
     return tiles ? (int32_t)s->hub_items.size() : s->blocks[0].d_l;
@@ -468,8 +561,12 @@ int32_t apply_partial_slots(const ecut_sectors *s) {
 
 // workspace size: either Hubbard variant may run on the same workspace
 int32_t apply_partial_slots_max(const ecut_sectors *s) {
-    return s->kernel == 1 ? std::max<int32_t>(std::max<int32_t>(s->blocks[0].d_l, (int32_t)s->hub_items.size()),
-                                              s->hubseg_ok ? s->hs_n_slots : 0)
+    // the two-pass kernels use the most slots with one row per right-pass item
+    const int32_t h6 = s->hub6_ok ? s->blocks[0].d_l * ((s->blocks[0].d_r + HUBD_THREADS - 1) / HUBD_THREADS) : 0;
+    return s->kernel == 1 ? std::max<int32_t>(std::max<int32_t>(std::max<int32_t>(s->blocks[0].d_l,
+                                                                                    (int32_t)s->hub_items.size()),
+                                                                  s->hubseg_ok ? s->hs_n_slots : 0),
+                                              h6)
                           : std::max(s->item_slots_cap, s->item_slots);
 }
 
@@ -651,7 +748,7 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
     I.n_cross_diag = (int32_t)s->xdiag.size();
     I.kernel = s->kernel;
     I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0) | (s->hubrow_ok ? 8 : 0) |
-                     (s->hubseg_ok ? 16 : 0);
+                     (s->hubseg_ok ? 16 : 0) | (s->hub6_ok ? 32 : 0);
     I.device_bytes = (int64_t)s->dev_bytes;
     I.n_eff = s->n_eff;
     *info = I;
@@ -691,15 +788,32 @@ ecut_status ecut_canonical_positions(const ecut_sectors *s, int64_t *pos) {
         for (int64_t i = 0; i < s->dim; ++i) pos[i] = (i / dR) * dR + hub_column(s, i % dR);
         return ECUT_OK;
     }
+    // Chunks of the canonical order on the host's threads: each chunk unranks
+    // its first word and steps to the next word of the same popcount (the
+    // smallest larger one: move the lowest movable set bit up by one and put
+    // the set bits below it back at the bottom).
     const int qmin = s->blocks[0].q_l;
-    for (int64_t i = 0; i < s->dim; ++i) {
-        const uint64_t w = colex_unrank(i, s->n_up);
-        uint64_t l = 0, r = 0;
-        for (size_t k = 0; k < s->lsites.size(); ++k) l |= ((w >> s->lsites[k]) & 1ull) << k;
-        for (size_t k = 0; k < s->rsites.size(); ++k) r |= ((w >> s->rsites[k]) & 1ull) << k;
-        const BlockDev &B = s->blocks[__builtin_popcountll(l) - qmin];
-        pos[i] = B.offset + colex_rank(l) * B.d_r + colex_rank(r);
-    }
+    const int64_t dim = s->dim;
+    const unsigned hw = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+    const int64_t chunk = std::max<int64_t>(1 << 16, (dim + hw - 1) / hw);
+    auto work = [&](int64_t i0, int64_t i1) {
+        uint64_t w = colex_unrank(i0, s->n_up);
+        for (int64_t i = i0; i < i1; ++i) {
+            uint64_t l = 0, r = 0;
+            for (size_t k = 0; k < s->lsites.size(); ++k) l |= ((w >> s->lsites[k]) & 1ull) << k;
+            for (size_t k = 0; k < s->rsites.size(); ++k) r |= ((w >> s->rsites[k]) & 1ull) << k;
+            const BlockDev &B = s->blocks[__builtin_popcountll(l) - qmin];
+            pos[i] = B.offset + colex_rank(l) * B.d_r + colex_rank(r);
+            if (w != 0 && i + 1 < i1) {
+                const int t = __builtin_ctzll(w);                  // lowest set bit
+                const int run = __builtin_ctzll(~(w >> t));        // set bits from there up
+                w = (w & ~(((1ull << run) - 1) << t)) | (1ull << (t + run)) | ((1ull << (run - 1)) - 1);
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int64_t i0 = 0; i0 < dim; i0 += chunk) th.emplace_back(work, i0, std::min(dim, i0 + chunk));
+    for (auto &t : th) t.join();
     return ECUT_OK;
 }
 

@@ -166,6 +166,48 @@ struct HubSegArgs {
     int32_t h, hs, uhs, pad_;
 };
 
+// Two-pass Hubbard application on flat work items (variant 6).
+// Pass 1 (left operator): y[a, c] = sum_a' H_up[a, a'] x[a', c] over a
+// column slab (64 lanes x 1 or 2 columns) and a run of rows of the row order;
+// items are slab-major, so the blocks an XCD has in flight cover one slab and
+// a window of the row order whose neighbour rows stay in its L2.
+struct HubUArgs {
+    const double *x;
+    double *y;
+    const int32_t *hl_ptr, *hl_col;   // up-spin hop rows (rows in colex order)
+    const double *hl_val;
+    const int32_t *rows;              // row processing order
+    double hop;                       // every hop value when uniform != 0 (the sum is scaled once)
+    int32_t uniform, pad_;
+    int32_t n_rows, dR;
+    int32_t rows_per_item, n_rgroups; // rows of the order per item, row runs per slab
+    int32_t n_slabs, n_items;
+};
+
+// Pass 2 (right operator, diagonal, epilogue): per element (a, c)
+//   y = xscale (y_pass1 + sum_q val_q x[a, col_q] + diag(a, c) x[a, c]) - zcoef z
+// with the down-spin hops of column c in bond-major slots (col[b * dR + c]).
+// An item is a run of rows x 256 columns; items are row-run-major, so the
+// blocks in flight on an XCD cover a few whole rows and the in-row gathers hit
+// its L2.  One partial <x, y> per item.
+struct HubDArgs {
+    const double *x;
+    double *y;
+    const double *z;
+    double *partials;
+    double xscale, zcoef;
+    const double *dscale;             // nullable: xscale = dscale[0], zcoef = dscale[1]
+    const int32_t *col;               // [n_slots][dR] source column of the hop across each bond, -1 if none
+    const double *val;                // [n_slots][dR] hop value (NULL: every hop is `hop`)
+    double hop;
+    const uint32_t *lwords;           // up word of each row
+    const uint32_t *rwords;           // down word of each column (column order)
+    const double *u;                  // [n_sites] U_i
+    double u0;
+    int32_t uniform_u, n_rows, dR, rows_per_item;
+    int32_t n_chunks, n_items, n_slots, pad_;
+};
+
 // Work item of the segment-tile kernel: up segment, down segment (global
 // index), down class; slot = index in the order-independent item list.
 // useg < 0 marks padding.
@@ -265,6 +307,16 @@ struct ecut_sectors {
     std::vector<ecut::HubSegItem> hs_items;   // processing order, padded to 8 equal XCD chunks
     int32_t hs_uhs = 1, hs_n_slots = 0, hs_max_tile = 0;
     ecut::HubSegArgs hseg{};
+    // two-pass flat kernels (variant 6): down-spin hops as slot-major ELL
+    bool hub6_ok = false;
+    std::vector<int32_t> level_rows;      // rows by inversion level (the left pass's row order)
+    bool h6_uniform = false;              // every hop of either spin has the value h6_hop
+    double h6_hop = 0.0;
+    int32_t h6_maxq = 0;                  // bond slots of the down-spin table
+    std::vector<int32_t> h6_col;
+    std::vector<double> h6_val;
+    ecut::HubUArgs h6u{};
+    ecut::HubDArgs h6d{};
     ecut::HubDev hub{};
     std::vector<int32_t> hub_lo_cnt, hub_lo_ent, hub_lo_rank, hub_hi_cnt, hub_hi_ent, hub_seg_off, hub_xb;
     std::vector<double> hub_coef, hub_u;
@@ -318,4 +370,6 @@ int32_t hub_column(const ecut_sectors *s, int64_t r);
 // returns the number of partial-sum slots
 int32_t make_spin_items(const ecut_sectors *s, int32_t tile, int32_t order, std::vector<ItemDev> &out);
 void release_device(ecut_sectors *s);
+// item counts of the two-pass kernels (variant 6) for the handle's tuning
+void hub6_shape(const ecut_sectors *s, HubUArgs &U, HubDArgs &D);
 }  // namespace ecut

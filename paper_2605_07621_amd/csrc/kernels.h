@@ -35,6 +35,13 @@ constexpr int HUBROW_P = 7;                  // column pairs per thread of the w
 constexpr int HUBROW_P_SHORT = 4;            // the same for 512-thread groups on rows of <= 4096 columns
 constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;
 constexpr int HUBROW_MAX_BOND = 64;
+constexpr int HUBU_THREADS = 256;            // two-pass kernels: left-operator pass, one row per wave at a time
+constexpr int HUBU_NB = 8;                   // neighbour-row loads issued together per lane
+constexpr int HUBU_ROWS = 4;                 // rows of the row order per left-operator item
+constexpr int HUBD_THREADS = 256;            // right-operator pass: one column per thread
+constexpr int HUBD_NB = 8;                   // in-row gathers issued together per lane
+constexpr int HUBD_MAX_SLOTS = 32;           // bonds of the down-spin hop table (held in registers)
+constexpr int HUBD_ROWS = 4;                 // default rows per right-operator item
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
 constexpr int64_t STREAM_STORE_MIN = (int64_t)32 << 20;   // elements: results of vectors this long bypass the cache
@@ -95,6 +102,13 @@ hipError_t launch_hub2(const ecut_sectors *s, const ProblemDev &prob, const HubI
 size_t hub3_lds_bytes(const ecut_sectors *s);
 // segment tiles: grid work groups, n_xcd = 8 (items in 8 XCD chunks) or 1
 hipError_t launch_hubseg(const ecut_sectors *s, const HubSegArgs &args, int grid, int n_xcd, hipStream_t st);
+// two-pass kernels (variants 6 and 7): the flat left-operator pass (slab
+// items; n_xcd 8 = XCD-contiguous items)
+hipError_t launch_hub6_left(const HubUArgs &U, int n_xcd, hipStream_t st);
+// pass 2 of the two-pass kernels alone
+hipError_t launch_hubD_only(const HubDArgs &D, int n_xcd, hipStream_t st);
+// split: the left operator is already in y (UP = false); slab_grid > 0 runs
+// the slab pass k_upslab first, 0 leaves y as the caller wrote it
 hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, int n_xcd, bool split, int slab_grid,
                        hipStream_t st);
 int hub_blocks_per_cu(int which, size_t lds);

@@ -1360,7 +1360,7 @@ hipError_t launch_hub3(const ecut_sectors *s, const Hub3Args &args, int grid, in
     if (grid < n_xcd) grid = n_xcd;
     A.n_xcd = n_xcd;
     A.per_xcd = (A.n_items + n_xcd - 1) / n_xcd;
-    if (split) {
+    if (split && slab_grid > 0) {
         // pass 1: left operator over column slabs held in L2; pass 2: tiles
         hipLaunchKernelGGL(k_upslab, dim3(slab_grid), dim3(SLAB_THREADS), 0, st, A.x, A.y, A.hl_ptr, A.hl_col, A.hl_val,
                            A.n_rows, A.dR, slab_grid / 8);
@@ -1428,6 +1428,194 @@ size_t hub_lds_bytes(const ecut_sectors *s) {
     b += al((size_t)(H.n_coef > 0 ? H.n_coef : 1) * 8);
     if (!H.uniform_u) b += 3 * 256 * 8;
     return b;
+}
+
+// ------------------------------------------------------------------------
+// Two-pass Hubbard application on flat work items (any hopping graph).
+//
+// The left operator H_up (x) 1 combines whole rows: every row is read by its
+// ~8 neighbours, which must find it in L2 for the gather not to cost one HBM
+// (or last-level-cache) read per neighbour.  The right operator 1 (x) H_dn
+// gathers inside a row, whose class of columns is too wide to keep the left
+// operator's neighbour window on chip at the same time.  So the two operators
+// run as two passes over the vector:
+//   pass 1 (k_hubU): y = H_up x on column slabs, items slab-major with the
+//           rows of a slab in level order, so the blocks an XCD has in flight
+//           share their neighbour rows;
+//   pass 2 (k_hubD): y = xscale (y + H_dn x + D x) - zcoef z on runs of whole
+//           rows, the in-row gathers served from L2, plus one partial
+//           <x, y> per item for the Lanczos step.
+// Both launches are one block per item (no persistent loop): the hardware
+// dispatches blocks in index order, so an XCD's blocks in flight are always a
+// contiguous window of its item range.  Block b runs on XCD b % 8 and takes
+// item (b % 8) * per_xcd + b / 8 (n_xcd == 8), or item b (n_xcd == 1).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_item(int n_xcd, int per_xcd) {
+    return n_xcd == 8 ? (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+}
+
+template <bool PAIR, bool STREAM>
+__device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
+    const int slab = it / A.n_rgroups;
+    const int rg = it - slab * A.n_rgroups;
+    constexpr int CPL = PAIR ? 2 : 1;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int c = (slab * 64 + lane) * CPL;
+    const bool ok = c < A.dR;
+    const int64_t dR = A.dR;
+    const int r0 = rg * A.rows_per_item;
+    const int r1 = min(r0 + A.rows_per_item, A.n_rows);
+    for (int r = r0 + wave; r < r1; r += HUBU_THREADS / 64) {
+        const int a = A.rows[r];
+        const int q0 = A.hl_ptr[a], q1 = A.hl_ptr[a + 1];
+        double acc0 = 0.0, acc1 = 0.0;
+        for (int q = q0; q < q1; q += HUBU_NB) {
+            double v0[HUBU_NB], v1[HUBU_NB];
+            // every load of the batch is issued before any is consumed
+#pragma unroll
+            for (int k = 0; k < HUBU_NB; ++k) {
+                v0[k] = v1[k] = 0.0;
+                if (q + k < q1 && ok) {
+                    const double *src = A.x + (int64_t)A.hl_col[q + k] * dR + c;
+                    if constexpr (PAIR) {
+                        const double2 p = *(const double2 *)src;
+                        v0[k] = p.x;
+                        v1[k] = p.y;
+                    } else {
+                        v0[k] = *src;
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < HUBU_NB; ++k)
+                if (q + k < q1) {
+                    const double h = A.uniform ? 1.0 : A.hl_val[q + k];
+                    acc0 += h * v0[k];
+                    acc1 += h * v1[k];
+                }
+        }
+        if (A.uniform) {   // sum, then scale once
+            acc0 *= A.hop;
+            acc1 *= A.hop;
+        }
+        if (ok) {
+            double *dst = A.y + (int64_t)a * dR + c;
+            if constexpr (PAIR) {
+                if constexpr (STREAM) {
+                    __builtin_nontemporal_store(acc0, dst);
+                    __builtin_nontemporal_store(acc1, dst + 1);
+                } else {
+                    *(double2 *)dst = make_double2(acc0, acc1);
+                }
+            } else {
+                store_result<STREAM>(dst, acc0);
+            }
+        }
+    }
+}
+
+template <bool PAIR, bool STREAM>
+__global__ __launch_bounds__(HUBU_THREADS) void k_hubU(const HubUArgs A, int n_xcd, int per_xcd) {
+    const int it = xcd_item(n_xcd, per_xcd);
+    if (it >= A.n_items) return;
+    hubU_item<PAIR, STREAM>(A, it);
+}
+
+// NS: bond slots held in registers (>= A.n_slots).  The source column of
+// each bond for this thread's column is loaded once per item and reused for
+// every row of it; a slot of -1 (the bond cannot hop from this column) reads
+// nothing.  The terms of an amplitude are summed in slot order.
+template <int NS, bool UNIF, bool STREAM>
+__global__ __launch_bounds__(HUBD_THREADS) void k_hubD(const HubDArgs A, int n_xcd, int per_xcd) {
+    __shared__ double red[HUBD_THREADS / 64];
+    const int it = xcd_item(n_xcd, per_xcd);
+    if (it >= A.n_items) return;   // uniform over the block
+    const double2 ef = epi_factors(A.dscale, A.xscale, A.zcoef);
+    const int rg = it / A.n_chunks;
+    const int chunk = it - rg * A.n_chunks;
+    const int c = chunk * HUBD_THREADS + (int)threadIdx.x;
+    const bool ok = c < A.dR;
+    const int64_t dR = A.dR;
+    int src[NS];
+    double hv[UNIF ? 1 : NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        src[k] = (ok && k < A.n_slots) ? A.col[(int64_t)k * dR + c] : -1;
+        if constexpr (!UNIF) hv[k] = src[k] >= 0 ? A.val[(int64_t)k * dR + c] : 0.0;
+    }
+    const uint32_t bw = ok ? A.rwords[c] : 0u;
+    const int r0 = rg * A.rows_per_item;
+    const int r1 = min(r0 + A.rows_per_item, A.n_rows);
+    double part = 0.0;
+    if (ok) {
+        for (int a = r0; a < r1; ++a) {
+            const int64_t base = (int64_t)a * dR;
+            const double *__restrict__ xr = A.x + base;
+            const double x0 = xr[c];
+            const double t = STREAM ? __builtin_nontemporal_load(A.y + base + c) : A.y[base + c];
+            const double zv = A.z ? (STREAM ? __builtin_nontemporal_load(A.z + base + c) : A.z[base + c]) : 0.0;
+            double dn = 0.0;
+#pragma unroll
+            for (int k0 = 0; k0 < NS; k0 += HUBD_NB) {
+                double v[HUBD_NB];
+#pragma unroll
+                for (int k = 0; k < HUBD_NB; ++k) v[k] = src[k0 + k] >= 0 ? xr[src[k0 + k]] : 0.0;
+#pragma unroll
+                for (int k = 0; k < HUBD_NB; ++k) dn += UNIF ? v[k] : hv[k0 + k] * v[k];
+            }
+            const uint32_t both = A.lwords[a] & bw;
+            double dg;
+            if (A.uniform_u) {
+                dg = A.u0 * (double)__popc(both);
+            } else {
+                dg = 0.0;
+                for (uint32_t m = both; m; m &= m - 1u) dg += A.u[__ffs(m) - 1];
+            }
+            double y = UNIF ? ef.x * (t + A.hop * dn + dg * x0) : ef.x * (t + dn + dg * x0);
+            if (A.z) y -= ef.y * zv;
+            store_result<STREAM>(A.y + base + c, y);
+            part += x0 * y;
+        }
+    }
+    if (A.partials) {
+        const double sum = block_sum(part, red);
+        if (threadIdx.x == 0) A.partials[it] = sum;
+    }
+}
+
+template <int NS>
+static void launch_hubD(const HubDArgs &D, bool stream, dim3 grid, int xu, int pd, hipStream_t st) {
+    const bool unif = D.val == nullptr;
+    if (unif && stream) hipLaunchKernelGGL((k_hubD<NS, true, true>), grid, dim3(HUBD_THREADS), 0, st, D, xu, pd);
+    else if (unif) hipLaunchKernelGGL((k_hubD<NS, true, false>), grid, dim3(HUBD_THREADS), 0, st, D, xu, pd);
+    else if (stream) hipLaunchKernelGGL((k_hubD<NS, false, true>), grid, dim3(HUBD_THREADS), 0, st, D, xu, pd);
+    else hipLaunchKernelGGL((k_hubD<NS, false, false>), grid, dim3(HUBD_THREADS), 0, st, D, xu, pd);
+}
+
+hipError_t launch_hub6_left(const HubUArgs &U, int n_xcd, hipStream_t st) {
+    const bool pair = (U.dR % 2 == 0) && !(((uintptr_t)U.x | (uintptr_t)U.y) & 15);
+    const bool stream = (int64_t)U.n_rows * U.dR >= STREAM_STORE_MIN;
+    const int xu = n_xcd == 1 ? 1 : 8;
+    const int pu = (U.n_items + xu - 1) / xu;
+    const dim3 gu(xu == 8 ? 8 * pu : U.n_items);
+    if (pair && stream) hipLaunchKernelGGL((k_hubU<true, true>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
+    else if (pair) hipLaunchKernelGGL((k_hubU<true, false>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
+    else if (stream) hipLaunchKernelGGL((k_hubU<false, true>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
+    else hipLaunchKernelGGL((k_hubU<false, false>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
+    return hipGetLastError();
+}
+
+hipError_t launch_hubD_only(const HubDArgs &D, int n_xcd, hipStream_t st) {
+    const bool stream = (int64_t)D.n_rows * D.dR >= STREAM_STORE_MIN;
+    const int xu = n_xcd == 1 ? 1 : 8;
+    const int pd = (D.n_items + xu - 1) / xu;
+    const dim3 gd(xu == 8 ? 8 * pd : D.n_items);
+    if (D.n_slots <= 8) launch_hubD<8>(D, stream, gd, xu, pd, st);
+    else if (D.n_slots <= 16) launch_hubD<16>(D, stream, gd, xu, pd, st);
+    else if (D.n_slots <= HUBD_MAX_SLOTS) launch_hubD<HUBD_MAX_SLOTS>(D, stream, gd, xu, pd, st);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------
@@ -1845,6 +2033,7 @@ hipError_t set_hub_lds_limits(size_t bytes) {
     const int b = (int)bytes;
     e = hipFuncSetAttribute((const void *)k_spin<true>, hipFuncAttributeMaxDynamicSharedMemorySize, SPIN_TILE * 8);
     if (e != hipSuccess) return e;
+
     e = hipFuncSetAttribute((const void *)k_hubrow<1024, HUBROW_P, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             2 * HUBROW_P * 1024 * 10);
     if (e != hipSuccess) return e;

@@ -141,6 +141,7 @@ static void build_spin_tables(ecut_sectors *s);
 static void build_hubseg_tables(ecut_sectors *s);
 static void make_rank_tables(ecut_sectors *s);
 static void build_hubrow_tables(ecut_sectors *s, const ecut_model_desc *m);
+static void build_hub6_tables(ecut_sectors *s, const ecut_model_desc *m);
 void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 
@@ -474,6 +475,8 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
         if (n <= 16) s->hub_rw16[col] = (uint16_t)w;
     }
     build_hubrow_tables(s, m);
+    build_hub6_tables(s, m);
+    make_row_order(s, 1, s->level_rows);
     make_row_order(s, 0, s->row_order);
 
     // ---- class tiles of the down basis
@@ -765,6 +768,54 @@ static void build_hubseg_tables(ecut_sectors *s) {
     s->hs_n_slots = slot;
     s->hs_max_tile = max_tile;
     s->hubseg_ok = true;
+}
+
+// Tables of the two-pass flat kernels: the down-spin operator H_dn in column
+// space (class-major columns), one slot per bond: col[b * d_R + c] is the
+// column reached from column c by a hop across bond b, or -1 if the bond
+// cannot hop there (both sites empty or both occupied); val[b * d_R + c] its
+// value -t_b times the fermion sign.  Bond-major slots make the gathers of a
+// wave for one bond touch neighbouring addresses: a hop inside the high half
+// moves a whole segment of columns by the same offset, a hop inside the low
+// half stays in the segment.  The values are dropped when every hop of both
+// spins has the same value (the kernels then scale the neighbour sums once).
+static void build_hub6_tables(ecut_sectors *s, const ecut_model_desc *m) {
+    s->hub6_ok = false;
+    const BlockDev &B = s->blocks[0];
+    const int64_t dR = B.d_r;
+    if (dR < 1 || B.d_l < 1 || dR >= (1ll << 30)) return;
+    std::vector<int> bonds;
+    for (int b = 0; b < m->n_bonds; ++b)
+        if (m->t[b] != 0.0) bonds.push_back(b);
+    const int nb = (int)bonds.size();
+    if (nb > HUBD_MAX_SLOTS || (int64_t)std::max(nb, 1) * dR >= (1ll << 31)) return;
+    bool uniform = true;
+    double hop = 0.0;
+    bool have = false;
+    for (const std::vector<double> *v : {&s->hl_val, &s->hr_val})
+        for (double x : *v) {
+            if (!have) { hop = x; have = true; }
+            uniform = uniform && x == hop;
+        }
+    s->h6_uniform = uniform;
+    s->h6_hop = hop;
+    s->h6_maxq = nb;
+    s->h6_col.assign(std::max<int64_t>(1, (int64_t)nb * dR), -1);
+    s->h6_val.clear();
+    if (!uniform) s->h6_val.assign(std::max<int64_t>(1, (int64_t)nb * dR), 0.0);
+    for (int64_t c = 0; c < dR; ++c) {
+        const uint32_t w = s->hub_rw32[c];
+        for (int k = 0; k < nb; ++k) {
+            const int b = bonds[k];
+            uint32_t w2;
+            int sg;
+            if (!fermion_hop(w, m->bond_i[b], m->bond_j[b], w2, sg) && !fermion_hop(w, m->bond_j[b], m->bond_i[b], w2, sg))
+                continue;
+            s->h6_col[(size_t)k * dR + c] = s->hub_col_of_rank[colex_rank(w2)];
+            if (!uniform) s->h6_val[(size_t)k * dR + c] = -m->t[b] * sg;
+        }
+    }
+    s->hub6_ok = true;
 }
 
 // Column of the down word of canonical rank r in the block (identity unless

@@ -73,7 +73,7 @@ void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) 
 }
 
 ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
-    if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 5)
+    if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 7)
         return fail(ECUT_EINVAL, "bad tuning");
     if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
     if (T.tile < 0) return fail(ECUT_EINVAL, "tile must not be negative");
@@ -85,8 +85,14 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
             return fail(ECUT_EINVAL, "whole-row work groups take 256, 512 or 1024 threads");
         if (T.tile != 0 && !s->blocks.empty() && s->blocks[0].d_r > 2 * HUBROW_P * T.tile)
             return fail(ECUT_EUNSUPPORTED, "rows longer than 14 columns per thread of the work group");
+    } else if (s->kernel == 1 && (T.variant == 6 || T.variant == 7)) {
+        // the two-pass kernels: tile = rows per item of the right-operator pass
+        if (T.tile != 0 && T.tile != 1 && T.tile != 2 && T.tile != 4 && T.tile != 8 && T.tile != 16)
+            return fail(ECUT_EINVAL, "two-pass items take 1, 2, 4, 8 or 16 rows");
+        if (T.grid > 64) return fail(ECUT_EINVAL, "left-operator items take at most 64 rows");
     } else if (T.tile != 0) {
-        return fail(ECUT_EUNSUPPORTED, "the tile applies to the spin kernel and the whole-row Hubbard kernel only");
+        return fail(ECUT_EUNSUPPORTED,
+                    "the tile applies to the spin kernel, the whole-row and the two-pass Hubbard kernels only");
     }
     if (s->spin_ok && T.order > 1) return fail(ECUT_EINVAL, "spin problems take row order 0 or 1");
     if ((T.variant == 0 || T.variant == 2) && s->kernel == 1 && !s->hub2_ok)
@@ -94,6 +100,10 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if (T.variant == 3 && s->kernel == 1 && !s->hub3_ok) return fail(ECUT_EUNSUPPORTED, "split passes not available");
     if (T.variant == 5 && s->kernel == 1 && !s->hubseg_ok)
         return fail(ECUT_EUNSUPPORTED, "segment tiles not available (needs uniform, sign-free hopping, <= 16 sites)");
+    if (T.variant == 6 && s->kernel == 1 && !s->hub6_ok) return fail(ECUT_EUNSUPPORTED, "two-pass kernels not available");
+    if (T.variant == 7 && s->kernel == 1 && !s->hub3_ok)
+        return fail(ECUT_EUNSUPPORTED, "two passes with class tiles need the uniform-chain tables");
+    if (T.variant == 7 && T.tile != 0) return fail(ECUT_EINVAL, "variant 7 takes tile 0");
     if (T.variant == 4 && s->kernel == 1 && !s->hubrow_ok)
         return fail(ECUT_EUNSUPPORTED, "whole-row kernel not available (more than 16 sites, odd or too long rows)");
     if (s->kernel == 1 && (T.order != s->tune.order || T.variant != s->tune.variant)) {
@@ -186,6 +196,14 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
                         for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, order, 4, threads == 1024 ? 0 : threads});
         if (s->hubseg_ok)
             for (int xcd : {1, 8}) cands.push_back(ApplyTuning{0, xcd, 0, 5});
+        if (s->hub6_ok)
+            for (int order : {0, 1, 2})
+                for (int xcd : {1, 8})
+                    for (int urows : {4, 8})
+                        for (int rows : {2, 8}) cands.push_back(ApplyTuning{urows, xcd, order, 6, rows});
+        if (s->hub3_ok)
+            for (int urows : {4, 8})
+                for (int order : {7, 8}) cands.push_back(ApplyTuning{urows, 8, order, 7, 0});
     } else if (s->spin_ok) {
         // spin kernel: short-row tile and grid; then the generic row kernel
         for (int order : {0, 1})

@@ -98,14 +98,14 @@ _HUB_CASES = [I.hubbard12(),
               I.Problem(I.random_hubbard_model(np.random.default_rng(78), 10, n_bonds=12), I.Cut("updn"), 3, 5)]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("order", [0, 2, 4, 7, 9])
 def test_hubbard_kernel_variants_and_orders(dev, variant, order):
     """Every Hubbard kernel (class tiles with the uniform-chain fast path,
     whole rows in LDS, generic class tiles, two passes, whole rows with
-    16-byte access and ranked hops, segment tiles) under several work orders
-    agrees with the oracle; uniform chains and random long-range couplings
-    (fermion signs), even and odd row lengths."""
+    16-byte access and ranked hops, segment tiles, two passes on flat items)
+    under several work orders agrees with the oracle; uniform chains and
+    random long-range couplings (fermion signs), even and odd row lengths."""
     for k, p in enumerate(_HUB_CASES):
         s = O.Sector(p.model, p.n_up, p.n_dn)
         psi = I.psi(500 + k, s.n)
@@ -120,6 +120,12 @@ def test_hubbard_kernel_variants_and_orders(dev, variant, order):
             with pytest.raises(_ecut().EcutError):
                 S.set_tuning(0, 1, order, variant)
             continue
+        if variant == 6:
+            assert S.info.kernel_flags & 32   # every up/down problem takes the two-pass kernels
+        if variant == 7 and not S.info.kernel_flags & 2:
+            with pytest.raises(_ecut().EcutError):
+                S.set_tuning(0, 1, order, variant)
+            continue
         if variant == 5 and not S.info.kernel_flags & 16:
             assert not S.info.kernel_flags & 2    # segment tiles cover every uniform sign-free chain here
             with pytest.raises(_ecut().EcutError):
@@ -128,6 +134,47 @@ def test_hubbard_kernel_variants_and_orders(dev, variant, order):
         S.set_tuning(0, 8 if order % 2 == 0 else 1, order, variant)
         assert S.get_tuning()["variant"] == variant
         _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} v{variant} o{order}")
+
+
+def test_hubbard_two_pass_item_shapes_bit_exact(dev):
+    """The two-pass kernels (variant 6) give the same vector bit for bit for
+    every rows-per-item tile of either pass, XCD chunking and row order (each
+    amplitude is summed in the same order whatever the item shape), the
+    oracle's vector;
+    in Lanczos steps the per-item partials follow the item split and the
+    energy stays the oracle's.  Cases: uniform chains (no hop values stored),
+    random long-range hoppings with fermion signs and site-dependent U, odd
+    row lengths (one column per lane), a 1 x n and an n x 1 block."""
+    import torch
+    E = _ecut()
+    cases = list(_HUB_CASES) + [I.Problem(I.hubbard_chain(7, 1.0, 2.0), I.Cut("updn"), 0, 3),
+                                I.Problem(I.hubbard_chain(7, 1.0, 2.0), I.Cut("updn"), 4, 7)]
+    for k, p in enumerate(cases):
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        psi = I.psi(1500 + k, s.n)
+        y_ref = s.apply(psi)
+        S = E.Sectors.from_problem(p)
+        assert S.info.kernel_flags & 32
+        x = S.import_(torch.from_numpy(psi).to(dev))
+        y0 = None
+        for tile, left in ((1, 0), (2, 4), (4, 0), (8, 16), (16, 1)):
+            for xcd, order in ((8, 0), (1, 1), (8, 2)):
+                # left: rows per item of the left-operator pass (0 = default)
+                S.set_tuning(left, xcd, order, 6, tile)
+                y = S.apply(x)
+                torch.cuda.synchronize()
+                if y0 is None:
+                    y0 = y
+                    _compare(S.export(y).cpu().numpy(), y_ref, f"{p.model.name} two-pass")
+                assert torch.equal(y, y0), (p.model.name, tile, xcd, order)
+        if s.n >= 64:
+            e_ref = s.lanczos(I.psi(1600 + k, s.n), 400, tol=1e-14)[0][-1]
+            v0 = S.import_(torch.from_numpy(I.psi(1600 + k, s.n)).to(dev))
+            for tile in (1, 16):
+                S.set_tuning(0, 8, 1, 6, tile)
+                ws = torch.full((S.lanczos_workspace(400, tol=1e-11),), float("nan"), dtype=torch.float64, device=dev)
+                e, st, _ = S.lanczos(v0, 400, tol=1e-11, workspace=ws)
+                assert st["converged"] and abs(e - e_ref) <= 1e-10, (p.model.name, tile, e, e_ref)
 
 
 def test_hubbard_whole_row_group_sizes(dev):
@@ -171,42 +218,90 @@ def test_apply_workload_full_vs_oracle(dev, name):
     _compare(_gpu_apply_canonical(S, psi, dev), y_ref, name)
 
 
-@pytest.mark.parametrize("name", ["hubbard16", "j1j2_6x5"])
-def test_apply_full_size_sampled_vs_oracle(dev, name):
-    """Full-size application in the launch configuration the bench times;
-    the oracle recomputes a few thousand sampled rows one by one."""
+def _full_size_setup(name, dev):
+    """Sector handle autotuned on the workload's input (the launch
+    configuration the benchmark times), the oracle's sector and the input."""
     import torch
     p = I.WORKLOADS[name]()
-    words = O.enumerate_basis(p.model.kind, p.model.n_sites, p.n_up, p.n_dn)
-    n = len(words)
-    psi = I.psi(p.meta["seed"], n)
+    sec = O.Sector(p.model, p.n_up, p.n_dn)
+    psi = I.psi(p.meta["seed"], sec.n)
     S = _ecut().Sectors.from_problem(p)
-    # the launch configuration the benchmark times: autotuned on this input
     xt = S.import_(torch.from_numpy(psi).to(dev))
-    S.autotune(xt, torch.empty_like(xt))
+    tuned = S.autotune(xt, torch.empty_like(xt))
     del xt
-    y = _gpu_apply_canonical(S, psi, dev)
-    rng = np.random.default_rng(5)
-    rows = np.unique(np.concatenate([rng.integers(0, n, 3000), [0, 1, n // 2, n - 2, n - 1]]))
-    sec = O.Sector.__new__(O.Sector)
-    sec.model, sec.om, sec.words, sec.n = p.model, O.OracleModel(p.model), words, n
-    y_ref = sec.apply_rows(psi, rows)
-    err = np.abs(y[rows] - y_ref)
-    assert np.max(err) <= RTOL * np.max(np.abs(y_ref)) * 10
-    assert np.linalg.norm(err) / np.linalg.norm(y_ref) <= RTOL
-    # Hermiticity at full size on the device: <phi|H psi> = <H phi|psi>
+    return p, sec, psi, S, tuned
+
+
+def _compare_full(y, y_ref, what):
+    """Whole-vector element-wise comparison (relative L2 and max error)."""
+    d = y - y_ref
+    err = np.linalg.norm(d) / np.linalg.norm(y_ref)
+    big = np.max(np.abs(d)) / np.max(np.abs(y_ref))
+    print(f"[full] {what}: relative L2 {err:.2e}, max {big:.2e}", flush=True)
+    assert err <= RTOL, f"{what}: relative L2 {err:.3e}"
+    assert big <= RTOL * 10, f"{what}: max element error {big:.3e}"
+
+
+# Hubbard kernels at full size, each compared with the oracle's whole vector:
+# (grid, n_xcd, row order, variant, tile)
+_FULL_HUB_TUNINGS = ((0, 8, 8, 0, 0), (0, 8, 7, 0, 0), (0, 1, 1, 4, 0), (0, 8, 2, 4, 0), (0, 8, 0, 5, 0),
+                     (0, 8, 8, 7, 0), (8, 8, 7, 7, 0), (0, 8, 1, 6, 4), (4, 1, 0, 6, 2), (16, 8, 2, 6, 8))
+
+
+def test_apply_full_size_hubbard16_whole_vector_vs_oracle(dev):
+    """16-site Hubbard chain, 165,636,900 amplitudes: the whole H*psi vector
+    of the autotuned launch configuration, and of every Hubbard kernel
+    variant, compared element by element with the oracle's (rows of the full
+    occupation-basis H, no stored matrix), plus Hermiticity on the device."""
+    import time
+    import torch
+    p, sec, psi, S, tuned = _full_size_setup("hubbard16", dev)
+    print(f"[full] hubbard16 autotuned {tuned}", flush=True)
+    t0 = time.time()
+    y_ref = sec.apply(psi, use_csr=False)
+    print(f"[full] oracle apply {time.time() - t0:.1f} s on {O.num_threads()} threads", flush=True)
+    _compare_full(_gpu_apply_canonical(S, psi, dev), y_ref, f"autotuned {tuned}")
+    for t in _FULL_HUB_TUNINGS:
+        S.set_tuning(*t)
+        _compare_full(_gpu_apply_canonical(S, psi, dev), y_ref, f"tuning {t}")
     x = torch.from_numpy(psi).to(dev)
-    phi = torch.from_numpy(I.psi(p.meta["seed"] + 2, n)).to(dev)
+    phi = torch.from_numpy(I.psi(p.meta["seed"] + 2, sec.n)).to(dev)
     xb, pb = S.import_(x), S.import_(phi)
     lhs = torch.dot(pb, S.apply(xb)).item()
     rhs = torch.dot(S.apply(pb), xb).item()
     assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
-    if name == "hubbard16":
-        # every Hubbard kernel at full size agrees with the autotuned one
-        for t in ((0, 8, 8, 0), (0, 1, 1, 4), (0, 8, 2, 4), (0, 8, 0, 5), (0, 1, 0, 5)):
-            S.set_tuning(*t)
-            yt = _gpu_apply_canonical(S, psi, dev)
-            assert np.linalg.norm(yt - y) / np.linalg.norm(y) <= RTOL, t
+
+
+def test_apply_full_size_j1j2_blocks_vs_oracle(dev):
+    """6x5 J1-J2 lattice, 155,117,520 amplitudes in 16 blocks: in the
+    autotuned launch configuration, every amplitude of the largest block
+    (6,435 x 6,435 = 41.4M) and of blocks 0, 1, 14 and 15 against the
+    oracle's rows, the blocks found through the
+    oracle's own bipartite map; Hermiticity on the device."""
+    import time
+    import torch
+    p, sec, psi, S, tuned = _full_size_setup("j1j2_6x5", dev)
+    print(f"[full] j1j2_6x5 autotuned {tuned}", flush=True)
+    y = _gpu_apply_canonical(S, psi, dev)
+    pos, blocks = sec.bipartite(p.cut.kind, p.cut.left_mask)
+    sizes = blocks[:, 1] * blocks[:, 2]
+    big = int(np.argmax(sizes))
+    for b in sorted({0, 1, big, len(blocks) - 2, len(blocks) - 1}):
+        off, n_b = int(blocks[b, 3]), int(sizes[b])
+        rows = np.nonzero((pos >= off) & (pos < off + n_b))[0]
+        assert len(rows) == n_b
+        t0 = time.time()
+        y_ref = sec.apply_rows(psi, rows)
+        print(f"[full] block {b}: {n_b} rows, oracle {time.time() - t0:.1f} s", flush=True)
+        _compare_full(y[rows], y_ref, f"j1j2 block {b}")
+        del rows, y_ref
+    del pos
+    x = torch.from_numpy(psi).to(dev)
+    phi = torch.from_numpy(I.psi(p.meta["seed"] + 2, sec.n)).to(dev)
+    xb, pb = S.import_(x), S.import_(phi)
+    lhs = torch.dot(pb, S.apply(xb)).item()
+    rhs = torch.dot(S.apply(pb), xb).item()
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
 
 
 def test_cut_invariance_heisenberg16(dev):

@@ -58,6 +58,10 @@ CASES = [
     I.Problem(I.j1j2_lattice(4, 3), I.Cut("spatial", I.left_mask_first(6)), 6),
     I.Problem(I.hubbard_chain(6, 1.0, 3.0), I.Cut("updn"), 2, 4),
     I.Problem(I.hubbard_chain(5, 1.0, 3.0), I.Cut("updn"), 0, 5),
+    # the two headline sizes: 165,636,900 and 155,117,520 positions, every one
+    # checked against the oracle's own enumeration
+    I.hubbard16(),
+    I.j1j2_6x5(),
 ]
 
 
@@ -118,7 +122,7 @@ def test_workload_block_structure():
     # a straight cut between x=2 and x=3 of the 6x5 lattice crosses 5 J1 and 8 J2 bonds
     assert S4.info.n_cut_bonds == 13 and S4.info.n_cross_offdiag == 26 and S4.info.n_cross_diag == 13
     S3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)
-    assert S3.dim == 165636900 and S3.info.kernel == 1 and S3.info.kernel_flags == 1 | 2 | 8 | 16
+    assert S3.dim == 165636900 and S3.info.kernel == 1 and S3.info.kernel_flags == 1 | 2 | 8 | 16 | 32
     assert S3.info.n_eff == pytest.approx(1.0)
 
 
