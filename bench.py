@@ -55,9 +55,29 @@ def traffic_from_profile(kernel, workload, per_launch_alg):
     return d.get("bytes_per_launch"), tuning
 
 
+def tuning_str(t):
+    return ",".join(str(t[k]) for k in ("grid", "n_xcd", "row_order", "variant", "tile"))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, seconds):
-    """The oracle, row by row, on a contiguous seeded slice of the same
-    workload's rows (bounded so the run stays short)."""
+    """The oracle on the host cores, timed on a bounded contiguous sample of
+    the workload's rows (the whole-sector CSR of the 16-site chain is 34 GB
+    and takes minutes to build): the CSR of the sample rows is built once,
+    then its product with the seeded input is timed on one thread and on all
+    threads; the row-by-row generator (no stored matrix) is timed on the
+    same sample.  Rates are scaled to whole applications (sample rows / dim
+    of an application per second of the sample)."""
     import numpy as np
     import oracle as O
     from paper_2605_07621_amd import inputs as I
@@ -66,20 +86,55 @@ def cpu_baseline(p, seconds):
     psi = I.psi(p.meta["seed"], n)
     sec = O.Sector.__new__(O.Sector)
     sec.model, sec.om, sec.words, sec.n = p.model, O.OracleModel(p.model), words, n
+    all_threads = O.num_threads()
     start = int(np.random.default_rng(11).integers(0, n // 2))
-    rows = np.arange(start, start + 20000, dtype=np.int64)
+    # sample size: about `seconds` of row-by-row work on all threads
+    probe = np.arange(start, start + 20000, dtype=np.int64)
     t0 = time.perf_counter()
-    sec.apply_rows(psi, rows)
+    sec.apply_rows(psi, probe)
     dt = time.perf_counter() - t0
-    m = int(min(n - start, max(20000, 20000 * seconds / max(dt, 1e-6))))
+    m = int(min(n - start, max(20000, 20000 * seconds / 4 / max(dt, 1e-6))))
     rows = np.arange(start, start + m, dtype=np.int64)
     t0 = time.perf_counter()
     sec.apply_rows(psi, rows)
-    dt = time.perf_counter() - t0
-    return dict(value=(m / n) / dt, unit="H*psi/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{m} of {n} rows (contiguous from row {start}), row-by-row oracle, "
-                       f"{dt:.1f} s; value scaled to full applications",
-                seconds=round(dt, 3))
+    t_rows = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rp, col, val = sec.csr_rows(start, start + m)
+    t_build = time.perf_counter() - t0
+    legs = {}
+    for threads in (1, all_threads):
+        O.set_threads(threads)
+        O.spmv_csr(rp, col, val, psi)   # first touch
+        reps, t_acc = 0, 0.0
+        while t_acc < (2.0 if threads == 1 else 1.0) or reps < 3:
+            t0 = time.perf_counter()
+            O.spmv_csr(rp, col, val, psi)
+            t_acc += time.perf_counter() - t0
+            reps += 1
+        legs[threads] = t_acc / reps
+    O.set_threads(all_threads)
+    frac = m / n
+    return dict(value=frac / legs[all_threads], unit="H*psi/s", cores=all_threads, kind="oracle",
+                sample=f"rows {start}..{start + m - 1} ({m} of {n}, contiguous): CSR of the sample rows "
+                       f"(oracle row generator), product timed; rate scaled to whole applications",
+                csr_spmv={"threads_all": all_threads, "threads_all_s_per_apply": legs[all_threads] / frac,
+                          "threads_1_s_per_apply": legs[1] / frac, "sample_nnz": int(len(col)),
+                          "sample_build_s": round(t_build, 2)},
+                row_generator={"threads": all_threads, "s_per_apply": t_rows / frac},
+                nproc=os.cpu_count(), cpu_model=_cpu_model(),
+                oracle_lanczos=_golden_lanczos_time(p))
+
+
+def _golden_lanczos_time(p):
+    """Seconds per step of the oracle's own Lanczos run that wrote the
+    workload's stored energy (tests/golden; that run's host and threads)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{p.meta.get('name', '')}_energy.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    return {"s_per_step": round(d["lanczos_s"] / d["steps"], 3), "steps": d["steps"], "threads": d["oracle_threads"],
+            "method": d["method"], "host": "the host that wrote tests/golden (not the benchmark host)"}
 
 
 def _run_server(reqs, arrivals, budget, max_active, sequential, tol=1e-10, max_steps=600):
@@ -127,6 +182,24 @@ def _warm_tunings(reqs, budget):
     return len(first)
 
 
+def _serving_oracle(n_requests):
+    """The oracle's ground energy of every request of the serving mix
+    (tests/golden/serving_2026_energies.json, written by
+    tests/golden/make_golden.py), or None for another mix."""
+    path = os.path.join(ROOT, "tests", "golden", "serving_2026_energies.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d["requests"] != n_requests:
+        return None
+    return [e["energy"] for e in d["energies"]]
+
+
+def _max_err(out, ref):
+    return max(abs(r["energy"] - e) for r, e in zip(out, ref))
+
+
 def serving_bench(n_requests, budget_gb):
     """Mixed ground-state requests (seeded XXZ and Hubbard chains, Sz=0 / half
     filling, tol 1e-10): sequential one-at-a-time solves vs continuous batching
@@ -147,9 +220,12 @@ def serving_bench(n_requests, budget_gb):
     cap = _run_server(reqs, zeros, budget, 32, False)
     s_cap = _lat_stats(cap, min(r["t_submit"] for r in cap))
     de = max(max(abs(a["energy"] - b["energy"]), abs(a["energy"] - c["energy"])) for a, b, c in zip(seq, bat, cap))
+    ref = _serving_oracle(n_requests)
     out = {"requests": len(reqs), "tol": 1e-10,
            "closed_loop": {"sequential": s_seq, "batched": s_bat, "batched_max32": s_cap},
            "max_energy_diff_batched_vs_sequential": de,
+           "max_abs_energy_error_vs_oracle": None if ref is None else {
+               "sequential": _max_err(seq, ref), "batched": _max_err(bat, ref), "batched_max32": _max_err(cap, ref)},
            "speedup_solves_per_s": round(s_bat["solves_per_s"] / s_seq["solves_per_s"], 3),
            "speedup_solves_per_s_max32": round(s_cap["solves_per_s"] / s_seq["solves_per_s"], 3)}
     mu = s_seq["solves_per_s"]
@@ -160,6 +236,8 @@ def serving_bench(n_requests, budget_gb):
         r_cap = _run_server(reqs, arr, budget, 32, False)
         progress(f"serving: poisson rho={rho} done")
         out[f"poisson_rho{rho}"] = {"rate_per_s": round(rho * mu, 3),
+                                    "max_abs_energy_error_vs_oracle": None if ref is None else max(
+                                        _max_err(r_seq, ref), _max_err(r_bat, ref), _max_err(r_cap, ref)),
                                     "sequential": _lat_stats(r_seq, min(r["t_submit"] for r in r_seq)),
                                     "batched": _lat_stats(r_bat, min(r["t_submit"] for r in r_bat)),
                                     "batched_max32": _lat_stats(r_cap, min(r["t_submit"] for r in r_cap))}
@@ -173,7 +251,8 @@ def kernel_name(S):
         v = t["variant"]
         if v == 0:
             return "k_hub3" if info.kernel_flags & 2 else "k_hub2"
-        return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3", 4: "k_hubrow", 5: "k_hubseg"}[v]
+        return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3", 4: "k_hubrow", 5: "k_hubseg", 6: "k_hubU+k_hubD",
+                7: "k_hubU+k_hub3"}[v]
     return "k_spin" if (info.kernel_flags & 4 and t["variant"] == 0) else "k_rows"
 
 
@@ -212,14 +291,20 @@ def other_workloads(names, stream):
                      "applies_per_s": round(1e3 / ms, 2), "algorithmic_GBps": round(alg / (ms * 1e-3) / 1e9, 1)}
         steps = p.meta.get("lanczos_steps")
         if name == "j1j2_6x5":
-            # Lanczos energy of the 6x5 lattice to 1e-10 (three-term recurrence);
-            # there is no oracle value at this size (parity unpinned)
+            # Lanczos energy of the 6x5 lattice to 1e-10 (three-term recurrence)
+            # against the oracle's stored energy
             v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to("cuda:0"))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             e, st, _ = S.lanczos(v0, 600, tol=1e-10, allow_notconv=True)
             out[name]["lanczos"] = {"steps": st["steps"], "converged": bool(st["converged"]),
                                     "seconds": round(time.perf_counter() - t0, 3), "energy": e, "tol": 1e-10}
+            gold = os.path.join(ROOT, "tests", "golden", f"{name}_energy.json")
+            if os.path.exists(gold):
+                with open(gold) as f:
+                    ref = json.load(f)["energy"]
+                out[name]["lanczos"]["oracle_energy"] = ref
+                out[name]["lanczos"]["abs_diff_vs_oracle"] = abs(e - ref)
             del v0
         if steps:
             # the configuration's fixed-step Lanczos energy (start vector: seed + 1)
@@ -452,7 +537,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the ground-state solve of the workload")
     ap.add_argument("--solve-keep", type=int, default=150)
     ap.add_argument("--no-others", action="store_true", help="skip the other configurations")
-    ap.add_argument("--tuning", default=None, help="grid,n_xcd,row_order,variant instead of autotuning")
+    ap.add_argument("--tuning", default=None, help="grid,n_xcd,row_order,variant,tile instead of autotuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, make 3 plain device copies of psi (scale reference for counter runs)")
     ap.add_argument("--summarize", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -530,6 +615,9 @@ def main():
     kernel = kernel_name(S)
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     traffic, traffic_tuning = traffic_from_profile(kernel, args.workload, alg_bytes)
+    if traffic is not None and traffic_tuning != tuning_str(tuning):
+        # counters taken at another launch tuning describe another kernel run
+        traffic = None
 
     # a few fused Lanczos steps (H*psi + alpha + update + beta) on the same input
     lz = None
@@ -577,6 +665,7 @@ def main():
         line["serving"] = serving_bench(args.serving, args.serving_budget_gb)
     progress("serving done")
     if not args.no_cpu_baseline:
+        p.meta["name"] = args.workload
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

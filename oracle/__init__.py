@@ -51,6 +51,12 @@ def lib():
         L.orc_find.argtypes = [vp, i64, ctypes.c_uint64]
         L.orc_build_csr.restype = i64
         L.orc_build_csr.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.orc_build_csr_rows.restype = i64
+        L.orc_build_csr_rows.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp]
+        L.orc_set_progress.restype = None
+        L.orc_set_progress.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_spmv_csr.restype = None
         L.orc_spmv_csr.argtypes = [i64, vp, vp, vp, vp, vp]
         L.orc_apply_rows.restype = ctypes.c_int
@@ -177,6 +183,19 @@ class Sector:
                 raise RuntimeError("oracle apply failed")
         return y
 
+    def csr_rows(self, r0, r1):
+        """CSR of rows [r0, r1) (row_ptr from 0; columns index the whole
+        sector)."""
+        rp = np.empty(r1 - r0 + 1, dtype=np.int64)
+        nnz = lib().orc_build_csr_rows(self.om.ref, _ptr(self.words), self.n, r0, r1, _ptr(rp), None, None)
+        if nnz < 0:
+            raise RuntimeError(f"oracle CSR build failed ({nnz})")
+        col = np.empty(nnz, dtype=np.int32)
+        val = np.empty(nnz, dtype=np.float64)
+        if lib().orc_build_csr_rows(self.om.ref, _ptr(self.words), self.n, r0, r1, _ptr(rp), _ptr(col), _ptr(val)) < 0:
+            raise RuntimeError("oracle CSR fill failed")
+        return rp, col, val
+
     def apply_rows(self, x, rows):
         x = np.ascontiguousarray(x, dtype=np.float64)
         rows = np.ascontiguousarray(rows, dtype=np.int64)
@@ -215,6 +234,23 @@ class Sector:
         if s < 0:
             raise RuntimeError(f"oracle lanczos failed ({s})")
         return e[:s].copy(), a[:s].copy(), b[:s].copy()
+
+
+def set_progress(every):
+    """Print every `every`-th Lanczos step's energy to stderr (0: off)."""
+    lib().orc_set_progress(int(every))
+
+
+def set_threads(n):
+    """OpenMP threads of the oracle's loops from now on."""
+    lib().orc_set_threads(int(n))
+
+
+def spmv_csr(rp, col, val, x):
+    """y = A x for a CSR block of rows (as returned by Sector.csr_rows)."""
+    y = np.empty(len(rp) - 1)
+    lib().orc_spmv_csr(len(rp) - 1, _ptr(rp), _ptr(col), _ptr(val), _ptr(np.ascontiguousarray(x)), _ptr(y))
+    return y
 
 
 def tridiag_eig(alpha, beta, k=0):

@@ -64,6 +64,7 @@ def run(name, max_steps=600, rows=False):
     if name == "j1j2_6x5" and _host_bytes() < 120 * 2**30:
         use_csr = False
     print(f"[golden] {name}: start ({'CSR' if use_csr else 'rows'}, {O.num_threads()} threads)", flush=True)
+    O.set_progress(5)
     r = solve(p, p.meta["seed"] + 1, max_steps, use_csr, log=lambda m: print(m, flush=True))
     out = {"workload": name, "model": p.model.name, "n_up": p.n_up, "n_dn": p.n_dn, **r,
            "tol": TOL,

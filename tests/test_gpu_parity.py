@@ -833,3 +833,40 @@ def test_caller_allocator_backs_sector_tables(dev):
     y = S.apply(refs[0][0]).cpu()
     S.close()
     assert torch.equal(y, refs[0][1])
+
+
+def test_lanczos_j1j2_6x5_vs_golden(dev):
+    """6x5 J1-J2 lattice (155,117,520 states, 16 blocks), autotuned spin
+    kernel: the three-term solve to 1e-10 reaches the oracle's stored ground
+    energy (tests/golden, the oracle's own Lanczos on the full sparse H)."""
+    import torch
+    p = I.j1j2_6x5()
+    S = _ecut().Sectors.from_problem(p)
+    v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to(dev))
+    S.autotune(v0, torch.empty_like(v0))
+    e, st, _ = S.lanczos(v0, 600, tol=1e-10)
+    assert st["converged"]
+    assert abs(e - _golden("j1j2_6x5")) <= 1e-10, (e, st)
+    del v0
+    torch.cuda.empty_cache()
+
+
+def test_server_mix_vs_oracle_per_request(dev):
+    """The first 48 requests of the 256-request serving mix (XXZ chains of
+    12-24 sites and Hubbard chains of 8-14 sites), batched with continuous
+    admission: every energy within 1e-10 of the oracle's energy for that
+    request (tests/golden/serving_2026_energies.json)."""
+    import json
+    import os
+    ecut = _ecut()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "serving_2026_energies.json")) as f:
+        ref = [e["energy"] for e in json.load(f)["energies"]]
+    reqs = I.serving_requests(256, seed=2026)[:48]
+    srv = ecut.Server(24 << 30, max_active=32, max_steps=600, tol=1e-10, autotune=True)
+    ids = [srv.submit(p, seed=p.meta["seed"]) for p in reqs]
+    srv.drain()
+    res = {r["req_id"]: r for r in srv.poll(64)}
+    srv.close()
+    err = [abs(res[i]["energy"] - ref[k]) for k, i in enumerate(ids)]
+    assert all(res[i]["status"] == 0 for i in ids)
+    assert max(err) <= 1e-10, (int(np.argmax(err)), max(err))

@@ -363,3 +363,46 @@ def test_bisection_vs_eigvalsh(m):
     ev = np.linalg.eigvalsh(T)
     for k in range(m):
         assert O.tridiag_eig(a, b, k) == pytest.approx(ev[k], abs=1e-13)
+
+
+@pytest.mark.parametrize("tol", [1e-9, 1e-12, 1e-14])
+def test_lanczos_stopping_rule(tol):
+    """The oracle's Lanczos stops once the lowest Ritz value has moved by at
+    most tol over three steps in a row, and not before: the energies it
+    returns are those of a fixed-step run (same arithmetic) up to that step,
+    the last three moves are within tol, no earlier three-step run is, and
+    the energy agrees with dense diagonalisation (eigh) within 1e-12 for the
+    tight tolerances, as a run continued well past convergence does."""
+    p = I.Problem(I.xxz_chain(12, 1.0, 0.8), I.Cut("spatial", I.left_mask_first(6)), 6)
+    s = O.Sector(p.model, p.n_up)
+    v0 = I.psi(31, s.n)
+    e_fixed, _, _ = s.lanczos(v0, 300)
+    e_tol, _, _ = s.lanczos(v0, 300, tol=tol)
+    k = len(e_tol)
+    assert 4 <= k < 300
+    np.testing.assert_array_equal(e_tol, e_fixed[:k])
+    moves = np.abs(np.diff(e_tol))
+    assert np.all(moves[-3:] <= tol)
+    run = 0
+    for m in moves[:-1]:
+        run = run + 1 if m <= tol else 0
+        assert run < 3
+    w0 = np.linalg.eigvalsh(s.dense())[0]
+    assert abs(e_fixed[-1] - w0) <= 1e-12
+    if tol <= 1e-12:
+        assert abs(e_tol[-1] - w0) <= 1e-12
+
+
+def test_csr_rows_block_matches_full_csr():
+    """A CSR block of a row range (the host baseline's sample) is the same
+    rows of the full CSR, and its product gives the same entries of H x."""
+    p = I.hubbard_chain(8, 1.0, 3.0)
+    s = O.Sector(p, 4, 3)
+    rp, col, val = s.csr()
+    r0, r1 = 17, 901
+    rb, cb, vb = s.csr_rows(r0, r1)
+    np.testing.assert_array_equal(rb, rp[r0:r1 + 1] - rp[r0])
+    np.testing.assert_array_equal(cb, col[rp[r0]:rp[r1]])
+    np.testing.assert_array_equal(vb, val[rp[r0]:rp[r1]])
+    x = I.psi(5, s.n)
+    np.testing.assert_array_equal(O.spmv_csr(rb, cb, vb, x), s.apply(x)[r0:r1])

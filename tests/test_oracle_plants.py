@@ -22,6 +22,7 @@ PLANTS = {
     4: "Sz Sz evaluated with the first site twice",
     5: "only the down spins hop",
     6: "wrong sign of the beta term in Lanczos",
+    7: "Lanczos stops after one step within tol instead of three",
 }
 
 
