@@ -543,6 +543,52 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
     return ECUT_OK;
 }
 
+bool hub6_batchable(const ecut_sectors *s) {
+    return s->kernel == 1 && s->hub6_ok && s->tune.variant == 6 && s->h6_maxq <= HUBD_BATCH_SLOTS;
+}
+
+void hub6_batch_add(HubBatch &b, const ecut_sectors *s, const ProblemDev &P) {
+    HubUArgs U = s->h6u;
+    HubDArgs D = s->h6d;
+    hub6_shape(s, U, D);
+    U.x = D.x = P.x;
+    U.y = D.y = P.y;
+    D.z = P.z;
+    D.partials = P.partials;
+    D.xscale = P.xscale;
+    D.zcoef = P.zcoef;
+    D.dscale = P.dscale;
+    b.u.push_back(U);
+    b.d.push_back(D);
+    b.off_u.push_back(b.off_u.back() + U.n_items);
+    b.off_d.push_back(b.off_d.back() + D.n_items);
+}
+
+HubBatchLayout hub6_batch_layout(const HubBatch &b, size_t base) {
+    auto al = [](size_t o) { return (o + 255) & ~(size_t)255; };
+    HubBatchLayout l;
+    l.u = al(base);
+    l.d = al(l.u + b.u.size() * sizeof(HubUArgs));
+    l.off_u = al(l.d + b.d.size() * sizeof(HubDArgs));
+    l.off_d = al(l.off_u + b.off_u.size() * sizeof(int32_t));
+    l.bytes = l.off_d + b.off_d.size() * sizeof(int32_t);
+    return l;
+}
+
+void hub6_batch_pack(const HubBatch &b, const HubBatchLayout &l, char *buf) {
+    std::memcpy(buf + l.u, b.u.data(), b.u.size() * sizeof(HubUArgs));
+    std::memcpy(buf + l.d, b.d.data(), b.d.size() * sizeof(HubDArgs));
+    std::memcpy(buf + l.off_u, b.off_u.data(), b.off_u.size() * sizeof(int32_t));
+    std::memcpy(buf + l.off_d, b.off_d.data(), b.off_d.size() * sizeof(int32_t));
+}
+
+hipError_t hub6_batch_launch(const HubBatch &b, const HubBatchLayout &l, const void *dev, hipStream_t st) {
+    if (b.empty()) return hipSuccess;
+    const char *d = (const char *)dev;
+    return launch_hub6_batch((const HubUArgs *)(d + l.u), (const HubDArgs *)(d + l.d), (const int32_t *)(d + l.off_u),
+                             (const int32_t *)(d + l.off_d), (int)b.u.size(), b.off_u.back(), b.off_d.back(), st);
+}
+
 // number of partial slots the apply kernel writes
 int32_t apply_partial_slots(const ecut_sectors *s) {
     if (s->kernel != 1) return s->item_slots;
@@ -667,6 +713,21 @@ hipError_t launch_rows_batch(const RowsBatch &b, const void *dev, hipStream_t st
     if (e == hipSuccess && b.n_spin < b.n_items)
         e = launch_rows(probs_d, b.rows_single, items_d + b.n_spin, b.n_items - b.n_spin, b.rows_tile, st);
     return e;
+}
+
+ecut_status batch_launch_hub(const HubBatch &hb, hipStream_t st) {
+    static thread_local Staging S;
+    const HubBatchLayout l = hub6_batch_layout(hb, 0);
+    ecut_status rs = S.reserve(l.bytes);
+    if (rs != ECUT_OK) return rs;
+    rs = S.wait();
+    if (rs != ECUT_OK) return rs;
+    hub6_batch_pack(hb, l, (char *)S.host);
+    rs = S.upload(l.bytes, st);
+    if (rs != ECUT_OK) return rs;
+    hipError_t e = hub6_batch_launch(hb, l, S.dev, st);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (batched Hubbard apply_H)");
+    return ECUT_OK;
 }
 
 ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items_in,
@@ -876,7 +937,7 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
     if (n == 0) return ECUT_OK;
     std::vector<ProblemDev> probs(n);
     std::vector<ItemDev> items;
-    std::vector<int32_t> tiles(n);
+    std::vector<int32_t> tiles(n), hub;
     for (int32_t k = 0; k < n; ++k) {
         ecut_status st = check_dev(s[k]);
         if (st != ECUT_OK) return st;
@@ -891,13 +952,23 @@ ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const do
         probs[k].zcoef = 0.0;
         probs[k].partials = nullptr;
         tiles[k] = max_tile_elems(s[k]);
+        if (hub6_batchable(s[k])) {
+            hub.push_back(k);   // one merged launch per pass for all of them
+            continue;
+        }
         if (s[k]->kernel == 1) {
-            // Hubbard up/down problems keep their own tuned kernels
+            // other Hubbard up/down tunings keep their own kernels
             ecut_status st = launch_apply(s[k], probs[k], (hipStream_t)stream);
             if (st != ECUT_OK) return st;
             continue;
         }
         for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
+    }
+    if (!hub.empty()) {
+        HubBatch hb;
+        for (int32_t k : hub) hub6_batch_add(hb, s[k], probs[k]);
+        ecut_status st = batch_launch_hub(hb, (hipStream_t)stream);
+        if (st != ECUT_OK) return st;
     }
     if (items.empty()) return ECUT_OK;
     // one queue over all problems, largest tiles first (stable: problem order breaks ties)

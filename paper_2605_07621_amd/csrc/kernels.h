@@ -41,6 +41,7 @@ constexpr int HUBU_ROWS = 4;                 // rows of the row order per left-o
 constexpr int HUBD_THREADS = 256;            // right-operator pass: one column per thread
 constexpr int HUBD_NB = 8;                   // in-row gathers issued together per lane
 constexpr int HUBD_MAX_SLOTS = 32;           // bonds of the down-spin hop table (held in registers)
+constexpr int HUBD_BATCH_SLOTS = 16;         // the same in the batched launch (problems with more launch alone)
 constexpr int HUBD_ROWS = 4;                 // default rows per right-operator item
 constexpr int VEC_THREADS = 256;
 constexpr int64_t VEC_CHUNK = 8192;          // elements per reduction partial
@@ -105,6 +106,10 @@ hipError_t launch_hubseg(const ecut_sectors *s, const HubSegArgs &args, int grid
 // two-pass kernels (variants 6 and 7): the flat left-operator pass (slab
 // items; n_xcd 8 = XCD-contiguous items)
 hipError_t launch_hub6_left(const HubUArgs &U, int n_xcd, hipStream_t st);
+// one launch per pass over the items of n_probs Hubbard problems (device
+// arrays of their arguments and of their first items, off[n_probs] = total)
+hipError_t launch_hub6_batch(const HubUArgs *probs_u, const HubDArgs *probs_d, const int32_t *off_u,
+                             const int32_t *off_d, int n_probs, int n_items_u, int n_items_d, hipStream_t st);
 // pass 2 of the two-pass kernels alone
 hipError_t launch_hubD_only(const HubDArgs &D, int n_xcd, hipStream_t st);
 // split: the left operator is already in y (UP = false); slab_grid > 0 runs

@@ -1527,10 +1527,7 @@ __global__ __launch_bounds__(HUBU_THREADS) void k_hubU(const HubUArgs A, int n_x
 // every row of it; a slot of -1 (the bond cannot hop from this column) reads
 // nothing.  The terms of an amplitude are summed in slot order.
 template <int NS, bool UNIF, bool STREAM>
-__global__ __launch_bounds__(HUBD_THREADS) void k_hubD(const HubDArgs A, int n_xcd, int per_xcd) {
-    __shared__ double red[HUBD_THREADS / 64];
-    const int it = xcd_item(n_xcd, per_xcd);
-    if (it >= A.n_items) return;   // uniform over the block
+__device__ __forceinline__ void hubD_item(const HubDArgs &A, int it, double *red) {
     const double2 ef = epi_factors(A.dscale, A.xscale, A.zcoef);
     const int rg = it / A.n_chunks;
     const int chunk = it - rg * A.n_chunks;
@@ -1582,6 +1579,64 @@ __global__ __launch_bounds__(HUBD_THREADS) void k_hubD(const HubDArgs A, int n_x
         const double sum = block_sum(part, red);
         if (threadIdx.x == 0) A.partials[it] = sum;
     }
+}
+
+template <int NS, bool UNIF, bool STREAM>
+__global__ __launch_bounds__(HUBD_THREADS) void k_hubD(const HubDArgs A, int n_xcd, int per_xcd) {
+    __shared__ double red[HUBD_THREADS / 64];
+    const int it = xcd_item(n_xcd, per_xcd);
+    if (it >= A.n_items) return;   // uniform over the block
+    hubD_item<NS, UNIF, STREAM>(A, it, red);
+}
+
+// Problem of global item `it` of a batch: the last p with off[p] <= it.
+__device__ __forceinline__ int batch_problem(const int32_t *__restrict__ off, int n_probs, int it) {
+    int lo = 0, hi = n_probs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Batches of Hubbard problems: one launch per pass over the items of every
+// problem (problem p owns items off[p] .. off[p + 1] - 1, its own item
+// numbering inside), each item computed exactly as in its problem's own
+// launch.  Column pairs, hop values and the slot count are per problem.
+__global__ __launch_bounds__(HUBU_THREADS) void k_hubU_batch(const HubUArgs *__restrict__ probs,
+                                                             const int32_t *__restrict__ off, int n_probs,
+                                                             int n_items, int per_xcd) {
+    const int it = xcd_item(8, per_xcd);
+    if (it >= n_items) return;
+    const int p = batch_problem(off, n_probs, it);
+    const HubUArgs A = probs[p];
+    const bool pair = (A.dR % 2 == 0) && !(((uintptr_t)A.x | (uintptr_t)A.y) & 15);
+    if (pair) hubU_item<true, false>(A, it - off[p]);
+    else hubU_item<false, false>(A, it - off[p]);
+}
+
+__global__ __launch_bounds__(HUBD_THREADS) void k_hubD_batch(const HubDArgs *__restrict__ probs,
+                                                             const int32_t *__restrict__ off, int n_probs,
+                                                             int n_items, int per_xcd) {
+    __shared__ double red[HUBD_THREADS / 64];
+    const int it = xcd_item(8, per_xcd);
+    if (it >= n_items) return;
+    const int p = batch_problem(off, n_probs, it);
+    const HubDArgs A = probs[p];
+    if (A.val == nullptr) hubD_item<HUBD_BATCH_SLOTS, true, false>(A, it - off[p], red);
+    else hubD_item<HUBD_BATCH_SLOTS, false, false>(A, it - off[p], red);
+}
+
+hipError_t launch_hub6_batch(const HubUArgs *probs_u, const HubDArgs *probs_d, const int32_t *off_u,
+                             const int32_t *off_d, int n_probs, int n_items_u, int n_items_d, hipStream_t st) {
+    if (n_probs <= 0) return hipSuccess;
+    const int pu = (n_items_u + 7) / 8, pd = (n_items_d + 7) / 8;
+    hipLaunchKernelGGL(k_hubU_batch, dim3(8 * pu), dim3(HUBU_THREADS), 0, st, probs_u, off_u, n_probs, n_items_u, pu);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hubD_batch, dim3(8 * pd), dim3(HUBD_THREADS), 0, st, probs_d, off_d, n_probs, n_items_d, pd);
+    return hipGetLastError();
 }
 
 template <int NS>

@@ -264,6 +264,8 @@ struct StepPlan {
     std::vector<const ecut_sectors *> own_s;
     RowsBatch rows;                           // the others, one row-kernel queue
     bool has_rows = false;
+    HubBatch hub;                             // Hubbard problems on the merged two-pass launches
+    HubBatchLayout hub_l;
     bool fuse_alpha = false;                  // alpha formed inside the update pass
     Pack P;
     size_t o_rows = 0, o_ja = 0, o_jx = 0, o_jb = 0, o_cj = 0, o_ci = 0, o_n0 = 0, o_n1 = 0;
@@ -288,7 +290,9 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
         P.z = zvec(*L);
         P.dscale = L->scal + LZ_S;
         P.partials = L->part_apply;
-        if (L->s->kernel == 1 || act.size() == 1) {
+        if (act.size() > 1 && hub6_batchable(L->s)) {
+            hub6_batch_add(pl.hub, L->s, P);
+        } else if (L->s->kernel == 1 || act.size() == 1) {
             pl.own.push_back(P);
             pl.own_s.push_back(L->s);
         } else {
@@ -309,6 +313,11 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
         make_rows_batch(rows_probs, rows_items, rows_tiles, pl.rows);
         pl.has_rows = true;
         pl.o_rows = pl.P.put(pl.rows.buf);
+    }
+    if (!pl.hub.empty()) {
+        pl.hub_l = hub6_batch_layout(pl.hub, pl.P.buf.size());
+        pl.P.buf.resize(pl.hub_l.bytes);
+        hub6_batch_pack(pl.hub, pl.hub_l, pl.P.buf.data());
     }
     // 2.-4. alpha, w = u - alpha v_j with norm partials, beta^2; 5. next factors.
     // When every block of the update pass can afford to re-add the alpha
@@ -385,6 +394,7 @@ static ecut_status enqueue_plan(const StepPlan &pl, const void *dev, hipStream_t
     const char *d = (const char *)dev;
     hipError_t e = hipSuccess;
     if (pl.has_rows) e = launch_rows_batch(pl.rows, d + pl.o_rows, st);
+    if (e == hipSuccess) e = hub6_batch_launch(pl.hub, pl.hub_l, d, st);
     if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");
     if (!pl.fuse_alpha) e = launch_reduce((const VecJob *)(d + pl.o_ja), pl.n_ja, st);
     if (e == hipSuccess)

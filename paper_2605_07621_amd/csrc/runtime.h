@@ -39,6 +39,29 @@ hipError_t launch_rows_batch(const RowsBatch &b, const void *dev, hipStream_t st
 ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items,
                               const std::vector<int32_t> &tiles, hipStream_t st);
 
+// Hubbard problems of a batch that share one launch per pass of the
+// two-pass kernels: their arguments (with each problem's vectors and
+// epilogue) and the first item of each problem in each pass.
+struct HubBatch {
+    std::vector<HubUArgs> u;
+    std::vector<HubDArgs> d;
+    std::vector<int32_t> off_u{0}, off_d{0};
+    bool empty() const { return u.empty(); }
+};
+// a problem joins the merged launch when its tuning selects the two-pass
+// kernels (variant 6) and its down-spin table fits the batched kernel
+bool hub6_batchable(const ecut_sectors *s);
+void hub6_batch_add(HubBatch &b, const ecut_sectors *s, const ProblemDev &P);
+// byte offsets of the four arrays in a buffer laid out by hub6_batch_pack
+struct HubBatchLayout {
+    size_t u = 0, d = 0, off_u = 0, off_d = 0, bytes = 0;
+};
+HubBatchLayout hub6_batch_layout(const HubBatch &b, size_t base);
+void hub6_batch_pack(const HubBatch &b, const HubBatchLayout &l, char *buf);
+hipError_t hub6_batch_launch(const HubBatch &b, const HubBatchLayout &l, const void *dev, hipStream_t st);
+// the merged Hubbard launches of ecut_apply_H_batch (per-thread staging, as batch_launch_rows)
+ecut_status batch_launch_hub(const HubBatch &hb, hipStream_t st);
+
 // Small reusable device + pinned-host staging buffer (not thread-safe).
 struct Staging {
     void *dev = nullptr;

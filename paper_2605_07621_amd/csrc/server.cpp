@@ -163,6 +163,9 @@ static size_t footprint(const ecut_sectors *s) { return lz_workspace_doubles(s, 
 // first request of the shape, x = its start vector, y = a ring vector the
 // solve overwrites later) and reused for every later request of the shape.
 static std::mutex g_tune_mu;
+// Hubbard problems up to this many amplitudes (chains of up to 10 sites at
+// half filling) share the merged two-pass launches of a step
+static constexpr int64_t SMALL_HUB_DIM = (int64_t)1 << 18;
 static std::map<std::string, ecut_tuning> g_tunings;
 
 static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStream_t st) {
@@ -173,7 +176,15 @@ static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStr
         if (it != g_tunings.end() && ecut_set_tuning(s, &it->second) == ECUT_OK) return ECUT_OK;
     }
     ecut_tuning best{};
-    ecut_status rs = ecut_autotune(s, x, y, st, &best);
+    ecut_status rs;
+    if (s->kernel == 1 && s->hub6_ok && s->dim <= SMALL_HUB_DIM && s->h6_maxq <= HUBD_BATCH_SLOTS) {
+        // small Hubbard problems take the two-pass kernels, so that every
+        // step runs all of them in one merged launch per pass
+        best = ecut_tuning{0, 8, 1, 6, 2};
+        rs = ecut_set_tuning(s, &best);
+    } else {
+        rs = ecut_autotune(s, x, y, st, &best);
+    }
     if (rs != ECUT_OK) return rs;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tunings.emplace(key, best);

@@ -870,3 +870,35 @@ def test_server_mix_vs_oracle_per_request(dev):
     err = [abs(res[i]["energy"] - ref[k]) for k, i in enumerate(ids)]
     assert all(res[i]["status"] == 0 for i in ids)
     assert max(err) <= 1e-10, (int(np.argmax(err)), max(err))
+
+
+def test_hubbard_batch_one_launch_bit_exact(dev):
+    """A Hubbard-heavy batch on the two-pass kernels (chains of 6 to 12 sites
+    with random U, random long-range hoppings with fermion signs, odd row
+    lengths) runs in one merged launch per pass: every output equals the
+    problem's own application bit for bit and the oracle's vector; spin
+    problems in the same batch keep their own queue."""
+    import torch
+    E = _ecut()
+    rng = np.random.default_rng(4242)
+    probs = []
+    for L in (6, 8, 10, 12, 8, 10):
+        probs.append(I.Problem(I.hubbard_chain(L, 1.0, float(rng.uniform(0, 10))), I.Cut("updn"), L // 2, L // 2))
+    probs.append(I.Problem(I.random_hubbard_model(np.random.default_rng(5), 9, n_bonds=14), I.Cut("updn"), 4, 5))
+    probs.append(I.Problem(I.hubbard_chain(7, 1.0, 2.0), I.Cut("updn"), 3, 2))
+    probs.append(I.heisenberg16())
+    probs.append(I.Problem(I.xxz_chain(12, 1.0, 0.8), I.Cut("spatial", I.left_mask_first(6)), 6))
+    Ss = [E.Sectors.from_problem(p) for p in probs]
+    for k, S in enumerate(Ss):
+        if probs[k].model.kind == "hubbard":
+            S.set_tuning(0, 8, 1, 6, 2 if k % 2 else 4)
+    psis = [I.psi(2100 + k, S.dim) for k, S in enumerate(Ss)]
+    xs = [S.import_(torch.from_numpy(x).to(dev)) for S, x in zip(Ss, psis)]
+    alone = [S.apply(x) for S, x in zip(Ss, xs)]
+    ys = [torch.empty_like(x) for x in xs]
+    E.apply_batch(Ss, xs, ys)
+    torch.cuda.synchronize()
+    for k, (p, S) in enumerate(zip(probs, Ss)):
+        assert torch.equal(alone[k], ys[k]), f"batch differs for problem {k} ({p.model.name})"
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        _compare(S.export(ys[k]).cpu().numpy(), s.apply(psis[k]), f"batched {p.model.name}")
