@@ -189,17 +189,43 @@ ecut_status ecut_export(const ecut_sectors *s, const double *bip_d, double *cano
 ecut_status ecut_apply_H(const ecut_sectors *s, const double *psi_d, double *y_d, void *stream);
 
 /*
- * n independent applications y_k = H_k psi_k.  Spin and generic problems
- * share one work queue over (problem, block, row tile), largest tiles first
- * (one launch of the spin kernel pair and/or one of the generic row kernel);
- * Hubbard up/down problems run their own tuned kernels.  Each output equals
- * what ecut_apply_H gives for that problem alone, bit for bit.
- * s, psi_d, y_d: host arrays of n entries.  Uses an internal device
- * descriptor buffer that the library allocates on first use and grows;
- * the call synchronises the stream before reusing it.
+ * n independent applications y_k = H_k psi_k, the batched sector dispatch
+ * over many Hamiltonians (the uneven symmetry sectors of the paper's
+ * discussion of symmetry fragmentation, Eq. (3) blocks of every problem).
+ * Spin and generic problems share one work queue over (problem, block, row
+ * tile), largest tiles first (one launch of the spin kernel pair and/or one
+ * of the generic row kernel); Hubbard up/down problems tuned to the two-pass
+ * kernels (variant 6, at most 16 hopping bonds) share one launch per pass,
+ * other Hubbard tunings run their own kernels.  Each output equals what
+ * ecut_apply_H gives for that problem alone, bit for bit.
+ * s, psi_d, y_d: host arrays of n entries.  The launch descriptors go
+ * through device buffers the library allocates on first use and grows (a
+ * ring of four per calling thread, with pinned staging): the call does not
+ * wait for the device unless all four still hold descriptors of batches in
+ * flight.  Asynchronous on stream otherwise.
  */
 ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
                                double *const *y_d, void *stream);
+
+/*
+ * ecut_apply_H_batch for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The same
+ * applications, launches and results (bit for bit) as ecut_apply_H_batch,
+ * but the launch descriptors go into a fixed device array of the library
+ * (ECUT_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends), written
+ * by a small kernel on `stream` that carries them as kernel arguments: no
+ * hipMalloc, hipFree or pinned host memory, and no wait on the host.  The
+ * caller still owns psi_d and y_d.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * descriptors: calls on one GPU must be ordered (the same stream, or streams
+ * the caller orders); calls that overlap on one GPU race.
+ * Errors: as ecut_apply_H_batch; ECUT_EINVAL (before any device work) when
+ * the batch's descriptors exceed ECUT_NOALLOC_SCRATCH_BYTES (problems with
+ * many small work items, e.g. small spin tiles, take the most).
+ */
+#define ECUT_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+ecut_status ecut_apply_H_batch_noalloc(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
+                                       double *const *y_d, void *stream);
 
 /*
  * Launch tuning of ecut_apply_H (used by the Hubbard up/down kernel, whose

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libecut.so")
-SOURCES = ["sectors.cpp", "api.cpp", "tune.cpp", "lanczos.cpp", "server.cpp", "kernels.hip"]
+SOURCES = ["sectors.cpp", "api.cpp", "tune.cpp", "lanczos.cpp", "server.cpp", "kernels.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

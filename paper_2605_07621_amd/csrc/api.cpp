@@ -16,6 +16,8 @@
 #include "kernels.h"
 #include "runtime.h"
 
+static ecut_status check_dev(const ecut_sectors *s);   // handle on the current device
+
 namespace ecut {
 
 static thread_local std::string g_err;
@@ -715,21 +717,6 @@ hipError_t launch_rows_batch(const RowsBatch &b, const void *dev, hipStream_t st
     return e;
 }
 
-ecut_status batch_launch_hub(const HubBatch &hb, hipStream_t st) {
-    static thread_local Staging S;
-    const HubBatchLayout l = hub6_batch_layout(hb, 0);
-    ecut_status rs = S.reserve(l.bytes);
-    if (rs != ECUT_OK) return rs;
-    rs = S.wait();
-    if (rs != ECUT_OK) return rs;
-    hub6_batch_pack(hb, l, (char *)S.host);
-    rs = S.upload(l.bytes, st);
-    if (rs != ECUT_OK) return rs;
-    hipError_t e = hub6_batch_launch(hb, l, S.dev, st);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch (batched Hubbard apply_H)");
-    return ECUT_OK;
-}
-
 ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::vector<ItemDev> &items_in,
                               const std::vector<int32_t> &tiles, hipStream_t st) {
     static thread_local Staging S;
@@ -747,6 +734,68 @@ ecut_status batch_launch_rows(const std::vector<ProblemDev> &probs, const std::v
     e = hipEventRecord(S.ev, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     S.pending = true;
+    return ECUT_OK;
+}
+
+ecut_status make_batch_plan(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
+                            double *const *y_d, BatchPlan &pl) {
+    if (n < 0 || (n > 0 && (!s || !psi_d || !y_d))) return fail(ECUT_EINVAL, "bad batch arguments");
+    pl = BatchPlan{};
+    if (n == 0) return ECUT_OK;
+    std::vector<ProblemDev> probs(n);
+    std::vector<ItemDev> items;
+    std::vector<int32_t> tiles(n);
+    for (int32_t k = 0; k < n; ++k) {
+        ecut_status st = check_dev(s[k]);
+        if (st != ECUT_OK) return st;
+        if (!psi_d[k] || !y_d[k] || psi_d[k] == y_d[k]) return fail(ECUT_EINVAL, "bad vector in batch");
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        probs[k] = s[k]->prob;
+        probs[k].x = psi_d[k];
+        probs[k].y = y_d[k];
+        probs[k].z = nullptr;
+        probs[k].xscale = 1.0;
+        probs[k].zcoef = 0.0;
+        probs[k].partials = nullptr;
+        tiles[k] = max_tile_elems(s[k]);
+        if (hub6_batchable(s[k])) {
+            hub6_batch_add(pl.hub, s[k], probs[k]);   // one merged launch per pass for all of them
+        } else if (s[k]->kernel == 1) {
+            pl.own.push_back(probs[k]);               // other Hubbard tunings keep their own kernels
+            pl.own_s.push_back(s[k]);
+        } else {
+            for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
+        }
+    }
+    if (!items.empty()) {
+        // one queue over all problems, largest tiles first (stable: problem order breaks ties)
+        std::stable_sort(items.begin(), items.end(), [&](const ItemDev &a, const ItemDev &b) {
+            const int64_t wa = (int64_t)(a.row1 - a.row0) * s[a.prob]->blocks[a.block].d_r;
+            const int64_t wb = (int64_t)(b.row1 - b.row0) * s[b.prob]->blocks[b.block].d_r;
+            return wa > wb;
+        });
+        make_rows_batch(probs, items, tiles, pl.rows);
+        pl.has_rows = true;
+        pl.buf = pl.rows.buf;
+    }
+    if (!pl.hub.empty()) {
+        pl.hub_l = hub6_batch_layout(pl.hub, pl.buf.size());
+        pl.buf.resize(pl.hub_l.bytes);
+        hub6_batch_pack(pl.hub, pl.hub_l, pl.buf.data());
+    }
+    return ECUT_OK;
+}
+
+ecut_status launch_batch_plan(const BatchPlan &pl, const void *dev, hipStream_t st) {
+    for (size_t k = 0; k < pl.own.size(); ++k) {
+        ecut_status rs = launch_apply(pl.own_s[k], pl.own[k], st);
+        if (rs != ECUT_OK) return rs;
+    }
+    hipError_t e = hipSuccess;
+    if (pl.has_rows) e = launch_rows_batch(pl.rows, dev, st);
+    if (e == hipSuccess) e = hub6_batch_launch(pl.hub, pl.hub_l, dev, st);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (batched apply_H)");
     return ECUT_OK;
 }
 
@@ -933,51 +982,36 @@ ecut_status ecut_apply_H(const ecut_sectors *s, const double *psi_d, double *y_d
 
 ecut_status ecut_apply_H_batch(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
                                double *const *y_d, void *stream) {
-    if (n < 0 || (n > 0 && (!s || !psi_d || !y_d))) return fail(ECUT_EINVAL, "bad batch arguments");
-    if (n == 0) return ECUT_OK;
-    std::vector<ProblemDev> probs(n);
-    std::vector<ItemDev> items;
-    std::vector<int32_t> tiles(n), hub;
-    for (int32_t k = 0; k < n; ++k) {
-        ecut_status st = check_dev(s[k]);
+    BatchPlan pl;
+    ecut_status st = make_batch_plan(n, s, psi_d, y_d, pl);
+    if (st != ECUT_OK || n == 0) return st;
+    // a descriptor buffer whose previous batch has been copied (a ring of a
+    // few per thread, so the call waits only when all of them are in flight)
+    static thread_local Staging ring[4];
+    static thread_local int next = 0;
+    Staging *S = nullptr;
+    for (int k = 0; k < 4 && !S; ++k) {
+        Staging &c = ring[(next + k) % 4];
+        if (!c.pending || hipEventQuery(c.ev) == hipSuccess) S = &c;
+    }
+    if (!S) S = &ring[next % 4];   // every buffer busy: the oldest use is waited for
+    next = (int)(S - ring + 1) % 4;
+    if (!pl.buf.empty()) {
+        st = S->reserve(pl.buf.size());
+        if (st == ECUT_OK) st = S->wait();
         if (st != ECUT_OK) return st;
-        if (!psi_d[k] || !y_d[k] || psi_d[k] == y_d[k]) return fail(ECUT_EINVAL, "bad vector in batch");
+        std::memcpy(S->host, pl.buf.data(), pl.buf.size());
+        hipError_t e = hipMemcpyAsync(S->dev, S->host, pl.buf.size(), hipMemcpyHostToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
     }
-    for (int32_t k = 0; k < n; ++k) {
-        probs[k] = s[k]->prob;
-        probs[k].x = psi_d[k];
-        probs[k].y = y_d[k];
-        probs[k].z = nullptr;
-        probs[k].xscale = 1.0;
-        probs[k].zcoef = 0.0;
-        probs[k].partials = nullptr;
-        tiles[k] = max_tile_elems(s[k]);
-        if (hub6_batchable(s[k])) {
-            hub.push_back(k);   // one merged launch per pass for all of them
-            continue;
-        }
-        if (s[k]->kernel == 1) {
-            // other Hubbard up/down tunings keep their own kernels
-            ecut_status st = launch_apply(s[k], probs[k], (hipStream_t)stream);
-            if (st != ECUT_OK) return st;
-            continue;
-        }
-        for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
+    st = launch_batch_plan(pl, S->dev, (hipStream_t)stream);
+    if (st != ECUT_OK) return st;
+    if (!pl.buf.empty()) {
+        hipError_t e = hipEventRecord(S->ev, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        S->pending = true;
     }
-    if (!hub.empty()) {
-        HubBatch hb;
-        for (int32_t k : hub) hub6_batch_add(hb, s[k], probs[k]);
-        ecut_status st = batch_launch_hub(hb, (hipStream_t)stream);
-        if (st != ECUT_OK) return st;
-    }
-    if (items.empty()) return ECUT_OK;
-    // one queue over all problems, largest tiles first (stable: problem order breaks ties)
-    std::stable_sort(items.begin(), items.end(), [&](const ItemDev &a, const ItemDev &b) {
-        const int64_t wa = (int64_t)(a.row1 - a.row0) * s[a.prob]->blocks[a.block].d_r;
-        const int64_t wb = (int64_t)(b.row1 - b.row0) * s[b.prob]->blocks[b.block].d_r;
-        return wa > wb;
-    });
-    return batch_launch_rows(probs, items, tiles, (hipStream_t)stream);
+    return ECUT_OK;
 }
 
 }  // extern "C"

@@ -59,8 +59,23 @@ struct HubBatchLayout {
 HubBatchLayout hub6_batch_layout(const HubBatch &b, size_t base);
 void hub6_batch_pack(const HubBatch &b, const HubBatchLayout &l, char *buf);
 hipError_t hub6_batch_launch(const HubBatch &b, const HubBatchLayout &l, const void *dev, hipStream_t st);
-// the merged Hubbard launches of ecut_apply_H_batch (per-thread staging, as batch_launch_rows)
-ecut_status batch_launch_hub(const HubBatch &hb, hipStream_t st);
+// Everything one ecut_apply_H_batch launches: problems on their own
+// kernels, the row-kernel queue of the spin and generic problems, the
+// merged Hubbard launches, and the device image of their descriptors (the
+// row queue's buffer at offset 0, then the Hubbard arrays).
+struct BatchPlan {
+    std::vector<ProblemDev> own;
+    std::vector<const ecut_sectors *> own_s;
+    RowsBatch rows;
+    bool has_rows = false;
+    HubBatch hub;
+    HubBatchLayout hub_l;
+    std::vector<char> buf;
+};
+ecut_status make_batch_plan(int32_t n, const ecut_sectors *const *s, const double *const *psi_d,
+                            double *const *y_d, BatchPlan &pl);
+// launches with dev = a device copy of pl.buf (nullable when pl.buf is empty)
+ecut_status launch_batch_plan(const BatchPlan &pl, const void *dev, hipStream_t st);
 
 // Small reusable device + pinned-host staging buffer (not thread-safe).
 struct Staging {

@@ -97,6 +97,7 @@ SYMBOLS = [
     ("ecut_export", _i32, [_vp, _vp, _vp, _vp]),
     ("ecut_apply_H", _i32, [_vp, _vp, _vp, _vp]),
     ("ecut_apply_H_batch", _i32, [_i32, _vp, _vp, _vp, _vp]),
+    ("ecut_apply_H_batch_noalloc", _i32, [_i32, _vp, _vp, _vp, _vp]),
     ("ecut_get_tuning", _i32, [_vp, ctypes.POINTER(Tuning)]),
     ("ecut_set_tuning", _i32, [_vp, ctypes.POINTER(Tuning)]),
     ("ecut_autotune", _i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(Tuning)]),
@@ -322,13 +323,14 @@ def torch_allocator():
     return alloc, free
 
 
-def apply_batch(sectors, psis, ys, stream=None):
+def apply_batch(sectors, psis, ys, stream=None, noalloc=False):
+    """ecut_apply_H_batch, or ecut_apply_H_batch_noalloc with noalloc=True."""
     n = len(sectors)
     hs = (_vp * n)(*[s.h for s in sectors])
     ps = (_vp * n)(*[_dptr(p, s.dim, "psi") for s, p in zip(sectors, psis)])
     qs = (_vp * n)(*[_dptr(y, s.dim, "y") for s, y in zip(sectors, ys)])
-    _check(lib().ecut_apply_H_batch(n, ctypes.cast(hs, _vp), ctypes.cast(ps, _vp), ctypes.cast(qs, _vp),
-                                    _stream(stream)))
+    f = lib().ecut_apply_H_batch_noalloc if noalloc else lib().ecut_apply_H_batch
+    _check(f(n, ctypes.cast(hs, _vp), ctypes.cast(ps, _vp), ctypes.cast(qs, _vp), _stream(stream)))
 
 
 class Server:
