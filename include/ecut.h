@@ -372,6 +372,50 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
                                       double *basis_d, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Entanglement spectrum of a state (the paper's discussion of the
+ * distributed entanglement spectrum, with its figure of xi_{q,i} over the
+ * sectors and the process-resolved W_P, and the End Matter's N_eff).
+ *   rho_L = Tr_R |psi><psi| / <psi|psi> is block diagonal over the blocks of
+ *   the cut; lambda_{q,i} are the eigenvalues of block q (the squared
+ *   Schmidt values, min(d_L, d_R) of them per block, descending), and
+ *   xi_{q,i} = -log lambda_{q,i} the spectrum of H_E = -log rho_L.
+ *   W_q = sum_i lambda_{q,i} (the entanglement weight of sector q);
+ *   W_P[p] = sum_{q in Q_p} W_q^2 over the sectors assigned to part p
+ *   (part_of_block, or when NULL a largest-first packing of the blocks by
+ *   dimension into n_parts parts, the sector sharding of this build);
+ *   chi_q = number of lambda_{q,i} above `cutoff` (the sector's Schmidt
+ *   rank), n_eff = 1 / sum_q (chi_q / sum chi)^2 (the End Matter's
+ *   participation number of the sector dimensions), weight_ipr =
+ *   1 / sum_q W_q^2, entropy = -sum lambda log lambda.
+ * Per block the Gram matrix of the smaller side (Psi_q Psi_q^T or
+ * Psi_q^T Psi_q) is formed with rocBLAS syrk and diagonalised with rocSOLVER
+ * syevd on the device; the rest on the host.
+ *   psi_d:       state in the bipartite layout (dim doubles, any norm, not 0).
+ *   workspace_d: ecut_entanglement_sizes(s, &n_lambda) doubles (device).
+ *   lambda, xi:  host, n_lambda doubles each, blocks in order (xi nullable;
+ *                +inf where lambda <= 0).
+ *   w_q, chi_q:  host, n_blocks entries; w_p: host, n_parts (nullable if
+ *                n_parts == 1).
+ * Synchronises the stream.  Errors: ECUT_EINVAL (null or bad arguments, zero
+ * state), ECUT_ENOTCONV (the eigensolver did not converge), ECUT_EDEVICE.
+ * ------------------------------------------------------------------------- */
+typedef struct ecut_entanglement {
+    int32_t n_blocks;
+    int32_t n_parts;
+    int64_t n_lambda;
+    double norm2;             /* <psi|psi> */
+    double weight_ipr;        /* 1 / sum_q W_q^2 */
+    double n_eff;             /* 1 / sum_q (chi_q / sum chi)^2 */
+    double entropy;           /* -sum lambda log lambda */
+} ecut_entanglement;
+
+size_t ecut_entanglement_sizes(const ecut_sectors *s, size_t *n_lambda);
+ecut_status ecut_entanglement_spectrum(const ecut_sectors *s, const double *psi_d, double cutoff, int32_t n_parts,
+                                       const int32_t *part_of_block, double *lambda, double *xi, double *w_q,
+                                       int32_t *chi_q, double *w_p, ecut_entanglement *summary,
+                                       double *workspace_d, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Continuous-batching ground-state server.
  * A worker thread owns one stream and a device arena of hbm_budget bytes;
  * a helper thread builds the sector tables of arrived requests (up to 16

@@ -259,3 +259,50 @@ def tridiag_eig(alpha, beta, k=0):
     if len(b) < max(len(a) - 1, 1):
         b = np.concatenate([b, np.zeros(max(len(a) - 1, 1) - len(b))])
     return lib().orc_tridiag_eig(_ptr(a), _ptr(b), len(a), k)
+
+
+# ---------------------------------------------------------------- ground state, entanglement spectrum
+
+def ground_state(sector, v0, tol=1e-14):
+    """Lowest eigenpair of the sector's H (its CSR) by the implicitly
+    restarted Lanczos method of ARPACK (scipy), started from v0.  Returns
+    (energy, unit vector in canonical order)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    rp, col, val = sector.csr()
+    A = sp.csr_matrix((val, col, rp), shape=(sector.n, sector.n))
+    w, v = sla.eigsh(A, k=1, which="SA", tol=tol, v0=np.asarray(v0, dtype=np.float64))
+    g = v[:, 0]
+    return float(w[0]), g / np.linalg.norm(g)
+
+
+def entanglement(sector, psi, cut_kind, left_mask=0, parts=None, cutoff=1e-14):
+    """Entanglement spectrum of psi (canonical order) across the cut: the
+    eigenvalues of rho_L = Tr_R |psi><psi| / <psi|psi> (the paper's
+    H_E = -log rho_L), block by block of the oracle's own bipartite map, from
+    the singular values of each block (numpy SVD).  Returns a dict: lam
+    (per block, descending), w_q = sum_i lam_{q,i}, chi_q = #(lam > cutoff),
+    n_eff = 1/sum (chi_q/sum chi)^2, weight_ipr = 1/sum W_q^2, entropy, and
+    w_p[p] = sum_{q in part p} W_q^2 when parts (block -> part) is given."""
+    psi = np.asarray(psi, dtype=np.float64)
+    pos, blocks = sector.bipartite(cut_kind, left_mask)
+    flat = np.empty_like(psi)
+    flat[pos] = psi
+    norm2 = float(psi @ psi)
+    lam = []
+    for q_l, d_l, d_r, off in blocks:
+        m = flat[off:off + d_l * d_r].reshape(d_l, d_r)
+        sv = np.linalg.svd(m, compute_uv=False) if m.size else np.zeros(0)
+        lam.append(np.sort(sv * sv / norm2)[::-1][:min(d_l, d_r)])
+    w_q = np.array([l.sum() for l in lam])
+    chi = np.array([int(np.sum(l > cutoff)) for l in lam])
+    c = chi / max(chi.sum(), 1)
+    allv = np.concatenate(lam)
+    pos_l = allv[allv > 0]
+    out = dict(lam=lam, w_q=w_q, chi_q=chi, n_eff=1.0 / np.sum(c * c), weight_ipr=1.0 / np.sum(w_q * w_q),
+               entropy=float(-np.sum(pos_l * np.log(pos_l))), blocks=blocks)
+    if parts is not None:
+        parts = np.asarray(parts)
+        out["w_p"] = np.array([np.sum(w_q[parts == p] ** 2) for p in range(int(parts.max()) + 1)])
+    return out
+

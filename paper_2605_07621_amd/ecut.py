@@ -86,6 +86,11 @@ class Result(ctypes.Structure):
 ALLOC_FN = ctypes.CFUNCTYPE(_vp, _sz, _i32, _vp)
 FREE_FN = ctypes.CFUNCTYPE(None, _vp, _sz, _i32, _vp)
 
+class Entanglement(ctypes.Structure):
+    _fields_ = [("n_blocks", _i32), ("n_parts", _i32), ("n_lambda", _i64), ("norm2", _dbl), ("weight_ipr", _dbl),
+                ("n_eff", _dbl), ("entropy", _dbl)]
+
+
 SYMBOLS = [
     ("ecut_build_sectors", _i32, [ctypes.POINTER(ModelDesc), ctypes.POINTER(CutDesc), QNum, _u32, ctypes.POINTER(_vp)]),
     ("ecut_sectors_free", None, [_vp]),
@@ -104,6 +109,9 @@ SYMBOLS = [
     ("ecut_lanczos_workspace", _sz, [_vp, ctypes.POINTER(LanczosOpts)]),
     ("ecut_lanczos_ground_state", _i32, [_vp, _vp, ctypes.POINTER(LanczosOpts), ctypes.POINTER(_dbl), _vp,
                                          ctypes.POINTER(LanczosStats), _vp, _vp]),
+    ("ecut_entanglement_sizes", _sz, [_vp, ctypes.POINTER(_sz)]),
+    ("ecut_entanglement_spectrum", _i32, [_vp, _vp, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                          ctypes.POINTER(Entanglement), _vp, _vp]),
     ("ecut_server_create", _i32, [_sz, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]),
     ("ecut_server_submit", _i32, [_vp, ctypes.POINTER(ModelDesc), ctypes.POINTER(CutDesc), QNum, _u64, _dbl,
                                   ctypes.POINTER(_u64)]),
@@ -252,6 +260,34 @@ class Sectors:
         out = torch.empty(self.dim, dtype=torch.float64, device=psi.device) if out is None else out
         _check(lib().ecut_apply_H(self.h, _dptr(psi, self.dim, "psi"), _dptr(out, self.dim, "out"), _stream(stream)))
         return out
+
+    def entanglement(self, psi, n_parts=1, part_of_block=None, cutoff=1e-14, stream=None):
+        """ecut_entanglement_spectrum: dict of lambda, xi (per block, lists of
+        numpy arrays), w_q, chi_q, w_p and the summary fields."""
+        import numpy as np
+        import torch
+        nl = _sz()
+        nws = int(lib().ecut_entanglement_sizes(self.h, ctypes.byref(nl)))
+        ws = torch.empty(nws, dtype=torch.float64, device=psi.device)
+        nb = self.info.n_blocks
+        lam = np.empty(nl.value)
+        xi = np.empty(nl.value)
+        wq = np.empty(nb)
+        chi = np.empty(nb, dtype=np.int32)
+        wp = np.empty(int(n_parts))
+        pob = None if part_of_block is None else np.ascontiguousarray(part_of_block, dtype=np.int32)
+        summ = Entanglement()
+        _check(lib().ecut_entanglement_spectrum(self.h, _dptr(psi, self.dim, "psi"), float(cutoff), int(n_parts),
+                                                None if pob is None else _vp(pob.ctypes.data),
+                                                _vp(lam.ctypes.data), _vp(xi.ctypes.data), _vp(wq.ctypes.data),
+                                                _vp(chi.ctypes.data), _vp(wp.ctypes.data), ctypes.byref(summ),
+                                                _dptr(ws, nws, "workspace"), _stream(stream)))
+        b = self.blocks()
+        m = np.minimum(b[:, 2], b[:, 3])
+        cut = np.concatenate([[0], np.cumsum(m)])
+        return dict(lam=[lam[cut[q]:cut[q + 1]] for q in range(nb)], xi=[xi[cut[q]:cut[q + 1]] for q in range(nb)],
+                    w_q=wq, chi_q=chi, w_p=wp, norm2=summ.norm2, weight_ipr=summ.weight_ipr, n_eff=summ.n_eff,
+                    entropy=summ.entropy)
 
     def get_tuning(self):
         t = Tuning()

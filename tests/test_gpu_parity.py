@@ -902,3 +902,73 @@ def test_hubbard_batch_one_launch_bit_exact(dev):
         assert torch.equal(alone[k], ys[k]), f"batch differs for problem {k} ({p.model.name})"
         s = O.Sector(p.model, p.n_up, p.n_dn)
         _compare(S.export(ys[k]).cpu().numpy(), s.apply(psis[k]), f"batched {p.model.name}")
+
+
+def _ent_compare(got, ref, what, lam_tol):
+    nb = len(ref["lam"])
+    assert len(got["lam"]) == nb
+    for q in range(nb):
+        a, b = got["lam"][q], ref["lam"][q]
+        assert a.shape == b.shape, (what, q)
+        assert np.max(np.abs(a - b), initial=0.0) <= lam_tol, (what, q, np.max(np.abs(a - b)))
+    np.testing.assert_allclose(got["w_q"], ref["w_q"], atol=lam_tol * 10, err_msg=what)
+    assert abs(got["entropy"] - ref["entropy"]) <= lam_tol * 1e3, what
+    assert abs(got["weight_ipr"] - ref["weight_ipr"]) <= lam_tol * 1e3 * ref["weight_ipr"], what
+
+
+@pytest.mark.parametrize("name", ["heisenberg16", "hubbard12"])
+def test_entanglement_spectrum_vs_oracle(dev, name):
+    """The oracle's ground state (ARPACK on the oracle's H), imported into
+    the bipartite layout: the device spectrum of rho_L per block (Gram matrix
+    + symmetric eigensolver) against numpy's singular values of the oracle's
+    own blocks (|d lambda| <= 1e-13: the Gram matrix carries an absolute
+    error of about eps * lambda_max), W_q, the entropy, the weight IPR,
+    N_eff of the sector Schmidt ranks and W_P over (up to) 3 parts."""
+    import torch
+    p = I.WORKLOADS[name]()
+    s = O.Sector(p.model, p.n_up, p.n_dn)
+    e0, g = O.ground_state(s, I.psi(p.meta["seed"] + 1, s.n))
+    S = _ecut().Sectors.from_problem(p)
+    nb = S.info.n_blocks
+    parts = np.arange(nb) % 3
+    ref = O.entanglement(s, g, p.cut.kind, p.cut.left_mask, parts=parts, cutoff=1e-10)
+    x = S.import_(torch.from_numpy(g).to(dev))
+    got = S.entanglement(x, n_parts=int(parts.max()) + 1, part_of_block=parts, cutoff=1e-10)
+    _ent_compare(got, ref, name, 1e-13)
+    assert abs(got["n_eff"] - ref["n_eff"]) <= 1e-12
+    np.testing.assert_allclose(got["w_p"], ref["w_p"], atol=1e-12)
+    assert abs(got["w_q"].sum() - 1.0) <= 1e-12
+    # the same state at another norm gives the same spectrum
+    got2 = S.entanglement(3.0 * x, n_parts=1, cutoff=1e-10)
+    _ent_compare(got2, ref, name + " x3", 1e-13)
+
+
+def test_entanglement_of_device_ground_state(dev):
+    """End to end: the device's own ground state (Lanczos with full
+    reorthogonalisation to a residual of 1e-8, 14-site XXZ chain, spatial
+    cut 7|7) against the oracle's: equal up to the vector's accuracy
+    (|d lambda| <= 1e-7, about residual / spectral gap)."""
+    import torch
+    p = I.Problem(I.xxz_chain(14, 1.0, 0.6), I.Cut("spatial", I.left_mask_first(7)), 7)
+    s = O.Sector(p.model, p.n_up)
+    e0, g = O.ground_state(s, I.psi(11, s.n))
+    ref = O.entanglement(s, g, "spatial", p.cut.left_mask)
+    S = _ecut().Sectors.from_problem(p)
+    v0 = torch.from_numpy(I.psi(12, S.dim)).to(dev)
+    e, st, gs = S.lanczos(v0, 80, tol=1e-12, reorth=True, max_restarts=6, want_gs=True)
+    assert abs(e - e0) <= 1e-10
+    got = S.entanglement(gs, cutoff=1e-14)
+    _ent_compare(got, ref, "device ground state", 1e-7)
+
+
+def test_entanglement_rejects_bad_arguments(dev):
+    import torch
+    E = _ecut()
+    S = E.Sectors.from_problem(I.heisenberg16())
+    with pytest.raises(E.EcutError) as err:
+        S.entanglement(torch.zeros(S.dim, dtype=torch.float64, device=dev))
+    assert err.value.status == E.ECUT_EINVAL
+    with pytest.raises(E.EcutError) as err:
+        S.entanglement(torch.ones(S.dim, dtype=torch.float64, device=dev), n_parts=2,
+                       part_of_block=np.full(S.info.n_blocks, 2))
+    assert err.value.status == E.ECUT_EINVAL

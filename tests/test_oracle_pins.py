@@ -406,3 +406,84 @@ def test_csr_rows_block_matches_full_csr():
     np.testing.assert_array_equal(vb, val[rp[r0]:rp[r1]])
     x = I.psi(5, s.n)
     np.testing.assert_array_equal(O.spmv_csr(rb, cb, vb, x), s.apply(x)[r0:r1])
+
+
+# ---------------------------------------------------------------- entanglement spectrum
+
+def _full_matrix(words, psi, n_sites, left_mask):
+    """psi as the full 2^n_L x 2^n_R matrix M[l, r] (no symmetry blocks),
+    by direct bit selection: the reference for the block-resolved
+    spectrum."""
+    lsites = [i for i in range(n_sites) if (left_mask >> i) & 1]
+    rsites = [i for i in range(n_sites) if not (left_mask >> i) & 1]
+    M = np.zeros((1 << len(lsites), 1 << len(rsites)))
+    for w, a in zip(words, psi):
+        w = int(w)
+        l = sum(((w >> s) & 1) << k for k, s in enumerate(lsites))
+        r = sum(((w >> s) & 1) << k for k, s in enumerate(rsites))
+        M[l, r] = a
+    return M
+
+
+@pytest.mark.parametrize("mask", [0b0000011111, 0b1010010110, 0b1])
+def test_entanglement_blocks_vs_full_matrix_svd(mask):
+    """The union of the block spectra equals the squared singular values of
+    the whole state matrix over the cut (normalised), for random states."""
+    p = I.xxz_chain(10, 1.0, 0.7)
+    s = O.Sector(p, 5)
+    psi = I.psi(41, s.n)
+    e = O.entanglement(s, psi, "spatial", mask)
+    sv = np.linalg.svd(_full_matrix(s.words, psi, 10, mask), compute_uv=False)
+    ref = np.sort(sv * sv / (psi @ psi))[::-1]
+    got = np.sort(np.concatenate(e["lam"]))[::-1]
+    k = min(len(ref), len(got))
+    np.testing.assert_allclose(got[:k], ref[:k], atol=1e-14)
+    assert np.all(ref[k:] < 1e-14) and np.all(got[k:] < 1e-14)
+    assert abs(e["w_q"].sum() - 1.0) < 1e-13
+
+
+def test_entanglement_product_state_and_singlet():
+    """A basis state has one Schmidt value 1 (xi = 0, zero entropy); the
+    two-site singlet has two equal weights 1/2 in two sectors (entropy log 2,
+    W_q = 1/2 each, weight IPR 2)."""
+    p = I.xxz_chain(8, 1.0, 1.0)
+    s = O.Sector(p, 4)
+    psi = np.zeros(s.n)
+    psi[17] = 3.0
+    e = O.entanglement(s, psi, "spatial", 0b00001111)
+    lam = np.concatenate(e["lam"])
+    assert np.sum(lam > 1e-15) == 1 and abs(lam.max() - 1.0) < 1e-15 and abs(e["entropy"]) < 1e-15
+    two = I.heisenberg_chain(2)
+    s2 = O.Sector(two, 1)
+    w, V = np.linalg.eigh(s2.dense())
+    assert abs(w[0] + 0.75) < 1e-14
+    e2 = O.entanglement(s2, V[:, 0], "spatial", 0b01, parts=np.array([0, 1]))
+    np.testing.assert_allclose([l[0] for l in e2["lam"]], [0.5, 0.5], atol=1e-15)
+    np.testing.assert_allclose(e2["w_q"], [0.5, 0.5], atol=1e-15)
+    assert abs(e2["entropy"] - np.log(2)) < 1e-14 and abs(e2["weight_ipr"] - 2.0) < 1e-13
+    np.testing.assert_allclose(e2["w_p"], [0.25, 0.25], atol=1e-15)
+
+
+def test_entanglement_hubbard_product_of_spin_words():
+    """Up/down cut: a state that is a product of an up-spin and a down-spin
+    amplitude vector has rank one; a sum of two such products with
+    orthogonal factors has the two weights of the sum."""
+    p = I.hubbard_chain(6, 1.0, 2.0)
+    s = O.Sector(p, 3, 2)
+    rng = np.random.default_rng(3)
+    nu, nd = 20, 15
+    a1, a2 = np.linalg.qr(rng.standard_normal((nu, 2)))[0].T
+    b1, b2 = np.linalg.qr(rng.standard_normal((nd, 2)))[0].T
+    psi = (0.8 * np.outer(a1, b1) + 0.6 * np.outer(a2, b2)).ravel()   # canonical order is up-major
+    e = O.entanglement(s, psi, "updn")
+    lam = e["lam"][0]
+    np.testing.assert_allclose(lam[:2], [0.64, 0.36], atol=1e-14)
+    assert np.all(lam[2:] < 1e-14)
+
+
+def test_ground_state_vs_dense():
+    p = I.xxz_chain(10, 1.0, 0.6)
+    s = O.Sector(p, 5)
+    e, g = O.ground_state(s, I.psi(2, s.n))
+    w, V = np.linalg.eigh(s.dense())
+    assert abs(e - w[0]) < 1e-12 and abs(abs(g @ V[:, 0]) - 1.0) < 1e-10
