@@ -372,6 +372,48 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
                                       double *basis_d, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Krylov dynamical correlations: the one-particle Green's function from
+ * Lanczos coefficients (the Krylov-based methods the paper names as the
+ * users of H*Psi, in the discussion after Eq. (3)).
+ *
+ * ecut_apply_cdag: y = c+_{site,spin} x (dagger = 1) or c_{site,spin} x
+ *   (dagger = 0) from sector src to sector dst of the same Hubbard lattice,
+ *   both with the up/down cut; dst must hold src's particle numbers with one
+ *   more (c+) or one fewer (c) of the given spin (0 = up, 1 = down).
+ *   Fermion order as in ecut_model_desc (all up modes, then all down modes,
+ *   each by site): the sign is (-1)^(occupied modes before the mode).  An up
+ *   mode maps rows of src to rows of dst, a down mode columns to columns.
+ *   x_d: src dim doubles; y_d: dst dim doubles (overwritten).  Asynchronous.
+ *   Errors: ECUT_EINVAL (sectors that do not match), ECUT_EUNSUPPORTED
+ *   (another model or cut).
+ *
+ * ecut_lanczos_tridiag: the Lanczos coefficients of H on the start vector
+ *   v0_d / |v0_d|: n_steps three-term steps (fewer at an invariant subspace),
+ *   alpha[j], beta[j] (beta[j] joins steps j and j + 1) into host arrays of
+ *   n_steps entries, *n_out = steps taken, *v0_norm2 = |v0|^2 (nullable).
+ *   basis_d: ecut_lanczos_workspace(s, {max_steps = n_steps, fixed_steps =
+ *   1}) doubles.  Synchronous.  Errors: ECUT_EINVAL (v0 zero: *v0_norm2 is
+ *   then 0), as ecut_lanczos_ground_state.
+ *
+ * ecut_continued_fraction: G(w) at n_omega frequencies (host arrays):
+ *   dagger = 1: G+(w) = weight / (z - a0 - b0^2 / (z - a1 - b1^2 / ...)),
+ *               z = w + i eta + e0;
+ *   dagger = 0: G-(w) = weight / (z + a0 - b0^2 / (z + a1 - ...)),
+ *               z = w + i eta - e0;
+ *   with the coefficients of H on c+ psi0 (resp. c psi0), weight = the
+ *   squared norm of that vector and e0 the ground energy of psi0, so that
+ *   G+(w) = <psi0| c (w + i eta + e0 - H)^-1 c+ |psi0> and
+ *   G-(w) = <psi0| c+ (w + i eta - e0 + H)^-1 c |psi0>.  Host only.
+ * ------------------------------------------------------------------------- */
+ecut_status ecut_apply_cdag(const ecut_sectors *src, const ecut_sectors *dst, int32_t site, int32_t spin,
+                            int32_t dagger, const double *x_d, double *y_d, void *stream);
+ecut_status ecut_lanczos_tridiag(const ecut_sectors *s, const double *v0_d, int32_t n_steps, double *alpha,
+                                 double *beta, int32_t *n_out, double *v0_norm2, double *basis_d, void *stream);
+ecut_status ecut_continued_fraction(const double *alpha, const double *beta, int32_t n, double weight, double e0,
+                                    int32_t dagger, const double *omega, int32_t n_omega, double eta, double *g_re,
+                                    double *g_im);
+
+/* ---------------------------------------------------------------------------
  * Entanglement spectrum of a state (the paper's discussion of the
  * distributed entanglement spectrum, with its figure of xi_{q,i} over the
  * sectors and the process-resolved W_P, and the End Matter's N_eff).

@@ -53,6 +53,8 @@ def lib():
         L.orc_build_csr.argtypes = [vp, vp, i64, vp, vp, vp]
         L.orc_build_csr_rows.restype = i64
         L.orc_build_csr_rows.argtypes = [vp, vp, i64, i64, i64, vp, vp, vp]
+        L.orc_apply_cdag.restype = ctypes.c_int
+        L.orc_apply_cdag.argtypes = [ctypes.c_int, vp, i64, vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
         L.orc_set_progress.restype = None
         L.orc_set_progress.argtypes = [ctypes.c_int]
         L.orc_set_threads.restype = None
@@ -305,4 +307,33 @@ def entanglement(sector, psi, cut_kind, left_mask=0, parts=None, cutoff=1e-14):
         parts = np.asarray(parts)
         out["w_p"] = np.array([np.sum(w_q[parts == p] ** 2) for p in range(int(parts.max()) + 1)])
     return out
+
+
+# ---------------------------------------------------------------- dynamical correlations
+
+def apply_cdag(src, dst, site, spin, dagger, x):
+    """y = c+_{site,spin} x (dagger) or c_{site,spin} x between the Hubbard
+    sectors src and dst (canonical order of each)."""
+    y = np.empty(dst.n)
+    r = lib().orc_apply_cdag(src.model.n_sites, _ptr(src.words), src.n, _ptr(dst.words), dst.n, int(site), int(spin),
+                             1 if dagger else 0, _ptr(np.ascontiguousarray(x, dtype=np.float64)), _ptr(y))
+    if r:
+        raise ValueError(f"oracle apply_cdag failed ({r})")
+    return y
+
+
+def continued_fraction(alpha, beta, weight, e0, dagger, omega, eta):
+    """Green's function from Lanczos coefficients of H on the start vector
+    c+ psi0 / |c+ psi0| (dagger) or c psi0 / |c psi0|:
+      G+(w) = weight / (z - a0 - b0^2 / (z - a1 - b1^2 / ...)),  z = w + i eta + E0;
+      G-(w) = weight / (z + a0 - b0^2 / (z + a1 - ...)),         z = w + i eta - E0;
+    beta[j] joins steps j and j + 1 (the last one is not used)."""
+    omega = np.asarray(omega, dtype=np.float64)
+    z = omega + 1j * eta + (e0 if dagger else -e0)
+    sgn = 1.0 if dagger else -1.0
+    g = np.zeros_like(z)
+    for j in range(len(alpha) - 1, -1, -1):
+        tail = beta[j] ** 2 * g if j + 1 < len(alpha) else 0.0
+        g = 1.0 / (z - sgn * alpha[j] - tail)
+    return weight * g
 

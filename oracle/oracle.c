@@ -67,7 +67,8 @@ typedef struct {
  *   1: drop the on-site U term        2: drop the fermion sign of hops
  *   3: flip amplitude jxy, not jxy/2  4: Sz Sz with the first site twice
  *   5: only the down spins hop        6: wrong sign of the beta term in Lanczos
- *   7: Lanczos stops after one step within tol instead of three */
+ *   7: Lanczos stops after one step within tol instead of three
+ *   8: c+ / c of one mode without its fermion sign */
 #ifndef ORC_PLANT
 #define ORC_PLANT 0
 #endif
@@ -413,6 +414,32 @@ int orc_apply_full(const orc_model *m, const uint64_t *words, int64_t n, const d
         y[r] = acc;
     }
     return err;
+}
+
+/* y = c+_{site,spin} x (dagger = 1) or c_{site,spin} x (dagger = 0) between
+ * two Hubbard sectors: source words ws[ns], destination words wd[nd] (each in
+ * increasing integer order).  The mode is (site, up) for spin 0, (site, dn)
+ * for spin 1; the sign is (-1)^(occupied modes before it in the creation-
+ * operator order), as for the hops of model_row.  y is overwritten. */
+int orc_apply_cdag(int n_sites, const uint64_t *ws, int64_t ns, const uint64_t *wd, int64_t nd,
+                   int site, int spin, int dagger, const double *x, double *y)
+{
+    if (site < 0 || site >= n_sites || spin < 0 || spin > 1 || n_sites > 31) return -1;
+    const int L = n_sites, mode = spin * L + site;
+    for (int64_t k = 0; k < nd; ++k) y[k] = 0.0;
+    int err = 0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < ns; ++k) {
+        const uint64_t w = ws[k];
+        const int occ = mode_occupied(w, L, mode);
+        if (occ == (dagger ? 1 : 0)) continue;   /* c+ on an occupied mode, c on an empty one: 0 */
+        const int sg = (ORC_PLANT != 8 && (occupied_before(w, L, mode) & 1)) ? -1 : 1;
+        const uint64_t w2 = w ^ (1ull << mode_bit(L, mode));
+        const int64_t t = orc_find(wd, nd, w2);
+        if (t < 0) { err = 1; continue; }
+        y[t] = sg * x[k];   /* the map is one-to-one: no two sources share a target */
+    }
+    return err ? -2 : 0;
 }
 
 /* Gather the bits of w found at the set positions of mask into the low bits,

@@ -957,6 +957,44 @@ static ecut_status permute(const ecut_sectors *s, const double *in, double *out,
     return ECUT_OK;
 }
 
+ecut_status ecut_apply_cdag(const ecut_sectors *src, const ecut_sectors *dst, int32_t site, int32_t spin,
+                            int32_t dagger, const double *x_d, double *y_d, void *stream) {
+    ecut_status st = check_dev(src);
+    if (st == ECUT_OK) st = check_dev(dst);
+    if (st != ECUT_OK) return st;
+    if (!x_d || !y_d || (const double *)y_d == x_d) return fail(ECUT_EINVAL, "null or overlapping vectors");
+    if (src->kind != ECUT_HUBBARD || dst->kind != ECUT_HUBBARD || src->cut_kind != ECUT_CUT_UPDN ||
+        dst->cut_kind != ECUT_CUT_UPDN)
+        return fail(ECUT_EUNSUPPORTED, "c+ / c is built for Hubbard sectors with the up/down cut");
+    if (src->n_sites != dst->n_sites) return fail(ECUT_EINVAL, "the two sectors belong to lattices of different size");
+    if (site < 0 || site >= src->n_sites || spin < 0 || spin > 1) return fail(ECUT_EINVAL, "site or spin out of range");
+    const int d = dagger ? 1 : -1;
+    const int want_up = src->n_up + (spin == 0 ? d : 0), want_dn = src->n_dn + (spin == 1 ? d : 0);
+    if (dst->n_up != want_up || dst->n_dn != want_dn)
+        return fail(ECUT_EINVAL, "the destination sector must hold the source's particles with one more (c+) or one "
+                                 "fewer (c) of the given spin");
+    const uint64_t *bt = nullptr;
+    st = device_res(nullptr, &bt, nullptr);
+    if (st != ECUT_OK) return st;
+    CdagArgs A{};
+    A.x = x_d;
+    A.y = y_d;
+    A.dim = dst->dim;
+    A.dR_dst = dst->blocks[0].d_r;
+    A.dR_src = src->blocks[0].d_r;
+    A.dst_lwords = dst->prob.lwords;
+    A.dst_rwords = dst->hub_ok ? dst->prob.hub.rwords32 : dst->prob.rwords;
+    A.src_col_of_rank = src->hub_ok ? src->prob.hub.col_of_rank : nullptr;
+    A.binom = bt;
+    A.site = site;
+    A.spin = spin;
+    A.dagger = dagger ? 1 : 0;
+    if (A.dim == 0) return ECUT_OK;
+    const hipError_t e = launch_cdag(A, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (apply_cdag)");
+    return ECUT_OK;
+}
+
 ecut_status ecut_import(const ecut_sectors *s, const double *canon_d, double *bip_d, void *stream) {
     return permute(s, canon_d, bip_d, true, stream);
 }

@@ -208,6 +208,20 @@ struct HubDArgs {
     int32_t n_chunks, n_items, n_slots, pad_;
 };
 
+// c+ / c of one (site, spin) mode between two Hubbard up/down sectors: each
+// destination element (a', c') reads its source element, or is 0.
+struct CdagArgs {
+    const double *x;                  // source vector
+    double *y;                        // destination vector
+    int64_t dim;                      // destination elements
+    int32_t dR_dst, dR_src;
+    const uint32_t *dst_lwords;       // up word of each destination row
+    const uint32_t *dst_rwords;       // down word of each destination column (column order)
+    const int32_t *src_col_of_rank;   // column of the source down word of colex rank r (NULL: r)
+    const uint64_t *binom;            // [65][65] binomial table
+    int32_t site, spin, dagger, pad_;
+};
+
 // Work item of the segment-tile kernel: up segment, down segment (global
 // index), down class; slot = index in the order-independent item list.
 // useg < 0 marks padding.

@@ -13,6 +13,7 @@
 // shape or on what else shares the launch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "ecut_internal.h"
@@ -1670,6 +1671,62 @@ hipError_t launch_hubD_only(const HubDArgs &D, int n_xcd, hipStream_t st) {
     else if (D.n_slots <= 16) launch_hubD<16>(D, stream, gd, xu, pd, st);
     else if (D.n_slots <= HUBD_MAX_SLOTS) launch_hubD<HUBD_MAX_SLOTS>(D, stream, gd, xu, pd, st);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// c+ / c of one mode between Hubbard up/down sectors (Krylov dynamical
+// correlations).  Fermion order: up modes, then down modes, each by site;
+// the sign is (-1)^(occupied modes before the mode) in the source word: the
+// up particles below the site for an up mode, every up particle plus the
+// down particles below the site for a down mode.  The destination word
+// has the mode occupied for c+ and empty for c; the source word is the
+// destination word with the mode flipped, found by its colex rank.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int64_t colex_rank_dev(uint32_t w, const uint64_t *__restrict__ binom) {
+    int64_t r = 0;
+    int j = 0;
+    while (w) {
+        const int p = __ffs(w) - 1;
+        r += (int64_t)binom[p * 65 + j + 1];
+        ++j;
+        w &= w - 1u;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_cdag(const CdagArgs A) {
+    const uint32_t bit = 1u << A.site;
+    const uint32_t below = bit - 1u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.dim; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = i / A.dR_dst;
+        const int c = (int)(i - a * A.dR_dst);
+        const uint32_t uw = A.dst_lwords[a];
+        const uint32_t dw = A.dst_rwords[c];
+        const uint32_t mw = A.spin == 0 ? uw : dw;
+        double v = 0.0;
+        if (((mw & bit) != 0) == (A.dagger != 0)) {
+            const uint32_t sw = mw ^ bit;   // the source word of the mode's spin
+            int par;
+            int64_t src;
+            if (A.spin == 0) {
+                par = __popc(sw & below);
+                src = colex_rank_dev(sw, A.binom) * A.dR_src + c;
+            } else {
+                par = __popc(uw) + __popc(sw & below);
+                const int64_t r = colex_rank_dev(sw, A.binom);
+                src = a * A.dR_src + (A.src_col_of_rank ? A.src_col_of_rank[r] : r);
+            }
+            const double xv = A.x[src];
+            v = (par & 1) ? -xv : xv;
+        }
+        A.y[i] = v;
+    }
+}
+
+hipError_t launch_cdag(const CdagArgs &A, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>((A.dim + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_cdag, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, A);
     return hipGetLastError();
 }
 

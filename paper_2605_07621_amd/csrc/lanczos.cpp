@@ -18,6 +18,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <string>
 
@@ -215,6 +216,7 @@ ecut_status lz_start(std::vector<LzSolve *> &solves, const std::vector<const dou
         hipError_t e = hipMemcpyAsync(h, L->scal + 8, sizeof(h), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "lanczos start norm");
+        L->start_norm2 = h[1];
         const double nrm = std::sqrt(std::max(h[1], 0.0));
         if (!(nrm > 0.0) || !std::isfinite(nrm)) {
             L->done = true;
@@ -619,6 +621,56 @@ double final_energy(const LzSolve &L) {
     return std::fabs(ql - L.energy) <= 1e-9 * (std::fabs(ql) + 1.0) ? ql : L.energy;
 }
 
+// One solve on the calling thread: carve the workspace, start, and run the
+// steps (two in flight without reorthogonalisation) until the solve stops.
+static ecut_status solve_one(const ecut_sectors *s, const double *v0_d, const ecut_lanczos_opts *opts,
+                             double *basis_d, hipStream_t &st, Staging &stg, LzSolve &L) {
+    if (opts->use_graph && !st) {
+        // graphs are captured on a stream of our own, ordered after the
+        // caller's work on the null stream; the call is synchronous anyway
+        static thread_local hipStream_t priv = nullptr;
+        static thread_local hipEvent_t after = nullptr;
+        hipError_t e = hipSuccess;
+        if (!priv) e = hipStreamCreateWithFlags(&priv, hipStreamNonBlocking);
+        if (e == hipSuccess && !after) e = hipEventCreateWithFlags(&after, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(after, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(priv, after, 0);
+        if (e != hipSuccess) return hip_fail(e, "lanczos stream");
+        st = priv;
+    }
+    lz_carve(L, s, opts->reorth != 0, opts->reorth ? opts->max_steps : 0, basis_d);
+    L.max_steps = opts->max_steps;
+    L.max_restarts = opts->max_restarts;
+    L.fixed = opts->fixed_steps != 0;
+    L.tol = opts->tol;
+    std::vector<LzSolve *> v{&L};
+    std::vector<const double *> v0{v0_d};
+    ecut_status rs = lz_start(v, v0, st, stg, true);
+    if (rs != ECUT_OK) return rs;
+    if (L.done) return L.status;
+    // three-term solves keep two steps in flight: the host processes step j
+    // while the device runs step j + 1 (its factors are set on the device),
+    // so a converged solve runs one extra step whose result is dropped
+    LzPipe pipe;
+    pipe.use_graph = opts->use_graph != 0;
+    while (!L.done || pipe.n > 0) {
+        if (!L.done && pipe.n < LzPipe::DEPTH && lz_can_launch(L)) {
+            rs = lz_launch(v, pipe, st, stg);
+        } else if (pipe.n > 0) {
+            rs = lz_finish(pipe, st, stg);
+        } else {
+            L.done = true;   // no step left to launch: the budget ends the solve
+            L.status = L.fixed ? ECUT_OK : ECUT_ENOTCONV;
+        }
+        if (rs != ECUT_OK) {
+            (void)hipStreamSynchronize(st);
+            return rs;
+        }
+    }
+    if (L.status != ECUT_OK && L.status != ECUT_ENOTCONV) return L.status;
+    return ECUT_OK;
+}
+
 }  // namespace ecut
 
 using namespace ecut;
@@ -645,52 +697,9 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
     static thread_local Staging stg;
-    if (opts->use_graph && !st) {
-        // graphs are captured on a stream of our own, ordered after the
-        // caller's work on the null stream; the call is synchronous anyway
-        static thread_local hipStream_t priv = nullptr;
-        static thread_local hipEvent_t after = nullptr;
-        hipError_t e = hipSuccess;
-        if (!priv) e = hipStreamCreateWithFlags(&priv, hipStreamNonBlocking);
-        if (e == hipSuccess && !after) e = hipEventCreateWithFlags(&after, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(after, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(priv, after, 0);
-        if (e != hipSuccess) return hip_fail(e, "lanczos stream");
-        st = priv;
-    }
     LzSolve L;
-    lz_carve(L, s, opts->reorth != 0, opts->reorth ? opts->max_steps : 0, basis_d);
-    L.max_steps = opts->max_steps;
-    L.max_restarts = opts->max_restarts;
-    L.fixed = opts->fixed_steps != 0;
-    L.tol = opts->tol;
-    std::vector<LzSolve *> v{&L};
-    std::vector<const double *> v0{v0_d};
-    ecut_status rs = lz_start(v, v0, st, stg, true);
+    ecut_status rs = solve_one(s, v0_d, opts, basis_d, st, stg, L);
     if (rs != ECUT_OK) return rs;
-    if (L.done) return L.status;
-    // three-term solves keep two steps in flight: the host processes step j
-    // while the device runs step j + 1 (its factors are set on the device),
-    // so a converged solve runs one extra step whose result is dropped
-    {
-        LzPipe pipe;
-        pipe.use_graph = opts->use_graph != 0;
-        while (!L.done || pipe.n > 0) {
-            if (!L.done && pipe.n < LzPipe::DEPTH && lz_can_launch(L)) {
-                rs = lz_launch(v, pipe, st, stg);
-            } else if (pipe.n > 0) {
-                rs = lz_finish(pipe, st, stg);
-            } else {
-                L.done = true;   // no step left to launch: the budget ends the solve
-                L.status = L.fixed ? ECUT_OK : ECUT_ENOTCONV;
-            }
-            if (rs != ECUT_OK) {
-                (void)hipStreamSynchronize(st);
-                return rs;
-            }
-        }
-    }
-    if (L.status != ECUT_OK && L.status != ECUT_ENOTCONV) return L.status;
     *energy = final_energy(L);
     if (gs_d) {
         rs = lz_ritz_vector(L, gs_d, st, stg);
@@ -706,6 +715,49 @@ ecut_status ecut_lanczos_ground_state(const ecut_sectors *s, const double *v0_d,
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     if (L.status == ECUT_ENOTCONV) return fail(ECUT_ENOTCONV, "Lanczos did not reach tol");
+    return ECUT_OK;
+}
+
+ecut_status ecut_lanczos_tridiag(const ecut_sectors *s, const double *v0_d, int32_t n_steps, double *alpha,
+                                 double *beta, int32_t *n_out, double *v0_norm2, double *basis_d, void *stream) {
+    if (!s || !v0_d || !alpha || !beta || !n_out || !basis_d) return fail(ECUT_EINVAL, "null argument");
+    if (!s->on_device) return fail(ECUT_EINVAL, "handle was built with ECUT_BUILD_HOST_ONLY");
+    if (n_steps < 1) return fail(ECUT_EINVAL, "n_steps must be >= 1");
+    ecut_lanczos_opts o{};
+    o.max_steps = n_steps;
+    o.fixed_steps = 1;
+    hipStream_t st = (hipStream_t)stream;
+    static thread_local Staging stg;
+    LzSolve L;
+    *n_out = 0;
+    ecut_status rs = solve_one(s, v0_d, &o, basis_d, st, stg, L);
+    if (v0_norm2) *v0_norm2 = L.start_norm2;
+    if (rs != ECUT_OK) return rs;
+    const int m = (int)L.a.size();
+    for (int j = 0; j < m; ++j) {
+        alpha[j] = L.a[j];
+        beta[j] = L.b[j];
+    }
+    *n_out = m;
+    return ECUT_OK;
+}
+
+ecut_status ecut_continued_fraction(const double *alpha, const double *beta, int32_t n, double weight, double e0,
+                                    int32_t dagger, const double *omega, int32_t n_omega, double eta, double *g_re,
+                                    double *g_im) {
+    if (!alpha || !beta || !omega || !g_re || !g_im || n < 1 || n_omega < 0) return fail(ECUT_EINVAL, "bad argument");
+    const double sgn = dagger ? 1.0 : -1.0;
+    for (int32_t k = 0; k < n_omega; ++k) {
+        const std::complex<double> z(omega[k] + (dagger ? e0 : -e0), eta);
+        std::complex<double> g(0.0, 0.0);
+        for (int32_t j = n - 1; j >= 0; --j) {
+            const std::complex<double> tail = j + 1 < n ? beta[j] * beta[j] * g : std::complex<double>(0.0, 0.0);
+            g = 1.0 / (z - sgn * alpha[j] - tail);
+        }
+        g *= weight;
+        g_re[k] = g.real();
+        g_im[k] = g.imag();
+    }
     return ECUT_OK;
 }
 

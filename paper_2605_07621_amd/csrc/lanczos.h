@@ -39,6 +39,7 @@ struct LzSolve {
     double tol = 0.0;
     std::vector<double> a, b, sc; // tridiagonal matrix; sc: scales of the basis vectors (reorth)
     double energy = 0.0, e_prev = 0.0, residual = 0.0;
+    double start_norm2 = 0.0;     // |v0|^2 (read by the host when the start asks for it)
     bool done = false;
     ecut_status status = ECUT_OK;
 };

@@ -109,6 +109,9 @@ SYMBOLS = [
     ("ecut_lanczos_workspace", _sz, [_vp, ctypes.POINTER(LanczosOpts)]),
     ("ecut_lanczos_ground_state", _i32, [_vp, _vp, ctypes.POINTER(LanczosOpts), ctypes.POINTER(_dbl), _vp,
                                          ctypes.POINTER(LanczosStats), _vp, _vp]),
+    ("ecut_apply_cdag", _i32, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp]),
+    ("ecut_lanczos_tridiag", _i32, [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _vp, _vp]),
+    ("ecut_continued_fraction", _i32, [_vp, _vp, _i32, _dbl, _dbl, _i32, _vp, _i32, _dbl, _vp, _vp]),
     ("ecut_entanglement_sizes", _sz, [_vp, ctypes.POINTER(_sz)]),
     ("ecut_entanglement_spectrum", _i32, [_vp, _vp, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                           ctypes.POINTER(Entanglement), _vp, _vp]),
@@ -327,6 +330,57 @@ class Sectors:
         stats = dict(steps=stt.steps, restarts=stt.restarts, converged=stt.converged, residual=stt.residual,
                      seconds=stt.seconds, status=st)
         return e.value, stats, gs
+
+
+def apply_cdag(src, dst, site, spin, dagger, x, out=None, stream=None):
+    """ecut_apply_cdag: c+ (dagger) or c of mode (site, spin) from sector
+    src to sector dst (bipartite layouts of each)."""
+    import torch
+    y = torch.empty(dst.dim, dtype=torch.float64, device=x.device) if out is None else out
+    _check(lib().ecut_apply_cdag(src.h, dst.h, int(site), int(spin), 1 if dagger else 0, _dptr(x, src.dim, "x"),
+                                 _dptr(y, dst.dim, "y"), _stream(stream)))
+    return y
+
+
+def lanczos_tridiag(S, v0, n_steps, stream=None):
+    """ecut_lanczos_tridiag: (alpha, beta, |v0|^2) of n_steps Lanczos steps
+    of S's H from v0."""
+    import numpy as np
+    import torch
+    o = LanczosOpts(int(n_steps), 0, 0, 1, 1e-10, 0)
+    nws = int(lib().ecut_lanczos_workspace(S.h, ctypes.byref(o)))
+    ws = torch.empty(nws, dtype=torch.float64, device=v0.device)
+    a = np.zeros(n_steps)
+    b = np.zeros(n_steps)
+    n = _i32()
+    nrm = _dbl()
+    _check(lib().ecut_lanczos_tridiag(S.h, _dptr(v0, S.dim, "v0"), int(n_steps), _vp(a.ctypes.data), _vp(b.ctypes.data),
+                                      ctypes.byref(n), ctypes.byref(nrm), _dptr(ws, nws, "workspace"), _stream(stream)))
+    return a[:n.value].copy(), b[:n.value].copy(), nrm.value
+
+
+def continued_fraction(alpha, beta, weight, e0, dagger, omega, eta):
+    """ecut_continued_fraction: complex numpy array of G(omega)."""
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    w = np.ascontiguousarray(omega, dtype=np.float64)
+    re = np.empty(len(w))
+    im = np.empty(len(w))
+    _check(lib().ecut_continued_fraction(_vp(a.ctypes.data), _vp(b.ctypes.data), len(a), float(weight), float(e0),
+                                         1 if dagger else 0, _vp(w.ctypes.data), len(w), float(eta),
+                                         _vp(re.ctypes.data), _vp(im.ctypes.data)))
+    return re + 1j * im
+
+
+def green_function(S0, gs, e0, S1, site, spin, dagger, n_steps, omega, eta, stream=None):
+    """G+(omega) (dagger) or G-(omega) of mode (site, spin) on the ground
+    state gs (bipartite layout of S0, energy e0), with S1 the sector of
+    c+ gs (resp. c gs): apply_cdag, lanczos_tridiag and continued_fraction
+    of the library in turn.  Returns (G, alpha, beta, weight)."""
+    y = apply_cdag(S0, S1, site, spin, dagger, gs, stream=stream)
+    a, b, w = lanczos_tridiag(S1, y, n_steps, stream=stream)
+    return continued_fraction(a, b, w, e0, dagger, omega, eta), a, b, w
 
 
 def set_allocator(alloc=None, free=None):

@@ -972,3 +972,76 @@ def test_entanglement_rejects_bad_arguments(dev):
         S.entanglement(torch.ones(S.dim, dtype=torch.float64, device=dev), n_parts=2,
                        part_of_block=np.full(S.info.n_blocks, 2))
     assert err.value.status == E.ECUT_EINVAL
+
+
+_CDAG_CASES = [(I.hubbard_chain(8, 1.0, 3.0), 4, 3), (I.hubbard_chain(7, 1.0, 2.0), 2, 4),
+               (I.random_hubbard_model(np.random.default_rng(61), 9, n_bonds=14), 4, 4),
+               (I.hubbard_chain(22, 1.0, 3.0), 2, 1)]   # beyond the up/down kernels' tables: colex columns
+
+
+@pytest.mark.parametrize("k", range(len(_CDAG_CASES)))
+def test_apply_cdag_vs_oracle(dev, k):
+    """c+ and c of every site and spin between Hubbard sectors equal the
+    oracle's full-basis operator bit for bit (a signed permutation), in
+    class-major and in colex column layouts."""
+    import torch
+    E = _ecut()
+    m, nu, nd = _CDAG_CASES[k]
+    L = m.n_sites
+    S0 = E.Sectors.from_problem(I.Problem(m, I.Cut("updn"), nu, nd))
+    s0 = O.Sector(m, nu, nd)
+    x = I.psi(2400 + k, s0.n)
+    xb = S0.import_(torch.from_numpy(x).to(dev))
+    sites = range(L) if L <= 9 else (0, 5, L - 1)
+    for spin in (0, 1):
+        for dagger in (True, False):
+            nu1, nd1 = nu + (spin == 0) * (1 if dagger else -1), nd + (spin == 1) * (1 if dagger else -1)
+            if not (0 <= nu1 <= L and 0 <= nd1 <= L):
+                continue
+            S1 = E.Sectors.from_problem(I.Problem(m, I.Cut("updn"), nu1, nd1))
+            s1 = O.Sector(m, nu1, nd1)
+            for site in sites:
+                y = S1.export(E.apply_cdag(S0, S1, site, spin, dagger, xb)).cpu().numpy()
+                ref = O.apply_cdag(s0, s1, site, spin, dagger, x)
+                assert np.array_equal(y, ref), (m.name, spin, dagger, site)
+            S1.close()
+    with pytest.raises(E.EcutError) as err:   # a destination that does not match the operator
+        E.apply_cdag(S0, S0, 0, 0, True, xb)
+    assert err.value.status == E.ECUT_EINVAL
+
+
+@pytest.mark.parametrize("site,spin,dagger", [(3, 0, True), (0, 1, False), (5, 1, True)])
+def test_green_function_vs_oracle(dev, site, spin, dagger):
+    """12-site Hubbard chain (U=4, half filling): from the oracle's ground
+    state, c+ psi0 (or c psi0) on the device, 60 Lanczos steps of the target
+    sector's H and the continued fraction, against the oracle's operator,
+    its own Lanczos coefficients and continued fraction on the same start
+    vector: weight to 1e-13, the first 10 coefficients to 1e-10 (two
+    three-term recurrences in different summation orders part once the
+    extreme Ritz values converge and orthogonality is lost, after about a
+    dozen steps here), and G(w) on a grid at eta = 0.5, where both continued
+    fractions have converged, to 1e-6 of its largest value."""
+    import torch
+    E = _ecut()
+    p = I.hubbard12()
+    s0 = O.Sector(p.model, 6, 6)
+    e0, g = O.ground_state(s0, I.psi(1, s0.n))
+    d = 1 if dagger else -1
+    nu1, nd1 = 6 + (spin == 0) * d, 6 + (spin == 1) * d
+    s1 = O.Sector(p.model, nu1, nd1)
+    phi = O.apply_cdag(s0, s1, site, spin, dagger, g)
+    w_ref = phi @ phi
+    _, a_ref, b_ref = s1.lanczos(phi, 60)
+    omega = np.linspace(-10, 10, 201)
+    G_ref = O.continued_fraction(a_ref, b_ref, w_ref, e0, dagger, omega, 0.5)
+    S0 = E.Sectors.from_problem(p)
+    S1 = E.Sectors.from_problem(I.Problem(p.model, I.Cut("updn"), nu1, nd1))
+    gb = S0.import_(torch.from_numpy(g).to(dev))
+    G, a, b, w = E.green_function(S0, gb, e0, S1, site, spin, dagger, 60, omega, 0.5)
+    assert abs(w - w_ref) <= 1e-13 * max(w_ref, 1.0)
+    assert len(a) == 60
+    np.testing.assert_allclose(a[:10], a_ref[:10], atol=1e-10)
+    np.testing.assert_allclose(b[:10], b_ref[:10], atol=1e-10)
+    assert np.max(np.abs(G - G_ref)) <= 1e-6 * np.max(np.abs(G_ref)), np.max(np.abs(G - G_ref))
+    # the library's continued fraction on the oracle's coefficients is the oracle's
+    np.testing.assert_allclose(E.continued_fraction(a_ref, b_ref, w_ref, e0, dagger, omega, 0.5), G_ref, atol=1e-13)

@@ -487,3 +487,73 @@ def test_ground_state_vs_dense():
     e, g = O.ground_state(s, I.psi(2, s.n))
     w, V = np.linalg.eigh(s.dense())
     assert abs(e - w[0]) < 1e-12 and abs(abs(g @ V[:, 0]) - 1.0) < 1e-10
+
+
+# ---------------------------------------------------------------- c+ / c and the continued fraction
+
+def _dense_cdag_word_basis(L, site, spin):
+    """c+_{site,spin} as a dense Jordan-Wigner matrix re-indexed to words."""
+    M = 2 * L
+    cd = jw_annihilator(spin * L + site, M).T
+    perm = np.zeros(2 ** M, dtype=np.int64)
+    for idx in range(2 ** M):
+        word = 0
+        for m in range(M):
+            if (idx >> m) & 1:
+                word |= 1 << ((L + m) if m < L else (m - L))
+        perm[idx] = word
+    out = np.zeros_like(cd)
+    out[np.ix_(perm, perm)] = cd
+    return out
+
+
+@pytest.mark.parametrize("site,spin", [(0, 0), (2, 0), (3, 1), (1, 1)])
+def test_apply_cdag_vs_jordan_wigner(site, spin):
+    """c+ and c between sectors equal the Jordan-Wigner matrices restricted
+    to the two sectors (signs included), and {c, c+} = 1 on a sector."""
+    L = 4
+    m = I.hubbard_chain(L, 1.0, 2.0)
+    cd = _dense_cdag_word_basis(L, site, spin)
+    nu, nd = 2, 1
+    src = O.Sector(m, nu, nd)
+    dst = O.Sector(m, nu + (spin == 0), nd + (spin == 1))
+    x = I.psi(7, src.n)
+    i_s, i_d = src.words.astype(np.int64), dst.words.astype(np.int64)
+    np.testing.assert_allclose(O.apply_cdag(src, dst, site, spin, True, x), cd[np.ix_(i_d, i_s)] @ x, atol=1e-15)
+    xd = I.psi(8, dst.n)
+    np.testing.assert_allclose(O.apply_cdag(dst, src, site, spin, False, xd), cd.T[np.ix_(i_s, i_d)] @ xd, atol=1e-15)
+    # c c+ + c+ c = 1 on the source sector
+    lower = O.Sector(m, nu - (spin == 0), nd - (spin == 1))
+    y = O.apply_cdag(dst, src, site, spin, False, O.apply_cdag(src, dst, site, spin, True, x)) + \
+        O.apply_cdag(lower, src, site, spin, True, O.apply_cdag(src, lower, site, spin, False, x))
+    np.testing.assert_allclose(y, x, atol=1e-14)
+
+
+@pytest.mark.parametrize("dagger", [True, False])
+def test_continued_fraction_vs_lehmann(dagger):
+    """Green's function of a 4-site Hubbard chain from the oracle's Lanczos
+    coefficients (the whole Krylov space) against the Lehmann sum over the
+    exact eigenstates of the target sector:
+      G+(w) = sum_n |<n|c+|0>|^2 / (w + i eta + E0 - E_n),
+      G-(w) = sum_n |<n|c|0>|^2 / (w + i eta - E0 + E_n)."""
+    L = 4
+    m = I.hubbard_chain(L, 1.0, 3.0)
+    s0 = O.Sector(m, 2, 2)
+    w0, V0 = np.linalg.eigh(s0.dense())
+    e0, g0 = w0[0], V0[:, 0]
+    s1 = O.Sector(m, 3 if dagger else 1, 2)
+    phi = O.apply_cdag(s0, s1, 1, 0, dagger, g0)
+    weight = phi @ phi
+    w1, V1 = np.linalg.eigh(s1.dense())
+    amp = (V1.T @ phi) ** 2
+    omega = np.linspace(-8, 8, 41)
+    eta = 0.1
+    if dagger:
+        lehmann = np.sum(amp[None, :] / (omega[:, None] + 1j * eta + e0 - w1[None, :]), axis=1)
+    else:
+        lehmann = np.sum(amp[None, :] / (omega[:, None] + 1j * eta - e0 + w1[None, :]), axis=1)
+    _, a, b = s1.lanczos(phi, s1.n, reorth=True)
+    g = O.continued_fraction(a, b, weight, e0, dagger, omega, eta)
+    np.testing.assert_allclose(g, lehmann, atol=1e-11)
+    # sum rule: the spectral weight integrates to |c+ psi0|^2
+    assert abs(weight - amp.sum()) < 1e-13

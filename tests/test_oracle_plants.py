@@ -23,6 +23,7 @@ PLANTS = {
     5: "only the down spins hop",
     6: "wrong sign of the beta term in Lanczos",
     7: "Lanczos stops after one step within tol instead of three",
+    8: "c+ / c of one mode without its fermion sign",
 }
 
 
