@@ -28,7 +28,7 @@ class _Model(ctypes.Structure):
                 ("n_bonds", ctypes.c_int32), ("pad_", ctypes.c_int32),
                 ("bi", ctypes.c_void_p), ("bj", ctypes.c_void_p),
                 ("jxy", ctypes.c_void_p), ("jz", ctypes.c_void_p),
-                ("t", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+                ("t", ctypes.c_void_p), ("u", ctypes.c_void_p), ("v", ctypes.c_void_p)]
 
 
 def lib():
@@ -68,6 +68,9 @@ def lib():
         L.orc_bipartite_positions.restype = ctypes.c_int
         L.orc_bipartite_positions.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                               ctypes.c_int, ctypes.c_int, vp, i64, vp, vp, ctypes.c_int]
+        L.orc_bipartite_hubbard_spatial.restype = ctypes.c_int
+        L.orc_bipartite_hubbard_spatial.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, vp, i64,
+                                                    vp, vp, vp, ctypes.c_int]
         L.orc_tridiag_eig.restype = dbl
         L.orc_tridiag_eig.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
         L.orc_lanczos.restype = ctypes.c_int
@@ -102,10 +105,14 @@ class OracleModel:
         else:
             self.t = np.ascontiguousarray(m.t, dtype=np.float64)
             self.u = None if m.u is None else np.ascontiguousarray(m.u, dtype=np.float64)
+            v = getattr(m, "v", None)
+            self.v = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
             self.jxy = self.jz = z
+        if self.kind == ORC_SPIN:
+            self.v = None
         self.c = _Model(self.kind, self.n_sites, self.n_bonds, 0,
                         _ptr(self.bi), _ptr(self.bj), _ptr(self.jxy), _ptr(self.jz),
-                        _ptr(self.t), _ptr(self.u))
+                        _ptr(self.t), _ptr(self.u), _ptr(self.v))
 
     @property
     def ref(self):
@@ -205,6 +212,20 @@ class Sector:
         if lib().orc_apply_rows(self.om.ref, _ptr(self.words), self.n, _ptr(x), _ptr(rows), len(rows), _ptr(y)):
             raise RuntimeError("oracle apply_rows failed")
         return y
+
+    def bipartite_signed(self, left_mask):
+        """Hubbard model, spatial cut: (pos, sign, blocks) with
+        bip[pos[i]] = sign[i] * canon[i]; blocks = int64 rows
+        (N_up_L, N_dn_L, d_L, d_R, offset) in lexicographic order."""
+        pos = np.empty(self.n, dtype=np.int64)
+        sign = np.empty(self.n, dtype=np.int8)
+        blocks = np.empty(5 * 33 * 33, dtype=np.int64)
+        nb = lib().orc_bipartite_hubbard_spatial(self.model.n_sites, int(left_mask), self.n_up, self.n_dn,
+                                                 _ptr(self.words), self.n, _ptr(pos), _ptr(sign), _ptr(blocks),
+                                                 33 * 33)
+        if nb < 0:
+            raise ValueError(f"oracle spatial Hubbard map failed ({nb})")
+        return pos, sign, blocks[:5 * nb].reshape(nb, 5).copy()
 
     def bipartite(self, cut_kind, left_mask=0):
         """(pos, blocks): pos[i] = bipartite position of canonical index i;

@@ -57,6 +57,8 @@ typedef struct {
     const double *jxy, *jz;   /* spin couplings per bond */
     const double *t;          /* Hubbard hopping per bond */
     const double *u;          /* Hubbard on-site U per site (may be NULL) */
+    const double *v;          /* Hubbard density interaction V n_i n_j per bond,
+                                 n = n_up + n_dn (may be NULL) */
 } orc_model;
 
 #define ORC_MAX_ROW 1024
@@ -68,7 +70,9 @@ typedef struct {
  *   3: flip amplitude jxy, not jxy/2  4: Sz Sz with the first site twice
  *   5: only the down spins hop        6: wrong sign of the beta term in Lanczos
  *   7: Lanczos stops after one step within tol instead of three
- *   8: c+ / c of one mode without its fermion sign */
+ *   8: c+ / c of one mode without its fermion sign
+ *   9: drop the bond density interaction V
+ *  10: spatial Hubbard cut without the reordering sign */
 #ifndef ORC_PLANT
 #define ORC_PLANT 0
 #endif
@@ -242,6 +246,13 @@ static int model_row(const orc_model *m, uint64_t w, uint64_t *cw, double *cv)
         if (m->u && ORC_PLANT != 1)
             for (int s = 0; s < L; ++s)
                 if (((w >> (L + s)) & 1u) && ((w >> s) & 1u)) diag += m->u[s];
+        if (m->v && ORC_PLANT != 9)
+            for (int b = 0; b < m->n_bonds; ++b) {
+                const int i = m->bi[b], j = m->bj[b];
+                const int ni = (int)((w >> (L + i)) & 1u) + (int)((w >> i) & 1u);
+                const int nj = (int)((w >> (L + j)) & 1u) + (int)((w >> j) & 1u);
+                diag += m->v[b] * ni * nj;
+            }
         for (int b = 0; b < m->n_bonds; ++b) {
             if (m->t[b] == 0.0) continue;
             for (int spin = ORC_PLANT == 5 ? 1 : 0; spin < 2; ++spin) {
@@ -495,6 +506,8 @@ int orc_bipartite_positions(int kind, int cut, int n_sites, uint64_t left_mask, 
         for (int b = 0; b < nb; ++b) { free(lw[b]); free(rw[b]); }
         return err ? -3 : nb;
     }
+    if (kind == ORC_HUBBARD && cut == ORC_CUT_SPATIAL)
+        return -5;   /* signed map: orc_bipartite_hubbard_spatial */
     if (kind == ORC_HUBBARD && cut == ORC_CUT_UPDN) {
         if (max_blocks < 1) return -2;
         int64_t nu = choose(n_sites, n_up), nd = choose(n_sites, n_dn);
@@ -514,6 +527,95 @@ int orc_bipartite_positions(int kind, int cut, int n_sites, uint64_t left_mask, 
         return err ? -3 : 1;
     }
     return -4;
+}
+
+/*
+ * Hubbard model with a spatial cut: L = the sites of left_mask, R = the
+ * others.  The bipartite basis state |l, r> is the ordered product of the
+ * creation operators of the occupied L modes (up modes by site, then down
+ * modes by site) followed by those of the R modes in the same order, acting
+ * on the vacuum; the canonical state of word w orders all up modes by site,
+ * then all down modes.  So |w> = sign(w) |l, r>, sign(w) = the parity of the
+ * permutation that sorts w's occupied modes from the one order to the other
+ * (counted here pair by pair).  Blocks are (N_up_L, N_dn_L) in lexicographic
+ * order; a block's rows are its L words (up bits of the L sites, then down
+ * bits, each compacted in site order: l = (up_L << n_L) | dn_L) in increasing
+ * integer order, its columns likewise its R words.
+ * pos[i], sign[i] for the canonical index i; blocks receive rows
+ * (N_up_L, N_dn_L, d_L, d_R, offset).  Returns the number of blocks.
+ */
+int orc_bipartite_hubbard_spatial(int n_sites, uint64_t left_mask, int n_up, int n_dn, const uint64_t *words, int64_t n,
+                                  int64_t *pos, int8_t *sign, int64_t *blocks, int max_blocks)
+{
+    const int S = n_sites;
+    if (S > 31) return -1;
+    const uint64_t full = (1ull << S) - 1;
+    if (left_mask & ~full) return -1;
+    const uint64_t rmask = full & ~left_mask;
+    const int nL = popcount64(left_mask), nR = S - nL;
+    /* subsystem words by (a, b): all 2n-bit words (up << n) | dn with a up and b down bits */
+    int nb = 0;
+    int64_t off = 0;
+    int64_t dl[65 * 33], dr[65 * 33], boff[65 * 33];
+    int bidx[33][33];
+    for (int a = 0; a <= nL; ++a)
+        for (int b = 0; b <= nL; ++b) {
+            bidx[a][b] = -1;
+            const int ar = n_up - a, br = n_dn - b;
+            if (ar < 0 || br < 0 || ar > nR || br > nR) continue;
+            if (nb >= max_blocks) return -2;
+            dl[nb] = choose(nL, a) * choose(nL, b);
+            dr[nb] = choose(nR, ar) * choose(nR, br);
+            boff[nb] = off;
+            blocks[5 * nb + 0] = a; blocks[5 * nb + 1] = b; blocks[5 * nb + 2] = dl[nb];
+            blocks[5 * nb + 3] = dr[nb]; blocks[5 * nb + 4] = off;
+            off += dl[nb] * dr[nb];
+            bidx[a][b] = nb++;
+        }
+    int err = 0;
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const uint64_t w = words[i];
+        const uint64_t up = w >> S, dn = w & full;
+        const uint64_t ul = compact_bits(up, left_mask), dl_ = compact_bits(dn, left_mask);
+        const uint64_t ur = compact_bits(up, rmask), dr_ = compact_bits(dn, rmask);
+        const int a = popcount64(ul), b = popcount64(dl_);
+        const int q = bidx[a][b];
+        if (q < 0) { err = 1; continue; }
+        /* row: rank of (ul << nL) | dl_ among words with a up and b down
+         * bits: the up part's position among the a-words times the number
+         * of b-words, plus the down part's position (up-major integer order) */
+        int64_t ra = 0, rb = 0, rc = 0, rd = 0;
+        /* positions by counting the smaller words of the same popcount */
+        for (uint64_t x = 0; x < ul; ++x) ra += popcount64(x) == a;
+        for (uint64_t x = 0; x < dl_; ++x) rb += popcount64(x) == b;
+        for (uint64_t x = 0; x < ur; ++x) rc += popcount64(x) == n_up - a;
+        for (uint64_t x = 0; x < dr_; ++x) rd += popcount64(x) == n_dn - b;
+        const int64_t row = ra * choose(nL, b) + rb, col = rc * choose(nR, n_dn - b) + rd;
+        pos[i] = boff[q] + row * dr[q] + col;
+        /* parity: list the occupied modes with their place in either order */
+        int gpos[64], bpos[64], k = 0;
+        for (int s = 0; s < S; ++s)
+            if ((up >> s) & 1u) {
+                const int inL = (int)((left_mask >> s) & 1u);
+                gpos[k] = s;
+                bpos[k] = inL ? s : 2 * S + s;            /* L up, then (later) R up */
+                ++k;
+            }
+        for (int s = 0; s < S; ++s)
+            if ((dn >> s) & 1u) {
+                const int inL = (int)((left_mask >> s) & 1u);
+                gpos[k] = S + s;
+                bpos[k] = inL ? S + s : 3 * S + s;        /* L down before R up */
+                ++k;
+            }
+        int inv = 0;
+        for (int x = 0; x < k; ++x)
+            for (int y = x + 1; y < k; ++y)
+                if ((gpos[x] < gpos[y]) != (bpos[x] < bpos[y])) ++inv;
+        if (sign) sign[i] = (ORC_PLANT == 10 || !(inv & 1)) ? 1 : -1;
+    }
+    return err ? -3 : nb;
 }
 
 /* ---------------- Lanczos ---------------- */

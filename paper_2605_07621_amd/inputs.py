@@ -25,6 +25,7 @@ class Model:
     t: Optional[np.ndarray] = None     # Hubbard: hopping per bond, term -t (c+c + h.c.)
     u: Optional[np.ndarray] = None     # Hubbard: on-site U per site
     name: str = ""
+    v: Optional[np.ndarray] = None     # Hubbard: density interaction V n_i n_j per bond (n = n_up + n_dn)
 
 
 @dataclass
@@ -78,10 +79,13 @@ def j1j2_lattice(lx, ly, J1=1.0, J2=0.5):
     return Model("spin", lx * ly, b, jxy=J.copy(), jz=J.copy(), name=f"j1j2_{lx}x{ly}")
 
 
-def hubbard_chain(n, t=1.0, U=4.0, periodic=False):
+def hubbard_chain(n, t=1.0, U=4.0, periodic=False, V=None):
+    """Hubbard chain; V (optional) adds V n_i n_{i+1} on every bond (the
+    extended model of the paper's spatial-cut benchmark)."""
     bonds = [(i, i + 1) for i in range(n - 1)] + ([(n - 1, 0)] if periodic and n > 2 else [])
     b = np.asarray(bonds, dtype=np.int32).reshape(-1, 2)
-    return Model("hubbard", n, b, t=_arr(t, len(b)), u=_arr(U, n), name=f"hubbard_chain_{n}")
+    return Model("hubbard", n, b, t=_arr(t, len(b)), u=_arr(U, n), name=f"hubbard_chain_{n}",
+                 v=None if V is None else _arr(V, len(b)))
 
 
 def random_spin_model(rng, n, n_bonds=None):
@@ -108,6 +112,14 @@ def random_hubbard_model(rng, n, n_bonds=None):
     b = np.asarray(sorted(pairs), dtype=np.int32)
     return Model("hubbard", n, b, t=rng.uniform(-1.2, 1.2, len(b)), u=rng.uniform(0, 6, n),
                  name=f"random_hubbard_{n}")
+
+
+def random_extended_hubbard_model(rng, n, n_bonds=None):
+    """Random hoppings, U_i and bond interactions V_b on random bonds."""
+    m = random_hubbard_model(rng, n, n_bonds)
+    m.v = rng.uniform(-1.0, 2.5, len(m.bonds))
+    m.name = f"random_ext_hubbard_{n}"
+    return m
 
 
 def left_mask_first(k):

@@ -557,3 +557,101 @@ def test_continued_fraction_vs_lehmann(dagger):
     np.testing.assert_allclose(g, lehmann, atol=1e-11)
     # sum rule: the spectral weight integrates to |c+ psi0|^2
     assert abs(weight - amp.sum()) < 1e-13
+
+
+# ---------------------------------------------------------------- extended Hubbard (V) and the spatial cut
+
+def dense_ext_hubbard_word_basis(model):
+    """dense_hubbard_word_basis plus V_b n_i n_j (n = n_up + n_dn) on every bond."""
+    L = model.n_sites
+    H = dense_hubbard_word_basis(model)
+    if model.v is None:
+        return H
+    d = np.zeros(2 ** (2 * L))
+    for w in range(2 ** (2 * L)):
+        for (i, j), v in zip(model.bonds, model.v):
+            ni = ((w >> (L + i)) & 1) + ((w >> i) & 1)
+            nj = ((w >> (L + j)) & 1) + ((w >> j) & 1)
+            d[w] += v * ni * nj
+    return H + np.diag(d)
+
+
+@pytest.mark.parametrize("seed,L", [(21, 3), (22, 4)])
+def test_extended_hubbard_vs_jordan_wigner(seed, L):
+    m = I.random_extended_hubbard_model(np.random.default_rng(seed), L, n_bonds=min(L * (L - 1) // 2, 2 * L))
+    Hfull = dense_ext_hubbard_word_basis(m)
+    for nu in range(L + 1):
+        for nd in range(L + 1):
+            s = O.Sector(m, nu, nd)
+            idx = s.words.astype(np.int64)
+            np.testing.assert_allclose(s.dense(), Hfull[np.ix_(idx, idx)], atol=1e-14, rtol=0)
+
+
+def _subsystem_ops(n):
+    """Annihilators of a subsystem of n sites: modes (up 0..n-1, dn 0..n-1),
+    Jordan-Wigner in that order; basis index = up_bits | dn_bits << n."""
+    return [jw_annihilator(m, 2 * n) for m in range(2 * n)]
+
+
+def bipartite_hubbard_kron(model, left_mask):
+    """The extended Hubbard H on the bipartite Fock space L (x) R built from
+    subsystem operators: an L mode acts as c_L (x) 1, an R mode as
+    P_L (x) c_R with P_L = (-1)^(N_L) (the R operators pass the L ones), the
+    L modes ordered before the R modes.  Returns (H, lsites, rsites)."""
+    S = model.n_sites
+    ls = [i for i in range(S) if (left_mask >> i) & 1]
+    rs = [i for i in range(S) if not (left_mask >> i) & 1]
+    nL, nR = len(ls), len(rs)
+    cL, cR = _subsystem_ops(nL), _subsystem_ops(nR)
+    dL, dR = 2 ** (2 * nL), 2 ** (2 * nR)
+    PL = np.diag([(-1.0) ** bin(k).count("1") for k in range(dL)])
+    IL, IR = np.eye(dL), np.eye(dR)
+
+    def c(site, spin):
+        if site in ls:
+            return np.kron(cL[spin * nL + ls.index(site)], IR)
+        return np.kron(PL, cR[spin * nR + rs.index(site)])
+
+    H = np.zeros((dL * dR, dL * dR))
+    for b, (i, j) in enumerate(model.bonds):
+        for sp in range(2):
+            H += -model.t[b] * (c(i, sp).T @ c(j, sp) + c(j, sp).T @ c(i, sp))
+        if model.v is not None:
+            ni = c(i, 0).T @ c(i, 0) + c(i, 1).T @ c(i, 1)
+            nj = c(j, 0).T @ c(j, 0) + c(j, 1).T @ c(j, 1)
+            H += model.v[b] * ni @ nj
+    for s in range(S):
+        H += model.u[s] * (c(s, 0).T @ c(s, 0)) @ (c(s, 1).T @ c(s, 1))
+    return H, ls, rs
+
+
+@pytest.mark.parametrize("seed,L,mask", [(31, 4, 0b0101), (32, 5, 0b10110), (33, 4, 0b0011), (34, 5, 0b00001),
+                                         (35, 4, 0b1111)])
+def test_spatial_hubbard_map_vs_fermionic_kron(seed, L, mask):
+    """The oracle's signed canonical -> bipartite map of the spatial Hubbard
+    cut, applied to its full-basis H, gives the block Hamiltonian of Eq. (2)
+    built from subsystem fermion operators (with the parity string of the
+    left part on every right operator), every sector and block."""
+    m = I.random_extended_hubbard_model(np.random.default_rng(seed), L, n_bonds=min(L * (L - 1) // 2, 2 * L))
+    Hk, ls, rs = bipartite_hubbard_kron(m, mask)
+    nL, nR = len(ls), len(rs)
+    dR_full = 2 ** (2 * nR)
+    for nu in range(L + 1):
+        for nd in range(L + 1):
+            s = O.Sector(m, nu, nd)
+            pos, sign, blocks = s.bipartite_signed(mask)
+            # Kronecker index of every bipartite position, block by block
+            kidx = np.empty(s.n, dtype=np.int64)
+            for a, b, d_l, d_r, off in blocks:
+                lw = [w for w in range(2 ** (2 * nL)) if bin(w >> nL).count("1") == a and bin(w & ((1 << nL) - 1)).count("1") == b]
+                rw = [w for w in range(2 ** (2 * nR)) if bin(w >> nR).count("1") == nu - a and bin(w & ((1 << nR) - 1)).count("1") == nd - b]
+                assert len(lw) == d_l and len(rw) == d_r
+                # subsystem word (up << n) | dn  ->  Jordan-Wigner index up | dn << n
+                jl = [(w >> nL) | ((w & ((1 << nL) - 1)) << nL) for w in lw]
+                jr = [(w >> nR) | ((w & ((1 << nR) - 1)) << nR) for w in rw]
+                for r_i, l in enumerate(jl):
+                    kidx[off + r_i * d_r: off + (r_i + 1) * d_r] = np.asarray(jl[r_i]) * dR_full + np.asarray(jr)
+            Hc = s.dense()
+            Hb = np.zeros_like(Hc)
+            Hb[np.ix_(pos, pos)] = Hc * np.outer(sign, sign)
+            np.testing.assert_allclose(Hb, Hk[np.ix_(kidx, kidx)], atol=1e-13, rtol=0, err_msg=f"{nu},{nd}")

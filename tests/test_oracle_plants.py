@@ -24,6 +24,8 @@ PLANTS = {
     6: "wrong sign of the beta term in Lanczos",
     7: "Lanczos stops after one step within tol instead of three",
     8: "c+ / c of one mode without its fermion sign",
+    9: "bond density interaction V dropped",
+    10: "spatial Hubbard cut without the reordering sign",
 }
 
 
