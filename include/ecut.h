@@ -70,7 +70,7 @@ enum {
  *                   S = sigma/2, i = bond_i[b], j = bond_j[b]; site i = bit i
  *                   of the occupation word, spin up = bit set.  t, u unused.
  *   ECUT_HUBBARD:   H = -sum_b t[b] sum_s (c+_{i s} c_{j s} + h.c.)
- *                       + sum_i u[i] n_{i up} n_{i dn}.
+ *                       + sum_i u[i] n_{i up} n_{i dn} + sum_b v[b] n_i n_j.
  *                   Fermion order: all up modes, then all down modes, each by
  *                   increasing site.  u may be NULL (all zero).  jxy, jz unused.
  * Arrays are read during ecut_build_sectors only.
@@ -86,6 +86,8 @@ typedef struct ecut_model_desc {
     const double *jz;         /* [n_bonds] spin */
     const double *t;          /* [n_bonds] Hubbard */
     const double *u;          /* [n_sites] Hubbard, nullable */
+    const double *v;          /* [n_bonds] Hubbard: + v[b] n_i n_j with n = n_up + n_dn (the extended
+                                 model); nullable; nonzero only with a spatial cut */
 } ecut_model_desc;
 
 /*
@@ -93,6 +95,17 @@ typedef struct ecut_model_desc {
  *   ECUT_CUT_SPATIAL (spin): L = sites whose bit is set in left_mask, R = the
  *       rest; subsystem word bit k = k-th site of that part in increasing
  *       site order.  Both parts need 1..32 sites.
+ *   ECUT_CUT_SPATIAL (Hubbard, the real-space cut of Fig. 1(b)): L and R as
+ *       above, at most 16 sites each; a subsystem word is (up << n) | dn
+ *       over its n sites; blocks are (N_up_L, N_dn_L) in lexicographic order
+ *       (ecut_sectors_labels), rows and columns the words of the block's
+ *       numbers in increasing integer order.  The bipartite basis state
+ *       |l, r> orders the creation operators of l's modes (up modes by site,
+ *       then down modes) before r's, so the layout map carries a fermion
+ *       sign (ecut_canonical_signs; ecut_import and ecut_export apply it).
+ *       Hops across the cut are the sector-changing cross terms
+ *       -t (c+_i (x) c_j + h.c.) with the left parity string, v[b] across
+ *       the cut a diagonal cross term.  The generic row kernel applies it.
  *   ECUT_CUT_UPDN (Hubbard): the cut in the spin-group space of Fig. 1(c):
  *       L = up-spin occupation word, R = down-spin word; one block
  *       (N_up, N_dn); left_mask unused.  The Hubbard H then has the diagonal
@@ -169,6 +182,18 @@ ecut_status ecut_sectors_words(const ecut_sectors *s, int32_t block,
  * (full occupation words in increasing integer order; Hubbard word =
  * (up << n_sites) | dn).  Host array of dim entries.  Host only. */
 ecut_status ecut_canonical_positions(const ecut_sectors *s, int64_t *pos);
+
+/* sign[i] = +-1 with bip[pos[i]] = sign[i] * canon[i]: the parity of the
+ * reordering of the i-th word's fermion modes from the canonical order to
+ * the bipartite order (spatial Hubbard cut; +1 for every other problem).
+ * Host array of dim entries.  Host only. */
+ecut_status ecut_canonical_signs(const ecut_sectors *s, int8_t *sign);
+
+/* labels: host int32 array of n_blocks x 4 entries (N_L, N_L2, N_R, N_R2):
+ * the particle numbers of each block's two parts (spin models and the
+ * up/down cut: N_L2 = N_R2 = 0 and N_L, N_R = q_l, q_r; spatial Hubbard cut:
+ * up-spin and down-spin numbers). */
+ecut_status ecut_sectors_labels(const ecut_sectors *s, int32_t *labels);
 
 /* Permute a device vector between canonical order and the bipartite layout
  * (bip[pos[i]] = canon[i] and back).  In and out must not overlap. */

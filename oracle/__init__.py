@@ -308,9 +308,16 @@ def entanglement(sector, psi, cut_kind, left_mask=0, parts=None, cutoff=1e-14):
     n_eff = 1/sum (chi_q/sum chi)^2, weight_ipr = 1/sum W_q^2, entropy, and
     w_p[p] = sum_{q in part p} W_q^2 when parts (block -> part) is given."""
     psi = np.asarray(psi, dtype=np.float64)
-    pos, blocks = sector.bipartite(cut_kind, left_mask)
     flat = np.empty_like(psi)
-    flat[pos] = psi
+    if sector.model.kind == "hubbard" and cut_kind == "spatial":
+        # fermion modes split by site: the signed map of the two parts'
+        # ordered products (blocks labelled by (N_up_L, N_dn_L))
+        pos, sign, b5 = sector.bipartite_signed(left_mask)
+        flat[pos] = sign * psi
+        blocks = b5[:, [0, 2, 3, 4]]
+    else:
+        pos, blocks = sector.bipartite(cut_kind, left_mask)
+        flat[pos] = psi
     norm2 = float(psi @ psi)
     lam = []
     for q_l, d_l, d_r, off in blocks:

@@ -890,8 +890,78 @@ ecut_status ecut_sectors_words(const ecut_sectors *s, int32_t block, uint32_t *l
     return ECUT_OK;
 }
 
+// Position and fermion sign of every canonical index of a spatial Hubbard
+// cut, on the host's threads (the layout map of the device kernel).
+static void hubsp_positions(const ecut_sectors *s, int64_t *pos, int8_t *sign) {
+    const int nL = (int)s->lsites.size(), nR = (int)s->rsites.size();
+    uint32_t lmask = 0, rmask = 0;
+    for (int k : s->lsites) lmask |= 1u << k;
+    for (int k : s->rsites) rmask |= 1u << k;
+    const int64_t nd_words = (int64_t)binom(s->n_sites, s->n_dn);
+    const int la0 = s->blocks.front().q_l, lb0 = s->blocks.front().q_l2;
+    const int nb_b = s->blocks.back().q_l2 - lb0 + 1;
+    auto compact = [](uint32_t w, uint32_t mask) {
+        uint32_t out = 0;
+        int k = 0;
+        for (uint32_t m = mask; m; m &= m - 1u, ++k) out |= ((w >> __builtin_ctz(m)) & 1u) << k;
+        return out;
+    };
+    auto work = [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const uint32_t up = (uint32_t)colex_unrank(i / nd_words, s->n_up);
+            const uint32_t dn = (uint32_t)colex_unrank(i % nd_words, s->n_dn);
+            const uint32_t ul = compact(up, lmask), dl = compact(dn, lmask), ur = compact(up, rmask),
+                           dr = compact(dn, rmask);
+            const int a = __builtin_popcount(ul), b = __builtin_popcount(dl);
+            const BlockDev &B = s->blocks[(size_t)((a - la0) * nb_b + (b - lb0))];
+            const int64_t row = colex_rank(ul) * (int64_t)binom(nL, b) + colex_rank(dl);
+            const int64_t col = colex_rank(ur) * (int64_t)binom(nR, s->n_dn - b) + colex_rank(dr);
+            if (pos) pos[i] = B.offset + row * B.d_r + col;
+            if (sign) {
+                int par = __builtin_popcount(ur) * b;
+                for (uint32_t m = lmask; m; m &= m - 1u) {
+                    const uint32_t below = (m & (0u - m)) - 1u;
+                    const int sb = __builtin_ctz(m);
+                    if ((up >> sb) & 1u) par += __builtin_popcount(up & rmask & below);
+                    if ((dn >> sb) & 1u) par += __builtin_popcount(dn & rmask & below);
+                }
+                sign[i] = (par & 1) ? -1 : 1;
+            }
+        }
+    };
+    const int64_t dim = s->dim;
+    const unsigned hw = std::max(1u, std::min(64u, std::thread::hardware_concurrency()));
+    const int64_t chunk = std::max<int64_t>(1 << 14, (dim + hw - 1) / hw);
+    std::vector<std::thread> th;
+    for (int64_t i0 = 0; i0 < dim; i0 += chunk) th.emplace_back(work, i0, std::min(dim, i0 + chunk));
+    for (auto &t : th) t.join();
+}
+
+ecut_status ecut_canonical_signs(const ecut_sectors *s, int8_t *sign) {
+    if (!s || !sign) return fail(ECUT_EINVAL, "null argument");
+    if (s->hub_spatial) hubsp_positions(s, nullptr, sign);
+    else std::fill(sign, sign + s->dim, (int8_t)1);
+    return ECUT_OK;
+}
+
+ecut_status ecut_sectors_labels(const ecut_sectors *s, int32_t *labels) {
+    if (!s || !labels) return fail(ECUT_EINVAL, "null argument");
+    for (size_t b = 0; b < s->blocks.size(); ++b) {
+        const BlockDev &B = s->blocks[b];
+        labels[4 * b + 0] = B.q_l;
+        labels[4 * b + 1] = B.q_l2;
+        labels[4 * b + 2] = B.q_r;
+        labels[4 * b + 3] = B.q_r2;
+    }
+    return ECUT_OK;
+}
+
 ecut_status ecut_canonical_positions(const ecut_sectors *s, int64_t *pos) {
     if (!s || !pos) return fail(ECUT_EINVAL, "null argument");
+    if (s->hub_spatial) {
+        hubsp_positions(s, pos, nullptr);
+        return ECUT_OK;
+    }
     if (s->kind == ECUT_HUBBARD) {
         // canonical index = up rank * d_R + down rank (up-major integer order)
         const int64_t dR = s->blocks[0].d_r;
@@ -936,6 +1006,24 @@ static ecut_status check_dev(const ecut_sectors *s) {
     return ECUT_OK;
 }
 
+static HubSpPerm hubsp_perm(const ecut_sectors *s, const uint64_t *binom_d) {
+    HubSpPerm A{};
+    A.blocks = s->prob.blocks;
+    A.binom = binom_d;
+    A.dim = s->dim;
+    A.n_dn_words = (int64_t)binom(s->n_sites, s->n_dn);
+    for (int k : s->lsites) A.lmask |= 1u << k;
+    for (int k : s->rsites) A.rmask |= 1u << k;
+    A.n_up = s->n_up;
+    A.n_dn = s->n_dn;
+    A.nL = (int32_t)s->lsites.size();
+    A.nR = (int32_t)s->rsites.size();
+    A.la0 = s->blocks.front().q_l;
+    A.lb0 = s->blocks.front().q_l2;
+    A.nb_b = s->blocks.back().q_l2 - A.lb0 + 1;
+    return A;
+}
+
 static ecut_status permute(const ecut_sectors *s, const double *in, double *out, bool to_bip, void *stream) {
     ecut_status st = check_dev(s);
     if (st != ECUT_OK) return st;
@@ -943,7 +1031,12 @@ static ecut_status permute(const ecut_sectors *s, const double *in, double *out,
     if (in == out) return fail(ECUT_EINVAL, "in and out must differ");
     hipStream_t hs = (hipStream_t)stream;
     hipError_t e;
-    if (s->kind == ECUT_HUBBARD && s->hub_ok) {
+    if (s->hub_spatial) {
+        const uint64_t *bt = nullptr;
+        st = device_res(nullptr, &bt, nullptr);
+        if (st != ECUT_OK) return st;
+        e = launch_perm_hubsp(hubsp_perm(s, bt), in, out, to_bip, hs);
+    } else if (s->kind == ECUT_HUBBARD && s->hub_ok) {
         e = launch_perm_cols(s->prob.hub.col_of_rank, s->blocks[0].d_l, s->blocks[0].d_r, in, out, to_bip, hs);
     } else if (s->kind == ECUT_HUBBARD) {
         e = hipMemcpyAsync(out, in, sizeof(double) * (size_t)s->dim, hipMemcpyDeviceToDevice, hs);

@@ -31,15 +31,20 @@ uint64_t colex_unrank(int64_t idx, int k);
 struct BlockDev {
     int64_t offset;      // first element of the block in the vector
     int32_t d_l, d_r;    // block shape, row-major [l][r]
-    int32_t q_l, q_r;    // subsystem particle numbers
+    int32_t q_l, q_r;    // subsystem particle numbers (spatial Hubbard cut: up-spin numbers)
     int32_t lbase, rbase;        // first word of count q_l (q_r) in the concatenated L (R) tables
     int32_t blk_lminus, blk_lplus;   // block with q_l-1 (q_l+1), or -1
+    int32_t q_l2, q_r2;          // spatial Hubbard cut: down-spin numbers of L and R (else 0)
+    int32_t blk_l2minus, blk_l2plus; // block with q_l2-1 (q_l2+1) and the same q_l, or -1
 };
 
-// Diagonal cross term coef * f(l_i) * f(r_j); f = n (occupation) or s = n - 1/2.
+// Diagonal cross term coef * f(l) * f(r); f(l) = n_li (+ n_li2 when
+// li2 >= 0, the two spins of a site: its density), and likewise for r;
+// spin_form: f = n - 1/2 instead (spin Sz Sz).
 struct XDiagDev {
     int32_t li, rj;
-    int32_t spin_form;   // 1: s*s (spin Sz Sz), 0: n*n (Hubbard U n_up n_dn)
+    int32_t spin_form;   // 1: s*s (spin Sz Sz), 0: n*n (Hubbard U n_up n_dn, or V n_i n_j with li2/rj2)
+    int32_t li2, rj2;    // second occupation bit of the left / right factor, or -1
     int32_t pad;
     double coef;
 };
@@ -52,11 +57,19 @@ struct XDiagDev {
 //         l' = lmap_ins[l], r' = rmap_del[r]
 // Map arrays are indexed by the global (concatenated) word index and give
 // the rank inside the target count, or -1.
+//
+// Spatial Hubbard cut (fermion = 1): the same two directions for one spin of
+// a cut bond, coef (c+_{i s} c_{j s} + h.c.) with coef = -t, maps entries
+// (rank << 1) | neg where neg is the fermion sign of that side's operator
+// (the product of both sides' signs is the term's sign); label 0 moves the
+// up-spin numbers (blk_lminus / blk_lplus), label 1 the down-spin ones
+// (blk_l2minus / blk_l2plus).
 struct XBondDev {
     int32_t li, rj;
     int32_t lmap_del, lmap_ins;   // offsets into maps[]
     int32_t rmap_del, rmap_ins;
     double coef;
+    int32_t label, fermion;
 };
 
 // Tables of the Hubbard up/down kernel (row = up word a, column = down word b).
@@ -222,6 +235,18 @@ struct CdagArgs {
     int32_t site, spin, dagger, pad_;
 };
 
+// Layout map of the spatial Hubbard cut (canonical index -> block position
+// and fermion sign); blocks are (N_up_L, N_dn_L) over the rectangle
+// [la0, la0 + nb_a) x [lb0, lb0 + nb_b), lexicographic.
+struct HubSpPerm {
+    const BlockDev *blocks;
+    const uint64_t *binom;
+    int64_t dim, n_dn_words;
+    uint32_t lmask, rmask;
+    int32_t n_up, n_dn, nL, nR;
+    int32_t la0, lb0, nb_b, pad_;
+};
+
 // Work item of the segment-tile kernel: up segment, down segment (global
 // index), down class; slot = index in the order-independent item list.
 // useg < 0 marks padding.
@@ -308,6 +333,7 @@ struct ecut_sectors {
     std::vector<ecut::XBondDev> xbond;
     std::vector<int32_t> maps;
     int32_t n_cut_bonds = 0;
+    bool hub_spatial = false;            // Hubbard model with a spatial cut (signed layout map)
     // Hubbard up/down kernel tables (host copies)
     bool hub_ok = false;
     bool hub2_ok = false;

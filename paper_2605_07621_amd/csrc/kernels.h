@@ -128,6 +128,8 @@ hipError_t launch_perm_cols(const int32_t *col_d, int64_t n_rows, int dR, const 
 hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
                        double *out, bool to_bip, hipStream_t st);
 hipError_t launch_cdag(const CdagArgs &A, hipStream_t st);
+// canonical <-> bipartite layout of the spatial Hubbard cut (with signs)
+hipError_t launch_perm_hubsp(const HubSpPerm &A, const double *in, double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);
 hipError_t launch_axpy_norm(const VecJob *jobs_d, const int32_t *chunk_job_d, const int32_t *chunk_idx_d, int n_chunks,
                             hipStream_t st);

@@ -104,6 +104,8 @@ __global__ __launch_bounds__(ROWS_THREADS) void k_rows(const ProblemDev *__restr
             for (int k = 0; k < P.n_xdiag; ++k) {
                 const XDiagDev X = P.xdiag[k];
                 double fl = (double)((lw >> X.li) & 1u), fr = (double)((rw >> X.rj) & 1u);
+                if (X.li2 >= 0) fl += (double)((lw >> X.li2) & 1u);
+                if (X.rj2 >= 0) fr += (double)((rw >> X.rj2) & 1u);
                 if (X.spin_form) { fl -= 0.5; fr -= 0.5; }
                 dg += X.coef * fl * fr;
             }
@@ -115,17 +117,23 @@ __global__ __launch_bounds__(ROWS_THREADS) void k_rows(const ProblemDev *__restr
                 const XBondDev X = P.xbond[k];
                 int src, lp, rp;
                 if ((lw >> X.li) & 1u) {
-                    src = B.blk_lminus;
+                    src = X.label ? B.blk_l2minus : B.blk_lminus;
                     lp = P.maps[X.lmap_del + gl];
                     rp = P.maps[X.rmap_ins + gr];
                 } else {
-                    src = B.blk_lplus;
+                    src = X.label ? B.blk_l2plus : B.blk_lplus;
                     lp = P.maps[X.lmap_ins + gl];
                     rp = P.maps[X.rmap_del + gr];
                 }
                 if (src >= 0 && lp >= 0 && rp >= 0) {
                     const BlockDev S = P.blocks[src];
-                    acc += X.coef * P.x[S.offset + (int64_t)lp * S.d_r + rp];
+                    double c = X.coef;
+                    if (X.fermion) {   // (rank << 1) | sign of each side
+                        if ((lp ^ rp) & 1) c = -c;
+                        lp >>= 1;
+                        rp >>= 1;
+                    }
+                    acc += c * P.x[S.offset + (int64_t)lp * S.d_r + rp];
                 }
             }
             double yv = ef.x * acc;
@@ -1722,6 +1730,69 @@ __global__ __launch_bounds__(256) void k_cdag(const CdagArgs A) {
         }
         A.y[i] = v;
     }
+}
+
+// colex unrank: the idx-th word with k set bits
+__device__ __forceinline__ uint32_t colex_unrank_dev(int64_t idx, int k, const uint64_t *__restrict__ binom) {
+    uint32_t w = 0;
+    for (int j = k; j >= 1; --j) {
+        int p = j - 1;
+        while ((int64_t)binom[(p + 1) * 65 + j] <= idx) ++p;
+        w |= 1u << p;
+        idx -= (int64_t)binom[p * 65 + j];
+    }
+    return w;
+}
+
+// bits of w at the set positions of mask, packed to the low bits in order
+__device__ __forceinline__ uint32_t compact_dev(uint32_t w, uint32_t mask) {
+    uint32_t out = 0;
+    int k = 0;
+    for (uint32_t m = mask; m; m &= m - 1u, ++k) out |= ((w >> (__ffs(m) - 1)) & 1u) << k;
+    return out;
+}
+
+// canonical <-> bipartite layout of the spatial Hubbard cut (see
+// build_hubbard_spatial): position of the canonical index and the parity of
+// reordering its modes from (all up, all down) to (L up, L down, R up,
+// R down): every R up particle below an L up particle, every R down particle
+// below an L down particle, and every (R up, L down) pair.
+__global__ __launch_bounds__(256) void k_perm_hubsp(const HubSpPerm A, const double *__restrict__ in,
+                                                    double *__restrict__ out, int to_bip) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.dim; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t iu = i / A.n_dn_words, id = i - iu * A.n_dn_words;
+        const uint32_t up = colex_unrank_dev(iu, A.n_up, A.binom), dn = colex_unrank_dev(id, A.n_dn, A.binom);
+        const uint32_t ul = compact_dev(up, A.lmask), dl = compact_dev(dn, A.lmask);
+        const uint32_t ur = compact_dev(up, A.rmask), dr = compact_dev(dn, A.rmask);
+        const int a = __popc(ul), b = __popc(dl);
+        const int q = (a - A.la0) * A.nb_b + (b - A.lb0);
+        const BlockDev B = A.blocks[q];
+        const int64_t row = colex_rank_dev(ul, A.binom) * (int64_t)A.binom[A.nL * 65 + b] + colex_rank_dev(dl, A.binom);
+        const int64_t col = colex_rank_dev(ur, A.binom) * (int64_t)A.binom[A.nR * 65 + (A.n_dn - b)] +
+                            colex_rank_dev(dr, A.binom);
+        const int64_t pos = B.offset + row * B.d_r + col;
+        int par = __popc(ur) * b;
+        for (uint32_t m = A.lmask; m; m &= m - 1u) {
+            const uint32_t below = (m & (0u - m)) - 1u;   // sites below this L site
+            const int site_bit = __ffs(m) - 1;
+            if ((up >> site_bit) & 1u) par += __popc(up & A.rmask & below);
+            if ((dn >> site_bit) & 1u) par += __popc(dn & A.rmask & below);
+        }
+        if (to_bip) {
+            const double v = in[i];
+            out[pos] = (par & 1) ? -v : v;
+        } else {
+            const double v = in[pos];
+            out[i] = (par & 1) ? -v : v;
+        }
+    }
+}
+
+hipError_t launch_perm_hubsp(const HubSpPerm &A, const double *in, double *out, bool to_bip, hipStream_t st) {
+    if (A.dim == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((A.dim + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_perm_hubsp, dim3((unsigned)blocks), dim3(256), 0, st, A, in, out, to_bip ? 1 : 0);
+    return hipGetLastError();
 }
 
 hipError_t launch_cdag(const CdagArgs &A, hipStream_t st) {

@@ -145,6 +145,199 @@ static void build_hub6_tables(ecut_sectors *s, const ecut_model_desc *m);
 void make_row_order(const ecut_sectors *s, int order, std::vector<int32_t> &out);
 void make_hub_item_order(const ecut_sectors *s, int order, std::vector<HubItem> &out);
 
+// Hubbard model with a spatial cut (the paper's Fig. 1(b)): L = the sites
+// of left_mask, R = the others.  A subsystem word is (up << n) | dn over the
+// subsystem's n sites in site order; the bipartite basis state |l, r> is the
+// ordered product of the creation operators of l's occupied modes (up modes
+// by site, then down modes by site), then r's, on the vacuum.  Blocks are
+// (N_up_L, N_dn_L) in lexicographic order; rows (columns) are the L (R)
+// words of the block's numbers in increasing integer order, so the rank of
+// a word inside its group is rank(up) * C(n, N_dn) + rank(dn).
+//  - hops inside L or inside R: CSR rows of H_L, H_R with the sign of the
+//    same-spin particles of that part strictly between the two sites;
+//  - U_i and V_b inside a part: the part's diagonal;
+//  - hops across the cut: per bond and spin the two directions of
+//    -t (c+_i c_j + h.c.), i in L: gathering (l, r) from (l - i, r + j) the
+//    sign is (-1)^(N_L(l) - 1 + occ_before_i(l)) * (-1)^(occ_before_j(r)),
+//    from (l + i, r - j) it is (-1)^(N_L(l) + occ_before_i(l)) *
+//    (-1)^(occ_before_j(r)) (the right operator passes every left
+//    particle; occ_before counts the part's occupied modes before the mode
+//    in the part's order);
+//  - V_b across the cut: a diagonal cross term of the two site densities.
+static ecut_status build_hubbard_spatial(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qnum q,
+                                         ecut_sectors *s, Sub &L, Sub &R) {
+    const int S = m->n_sites;
+    if (S > 32) return fail(ECUT_EUNSUPPORTED, "Hubbard models up to 32 sites");
+    if (m->n_bonds > 0 && !m->t) return fail(ECUT_EINVAL, "Hubbard model needs t");
+    const uint64_t full = S == 64 ? ~0ull : ((1ull << S) - 1);
+    if (c->left_mask & ~full) return fail(ECUT_EINVAL, "left_mask names sites beyond n_sites");
+    if (q.n_up < 0 || q.n_up > S || q.n_dn < 0 || q.n_dn > S) return fail(ECUT_EINVAL, "particle numbers outside 0..n_sites");
+    s->lsites.clear();
+    s->rsites.clear();
+    for (int i = 0; i < S; ++i) ((c->left_mask >> i) & 1u ? s->lsites : s->rsites).push_back(i);
+    const int nL = (int)s->lsites.size(), nR = (int)s->rsites.size();
+    if (nL > 16 || nR > 16) return fail(ECUT_EUNSUPPORTED, "spatial Hubbard cuts need at most 16 sites on each side");
+    std::vector<int> side(S), loc(S);
+    for (int k = 0; k < nL; ++k) { side[s->lsites[k]] = 0; loc[s->lsites[k]] = k; }
+    for (int k = 0; k < nR; ++k) { side[s->rsites[k]] = 1; loc[s->rsites[k]] = k; }
+    const int Nu = q.n_up, Nd = q.n_dn;
+    // groups of subsystem words by (up, down) numbers
+    auto groups = [](Sub &X, int n, int a0, int a1, int b0, int b1, std::map<std::pair<int, int>, int32_t> &base) {
+        X.n = 2 * n;
+        X.words.clear();
+        for (int a = a0; a <= a1; ++a)
+            for (int b = b0; b <= b1; ++b) {
+                base[{a, b}] = (int32_t)X.words.size();
+                const int64_t nu = (int64_t)binom(n, a), nd = (int64_t)binom(n, b);
+                for (int64_t i = 0; i < nu; ++i)
+                    for (int64_t k = 0; k < nd; ++k)
+                        X.words.push_back(((uint32_t)colex_unrank(i, a) << n) | (uint32_t)colex_unrank(k, b));
+            }
+        X.rows.assign(X.words.size(), {});
+        X.diag.assign(X.words.size(), 0.0);
+    };
+    const int la0 = std::max(0, Nu - nR), la1 = std::min(nL, Nu), lb0 = std::max(0, Nd - nR), lb1 = std::min(nL, Nd);
+    if (la0 > la1 || lb0 > lb1) return fail(ECUT_EINVAL, "empty sector");
+    std::map<std::pair<int, int>, int32_t> lbase, rbase;
+    groups(L, nL, la0, la1, lb0, lb1, lbase);
+    groups(R, nR, Nu - la1, Nu - la0, Nd - lb1, Nd - lb0, rbase);
+    L.cmin = R.cmin = 0;
+    L.cmax = R.cmax = -1;
+    // blocks
+    s->blocks.clear();
+    std::map<std::pair<int, int>, int32_t> bidx;
+    int64_t off = 0;
+    for (int a = la0; a <= la1; ++a)
+        for (int b = lb0; b <= lb1; ++b) {
+            BlockDev B{};
+            B.offset = off;
+            B.q_l = a;
+            B.q_l2 = b;
+            B.q_r = Nu - a;
+            B.q_r2 = Nd - b;
+            B.d_l = (int32_t)(binom(nL, a) * binom(nL, b));
+            B.d_r = (int32_t)(binom(nR, Nu - a) * binom(nR, Nd - b));
+            B.lbase = lbase[{a, b}];
+            B.rbase = rbase[{Nu - a, Nd - b}];
+            bidx[{a, b}] = (int32_t)s->blocks.size();
+            off += (int64_t)B.d_l * B.d_r;
+            s->blocks.push_back(B);
+        }
+    for (BlockDev &B : s->blocks) {
+        auto nb = [&](int a, int b) {
+            auto it = bidx.find({a, b});
+            return it == bidx.end() ? -1 : it->second;
+        };
+        B.blk_lminus = nb(B.q_l - 1, B.q_l2);
+        B.blk_lplus = nb(B.q_l + 1, B.q_l2);
+        B.blk_l2minus = nb(B.q_l, B.q_l2 - 1);
+        B.blk_l2plus = nb(B.q_l, B.q_l2 + 1);
+    }
+    s->dim = off;
+    // rank of a subsystem word inside its (up, down) group
+    auto grank = [](uint32_t w, int n) -> int32_t {
+        const uint32_t dn = w & ((1u << n) - 1u), up = w >> n;
+        return (int32_t)(colex_rank(up) * (int64_t)binom(n, __builtin_popcount(dn)) + colex_rank(dn));
+    };
+    // occupied modes of a part before mode (spin, k) in the part's order
+    auto occ_before = [](uint32_t w, int n, int spin, int k) -> int {
+        const uint32_t dn = w & ((1u << n) - 1u), up = w >> n;
+        const uint32_t below = (1u << k) - 1u;
+        return spin == 0 ? __builtin_popcount(up & below) : __builtin_popcount(up) + __builtin_popcount(dn & below);
+    };
+    auto density = [](uint32_t w, int n, int k) { return (int)((w >> (n + k)) & 1u) + (int)((w >> k) & 1u); };
+    // operators inside the two parts
+    for (int part = 0; part < 2; ++part) {
+        Sub &X = part == 0 ? L : R;
+        const int n = part == 0 ? nL : nR;
+        for (size_t g = 0; g < X.words.size(); ++g) {
+            const uint32_t w = X.words[g];
+            for (int k = 0; k < n; ++k) {
+                const int site = part == 0 ? s->lsites[k] : s->rsites[k];
+                if (m->u && ((w >> (n + k)) & 1u) && ((w >> k) & 1u)) X.diag[g] += m->u[site];
+            }
+        }
+        for (int b = 0; b < m->n_bonds; ++b) {
+            const int i = m->bond_i[b], j = m->bond_j[b];
+            if (side[i] != part || side[j] != part) continue;
+            const int li = loc[i], lj = loc[j];
+            const double t = m->t[b], v = m->v ? m->v[b] : 0.0;
+            for (size_t g = 0; g < X.words.size(); ++g) {
+                const uint32_t w = X.words[g];
+                if (v != 0.0) X.diag[g] += v * density(w, n, li) * density(w, n, lj);
+                if (t == 0.0) continue;
+                const uint32_t dn = w & ((1u << n) - 1u), up = w >> n;
+                uint32_t w2;
+                int sg;
+                if (fermion_hop(up, li, lj, w2, sg)) X.rows[g].push_back({grank((w2 << n) | dn, n), -t * sg});
+                if (fermion_hop(dn, li, lj, w2, sg)) X.rows[g].push_back({grank((up << n) | w2, n), -t * sg});
+            }
+        }
+    }
+    // across the cut
+    s->xdiag.clear();
+    s->xbond.clear();
+    s->maps.clear();
+    s->n_cut_bonds = 0;
+    auto has_group = [](const std::map<std::pair<int, int>, int32_t> &base, uint32_t w, int n) {
+        return base.count({__builtin_popcount(w >> n), __builtin_popcount(w & ((1u << n) - 1u))}) != 0;
+    };
+    for (int b = 0; b < m->n_bonds; ++b) {
+        int i = m->bond_i[b], j = m->bond_j[b];
+        if (side[i] == side[j]) continue;
+        if (side[i] == 1) std::swap(i, j);   // i in L, j in R
+        ++s->n_cut_bonds;
+        const int li = loc[i], rj = loc[j];
+        const double v = m->v ? m->v[b] : 0.0;
+        if (v != 0.0) s->xdiag.push_back(XDiagDev{nL + li, nR + rj, 0, li, rj, 0, v});
+        if (m->t[b] == 0.0) continue;
+        for (int spin = 0; spin < 2; ++spin) {
+            XBondDev X{};
+            X.li = spin == 0 ? nL + li : li;
+            X.rj = spin == 0 ? nR + rj : rj;
+            X.coef = -m->t[b];
+            X.label = spin;
+            X.fermion = 1;
+            const uint32_t lbit = 1u << X.li, rbit = 1u << X.rj;
+            X.lmap_del = (int32_t)s->maps.size();
+            for (uint32_t w : L.words) {   // target has mode i: source l - i
+                int32_t e = -1;
+                if ((w & lbit) && has_group(lbase, w ^ lbit, nL)) {
+                    const int par = __builtin_popcount(w) - 1 + occ_before(w, nL, spin, li);
+                    e = (grank(w ^ lbit, nL) << 1) | (par & 1);
+                }
+                s->maps.push_back(e);
+            }
+            X.lmap_ins = (int32_t)s->maps.size();
+            for (uint32_t w : L.words) {   // target lacks mode i: source l + i
+                int32_t e = -1;
+                if (!(w & lbit) && has_group(lbase, w | lbit, nL)) {
+                    const int par = __builtin_popcount(w) + occ_before(w, nL, spin, li);
+                    e = (grank(w | lbit, nL) << 1) | (par & 1);
+                }
+                s->maps.push_back(e);
+            }
+            X.rmap_ins = (int32_t)s->maps.size();
+            for (uint32_t w : R.words) {   // source r + j
+                int32_t e = -1;
+                if (!(w & rbit) && has_group(rbase, w | rbit, nR))
+                    e = (grank(w | rbit, nR) << 1) | (occ_before(w, nR, spin, rj) & 1);
+                s->maps.push_back(e);
+            }
+            X.rmap_del = (int32_t)s->maps.size();
+            for (uint32_t w : R.words) {   // source r - j
+                int32_t e = -1;
+                if ((w & rbit) && has_group(rbase, w ^ rbit, nR))
+                    e = (grank(w ^ rbit, nR) << 1) | (occ_before(w, nR, spin, rj) & 1);
+                s->maps.push_back(e);
+            }
+            s->xbond.push_back(X);
+        }
+    }
+    s->hub_spatial = true;
+    return ECUT_OK;
+}
+
 ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qnum q, ecut_sectors *s) {
     if (!m || !c) return fail(ECUT_EINVAL, "null model or cut");
     if (m->reserved != 0 || c->reserved != 0) return fail(ECUT_EINVAL, "reserved fields must be 0");
@@ -197,6 +390,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
             B.rbase = R.base(B.q_r);
             B.blk_lminus = ql > qmin ? (int32_t)s->blocks.size() - 1 : -1;
             B.blk_lplus = ql < qmax ? (int32_t)s->blocks.size() + 1 : -1;
+            B.blk_l2minus = B.blk_l2plus = -1;
             off += (int64_t)B.d_l * B.d_r;
             s->blocks.push_back(B);
         }
@@ -237,7 +431,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
                 ++s->n_cut_bonds;
                 int li = side[i] == 0 ? loc[i] : loc[j];
                 int rj = side[i] == 0 ? loc[j] : loc[i];
-                if (jz != 0.0) s->xdiag.push_back(XDiagDev{li, rj, 1, 0, jz});
+                if (jz != 0.0) s->xdiag.push_back(XDiagDev{li, rj, 1, -1, -1, 0, jz});
                 if (jxy != 0.0) {
                     XBondDev X{};
                     X.li = li;
@@ -255,10 +449,16 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
         // one source row of a left site once for all its bonds
         std::stable_sort(s->xbond.begin(), s->xbond.end(),
                          [](const XBondDev &a, const XBondDev &b) { return a.li < b.li; });
+    } else if (c->kind == ECUT_CUT_SPATIAL) {
+        ecut_status st = build_hubbard_spatial(m, c, q, s, L, R);
+        if (st != ECUT_OK) return st;
     } else {
-        if (c->kind != ECUT_CUT_UPDN)
-            return fail(ECUT_EUNSUPPORTED, "Hubbard models take the up/down cut (spatial fermionic cut not built)");
+        if (c->kind != ECUT_CUT_UPDN) return fail(ECUT_EINVAL, "unknown cut kind");
         if (m->n_sites > 32) return fail(ECUT_EUNSUPPORTED, "Hubbard models up to 32 sites");
+        if (m->v)
+            for (int b = 0; b < m->n_bonds; ++b)
+                if (m->v[b] != 0.0)
+                    return fail(ECUT_EUNSUPPORTED, "the bond interaction V is built for the spatial cut only");
         if (m->n_bonds > 0 && !m->t) return fail(ECUT_EINVAL, "Hubbard model needs t");
         int Ls = m->n_sites;
         if (q.n_up < 0 || q.n_up > Ls || q.n_dn < 0 || q.n_dn > Ls)
@@ -276,7 +476,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
         B.d_r = (int32_t)binom(Ls, q.n_dn);
         B.lbase = 0;
         B.rbase = 0;
-        B.blk_lminus = B.blk_lplus = -1;
+        B.blk_lminus = B.blk_lplus = B.blk_l2minus = B.blk_l2plus = -1;
         s->blocks.assign(1, B);
         s->dim = (int64_t)B.d_l * B.d_r;
         for (Sub *S : {&L, &R}) {
@@ -298,7 +498,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
         s->n_cut_bonds = 0;
         if (m->u)
             for (int i = 0; i < Ls; ++i)
-                if (m->u[i] != 0.0) s->xdiag.push_back(XDiagDev{i, i, 0, 0, m->u[i]});
+                if (m->u[i] != 0.0) s->xdiag.push_back(XDiagDev{i, i, 0, -1, -1, 0, m->u[i]});
     }
 
     s->lcmin = L.cmin;
@@ -345,7 +545,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
     s->hub_ok = false;
     s->kernel = 2;
     build_spin_tables(s);
-    if (s->kind == ECUT_HUBBARD) build_hub_tables(s, m);
+    if (s->kind == ECUT_HUBBARD && s->cut_kind == ECUT_CUT_UPDN) build_hub_tables(s, m);
     return ECUT_OK;
 }
 

@@ -92,7 +92,7 @@ struct Request {
     uint64_t seed = 0;
     double not_before = 0.0, t_submit = 0.0;
     std::vector<int32_t> bi, bj;
-    std::vector<double> jxy, jz, t, u;
+    std::vector<double> jxy, jz, t, u, v;
     // sectors built ahead of admission by the helper thread (or kept while
     // the request waits for memory); state 0 not built, 1 building, 2 built
     ecut_sectors *built = nullptr;
@@ -109,12 +109,14 @@ struct Request {
         if (m.jz) jz.assign(m.jz, m.jz + m.n_bonds);
         if (m.t) t.assign(m.t, m.t + m.n_bonds);
         if (m.u) u.assign(m.u, m.u + m.n_sites);
+        if (m.v) v.assign(m.v, m.v + m.n_bonds);
         model.bond_i = bi.data();
         model.bond_j = bj.data();
         model.jxy = m.jxy ? jxy.data() : nullptr;
         model.jz = m.jz ? jz.data() : nullptr;
         model.t = m.t ? t.data() : nullptr;
         model.u = m.u ? u.data() : nullptr;
+        model.v = m.v ? v.data() : nullptr;
     }
 };
 

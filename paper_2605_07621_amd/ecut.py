@@ -35,7 +35,7 @@ _i32, _i64, _u32, _u64, _dbl, _sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_uin
 
 class ModelDesc(ctypes.Structure):
     _fields_ = [("kind", _i32), ("n_sites", _i32), ("n_bonds", _i32), ("reserved", _i32),
-                ("bond_i", _vp), ("bond_j", _vp), ("jxy", _vp), ("jz", _vp), ("t", _vp), ("u", _vp)]
+                ("bond_i", _vp), ("bond_j", _vp), ("jxy", _vp), ("jz", _vp), ("t", _vp), ("u", _vp), ("v", _vp)]
 
 
 class CutDesc(ctypes.Structure):
@@ -98,6 +98,8 @@ SYMBOLS = [
     ("ecut_sectors_blocks", _i32, [_vp, _vp]),
     ("ecut_sectors_words", _i32, [_vp, _i32, _vp, _vp]),
     ("ecut_canonical_positions", _i32, [_vp, _vp]),
+    ("ecut_canonical_signs", _i32, [_vp, _vp]),
+    ("ecut_sectors_labels", _i32, [_vp, _vp]),
     ("ecut_import", _i32, [_vp, _vp, _vp, _vp]),
     ("ecut_export", _i32, [_vp, _vp, _vp, _vp]),
     ("ecut_apply_H", _i32, [_vp, _vp, _vp, _vp]),
@@ -182,17 +184,19 @@ class _ModelArgs:
         if model.kind == "spin":
             self.jxy = np.ascontiguousarray(model.jxy, dtype=np.float64)
             self.jz = np.ascontiguousarray(model.jz, dtype=np.float64)
-            self.t = self.u = None
+            self.t = self.u = self.v = None
             kind = ECUT_SPIN_HALF
         elif model.kind == "hubbard":
             self.t = np.ascontiguousarray(model.t, dtype=np.float64)
             self.u = None if model.u is None else np.ascontiguousarray(model.u, dtype=np.float64)
+            v = getattr(model, "v", None)
+            self.v = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
             self.jxy = self.jz = None
             kind = ECUT_HUBBARD
         else:
             raise ValueError(f"unknown model kind {model.kind!r}")
         self.m = ModelDesc(kind, int(model.n_sites), nb, 0, p(self.bi), p(self.bj), p(self.jxy), p(self.jz),
-                           p(self.t), p(self.u))
+                           p(self.t), p(self.u), p(self.v))
         ck = {"spatial": ECUT_CUT_SPATIAL, "updn": ECUT_CUT_UPDN}.get(cut.kind)
         if ck is None:
             raise ValueError(f"unknown cut kind {cut.kind!r}")
@@ -245,6 +249,16 @@ class Sectors:
         pos = np.empty(self.dim, dtype=np.int64)
         _check(lib().ecut_canonical_positions(self.h, pos.ctypes.data))
         return pos
+
+    def canonical_signs(self):
+        sg = np.empty(self.dim, dtype=np.int8)
+        _check(lib().ecut_canonical_signs(self.h, _vp(sg.ctypes.data)))
+        return sg
+
+    def labels(self):
+        lab = np.empty((self.info.n_blocks, 4), dtype=np.int32)
+        _check(lib().ecut_sectors_labels(self.h, _vp(lab.ctypes.data)))
+        return lab
 
     def import_(self, canon, out=None, stream=None):
         import torch

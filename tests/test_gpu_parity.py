@@ -1045,3 +1045,80 @@ def test_green_function_vs_oracle(dev, site, spin, dagger):
     assert np.max(np.abs(G - G_ref)) <= 1e-6 * np.max(np.abs(G_ref)), np.max(np.abs(G - G_ref))
     # the library's continued fraction on the oracle's coefficients is the oracle's
     np.testing.assert_allclose(E.continued_fraction(a_ref, b_ref, w_ref, e0, dagger, omega, 0.5), G_ref, atol=1e-13)
+
+
+# ---------------------------------------------------------------- spatial-cut Hubbard (fermionic cross terms, V)
+
+def _spatial_hubbard_cases():
+    rng = np.random.default_rng(2605)
+    out = []
+    for n, nu, nd in ((2, 1, 1), (4, 2, 1), (5, 2, 3), (6, 3, 3), (7, 4, 2), (8, 3, 5), (9, 4, 4), (10, 5, 5)):
+        m = I.random_extended_hubbard_model(rng, n)
+        out.append((m, int(rng.integers(1, (1 << n) - 1)), nu, nd))
+    out.append((I.hubbard_chain(6, V=1.0), (1 << 6) - 1, 3, 2))   # everything on the left
+    out.append((I.hubbard_chain(6, V=1.0), 0, 2, 3))              # everything on the right
+    out.append((I.hubbard_chain(8, 1.0, 4.0, periodic=True, V=1.5), 0b10101010, 4, 4))
+    out.append((I.hubbard_chain(8, V=1.0), 0b11110000, 0, 4))     # one spin species empty
+    return out
+
+
+@pytest.mark.parametrize("k", range(len(_spatial_hubbard_cases())))
+def test_spatial_hubbard_apply_vs_oracle(dev, k):
+    """Hubbard models with bond interactions V on random (also long-range)
+    bonds, cut by random site masks: H*psi in the bipartite layout, with the
+    fermion signs of hops across the cut, against the oracle's occupation-
+    basis H (canonical order, through the signed layout map)."""
+    m, mask, nu, nd = _spatial_hubbard_cases()[k]
+    S = _ecut().Sectors(m, I.Cut("spatial", mask), nu, nd)
+    s = O.Sector(m, nu, nd)
+    psi = I.psi(2700 + k, s.n)
+    _compare(_gpu_apply_canonical(S, psi, dev), s.apply(psi), f"{m.name} mask {mask:#x}")
+
+
+def test_spatial_hubbard14_full_vector_vs_oracle(dev):
+    """The paper's spatial-cut Hubbard ED size: 14-site chain, t=1, U=4,
+    V=1, N_up=N_dn=7, cut in the middle (11,778,624 amplitudes in 64
+    blocks): the whole H*psi against the oracle's; Hermiticity on the
+    device; cut invariance (for V=0 the spatial and up/down cuts give the
+    same canonical H*psi)."""
+    import time
+    import torch
+    E = _ecut()
+    m = I.hubbard_chain(14, 1.0, 4.0, V=1.0)
+    S = E.Sectors(m, I.Cut("spatial", I.left_mask_first(7)), 7, 7)
+    assert S.info.n_blocks == 64
+    s = O.Sector(m, 7, 7)
+    psi = I.psi(2750, s.n)
+    t0 = time.time()
+    y_ref = s.apply(psi, use_csr=False)
+    print(f"[full] oracle apply {time.time() - t0:.1f} s", flush=True)
+    _compare_full(_gpu_apply_canonical(S, psi, dev), y_ref, "spatial hubbard14 V=1")
+    xb = S.import_(torch.from_numpy(psi).to(dev))
+    pb = S.import_(torch.from_numpy(I.psi(2751, s.n)).to(dev))
+    lhs = torch.dot(pb, S.apply(xb)).item()
+    rhs = torch.dot(S.apply(pb), xb).item()
+    assert abs(lhs - rhs) <= 1e-11 * abs(lhs)
+    m0 = I.hubbard_chain(14, 1.0, 4.0)
+    a = _gpu_apply_canonical(E.Sectors(m0, I.Cut("spatial", I.left_mask_first(7)), 7, 7), psi, dev)
+    b = _gpu_apply_canonical(E.Sectors(m0, I.Cut("updn"), 7, 7), psi, dev)
+    _compare_full(a, b, "spatial vs up/down cut, V=0")
+
+
+def test_spatial_hubbard_lanczos_and_entanglement_vs_oracle(dev):
+    """10-site extended Hubbard chain (t=1, U=4, V=1.5, 5+5 particles), cut
+    5|5: the device Lanczos ground energy against ARPACK on the oracle's H,
+    and the entanglement spectrum of the oracle's ground state across the
+    fermionic mode partition (blocks (N_up_L, N_dn_L)) against numpy's
+    singular values of the oracle's signed blocks."""
+    import torch
+    m = I.hubbard_chain(10, 1.0, 4.0, V=1.5)
+    S = _ecut().Sectors(m, I.Cut("spatial", I.left_mask_first(5)), 5, 5)
+    s = O.Sector(m, 5, 5)
+    e0, g = O.ground_state(s, I.psi(2760, s.n))
+    v0 = torch.from_numpy(I.psi(2761, S.dim)).to(dev)
+    e, st, _ = S.lanczos(v0, 300, tol=1e-12)
+    assert abs(e - e0) <= 1e-10 * abs(e0), (e, e0)
+    ref = O.entanglement(s, g, "spatial", I.left_mask_first(5), cutoff=1e-10)
+    got = S.entanglement(S.import_(torch.from_numpy(g).to(dev)), cutoff=1e-10)
+    _ent_compare(got, ref, "spatial hubbard10", 1e-13)
+    assert abs(got["n_eff"] - ref["n_eff"]) <= 1e-12

@@ -655,3 +655,33 @@ def test_spatial_hubbard_map_vs_fermionic_kron(seed, L, mask):
             Hb = np.zeros_like(Hc)
             Hb[np.ix_(pos, pos)] = Hc * np.outer(sign, sign)
             np.testing.assert_allclose(Hb, Hk[np.ix_(kidx, kidx)], atol=1e-13, rtol=0, err_msg=f"{nu},{nd}")
+
+
+@pytest.mark.parametrize("seed,L,mask,nu,nd", [(41, 4, 0b0101, 2, 2), (42, 5, 0b10110, 2, 3), (43, 5, 0b00111, 3, 2)])
+def test_spatial_hubbard_entanglement_vs_fermionic_kron(seed, L, mask, nu, nd):
+    """Entanglement spectrum across the fermionic mode partition of a spatial
+    Hubbard cut: the oracle's (its signed blocks of the ground state) equals
+    the squared singular values of the ground state of the Kronecker-built H
+    (subsystem fermion operators, no layout map) reshaped to L x R."""
+    m = I.random_extended_hubbard_model(np.random.default_rng(seed), L, n_bonds=min(L * (L - 1) // 2, 2 * L))
+    Hk, ls, rs = bipartite_hubbard_kron(m, mask)
+    nL, nR = len(ls), len(rs)
+    dL, dR = 2 ** (2 * nL), 2 ** (2 * nR)
+    # number sector in the Kronecker basis: index = jl * dR + jr, each part
+    # a Jordan-Wigner index up | dn << n
+    def counts(j, n):
+        return bin(j & ((1 << n) - 1)).count("1"), bin(j >> n).count("1")
+    sel = [k for k in range(dL * dR)
+           if counts(k // dR, nL)[0] + counts(k % dR, nR)[0] == nu and counts(k // dR, nL)[1] + counts(k % dR, nR)[1] == nd]
+    w, V = np.linalg.eigh(Hk[np.ix_(sel, sel)])
+    assert w[1] - w[0] > 1e-8   # a unique ground state
+    full = np.zeros(dL * dR)
+    full[sel] = V[:, 0]
+    lam_k = np.sort(np.linalg.svd(full.reshape(dL, dR), compute_uv=False) ** 2)[::-1]
+    s = O.Sector(m, nu, nd)
+    e0, g = O.ground_state(s, I.psi(seed, s.n))
+    assert abs(e0 - w[0]) < 1e-11
+    ref = O.entanglement(s, g, "spatial", mask)
+    lam_o = np.sort(np.concatenate(ref["lam"]))[::-1]
+    np.testing.assert_allclose(lam_o, lam_k[:len(lam_o)], atol=1e-11)
+    assert np.all(lam_k[len(lam_o):] < 1e-11)

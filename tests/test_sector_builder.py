@@ -159,7 +159,10 @@ def test_error_paths():
     assert _status(lambda: E.Sectors(m, I.Cut("spatial", 0b111), 7, host_only=True)) == E.ECUT_EINVAL
     assert _status(lambda: E.Sectors(m, I.Cut("spatial", 1 << 9), 3, host_only=True)) == E.ECUT_EINVAL
     h = I.hubbard_chain(6)
-    assert _status(lambda: E.Sectors(h, I.Cut("spatial", 0b111), 3, 3, host_only=True)) == E.ECUT_EUNSUPPORTED
+    hv = I.hubbard_chain(6, V=1.0)
+    assert _status(lambda: E.Sectors(hv, I.Cut("updn"), 3, 3, host_only=True)) == E.ECUT_EUNSUPPORTED
+    h18 = I.hubbard_chain(18)
+    assert _status(lambda: E.Sectors(h18, I.Cut("spatial", 1), 2, 2, host_only=True)) == E.ECUT_EUNSUPPORTED
     assert _status(lambda: E.Sectors(h, I.Cut("updn"), 3, 7, host_only=True)) == E.ECUT_EINVAL
     bad = I.Model("spin", 4, np.array([[0, 0]], dtype=np.int32), jxy=np.ones(1), jz=np.ones(1))
     assert _status(lambda: E.Sectors(bad, I.Cut("spatial", 0b11), 2, host_only=True)) == E.ECUT_EINVAL
@@ -267,3 +270,46 @@ def test_whole_row_group_size_tuning_host():
         assert _status(lambda: C3.set_tuning(0, 8, 0, 4, tile)) == E.ECUT_EUNSUPPORTED
     C3.set_tuning(0, 8, 0, 4, 1024)
     assert C3.get_tuning()["tile"] == 1024
+
+
+def _spatial_hubbard_cases():
+    rng = np.random.default_rng(2605)
+    out = []
+    for n, nu, nd in ((2, 1, 1), (4, 2, 1), (5, 2, 3), (6, 3, 3), (7, 4, 2), (8, 3, 5), (9, 4, 4), (10, 5, 5)):
+        m = I.random_extended_hubbard_model(rng, n)
+        mask = int(rng.integers(1, (1 << n) - 1))
+        out.append((m, mask, nu, nd))
+    # whole system on one side, empty sectors on the other, the chain's half cut
+    out.append((I.hubbard_chain(6, V=1.0), (1 << 6) - 1, 3, 2))
+    out.append((I.hubbard_chain(6, V=1.0), 0, 2, 3))
+    out.append((I.hubbard_chain(10, V=1.0), I.left_mask_first(5), 5, 5))
+    out.append((I.hubbard_chain(8, V=1.0), 0b10101010, 0, 4))
+    return out
+
+
+@pytest.mark.parametrize("case", _spatial_hubbard_cases(), ids=lambda c: f"{c[0].name}-{c[1]:#x}-{c[2]}-{c[3]}")
+def test_spatial_hubbard_layout_and_signs_bit_exact(case):
+    """Blocks (N_up_L, N_dn_L), positions and fermion signs of the spatial
+    Hubbard cut against the oracle's signed map (itself pinned against
+    fermionic Kronecker products of the two parts)."""
+    m, mask, nu, nd = case
+    S = E.Sectors(m, I.Cut("spatial", mask), nu, nd, host_only=True)
+    pos, sign, ob = O.Sector(m, nu, nd).bipartite_signed(mask)
+    blocks, lab = S.blocks(), S.labels()
+    assert S.dim == len(pos)
+    assert blocks.shape[0] == ob.shape[0]
+    np.testing.assert_array_equal(lab[:, 0], ob[:, 0])
+    np.testing.assert_array_equal(lab[:, 1], ob[:, 1])
+    np.testing.assert_array_equal(lab[:, 2], nu - ob[:, 0])
+    np.testing.assert_array_equal(lab[:, 3], nd - ob[:, 1])
+    np.testing.assert_array_equal(blocks[:, 2], ob[:, 2])
+    np.testing.assert_array_equal(blocks[:, 3], ob[:, 3])
+    np.testing.assert_array_equal(blocks[:, 4], ob[:, 4])
+    np.testing.assert_array_equal(S.canonical_positions(), pos)
+    np.testing.assert_array_equal(S.canonical_signs(), sign)
+
+
+def test_canonical_signs_are_one_without_fermion_reordering():
+    for p in (I.Problem(I.xxz_chain(8), I.Cut("spatial", 0b1111), 4), I.hubbard12()):
+        S = E.Sectors.from_problem(p, host_only=True)
+        assert np.all(S.canonical_signs() == 1)
