@@ -143,7 +143,10 @@ typedef struct ecut_sectors_info {
                                  Hubbard: bit 3 the whole-row kernel available (<= 16 sites, even
                                  row length <= 14336, <= 64 bonds); bit 4 the segment-tile kernel
                                  available (as bit 1, and every tile fits 512 threads x 10
-                                 slots and 48 KB of LDS) */
+                                 slots and 48 KB of LDS); bit 5 the two-pass kernels available
+                                 (at most 32 hopping bonds); spin: bit 6 the two-pass spin
+                                 kernels available (as bit 2, and at most 64 left-operator
+                                 terms per row) */
     int32_t reserved;
     int64_t device_bytes;     /* device metadata held by the handle */
     double n_eff;             /* 1 / sum_q w_q^2 with w_q = d_L d_R / dim (block-size participation number) */
@@ -288,12 +291,31 @@ ecut_status ecut_apply_H_batch_noalloc(int32_t n, const ecut_sectors *const *s, 
  *              (up segment x down class) run together on one XCD so the
  *              down high-half hops find their source in L2 (needs
  *              kernel_flags bit 4; row_order ignored; n_xcd 1 = plain grid
- *              stride, else 8 XCD chunks).
+ *              stride, else 8 XCD chunks),
+ *              6 two passes of one work group per item (kernel_flags bit 5):
+ *              the left operator over column slabs in inversion-level row
+ *              order (grid = rows per item, 0 = 4, at most 32), then the
+ *              right operator, diagonal and epilogue with the source
+ *              column of every hopping bond held in registers (tile = rows
+ *              per item of that pass, 1, 2, 4, 8 or 16; 0 = 2); items dealt
+ *              to the XCDs in contiguous ranges (n_xcd 1 = in launch order),
+ *              7 the same left pass, then the right operator on class tiles
+ *              (needs kernel_flags bit 1); tile = slabs side by side in one
+ *              left-pass item (0 = 1, or 2 or 4; grid at most 32 / tile).
  *              Spin and generic problems (kernel 2) take variant 0 (the
  *              ranking-table spin kernel when kernel_flags bit 2 is set, else
  *              the generic row kernel) or 1 (the generic row kernel, which
  *              reads the right operator's CSR); n_xcd and row_order are
- *              ignored for them;
+ *              ignored for them.  Spin problems also take variant 2: two
+ *              passes, the left operator of every block over column slabs in
+ *              inversion-level row order (grid = rows per item, 0 = 4, at
+ *              most 32), then the spin kernel's right operator, cross terms,
+ *              diagonal and epilogue starting from that sum, its one-row
+ *              items grouped by the left sites no cross term touches (so a
+ *              group's rows are each other's cross-term source rows);
+ *              n_xcd 1 deals items in launch order, else in 8 contiguous
+ *              XCD ranges; tile as for variant 0; the vector is variant
+ *              0's bit for bit;
  *   tile:      Hubbard variant 4: threads per work group, 256, 512 or 1024
  *              (0 = 1024); a row must fit 14 columns per thread (2 x 7
  *              column pairs), and smaller groups put more rows in flight on a
@@ -330,7 +352,7 @@ ecut_status ecut_set_tuning(ecut_sectors *s, const ecut_tuning *t);
 /*
  * Autotuner: times ecut_apply_H(x_d -> y_d) for each candidate launch tuning
  * (Hubbard: kernel variant, row order, XCD chunking; spin: short-row tile and
- * grid, then the generic row kernel) with HIP events on `stream`, keeps the
+ * grid, the generic row kernel, the two-pass kernels) with HIP events on `stream`, keeps the
  * fastest on the handle and returns it in *best (nullable).  x_d, y_d: dim
  * doubles each (contents of y_d are overwritten).  If the environment
  * variable ECUT_TUNE_CACHE names a JSON file, results are read from and

@@ -233,9 +233,15 @@ ecut_status upload(ecut_sectors *s) {
         o_hbb = A.add(s->hrow_bbetw);
         o_hbc = A.add(s->hrow_bcoef);
     }
+    size_t o_spr = 0, o_spb = 0, o_spp = 0, o_spc = 0, o_spv = 0;
     if (s->spin_ok) {
         o_sfm = A.add(s->spin_fmask);
         o_sfc = A.add(s->spin_fcoef);
+        o_spr = A.add(s->sp_level_rows);
+        o_spb = A.add(s->sp_lblocks);
+        o_spp = A.add(s->sp_pptr);
+        o_spc = A.add(s->sp_pcol);
+        o_spv = A.add(s->sp_pval);
     }
     size_t o_3si = 0, o_3li = 0, o_3lo = 0, o_3hn = 0, o_3hc = 0;
     if (s->hub3_ok) {
@@ -253,11 +259,14 @@ ecut_status upload(ecut_sectors *s) {
         o_5ux = A.add(s->hs_ucross);
         o_5it = A.add(s->hs_items);
     }
-    size_t o_6k = 0, o_6v = 0, o_6r = 0;
+    size_t o_6k = 0, o_6v = 0, o_6r = 0, o_6p = 0, o_6c = 0, o_6w = 0;
     if (s->hub6_ok) {
         o_6k = A.add(s->h6_col);
         o_6v = A.add(s->h6_val);
         o_6r = A.add(s->level_rows);
+        o_6p = A.add(s->h6_pptr);
+        o_6c = A.add(s->h6_pcol);
+        o_6w = A.add(s->h6_pval);
     }
     void *mem = nullptr;
     st = table_alloc(&mem, A.off, dev);
@@ -302,6 +311,11 @@ ecut_status upload(ecut_sectors *s) {
         P.rank_hi = (const int32_t *)(b + o_srh);
         P.rflip_mask = (const uint32_t *)(b + o_sfm);
         P.rflip_coef = (const double *)(b + o_sfc);
+        s->dev_sp_rows = (int32_t *)(b + o_spr);
+        s->dev_sp_lblocks = (SpinLBlock *)(b + o_spb);
+        s->dev_sp_pptr = (const int32_t *)(b + o_spp);
+        s->dev_sp_pcol = (const int32_t *)(b + o_spc);
+        s->dev_sp_pval = (const double *)(b + o_spv);
     }
     s->dev_items = (ItemDev *)(b + o_items);
     if (s->hub_ok) {
@@ -391,10 +405,12 @@ ecut_status upload(ecut_sectors *s) {
         const BlockDev &B0 = s->blocks[0];
         HubUArgs &U = s->h6u;
         U = HubUArgs{};
-        U.hl_ptr = P.hl_ptr;
-        U.hl_col = P.hl_col;
-        U.hl_val = P.hl_val;
-        U.rows = (const int32_t *)(b + o_6r);   // level order: a row's neighbours sit in the levels beside it
+        // level order: a row's neighbours sit in the levels beside it; the
+        // left operator's CSR in that order
+        U.hl_ptr = (const int32_t *)(b + o_6p);
+        U.hl_col = (const int32_t *)(b + o_6c);
+        U.hl_val = (const double *)(b + o_6w);
+        U.rows = (const int32_t *)(b + o_6r);
         U.uniform = 1;
         for (double v : s->hl_val) U.uniform = U.uniform && v == s->hl_val[0];
         U.hop = s->hl_val.empty() ? 0.0 : s->hl_val[0];
@@ -438,7 +454,8 @@ void hub6_shape(const ecut_sectors *s, HubUArgs &U, HubDArgs &D) {
     const int32_t cols = (dR % 2 == 0 ? 2 : 1) * 64;
     U.rows_per_item = s->tune.grid > 0 ? s->tune.grid : HUBU_ROWS;
     U.n_rgroups = (nr + U.rows_per_item - 1) / U.rows_per_item;
-    U.n_slabs = (dR + cols - 1) / cols;
+    U.slab_ways = (s->tune.variant == 7 && s->tune.tile > 0) ? s->tune.tile : 1;
+    U.n_slabs = ((dR + cols - 1) / cols + U.slab_ways - 1) / U.slab_ways;
     U.n_items = U.n_slabs * U.n_rgroups;
     D.rows_per_item = hub6_rows_d(s);
     D.n_chunks = (dR + HUBD_THREADS - 1) / HUBD_THREADS;
@@ -534,6 +551,22 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             const int grid = T.grid > 0 ? T.grid : n_cu;
             e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
         }
+    } else if (s->spin_ok && s->tune.variant == 2) {
+        SpinLArgs L{};
+        L.x = P.x;
+        L.y = P.y;
+        L.hl_ptr = s->dev_sp_pptr;
+        L.hl_col = s->dev_sp_pcol;
+        L.hl_val = s->dev_sp_pval;
+        L.rows = s->dev_sp_rows;
+        L.blocks = s->dev_sp_lblocks;
+        L.n_blocks = (int32_t)s->sp_lblocks.size();
+        L.n_items = s->sp_lblocks.empty() ? 0
+                                          : s->sp_lblocks.back().item0 +
+                                                s->sp_lblocks.back().n_rgroups * s->sp_lblocks.back().n_slabs;
+        L.rows_per_item = s->tune.grid > 0 ? s->tune.grid : HUBU_ROWS;
+        e = launch_spin2(L, P, s->dev_items, s->sp_n_one, (int)s->items.size(), s->max_d_r,
+                         s->tune.n_xcd == 1 ? 1 : 8, st);
     } else if (P.spin_ok) {
         int grid = s->tune.grid;
         if (s->tune.order == 1) grid = std::max(8, ((grid > 0 ? grid : 2048) / 8) * 8);   // keeps chunk c on XCD c
@@ -544,6 +577,8 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
     if (e != hipSuccess) return hip_fail(e, "kernel launch (apply_H)");
     return ECUT_OK;
 }
+
+bool own_launch(const ecut_sectors *s) { return s->kernel == 1 || (s->spin_ok && s->tune.variant == 2); }
 
 bool hub6_batchable(const ecut_sectors *s) {
     return s->kernel == 1 && s->hub6_ok && s->tune.variant == 6 && s->h6_maxq <= HUBD_BATCH_SLOTS;
@@ -761,8 +796,8 @@ ecut_status make_batch_plan(int32_t n, const ecut_sectors *const *s, const doubl
         tiles[k] = max_tile_elems(s[k]);
         if (hub6_batchable(s[k])) {
             hub6_batch_add(pl.hub, s[k], probs[k]);   // one merged launch per pass for all of them
-        } else if (s[k]->kernel == 1) {
-            pl.own.push_back(probs[k]);               // other Hubbard tunings keep their own kernels
+        } else if (own_launch(s[k])) {
+            pl.own.push_back(probs[k]);               // other Hubbard tunings and two-pass spin keep their own kernels
             pl.own_s.push_back(s[k]);
         } else {
             for (const ItemDev &it : s[k]->items) items.push_back(ItemDev{k, it.block, it.row0, it.row1, it.slot, 0});
@@ -858,7 +893,7 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
     I.n_cross_diag = (int32_t)s->xdiag.size();
     I.kernel = s->kernel;
     I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0) | (s->hubrow_ok ? 8 : 0) |
-                     (s->hubseg_ok ? 16 : 0) | (s->hub6_ok ? 32 : 0);
+                     (s->hubseg_ok ? 16 : 0) | (s->hub6_ok ? 32 : 0) | (s->spin_ok && s->sp2_ok ? 64 : 0);
     I.device_bytes = (int64_t)s->dev_bytes;
     I.n_eff = s->n_eff;
     *info = I;

@@ -187,14 +187,15 @@ struct HubSegArgs {
 struct HubUArgs {
     const double *x;
     double *y;
-    const int32_t *hl_ptr, *hl_col;   // up-spin hop rows (rows in colex order)
+    const int32_t *hl_ptr, *hl_col;   // left-operator CSR, its rows in processing order (at most 64 entries each)
     const double *hl_val;
-    const int32_t *rows;              // row processing order
+    const int32_t *rows;              // processing position -> row of the block
     double hop;                       // every hop value when uniform != 0 (the sum is scaled once)
-    int32_t uniform, pad_;
+    int32_t uniform;
+    int32_t slab_ways;                // slabs side by side in one item (1, 2 or 4), rows split between them
     int32_t n_rows, dR;
-    int32_t rows_per_item, n_rgroups; // rows of the order per item, row runs per slab
-    int32_t n_slabs, n_items;
+    int32_t rows_per_item, n_rgroups; // rows of the order per item, row runs per slab group
+    int32_t n_slabs, n_items;         // slab groups (of slab_ways slabs), items
 };
 
 // Pass 2 (right operator, diagonal, epilogue): per element (a, c)
@@ -233,6 +234,24 @@ struct CdagArgs {
     const int32_t *src_col_of_rank;   // column of the source down word of colex rank r (NULL: r)
     const uint64_t *binom;            // [65][65] binomial table
     int32_t site, spin, dagger, pad_;
+};
+
+// Left-operator pass of the two-pass spin kernels over every block of a
+// problem: block b owns items item0 .. item0 + n_rgroups * n_slabs - 1,
+// slab-major like HubUArgs, its rows in level order at rows + lbase.
+struct SpinLBlock {
+    int64_t offset;
+    int32_t d_l, d_r, lbase, item0;
+    int32_t n_rgroups, n_slabs;
+};
+struct SpinLArgs {
+    const double *x;
+    double *y;
+    const int32_t *hl_ptr, *hl_col;   // left-operator CSR in processing order (per block at lbase), local source rows
+    const double *hl_val;
+    const int32_t *rows;              // per block at lbase: processing position -> local row (level order)
+    const SpinLBlock *blocks;
+    int32_t n_blocks, n_items, rows_per_item, pad_;
 };
 
 // Layout map of the spatial Hubbard cut (canonical index -> block position
@@ -350,6 +369,9 @@ struct ecut_sectors {
     // two-pass flat kernels (variant 6): down-spin hops as slot-major ELL
     bool hub6_ok = false;
     std::vector<int32_t> level_rows;      // rows by inversion level (the left pass's row order)
+    // the left operator's CSR with its rows in that order (row k = level_rows[k])
+    std::vector<int32_t> h6_pptr, h6_pcol;
+    std::vector<double> h6_pval;
     bool h6_uniform = false;              // every hop of either spin has the value h6_hop
     double h6_hop = 0.0;
     int32_t h6_maxq = 0;                  // bond slots of the down-spin table
@@ -380,6 +402,18 @@ struct ecut_sectors {
     // items with row1 == row0 and slot -1)
     std::vector<ecut::ItemDev> items;
     size_t items_cap = 0;                 // device capacity for any spin tile size and order
+    // two-pass spin kernels (variant 2): per-block level order of the left
+    // words, the left pass's block table, one-row items at the head of `items`
+    std::vector<int32_t> sp_level_rows;
+    std::vector<int32_t> sp_pptr, sp_pcol;   // left operator's CSR in that order (per block, at lbase)
+    std::vector<double> sp_pval;
+    bool sp2_ok = false;                     // every left word has at most 64 neighbours
+    std::vector<ecut::SpinLBlock> sp_lblocks;
+    int32_t sp_n_one = 0;
+    int32_t *dev_sp_rows = nullptr;
+    const int32_t *dev_sp_pptr = nullptr, *dev_sp_pcol = nullptr;
+    const double *dev_sp_pval = nullptr;
+    ecut::SpinLBlock *dev_sp_lblocks = nullptr;
     int32_t item_slots = 0;               // partial-sum slots of `items` (its non-padding items)
     int32_t item_slots_cap = 0;           // most slots any spin tiling can use
     std::vector<int32_t> row_order;       // Hubbard kernel: row processing order
@@ -409,6 +443,14 @@ int32_t hub_column(const ecut_sectors *s, int64_t r);
 // order 0 largest first, 1 segments dealt to 8 XCD chunks (padded list);
 // returns the number of partial-sum slots
 int32_t make_spin_items(const ecut_sectors *s, int32_t tile, int32_t order, std::vector<ItemDev> &out);
+// The left operator's CSR (hl_ptr / hl_col / hl_val) with its rows permuted:
+// processing position p of a block takes the block's local row order[p]
+// (positions and rows counted from the block's lbase); entries keep their
+// order.  Returns the largest row length.
+int32_t processing_csr(const ecut_sectors *s, const std::vector<int32_t> &order, std::vector<int32_t> &pptr,
+                       std::vector<int32_t> &pcol, std::vector<double> &pval);
+// left-pass block table of the two-pass spin kernels
+void spin_left_blocks(const ecut_sectors *s, int32_t rows_per_item, std::vector<SpinLBlock> &out);
 void release_device(ecut_sectors *s);
 // item counts of the two-pass kernels (variant 6) for the handle's tuning
 void hub6_shape(const ecut_sectors *s, HubUArgs &U, HubDArgs &D);

@@ -37,7 +37,8 @@ constexpr int HUBROW_COLS = 2 * HUBROW_P * HUBROW_THREADS;
 constexpr int HUBROW_MAX_BOND = 64;
 constexpr int HUBU_THREADS = 256;            // two-pass kernels: left-operator pass, one row per wave at a time
 constexpr int HUBU_NB = 8;                   // neighbour-row loads issued together per lane
-constexpr int HUBU_ROWS = 4;                 // rows of the row order per left-operator item
+constexpr int HUBU_ROWS = 4;                  // rows of the row order per left-operator item
+constexpr int HUBU_RMAX = 8;                  // most rows of one wave in a left-operator item
 constexpr int HUBD_THREADS = 256;            // right-operator pass: one column per thread
 constexpr int HUBD_NB = 8;                   // in-row gathers issued together per lane
 constexpr int HUBD_MAX_SLOTS = 32;           // bonds of the down-spin hop table (held in registers)
@@ -128,6 +129,10 @@ hipError_t launch_perm_cols(const int32_t *col_d, int64_t n_rows, int dR, const 
 hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const BlockDev *blocks_d, const double *in,
                        double *out, bool to_bip, hipStream_t st);
 hipError_t launch_cdag(const CdagArgs &A, hipStream_t st);
+// two-pass spin kernels: left pass over slab items, then the one-row items
+// [0, n_one) and the several-row items [n_one, n_items) without the left operator
+hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const ItemDev *items_d, int n_one, int n_items,
+                        int max_d_r, int n_xcd, hipStream_t st);
 // canonical <-> bipartite layout of the spatial Hubbard cut (with signs)
 hipError_t launch_perm_hubsp(const HubSpPerm &A, const double *in, double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);

@@ -715,7 +715,9 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // the cross terms) is uniform across the work group.  One LDS buffer: it
 // first holds the source rows of the cross terms (one per left site), then
 // the item's own row for the right operator.
-template <int NT, int M>
+// LEFT: the left operator here; otherwise its sum is already in y (the
+// two-pass kernels' left pass) and is read as the starting value.
+template <int NT, int M, bool LEFT>
 __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                              const int32_t *rl, const int32_t *rh, const uint32_t *fm,
                                              const double *fc, int n_flip, double *red) {
@@ -735,8 +737,16 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
         wr[m] = e < dR ? P.rwords[B.rbase + e] : 0u;
         acc[m] = 0.0;
     }
+    if (!LEFT) {
+        double *__restrict__ yt = P.y + B.offset + (int64_t)l * dR;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = tid + m * NT;
+            acc[m] = e < dR ? yt[e] : 0.0;
+        }
+    }
     // left operator: neighbour rows of the same block at the same columns
-    {
+    if (LEFT) {
         const int q1 = P.hl_ptr[gl + 1];
         for (int q = P.hl_ptr[gl]; q < q1; ++q) {
             const double c = P.hl_val[q];
@@ -841,7 +851,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
 
 // Item of several short rows: per-element rows, cross terms gathered from
 // global memory (these blocks are small).
-template <int NT, int M>
+template <int NT, int M, bool LEFT>
 __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                                const int32_t *rl, const int32_t *rh, const uint32_t *fm,
                                                const double *fc, int n_flip, double *red) {
@@ -885,8 +895,12 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
         const int gl = B.lbase + W.row0 + lr;
         const uint32_t lw = P.lwords[gl];
         double a = 0.0;
-        const int q1 = P.hl_ptr[gl + 1];
-        for (int q = P.hl_ptr[gl]; q < q1; ++q) a += P.hl_val[q] * xblk[(int64_t)P.hl_col[q] * dR + r];
+        if (LEFT) {
+            const int q1 = P.hl_ptr[gl + 1];
+            for (int q = P.hl_ptr[gl]; q < q1; ++q) a += P.hl_val[q] * xblk[(int64_t)P.hl_col[q] * dR + r];
+        } else {
+            a = P.y[B.offset + (int64_t)W.row0 * dR + e];
+        }
         for (int k = 0; k < P.n_xbond; ++k) {
             const XBondDev X = P.xbond[k];
             const uint32_t bl = (lw >> X.li) & 1u;
@@ -969,10 +983,86 @@ __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, ONE ? 4 : 2
         }
         const BlockDev B = P.blocks[W.block];
         if (ONE)
-            spin_one_row<NT, M>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
+            spin_one_row<NT, M, true>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
         else
-            spin_many_rows<NT, M>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
+            spin_many_rows<NT, M, true>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
     }
+}
+
+// ------------------------------------------------------------------------
+// Two-pass spin kernels.  Pass 1 (k_spinL): the left operator H_L (x) 1 of
+// every block on slab items (64 columns x rows_per_item rows of the block's
+// level order), as the Hubbard left pass; y = H_L x.  Pass 2 (k_spinR): the
+// one-row and several-row items of the spin kernel without the left
+// operator, which start from y; the one-row items come grouped by the
+// interior of the left word, so the cross-term source rows of a group (rows
+// differing only at the cut's left sites) are read from HBM about once.
+// Both passes run one work group per item, dealt to the XCDs in contiguous
+// ranges (xcd_item): a group's rows stay on one XCD and in its L2.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_item(int n_xcd, int per_xcd);
+template <bool PAIR, bool STREAM>
+__device__ __forceinline__ void hubU_item(const HubUArgs &A, int it);
+
+template <bool STREAM>
+__global__ __launch_bounds__(HUBU_THREADS) void k_spinL(const SpinLArgs A, int n_xcd, int per_xcd) {
+    const int it = xcd_item(n_xcd, per_xcd);
+    if (it >= A.n_items) return;
+    int lo = 0, hi = A.n_blocks - 1;   // the last block with item0 <= it
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.blocks[mid].item0 <= it) lo = mid;
+        else hi = mid - 1;
+    }
+    const SpinLBlock L = A.blocks[lo];
+    HubUArgs U;
+    U.x = A.x + L.offset;
+    U.y = A.y + L.offset;
+    U.hl_ptr = A.hl_ptr + L.lbase;
+    U.hl_col = A.hl_col;
+    U.hl_val = A.hl_val;
+    U.rows = A.rows + L.lbase;
+    U.hop = 0.0;
+    U.uniform = 0;
+    U.slab_ways = 1;
+    U.n_rows = L.d_l;
+    U.dR = L.d_r;
+    U.rows_per_item = A.rows_per_item;
+    U.n_rgroups = L.n_rgroups;
+    U.n_slabs = L.n_slabs;
+    U.n_items = L.n_rgroups * L.n_slabs;
+    hubU_item<false, STREAM>(U, it - L.item0);
+}
+
+template <bool ONE>
+__global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, 2) void k_spinR(
+    const ProblemDev P, const ItemDev *__restrict__ items, int n_items, int n_xcd, int per_xcd) {
+    constexpr int NT = ONE ? SPIN_THREADS : SPIN_MANY_THREADS;
+    constexpr int M = ONE ? SPIN_M : SPIN_MANY_TILE / SPIN_MANY_THREADS;
+    extern __shared__ __align__(16) double xs[];
+    __shared__ double red[NT / 64];
+    __shared__ int32_t rl[256];
+    __shared__ int32_t rh[256 * 9];
+    __shared__ uint32_t fm[SPIN_MAX_FLIP];
+    __shared__ double fc[SPIN_MAX_FLIP];
+    const int it = xcd_item(n_xcd, per_xcd);
+    if (it >= n_items) return;   // uniform over the work group
+    const ItemDev W = items[it];
+    if (W.row1 <= W.row0) return;
+    const int tid = threadIdx.x;
+    const int n_flip = P.n_rflip;
+    for (int i = tid; i < 256; i += NT) rl[i] = P.rank_lo[i];
+    for (int i = tid; i < 256 * 9; i += NT) rh[i] = P.rank_hi[i];
+    for (int i = tid; i < n_flip; i += NT) {
+        fm[i] = P.rflip_mask[i];
+        fc[i] = P.rflip_coef[i];
+    }
+    __syncthreads();
+    const BlockDev B = P.blocks[W.block];
+    if (ONE)
+        spin_one_row<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
+    else
+        spin_many_rows<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
 }
 
 // ------------------------------------------------------------------------
@@ -1463,45 +1553,74 @@ __device__ __forceinline__ int xcd_item(int n_xcd, int per_xcd) {
     return n_xcd == 8 ? (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3) : (int)blockIdx.x;
 }
 
+// A wave takes every (4 / ways)-th row of its item (at most HUBU_RMAX).  Its
+// rows' CSR ranges, output rows and source rows are loaded once, one entry
+// per lane, and read back with readlane, so the gathers of a row wait for no
+// index load of their own.
 template <bool PAIR, bool STREAM>
 __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
-    const int slab = it / A.n_rgroups;
-    const int rg = it - slab * A.n_rgroups;
+    const int sg = it / A.n_rgroups;
+    const int rg = it - sg * A.n_rgroups;
     constexpr int CPL = PAIR ? 2 : 1;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // wave w takes slab w % ways of the group and every (4 / ways)-th row
+    const int ways = A.slab_ways;
+    const int slab = sg * ways + wave % ways;
     const int c = (slab * 64 + lane) * CPL;
     const bool ok = c < A.dR;
     const int64_t dR = A.dR;
-    const int r0 = rg * A.rows_per_item;
-    const int r1 = min(r0 + A.rows_per_item, A.n_rows);
-    for (int r = r0 + wave; r < r1; r += HUBU_THREADS / 64) {
-        const int a = A.rows[r];
-        const int q0 = A.hl_ptr[a], q1 = A.hl_ptr[a + 1];
+    const int step = HUBU_THREADS / 64 / ways;
+    const int r0 = rg * A.rows_per_item + wave / ways;
+    const int r1 = min(rg * A.rows_per_item + A.rows_per_item, A.n_rows);
+    const int nrw = r0 < r1 ? min((r1 - r0 + step - 1) / step, HUBU_RMAX) : 0;
+    int pa = 0, pb = 0, ar = 0;
+    if (lane < nrw) {
+        const int rr = r0 + lane * step;
+        pa = A.hl_ptr[rr];
+        pb = A.hl_ptr[rr + 1];
+        ar = A.rows[rr];
+    }
+    int colv[HUBU_RMAX];
+#pragma unroll
+    for (int k = 0; k < HUBU_RMAX; ++k) {
+        colv[k] = 0;
+        if (k < nrw) {
+            const int q0 = __builtin_amdgcn_readlane(pa, k);
+            if (lane < __builtin_amdgcn_readlane(pb, k) - q0) colv[k] = A.hl_col[q0 + lane];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < HUBU_RMAX; ++k) {
+        if (k >= nrw) break;
+        const int q0 = __builtin_amdgcn_readlane(pa, k);
+        const int deg = __builtin_amdgcn_readlane(pb, k) - q0;
+        const int a = __builtin_amdgcn_readlane(ar, k);
         double acc0 = 0.0, acc1 = 0.0;
-        for (int q = q0; q < q1; q += HUBU_NB) {
+        for (int j = 0; j < deg; j += HUBU_NB) {
             double v0[HUBU_NB], v1[HUBU_NB];
             // every load of the batch is issued before any is consumed
 #pragma unroll
-            for (int k = 0; k < HUBU_NB; ++k) {
-                v0[k] = v1[k] = 0.0;
-                if (q + k < q1 && ok) {
-                    const double *src = A.x + (int64_t)A.hl_col[q + k] * dR + c;
+            for (int u = 0; u < HUBU_NB; ++u) {
+                v0[u] = v1[u] = 0.0;
+                const int src = j + u < deg ? __builtin_amdgcn_readlane(colv[k], j + u) : 0;
+                if (j + u < deg && ok) {
+                    const double *p = A.x + (int64_t)src * dR + c;
                     if constexpr (PAIR) {
-                        const double2 p = *(const double2 *)src;
-                        v0[k] = p.x;
-                        v1[k] = p.y;
+                        const double2 q = *(const double2 *)p;
+                        v0[u] = q.x;
+                        v1[u] = q.y;
                     } else {
-                        v0[k] = *src;
+                        v0[u] = *p;
                     }
                 }
             }
 #pragma unroll
-            for (int k = 0; k < HUBU_NB; ++k)
-                if (q + k < q1) {
-                    const double h = A.uniform ? 1.0 : A.hl_val[q + k];
-                    acc0 += h * v0[k];
-                    acc1 += h * v1[k];
+            for (int u = 0; u < HUBU_NB; ++u)
+                if (j + u < deg) {
+                    const double h = A.uniform ? 1.0 : A.hl_val[q0 + j + u];
+                    acc0 += h * v0[u];
+                    acc1 += h * v1[u];
                 }
         }
         if (A.uniform) {   // sum, then scale once
@@ -2189,6 +2308,39 @@ hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, cons
     hipLaunchKernelGGL(k_spin<true>, dim3(grid), dim3(SPIN_THREADS), lds1, st, probs_d, single, items_d, n_items);
     const size_t lds2 = (size_t)SPIN_MANY_TILE * 8;
     hipLaunchKernelGGL(k_spin<false>, dim3(grid), dim3(SPIN_MANY_THREADS), lds2, st, probs_d, single, items_d, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const ItemDev *items_d, int n_one, int n_items,
+                        int max_d_r, int n_xcd, hipStream_t st) {
+    if (max_d_r > SPIN_TILE) return hipErrorInvalidValue;
+    const int xu = n_xcd == 1 ? 1 : 8;
+    auto grid_of = [&](int n, int &per) {
+        per = (n + xu - 1) / xu;
+        return dim3(xu == 8 ? 8 * per : n);
+    };
+    int per = 0;
+    if (L.n_items > 0) {
+        const dim3 g = grid_of(L.n_items, per);
+        if ((int64_t)P.dim >= STREAM_STORE_MIN)
+            hipLaunchKernelGGL(k_spinL<true>, g, dim3(HUBU_THREADS), 0, st, L, xu, per);
+        else
+            hipLaunchKernelGGL(k_spinL<false>, g, dim3(HUBU_THREADS), 0, st, L, xu, per);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_one > 0) {
+        const dim3 g = grid_of(n_one, per);
+        const size_t lds = (size_t)std::max(max_d_r, 1) * 8;
+        hipLaunchKernelGGL(k_spinR<true>, g, dim3(SPIN_THREADS), lds, st, P, items_d, n_one, xu, per);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (n_items > n_one) {
+        const dim3 g = grid_of(n_items - n_one, per);
+        hipLaunchKernelGGL(k_spinR<false>, g, dim3(SPIN_MANY_THREADS), (size_t)SPIN_MANY_TILE * 8, st, P,
+                           items_d + n_one, n_items - n_one, xu, per);
+    }
     return hipGetLastError();
 }
 

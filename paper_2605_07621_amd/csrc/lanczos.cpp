@@ -294,7 +294,7 @@ static void build_plan(const std::vector<LzSolve *> &act, double *out2, StepPlan
         P.partials = L->part_apply;
         if (act.size() > 1 && hub6_batchable(L->s)) {
             hub6_batch_add(pl.hub, L->s, P);
-        } else if (L->s->kernel == 1 || act.size() == 1) {
+        } else if (own_launch(L->s) || act.size() == 1) {
             pl.own.push_back(P);
             pl.own_s.push_back(L->s);
         } else {

@@ -51,6 +51,9 @@ struct HubBatch {
 // a problem joins the merged launch when its tuning selects the two-pass
 // kernels (variant 6) and its down-spin table fits the batched kernel
 bool hub6_batchable(const ecut_sectors *s);
+// a problem that a batch launches on its own kernels (Hubbard kernels other
+// than the merged two-pass launch, two-pass spin kernels)
+bool own_launch(const ecut_sectors *s);
 void hub6_batch_add(HubBatch &b, const ecut_sectors *s, const ProblemDev &P);
 // byte offsets of the four arrays in a buffer laid out by hub6_batch_pack
 struct HubBatchLayout {

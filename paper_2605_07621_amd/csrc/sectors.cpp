@@ -138,6 +138,7 @@ inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
 
 static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
 static void build_spin_tables(ecut_sectors *s);
+static int inversions(uint32_t w, int n);
 static void build_hubseg_tables(ecut_sectors *s);
 static void make_rank_tables(ecut_sectors *s);
 static void build_hubrow_tables(ecut_sectors *s, const ecut_model_desc *m);
@@ -677,6 +678,7 @@ static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m) {
     build_hubrow_tables(s, m);
     build_hub6_tables(s, m);
     make_row_order(s, 1, s->level_rows);
+    if (s->hub6_ok) processing_csr(s, s->level_rows, s->h6_pptr, s->h6_pcol, s->h6_pval);
     make_row_order(s, 0, s->row_order);
 
     // ---- class tiles of the down basis
@@ -1089,7 +1091,66 @@ static void build_spin_tables(ecut_sectors *s) {
     s->item_slots_cap = (int32_t)std::max(s->items.size(), rows);
     s->items_cap = 8 * (size_t)s->item_slots_cap;
     make_rank_tables(s);
+    // two-pass kernels: the rows of every block by inversion level of the
+    // left word (a flip-flop on bond (i, j) moves a word |i - j| levels, so
+    // the neighbour rows of a level lie in the levels next to it)
+    s->sp_level_rows.assign(s->lwords.size(), 0);
+    for (const BlockDev &B : s->blocks) {
+        std::vector<int64_t> key((size_t)B.d_l);
+        for (int32_t a = 0; a < B.d_l; ++a)
+            key[a] = (int64_t)inversions(s->lwords[(size_t)B.lbase + a], (int)s->lsites.size()) << 32 | a;
+        std::sort(key.begin(), key.end());
+        for (int32_t a = 0; a < B.d_l; ++a) s->sp_level_rows[(size_t)B.lbase + a] = (int32_t)(key[a] & 0xffffffff);
+    }
+    s->sp2_ok = processing_csr(s, s->sp_level_rows, s->sp_pptr, s->sp_pcol, s->sp_pval) <= 64;
+    spin_left_blocks(s, HUBU_ROWS, s->sp_lblocks);
     s->spin_ok = true;
+}
+
+int32_t processing_csr(const ecut_sectors *s, const std::vector<int32_t> &order, std::vector<int32_t> &pptr,
+                       std::vector<int32_t> &pcol, std::vector<double> &pval) {
+    const size_t n = s->lwords.size();
+    std::vector<int64_t> src(n, -1);   // processing position -> global row
+    for (const BlockDev &B : s->blocks)
+        for (int32_t p = 0; p < B.d_l; ++p) src[(size_t)B.lbase + p] = (int64_t)B.lbase + order[(size_t)B.lbase + p];
+    pptr.assign(n + 1, 0);
+    pcol.clear();
+    pval.clear();
+    int32_t maxd = 0;
+    for (size_t p = 0; p < n; ++p) {
+        if (src[p] >= 0) {
+            const int32_t q0 = s->hl_ptr[(size_t)src[p]], q1 = s->hl_ptr[(size_t)src[p] + 1];
+            pcol.insert(pcol.end(), s->hl_col.begin() + q0, s->hl_col.begin() + q1);
+            pval.insert(pval.end(), s->hl_val.begin() + q0, s->hl_val.begin() + q1);
+            maxd = std::max(maxd, q1 - q0);
+        }
+        pptr[p + 1] = (int32_t)pcol.size();
+    }
+    if (pcol.empty()) {   // keep the device arrays non-empty
+        pcol.push_back(0);
+        pval.push_back(0.0);
+    }
+    return maxd;
+}
+
+// Left-pass block table of the two-pass spin kernels for items of
+// `rows_per_item` rows: slabs of 64 columns, every block with amplitudes.
+void spin_left_blocks(const ecut_sectors *s, int32_t rows_per_item, std::vector<SpinLBlock> &out) {
+    out.clear();
+    int32_t item0 = 0;
+    for (const BlockDev &B : s->blocks) {
+        if ((int64_t)B.d_l * B.d_r == 0) continue;
+        SpinLBlock L{};
+        L.offset = B.offset;
+        L.d_l = B.d_l;
+        L.d_r = B.d_r;
+        L.lbase = B.lbase;
+        L.item0 = item0;
+        L.n_rgroups = (B.d_l + rows_per_item - 1) / rows_per_item;
+        L.n_slabs = (B.d_r + 63) / 64;
+        item0 += L.n_rgroups * L.n_slabs;
+        out.push_back(L);
+    }
 }
 
 // Work items of the spin kernel: a row longer than half the tile is an item of
@@ -1103,6 +1164,9 @@ static void build_spin_tables(ecut_sectors *s) {
 // to one length with empty items and interleaved, position 8 k + c holding
 // item k of chunk c, so a grid-stride walk with a grid that is a multiple of
 // 8 runs chunk c on XCD c (work group w runs on XCD w % 8).
+//
+// Order 2 (the two-pass kernels) puts the one-row items first, grouped by the
+// interior of the left word, then the items of several rows.
 int32_t make_spin_items(const ecut_sectors *s, int32_t tile, int32_t order, std::vector<ItemDev> &out) {
     std::vector<ItemDev> base;
     for (int b = 0; b < (int)s->blocks.size(); ++b) {
@@ -1114,6 +1178,24 @@ int32_t make_spin_items(const ecut_sectors *s, int32_t tile, int32_t order, std:
     std::stable_sort(base.begin(), base.end(), [&](const ItemDev &a, const ItemDev &b) { return work(a) > work(b); });
     for (size_t k = 0; k < base.size(); ++k) base[k].slot = (int32_t)k;
     const int32_t n_slots = (int32_t)base.size();
+    if (order == 2) {
+        // one-row items first, grouped by the left sites that no cross term
+        // touches: the cross-term source rows of a row differ from it only
+        // at the cut's left sites, so the rows of one group (in every block)
+        // are each other's source rows
+        uint32_t bmask = 0;
+        for (const XBondDev &X : s->xbond) bmask |= 1u << X.li;
+        auto key = [&](const ItemDev &a) {
+            const uint32_t w = s->lwords[(size_t)s->blocks[a.block].lbase + a.row0];
+            return (uint64_t)(w & ~bmask) << 32 | (w & bmask);
+        };
+        std::vector<ItemDev> one, many;
+        for (const ItemDev &a : base) (a.row1 - a.row0 == 1 ? one : many).push_back(a);
+        std::stable_sort(one.begin(), one.end(), [&](const ItemDev &a, const ItemDev &b) { return key(a) < key(b); });
+        out = one;
+        out.insert(out.end(), many.begin(), many.end());
+        return n_slots;
+    }
     if (order != 1) {
         out.swap(base);
         return n_slots;

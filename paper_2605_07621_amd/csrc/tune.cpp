@@ -75,10 +75,15 @@ void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) 
 ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 7)
         return fail(ECUT_EINVAL, "bad tuning");
-    if (s->kernel != 1 && T.variant > 1) return fail(ECUT_EINVAL, "spin and generic problems take variant 0 or 1");
+    if (s->kernel != 1 && T.variant > (s->spin_ok ? 2 : 1))
+        return fail(ECUT_EINVAL, "spin problems take variant 0, 1 or 2, generic problems 0 or 1");
     if (T.tile < 0) return fail(ECUT_EINVAL, "tile must not be negative");
     if (s->spin_ok) {
         if (T.tile > SPIN_MANY_TILE) return fail(ECUT_EINVAL, "tile must lie in 0..512");
+        if (T.variant == 2 && T.grid > HUBU_RMAX * (HUBU_THREADS / 64))
+            return fail(ECUT_EINVAL, "left-pass items of the two-pass spin kernels take at most 32 rows");
+        if (T.variant == 2 && !s->sp2_ok)
+            return fail(ECUT_EUNSUPPORTED, "two-pass spin kernels need at most 64 left-operator terms per row");
     } else if (s->kernel == 1 && T.variant == 4) {
         // the whole-row Hubbard kernel: tile = threads per work group
         if (T.tile != 0 && T.tile != 256 && T.tile != 512 && T.tile != 1024)
@@ -89,7 +94,9 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
         // the two-pass kernels: tile = rows per item of the right-operator pass
         if (T.tile != 0 && T.tile != 1 && T.tile != 2 && T.tile != 4 && T.tile != 8 && T.tile != 16)
             return fail(ECUT_EINVAL, "two-pass items take 1, 2, 4, 8 or 16 rows");
-        if (T.grid > 64) return fail(ECUT_EINVAL, "left-operator items take at most 64 rows");
+        const int ways = (T.variant == 7 && T.tile > 0) ? T.tile : 1;
+        if (T.grid > HUBU_RMAX * (HUBU_THREADS / 64) / ways)
+            return fail(ECUT_EINVAL, "left-operator items take at most 32 rows (8 with 4 slabs side by side)");
     } else if (T.tile != 0) {
         return fail(ECUT_EUNSUPPORTED,
                     "the tile applies to the spin kernel, the whole-row and the two-pass Hubbard kernels only");
@@ -103,7 +110,8 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if (T.variant == 6 && s->kernel == 1 && !s->hub6_ok) return fail(ECUT_EUNSUPPORTED, "two-pass kernels not available");
     if (T.variant == 7 && s->kernel == 1 && !s->hub3_ok)
         return fail(ECUT_EUNSUPPORTED, "two passes with class tiles need the uniform-chain tables");
-    if (T.variant == 7 && T.tile != 0) return fail(ECUT_EINVAL, "variant 7 takes tile 0");
+    if (T.variant == 7 && T.tile != 0 && T.tile != 1 && T.tile != 2 && T.tile != 4)
+        return fail(ECUT_EINVAL, "variant 7 takes tile 0, 1, 2 or 4 (slabs side by side in a left-pass item)");
     if (T.variant == 4 && s->kernel == 1 && !s->hubrow_ok)
         return fail(ECUT_EUNSUPPORTED, "whole-row kernel not available (more than 16 sites, odd or too long rows)");
     if (s->kernel == 1 && (T.order != s->tune.order || T.variant != s->tune.variant)) {
@@ -120,9 +128,10 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
         }
     }
     const int32_t tile = T.tile > 0 ? T.tile : SPIN_MANY_TILE, cur = s->tune.tile > 0 ? s->tune.tile : SPIN_MANY_TILE;
-    if (s->spin_ok && (tile != cur || T.order != s->tune.order)) {
+    const int32_t spin_order = T.variant == 2 ? 2 : T.order, cur_order = s->tune.variant == 2 ? 2 : s->tune.order;
+    if (s->spin_ok && (tile != cur || spin_order != cur_order)) {
         std::vector<ItemDev> items;
-        const int32_t slots = make_spin_items(s, tile, T.order, items);
+        const int32_t slots = make_spin_items(s, tile, spin_order, items);
         if (items.size() > s->items_cap || slots > s->item_slots_cap)
             return fail(ECUT_EINVAL, "work list exceeds its buffer");
         if (s->on_device && s->dev_items) {
@@ -132,6 +141,23 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
         }
         s->items.swap(items);
         s->item_slots = slots;
+    }
+    if (s->spin_ok) {
+        s->sp_n_one = 0;
+        if (spin_order == 2)
+            for (const ItemDev &it : s->items) s->sp_n_one += (it.row1 - it.row0 == 1) ? 1 : 0;
+        const int32_t rpi = T.grid > 0 ? T.grid : HUBU_ROWS, cur_rpi = s->tune.grid > 0 ? s->tune.grid : HUBU_ROWS;
+        if (T.variant == 2 && (rpi != cur_rpi || s->tune.variant != 2)) {
+            std::vector<SpinLBlock> lb;
+            spin_left_blocks(s, rpi, lb);
+            if (lb.size() != s->sp_lblocks.size()) return fail(ECUT_EINVAL, "left-pass block table changed size");
+            if (s->on_device && s->dev_sp_lblocks) {
+                hipError_t e =
+                    hipMemcpy(s->dev_sp_lblocks, lb.data(), lb.size() * sizeof(SpinLBlock), hipMemcpyHostToDevice);
+                if (e != hipSuccess) return hip_fail(e, "hipMemcpy(left-pass blocks)");
+            }
+            s->sp_lblocks.swap(lb);
+        }
     }
     s->tune = T;
     if (s->kernel != 1) s->prob.spin_ok = (s->spin_ok && s->on_device && T.variant == 0) ? 1 : 0;
@@ -210,6 +236,10 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
             for (int tile : {128, 256, 512})
                 for (int grid : {0, 512, 1024}) cands.push_back(ApplyTuning{grid, 0, order, 0, tile});
         cands.push_back(ApplyTuning{0, 0, 0, 1, 0});
+        // two-pass kernels: left-pass rows per item, XCD dealing
+        if (s->sp2_ok)
+            for (int rows : {4, 8, 16})
+                for (int xcd : {1, 8}) cands.push_back(ApplyTuning{rows, xcd, 0, 2, 0});
     } else {
         cands.push_back(ApplyTuning{0, 0, 0, 0, 0});
     }

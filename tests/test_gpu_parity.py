@@ -388,17 +388,19 @@ _SPIN_CASES = [p for p in SMALL if p.model.kind == "spin"] + [
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_spin_kernel_variants(dev, variant):
-    """The ranking-table spin kernel (variant 0) and the generic row kernel
-    (variant 1) both agree with the oracle: Heisenberg, XXZ and J1-J2 models,
-    random couplings and cuts, one-row and many-row tiles, empty and full
-    sectors."""
+    """The ranking-table spin kernel (variant 0), the generic row kernel
+    (variant 1) and the two-pass spin kernels (variant 2) all agree with the
+    oracle: Heisenberg, XXZ and J1-J2 models, random couplings and cuts,
+    one-row and many-row tiles, empty and full sectors."""
     for k, p in enumerate(_SPIN_CASES):
         s = O.Sector(p.model, p.n_up, p.n_dn)
         psi = I.psi(700 + k, s.n)
         y_ref = s.apply(psi)
         S = _ecut().Sectors.from_problem(p)
+        if variant == 2 and not S.info.kernel_flags & 64:
+            continue
         S.set_tuning(0, 0, 0, variant)
         assert S.get_tuning()["variant"] == variant
         _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{p.model.name} n_up={p.n_up} variant {variant}")
@@ -419,10 +421,36 @@ def test_spin_kernel_full_size_variants_agree(dev):
     torch.cuda.synchronize()
     err = (torch.linalg.vector_norm(y0 - y1) / torch.linalg.vector_norm(y1)).item()
     assert err <= RTOL, err
-    # the autotuner times each candidate with its own kernel: the spin kernel
-    # is several times faster here, so it must win
-    assert S.autotune(x, y1)["variant"] == 0
+    # the autotuner times each candidate with its own kernel: a spin kernel
+    # is several times faster here than the generic one, so it must win
+    assert S.autotune(x, y1)["variant"] in (0, 2)
     del y0, y1, x
+
+
+def test_spin_two_pass_bit_exact(dev):
+    """The two-pass spin kernels sum every amplitude's terms in the spin
+    kernel's order (left operator in CSR order, then cross terms, right
+    operator, diagonal), so every left-pass row count, XCD dealing and
+    short-row tile gives the one-pass vector bit for bit; and the oracle's."""
+    import torch
+    n_run = 0
+    for k, p in enumerate(_SPIN_CASES):
+        S = _ecut().Sectors.from_problem(p)
+        if not S.info.kernel_flags & 64:
+            continue
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        psi = I.psi(1500 + k, s.n)
+        x = S.import_(torch.from_numpy(psi).to(dev))
+        S.set_tuning(0, 0, 0, 0, 0)
+        y0 = S.apply(x)
+        for rows, xcd, tile in ((0, 8, 0), (4, 1, 0), (8, 8, 64), (16, 8, 1), (32, 1, 512), (5, 8, 300)):
+            S.set_tuning(rows, xcd, 0, 2, tile)
+            y = S.apply(x)
+            torch.cuda.synchronize()
+            assert torch.equal(y, y0), f"{p.model.name} n_up={p.n_up} rows {rows} xcd {xcd} tile {tile}"
+        _compare(_gpu_apply_canonical(S, psi, dev), s.apply(psi), f"{p.model.name} n_up={p.n_up} two-pass")
+        n_run += 1
+    assert n_run >= 4
 
 
 # (tile, grid, row order): order 1 deals segments of rows to the 8 XCDs
@@ -471,6 +499,12 @@ def test_spin_tile_tunings_full_size(dev):
         S.apply(x, out=y)
         torch.cuda.synchronize()
         assert torch.equal(y, y0), (tile, grid, order)
+    # the two-pass kernels: the same sums in the same order
+    for rows, xcd in ((0, 8), (8, 8), (16, 1)):
+        S.set_tuning(rows, xcd, 0, 2, 0)
+        S.apply(x, out=y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y0), ("two-pass", rows, xcd)
     # the generic row kernel walks the padded list of order 1 too
     S.set_tuning(0, 0, 1, 1, 0)
     S.apply(x, out=y)

@@ -131,7 +131,7 @@ def test_spin_kernel_eligibility():
     # that fit its work group and <= 64 flip-flop terms inside the right part
     for p in (I.heisenberg16(), I.j1j2_6x5(), I.Problem(I.xxz_chain(24, 1.0, 0.7), I.Cut("spatial", (1 << 12) - 1), 12)):
         S = E.Sectors.from_problem(p, host_only=True)
-        assert S.info.kernel == 2 and S.info.kernel_flags == 4, p.model.name
+        assert S.info.kernel == 2 and S.info.kernel_flags == 4 | 64, p.model.name
     wide = I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", 0b111), 10)   # right part: 17 sites
     assert E.Sectors.from_problem(wide, host_only=True).info.kernel_flags == 0
     dense = I.Problem(I.random_spin_model(np.random.default_rng(3), 14, n_bonds=91), I.Cut("spatial", 0b1), 7)
@@ -185,7 +185,7 @@ def test_bench_names_every_kernel_variant():
         names.add(bench.kernel_name(S3))
     assert names == {"k_hub3", "k_hub", "k_hub2", "k_upslab+k_hub3", "k_hubrow", "k_hubseg"}
     S4 = E.Sectors.from_problem(I.j1j2_6x5(), host_only=True)
-    for v, want in ((0, "k_spin"), (1, "k_rows")):
+    for v, want in ((0, "k_spin"), (1, "k_rows"), (2, "k_spinL+k_spinR")):
         S4.set_tuning(0, 0, 0, v)
         assert bench.kernel_name(S4) == want
 
