@@ -233,7 +233,7 @@ ecut_status upload(ecut_sectors *s) {
         o_hbb = A.add(s->hrow_bbetw);
         o_hbc = A.add(s->hrow_bcoef);
     }
-    size_t o_spr = 0, o_spb = 0, o_spp = 0, o_spc = 0, o_spv = 0;
+    size_t o_spr = 0, o_spb = 0, o_spp = 0, o_spc = 0, o_spv = 0, o_spt = 0, o_sptb = 0;
     if (s->spin_ok) {
         o_sfm = A.add(s->spin_fmask);
         o_sfc = A.add(s->spin_fcoef);
@@ -242,6 +242,8 @@ ecut_status upload(ecut_sectors *s) {
         o_spp = A.add(s->sp_pptr);
         o_spc = A.add(s->sp_pcol);
         o_spv = A.add(s->sp_pval);
+        o_spt = A.add(s->sp_tab);
+        o_sptb = A.add(s->sp_tbase);
     }
     size_t o_3si = 0, o_3li = 0, o_3lo = 0, o_3hn = 0, o_3hc = 0;
     if (s->hub3_ok) {
@@ -316,6 +318,8 @@ ecut_status upload(ecut_sectors *s) {
         s->dev_sp_pptr = (const int32_t *)(b + o_spp);
         s->dev_sp_pcol = (const int32_t *)(b + o_spc);
         s->dev_sp_pval = (const double *)(b + o_spv);
+        s->dev_sp_tab = (const uint16_t *)(b + o_spt);
+        s->dev_sp_tbase = (const int64_t *)(b + o_sptb);
     }
     s->dev_items = (ItemDev *)(b + o_items);
     if (s->hub_ok) {
@@ -565,8 +569,8 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
                                           : s->sp_lblocks.back().item0 +
                                                 s->sp_lblocks.back().n_rgroups * s->sp_lblocks.back().n_slabs;
         L.rows_per_item = s->tune.grid > 0 ? s->tune.grid : HUBU_ROWS;
-        e = launch_spin2(L, P, s->dev_items, s->sp_n_one, (int)s->items.size(), s->max_d_r,
-                         s->tune.n_xcd == 1 ? 1 : 8, st);
+        e = launch_spin2(L, P, s->dev_sp_tab, s->dev_sp_tbase, s->dev_items, s->sp_n_one, (int)s->items.size(),
+                         s->max_d_r, s->tune.n_xcd == 1 ? 1 : 8, st);
     } else if (P.spin_ok) {
         int grid = s->tune.grid;
         if (s->tune.order == 1) grid = std::max(8, ((grid > 0 ? grid : 2048) / 8) * 8);   // keeps chunk c on XCD c

@@ -408,6 +408,13 @@ struct ecut_sectors {
     std::vector<int32_t> sp_pptr, sp_pcol;   // left operator's CSR in that order (per block, at lbase)
     std::vector<double> sp_pval;
     bool sp2_ok = false;                     // every left word has at most 64 neighbours
+    // source columns of the right flip-flop terms and of the cross terms, per
+    // block: right term f of column e at tbase[2b] + ((f / 4) * d_R + e) * 4 + f % 4,
+    // cross term k at tbase[2b + 1] + k * d_R + e; 0xffff = no term
+    std::vector<uint16_t> sp_tab;
+    std::vector<int64_t> sp_tbase;
+    const uint16_t *dev_sp_tab = nullptr;
+    const int64_t *dev_sp_tbase = nullptr;
     std::vector<ecut::SpinLBlock> sp_lblocks;
     int32_t sp_n_one = 0;
     int32_t *dev_sp_rows = nullptr;

@@ -131,8 +131,8 @@ hipError_t launch_perm(const ecut_sectors *s, const uint64_t *binom_d, const Blo
 hipError_t launch_cdag(const CdagArgs &A, hipStream_t st);
 // two-pass spin kernels: left pass over slab items, then the one-row items
 // [0, n_one) and the several-row items [n_one, n_items) without the left operator
-hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const ItemDev *items_d, int n_one, int n_items,
-                        int max_d_r, int n_xcd, hipStream_t st);
+hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t *tab, const int64_t *tbase,
+                        const ItemDev *items_d, int n_one, int n_items, int max_d_r, int n_xcd, hipStream_t st);
 // canonical <-> bipartite layout of the spatial Hubbard cut (with signs)
 hipError_t launch_perm_hubsp(const HubSpPerm &A, const double *in, double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);

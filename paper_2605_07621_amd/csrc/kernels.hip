@@ -717,10 +717,15 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // the item's own row for the right operator.
 // LEFT: the left operator here; otherwise its sum is already in y (the
 // two-pass kernels' left pass) and is read as the starting value.
+// tabR / tabX (non-null): the block's source-column tables of the right
+// flip-flop terms and the cross terms (0xffff = no term) instead of ranking
+// the flipped words; the terms are summed in the same order either way.
 template <int NT, int M, bool LEFT>
 __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                              const int32_t *rl, const int32_t *rh, const uint32_t *fm,
-                                             const double *fc, int n_flip, double *red) {
+                                             const double *fc, int n_flip, double *red,
+                                             const uint16_t *__restrict__ tabR = nullptr,
+                                             const uint16_t *__restrict__ tabX = nullptr) {
     const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
     const int tid = threadIdx.x;
     const int dR = B.d_r;
@@ -793,10 +798,25 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             for (int kk = k; kk < k1; ++kk) {
                 const int rj = P.xbond[kk].rj;
                 const double c = P.xbond[kk].coef;
+                if (tabX) {
+                    uint32_t sx[M];
 #pragma unroll
-                for (int m = 0; m < M; ++m) {
-                    const int e = tid + m * NT;
-                    if (e < dR && ((wr[m] >> rj) & 1u) != bl) acc[m] += c * xs[rank16(wr[m] ^ (1u << rj), rl, rh)];
+                    for (int m = 0; m < M; ++m) {
+                        const int e = tid + m * NT;
+                        sx[m] = e < dR ? tabX[(int64_t)kk * dR + e] : 0u;
+                    }
+#pragma unroll
+                    for (int m = 0; m < M; ++m) {
+                        const int e = tid + m * NT;
+                        if (e < dR && ((wr[m] >> rj) & 1u) != bl) acc[m] += c * xs[sx[m]];
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < M; ++m) {
+                        const int e = tid + m * NT;
+                        if (e < dR && ((wr[m] >> rj) & 1u) != bl)
+                            acc[m] += c * xs[rank16(wr[m] ^ (1u << rj), rl, rh)];
+                    }
                 }
             }
         }
@@ -821,16 +841,41 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
     // right operator from the staged row, diagonal, epilogue
     double dgl = P.diag_l[gl];
     double part = 0.0;
+    double ra[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) ra[m] = 0.0;
+    if (tabR) {   // four terms' source columns per 8-byte load
+        for (int g = 0; g * 4 < n_flip; ++g) {
+            uint64_t t[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int e = tid + m * NT;
+                t[m] = e < dR ? *(const uint64_t *)(tabR + ((int64_t)g * dR + e) * 4) : ~0ull;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int f = 4 * g + i;
+                if (f >= n_flip) break;
+                const double cf = fc[f];
+#pragma unroll
+                for (int m = 0; m < M; ++m) {
+                    const uint32_t src = (uint32_t)(t[m] >> (16 * i)) & 0xffffu;
+                    if (src != 0xffffu) ra[m] += cf * xs[src];
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int e = tid + m * NT;
         if (e >= dR) continue;
         const uint32_t w = wr[m];
-        double a = 0.0;
-        for (int f = 0; f < n_flip; ++f) {
-            const uint32_t msk = fm[f];
-            if (__popc(w & msk) == 1) a += fc[f] * xs[rank16(w ^ msk, rl, rh)];
-        }
+        double a = ra[m];
+        if (!tabR)
+            for (int f = 0; f < n_flip; ++f) {
+                const uint32_t msk = fm[f];
+                if (__popc(w & msk) == 1) a += fc[f] * xs[rank16(w ^ msk, rl, rh)];
+            }
         double dg = dgl + P.diag_r[B.rbase + e];
         for (int x = 0; x < P.n_xdiag; ++x) {
             const XDiagDev X = P.xdiag[x];
@@ -1036,7 +1081,8 @@ __global__ __launch_bounds__(HUBU_THREADS) void k_spinL(const SpinLArgs A, int n
 
 template <bool ONE>
 __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, 2) void k_spinR(
-    const ProblemDev P, const ItemDev *__restrict__ items, int n_items, int n_xcd, int per_xcd) {
+    const ProblemDev P, const uint16_t *__restrict__ tab, const int64_t *__restrict__ tbase,
+    const ItemDev *__restrict__ items, int n_items, int n_xcd, int per_xcd) {
     constexpr int NT = ONE ? SPIN_THREADS : SPIN_MANY_THREADS;
     constexpr int M = ONE ? SPIN_M : SPIN_MANY_TILE / SPIN_MANY_THREADS;
     extern __shared__ __align__(16) double xs[];
@@ -1060,7 +1106,8 @@ __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, 2) void k_s
     __syncthreads();
     const BlockDev B = P.blocks[W.block];
     if (ONE)
-        spin_one_row<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
+        spin_one_row<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red, tab + tbase[2 * W.block],
+                                   tab + tbase[2 * W.block + 1]);
     else
         spin_many_rows<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
 }
@@ -2311,8 +2358,8 @@ hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, cons
     return hipGetLastError();
 }
 
-hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const ItemDev *items_d, int n_one, int n_items,
-                        int max_d_r, int n_xcd, hipStream_t st) {
+hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t *tab, const int64_t *tbase,
+                        const ItemDev *items_d, int n_one, int n_items, int max_d_r, int n_xcd, hipStream_t st) {
     if (max_d_r > SPIN_TILE) return hipErrorInvalidValue;
     const int xu = n_xcd == 1 ? 1 : 8;
     auto grid_of = [&](int n, int &per) {
@@ -2332,13 +2379,13 @@ hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const ItemDev *
     if (n_one > 0) {
         const dim3 g = grid_of(n_one, per);
         const size_t lds = (size_t)std::max(max_d_r, 1) * 8;
-        hipLaunchKernelGGL(k_spinR<true>, g, dim3(SPIN_THREADS), lds, st, P, items_d, n_one, xu, per);
+        hipLaunchKernelGGL(k_spinR<true>, g, dim3(SPIN_THREADS), lds, st, P, tab, tbase, items_d, n_one, xu, per);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n_items > n_one) {
         const dim3 g = grid_of(n_items - n_one, per);
-        hipLaunchKernelGGL(k_spinR<false>, g, dim3(SPIN_MANY_THREADS), (size_t)SPIN_MANY_TILE * 8, st, P,
+        hipLaunchKernelGGL(k_spinR<false>, g, dim3(SPIN_MANY_THREADS), (size_t)SPIN_MANY_TILE * 8, st, P, tab, tbase,
                            items_d + n_one, n_items - n_one, xu, per);
     }
     return hipGetLastError();

@@ -1103,6 +1103,33 @@ static void build_spin_tables(ecut_sectors *s) {
         for (int32_t a = 0; a < B.d_l; ++a) s->sp_level_rows[(size_t)B.lbase + a] = (int32_t)(key[a] & 0xffffffff);
     }
     s->sp2_ok = processing_csr(s, s->sp_level_rows, s->sp_pptr, s->sp_pcol, s->sp_pval) <= 64;
+    // source-column tables of the two-pass kernels' right pass
+    {
+        const int nf = (int)s->spin_fmask.size(), ng = (nf + 3) / 4, nx = (int)s->xbond.size();
+        s->sp_tbase.assign(2 * s->blocks.size(), 0);
+        int64_t n = 0;
+        for (size_t b = 0; b < s->blocks.size(); ++b) {
+            s->sp_tbase[2 * b] = n;
+            n += (int64_t)ng * 4 * s->blocks[b].d_r;
+            s->sp_tbase[2 * b + 1] = n;
+            n += (int64_t)nx * s->blocks[b].d_r;
+            n = (n + 3) & ~(int64_t)3;   // 8-byte aligned groups
+        }
+        s->sp_tab.assign((size_t)std::max<int64_t>(n, 4), 0xffff);
+        for (size_t b = 0; b < s->blocks.size(); ++b) {
+            const BlockDev &B = s->blocks[b];
+            for (int32_t e = 0; e < B.d_r; ++e) {
+                const uint32_t w = s->rwords[(size_t)B.rbase + e];
+                for (int f = 0; f < nf; ++f)
+                    if (__builtin_popcount(w & s->spin_fmask[f]) == 1)
+                        s->sp_tab[(size_t)(s->sp_tbase[2 * b] + ((int64_t)(f / 4) * B.d_r + e) * 4 + f % 4)] =
+                            (uint16_t)colex_rank(w ^ s->spin_fmask[f]);
+                for (int k = 0; k < nx; ++k)
+                    s->sp_tab[(size_t)(s->sp_tbase[2 * b + 1] + (int64_t)k * B.d_r + e)] =
+                        (uint16_t)colex_rank(w ^ (1u << s->xbond[k].rj));
+            }
+        }
+    }
     spin_left_blocks(s, HUBU_ROWS, s->sp_lblocks);
     s->spin_ok = true;
 }
