@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libecut.so")
+# ECUT_LIB: another build of the same library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("ECUT_LIB") or os.path.join(_HERE, "libecut.so")
 
 ECUT_OK, ECUT_EINVAL, ECUT_ENOMEM, ECUT_EDEVICE, ECUT_ENOTCONV, ECUT_EUNSUPPORTED, ECUT_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 ECUT_SPIN_HALF, ECUT_HUBBARD = 1, 2
