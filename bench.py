@@ -259,7 +259,7 @@ def kernel_name(S):
             return "k_hub3" if info.kernel_flags & 2 else "k_hub2"
         return {1: "k_hub", 2: "k_hub2", 3: "k_upslab+k_hub3", 4: "k_hubrow", 5: "k_hubseg", 6: "k_hubU+k_hubD",
                 7: "k_hubU+k_hub3"}[v]
-    if info.kernel_flags & 4 and t["variant"] == 2:
+    if info.kernel_flags & 64 and t["variant"] == 2:
         return "k_spinL+k_spinR"
     return "k_spin" if (info.kernel_flags & 4 and t["variant"] == 0) else "k_rows"
 

@@ -224,7 +224,7 @@ ecut_status upload(ecut_sectors *s) {
         o_hit = A.add(items_cap);
     }
     size_t o_srl = 0, o_srh = 0, o_sfm = 0, o_sfc = 0, o_hbm = 0, o_hbb = 0, o_hbc = 0;
-    if (s->spin_ok || s->hubrow_ok) {
+    if (s->spin_ok || s->hubrow_ok || s->sp2_ok) {
         o_srl = A.add(s->spin_rank_lo);
         o_srh = A.add(s->spin_rank_hi);
     }
@@ -234,7 +234,7 @@ ecut_status upload(ecut_sectors *s) {
         o_hbc = A.add(s->hrow_bcoef);
     }
     size_t o_spr = 0, o_spb = 0, o_spp = 0, o_spc = 0, o_spv = 0, o_spt = 0, o_sptb = 0;
-    if (s->spin_ok) {
+    if (s->spin_ok || s->sp2_ok) {
         o_sfm = A.add(s->spin_fmask);
         o_sfc = A.add(s->spin_fcoef);
         o_spr = A.add(s->sp_level_rows);
@@ -305,8 +305,8 @@ ecut_status upload(ecut_sectors *s) {
     P.maps = (const int32_t *)(b + o_maps);
     P.dim = s->dim;
     P.xscale = 1.0;
-    if (s->spin_ok) {
-        P.spin_ok = s->tune.variant == 0 ? 1 : 0;
+    if (s->spin_ok || s->sp2_ok) {
+        P.spin_ok = (s->spin_ok && s->tune.variant == 0) ? 1 : 0;
         P.n_rflip = (int32_t)s->spin_fmask.size();
         P.max_d_r = s->max_d_r;
         P.rank_lo = (const int32_t *)(b + o_srl);
@@ -555,7 +555,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
             const int grid = T.grid > 0 ? T.grid : n_cu;
             e = launch_hub(s, P, s->dev_row_order, s->blocks[0].d_l, grid, n_xcd, st);
         }
-    } else if (s->spin_ok && s->tune.variant == 2) {
+    } else if (s->sp2_ok && s->tune.variant == 2) {
         SpinLArgs L{};
         L.x = P.x;
         L.y = P.y;
@@ -570,7 +570,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
                                                 s->sp_lblocks.back().n_rgroups * s->sp_lblocks.back().n_slabs;
         L.rows_per_item = s->tune.grid > 0 ? s->tune.grid : HUBU_ROWS;
         e = launch_spin2(L, P, s->dev_sp_tab, s->dev_sp_tbase, s->dev_items, s->sp_n_one, (int)s->items.size(),
-                         s->max_d_r, s->tune.n_xcd == 1 ? 1 : 8, st);
+                         s->max_d_r, s->tune.n_xcd == 1 ? 1 : 8, s->hub_spatial, st);
     } else if (P.spin_ok) {
         int grid = s->tune.grid;
         if (s->tune.order == 1) grid = std::max(8, ((grid > 0 ? grid : 2048) / 8) * 8);   // keeps chunk c on XCD c
@@ -582,7 +582,7 @@ ecut_status launch_apply(const ecut_sectors *s, const ProblemDev &P, hipStream_t
     return ECUT_OK;
 }
 
-bool own_launch(const ecut_sectors *s) { return s->kernel == 1 || (s->spin_ok && s->tune.variant == 2); }
+bool own_launch(const ecut_sectors *s) { return s->kernel == 1 || (s->sp2_ok && s->tune.variant == 2); }
 
 bool hub6_batchable(const ecut_sectors *s) {
     return s->kernel == 1 && s->hub6_ok && s->tune.variant == 6 && s->h6_maxq <= HUBD_BATCH_SLOTS;
@@ -897,7 +897,7 @@ ecut_status ecut_sectors_get_info(const ecut_sectors *s, ecut_sectors_info *info
     I.n_cross_diag = (int32_t)s->xdiag.size();
     I.kernel = s->kernel;
     I.kernel_flags = (s->hub2_ok ? 1 : 0) | (s->hub3_ok ? 2 : 0) | (s->spin_ok ? 4 : 0) | (s->hubrow_ok ? 8 : 0) |
-                     (s->hubseg_ok ? 16 : 0) | (s->hub6_ok ? 32 : 0) | (s->spin_ok && s->sp2_ok ? 64 : 0);
+                     (s->hubseg_ok ? 16 : 0) | (s->hub6_ok ? 32 : 0) | (s->sp2_ok ? 64 : 0);
     I.device_bytes = (int64_t)s->dev_bytes;
     I.n_eff = s->n_eff;
     *info = I;

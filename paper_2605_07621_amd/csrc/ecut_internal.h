@@ -411,6 +411,8 @@ struct ecut_sectors {
     // source columns of the right flip-flop terms and of the cross terms, per
     // block: right term f of column e at tbase[2b] + ((f / 4) * d_R + e) * 4 + f % 4,
     // cross term k at tbase[2b + 1] + k * d_R + e; 0xffff = no term
+    std::vector<uint32_t> sp_rbetw;          // spatial Hubbard cut: bits between the two sites of each right hop
+    std::vector<ecut::ItemDev> generic_items; // spatial Hubbard cut: the row kernel's items (variants 0, 1)
     std::vector<uint16_t> sp_tab;
     std::vector<int64_t> sp_tbase;
     const uint16_t *dev_sp_tab = nullptr;

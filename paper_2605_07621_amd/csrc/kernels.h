@@ -28,6 +28,8 @@ constexpr int SPIN_THREADS = 512;
 constexpr int SPIN_M = 13;                   // element slots per thread of the spin kernel
 constexpr int SPIN_TILE = SPIN_THREADS * SPIN_M;
 constexpr int SPIN_MAX_FLIP = 64;            // flip-flop terms inside the right part
+constexpr int SPIN_SHORT_THREADS = 256;      // two-pass one-row items of rows up to 256 x 5 amplitudes
+constexpr int SPIN_SHORT_M = 5;
 constexpr int SPIN_MANY_THREADS = 256;       // kernel for items of several short rows
 constexpr int SPIN_MANY_TILE = 512;          // most amplitudes per such item: the default and largest tile
 constexpr int HUBROW_THREADS = 1024;
@@ -132,7 +134,8 @@ hipError_t launch_cdag(const CdagArgs &A, hipStream_t st);
 // two-pass spin kernels: left pass over slab items, then the one-row items
 // [0, n_one) and the several-row items [n_one, n_items) without the left operator
 hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t *tab, const int64_t *tbase,
-                        const ItemDev *items_d, int n_one, int n_items, int max_d_r, int n_xcd, hipStream_t st);
+                        const ItemDev *items_d, int n_one, int n_items, int max_d_r, int n_xcd, bool fermion,
+                        hipStream_t st);
 // canonical <-> bipartite layout of the spatial Hubbard cut (with signs)
 hipError_t launch_perm_hubsp(const HubSpPerm &A, const double *in, double *out, bool to_bip, hipStream_t st);
 hipError_t launch_reduce(const VecJob *jobs_d, int n_jobs, hipStream_t st);

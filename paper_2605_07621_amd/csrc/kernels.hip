@@ -720,7 +720,10 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // tabR / tabX (non-null): the block's source-column tables of the right
 // flip-flop terms and the cross terms (0xffff = no term) instead of ranking
 // the flipped words; the terms are summed in the same order either way.
-template <int NT, int M, bool LEFT>
+// FERM: the spatial Hubbard cut's cross terms (block by the mode's spin,
+// fermion signs from the maps and the tables' bit 15) and right hops with
+// signs; spin problems compile without them.
+template <int NT, int M, bool LEFT, bool FERM = false>
 __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                              const int32_t *rl, const int32_t *rh, const uint32_t *fm,
                                              const double *fc, int n_flip, double *red,
@@ -775,8 +778,18 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
         int k1 = k + 1;
         while (k1 < nx && P.xbond[k1].li == li) ++k1;
         const uint32_t bl = (lw >> li) & 1u;
-        const int src = bl ? B.blk_lminus : B.blk_lplus;
-        const int lp = src >= 0 ? P.maps[(bl ? P.xbond[k].lmap_del : P.xbond[k].lmap_ins) + gl] : -1;
+        // the block with one particle of this mode's kind more or fewer on the left
+        int src;
+        if constexpr (FERM)
+            src = P.xbond[k].label ? (bl ? B.blk_l2minus : B.blk_l2plus) : (bl ? B.blk_lminus : B.blk_lplus);
+        else
+            src = bl ? B.blk_lminus : B.blk_lplus;
+        int lp = src >= 0 ? P.maps[(bl ? P.xbond[k].lmap_del : P.xbond[k].lmap_ins) + gl] : -1;
+        bool lneg = false;   // fermions: the left part's sign, in the map's low bit
+        if (FERM && lp >= 0) {
+            lneg = lp & 1;
+            lp >>= 1;
+        }
         if (lp >= 0) {
             const BlockDev S = P.blocks[src];
             const double *__restrict__ srow = P.x + S.offset + (int64_t)lp * S.d_r;
@@ -797,8 +810,8 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             __syncthreads();
             for (int kk = k; kk < k1; ++kk) {
                 const int rj = P.xbond[kk].rj;
-                const double c = P.xbond[kk].coef;
-                if (tabX) {
+                const double c = lneg ? -P.xbond[kk].coef : P.xbond[kk].coef;
+                if (tabX) {   // source column in bits 0..14, the right part's sign in bit 15
                     uint32_t sx[M];
 #pragma unroll
                     for (int m = 0; m < M; ++m) {
@@ -808,7 +821,12 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
 #pragma unroll
                     for (int m = 0; m < M; ++m) {
                         const int e = tid + m * NT;
-                        if (e < dR && ((wr[m] >> rj) & 1u) != bl) acc[m] += c * xs[sx[m]];
+                        if (e < dR && ((wr[m] >> rj) & 1u) != bl) {
+                            if constexpr (FERM)
+                                acc[m] += (sx[m] & 0x8000u ? -c : c) * xs[sx[m] & 0x7fffu];
+                            else
+                                acc[m] += c * xs[sx[m]];
+                        }
                     }
                 } else {
 #pragma unroll
@@ -860,7 +878,12 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const uint32_t src = (uint32_t)(t[m] >> (16 * i)) & 0xffffu;
-                    if (src != 0xffffu) ra[m] += cf * xs[src];
+                    if (src != 0xffffu) {
+                        if constexpr (FERM)
+                            ra[m] += (src & 0x8000u ? -cf : cf) * xs[src & 0x7fffu];
+                        else
+                            ra[m] += cf * xs[src];
+                    }
                 }
             }
         }
@@ -879,7 +902,18 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
         double dg = dgl + P.diag_r[B.rbase + e];
         for (int x = 0; x < P.n_xdiag; ++x) {
             const XDiagDev X = P.xdiag[x];
-            dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
+            if constexpr (FERM) {   // densities of the two sites (V n_i n_j)
+                double fl = (double)((lw >> X.li) & 1u), fr = (double)((w >> X.rj) & 1u);
+                if (X.li2 >= 0) fl += (double)((lw >> X.li2) & 1u);
+                if (X.rj2 >= 0) fr += (double)((w >> X.rj2) & 1u);
+                if (X.spin_form) {
+                    fl -= 0.5;
+                    fr -= 0.5;
+                }
+                dg += X.coef * fl * fr;
+            } else {
+                dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
+            }
         }
         const double x0 = xs[e];
         double yv = ef.x * (acc[m] + a + dg * x0);
@@ -1079,16 +1113,20 @@ __global__ __launch_bounds__(HUBU_THREADS) void k_spinL(const SpinLArgs A, int n
     hubU_item<false, STREAM>(U, it - L.item0);
 }
 
-template <bool ONE>
-__global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, 2) void k_spinR(
+// ONE: one-row items on NT1 threads with M1 amplitudes each (512 x 13 for
+// rows of up to 6,656 amplitudes, 256 x 5 for rows of up to 1,280); the
+// source-column tables replace the ranking tables, which only the items of
+// several rows (ONE = false) load.
+template <bool ONE, int NT1, int M1, bool FERM>
+__global__ __launch_bounds__(ONE ? NT1 : SPIN_MANY_THREADS, (ONE && NT1 == SPIN_THREADS) ? 4 : 2) void k_spinR(
     const ProblemDev P, const uint16_t *__restrict__ tab, const int64_t *__restrict__ tbase,
     const ItemDev *__restrict__ items, int n_items, int n_xcd, int per_xcd) {
-    constexpr int NT = ONE ? SPIN_THREADS : SPIN_MANY_THREADS;
-    constexpr int M = ONE ? SPIN_M : SPIN_MANY_TILE / SPIN_MANY_THREADS;
+    constexpr int NT = ONE ? NT1 : SPIN_MANY_THREADS;
+    constexpr int M = ONE ? M1 : SPIN_MANY_TILE / SPIN_MANY_THREADS;
     extern __shared__ __align__(16) double xs[];
     __shared__ double red[NT / 64];
-    __shared__ int32_t rl[256];
-    __shared__ int32_t rh[256 * 9];
+    __shared__ int32_t rl[ONE ? 1 : 256];
+    __shared__ int32_t rh[ONE ? 1 : 256 * 9];
     __shared__ uint32_t fm[SPIN_MAX_FLIP];
     __shared__ double fc[SPIN_MAX_FLIP];
     const int it = xcd_item(n_xcd, per_xcd);
@@ -1097,17 +1135,19 @@ __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, 2) void k_s
     if (W.row1 <= W.row0) return;
     const int tid = threadIdx.x;
     const int n_flip = P.n_rflip;
-    for (int i = tid; i < 256; i += NT) rl[i] = P.rank_lo[i];
-    for (int i = tid; i < 256 * 9; i += NT) rh[i] = P.rank_hi[i];
+    if (!ONE) {
+        for (int i = tid; i < 256; i += NT) rl[i] = P.rank_lo[i];
+        for (int i = tid; i < 256 * 9; i += NT) rh[i] = P.rank_hi[i];
+    }
     for (int i = tid; i < n_flip; i += NT) {
         fm[i] = P.rflip_mask[i];
         fc[i] = P.rflip_coef[i];
     }
     __syncthreads();
     const BlockDev B = P.blocks[W.block];
-    if (ONE)
-        spin_one_row<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red, tab + tbase[2 * W.block],
-                                   tab + tbase[2 * W.block + 1]);
+    if constexpr (ONE)
+        spin_one_row<NT, M, false, FERM>(P, B, W, xs, rl, rh, fm, fc, n_flip, red, tab + tbase[2 * W.block],
+                                         tab + tbase[2 * W.block + 1]);
     else
         spin_many_rows<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
 }
@@ -2359,7 +2399,8 @@ hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, cons
 }
 
 hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t *tab, const int64_t *tbase,
-                        const ItemDev *items_d, int n_one, int n_items, int max_d_r, int n_xcd, hipStream_t st) {
+                        const ItemDev *items_d, int n_one, int n_items, int max_d_r, int n_xcd, bool fermion,
+                        hipStream_t st) {
     if (max_d_r > SPIN_TILE) return hipErrorInvalidValue;
     const int xu = n_xcd == 1 ? 1 : 8;
     auto grid_of = [&](int n, int &per) {
@@ -2379,14 +2420,22 @@ hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t 
     if (n_one > 0) {
         const dim3 g = grid_of(n_one, per);
         const size_t lds = (size_t)std::max(max_d_r, 1) * 8;
-        hipLaunchKernelGGL(k_spinR<true>, g, dim3(SPIN_THREADS), lds, st, P, tab, tbase, items_d, n_one, xu, per);
+        const bool short_rows = max_d_r <= SPIN_SHORT_THREADS * SPIN_SHORT_M;
+#define ECUT_SPINR(NT_, M_, F_)                                                                              \
+    hipLaunchKernelGGL((k_spinR<true, NT_, M_, F_>), g, dim3(NT_), lds, st, P, tab, tbase, items_d, n_one, xu, per)
+        if (short_rows && fermion) ECUT_SPINR(SPIN_SHORT_THREADS, SPIN_SHORT_M, true);
+        else if (short_rows) ECUT_SPINR(SPIN_SHORT_THREADS, SPIN_SHORT_M, false);
+        else if (fermion) ECUT_SPINR(SPIN_THREADS, SPIN_M, true);
+        else ECUT_SPINR(SPIN_THREADS, SPIN_M, false);
+#undef ECUT_SPINR
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (n_items > n_one) {
         const dim3 g = grid_of(n_items - n_one, per);
-        hipLaunchKernelGGL(k_spinR<false>, g, dim3(SPIN_MANY_THREADS), (size_t)SPIN_MANY_TILE * 8, st, P, tab, tbase,
-                           items_d + n_one, n_items - n_one, xu, per);
+        if (fermion) return hipErrorInvalidValue;   // the several-row items rank without signs
+        hipLaunchKernelGGL((k_spinR<false, SPIN_THREADS, SPIN_M, false>), g, dim3(SPIN_MANY_THREADS),
+                           (size_t)SPIN_MANY_TILE * 8, st, P, tab, tbase, items_d + n_one, n_items - n_one, xu, per);
     }
     return hipGetLastError();
 }

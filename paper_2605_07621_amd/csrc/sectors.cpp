@@ -138,6 +138,7 @@ inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
 
 static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
 static void build_spin_tables(ecut_sectors *s);
+static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<uint32_t> &rbetw);
 static int inversions(uint32_t w, int n);
 static void build_hubseg_tables(ecut_sectors *s);
 static void make_rank_tables(ecut_sectors *s);
@@ -333,6 +334,26 @@ static ecut_status build_hubbard_spatial(const ecut_model_desc *m, const ecut_cu
                 s->maps.push_back(e);
             }
             s->xbond.push_back(X);
+        }
+    }
+    // the cross terms of one left mode together (the two-pass kernels stage
+    // the one source row of a left mode once for all its terms)
+    std::stable_sort(s->xbond.begin(), s->xbond.end(), [](const XBondDev &a, const XBondDev &b) { return a.li < b.li; });
+    // hops inside R as right terms of the two-pass kernels: the two bits of
+    // the hop in the right word, the bits strictly between them (the fermion
+    // sign), the value -t
+    s->spin_fmask.clear();
+    s->spin_fcoef.clear();
+    s->sp_rbetw.clear();
+    for (int b = 0; b < m->n_bonds; ++b) {
+        const int i = m->bond_i[b], j = m->bond_j[b];
+        if (side[i] != 1 || side[j] != 1 || m->t[b] == 0.0) continue;
+        const int lo = std::min(loc[i], loc[j]), hi = std::max(loc[i], loc[j]);
+        for (int spin = 0; spin < 2; ++spin) {
+            const int o = spin == 0 ? nR : 0;
+            s->spin_fmask.push_back((1u << (o + lo)) | (1u << (o + hi)));
+            s->sp_rbetw.push_back(((1u << (o + hi)) - 1u) & ~((1u << (o + lo + 1)) - 1u));
+            s->spin_fcoef.push_back(-m->t[b]);
         }
     }
     s->hub_spatial = true;
@@ -546,6 +567,16 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
     s->hub_ok = false;
     s->kernel = 2;
     build_spin_tables(s);
+    if (s->hub_spatial) {
+        // two-pass kernels over one-row items (every row its own item)
+        s->generic_items = s->items;
+        make_rank_tables(s);
+        build_two_pass_tables(s, 2 * (int)s->lsites.size(), s->sp_rbetw);
+        size_t rows = 0;
+        for (const BlockDev &B : s->blocks) rows += (size_t)B.d_l;
+        s->items_cap = std::max(s->items_cap, rows);
+        s->item_slots_cap = std::max<int32_t>(s->item_slots_cap, (int32_t)rows);
+    }
     if (s->kind == ECUT_HUBBARD && s->cut_kind == ECUT_CUT_UPDN) build_hub_tables(s, m);
     return ECUT_OK;
 }
@@ -1091,47 +1122,79 @@ static void build_spin_tables(ecut_sectors *s) {
     s->item_slots_cap = (int32_t)std::max(s->items.size(), rows);
     s->items_cap = 8 * (size_t)s->item_slots_cap;
     make_rank_tables(s);
-    // two-pass kernels: the rows of every block by inversion level of the
-    // left word (a flip-flop on bond (i, j) moves a word |i - j| levels, so
-    // the neighbour rows of a level lie in the levels next to it)
+    build_two_pass_tables(s, (int)s->lsites.size(), {});
+    s->spin_ok = true;
+}
+
+// Tables of the two-pass row kernels (spin problems and the spatial Hubbard
+// cut), for left words of lbits bits:
+//  - the rows of every block by inversion level of the left word (a hop or
+//    flip-flop on bond (i, j) moves a word at most |i - j| levels, so the
+//    neighbour rows of a level lie in the levels next to it), and the left
+//    operator's CSR in that order;
+//  - per block, the source column of every right term (spin_fmask /
+//    spin_fcoef: a flip-flop or a hop of one spin, with the fermion sign
+//    (-1)^popc(w & rbetw[f]) when rbetw is given) and of every cross term
+//    (the right word with bit rj flipped; on the spatial Hubbard cut with
+//    the right part's sign (-1)^(occupied modes before the mode)), in the
+//    low 15 bits, the sign in bit 15, 0xffff for no term.
+static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<uint32_t> &rbetw) {
+    s->sp2_ok = false;
+    if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP || s->max_d_r > SPIN_TILE) return;
+    const int nR = (int)s->rsites.size();
+    const bool fermion = s->hub_spatial;
+    // a right word's column inside its group
+    auto rank = [&](uint32_t w) -> int64_t {
+        if (!fermion) return colex_rank(w);
+        const uint32_t dn = w & ((1u << nR) - 1u), up = w >> nR;
+        return colex_rank(up) * (int64_t)binom(nR, __builtin_popcount(dn)) + colex_rank(dn);
+    };
+    // occupied modes of the right word before mode (spin, site k): up modes
+    // first, then down modes, each by site
+    auto occ_before = [&](uint32_t w, int spin, int k) {
+        const uint32_t dn = w & ((1u << nR) - 1u), up = w >> nR, below = (1u << k) - 1u;
+        return spin == 0 ? __builtin_popcount(up & below) : __builtin_popcount(up) + __builtin_popcount(dn & below);
+    };
     s->sp_level_rows.assign(s->lwords.size(), 0);
     for (const BlockDev &B : s->blocks) {
         std::vector<int64_t> key((size_t)B.d_l);
         for (int32_t a = 0; a < B.d_l; ++a)
-            key[a] = (int64_t)inversions(s->lwords[(size_t)B.lbase + a], (int)s->lsites.size()) << 32 | a;
+            key[a] = (int64_t)inversions(s->lwords[(size_t)B.lbase + a], lbits) << 32 | a;
         std::sort(key.begin(), key.end());
         for (int32_t a = 0; a < B.d_l; ++a) s->sp_level_rows[(size_t)B.lbase + a] = (int32_t)(key[a] & 0xffffffff);
     }
-    s->sp2_ok = processing_csr(s, s->sp_level_rows, s->sp_pptr, s->sp_pcol, s->sp_pval) <= 64;
-    // source-column tables of the two-pass kernels' right pass
-    {
-        const int nf = (int)s->spin_fmask.size(), ng = (nf + 3) / 4, nx = (int)s->xbond.size();
-        s->sp_tbase.assign(2 * s->blocks.size(), 0);
-        int64_t n = 0;
-        for (size_t b = 0; b < s->blocks.size(); ++b) {
-            s->sp_tbase[2 * b] = n;
-            n += (int64_t)ng * 4 * s->blocks[b].d_r;
-            s->sp_tbase[2 * b + 1] = n;
-            n += (int64_t)nx * s->blocks[b].d_r;
-            n = (n + 3) & ~(int64_t)3;   // 8-byte aligned groups
-        }
-        s->sp_tab.assign((size_t)std::max<int64_t>(n, 4), 0xffff);
-        for (size_t b = 0; b < s->blocks.size(); ++b) {
-            const BlockDev &B = s->blocks[b];
-            for (int32_t e = 0; e < B.d_r; ++e) {
-                const uint32_t w = s->rwords[(size_t)B.rbase + e];
-                for (int f = 0; f < nf; ++f)
-                    if (__builtin_popcount(w & s->spin_fmask[f]) == 1)
-                        s->sp_tab[(size_t)(s->sp_tbase[2 * b] + ((int64_t)(f / 4) * B.d_r + e) * 4 + f % 4)] =
-                            (uint16_t)colex_rank(w ^ s->spin_fmask[f]);
-                for (int k = 0; k < nx; ++k)
-                    s->sp_tab[(size_t)(s->sp_tbase[2 * b + 1] + (int64_t)k * B.d_r + e)] =
-                        (uint16_t)colex_rank(w ^ (1u << s->xbond[k].rj));
+    const bool csr_ok = processing_csr(s, s->sp_level_rows, s->sp_pptr, s->sp_pcol, s->sp_pval) <= 64;
+    const int nf = (int)s->spin_fmask.size(), ng = (nf + 3) / 4, nx = (int)s->xbond.size();
+    s->sp_tbase.assign(2 * s->blocks.size(), 0);
+    int64_t n = 0;
+    for (size_t b = 0; b < s->blocks.size(); ++b) {
+        s->sp_tbase[2 * b] = n;
+        n += (int64_t)ng * 4 * s->blocks[b].d_r;
+        s->sp_tbase[2 * b + 1] = n;
+        n += (int64_t)nx * s->blocks[b].d_r;
+        n = (n + 3) & ~(int64_t)3;   // 8-byte aligned groups
+    }
+    s->sp_tab.assign((size_t)std::max<int64_t>(n, 4), 0xffff);
+    for (size_t b = 0; b < s->blocks.size(); ++b) {
+        const BlockDev &B = s->blocks[b];
+        for (int32_t e = 0; e < B.d_r; ++e) {
+            const uint32_t w = s->rwords[(size_t)B.rbase + e];
+            for (int f = 0; f < nf; ++f)
+                if (__builtin_popcount(w & s->spin_fmask[f]) == 1) {
+                    const int sg = rbetw.empty() ? 0 : (__builtin_popcount(w & rbetw[f]) & 1);
+                    s->sp_tab[(size_t)(s->sp_tbase[2 * b] + ((int64_t)(f / 4) * B.d_r + e) * 4 + f % 4)] =
+                        (uint16_t)(rank(w ^ s->spin_fmask[f]) | (sg << 15));
+                }
+            for (int k = 0; k < nx; ++k) {
+                const XBondDev &X = s->xbond[k];
+                const int sg = fermion ? (occ_before(w, X.label, X.label ? X.rj : X.rj - nR) & 1) : 0;
+                s->sp_tab[(size_t)(s->sp_tbase[2 * b + 1] + (int64_t)k * B.d_r + e)] =
+                    (uint16_t)(rank(w ^ (1u << X.rj)) | (sg << 15));
             }
         }
     }
     spin_left_blocks(s, HUBU_ROWS, s->sp_lblocks);
-    s->spin_ok = true;
+    s->sp2_ok = csr_ok && s->max_d_r < 32768;
 }
 
 int32_t processing_csr(const ecut_sectors *s, const std::vector<int32_t> &order, std::vector<int32_t> &pptr,

@@ -75,15 +75,17 @@ void write_cache(const char *path, const std::map<std::string, ApplyTuning> &m) 
 ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
     if (T.order < 0 || T.order > 10 || T.grid < 0 || T.n_xcd < 0 || T.variant < 0 || T.variant > 7)
         return fail(ECUT_EINVAL, "bad tuning");
-    if (s->kernel != 1 && T.variant > (s->spin_ok ? 2 : 1))
-        return fail(ECUT_EINVAL, "spin problems take variant 0, 1 or 2, generic problems 0 or 1");
+    if (s->kernel != 1 && T.variant > (s->spin_ok || s->sp2_ok ? 2 : 1))
+        return fail(ECUT_EINVAL, "spin problems take variant 0, 1 or 2, generic problems 0 or 1 (2 with two-pass tables)");
+    if (s->kernel != 1 && T.variant == 2) {
+        if (!s->sp2_ok)
+            return fail(ECUT_EUNSUPPORTED, "two-pass row kernels need at most 64 left-operator terms per row");
+        if (T.grid > HUBU_RMAX * (HUBU_THREADS / 64))
+            return fail(ECUT_EINVAL, "left-pass items of the two-pass row kernels take at most 32 rows");
+    }
     if (T.tile < 0) return fail(ECUT_EINVAL, "tile must not be negative");
     if (s->spin_ok) {
         if (T.tile > SPIN_MANY_TILE) return fail(ECUT_EINVAL, "tile must lie in 0..512");
-        if (T.variant == 2 && T.grid > HUBU_RMAX * (HUBU_THREADS / 64))
-            return fail(ECUT_EINVAL, "left-pass items of the two-pass spin kernels take at most 32 rows");
-        if (T.variant == 2 && !s->sp2_ok)
-            return fail(ECUT_EUNSUPPORTED, "two-pass spin kernels need at most 64 left-operator terms per row");
     } else if (s->kernel == 1 && T.variant == 4) {
         // the whole-row Hubbard kernel: tile = threads per work group
         if (T.tile != 0 && T.tile != 256 && T.tile != 512 && T.tile != 1024)
@@ -142,7 +144,22 @@ ecut_status apply_tuning(ecut_sectors *s, const ApplyTuning &T) {
         s->items.swap(items);
         s->item_slots = slots;
     }
-    if (s->spin_ok) {
+    if (s->hub_spatial && s->sp2_ok && (T.variant == 2) != (s->tune.variant == 2)) {
+        // every row its own item for the two-pass kernels, else the row kernel's tiles
+        std::vector<ItemDev> items;
+        const int32_t slots = T.variant == 2 ? make_spin_items(s, 1, 2, items)
+                                             : (items = s->generic_items, (int32_t)items.size());
+        if (items.size() > s->items_cap || slots > s->item_slots_cap)
+            return fail(ECUT_EINVAL, "work list exceeds its buffer");
+        if (s->on_device && s->dev_items) {
+            hipError_t e =
+                hipMemcpy(s->dev_items, items.data(), items.size() * sizeof(ItemDev), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpy(work items)");
+        }
+        s->items.swap(items);
+        s->item_slots = slots;
+    }
+    if (s->spin_ok || s->sp2_ok) {
         s->sp_n_one = 0;
         if (spin_order == 2)
             for (const ItemDev &it : s->items) s->sp_n_one += (it.row1 - it.row0 == 1) ? 1 : 0;
@@ -242,6 +259,9 @@ ecut_status ecut_autotune(ecut_sectors *s, const double *x_d, double *y_d, void 
                 for (int xcd : {1, 8}) cands.push_back(ApplyTuning{rows, xcd, 0, 2, 0});
     } else {
         cands.push_back(ApplyTuning{0, 0, 0, 0, 0});
+        if (s->sp2_ok)   // the spatial Hubbard cut: the two-pass row kernels
+            for (int rows : {4, 8, 16})
+                for (int xcd : {1, 8}) cands.push_back(ApplyTuning{rows, xcd, 0, 2, 0});
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

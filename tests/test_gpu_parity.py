@@ -1106,7 +1106,15 @@ def test_spatial_hubbard_apply_vs_oracle(dev, k):
     S = _ecut().Sectors(m, I.Cut("spatial", mask), nu, nd)
     s = O.Sector(m, nu, nd)
     psi = I.psi(2700 + k, s.n)
-    _compare(_gpu_apply_canonical(S, psi, dev), s.apply(psi), f"{m.name} mask {mask:#x}")
+    y_ref = s.apply(psi)
+    _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{m.name} mask {mask:#x}")
+    # the two-pass row kernels (signed source-column tables), every item shape
+    assert S.info.kernel_flags & 64
+    for rows, xcd in ((0, 8), (4, 1), (16, 8), (32, 1)):
+        S.set_tuning(rows, xcd, 0, 2, 0)
+        _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{m.name} mask {mask:#x} two-pass {rows},{xcd}")
+    S.set_tuning(0, 0, 0, 0, 0)   # and back to the row kernel
+    _compare(_gpu_apply_canonical(S, psi, dev), y_ref, f"{m.name} mask {mask:#x} row kernel again")
 
 
 def test_spatial_hubbard14_full_vector_vs_oracle(dev):
@@ -1127,6 +1135,11 @@ def test_spatial_hubbard14_full_vector_vs_oracle(dev):
     y_ref = s.apply(psi, use_csr=False)
     print(f"[full] oracle apply {time.time() - t0:.1f} s", flush=True)
     _compare_full(_gpu_apply_canonical(S, psi, dev), y_ref, "spatial hubbard14 V=1")
+    S.set_tuning(8, 8, 0, 2, 0)
+    _compare_full(_gpu_apply_canonical(S, psi, dev), y_ref, "spatial hubbard14 V=1, two-pass")
+    x = torch.from_numpy(psi).to(dev)
+    print("[full] spatial hubbard14 autotuned", S.autotune(S.import_(x), torch.empty_like(x)), flush=True)
+    _compare_full(_gpu_apply_canonical(S, psi, dev), y_ref, "spatial hubbard14 V=1, autotuned")
     xb = S.import_(torch.from_numpy(psi).to(dev))
     pb = S.import_(torch.from_numpy(I.psi(2751, s.n)).to(dev))
     lhs = torch.dot(pb, S.apply(xb)).item()
@@ -1152,6 +1165,10 @@ def test_spatial_hubbard_lanczos_and_entanglement_vs_oracle(dev):
     v0 = torch.from_numpy(I.psi(2761, S.dim)).to(dev)
     e, st, _ = S.lanczos(v0, 300, tol=1e-12)
     assert abs(e - e0) <= 1e-10 * abs(e0), (e, e0)
+    S.set_tuning(8, 8, 0, 2, 0)   # the two-pass row kernels, with the Lanczos partials of their items
+    e2, st2, _ = S.lanczos(v0, 300, tol=1e-12)
+    assert abs(e2 - e0) <= 1e-10 * abs(e0), (e2, e0)
+    S.set_tuning(0, 0, 0, 0, 0)
     ref = O.entanglement(s, g, "spatial", I.left_mask_first(5), cutoff=1e-10)
     got = S.entanglement(S.import_(torch.from_numpy(g).to(dev)), cutoff=1e-10)
     _ent_compare(got, ref, "spatial hubbard10", 1e-13)
