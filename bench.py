@@ -298,9 +298,9 @@ def other_workloads(names, stream):
         out[name] = {"dim": S.dim, "blocks": int(S.info.n_blocks), "kernel": kernel_name(S), "ms": round(ms, 4),
                      "applies_per_s": round(1e3 / ms, 2), "algorithmic_GBps": round(alg / (ms * 1e-3) / 1e9, 1)}
         steps = p.meta.get("lanczos_steps")
-        if name == "j1j2_6x5":
-            # Lanczos energy of the 6x5 lattice to 1e-10 (three-term recurrence)
-            # against the oracle's stored energy
+        if name in ("j1j2_6x5", "hubbard14_spatial"):
+            # Lanczos energy to 1e-10 (three-term recurrence) against the
+            # oracle's stored energy
             v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to("cuda:0"))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -666,8 +666,8 @@ def main():
     torch.cuda.empty_cache()
     progress(f"headline done: {kern_ms:.4f} ms per apply")
     if not args.no_others:
-        line["other_workloads"] = other_workloads([w for w in ("heisenberg16", "hubbard12", "j1j2_6x5")
-                                                   if w != args.workload], stream)
+        line["other_workloads"] = other_workloads([w for w in ("heisenberg16", "hubbard12", "j1j2_6x5",
+                                                             "hubbard14_spatial") if w != args.workload], stream)
     progress("other workloads done")
     if not args.no_solve:
         p.meta["name"] = args.workload

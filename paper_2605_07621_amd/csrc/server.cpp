@@ -168,6 +168,7 @@ static std::mutex g_tune_mu;
 // Hubbard problems up to this many amplitudes (chains of up to 10 sites at
 // half filling) share the merged two-pass launches of a step
 static constexpr int64_t SMALL_HUB_DIM = (int64_t)1 << 18;
+static constexpr int64_t SMALL_SPIN_DIM = (int64_t)1 << 20;
 static std::map<std::string, ecut_tuning> g_tunings;
 
 static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStream_t st) {
@@ -186,6 +187,12 @@ static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStr
         rs = ecut_set_tuning(s, &best);
     } else {
         rs = ecut_autotune(s, x, y, st, &best);
+        if (rs == ECUT_OK && s->spin_ok && s->dim <= SMALL_SPIN_DIM && best.variant != 0) {
+            // small spin problems keep the one-pass kernel, whose work items
+            // join every other spin problem's in one merged launch per step
+            best = ecut_tuning{0, 0, 0, 0, 0};
+            rs = ecut_set_tuning(s, &best);
+        }
     }
     if (rs != ECUT_OK) return rs;
     std::lock_guard<std::mutex> g(g_tune_mu);

@@ -158,11 +158,20 @@ def j1j2_6x5():
     return Problem(m, Cut("spatial", left_mask_first(15)), 15, meta=dict(seed=1004))
 
 
+def hubbard14_spatial():
+    """Extended Hubbard open chain of the paper's spatial-cut ED benchmark:
+    14 sites, t=1, U=4, V=1 on every bond, N_up=N_dn=7, cut 7|7
+    (11,778,624 amplitudes in 64 blocks (N_up_L, N_dn_L))."""
+    return Problem(hubbard_chain(14, 1.0, 4.0, V=1.0), Cut("spatial", left_mask_first(7)), 7, 7,
+                   meta=dict(seed=1005))
+
+
 WORKLOADS = {
     "heisenberg16": heisenberg16,
     "hubbard12": hubbard12,
     "hubbard16": hubbard16,
     "j1j2_6x5": j1j2_6x5,
+    "hubbard14_spatial": hubbard14_spatial,
 }
 
 

@@ -7,7 +7,7 @@ in a row.
 
 Usage:
   python tests/golden/make_golden.py [name ...]
-    names: heisenberg16 hubbard12 hubbard16 j1j2_6x5 serving
+    names: heisenberg16 hubbard12 hubbard16 j1j2_6x5 hubbard14_spatial serving
   --rows   apply H row by row (no stored matrix) instead of through CSR;
            the 6x5 J1-J2 sector's CSR takes about 86 GB of host memory, so
            it defaults to row-by-row when the host has less than 120 GB.

@@ -1173,3 +1173,22 @@ def test_spatial_hubbard_lanczos_and_entanglement_vs_oracle(dev):
     got = S.entanglement(S.import_(torch.from_numpy(g).to(dev)), cutoff=1e-10)
     _ent_compare(got, ref, "spatial hubbard10", 1e-13)
     assert abs(got["n_eff"] - ref["n_eff"]) <= 1e-12
+
+
+def test_lanczos_hubbard14_spatial_vs_golden(dev):
+    """The paper's spatial-cut ED benchmark (14-site extended Hubbard chain,
+    V=1, cut 7|7) on the autotuned kernel: three-term Lanczos to 1e-10
+    against the oracle's energy (tests/golden, written from the oracle's CSR
+    to 1e-14)."""
+    import json
+    import os
+    import torch
+    p = I.hubbard14_spatial()
+    with open(os.path.join(os.path.dirname(__file__), "golden", "hubbard14_spatial_energy.json")) as f:
+        ref = json.load(f)["energy"]
+    S = _ecut().Sectors.from_problem(p)
+    x = torch.from_numpy(I.psi(p.meta["seed"], S.dim)).to(dev)
+    print("[full] hubbard14_spatial autotuned", S.autotune(S.import_(x), torch.empty_like(x)), flush=True)
+    v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to(dev))
+    e, st, _ = S.lanczos(v0, 600, tol=1e-10)
+    assert st["converged"] and abs(e - ref) <= 1e-10, (e, ref)

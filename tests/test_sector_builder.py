@@ -121,6 +121,9 @@ def test_workload_block_structure():
     assert list(b4[:, 2] * b4[:, 3]) == [math.comb(15, k) ** 2 for k in range(16)]
     # a straight cut between x=2 and x=3 of the 6x5 lattice crosses 5 J1 and 8 J2 bonds
     assert S4.info.n_cut_bonds == 13 and S4.info.n_cross_offdiag == 26 and S4.info.n_cross_diag == 13
+    S5 = E.Sectors.from_problem(I.hubbard14_spatial(), host_only=True)
+    assert S5.dim == 3432 ** 2 and S5.info.n_blocks == 64 and S5.info.kernel == 2 and S5.info.kernel_flags == 64
+    assert sorted(map(tuple, S5.labels()[:, :2].tolist())) == [(a, b) for a in range(8) for b in range(8)]
     S3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)
     assert S3.dim == 165636900 and S3.info.kernel == 1 and S3.info.kernel_flags == 1 | 2 | 8 | 16 | 32
     assert S3.info.n_eff == pytest.approx(1.0)
