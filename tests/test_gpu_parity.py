@@ -1192,3 +1192,37 @@ def test_lanczos_hubbard14_spatial_vs_golden(dev):
     v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to(dev))
     e, st, _ = S.lanczos(v0, 600, tol=1e-10)
     assert st["converged"] and abs(e - ref) <= 1e-10, (e, ref)
+
+
+def test_batch_with_two_pass_row_problems_bit_exact(dev):
+    """A batch of spatial-cut Hubbard problems on the two-pass row kernels
+    (and one on the row kernel), spin problems on the two-pass and on the
+    one-pass kernels, and up/down Hubbard problems in the merged launches:
+    every output equals the problem's own application bit for bit, and the
+    oracle's vector; the same through the no-allocation entry point."""
+    import torch
+    E = _ecut()
+    rng = np.random.default_rng(77)
+    probs = [I.Problem(I.random_extended_hubbard_model(rng, 8), I.Cut("spatial", 0b10110101), 4, 3),
+             I.Problem(I.hubbard_chain(10, 1.0, 3.0, V=0.7), I.Cut("spatial", I.left_mask_first(5)), 5, 5),
+             I.Problem(I.hubbard_chain(8, 1.0, 2.0, V=1.2), I.Cut("spatial", I.left_mask_first(4)), 4, 4),
+             I.heisenberg16(),
+             I.Problem(I.xxz_chain(14, 1.0, 0.8), I.Cut("spatial", I.left_mask_first(7)), 7),
+             I.Problem(I.hubbard_chain(8, 1.0, 4.0), I.Cut("updn"), 4, 4)]
+    tunings = [(8, 8, 0, 2, 0), (0, 1, 0, 2, 0), (0, 0, 0, 0, 0), (4, 8, 0, 2, 0), (0, 0, 0, 0, 0), (0, 8, 1, 6, 2)]
+    Ss = [E.Sectors.from_problem(p) for p in probs]
+    for S, t in zip(Ss, tunings):
+        S.set_tuning(*t)
+    psis = [I.psi(2900 + k, S.dim) for k, S in enumerate(Ss)]
+    xs = [S.import_(torch.from_numpy(x).to(dev)) for S, x in zip(Ss, psis)]
+    alone = [S.apply(x) for S, x in zip(Ss, xs)]
+    ys = [torch.full_like(x, float("nan")) for x in xs]
+    ys2 = [torch.full_like(x, float("nan")) for x in xs]
+    E.apply_batch(Ss, xs, ys)
+    E.apply_batch(Ss, xs, ys2, noalloc=True)
+    torch.cuda.synchronize()
+    for k, (p, S) in enumerate(zip(probs, Ss)):
+        assert torch.equal(alone[k], ys[k]), f"batch differs for problem {k} ({p.model.name})"
+        assert torch.equal(alone[k], ys2[k]), f"no-allocation batch differs for problem {k} ({p.model.name})"
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        _compare(S.export(ys[k]).cpu().numpy(), s.apply(psis[k]), f"batched {p.model.name}")
