@@ -2111,8 +2111,18 @@ __global__ __launch_bounds__(VEC_THREADS) void k_reduce(const VecJob *__restrict
     if (j >= n_jobs) return;
     const VecJob J = jobs[j];
     double s = 0.0;
-    // fixed assignment of partial slots to threads, then a fixed-order block sum
-    for (int i = threadIdx.x; i < J.n_partials; i += blockDim.x) s += J.partials[i];
+    // fixed assignment of partial slots to threads, then a fixed-order block
+    // sum; eight loads in flight, added in slot order
+    const int nt = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * nt < J.n_partials; i += 8 * nt) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = J.partials[i + k * nt];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; i < J.n_partials; i += nt) s += J.partials[i];
     s = block_sum(s, red);
     if (threadIdx.x == 0) {
         if (J.mode == 0) J.scalars[J.out] = (J.dscale ? J.dscale[0] : J.scale) * s;
