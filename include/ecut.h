@@ -144,9 +144,10 @@ typedef struct ecut_sectors_info {
                                  row length <= 14336, <= 64 bonds); bit 4 the segment-tile kernel
                                  available (as bit 1, and every tile fits 512 threads x 10
                                  slots and 48 KB of LDS); bit 5 the two-pass kernels available
-                                 (at most 32 hopping bonds); spin: bit 6 the two-pass spin
-                                 kernels available (as bit 2, and at most 64 left-operator
-                                 terms per row) */
+                                 (at most 32 hopping bonds); spin and the spatial Hubbard cut:
+                                 bit 6 the two-pass row kernels available (both parts <= 16
+                                 sites, rows <= 6,656 amplitudes, <= 64 right terms and <= 64
+                                 left-operator terms per row) */
     int32_t reserved;
     int64_t device_bytes;     /* device metadata held by the handle */
     double n_eff;             /* 1 / sum_q w_q^2 with w_q = d_L d_R / dim (block-size participation number) */
@@ -315,7 +316,11 @@ ecut_status ecut_apply_H_batch_noalloc(int32_t n, const ecut_sectors *const *s, 
  *              group's rows are each other's cross-term source rows);
  *              n_xcd 1 deals items in launch order, else in 8 contiguous
  *              XCD ranges; tile as for variant 0; the vector is variant
- *              0's bit for bit;
+ *              0's bit for bit.  The spatial Hubbard cut (kernel 2,
+ *              kernel_flags bit 6) takes variant 2 too: the same two passes
+ *              with the fermion signs of hops inside the right part and
+ *              across the cut, every row its own item (tile 0); its
+ *              vector agrees with variant 0's to rounding;
  *   tile:      Hubbard variant 4: threads per work group, 256, 512 or 1024
  *              (0 = 1024); a row must fit 14 columns per thread (2 x 7
  *              column pairs), and smaller groups put more rows in flight on a

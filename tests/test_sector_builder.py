@@ -316,3 +316,25 @@ def test_canonical_signs_are_one_without_fermion_reordering():
     for p in (I.Problem(I.xxz_chain(8), I.Cut("spatial", 0b1111), 4), I.hubbard12()):
         S = E.Sectors.from_problem(p, host_only=True)
         assert np.all(S.canonical_signs() == 1)
+
+
+def test_tuning_validation_host():
+    """Tunings outside what a handle's kernels take are refused before any
+    device work: two-pass rows per item, the slabs side by side of variant 7,
+    variant 2 on problems without two-pass tables."""
+    C3 = E.Sectors.from_problem(I.hubbard16(), host_only=True)
+    for t in ((8, 8, 8, 7, 0), (8, 8, 8, 7, 2), (8, 8, 8, 7, 4), (32, 8, 8, 7, 0), (0, 8, 1, 6, 16)):
+        C3.set_tuning(*t)
+    for t in ((33, 8, 8, 7, 0), (16, 8, 8, 7, 4), (8, 8, 8, 7, 3), (8, 8, 1, 6, 3)):
+        assert _status(lambda: C3.set_tuning(*t)) == E.ECUT_EINVAL, t
+    C4 = E.Sectors.from_problem(I.j1j2_6x5(), host_only=True)
+    C4.set_tuning(32, 8, 0, 2, 0)
+    assert _status(lambda: C4.set_tuning(33, 8, 0, 2, 0)) == E.ECUT_EINVAL
+    assert _status(lambda: C4.set_tuning(0, 8, 0, 3, 0)) == E.ECUT_EINVAL
+    H = E.Sectors.from_problem(I.hubbard14_spatial(), host_only=True)
+    H.set_tuning(8, 8, 0, 2, 0)
+    H.set_tuning(0, 0, 0, 0, 0)
+    assert _status(lambda: H.set_tuning(0, 0, 0, 2, 64)) != E.ECUT_OK   # every row is its own item
+    wide = E.Sectors.from_problem(I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", 0b111), 10), host_only=True)
+    assert not wide.info.kernel_flags & 64
+    assert _status(lambda: wide.set_tuning(0, 0, 0, 2, 0)) != E.ECUT_OK
