@@ -335,6 +335,81 @@ def other_workloads(names, stream):
     return out
 
 
+def analyses(stream):
+    """The analyses built on the layout, timed on device-resident states
+    (their parity with the oracle is in the GPU tests):
+     - entanglement spectrum of the spatial-cut Hubbard benchmark's ground
+       state (64 blocks, Gram matrices with rocBLAS dsyrk, eigenvalues with
+       rocSOLVER dsyevd);
+     - Krylov dynamical correlations on the 14-site Hubbard chain (up/down
+       cut): c+ of one mode from the ground state's sector to the next, and
+       the Lanczos coefficients of G+(omega) from that vector."""
+    import numpy as np
+    import torch
+    from paper_2605_07621_amd import ecut, inputs as I
+    out = {}
+    p = I.hubbard14_spatial()
+    S = ecut.Sectors.from_problem(p)
+    x = torch.from_numpy(I.psi(p.meta["seed"], S.dim)).to("cuda:0")
+    S.autotune(S.import_(x), torch.empty_like(x), stream=stream)
+    v0 = S.import_(torch.from_numpy(I.psi(p.meta["seed"] + 1, S.dim)).to("cuda:0"))
+    e0, st, gs = S.lanczos(v0, 150, tol=1e-12, reorth=True, max_restarts=8, want_gs=True)
+    blocks = S.blocks()
+    m = np.minimum(blocks[:, 2], blocks[:, 3]).astype(np.float64)
+    k = np.maximum(blocks[:, 2], blocks[:, 3]).astype(np.float64)
+    ent = S.entanglement(gs, n_parts=8, cutoff=1e-12)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        ent = S.entanglement(gs, n_parts=8, cutoff=1e-12)
+        times.append(time.perf_counter() - t0)
+    out["entanglement"] = {
+        "workload": "hubbard14_spatial ground state", "energy": e0, "lanczos_steps": st["steps"],
+        "blocks": int(S.info.n_blocks), "schmidt_values": int(sum(len(l) for l in ent["lam"])),
+        "ms": round(min(times) * 1e3, 3), "gram_gflop": round(float(np.sum(m * (m + 1) * k)) / 1e9, 3),
+        "entropy": ent["entropy"], "n_eff": ent["n_eff"], "w_p_8": [round(float(w), 6) for w in ent["w_p"]]}
+    progress("entanglement spectrum timed")
+    del S, x, v0, gs
+    # c+ and the Lanczos coefficients of G+ on the 14-site Hubbard chain
+    m0 = I.hubbard_chain(14, 1.0, 4.0)
+    S0 = ecut.Sectors(m0, I.Cut("updn"), 7, 7)
+    S1 = ecut.Sectors(m0, I.Cut("updn"), 8, 7)
+    x = torch.from_numpy(I.psi(1006, S0.dim)).to("cuda:0")
+    for T in (S0, S1):
+        xt = torch.from_numpy(I.psi(1006, T.dim)).to("cuda:0")
+        T.autotune(T.import_(xt), torch.empty_like(xt), stream=stream)
+    e0, st, gs = S0.lanczos(S0.import_(x), 150, tol=1e-12, reorth=True, max_restarts=8, want_gs=True)
+    y = ecut.apply_cdag(S0, S1, 0, 0, True, gs)
+    reps = 20
+    torch.cuda.synchronize()
+    e_0 = torch.cuda.Event(enable_timing=True)
+    e_1 = torch.cuda.Event(enable_timing=True)
+    e_0.record(stream)
+    for _ in range(reps):
+        ecut.apply_cdag(S0, S1, 0, 0, True, gs, out=y, stream=stream)
+    e_1.record(stream)
+    torch.cuda.synchronize()
+    ms = e_0.elapsed_time(e_1) / reps
+    n_steps = 200
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a, b, w = ecut.lanczos_tridiag(S1, y, n_steps)
+    dt = time.perf_counter() - t0
+    omega = np.linspace(-10.0, 10.0, 201)
+    g = ecut.continued_fraction(a, b, w, e0, True, omega, 0.1)
+    out["green_function"] = {
+        "workload": "hubbard_chain_14 (t=1, U=4), c+ of site 0, spin up, from (7,7) to (8,7)",
+        "ground_energy": e0, "cdag_ms": round(ms, 4), "cdag_GBps": round((S0.dim + S1.dim) * 8 / (ms * 1e-3) / 1e9, 1),
+        "cdag_roofline_frac": round((S0.dim + S1.dim) * 8 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "weight": w, "lanczos_steps": len(a), "ms_per_lanczos_step": round(dt * 1e3 / max(len(a), 1), 4),
+        "spectral_sum": float(-np.trapezoid(g.imag, omega) / np.pi)}
+    progress("dynamical correlations timed")
+    del S0, S1, x, y, gs
+    torch.cuda.empty_cache()
+    return out
+
+
 def ground_state_solve(S, p, n_keep, tol):
     """Lanczos to the ground energy with full reorthogonalisation over at
     most n_keep stored vectors (explicit restarts), compared with the
@@ -545,6 +620,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the ground-state solve of the workload")
     ap.add_argument("--solve-keep", type=int, default=150)
     ap.add_argument("--no-others", action="store_true", help="skip the other configurations")
+    ap.add_argument("--no-analyses", action="store_true",
+                    help="skip the timed entanglement spectrum and dynamical correlations")
     ap.add_argument("--tuning", default=None,
                     help="grid,n_xcd,row_order,variant,tile (default: the pinned tuning of the workload, if any)")
     ap.add_argument("--autotune", action="store_true", help="autotune instead of the pinned tuning")
@@ -673,6 +750,8 @@ def main():
         p.meta["name"] = args.workload
         line["ground_state"] = ground_state_solve(S, p, args.solve_keep, 1e-10)
     progress("ground-state solve done")
+    if not args.no_analyses and not args.no_others:
+        line["analyses"] = analyses(stream)
     if args.serving > 0:
         line["serving"] = serving_bench(args.serving, args.serving_budget_gb)
     progress("serving done")

@@ -66,12 +66,15 @@ std::vector<int32_t> pack_blocks(const ecut_sectors *s, int32_t n_parts) {
 
 extern "C" {
 
+// Workspace: the Gram matrix of the largest block, the eigenvalues of every
+// block, the eigensolver's off-diagonal, one status word per block.
 size_t ecut_entanglement_sizes(const ecut_sectors *s, size_t *n_lambda) {
     if (!s) return 0;
     size_t m_max = 0;
     for (const BlockDev &B : s->blocks) m_max = std::max(m_max, (size_t)std::min(B.d_l, B.d_r));
-    if (n_lambda) *n_lambda = (size_t)schmidt_count(s);
-    return m_max * m_max + 2 * m_max + 1;
+    const size_t nl = (size_t)schmidt_count(s);
+    if (n_lambda) *n_lambda = nl;
+    return m_max * m_max + nl + m_max + (s->blocks.size() + 1) / 2 + 1;
 }
 
 ecut_status ecut_entanglement_spectrum(const ecut_sectors *s, const double *psi_d, double cutoff, int32_t n_parts,
@@ -96,7 +99,10 @@ ecut_status ecut_entanglement_spectrum(const ecut_sectors *s, const double *psi_
     if (rocblas_set_stream(h, hs) != rocblas_status_success) return fail(ECUT_EDEVICE, "rocblas_set_stream");
     size_t m_max = 0;
     for (const BlockDev &B : s->blocks) m_max = std::max(m_max, (size_t)std::min(B.d_l, B.d_r));
-    double *G = workspace_d, *D = workspace_d + m_max * m_max, *E = D + m_max;
+    const int64_t n_lam = schmidt_count(s);
+    // one Gram matrix at a time (the stream orders the blocks), the
+    // eigenvalues of every block side by side, one copy to the host at the end
+    double *G = workspace_d, *Dall = workspace_d + m_max * m_max, *E = Dall + n_lam;
     rocblas_int *info = (rocblas_int *)(E + m_max);
     const double one = 1.0, zero = 0.0;
     int64_t off_l = 0;
@@ -110,16 +116,23 @@ ecut_status ecut_entanglement_spectrum(const ecut_sectors *s, const double *psi_
         rocblas_status rs = rocblas_dsyrk(h, rocblas_fill_upper, left ? rocblas_operation_transpose : rocblas_operation_none,
                                           m, left ? B.d_r : B.d_l, &one, A, B.d_r, &zero, G, m);
         if (rs != rocblas_status_success) return fail(ECUT_EDEVICE, "rocblas_dsyrk: status " + std::to_string((int)rs));
-        rs = rocsolver_dsyevd(h, rocblas_evect_none, rocblas_fill_upper, m, G, m, D, E, info);
+        rs = rocsolver_dsyevd(h, rocblas_evect_none, rocblas_fill_upper, m, G, m, Dall + off_l, E, info + q);
         if (rs != rocblas_status_success) return fail(ECUT_EDEVICE, "rocsolver_dsyevd: status " + std::to_string((int)rs));
-        std::vector<double> ev(m);
-        rocblas_int inf = 0;
-        hipError_t e = hipMemcpyAsync(ev.data(), D, sizeof(double) * m, hipMemcpyDeviceToHost, hs);
-        if (e == hipSuccess) e = hipMemcpyAsync(&inf, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, hs);
-        if (e == hipSuccess) e = hipStreamSynchronize(hs);
-        if (e != hipSuccess) return fail(ECUT_EDEVICE, std::string("entanglement spectrum: ") + hipGetErrorString(e));
-        if (inf != 0) return fail(ECUT_ENOTCONV, "rocsolver_dsyevd did not converge on block " + std::to_string(q));
-        for (int i = 0; i < m; ++i) lambda[off_l + i] = ev[m - 1 - i];   // descending
+        off_l += m;
+    }
+    std::vector<double> ev((size_t)n_lam);
+    std::vector<rocblas_int> inf((size_t)nb, 0);
+    hipError_t e = n_lam ? hipMemcpyAsync(ev.data(), Dall, sizeof(double) * n_lam, hipMemcpyDeviceToHost, hs) : hipSuccess;
+    if (e == hipSuccess) e = hipMemcpyAsync(inf.data(), info, sizeof(rocblas_int) * nb, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return fail(ECUT_EDEVICE, std::string("entanglement spectrum: ") + hipGetErrorString(e));
+    off_l = 0;
+    for (int32_t q = 0; q < nb; ++q) {
+        const BlockDev &B = s->blocks[q];
+        const int m = std::min(B.d_l, B.d_r);
+        if (m == 0) continue;
+        if (inf[q] != 0) return fail(ECUT_ENOTCONV, "rocsolver_dsyevd did not converge on block " + std::to_string(q));
+        for (int i = 0; i < m; ++i) lambda[off_l + i] = ev[(size_t)(off_l + m - 1 - i)];   // descending
         off_l += m;
     }
     // normalise to the state's norm: the eigenvalues of rho_L of psi / |psi|
