@@ -718,7 +718,7 @@ def main():
         lz = dict(steps=st["steps"], ms_per_step=round((time.perf_counter() - tl) * 1e3 / st["steps"], 4))
 
     line = {
-        "metric": "H*psi applies/s (16-site Hubbard, FP64) + HBM GB/s",
+        "metric": "H\u00b7\u03c8 applies/s + HBM GB/s (16-site Hubbard); batched solves/s, p50/p99 lat",
         "value": round(args.steps / wall, 3),
         "unit": "H*psi/s",
         "n_gpus": 1,
