@@ -179,12 +179,15 @@ def _warm_tunings(reqs, budget):
         if key not in seen:
             seen.add(key)
             first.append(p)
-    srv = ecut.Server(int(budget), max_active=1, max_steps=2, tol=1e-10, autotune=True)
-    for p in first:
-        srv.submit(p, seed=p.meta["seed"])
-    srv.drain()
-    srv.poll(len(first) + 8)   # two-step solves: statuses are not looked at
-    srv.close()
+    # one server per mode: the sequential baseline keeps each shape's tuning
+    # for a problem alone, a batching server the tuning whose launches merge
+    for max_active in (1, 32):
+        srv = ecut.Server(int(budget), max_active=max_active, max_steps=2, tol=1e-10, autotune=True)
+        for p in first:
+            srv.submit(p, seed=p.meta["seed"])
+        srv.drain()
+        srv.poll(len(first) + 8)   # two-step solves: statuses are not looked at
+        srv.close()
     return len(first)
 
 

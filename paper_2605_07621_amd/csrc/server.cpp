@@ -171,8 +171,12 @@ static constexpr int64_t SMALL_HUB_DIM = (int64_t)1 << 18;
 static constexpr int64_t SMALL_SPIN_DIM = (int64_t)1 << 20;
 static std::map<std::string, ecut_tuning> g_tunings;
 
-static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStream_t st) {
-    const std::string key = tune_shape_key(s);
+// merged: the tuning of a server that runs several solves per step (small
+// problems then prefer the kernels whose launches merge across problems);
+// else the autotuner's pick for the problem alone.  Kept per shape and mode
+// for the life of the process.
+static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStream_t st, bool merged) {
+    const std::string key = tune_shape_key(s) + (merged ? "|merged" : "|alone");
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tunings.find(key);
@@ -180,14 +184,14 @@ static ecut_status tune_once(ecut_sectors *s, const double *x, double *y, hipStr
     }
     ecut_tuning best{};
     ecut_status rs;
-    if (s->kernel == 1 && s->hub6_ok && s->dim <= SMALL_HUB_DIM && s->h6_maxq <= HUBD_BATCH_SLOTS) {
+    if (merged && s->kernel == 1 && s->hub6_ok && s->dim <= SMALL_HUB_DIM && s->h6_maxq <= HUBD_BATCH_SLOTS) {
         // small Hubbard problems take the two-pass kernels, so that every
         // step runs all of them in one merged launch per pass
         best = ecut_tuning{0, 8, 1, 6, 2};
         rs = ecut_set_tuning(s, &best);
     } else {
         rs = ecut_autotune(s, x, y, st, &best);
-        if (rs == ECUT_OK && s->spin_ok && s->dim <= SMALL_SPIN_DIM && best.variant != 0) {
+        if (rs == ECUT_OK && merged && s->spin_ok && s->dim <= SMALL_SPIN_DIM && best.variant != 0) {
             // small spin problems keep the one-pass kernel, whose work items
             // join every other spin problem's in one merged launch per step
             best = ecut_tuning{0, 0, 0, 0, 0};
@@ -339,7 +343,8 @@ void ecut_server::run() {
             for (Active *A : fresh) {
                 hipError_t e = launch_fill_normal(A->L.ring[0], A->L.n, A->req->seed, stream);
                 if (e != hipSuccess) st = hip_fail(e, "seeded start vector");
-                if (st == ECUT_OK && opts.autotune) st = tune_once(A->s, A->L.ring[0], A->L.ring[1], stream);
+                if (st == ECUT_OK && opts.autotune)
+                    st = tune_once(A->s, A->L.ring[0], A->L.ring[1], stream, max_active > 1);
                 ls.push_back(&A->L);
                 v0.push_back(A->L.ring[0]);
             }

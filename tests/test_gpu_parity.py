@@ -745,7 +745,8 @@ def test_server_batched_vs_alone_vs_oracle(dev):
     # never pick up the graphs of a retired request
     for mode in ("alone", "mix", "mix_graph", "alone_graph"):
         alone = mode.startswith("alone")
-        # every server tunes each new problem shape once (shared by all of them)
+        # each new problem shape is tuned once per mode (one solve at a time:
+        # the pick for the problem alone; several: kernels whose launches merge)
         srv = ecut.Server(2 << 30, max_active=(1 if alone else 0), max_steps=600, tol=1e-10,
                           sequential=alone, use_graph=mode.endswith("graph"), autotune=True)
         print(f"[server] mode {mode}", flush=True)
@@ -760,7 +761,9 @@ def test_server_batched_vs_alone_vs_oracle(dev):
         assert abs(a["energy"] - refs[k]) <= 1e-10, (k, a["energy"], refs[k])
         assert abs(m["energy"] - refs[k]) <= 1e-10, (k, m["energy"], refs[k])
         assert abs(a["energy"] - m["energy"]) <= 1e-10
-        assert a["steps"] == m["steps"]
+        # the two modes may run different kernels (summation orders), so the
+        # stopping step may move by one or two
+        assert abs(a["steps"] - m["steps"]) <= 2
         # graph replay of the step changes nothing
         g = results["mix_graph"][k]
         assert g["status"] == 0 and g["energy"] == m["energy"] and g["steps"] == m["steps"]
