@@ -482,8 +482,9 @@ ecut_status ecut_continued_fraction(const double *alpha, const double *beta, int
  *   participation number of the sector dimensions), weight_ipr =
  *   1 / sum_q W_q^2, entropy = -sum lambda log lambda.
  * Per block the Gram matrix of the smaller side (Psi_q Psi_q^T or
- * Psi_q^T Psi_q) is formed with rocBLAS syrk and diagonalised with rocSOLVER
- * syevd on the device; the rest on the host.
+ * Psi_q^T Psi_q) is formed with rocBLAS syrk, and the blocks whose Gram
+ * matrices have one size are diagonalised together with rocSOLVER's batched
+ * syevd, on the device; the rest on the host.
  *   psi_d:       state in the bipartite layout (dim doubles, any norm, not 0).
  *   workspace_d: ecut_entanglement_sizes(s, &n_lambda) doubles (device).
  *   lambda, xi:  host, n_lambda doubles each, blocks in order (xi nullable;

@@ -62,19 +62,35 @@ std::vector<int32_t> pack_blocks(const ecut_sectors *s, int32_t n_parts) {
     return part;
 }
 
+// the blocks by the size of their Gram matrix (m = min(d_L, d_R) > 0), in
+// block order inside each size
+std::map<int, std::vector<int32_t>> gram_groups(const ecut_sectors *s) {
+    std::map<int, std::vector<int32_t>> g;
+    for (int32_t q = 0; q < (int32_t)s->blocks.size(); ++q) {
+        const int m = std::min(s->blocks[q].d_l, s->blocks[q].d_r);
+        if (m > 0) g[m].push_back(q);
+    }
+    return g;
+}
+
 }  // namespace
 
 extern "C" {
 
-// Workspace: the Gram matrix of the largest block, the eigenvalues of every
-// block, the eigensolver's off-diagonal, one status word per block.
+// Workspace: the Gram matrices of the largest group of equal-size blocks,
+// the eigenvalues of every block, the eigensolver's off-diagonals for that
+// group, one status word per block.
 size_t ecut_entanglement_sizes(const ecut_sectors *s, size_t *n_lambda) {
     if (!s) return 0;
-    size_t m_max = 0;
-    for (const BlockDev &B : s->blocks) m_max = std::max(m_max, (size_t)std::min(B.d_l, B.d_r));
+    size_t g_max = 0, e_max = 0;
+    for (const auto &kv : gram_groups(s)) {
+        const size_t m = (size_t)kv.first, c = kv.second.size();
+        g_max = std::max(g_max, c * m * m);
+        e_max = std::max(e_max, c * m);
+    }
     const size_t nl = (size_t)schmidt_count(s);
     if (n_lambda) *n_lambda = nl;
-    return m_max * m_max + nl + m_max + (s->blocks.size() + 1) / 2 + 1;
+    return g_max + nl + e_max + (s->blocks.size() + 1) / 2 + 1;
 }
 
 ecut_status ecut_entanglement_spectrum(const ecut_sectors *s, const double *psi_d, double cutoff, int32_t n_parts,
@@ -97,44 +113,64 @@ ecut_status ecut_entanglement_spectrum(const ecut_sectors *s, const double *psi_
     if (st != ECUT_OK) return st;
     const hipStream_t hs = (hipStream_t)stream;
     if (rocblas_set_stream(h, hs) != rocblas_status_success) return fail(ECUT_EDEVICE, "rocblas_set_stream");
-    size_t m_max = 0;
-    for (const BlockDev &B : s->blocks) m_max = std::max(m_max, (size_t)std::min(B.d_l, B.d_r));
+    const auto groups = gram_groups(s);
+    size_t g_max = 0;
+    for (const auto &kv : groups) g_max = std::max(g_max, kv.second.size() * (size_t)kv.first * (size_t)kv.first);
     const int64_t n_lam = schmidt_count(s);
-    // one Gram matrix at a time (the stream orders the blocks), the
-    // eigenvalues of every block side by side, one copy to the host at the end
-    double *G = workspace_d, *Dall = workspace_d + m_max * m_max, *E = Dall + n_lam;
-    rocblas_int *info = (rocblas_int *)(E + m_max);
+    // per group of equal-size blocks: their Gram matrices side by side
+    // (rocBLAS syrk each), one batched eigensolve; the eigenvalues of every
+    // group side by side, one copy to the host at the end
+    double *G = workspace_d, *Dg = workspace_d + g_max, *E = Dg + n_lam;
+    size_t e_max = 0;
+    for (const auto &kv : groups) e_max = std::max(e_max, kv.second.size() * (size_t)kv.first);
+    rocblas_int *info = (rocblas_int *)(E + e_max);
     const double one = 1.0, zero = 0.0;
-    int64_t off_l = 0;
-    for (int32_t q = 0; q < nb; ++q) {
-        const BlockDev &B = s->blocks[q];
-        const int m = std::min(B.d_l, B.d_r);
-        if (m == 0) continue;
-        // Psi_q is row-major d_L x d_R: column-major it is A (d_R x d_L, lda = d_R)
-        const double *A = psi_d + B.offset;
-        const bool left = B.d_l <= B.d_r;   // Psi Psi^T = A^T A (d_L x d_L), else Psi^T Psi = A A^T
-        rocblas_status rs = rocblas_dsyrk(h, rocblas_fill_upper, left ? rocblas_operation_transpose : rocblas_operation_none,
-                                          m, left ? B.d_r : B.d_l, &one, A, B.d_r, &zero, G, m);
-        if (rs != rocblas_status_success) return fail(ECUT_EDEVICE, "rocblas_dsyrk: status " + std::to_string((int)rs));
-        rs = rocsolver_dsyevd(h, rocblas_evect_none, rocblas_fill_upper, m, G, m, Dall + off_l, E, info + q);
-        if (rs != rocblas_status_success) return fail(ECUT_EDEVICE, "rocsolver_dsyevd: status " + std::to_string((int)rs));
-        off_l += m;
+    int64_t goff = 0;
+    int32_t ioff = 0;
+    for (const auto &kv : groups) {
+        const int m = kv.first;
+        const int c = (int)kv.second.size();
+        for (int i = 0; i < c; ++i) {
+            const BlockDev &B = s->blocks[kv.second[i]];
+            // Psi_q is row-major d_L x d_R: column-major it is A (d_R x d_L, lda = d_R)
+            const double *A = psi_d + B.offset;
+            const bool left = B.d_l <= B.d_r;   // Psi Psi^T = A^T A (d_L x d_L), else Psi^T Psi = A A^T
+            rocblas_status rs =
+                rocblas_dsyrk(h, rocblas_fill_upper, left ? rocblas_operation_transpose : rocblas_operation_none, m,
+                              left ? B.d_r : B.d_l, &one, A, B.d_r, &zero, G + (size_t)i * m * m, m);
+            if (rs != rocblas_status_success) return fail(ECUT_EDEVICE, "rocblas_dsyrk: status " + std::to_string((int)rs));
+        }
+        const rocblas_status rs = rocsolver_dsyevd_strided_batched(h, rocblas_evect_none, rocblas_fill_upper, m, G, m,
+                                                                   (rocblas_stride)m * m, Dg + goff, m, E, m,
+                                                                   info + ioff, c);
+        if (rs != rocblas_status_success)
+            return fail(ECUT_EDEVICE, "rocsolver_dsyevd_strided_batched: status " + std::to_string((int)rs));
+        goff += (int64_t)c * m;
+        ioff += c;
     }
     std::vector<double> ev((size_t)n_lam);
-    std::vector<rocblas_int> inf((size_t)nb, 0);
-    hipError_t e = n_lam ? hipMemcpyAsync(ev.data(), Dall, sizeof(double) * n_lam, hipMemcpyDeviceToHost, hs) : hipSuccess;
-    if (e == hipSuccess) e = hipMemcpyAsync(inf.data(), info, sizeof(rocblas_int) * nb, hipMemcpyDeviceToHost, hs);
+    std::vector<rocblas_int> inf((size_t)std::max(ioff, 1), 0);
+    hipError_t e = n_lam ? hipMemcpyAsync(ev.data(), Dg, sizeof(double) * n_lam, hipMemcpyDeviceToHost, hs) : hipSuccess;
+    if (e == hipSuccess && ioff)
+        e = hipMemcpyAsync(inf.data(), info, sizeof(rocblas_int) * ioff, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return fail(ECUT_EDEVICE, std::string("entanglement spectrum: ") + hipGetErrorString(e));
-    off_l = 0;
-    for (int32_t q = 0; q < nb; ++q) {
-        const BlockDev &B = s->blocks[q];
-        const int m = std::min(B.d_l, B.d_r);
-        if (m == 0) continue;
-        if (inf[q] != 0) return fail(ECUT_ENOTCONV, "rocsolver_dsyevd did not converge on block " + std::to_string(q));
-        for (int i = 0; i < m; ++i) lambda[off_l + i] = ev[(size_t)(off_l + m - 1 - i)];   // descending
-        off_l += m;
+    // each block's eigenvalues, descending, at its place in block order
+    std::vector<int64_t> lam_off((size_t)nb + 1, 0);
+    for (int32_t q = 0; q < nb; ++q)
+        lam_off[q + 1] = lam_off[q] + std::min(s->blocks[q].d_l, s->blocks[q].d_r);
+    goff = 0;
+    ioff = 0;
+    for (const auto &kv : groups) {
+        const int m = kv.first;
+        for (size_t i = 0; i < kv.second.size(); ++i, ++ioff) {
+            const int32_t q = kv.second[i];
+            if (inf[ioff] != 0) return fail(ECUT_ENOTCONV, "rocsolver_dsyevd did not converge on block " + std::to_string(q));
+            for (int k = 0; k < m; ++k) lambda[lam_off[q] + k] = ev[(size_t)(goff + (int64_t)i * m + m - 1 - k)];
+        }
+        goff += (int64_t)kv.second.size() * m;
     }
+    int64_t off_l = n_lam;
     // normalise to the state's norm: the eigenvalues of rho_L of psi / |psi|
     const double norm2 = std::accumulate(lambda, lambda + off_l, 0.0);
     if (!(norm2 > 0.0)) return fail(ECUT_EINVAL, "the state is zero");
