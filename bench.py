@@ -143,11 +143,16 @@ def _golden_lanczos_time(p):
             "method": d["method"], "host": "the host that wrote tests/golden (not the benchmark host)"}
 
 
-def _run_server(reqs, arrivals, budget, max_active, sequential, tol=1e-10, max_steps=600):
+# the two-lane server's threshold: the mix's 14-site Hubbard chains (11.8M
+# amplitudes) get their own worker and stream, everything else batches on the other
+LARGE_DIM = 1 << 22
+
+
+def _run_server(reqs, arrivals, budget, max_active, sequential, tol=1e-10, max_steps=600, large_dim=0):
     from paper_2605_07621_amd import ecut
     # each problem shape is autotuned once per process (first request), in every mode
     srv = ecut.Server(int(budget), max_active=max_active, max_steps=max_steps, tol=tol, sequential=sequential,
-                      autotune=True)
+                      autotune=True, large_dim=large_dim)
     t0 = srv.now()
     ids = [srv.submit(p, seed=p.meta["seed"], not_before=t0 + float(a)) for p, a in zip(reqs, arrivals)]
     srv.drain()
@@ -228,28 +233,38 @@ def serving_bench(n_requests, budget_gb):
     s_bat = _lat_stats(bat, min(r["t_submit"] for r in bat))
     cap = _run_server(reqs, zeros, budget, 32, False)
     s_cap = _lat_stats(cap, min(r["t_submit"] for r in cap))
-    de = max(max(abs(a["energy"] - b["energy"]), abs(a["energy"] - c["energy"])) for a, b, c in zip(seq, bat, cap))
+    lan = _run_server(reqs, zeros, budget, 0, False, large_dim=LARGE_DIM)
+    s_lan = _lat_stats(lan, min(r["t_submit"] for r in lan))
+    progress("serving: batched closed loops done")
+    de = max(max(abs(a["energy"] - b["energy"]), abs(a["energy"] - c["energy"]), abs(a["energy"] - d["energy"]))
+             for a, b, c, d in zip(seq, bat, cap, lan))
     ref = _serving_oracle(n_requests)
-    out = {"requests": len(reqs), "tol": 1e-10,
-           "closed_loop": {"sequential": s_seq, "batched": s_bat, "batched_max32": s_cap},
+    out = {"requests": len(reqs), "tol": 1e-10, "two_lane_large_dim": LARGE_DIM,
+           "closed_loop": {"sequential": s_seq, "batched": s_bat, "batched_max32": s_cap,
+                           "batched_two_lanes": s_lan},
            "max_energy_diff_batched_vs_sequential": de,
            "max_abs_energy_error_vs_oracle": None if ref is None else {
-               "sequential": _max_err(seq, ref), "batched": _max_err(bat, ref), "batched_max32": _max_err(cap, ref)},
+               "sequential": _max_err(seq, ref), "batched": _max_err(bat, ref), "batched_max32": _max_err(cap, ref),
+               "batched_two_lanes": _max_err(lan, ref)},
            "speedup_solves_per_s": round(s_bat["solves_per_s"] / s_seq["solves_per_s"], 3),
-           "speedup_solves_per_s_max32": round(s_cap["solves_per_s"] / s_seq["solves_per_s"], 3)}
+           "speedup_solves_per_s_max32": round(s_cap["solves_per_s"] / s_seq["solves_per_s"], 3),
+           "speedup_solves_per_s_two_lanes": round(s_lan["solves_per_s"] / s_seq["solves_per_s"], 3)}
     mu = s_seq["solves_per_s"]
     for rho in (0.5, 2.0):
         arr = I.poisson_arrivals(len(reqs), rho * mu)
         r_seq = _run_server(reqs, arr, budget, 1, True)
         r_bat = _run_server(reqs, arr, budget, 0, False)
         r_cap = _run_server(reqs, arr, budget, 32, False)
+        r_lan = _run_server(reqs, arr, budget, 0, False, large_dim=LARGE_DIM)
         progress(f"serving: poisson rho={rho} done")
         out[f"poisson_rho{rho}"] = {"rate_per_s": round(rho * mu, 3),
                                     "max_abs_energy_error_vs_oracle": None if ref is None else max(
-                                        _max_err(r_seq, ref), _max_err(r_bat, ref), _max_err(r_cap, ref)),
+                                        _max_err(r_seq, ref), _max_err(r_bat, ref), _max_err(r_cap, ref),
+                                        _max_err(r_lan, ref)),
                                     "sequential": _lat_stats(r_seq, min(r["t_submit"] for r in r_seq)),
                                     "batched": _lat_stats(r_bat, min(r["t_submit"] for r in r_bat)),
-                                    "batched_max32": _lat_stats(r_cap, min(r["t_submit"] for r in r_cap))}
+                                    "batched_max32": _lat_stats(r_cap, min(r["t_submit"] for r in r_cap)),
+                                    "batched_two_lanes": _lat_stats(r_lan, min(r["t_submit"] for r in r_lan))}
     return out
 
 

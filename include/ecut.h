@@ -540,6 +540,14 @@ typedef struct ecut_server_opts {
                                  workspace (ecut_autotune); the tuning is kept for the life of the
                                  process and applied to every later request of that shape, in any
                                  server.  0: default launch tuning */
+    int64_t large_dim;        /* > 0 (and not sequential): requests of at least this many amplitudes
+                                 run on a second worker with its own stream, one at a time with
+                                 the tuning for a problem alone, while the others batch on the
+                                 first worker (max_active applies there); the two streams'
+                                 kernels overlap on the device and share the arena.  Admission
+                                 is FIFO within each lane.  A large request then never shares
+                                 its steps with the small ones that arrive meanwhile.  Not with
+                                 use_graph (ECUT_EINVAL).  0: one worker */
 } ecut_server_opts;
 
 typedef struct ecut_result {

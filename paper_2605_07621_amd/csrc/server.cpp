@@ -16,6 +16,12 @@
 //      their arena space and slot.
 // With max_active = 1 the same loop is the sequential baseline: one request
 // at a time on the same engine.
+// A two-lane server (large_dim > 0) runs this loop on two workers, each with
+// its own stream: lane 1 admits the requests of at least large_dim
+// amplitudes, lane 0 the others, both from the one arrival-ordered queue and
+// the one arena.  Lane 1 runs one request at a time, with the tuning for a
+// problem alone, so a large request never shares its steps; lane 0 batches
+// the rest, and the two lanes' kernels overlap on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,6 +104,7 @@ struct Request {
     ecut_sectors *built = nullptr;
     int state = 0;
     ecut_status build_status = ECUT_OK;
+    int lane = 0;   // the worker that admits it (1: a large request of a two-lane server)
     ~Request() {
         if (built) ecut_sectors_free(built);
     }
@@ -133,15 +140,24 @@ struct Active {
 
 using namespace ecut;
 
+// One worker with its own stream and staging buffers.  A two-lane server
+// runs large requests on lane 1 and the others on lane 0; each lane batches
+// its own solves, and the two streams' kernels overlap on the device.
+struct ServerLane {
+    hipStream_t stream = nullptr;
+    Staging stg;
+    std::thread worker;
+};
+
 struct ecut_server {
     size_t budget = 0;
     ecut_server_opts opts{};
     int device = 0;
     void *arena = nullptr;
-    ArenaAlloc alloc;
-    hipStream_t stream = nullptr;
-    Staging stg;
-    std::thread worker, helper;
+    ArenaAlloc alloc;   // shared by the lanes, guarded by mu
+    ServerLane lanes[2];
+    int n_lanes = 1;
+    std::thread helper;
     std::mutex mu;
     std::condition_variable cv, cv_done, cv_help;
     std::vector<ecut_sectors *> graveyard;   // retired handles, freed by the helper
@@ -155,11 +171,27 @@ struct ecut_server {
     std::string worker_msg;   // the worker's error message (error messages are per thread)
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
-    void run();
+    // the oldest queued request of a lane (mu held), or the end of the queue
+    std::deque<std::unique_ptr<Request>>::iterator head(int lane) {
+        return std::find_if(queue.begin(), queue.end(), [lane](const std::unique_ptr<Request> &r) { return r->lane == lane; });
+    }
+    void run(int lane);
     void help();
 };
 
 static size_t footprint(const ecut_sectors *s) { return lz_workspace_doubles(s, false, 0) * sizeof(double); }
+
+// Amplitudes of a request's sector (any cut gives the same count): C(n, N_up)
+// for spins, C(n, N_up) C(n, N_dn) for Hubbard; 0 for numbers out of range.
+static double sector_states(const ecut_model_desc &m, ecut_qnum q) {
+    auto c = [](int n, int k) {
+        if (k < 0 || k > n) return 0.0;
+        double r = 1.0;
+        for (int i = 1; i <= k; ++i) r = r * (double)(n - k + i) / (double)i;
+        return r;
+    };
+    return m.kind == ECUT_HUBBARD ? c(m.n_sites, q.n_up) * c(m.n_sites, q.n_dn) : c(m.n_sites, q.n_up);
+}
 
 // Launch tuning of each problem shape, measured once per process (on the
 // first request of the shape, x = its start vector, y = a ring vector the
@@ -257,7 +289,9 @@ void ecut_server::help() {
     }
 }
 
-void ecut_server::run() {
+void ecut_server::run(int lane) {
+    hipStream_t stream = lanes[lane].stream;
+    Staging &stg = lanes[lane].stg;
     const hipError_t dev_err = hipSetDevice(device);
     if (dev_err != hipSuccess) {   // nothing can run: drain and poll report it
         const ecut_status st = hip_fail(dev_err, "hipSetDevice (server worker)");
@@ -270,16 +304,19 @@ void ecut_server::run() {
     std::vector<std::unique_ptr<Active>> active;
     LzPipe pipe;   // batched steps in flight (two: the host processes one while the device runs the next)
     pipe.use_graph = opts.use_graph != 0;
-    const int max_active = opts.max_active > 0 ? opts.max_active : 1 << 30;
+    // the large lane runs its requests one at a time: they are bandwidth-bound,
+    // so sharing steps among them would only stretch each one's latency
+    const int max_active = lane == 1 ? 1 : opts.max_active > 0 ? opts.max_active : 1 << 30;
     while (true) {
         // ---- admission
         std::vector<Active *> fresh;
         {
             std::unique_lock<std::mutex> lk(mu);
             while (!stop && active.empty()) {
-                if (!queue.empty()) {
-                    const double wait = queue.front()->not_before - now();
-                    if (wait <= 0 && queue.front()->state == 2) break;
+                const auto h = head(lane);
+                if (h != queue.end()) {
+                    const double wait = (*h)->not_before - now();
+                    if (wait <= 0 && (*h)->state == 2) break;
                     // not arrived yet, or the helper is still building it
                     cv.wait_for(lk, std::chrono::duration<double>(wait > 0 ? std::min(wait, 0.05) : 0.05));
                 } else {
@@ -287,10 +324,11 @@ void ecut_server::run() {
                 }
             }
             if (stop && active.empty()) break;
-            while (!queue.empty() && (int)active.size() < max_active && queue.front()->not_before <= now() &&
-                   queue.front()->state == 2) {
-                Request &R = *queue.front();
-                lk.unlock();
+            // strict FIFO within the lane; the arena allocator is guarded by mu
+            for (auto h = head(lane); h != queue.end() && (int)active.size() < max_active &&
+                                      (*h)->not_before <= now() && (*h)->state == 2;
+                 h = head(lane)) {
+                Request &R = **h;
                 ecut_sectors *s = R.built;
                 R.built = nullptr;
                 ecut_status st = R.build_status;
@@ -301,7 +339,6 @@ void ecut_server::run() {
                     fits = alloc.alloc(bytes, off);
                     if (!fits && bytes > alloc.size) st = fail(ECUT_ENOMEM, "request larger than the server budget");
                 }
-                lk.lock();
                 if (st != ECUT_OK) {
                     ecut_result r{};
                     r.req_id = R.id;
@@ -310,20 +347,20 @@ void ecut_server::run() {
                     r.t_admit = r.t_done = now();
                     finished.push_back(r);
                     ++n_finished;
-                    queue.pop_front();
+                    queue.erase(h);
                     if (s) ecut_sectors_free(s);
                     cv_done.notify_all();
                     continue;
                 }
                 if (!fits) {
-                    // wait for memory: strict FIFO, the head is never overtaken
+                    // wait for memory: strict FIFO, the lane's head is never overtaken
                     R.built = s;
                     break;
                 }
                 cv_help.notify_one();   // the look-ahead window moves on
                 auto A = std::make_unique<Active>();
-                A->req = std::move(queue.front());
-                queue.pop_front();
+                A->req = std::move(*h);
+                queue.erase(h);
                 A->s = s;
                 A->off = off;
                 A->bytes = bytes;
@@ -335,6 +372,9 @@ void ecut_server::run() {
                 fresh.push_back(A.get());
                 active.push_back(std::move(A));
             }
+            // an idle lane whose head waits for arena space the other lane
+            // holds: sleep until a retirement (or a short timeout)
+            if (active.empty() && !stop) cv.wait_for(lk, std::chrono::milliseconds(2));
         }
         ecut_status st = ECUT_OK;
         if (!fresh.empty()) {
@@ -376,6 +416,7 @@ void ecut_server::run() {
         // ---- retire
         std::vector<ecut_result> out;
         std::vector<ecut_sectors *> retired;
+        std::vector<std::pair<size_t, size_t>> spans;   // arena space of the retired solves
         for (auto it = active.begin(); it != active.end();) {
             Active &A = **it;
             if (!A.L.done || A.L.pending > 0) { ++it; continue; }   // retire once no step of it is in flight
@@ -389,15 +430,17 @@ void ecut_server::run() {
             r.t_admit = A.t_admit;
             r.t_done = now();
             out.push_back(r);
-            alloc.release(A.off, A.bytes);
+            spans.emplace_back(A.off, A.bytes);
             retired.push_back(A.s);   // freed by the helper: hipFree waits for the device
             it = active.erase(it);
         }
         if (!retired.empty()) {
             std::lock_guard<std::mutex> g(mu);
+            for (auto &sp : spans) alloc.release(sp.first, sp.second);
             graveyard.insert(graveyard.end(), retired.begin(), retired.end());
             retired.clear();
             cv_help.notify_one();
+            cv.notify_all();   // the other lane may be waiting for memory
         }
         if (!out.empty()) {
             std::lock_guard<std::mutex> g(mu);
@@ -414,34 +457,42 @@ ecut_status ecut_server_create(size_t hbm_budget, const ecut_server_opts *opts, 
     if (!out || !opts) return fail(ECUT_EINVAL, "null argument");
     *out = nullptr;
     if (hbm_budget < 4096) return fail(ECUT_EINVAL, "budget too small");
-    if (opts->max_steps < 2 || !(opts->tol > 0.0)) return fail(ECUT_EINVAL, "bad server options");
+    if (opts->max_steps < 2 || !(opts->tol > 0.0) || opts->large_dim < 0) return fail(ECUT_EINVAL, "bad server options");
+    if (opts->large_dim > 0 && opts->use_graph && !opts->sequential)
+        return fail(ECUT_EINVAL, "a two-lane server does not replay graphs (large_dim > 0 with use_graph)");
     auto *S = new (std::nothrow) ecut_server();
     if (!S) return fail(ECUT_ENOMEM, "host allocation");
     S->budget = hbm_budget;
     S->opts = *opts;
     if (S->opts.sequential) S->opts.max_active = 1;
+    S->n_lanes = S->opts.large_dim > 0 && !S->opts.sequential ? 2 : 1;
     hipError_t e = hipGetDevice(&S->device);
     if (e == hipSuccess) e = hipMalloc(&S->arena, hbm_budget);
     if (e != hipSuccess) {
         delete S;
         return fail(ECUT_ENOMEM, std::string("server arena: ") + hipGetErrorString(e));
     }
-    e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) {
+    auto undo = [S]() {
+        for (ServerLane &l : S->lanes)
+            if (l.stream) hipStreamDestroy(l.stream);
         hipFree(S->arena);
         delete S;
-        return hip_fail(e, "hipStreamCreate");
+    };
+    for (int k = 0; k < S->n_lanes; ++k) {
+        e = hipStreamCreateWithFlags(&S->lanes[k].stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            undo();
+            return hip_fail(e, "hipStreamCreate");
+        }
     }
     ecut_status rs = device_res(nullptr, nullptr, nullptr);
     if (rs != ECUT_OK) {
-        hipStreamDestroy(S->stream);
-        hipFree(S->arena);
-        delete S;
+        undo();
         return rs;
     }
     S->alloc.init(hbm_budget);
     S->t0 = std::chrono::steady_clock::now();
-    S->worker = std::thread([S] { S->run(); });
+    for (int k = 0; k < S->n_lanes; ++k) S->lanes[k].worker = std::thread([S, k] { S->run(k); });
     S->helper = std::thread([S] { S->help(); });
     *out = S;
     return ECUT_OK;
@@ -458,6 +509,7 @@ ecut_status ecut_server_submit(ecut_server *srv, const ecut_model_desc *model, c
     R->cut = *cut;
     R->q = q;
     R->seed = seed;
+    R->lane = srv->n_lanes > 1 && sector_states(*model, q) >= (double)srv->opts.large_dim ? 1 : 0;
     std::lock_guard<std::mutex> g(srv->mu);
     R->id = srv->next_id++;
     R->t_submit = srv->now();
@@ -508,7 +560,8 @@ void ecut_server_destroy(ecut_server *srv) {
         srv->cv.notify_all();
         srv->cv_help.notify_all();
     }
-    if (srv->worker.joinable()) srv->worker.join();
+    for (ServerLane &l : srv->lanes)
+        if (l.worker.joinable()) l.worker.join();
     {
         std::lock_guard<std::mutex> g(srv->mu);
         srv->cv_help.notify_all();
@@ -517,9 +570,12 @@ void ecut_server_destroy(ecut_server *srv) {
     for (ecut_sectors *s : srv->graveyard) ecut_sectors_free(s);
     srv->graveyard.clear();
     dropped.clear();
-    srv->stg.release();
-    hipStreamSynchronize(srv->stream);
-    hipStreamDestroy(srv->stream);
+    for (ServerLane &l : srv->lanes) {
+        l.stg.release();
+        if (!l.stream) continue;
+        hipStreamSynchronize(l.stream);
+        hipStreamDestroy(l.stream);
+    }
     hipFree(srv->arena);
     delete srv;
 }

@@ -74,7 +74,7 @@ def _tuning_dict(t):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_active", _i32), ("max_steps", _i32), ("tol", _dbl), ("sequential", _i32), ("use_graph", _i32),
-                ("autotune", _i32)]
+                ("autotune", _i32), ("large_dim", _i64)]
 
 
 class Result(ctypes.Structure):
@@ -442,9 +442,9 @@ class Server:
     """Continuous-batching ground-state server (ecut_server_*)."""
 
     def __init__(self, hbm_budget, max_active=0, max_steps=400, tol=1e-10, sequential=False, use_graph=False,
-                 autotune=False):
+                 autotune=False, large_dim=0):
         o = ServerOpts(int(max_active), int(max_steps), float(tol), int(bool(sequential)), int(bool(use_graph)),
-                       int(bool(autotune)))
+                       int(bool(autotune)), int(large_dim))
         h = _vp()
         _check(lib().ecut_server_create(int(hbm_budget), ctypes.byref(o), ctypes.byref(h)))
         self.h = h

@@ -743,12 +743,15 @@ def test_server_batched_vs_alone_vs_oracle(dev):
     # alone_graph: one request at a time with graph replay; each request takes
     # the slot (and the host address) of the one before, so a replay must
     # never pick up the graphs of a retired request
-    for mode in ("alone", "mix", "mix_graph", "alone_graph"):
+    # lanes: two workers, the problems of at least 10,000 amplitudes (the
+    # 16-site XXZ chain and the 10-site Hubbard chain) on their own stream
+    for mode in ("alone", "mix", "mix_graph", "alone_graph", "lanes"):
         alone = mode.startswith("alone")
         # each new problem shape is tuned once per mode (one solve at a time:
         # the pick for the problem alone; several: kernels whose launches merge)
         srv = ecut.Server(2 << 30, max_active=(1 if alone else 0), max_steps=600, tol=1e-10,
-                          sequential=alone, use_graph=mode.endswith("graph"), autotune=True)
+                          sequential=alone, use_graph=mode.endswith("graph"), autotune=True,
+                          large_dim=(10000 if mode == "lanes" else 0))
         print(f"[server] mode {mode}", flush=True)
         ids = [srv.submit(p, seed=1000 + k) for k, p in enumerate(reqs)]
         srv.drain()
@@ -769,6 +772,14 @@ def test_server_batched_vs_alone_vs_oracle(dev):
         assert g["status"] == 0 and g["energy"] == m["energy"] and g["steps"] == m["steps"]
         g = results["alone_graph"][k]
         assert g["status"] == 0 and g["energy"] == a["energy"] and g["steps"] == a["steps"]
+        # two lanes: a large problem runs alone on its lane with the tuning
+        # for a problem alone (the sequential run's vectors), the others
+        # batch with the mix's tunings (the mix's vectors)
+        g = results["lanes"][k]
+        p = reqs[k]
+        states = math.comb(p.model.n_sites, p.n_up) * (math.comb(p.model.n_sites, p.n_dn) if p.model.kind == "hubbard" else 1)
+        same = a if states >= 10000 else m
+        assert g["status"] == 0 and g["energy"] == same["energy"] and g["steps"] == same["steps"], k
 
 
 def test_server_failed_build_is_reported(dev):
@@ -888,10 +899,12 @@ def test_lanczos_j1j2_6x5_vs_golden(dev):
     torch.cuda.empty_cache()
 
 
-def test_server_mix_vs_oracle_per_request(dev):
+@pytest.mark.parametrize("large_dim", [0, 1 << 22])
+def test_server_mix_vs_oracle_per_request(dev, large_dim):
     """The first 48 requests of the 256-request serving mix (XXZ chains of
     12-24 sites and Hubbard chains of 8-14 sites), batched with continuous
-    admission: every energy within 1e-10 of the oracle's energy for that
+    admission, on one worker and on two (the 14-site Hubbard chains on their
+    own lane): every energy within 1e-10 of the oracle's energy for that
     request (tests/golden/serving_2026_energies.json)."""
     import json
     import os
@@ -899,7 +912,7 @@ def test_server_mix_vs_oracle_per_request(dev):
     with open(os.path.join(os.path.dirname(__file__), "golden", "serving_2026_energies.json")) as f:
         ref = [e["energy"] for e in json.load(f)["energies"]]
     reqs = I.serving_requests(256, seed=2026)[:48]
-    srv = ecut.Server(24 << 30, max_active=32, max_steps=600, tol=1e-10, autotune=True)
+    srv = ecut.Server(24 << 30, max_active=32, max_steps=600, tol=1e-10, autotune=True, large_dim=large_dim)
     ids = [srv.submit(p, seed=p.meta["seed"]) for p in reqs]
     srv.drain()
     res = {r["req_id"]: r for r in srv.poll(64)}

@@ -221,12 +221,13 @@ def test_option_structs_match_header():
     # the binding's ctypes structs follow the header's field order and types
     import ctypes
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "ecut.h")).read()
-    ctype = {"int32_t": ctypes.c_int32, "double": ctypes.c_double, "uint64_t": ctypes.c_uint64}
+    ctype = {"int32_t": ctypes.c_int32, "int64_t": ctypes.c_int64, "double": ctypes.c_double,
+             "uint64_t": ctypes.c_uint64}
     for cname, py in (("ecut_lanczos_opts", E.LanczosOpts), ("ecut_server_opts", E.ServerOpts),
                       ("ecut_tuning", E.Tuning), ("ecut_lanczos_stats", E.LanczosStats), ("ecut_result", E.Result)):
         body = re.search(r"typedef struct " + cname + r" \{(.*?)\} " + cname + ";", hdr, re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-        fields = re.findall(r"(int32_t|double|uint64_t)\s+(\w+);", body)
+        fields = re.findall(r"(int32_t|int64_t|double|uint64_t)\s+(\w+);", body)
         assert [f for f, _ in py._fields_] == [n for _, n in fields], cname
         assert [t for _, t in py._fields_] == [ctype[ty] for ty, _ in fields], cname
 
@@ -338,3 +339,12 @@ def test_tuning_validation_host():
     wide = E.Sectors.from_problem(I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", 0b111), 10), host_only=True)
     assert not wide.info.kernel_flags & 64
     assert _status(lambda: wide.set_tuning(0, 0, 0, 2, 0)) != E.ECUT_OK
+
+
+def test_server_two_lane_option_checks():
+    # a two-lane server (large_dim > 0) does not replay graphs, and a negative
+    # threshold is refused; both are checked before any device call
+    for kw in (dict(use_graph=True, large_dim=100), dict(large_dim=-1)):
+        with pytest.raises(E.EcutError) as ei:
+            E.Server(1 << 20, **kw)
+        assert ei.value.status == E.ECUT_EINVAL, kw
