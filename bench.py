@@ -516,26 +516,39 @@ def summarize_profiles(workload, kernel, copy_bytes, trace_dir, fetch_dir, write
     return out
 
 
-def serving_trace(n_requests, budget_gb):
-    """The batched closed-loop serving run (at most 32 active) alone, after
-    the tuning warm-up, for a kernel trace: prints its statistics and its
-    timed window on the monotonic clock (the clock of rocprofv3's stamps)."""
+SERVING_TRACES = {
+    "max32": ("batched_max32_closed_loop", "serving_c5_batched32_trace.txt",
+              "batched closed loop on one worker (at most 32 active)"),
+    "two_lanes": ("two_lanes_closed_loop", "serving_c5_two_lanes_trace.txt",
+                  "closed loop on the two-lane server (14-site Hubbard requests one at a time on their own stream)"),
+}
+
+
+def serving_trace(n_requests, budget_gb, mode="max32"):
+    """One closed-loop serving run alone (the batched server with at most 32
+    active, or the two-lane server), after the tuning warm-up, for a kernel
+    trace: prints its statistics and its timed window on the monotonic clock
+    (the clock of rocprofv3's stamps)."""
     import numpy as np
     from paper_2605_07621_amd import inputs as I
     reqs = I.serving_requests(n_requests, seed=2026)
     budget = budget_gb * 2**30
     _warm_tunings(reqs, budget)
     t0 = time.monotonic_ns()
-    out = _run_server(reqs, np.zeros(len(reqs)), budget, 32, False)
+    if mode == "two_lanes":
+        out = _run_server(reqs, np.zeros(len(reqs)), budget, 0, False, large_dim=LARGE_DIM)
+    else:
+        out = _run_server(reqs, np.zeros(len(reqs)), budget, 32, False)
     t1 = time.monotonic_ns()
-    return dict(run="batched_max32_closed_loop", requests=n_requests, window_ns=[t0, t1],
+    return dict(run=SERVING_TRACES[mode][0], requests=n_requests, window_ns=[t0, t1],
                 **_lat_stats(out, min(r["t_submit"] for r in out)))
 
 
-def summarize_serving(trace_dir, window, command):
-    """profiles/serving_c5_batched32_trace.txt: the kernels of the timed
-    serving window from a rocprofv3 kernel trace, and how busy the GPU was."""
+def summarize_serving(trace_dir, run, window, command):
+    """profiles/serving_c5_<mode>_trace.txt: the kernels of the timed serving
+    window from a rocprofv3 kernel trace, and how busy the GPU was."""
     import csv
+    mode = next(k for k, v in SERVING_TRACES.items() if v[0] == run)
     t0, t1 = window
     rows = []
     for fn in os.listdir(trace_dir):
@@ -558,15 +571,17 @@ def summarize_serving(trace_dir, window, command):
         k = r["Kernel_Name"].split("(")[0].replace("void ", "")
         n, tot = per.get(k, (0, 0))
         per[k] = (n + 1, tot + int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    lines = ["# rocprofv3 kernel trace: 256 mixed serving requests, batched closed loop (at most 32 active)", "",
+    ktime = sum(tot for _, tot in per.values())
+    lines = [f"# rocprofv3 kernel trace: 256 mixed serving requests, {SERVING_TRACES[mode][2]}", "",
              "command (from the repository root):", "  cd /tmp && export TMPDIR=/tmp && cd -", "  " + command, "",
              f"timed window {span / 1e9:.3f} s, {len(rows)} kernels, GPU busy {busy / 1e9:.3f} s "
-             f"({100.0 * busy / span:.1f}% of the window; kernels of different queues overlap, so the",
-             "shares, of the busy time, can sum above 100%: uploads of sector tables run beside the steps)", "",
+             f"({100.0 * busy / span:.1f}% of the window); kernel time summed over all queues {ktime / 1e9:.3f} s",
+             f"({ktime / max(busy, 1):.2f}x the busy time: kernels of different queues overlap, so the shares, of",
+             "the busy time, can sum above 100%; uploads of sector tables run beside the steps)", "",
              f"{'kernel':60s} {'calls':>8s} {'total_ms':>10s} {'share':>7s}"]
     for k, (n, tot) in sorted(per.items(), key=lambda kv: -kv[1][1])[:16]:
         lines.append(f"{k[:60]:60s} {n:8d} {tot / 1e6:10.1f} {100.0 * tot / max(busy, 1):6.1f}%")
-    path = os.path.join(ROOT, "profiles", "serving_c5_batched32_trace.txt")
+    path = os.path.join(ROOT, "profiles", SERVING_TRACES[mode][1])
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     return path
@@ -650,22 +665,22 @@ def main():
     ap.add_argument("--kernel", default="k_hub3", help="kernel named in --summarize")
     ap.add_argument("--commands", default=None, help="JSON of the profiling commands, for --summarize")
     ap.add_argument("--serving-budget-gb", type=float, default=24.0)
-    ap.add_argument("--serving-trace", action="store_true",
-                    help="run only the batched serving closed loop (for a kernel trace) and print its window")
+    ap.add_argument("--serving-trace", nargs="?", const="max32", default=None, choices=sorted(SERVING_TRACES),
+                    help="run only one serving closed loop (for a kernel trace) and print its window")
     ap.add_argument("--summarize-solve", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
                     help="write profiles/lanczos_reorth_hubbard16_trace.txt from a kernel trace of a bench run")
     ap.add_argument("--summarize-serving", nargs=2, metavar=("TRACE_DIR", "WINDOW_JSON"),
-                    help="write profiles/serving_c5_batched32_trace.txt from a --serving-trace kernel trace")
+                    help="write profiles/serving_c5_<mode>_trace.txt from a --serving-trace kernel trace")
     args = ap.parse_args()
     if args.summarize_solve:
         print(summarize_solve(args.summarize_solve[0], args.summarize_solve[1], args.commands or ""))
         return
     if args.summarize_serving:
         w = json.loads(open(args.summarize_serving[1]).read().strip().splitlines()[-1])
-        print(summarize_serving(args.summarize_serving[0], w["window_ns"], args.commands or ""))
+        print(summarize_serving(args.summarize_serving[0], w["run"], w["window_ns"], args.commands or ""))
         return
     if args.serving_trace:
-        print(json.dumps(serving_trace(args.serving, args.serving_budget_gb)), flush=True)
+        print(json.dumps(serving_trace(args.serving, args.serving_budget_gb, args.serving_trace)), flush=True)
         return
     if args.summarize:
         from paper_2605_07621_amd import inputs as I
