@@ -187,7 +187,7 @@ ecut_status upload(ecut_sectors *s) {
     const size_t o_hlp = A.add(s->hl_ptr), o_hlc = A.add(s->hl_col), o_hlv = A.add(s->hl_val);
     const size_t o_hrp = A.add(s->hr_ptr), o_hrc = A.add(s->hr_col), o_hrv = A.add(s->hr_val);
     const size_t o_dl = A.add(s->diag_l), o_dr = A.add(s->diag_r);
-    const size_t o_xd = A.add(s->xdiag), o_xb = A.add(s->xbond), o_maps = A.add(s->maps);
+    const size_t o_xd = A.add(s->xdiag), o_xb = A.add(s->xbond), o_maps = A.add(s->maps), o_xdl = A.add(s->xdl);
     std::vector<ItemDev> row_items(std::max(s->items_cap, s->items.size()), ItemDev{0, 0, 0, 0, 0, 0});
     std::copy(s->items.begin(), s->items.end(), row_items.begin());   // capacity for any tile size
     const size_t o_items = A.add(row_items);
@@ -301,6 +301,9 @@ ecut_status upload(ecut_sectors *s) {
     P.diag_l = (const double *)(b + o_dl);
     P.diag_r = (const double *)(b + o_dr);
     P.xdiag = (const XDiagDev *)(b + o_xd);
+    P.xdl = (const double *)(b + o_xdl);
+    P.n_xr = (int32_t)s->xr_site.size();
+    for (int g = 0; g < P.n_xr; ++g) P.xr_site[g] = s->xr_site[g];
     P.xbond = (const XBondDev *)(b + o_xb);
     P.maps = (const int32_t *)(b + o_maps);
     P.dim = s->dim;

@@ -38,6 +38,10 @@ struct BlockDev {
     int32_t blk_l2minus, blk_l2plus; // block with q_l2-1 (q_l2+1) and the same q_l, or -1
 };
 
+// Right sites of a spin cut's diagonal cross terms that the row kernels
+// fold per left word (more distinct sites: the terms are summed one by one).
+constexpr int XR_MAX = 8;
+
 // Diagonal cross term coef * f(l) * f(r); f(l) = n_li (+ n_li2 when
 // li2 >= 0, the two spins of a site: its density), and likewise for r;
 // spin_form: f = n - 1/2 instead (spin Sz Sz).
@@ -302,6 +306,14 @@ struct ProblemDev {
     const int32_t *rank_hi;      // colex rank of the high byte given popc(low byte): 256 x 9
     const uint32_t *rflip_mask;  // the two right-part bits of each flip-flop term
     const double *rflip_coef;    // jxy/2 of each term
+    // diagonal cross terms of a spin cut folded per left word: for left word
+    // gl and the g-th distinct right site xr_site[g] of the terms,
+    // xdl[gl * n_xr + g] = 1/2 sum over the terms on that site of coef (s_li - 1/2),
+    // so the terms of (l, r) sum to sum_g (bit xr_site[g] of r ? +1 : -1) xdl[...].
+    // n_xr = 0: no table (Hubbard, or more than XR_MAX sites)
+    const double *xdl;
+    int32_t n_xr;
+    int32_t xr_site[XR_MAX];
     int64_t dim;
     // per launch (filled by the launcher)
     const double *x;             // input vector
@@ -349,6 +361,8 @@ struct ecut_sectors {
     std::vector<int32_t> hl_ptr, hl_col, hr_ptr, hr_col;
     std::vector<double> hl_val, hr_val, diag_l, diag_r;
     std::vector<ecut::XDiagDev> xdiag;
+    std::vector<double> xdl;             // ProblemDev::xdl (empty: the terms one by one)
+    std::vector<int32_t> xr_site;        // ProblemDev::xr_site
     std::vector<ecut::XBondDev> xbond;
     std::vector<int32_t> maps;
     int32_t n_cut_bonds = 0;

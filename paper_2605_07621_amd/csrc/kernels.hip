@@ -807,6 +807,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                 const int e = tid + m * NT;
                 if (e < S.d_r) xs[e] = sv[m];
             }
+            if (!FERM && tabX && tid == 0) xs[S.d_r] = 0.0;   // the slot a term that does not apply reads
             __syncthreads();
             for (int kk = k; kk < k1; ++kk) {
                 const int rj = P.xbond[kk].rj;
@@ -818,15 +819,24 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                         const int e = tid + m * NT;
                         sx[m] = e < dR ? tabX[(int64_t)kk * dR + e] : 0u;
                     }
+                    if constexpr (FERM) {
 #pragma unroll
-                    for (int m = 0; m < M; ++m) {
-                        const int e = tid + m * NT;
-                        if (e < dR && ((wr[m] >> rj) & 1u) != bl) {
-                            if constexpr (FERM)
+                        for (int m = 0; m < M; ++m) {
+                            const int e = tid + m * NT;
+                            if (e < dR && ((wr[m] >> rj) & 1u) != bl)
                                 acc[m] += (sx[m] & 0x8000u ? -c : c) * xs[sx[m] & 0x7fffu];
-                            else
-                                acc[m] += c * xs[sx[m]];
                         }
+                    } else {
+                        // branch-free: a term that does not apply adds c * 0 from
+                        // the zero slot, so all reads of the bond are in flight together
+                        double v[M];
+#pragma unroll
+                        for (int m = 0; m < M; ++m) {
+                            const int e = tid + m * NT;
+                            v[m] = xs[e < dR && ((wr[m] >> rj) & 1u) != bl ? sx[m] : (uint32_t)S.d_r];
+                        }
+#pragma unroll
+                        for (int m = 0; m < M; ++m) acc[m] += c * v[m];
                     }
                 } else {
 #pragma unroll
@@ -854,15 +864,19 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             const int e = tid + m * NT;
             if (e < dR) xs[e] = xv[m];
         }
+        if (!FERM && tabR && tid == 0) xs[dR] = 0.0;   // the slot a term that does not apply reads
         __syncthreads();
     }
     // right operator from the staged row, diagonal, epilogue
     double dgl = P.diag_l[gl];
+    double xh[XR_MAX];   // the row's folded Sz Sz cross terms (spin cuts)
+#pragma unroll
+    for (int g = 0; g < XR_MAX; ++g) xh[g] = !FERM && g < P.n_xr ? P.xdl[(int64_t)gl * P.n_xr + g] : 0.0;
     double part = 0.0;
     double ra[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) ra[m] = 0.0;
-    if (tabR) {   // four terms' source columns per 8-byte load
+    if (tabR && FERM) {   // four terms' source columns (and signs) per 8-byte load
         for (int g = 0; g * 4 < n_flip; ++g) {
             uint64_t t[M];
 #pragma unroll
@@ -878,12 +892,35 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
 #pragma unroll
                 for (int m = 0; m < M; ++m) {
                     const uint32_t src = (uint32_t)(t[m] >> (16 * i)) & 0xffffu;
-                    if (src != 0xffffu) {
-                        if constexpr (FERM)
-                            ra[m] += (src & 0x8000u ? -cf : cf) * xs[src & 0x7fffu];
-                        else
-                            ra[m] += cf * xs[src];
-                    }
+                    if (src != 0xffffu) ra[m] += (src & 0x8000u ? -cf : cf) * xs[src & 0x7fffu];
+                }
+            }
+        }
+    } else if (tabR) {   // four terms' source columns per 8-byte load
+        // branch-free: an entry 0xffff (no term) reads the zero slot xs[dR]
+        for (int g = 0; g * 4 < n_flip; ++g) {
+            uint64_t t[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int e = tid + m * NT;
+                t[m] = e < dR ? *(const uint64_t *)(tabR + ((int64_t)g * dR + e) * 4) : ~0ull;
+            }
+            double cf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cf[i] = 4 * g + i < n_flip ? fc[4 * g + i] : 0.0;
+            // per slot: the 4 terms' reads in flight together, then summed in term order
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                double v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint32_t src = (uint32_t)(t[m] >> (16 * i)) & 0xffffu;
+                    v[i] = xs[src == 0xffffu ? (uint32_t)dR : src];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (4 * g + i >= n_flip) break;
+                    ra[m] += cf[i] * v[i];
                 }
             }
         }
@@ -900,19 +937,25 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                 if (__popc(w & msk) == 1) a += fc[f] * xs[rank16(w ^ msk, rl, rh)];
             }
         double dg = dgl + P.diag_r[B.rbase + e];
-        for (int x = 0; x < P.n_xdiag; ++x) {
-            const XDiagDev X = P.xdiag[x];
-            if constexpr (FERM) {   // densities of the two sites (V n_i n_j)
-                double fl = (double)((lw >> X.li) & 1u), fr = (double)((w >> X.rj) & 1u);
-                if (X.li2 >= 0) fl += (double)((lw >> X.li2) & 1u);
-                if (X.rj2 >= 0) fr += (double)((w >> X.rj2) & 1u);
-                if (X.spin_form) {
-                    fl -= 0.5;
-                    fr -= 0.5;
+        if (!FERM && P.n_xr > 0) {
+#pragma unroll
+            for (int g = 0; g < XR_MAX; ++g)
+                if (g < P.n_xr) dg += ((w >> P.xr_site[g]) & 1u) ? xh[g] : -xh[g];
+        } else {
+            for (int x = 0; x < P.n_xdiag; ++x) {
+                const XDiagDev X = P.xdiag[x];
+                if constexpr (FERM) {   // densities of the two sites (V n_i n_j)
+                    double fl = (double)((lw >> X.li) & 1u), fr = (double)((w >> X.rj) & 1u);
+                    if (X.li2 >= 0) fl += (double)((lw >> X.li2) & 1u);
+                    if (X.rj2 >= 0) fr += (double)((w >> X.rj2) & 1u);
+                    if (X.spin_form) {
+                        fl -= 0.5;
+                        fr -= 0.5;
+                    }
+                    dg += X.coef * fl * fr;
+                } else {
+                    dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
                 }
-                dg += X.coef * fl * fr;
-            } else {
-                dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
             }
         }
         const double x0 = xs[e];
@@ -1011,9 +1054,18 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
             if (__popc(w & msk) == 1) a += fc[f] * xrow[rank16(w ^ msk, rl, rh)];
         }
         double dg = P.diag_l[gl] + P.diag_r[B.rbase + r];
-        for (int x = 0; x < P.n_xdiag; ++x) {
-            const XDiagDev X = P.xdiag[x];
-            dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
+        if (P.n_xr > 0) {   // the folded table, in the one-row kernel's order
+#pragma unroll
+            for (int g = 0; g < XR_MAX; ++g)
+                if (g < P.n_xr) {
+                    const double h = P.xdl[(int64_t)gl * P.n_xr + g];
+                    dg += ((w >> P.xr_site[g]) & 1u) ? h : -h;
+                }
+        } else {
+            for (int x = 0; x < P.n_xdiag; ++x) {
+                const XDiagDev X = P.xdiag[x];
+                dg += X.coef * ((double)((lw >> X.li) & 1u) - 0.5) * ((double)((w >> X.rj) & 1u) - 0.5);
+            }
         }
         const double x0 = xs[e];
         double yv = ef.x * (acc[m] + a + dg * x0);
@@ -2429,7 +2481,7 @@ hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t 
     }
     if (n_one > 0) {
         const dim3 g = grid_of(n_one, per);
-        const size_t lds = (size_t)std::max(max_d_r, 1) * 8;
+        const size_t lds = (size_t)(std::max(max_d_r, 1) + 1) * 8;   // + the zero slot
         const bool short_rows = max_d_r <= SPIN_SHORT_THREADS * SPIN_SHORT_M;
 #define ECUT_SPINR(NT_, M_, F_)                                                                              \
     hipLaunchKernelGGL((k_spinR<true, NT_, M_, F_>), g, dim3(NT_), lds, st, P, tab, tbase, items_d, n_one, xu, per)

@@ -138,6 +138,7 @@ inline bool fermion_hop(uint32_t w, int i, int j, uint32_t &w2, int &sign) {
 
 static void build_hub_tables(ecut_sectors *s, const ecut_model_desc *m);
 static void build_spin_tables(ecut_sectors *s);
+static void fold_cross_diagonal(ecut_sectors *s);
 static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<uint32_t> &rbetw);
 static int inversions(uint32_t w, int n);
 static void build_hubseg_tables(ecut_sectors *s);
@@ -566,6 +567,7 @@ ecut_status build_host(const ecut_model_desc *m, const ecut_cut_desc *c, ecut_qn
 
     s->hub_ok = false;
     s->kernel = 2;
+    fold_cross_diagonal(s);
     build_spin_tables(s);
     if (s->hub_spatial) {
         // two-pass kernels over one-row items (every row its own item)
@@ -1107,6 +1109,34 @@ static void build_hubrow_tables(ecut_sectors *s, const ecut_model_desc *m) {
 // and the popcount of the low byte:
 //   rank(w) = rank_lo[w & 255] + rank_hi[(w >> 8) * 9 + popc(w & 255)].
 // The tables do not depend on the sector, so one pair serves every block.
+// The Sz Sz cross terms coef (s_i - 1/2)(s_j - 1/2) (i in L, j in R) of one
+// amplitude, grouped by j: sum_j (s_j - 1/2) G_j(l) with
+// G_j(l) = sum over the terms on j of coef (s_i(l) - 1/2), in term order.
+// The table holds G_j / 2 per left word, so a kernel adds +-G_j/2 per right
+// site (exact: s_j - 1/2 is +-1/2).  At most XR_MAX distinct right sites.
+static void fold_cross_diagonal(ecut_sectors *s) {
+    s->xdl.clear();
+    s->xr_site.clear();
+    if (s->kind != ECUT_SPIN_HALF || s->xdiag.empty()) return;
+    std::vector<int32_t> sites;
+    for (const XDiagDev &X : s->xdiag)
+        if (std::find(sites.begin(), sites.end(), X.rj) == sites.end()) sites.push_back(X.rj);
+    if (sites.size() > (size_t)XR_MAX) return;
+    std::sort(sites.begin(), sites.end());
+    const size_t nl = s->lwords.size(), nr = sites.size();
+    s->xdl.assign(nl * nr, 0.0);
+    for (size_t g = 0; g < nl; ++g) {
+        const uint32_t lw = s->lwords[g];
+        for (size_t k = 0; k < nr; ++k) {
+            double G = 0.0;
+            for (const XDiagDev &X : s->xdiag)
+                if (X.rj == sites[k]) G += X.coef * ((double)((lw >> X.li) & 1u) - 0.5);
+            s->xdl[g * nr + k] = 0.5 * G;
+        }
+    }
+    s->xr_site = sites;
+}
+
 static void build_spin_tables(ecut_sectors *s) {
     s->spin_ok = false;
     if (s->kind != ECUT_SPIN_HALF) return;
