@@ -824,6 +824,46 @@ def test_server_budget_admission(dev):
     assert max(e) - min(e) <= 1e-10
 
 
+def test_server_two_lanes_share_the_budget(dev):
+    """Two lanes over one small arena: a large request waits for the memory
+    that the small lane's solves hold and is served once they retire; a
+    large request over the budget and one whose sectors cannot be built fail
+    on the large lane; every valid request matches the oracle."""
+    ecut = _ecut()
+    small = I.Problem(I.xxz_chain(12, 1.0, 0.9), I.Cut("spatial", I.left_mask_first(6)), 6)
+    large = I.Problem(I.xxz_chain(16, 1.0, 1.1), I.Cut("spatial", I.left_mask_first(8)), 8)
+    huge = I.Problem(I.xxz_chain(20, 1.0, 1.0), I.Cut("spatial", I.left_mask_first(10)), 10)
+    bad = I.Problem(I.xxz_chain(40, 1.0, 1.0), I.Cut("spatial", I.left_mask_first(34)), 20)   # 34 > 32 sites
+    refs = {}
+    for name, p in (("small", small), ("large", large)):
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        refs[name] = s.lanczos(I.psi(3, s.n), 600, tol=1e-14)[0][-1]
+    # room for one large solve, or for the four small ones, not for both (a
+    # server solve's footprint is the three-term Lanczos workspace, in 256-byte
+    # granules)
+    def footprint(p):
+        n = 8 * ecut.Sectors.from_problem(p, host_only=True).lanczos_workspace(600)
+        return (n + 255) // 256 * 256
+    f_small, f_large = footprint(small), footprint(large)
+    budget = max(f_large, 4 * f_small) + 1024
+    assert budget - 4 * f_small < f_large and budget < footprint(huge)
+    srv = ecut.Server(budget, max_active=0, max_steps=600, tol=1e-10, large_dim=5000)
+    ids = [srv.submit(small, seed=k) for k in range(4)]
+    ids += [srv.submit(large, seed=7), srv.submit(huge, seed=8), srv.submit(bad, seed=9), srv.submit(large, seed=10)]
+    srv.drain()
+    res = {r["req_id"]: r for r in srv.poll()}
+    srv.close()
+    assert sorted(res) == sorted(ids)
+    for i in ids[:4]:
+        assert res[i]["status"] == 0 and abs(res[i]["energy"] - refs["small"]) <= 1e-10
+    for i in (ids[4], ids[7]):
+        assert res[i]["status"] == 0 and abs(res[i]["energy"] - refs["large"]) <= 1e-10
+    assert res[ids[5]]["status"] == ecut.ECUT_ENOMEM
+    assert res[ids[6]]["status"] == ecut.ECUT_EUNSUPPORTED
+    # FIFO inside the large lane: the second valid large request is admitted after the first
+    assert res[ids[7]]["t_admit"] >= res[ids[4]]["t_admit"]
+
+
 def test_caller_allocator_backs_sector_tables(dev):
     """ecut_set_allocator: sector tables taken from torch's caching allocator
     give the same H*psi bit for bit; a server builds and frees its requests'
