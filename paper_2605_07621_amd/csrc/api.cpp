@@ -304,6 +304,10 @@ ecut_status upload(ecut_sectors *s) {
     P.xdl = (const double *)(b + o_xdl);
     P.n_xr = (int32_t)s->xr_site.size();
     for (int g = 0; g < P.n_xr; ++g) P.xr_site[g] = s->xr_site[g];
+    P.xr_lo = P.n_xr > 0 ? P.xr_site[0] : 0;
+    P.xr_contig = 1;
+    for (int g = 1; g < P.n_xr; ++g)
+        if (P.xr_site[g] != P.xr_lo + g) P.xr_contig = 0;
     P.xbond = (const XBondDev *)(b + o_xb);
     P.maps = (const int32_t *)(b + o_maps);
     P.dim = s->dim;

@@ -314,6 +314,7 @@ struct ProblemDev {
     const double *xdl;
     int32_t n_xr;
     int32_t xr_site[XR_MAX];
+    int32_t xr_lo, xr_contig;    // xr_contig: the sites are xr_lo, xr_lo + 1, ... (one bit field of r)
     int64_t dim;
     // per launch (filled by the launcher)
     const double *x;             // input vector

@@ -27,6 +27,7 @@ constexpr int SLAB_THREADS = 256;
 constexpr int SPIN_THREADS = 512;
 constexpr int SPIN_M = 13;                   // element slots per thread of the spin kernel
 constexpr int SPIN_TILE = SPIN_THREADS * SPIN_M;
+constexpr int XTAB_SLOTS = 256;               // LDS doubles of a row's folded diagonal table (2^XR_MAX)
 constexpr int SPIN_MAX_FLIP = 64;            // flip-flop terms inside the right part
 constexpr int SPIN_SHORT_THREADS = 256;      // two-pass one-row items of rows up to 256 x 5 amplitudes
 constexpr int SPIN_SHORT_M = 5;

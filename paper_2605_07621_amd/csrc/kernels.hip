@@ -723,10 +723,12 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // FERM: the spatial Hubbard cut's cross terms (block by the mode's spin,
 // fermion signs from the maps and the tables' bit 15) and right hops with
 // signs; spin problems compile without them.
+static_assert(XTAB_SLOTS >= (1 << XR_MAX), "a table entry for every pattern of the folded sites");
+
 template <int NT, int M, bool LEFT, bool FERM = false>
 __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
                                              const int32_t *rl, const int32_t *rh, const uint32_t *fm,
-                                             const double *fc, int n_flip, double *red,
+                                             const double *fc, int n_flip, double *red, double *xtab,
                                              const uint16_t *__restrict__ tabR = nullptr,
                                              const uint16_t *__restrict__ tabX = nullptr) {
     const double2 ef = epi_factors(P.dscale, P.xscale, P.zcoef);
@@ -865,13 +867,23 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             if (e < dR) xs[e] = xv[m];
         }
         if (!FERM && tabR && tid == 0) xs[dR] = 0.0;   // the slot a term that does not apply reads
+        if (!LEFT && !FERM && P.n_xr > 0 && tid < (1 << P.n_xr)) {
+            // the row's Sz Sz cross terms for every pattern of the n_xr right
+            // sites: t = sum_g (bit g ? +1 : -1) xdl[gl][g], in g order
+            double t = 0.0;
+            for (int g = 0; g < P.n_xr; ++g) {
+                const double h = P.xdl[(int64_t)gl * P.n_xr + g];
+                t += ((tid >> g) & 1) ? h : -h;
+            }
+            xtab[tid] = t;
+        }
         __syncthreads();
     }
     // right operator from the staged row, diagonal, epilogue
     double dgl = P.diag_l[gl];
-    double xh[XR_MAX];   // the row's folded Sz Sz cross terms (spin cuts)
+    double xh[XR_MAX];   // one pass: the row's folded Sz Sz cross terms
 #pragma unroll
-    for (int g = 0; g < XR_MAX; ++g) xh[g] = !FERM && g < P.n_xr ? P.xdl[(int64_t)gl * P.n_xr + g] : 0.0;
+    for (int g = 0; g < XR_MAX; ++g) xh[g] = LEFT && !FERM && g < P.n_xr ? P.xdl[(int64_t)gl * P.n_xr + g] : 0.0;
     double part = 0.0;
     double ra[M];
 #pragma unroll
@@ -917,11 +929,10 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                     const uint32_t src = (uint32_t)(t[m] >> (16 * i)) & 0xffffu;
                     v[i] = xs[src == 0xffffu ? (uint32_t)dR : src];
                 }
+                // the last word's pad entries are 0xffff (the zero slot) and
+                // their coefficients 0, so all 4 terms are summed unguarded
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (4 * g + i >= n_flip) break;
-                    ra[m] += cf[i] * v[i];
-                }
+                for (int i = 0; i < 4; ++i) ra[m] += cf[i] * v[i];
             }
         }
     }
@@ -938,9 +949,22 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             }
         double dg = dgl + P.diag_r[B.rbase + e];
         if (!FERM && P.n_xr > 0) {
+            if constexpr (LEFT) {   // one pass: the table entry's sum, computed in place
+                double t = 0.0;
 #pragma unroll
-            for (int g = 0; g < XR_MAX; ++g)
-                if (g < P.n_xr) dg += ((w >> P.xr_site[g]) & 1u) ? xh[g] : -xh[g];
+                for (int g = 0; g < XR_MAX; ++g)
+                    if (g < P.n_xr) t += ((w >> P.xr_site[g]) & 1u) ? xh[g] : -xh[g];
+                dg += t;
+            } else {   // the row's table, indexed by the right sites' bits
+                uint32_t ix;
+                if (P.xr_contig) {
+                    ix = (w >> P.xr_lo) & ((1u << P.n_xr) - 1u);
+                } else {
+                    ix = 0u;
+                    for (int g = 0; g < P.n_xr; ++g) ix |= ((w >> P.xr_site[g]) & 1u) << g;
+                }
+                dg += xtab[ix];
+            }
         } else {
             for (int x = 0; x < P.n_xdiag; ++x) {
                 const XDiagDev X = P.xdiag[x];
@@ -1054,13 +1078,13 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
             if (__popc(w & msk) == 1) a += fc[f] * xrow[rank16(w ^ msk, rl, rh)];
         }
         double dg = P.diag_l[gl] + P.diag_r[B.rbase + r];
-        if (P.n_xr > 0) {   // the folded table, in the one-row kernel's order
-#pragma unroll
-            for (int g = 0; g < XR_MAX; ++g)
-                if (g < P.n_xr) {
-                    const double h = P.xdl[(int64_t)gl * P.n_xr + g];
-                    dg += ((w >> P.xr_site[g]) & 1u) ? h : -h;
-                }
+        if (P.n_xr > 0) {   // the folded terms, summed as the one-row kernel's table entry
+            double t = 0.0;
+            for (int g = 0; g < P.n_xr; ++g) {
+                const double h = P.xdl[(int64_t)gl * P.n_xr + g];
+                t += ((w >> P.xr_site[g]) & 1u) ? h : -h;
+            }
+            dg += t;
         } else {
             for (int x = 0; x < P.n_xdiag; ++x) {
                 const XDiagDev X = P.xdiag[x];
@@ -1086,7 +1110,8 @@ __device__ __forceinline__ void spin_many_rows(const ProblemDev &P, const BlockD
 // kernel skips the other kind of item, so both run over the same list.
 template <bool ONE>
 __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, ONE ? 4 : 2) void k_spin(
-    const ProblemDev *__restrict__ probs, const ProblemDev single, const ItemDev *__restrict__ items, int n_items) {
+    const ProblemDev *__restrict__ probs, const ProblemDev single, const ItemDev *__restrict__ items, int n_items,
+    int xtab_off) {
     constexpr int NT = ONE ? SPIN_THREADS : SPIN_MANY_THREADS;
     constexpr int M = ONE ? SPIN_M : SPIN_MANY_TILE / SPIN_MANY_THREADS;
     extern __shared__ __align__(16) double xs[];
@@ -1114,7 +1139,7 @@ __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, ONE ? 4 : 2
         }
         const BlockDev B = P.blocks[W.block];
         if (ONE)
-            spin_one_row<NT, M, true>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
+            spin_one_row<NT, M, true>(P, B, W, xs, rl, rh, fm, fc, n_flip, red, xs + xtab_off);
         else
             spin_many_rows<NT, M, true>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
     }
@@ -1172,7 +1197,7 @@ __global__ __launch_bounds__(HUBU_THREADS) void k_spinL(const SpinLArgs A, int n
 template <bool ONE, int NT1, int M1, bool FERM>
 __global__ __launch_bounds__(ONE ? NT1 : SPIN_MANY_THREADS, (ONE && NT1 == SPIN_THREADS) ? 4 : 2) void k_spinR(
     const ProblemDev P, const uint16_t *__restrict__ tab, const int64_t *__restrict__ tbase,
-    const ItemDev *__restrict__ items, int n_items, int n_xcd, int per_xcd) {
+    const ItemDev *__restrict__ items, int n_items, int n_xcd, int per_xcd, int xtab_off) {
     constexpr int NT = ONE ? NT1 : SPIN_MANY_THREADS;
     constexpr int M = ONE ? M1 : SPIN_MANY_TILE / SPIN_MANY_THREADS;
     extern __shared__ __align__(16) double xs[];
@@ -1198,7 +1223,7 @@ __global__ __launch_bounds__(ONE ? NT1 : SPIN_MANY_THREADS, (ONE && NT1 == SPIN_
     __syncthreads();
     const BlockDev B = P.blocks[W.block];
     if constexpr (ONE)
-        spin_one_row<NT, M, false, FERM>(P, B, W, xs, rl, rh, fm, fc, n_flip, red, tab + tbase[2 * W.block],
+        spin_one_row<NT, M, false, FERM>(P, B, W, xs, rl, rh, fm, fc, n_flip, red, xs + xtab_off, tab + tbase[2 * W.block],
                                          tab + tbase[2 * W.block + 1]);
     else
         spin_many_rows<NT, M, false>(P, B, W, xs, rl, rh, fm, fc, n_flip, red);
@@ -2453,10 +2478,13 @@ hipError_t launch_spin(const ProblemDev *probs_d, const ProblemDev &single, cons
     if (grid > n_items) grid = n_items;   // groups walk the list with a stride of the grid
     // one-row items: the row and the cross-term source rows; then the items of
     // several short rows (their tiles are at most SPIN_MANY_TILE)
-    const size_t lds1 = (size_t)std::max(std::max(max_tile_elems, max_src), 1) * 8;
-    hipLaunchKernelGGL(k_spin<true>, dim3(grid), dim3(SPIN_THREADS), lds1, st, probs_d, single, items_d, n_items);
+    // the row buffer (the one-pass kernel sums the folded diagonal in place)
+    const int cap = std::max(std::max(max_tile_elems, max_src), 1);
+    const size_t lds1 = (size_t)cap * 8;
+    hipLaunchKernelGGL(k_spin<true>, dim3(grid), dim3(SPIN_THREADS), lds1, st, probs_d, single, items_d, n_items, cap);
     const size_t lds2 = (size_t)SPIN_MANY_TILE * 8;
-    hipLaunchKernelGGL(k_spin<false>, dim3(grid), dim3(SPIN_MANY_THREADS), lds2, st, probs_d, single, items_d, n_items);
+    hipLaunchKernelGGL(k_spin<false>, dim3(grid), dim3(SPIN_MANY_THREADS), lds2, st, probs_d, single, items_d, n_items,
+                       0);
     return hipGetLastError();
 }
 
@@ -2481,10 +2509,11 @@ hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t 
     }
     if (n_one > 0) {
         const dim3 g = grid_of(n_one, per);
-        const size_t lds = (size_t)(std::max(max_d_r, 1) + 1) * 8;   // + the zero slot
+        const int cap = std::max(max_d_r, 1) + 1;   // + the zero slot
+        const size_t lds = (size_t)(cap + XTAB_SLOTS) * 8;   // then the folded diagonal table
         const bool short_rows = max_d_r <= SPIN_SHORT_THREADS * SPIN_SHORT_M;
 #define ECUT_SPINR(NT_, M_, F_)                                                                              \
-    hipLaunchKernelGGL((k_spinR<true, NT_, M_, F_>), g, dim3(NT_), lds, st, P, tab, tbase, items_d, n_one, xu, per)
+    hipLaunchKernelGGL((k_spinR<true, NT_, M_, F_>), g, dim3(NT_), lds, st, P, tab, tbase, items_d, n_one, xu, per, cap)
         if (short_rows && fermion) ECUT_SPINR(SPIN_SHORT_THREADS, SPIN_SHORT_M, true);
         else if (short_rows) ECUT_SPINR(SPIN_SHORT_THREADS, SPIN_SHORT_M, false);
         else if (fermion) ECUT_SPINR(SPIN_THREADS, SPIN_M, true);
@@ -2497,7 +2526,7 @@ hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t 
         const dim3 g = grid_of(n_items - n_one, per);
         if (fermion) return hipErrorInvalidValue;   // the several-row items rank without signs
         hipLaunchKernelGGL((k_spinR<false, SPIN_THREADS, SPIN_M, false>), g, dim3(SPIN_MANY_THREADS),
-                           (size_t)SPIN_MANY_TILE * 8, st, P, tab, tbase, items_d + n_one, n_items - n_one, xu, per);
+                           (size_t)SPIN_MANY_TILE * 8, st, P, tab, tbase, items_d + n_one, n_items - n_one, xu, per, 0);
     }
     return hipGetLastError();
 }
