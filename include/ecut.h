@@ -545,9 +545,11 @@ typedef struct ecut_server_opts {
                                  the tuning for a problem alone, while the others batch on the
                                  first worker (max_active applies there); the two streams'
                                  kernels overlap on the device and share the arena.  Admission
-                                 is FIFO within each lane.  A large request then never shares
-                                 its steps with the small ones that arrive meanwhile.  Not with
-                                 use_graph (ECUT_EINVAL).  0: one worker */
+                                 is FIFO within each lane, and no request takes arena space
+                                 ahead of an earlier one of the other lane that waits for it.
+                                 A large request then never shares its steps with the small
+                                 ones that arrive meanwhile.  Not with use_graph (ECUT_EINVAL).
+                                 0: one worker */
 } ecut_server_opts;
 
 typedef struct ecut_result {

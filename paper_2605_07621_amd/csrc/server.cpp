@@ -157,6 +157,9 @@ struct ecut_server {
     ArenaAlloc alloc;   // shared by the lanes, guarded by mu
     ServerLane lanes[2];
     int n_lanes = 1;
+    // lane k's head is built and has a free slot but waits for arena space;
+    // the other lane then admits nothing that arrived after it (guarded by mu)
+    bool mem_wait[2] = {false, false};
     std::thread helper;
     std::mutex mu;
     std::condition_variable cv, cv_done, cv_help;
@@ -324,10 +327,16 @@ void ecut_server::run(int lane) {
                 }
             }
             if (stop && active.empty()) break;
-            // strict FIFO within the lane; the arena allocator is guarded by mu
+            // strict FIFO within the lane; the arena allocator is guarded by mu.
+            // Across lanes, no request takes memory ahead of an earlier one of
+            // the other lane that waits for it.
             for (auto h = head(lane); h != queue.end() && (int)active.size() < max_active &&
                                       (*h)->not_before <= now() && (*h)->state == 2;
                  h = head(lane)) {
+                if (n_lanes > 1 && mem_wait[1 - lane]) {
+                    const auto o = head(1 - lane);
+                    if (o != queue.end() && o < h) break;
+                }
                 Request &R = **h;
                 ecut_sectors *s = R.built;
                 R.built = nullptr;
@@ -339,6 +348,7 @@ void ecut_server::run(int lane) {
                     fits = alloc.alloc(bytes, off);
                     if (!fits && bytes > alloc.size) st = fail(ECUT_ENOMEM, "request larger than the server budget");
                 }
+                mem_wait[lane] = st == ECUT_OK && !fits;
                 if (st != ECUT_OK) {
                     ecut_result r{};
                     r.req_id = R.id;

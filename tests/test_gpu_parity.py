@@ -864,6 +864,43 @@ def test_server_two_lanes_share_the_budget(dev):
     assert res[ids[7]]["t_admit"] >= res[ids[4]]["t_admit"]
 
 
+def test_server_two_lanes_memory_order(dev):
+    """A large request waiting for arena space is not overtaken by small
+    requests that arrived after it: with room for three small solves or the
+    large one alone, the two small requests submitted after the large one are
+    admitted only after it; every energy matches the oracle."""
+    ecut = _ecut()
+    small = I.Problem(I.xxz_chain(14, 1.0, 0.8), I.Cut("spatial", I.left_mask_first(7)), 7)
+    large = I.Problem(I.xxz_chain(16, 1.0, 1.1), I.Cut("spatial", I.left_mask_first(8)), 8)
+    refs = {}
+    for name, p in (("small", small), ("large", large)):
+        s = O.Sector(p.model, p.n_up, p.n_dn)
+        refs[name] = s.lanczos(I.psi(3, s.n), 600, tol=1e-14)[0][-1]
+
+    def footprint(p):
+        n = 8 * ecut.Sectors.from_problem(p, host_only=True).lanczos_workspace(600)
+        return (n + 255) // 256 * 256
+    f_small, f_large = footprint(small), footprint(large)
+    budget = f_large + 1024
+    assert 3 * f_small <= budget < 4 * f_small and f_large + f_small > budget
+    srv = ecut.Server(budget, max_active=0, max_steps=600, tol=1e-10, large_dim=5000)
+    early = [srv.submit(small, seed=k) for k in range(3)]
+    big = srv.submit(large, seed=7)
+    late = [srv.submit(small, seed=10 + k) for k in range(2)]
+    srv.drain()
+    res = {r["req_id"]: r for r in srv.poll()}
+    srv.close()
+    for i in early + late:
+        assert res[i]["status"] == 0 and abs(res[i]["energy"] - refs["small"]) <= 1e-10
+    assert res[big]["status"] == 0 and abs(res[big]["energy"] - refs["large"]) <= 1e-10
+    # the large solve never shares the arena with a small one, and the late
+    # small requests come after it
+    for i in late:
+        assert res[i]["t_admit"] >= res[big]["t_done"] - 1e-9, (res[i], res[big])
+    for i in early:
+        assert res[i]["t_done"] <= res[big]["t_admit"] + 1e-9
+
+
 def test_caller_allocator_backs_sector_tables(dev):
     """ecut_set_allocator: sector tables taken from torch's caching allocator
     give the same H*psi bit for bit; a server builds and frees its requests'
