@@ -385,6 +385,12 @@ _SPIN_CASES = [p for p in SMALL if p.model.kind == "spin"] + [
     I.Problem(I.j1j2_lattice(4, 3, 1.0, 0.5), I.Cut("spatial", (1 << 6) - 1), 6),
     I.Problem(I.j1j2_lattice(4, 4, 1.0, 0.5), I.Cut("spatial", 0b1010101101010110), 7),
     I.Problem(I.random_spin_model(np.random.default_rng(91), 16, n_bonds=60), I.Cut("spatial", 0x0f0f), 8),
+    # the diagonal cross terms' right sites are not one bit field of the right
+    # word (positions 0, 4, 5): the kernels gather the bits into the table index
+    I.Problem(I.xxz_chain(20, 1.0, 1.3), I.Cut("spatial", 0x7C1F), 10),
+    # nine distinct right sites, more than the folded table takes: the terms
+    # are summed one by one
+    I.Problem(I.random_spin_model(np.random.default_rng(93), 18, n_bonds=90), I.Cut("spatial", (1 << 9) - 1), 9),
 ]
 
 
