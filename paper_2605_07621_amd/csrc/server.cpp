@@ -383,7 +383,8 @@ void ecut_server::run(int lane) {
                 active.push_back(std::move(A));
             }
             // an idle lane whose head waits for arena space the other lane
-            // holds: sleep until a retirement (or a short timeout)
+            // holds, or stands behind an earlier request of the other lane that
+            // waits for it: sleep until a retirement (or a short timeout)
             if (active.empty() && !stop) cv.wait_for(lk, std::chrono::milliseconds(2));
         }
         ecut_status st = ECUT_OK;
