@@ -718,8 +718,9 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // LEFT: the left operator here; otherwise its sum is already in y (the
 // two-pass kernels' left pass) and is read as the starting value.
 // tabR / tabX (non-null): the block's source-column tables of the right
-// flip-flop terms and the cross terms (0xffff = no term) instead of ranking
-// the flipped words; the terms are summed in the same order either way.
+// flip-flop terms and the cross terms, instead of ranking the flipped words
+// (no term: 0xffff on a fermion cut; the row length dR, the zero slot, in a
+// spin cut's flip table); the terms are summed in the same order either way.
 // FERM: the spatial Hubbard cut's cross terms (block by the mode's spin,
 // fermion signs from the maps and the tables' bit 15) and right hops with
 // signs; spin problems compile without them.
@@ -909,13 +910,15 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             }
         }
     } else if (tabR) {   // four terms' source columns per 8-byte load
-        // branch-free: an entry 0xffff (no term) reads the zero slot xs[dR]
+        // branch-free: a spin cut's table holds dR for "no term" (and in its
+        // pads), the zero slot xs[dR]; slots past the row end take four of them
+        const uint64_t none4 = (uint64_t)(uint32_t)dR * 0x0001000100010001ull;
         for (int g = 0; g * 4 < n_flip; ++g) {
             uint64_t t[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int e = tid + m * NT;
-                t[m] = e < dR ? *(const uint64_t *)(tabR + ((int64_t)g * dR + e) * 4) : ~0ull;
+                t[m] = e < dR ? *(const uint64_t *)(tabR + ((int64_t)g * dR + e) * 4) : none4;
             }
             double cf[4];
 #pragma unroll
@@ -925,11 +928,8 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             for (int m = 0; m < M; ++m) {
                 double v[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint32_t src = (uint32_t)(t[m] >> (16 * i)) & 0xffffu;
-                    v[i] = xs[src == 0xffffu ? (uint32_t)dR : src];
-                }
-                // the last word's pad entries are 0xffff (the zero slot) and
+                for (int i = 0; i < 4; ++i) v[i] = xs[(uint32_t)(t[m] >> (16 * i)) & 0xffffu];
+                // the last word's pad entries are dR (the zero slot) and
                 // their coefficients 0, so all 4 terms are summed unguarded
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ra[m] += cf[i] * v[i];

@@ -1205,6 +1205,14 @@ static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<
         n = (n + 3) & ~(int64_t)3;   // 8-byte aligned groups
     }
     s->sp_tab.assign((size_t)std::max<int64_t>(n, 4), 0xffff);
+    // "no term" in a flip table: 0xffff with fermion signs; for spin cuts the
+    // block's d_r, the index of the zero slot the kernel keeps after the row,
+    // so a term that does not apply (and a pad entry) reads 0 with no test
+    if (!fermion)
+        for (size_t b = 0; b < s->blocks.size(); ++b)
+            std::fill(s->sp_tab.begin() + s->sp_tbase[2 * b],
+                      s->sp_tab.begin() + s->sp_tbase[2 * b] + (int64_t)ng * 4 * s->blocks[b].d_r,
+                      (uint16_t)s->blocks[b].d_r);
     for (size_t b = 0; b < s->blocks.size(); ++b) {
         const BlockDev &B = s->blocks[b];
         for (int32_t e = 0; e < B.d_r; ++e) {
