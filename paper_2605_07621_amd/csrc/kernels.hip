@@ -1733,6 +1733,9 @@ __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
     const int slab = sg * ways + wave % ways;
     const int c = (slab * 64 + lane) * CPL;
     const bool ok = c < A.dR;
+    // lanes past the row end gather column 0 (always present) instead of
+    // masking every load; their store is the one thing skipped
+    const int cl = ok ? c : 0;
     const int64_t dR = A.dR;
     const int step = HUBU_THREADS / 64 / ways;
     const int r0 = rg * A.rows_per_item + wave / ways;
@@ -1754,22 +1757,51 @@ __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
             if (lane < __builtin_amdgcn_readlane(pb, k) - q0) colv[k] = A.hl_col[q0 + lane];
         }
     }
+    const double *__restrict__ xc = A.x + cl;
 #pragma unroll
     for (int k = 0; k < HUBU_RMAX; ++k) {
         if (k >= nrw) break;
         const int q0 = __builtin_amdgcn_readlane(pa, k);
         const int deg = __builtin_amdgcn_readlane(pb, k) - q0;
         const int a = __builtin_amdgcn_readlane(ar, k);
+        const double *__restrict__ hv = A.hl_val + q0;
         double acc0 = 0.0, acc1 = 0.0;
-        for (int j = 0; j < deg; j += HUBU_NB) {
+        int j = 0;
+        // whole batches: every load of a batch is issued before any is
+        // consumed, with no per-neighbour test
+        for (; j + HUBU_NB <= deg; j += HUBU_NB) {
+            double v0[HUBU_NB], v1[HUBU_NB], h[HUBU_NB];
+#pragma unroll
+            for (int u = 0; u < HUBU_NB; ++u) {
+                const double *p = xc + (int64_t)__builtin_amdgcn_readlane(colv[k], j + u) * dR;
+                if constexpr (PAIR) {
+                    const double2 q = *(const double2 *)p;
+                    v0[u] = q.x;
+                    v1[u] = q.y;
+                } else {
+                    v0[u] = *p;
+                    v1[u] = 0.0;
+                }
+            }
+            if (!A.uniform) {
+#pragma unroll
+                for (int u = 0; u < HUBU_NB; ++u) h[u] = hv[j + u];
+            }
+#pragma unroll
+            for (int u = 0; u < HUBU_NB; ++u) {
+                const double hu = A.uniform ? 1.0 : h[u];
+                acc0 += hu * v0[u];
+                acc1 += hu * v1[u];
+            }
+        }
+        // the last, partial batch (same order of terms)
+        if (j < deg) {
             double v0[HUBU_NB], v1[HUBU_NB];
-            // every load of the batch is issued before any is consumed
 #pragma unroll
             for (int u = 0; u < HUBU_NB; ++u) {
                 v0[u] = v1[u] = 0.0;
-                const int src = j + u < deg ? __builtin_amdgcn_readlane(colv[k], j + u) : 0;
-                if (j + u < deg && ok) {
-                    const double *p = A.x + (int64_t)src * dR + c;
+                if (j + u < deg) {
+                    const double *p = xc + (int64_t)__builtin_amdgcn_readlane(colv[k], j + u) * dR;
                     if constexpr (PAIR) {
                         const double2 q = *(const double2 *)p;
                         v0[u] = q.x;
@@ -1782,9 +1814,9 @@ __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
 #pragma unroll
             for (int u = 0; u < HUBU_NB; ++u)
                 if (j + u < deg) {
-                    const double h = A.uniform ? 1.0 : A.hl_val[q0 + j + u];
-                    acc0 += h * v0[u];
-                    acc1 += h * v1[u];
+                    const double hu = A.uniform ? 1.0 : hv[j + u];
+                    acc0 += hu * v0[u];
+                    acc1 += hu * v1[u];
                 }
         }
         if (A.uniform) {   // sum, then scale once
