@@ -719,12 +719,18 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // two-pass kernels' left pass) and is read as the starting value.
 // tabR / tabX (non-null): the block's source-column tables of the right
 // flip-flop terms and the cross terms, instead of ranking the flipped words
-// (no term: 0xffff on a fermion cut; the row length dR, the zero slot, in a
-// spin cut's flip table); the terms are summed in the same order either way.
+// (fermion cut: the column, 0xffff for no term; spin cut: the column's byte
+// offset in xs, 8 * dR, the zero slot, for no term); the terms are summed in
+// the same order either way.
 // FERM: the spatial Hubbard cut's cross terms (block by the mode's spin,
 // fermion signs from the maps and the tables' bit 15) and right hops with
 // signs; spin problems compile without them.
 static_assert(XTAB_SLOTS >= (1 << XR_MAX), "a table entry for every pattern of the folded sites");
+
+// the staged element at byte offset off of xs (a spin cut's table entry)
+__device__ __forceinline__ double lds_at(const double *xs, uint32_t off) {
+    return *(const double *)((const char *)xs + off);
+}
 
 template <int NT, int M, bool LEFT, bool FERM = false>
 __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev &B, const ItemDev &W, double *xs,
@@ -836,7 +842,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
 #pragma unroll
                         for (int m = 0; m < M; ++m) {
                             const int e = tid + m * NT;
-                            v[m] = xs[e < dR && ((wr[m] >> rj) & 1u) != bl ? sx[m] : (uint32_t)S.d_r];
+                            v[m] = lds_at(xs, e < dR && ((wr[m] >> rj) & 1u) != bl ? sx[m] : 8u * S.d_r);
                         }
 #pragma unroll
                         for (int m = 0; m < M; ++m) acc[m] += c * v[m];
@@ -910,9 +916,10 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             }
         }
     } else if (tabR) {   // four terms' source columns per 8-byte load
-        // branch-free: a spin cut's table holds dR for "no term" (and in its
-        // pads), the zero slot xs[dR]; slots past the row end take four of them
-        const uint64_t none4 = (uint64_t)(uint32_t)dR * 0x0001000100010001ull;
+        // branch-free: a spin cut's table holds 8 * dR, the byte offset of the
+        // zero slot xs[dR], for "no term" (and in its pads); slots past the
+        // row end take four of them
+        const uint64_t none4 = (uint64_t)(8u * dR) * 0x0001000100010001ull;
         for (int g = 0; g * 4 < n_flip; ++g) {
             uint64_t t[M];
 #pragma unroll
@@ -928,7 +935,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             for (int m = 0; m < M; ++m) {
                 double v[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) v[i] = xs[(uint32_t)(t[m] >> (16 * i)) & 0xffffu];
+                for (int i = 0; i < 4; ++i) v[i] = lds_at(xs, (uint32_t)(t[m] >> (16 * i)) & 0xffffu);
                 // the last word's pad entries are dR (the zero slot) and
                 // their coefficients 0, so all 4 terms are summed unguarded
 #pragma unroll

@@ -1167,7 +1167,9 @@ static void build_spin_tables(ecut_sectors *s) {
 //    (-1)^popc(w & rbetw[f]) when rbetw is given) and of every cross term
 //    (the right word with bit rj flipped; on the spatial Hubbard cut with
 //    the right part's sign (-1)^(occupied modes before the mode)), in the
-//    low 15 bits, the sign in bit 15, 0xffff for no term.
+//    low 15 bits, the sign in bit 15, 0xffff for no term. On a spin cut
+//    (no signs) an entry is the column's byte offset in the staged row,
+//    8 * column, and "no term" is 8 * d_r, the zero slot after the row.
 static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<uint32_t> &rbetw) {
     s->sp2_ok = false;
     if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP || s->max_d_r > SPIN_TILE) return;
@@ -1206,13 +1208,15 @@ static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<
     }
     s->sp_tab.assign((size_t)std::max<int64_t>(n, 4), 0xffff);
     // "no term" in a flip table: 0xffff with fermion signs; for spin cuts the
-    // block's d_r, the index of the zero slot the kernel keeps after the row,
+    // byte offset of the zero slot the kernel keeps after the row (8 * d_r),
     // so a term that does not apply (and a pad entry) reads 0 with no test
+    static_assert(SPIN_TILE * 8 < 0xffff, "a spin cut's byte offsets fit 16 bits");
+    const int64_t unit = fermion ? 1 : 8;   // a spin cut's entries are byte offsets
     if (!fermion)
         for (size_t b = 0; b < s->blocks.size(); ++b)
             std::fill(s->sp_tab.begin() + s->sp_tbase[2 * b],
                       s->sp_tab.begin() + s->sp_tbase[2 * b] + (int64_t)ng * 4 * s->blocks[b].d_r,
-                      (uint16_t)s->blocks[b].d_r);
+                      (uint16_t)(8 * s->blocks[b].d_r));
     for (size_t b = 0; b < s->blocks.size(); ++b) {
         const BlockDev &B = s->blocks[b];
         for (int32_t e = 0; e < B.d_r; ++e) {
@@ -1221,13 +1225,13 @@ static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<
                 if (__builtin_popcount(w & s->spin_fmask[f]) == 1) {
                     const int sg = rbetw.empty() ? 0 : (__builtin_popcount(w & rbetw[f]) & 1);
                     s->sp_tab[(size_t)(s->sp_tbase[2 * b] + ((int64_t)(f / 4) * B.d_r + e) * 4 + f % 4)] =
-                        (uint16_t)(rank(w ^ s->spin_fmask[f]) | (sg << 15));
+                        (uint16_t)(unit * rank(w ^ s->spin_fmask[f]) | (sg << 15));
                 }
             for (int k = 0; k < nx; ++k) {
                 const XBondDev &X = s->xbond[k];
                 const int sg = fermion ? (occ_before(w, X.label, X.label ? X.rj : X.rj - nR) & 1) : 0;
                 s->sp_tab[(size_t)(s->sp_tbase[2 * b + 1] + (int64_t)k * B.d_r + e)] =
-                    (uint16_t)(rank(w ^ (1u << X.rj)) | (sg << 15));
+                    (uint16_t)(unit * rank(w ^ (1u << X.rj)) | (sg << 15));
             }
         }
     }
