@@ -717,11 +717,11 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // the item's own row for the right operator.
 // LEFT: the left operator here; otherwise its sum is already in y (the
 // two-pass kernels' left pass) and is read as the starting value.
-// tabR / tabX (non-null): the block's source-column tables of the right
-// flip-flop terms and the cross terms, instead of ranking the flipped words
-// (fermion cut: the column, 0xffff for no term; spin cut: the column's byte
-// offset in xs, 8 * dR, the zero slot, for no term); the terms are summed in
-// the same order either way.
+// tabR / tabX (given exactly when !LEFT, the two-pass right kernel): the
+// block's source-column tables of the right flip-flop terms and the cross
+// terms, instead of ranking the flipped words (fermion cut: the column,
+// 0xffff for no term; spin cut: the column's byte offset in xs, 8 * dR, the
+// zero slot, for no term); the terms are summed in the same order either way.
 // FERM: the spatial Hubbard cut's cross terms (block by the mode's spin,
 // fermion signs from the maps and the tables' bit 15) and right hops with
 // signs; spin problems compile without them.
@@ -816,12 +816,12 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                 const int e = tid + m * NT;
                 if (e < S.d_r) xs[e] = sv[m];
             }
-            if (!FERM && tabX && tid == 0) xs[S.d_r] = 0.0;   // the slot a term that does not apply reads
+            if (!FERM && !LEFT && tid == 0) xs[S.d_r] = 0.0;   // the slot a term that does not apply reads
             __syncthreads();
             for (int kk = k; kk < k1; ++kk) {
                 const int rj = P.xbond[kk].rj;
                 const double c = lneg ? -P.xbond[kk].coef : P.xbond[kk].coef;
-                if (tabX) {   // source column in bits 0..14, the right part's sign in bit 15
+                if constexpr (!LEFT) {   // from the table
                     uint32_t sx[M];
 #pragma unroll
                     for (int m = 0; m < M; ++m) {
@@ -837,13 +837,12 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                         }
                     } else {
                         // branch-free: a term that does not apply adds c * 0 from
-                        // the zero slot, so all reads of the bond are in flight together
+                        // the zero slot, so all reads of the bond are in flight
+                        // together. A slot past the row end (wr 0, sx 0) reads
+                        // inside the staged row, and its sum is never stored.
                         double v[M];
 #pragma unroll
-                        for (int m = 0; m < M; ++m) {
-                            const int e = tid + m * NT;
-                            v[m] = lds_at(xs, e < dR && ((wr[m] >> rj) & 1u) != bl ? sx[m] : 8u * S.d_r);
-                        }
+                        for (int m = 0; m < M; ++m) v[m] = lds_at(xs, ((wr[m] >> rj) & 1u) != bl ? sx[m] : 8u * S.d_r);
 #pragma unroll
                         for (int m = 0; m < M; ++m) acc[m] += c * v[m];
                     }
@@ -873,7 +872,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             const int e = tid + m * NT;
             if (e < dR) xs[e] = xv[m];
         }
-        if (!FERM && tabR && tid == 0) xs[dR] = 0.0;   // the slot a term that does not apply reads
+        if (!FERM && !LEFT && tid == 0) xs[dR] = 0.0;   // the slot a term that does not apply reads
         if (!LEFT && !FERM && P.n_xr > 0 && tid < (1 << P.n_xr)) {
             // the row's Sz Sz cross terms for every pattern of the n_xr right
             // sites: t = sum_g (bit g ? +1 : -1) xdl[gl][g], in g order
@@ -895,7 +894,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
     double ra[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) ra[m] = 0.0;
-    if (tabR && FERM) {   // four terms' source columns (and signs) per 8-byte load
+    if constexpr (!LEFT && FERM) {   // four terms' source columns (and signs) per 8-byte load
         for (int g = 0; g * 4 < n_flip; ++g) {
             uint64_t t[M];
 #pragma unroll
@@ -915,7 +914,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                 }
             }
         }
-    } else if (tabR) {   // four terms' source columns per 8-byte load
+    } else if constexpr (!LEFT) {   // four terms' source columns per 8-byte load
         // branch-free: a spin cut's table holds 8 * dR, the byte offset of the
         // zero slot xs[dR], for "no term" (and in its pads); slots past the
         // row end take four of them
@@ -949,7 +948,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
         if (e >= dR) continue;
         const uint32_t w = wr[m];
         double a = ra[m];
-        if (!tabR)
+        if constexpr (LEFT)
             for (int f = 0; f < n_flip; ++f) {
                 const uint32_t msk = fm[f];
                 if (__popc(w & msk) == 1) a += fc[f] * xs[rank16(w ^ msk, rl, rh)];
