@@ -721,7 +721,9 @@ hipError_t launch_hubrow(const ecut_sectors *s, const ProblemDev &prob, const in
 // block's source-column tables of the right flip-flop terms and the cross
 // terms, instead of ranking the flipped words (fermion cut: the column,
 // 0xffff for no term; spin cut: the column's byte offset in xs, 8 * dR, the
-// zero slot, for no term); the terms are summed in the same order either way.
+// zero slot, for no term, and for a cross term the source row's zero slot
+// minus the column's byte offset); the terms are summed in the same order
+// either way.
 // FERM: the spatial Hubbard cut's cross terms (block by the mode's spin,
 // fermion signs from the maps and the tables' bit 15) and right hops with
 // signs; spin problems compile without them.
@@ -818,6 +820,8 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             }
             if (!FERM && !LEFT && tid == 0) xs[S.d_r] = 0.0;   // the slot a term that does not apply reads
             __syncthreads();
+            const uint32_t flipm = bl ? ~0u : 0u;   // bit rj of w ^ flipm: the term applies
+            const int32_t zs = 8 * S.d_r;            // the zero slot's byte offset
             for (int kk = k; kk < k1; ++kk) {
                 const int rj = P.xbond[kk].rj;
                 const double c = lneg ? -P.xbond[kk].coef : P.xbond[kk].coef;
@@ -838,11 +842,17 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                     } else {
                         // branch-free: a term that does not apply adds c * 0 from
                         // the zero slot, so all reads of the bond are in flight
-                        // together. A slot past the row end (wr 0, sx 0) reads
-                        // inside the staged row, and its sum is never stored.
+                        // together. The entry is the zero slot minus the source
+                        // column (bytes); the sign-extended bit test (-1 where the
+                        // term applies, bit rj of the word differing from bl)
+                        // scales it. A slot past the row end (sx 0) reads the
+                        // zero slot, and its sum is never stored.
                         double v[M];
 #pragma unroll
-                        for (int m = 0; m < M; ++m) v[m] = lds_at(xs, ((wr[m] >> rj) & 1u) != bl ? sx[m] : 8u * S.d_r);
+                        for (int m = 0; m < M; ++m) {
+                            const int32_t on = __builtin_amdgcn_sbfe((int32_t)(wr[m] ^ flipm), rj, 1);
+                            v[m] = lds_at(xs, (uint32_t)(zs + on * (int32_t)sx[m]));
+                        }
 #pragma unroll
                         for (int m = 0; m < M; ++m) acc[m] += c * v[m];
                     }

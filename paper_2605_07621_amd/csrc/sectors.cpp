@@ -1168,8 +1168,9 @@ static void build_spin_tables(ecut_sectors *s) {
 //    (the right word with bit rj flipped; on the spatial Hubbard cut with
 //    the right part's sign (-1)^(occupied modes before the mode)), in the
 //    low 15 bits, the sign in bit 15, 0xffff for no term. On a spin cut
-//    (no signs) an entry is the column's byte offset in the staged row,
-//    8 * column, and "no term" is 8 * d_r, the zero slot after the row.
+//    (no signs) a flip entry is the column's byte offset in the staged row,
+//    8 * column, and "no term" is 8 * d_r, the zero slot after the row; a
+//    cross entry is the source block's zero slot minus the column, in bytes.
 static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<uint32_t> &rbetw) {
     s->sp2_ok = false;
     if (s->spin_fmask.size() > (size_t)SPIN_MAX_FLIP || s->max_d_r > SPIN_TILE) return;
@@ -1229,9 +1230,20 @@ static void build_two_pass_tables(ecut_sectors *s, int lbits, const std::vector<
                 }
             for (int k = 0; k < nx; ++k) {
                 const XBondDev &X = s->xbond[k];
-                const int sg = fermion ? (occ_before(w, X.label, X.label ? X.rj : X.rj - nR) & 1) : 0;
-                s->sp_tab[(size_t)(s->sp_tbase[2 * b + 1] + (int64_t)k * B.d_r + e)] =
-                    (uint16_t)(unit * rank(w ^ (1u << X.rj)) | (sg << 15));
+                const uint32_t wp = w ^ (1u << X.rj);
+                uint16_t v;
+                if (fermion) {
+                    const int sg = occ_before(w, X.label, X.label ? X.rj : X.rj - nR) & 1;
+                    v = (uint16_t)(rank(wp) | (sg << 15));
+                } else {
+                    // the source block's zero slot minus the source column, in
+                    // bytes: the kernel subtracts it from the zero slot when the
+                    // term applies (a source block too wide for the kernel does
+                    // not exist in a problem on it, and its entry is never read)
+                    const int64_t z = 8 * (int64_t)binom(nR, __builtin_popcount(wp));
+                    v = z <= 8 * (int64_t)s->max_d_r ? (uint16_t)(z - 8 * rank(wp)) : (uint16_t)0;
+                }
+                s->sp_tab[(size_t)(s->sp_tbase[2 * b + 1] + (int64_t)k * B.d_r + e)] = v;
             }
         }
     }
