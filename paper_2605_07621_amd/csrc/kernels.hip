@@ -1173,7 +1173,7 @@ __global__ __launch_bounds__(ONE ? SPIN_THREADS : SPIN_MANY_THREADS, ONE ? 4 : 2
 // ranges (xcd_item): a group's rows stay on one XCD and in its L2.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ int xcd_item(int n_xcd, int per_xcd);
-template <bool PAIR, bool STREAM>
+template <bool PAIR, bool STREAM, bool OFF32 = false>
 __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it);
 
 template <bool STREAM>
@@ -1737,7 +1737,7 @@ __device__ __forceinline__ int xcd_item(int n_xcd, int per_xcd) {
 // rows' CSR ranges, output rows and source rows are loaded once, one entry
 // per lane, and read back with readlane, so the gathers of a row wait for no
 // index load of their own.
-template <bool PAIR, bool STREAM>
+template <bool PAIR, bool STREAM, bool OFF32>
 __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
     const int sg = it / A.n_rgroups;
     const int rg = it - sg * A.n_rgroups;
@@ -1764,16 +1764,29 @@ __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
         pb = A.hl_ptr[rr + 1];
         ar = A.rows[rr];
     }
+    // OFF32 (the vector's bytes fit 32 bits): the neighbour rows' byte
+    // offsets, added to the lane's own, so a gather is one 32-bit add
+    // beside the scalar base instead of a 64-bit row product per neighbour
     int colv[HUBU_RMAX];
+    const uint32_t row_bytes = 8u * (uint32_t)A.dR;
 #pragma unroll
     for (int k = 0; k < HUBU_RMAX; ++k) {
         colv[k] = 0;
         if (k < nrw) {
             const int q0 = __builtin_amdgcn_readlane(pa, k);
-            if (lane < __builtin_amdgcn_readlane(pb, k) - q0) colv[k] = A.hl_col[q0 + lane];
+            if (lane < __builtin_amdgcn_readlane(pb, k) - q0) {
+                const int col = A.hl_col[q0 + lane];
+                colv[k] = OFF32 ? (int)((uint32_t)col * row_bytes) : col;
+            }
         }
     }
     const double *__restrict__ xc = A.x + cl;
+    const uint32_t lane_bytes = 8u * (uint32_t)cl;
+    auto nb_src = [&](int k, int n) -> const double * {
+        const int v = __builtin_amdgcn_readlane(colv[k], n);
+        if constexpr (OFF32) return (const double *)((const char *)A.x + ((uint32_t)v + lane_bytes));
+        else return xc + (int64_t)v * dR;
+    };
 #pragma unroll
     for (int k = 0; k < HUBU_RMAX; ++k) {
         if (k >= nrw) break;
@@ -1789,7 +1802,7 @@ __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
             double v0[HUBU_NB], v1[HUBU_NB], h[HUBU_NB];
 #pragma unroll
             for (int u = 0; u < HUBU_NB; ++u) {
-                const double *p = xc + (int64_t)__builtin_amdgcn_readlane(colv[k], j + u) * dR;
+                const double *p = nb_src(k, j + u);
                 if constexpr (PAIR) {
                     const double2 q = *(const double2 *)p;
                     v0[u] = q.x;
@@ -1817,7 +1830,7 @@ __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
             for (int u = 0; u < HUBU_NB; ++u) {
                 v0[u] = v1[u] = 0.0;
                 if (j + u < deg) {
-                    const double *p = xc + (int64_t)__builtin_amdgcn_readlane(colv[k], j + u) * dR;
+                    const double *p = nb_src(k, j + u);
                     if constexpr (PAIR) {
                         const double2 q = *(const double2 *)p;
                         v0[u] = q.x;
@@ -1855,12 +1868,16 @@ __device__ __forceinline__ void hubU_item(const HubUArgs &A, int it) {
     }
 }
 
-template <bool PAIR, bool STREAM>
+template <bool PAIR, bool STREAM, bool OFF32>
 __global__ __launch_bounds__(HUBU_THREADS) void k_hubU(const HubUArgs A, int n_xcd, int per_xcd) {
     const int it = xcd_item(n_xcd, per_xcd);
     if (it >= A.n_items) return;
-    hubU_item<PAIR, STREAM>(A, it);
+    hubU_item<PAIR, STREAM, OFF32>(A, it);
 }
+
+// every byte offset into a vector of n elements (a 16-byte read at most)
+// fits 32 bits
+static bool fits_off32(int64_t n) { return n * 8 + 16 <= (int64_t)UINT32_MAX; }
 
 // NS: bond slots held in registers (>= A.n_slots).  The source column of
 // each bond for this thread's column is loaded once per item and reused for
@@ -1994,10 +2011,19 @@ hipError_t launch_hub6_left(const HubUArgs &U, int n_xcd, hipStream_t st) {
     const int xu = n_xcd == 1 ? 1 : 8;
     const int pu = (U.n_items + xu - 1) / xu;
     const dim3 gu(xu == 8 ? 8 * pu : U.n_items);
-    if (pair && stream) hipLaunchKernelGGL((k_hubU<true, true>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
-    else if (pair) hipLaunchKernelGGL((k_hubU<true, false>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
-    else if (stream) hipLaunchKernelGGL((k_hubU<false, true>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
-    else hipLaunchKernelGGL((k_hubU<false, false>), gu, dim3(HUBU_THREADS), 0, st, U, xu, pu);
+    const bool o32 = fits_off32((int64_t)U.n_rows * U.dR);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, gu, dim3(HUBU_THREADS), 0, st, U, xu, pu); };
+    if (o32) {
+        if (pair && stream) go(k_hubU<true, true, true>);
+        else if (pair) go(k_hubU<true, false, true>);
+        else if (stream) go(k_hubU<false, true, true>);
+        else go(k_hubU<false, false, true>);
+    } else {
+        if (pair && stream) go(k_hubU<true, true, false>);
+        else if (pair) go(k_hubU<true, false, false>);
+        else if (stream) go(k_hubU<false, true, false>);
+        else go(k_hubU<false, false, false>);
+    }
     return hipGetLastError();
 }
 
@@ -2548,6 +2574,8 @@ hipError_t launch_spin2(const SpinLArgs &L, const ProblemDev &P, const uint16_t 
     int per = 0;
     if (L.n_items > 0) {
         const dim3 g = grid_of(L.n_items, per);
+        // 64-bit row products here: the 32-bit form of the Hubbard left pass
+        // (fewer registers, eight waves per SIMD) measured slower on spin blocks
         if ((int64_t)P.dim >= STREAM_STORE_MIN)
             hipLaunchKernelGGL(k_spinL<true>, g, dim3(HUBU_THREADS), 0, st, L, xu, per);
         else
