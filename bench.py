@@ -17,6 +17,7 @@ the serving comparison (sequential vs continuous batching).
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -28,13 +29,22 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
+def _code_only(text):
+    """The source without its comments and blank space, so that an edit of
+    a comment leaves the hash (and the counters it guards) valid."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
     """Hash of the sources that decide what a profiled kernel does: the
-    kernels, their constants and argument structs, and the work lists."""
+    kernels, their constants and argument structs, and the work lists
+    (their code, not their comments)."""
     h = hashlib.sha256()
     for name in ("kernels.hip", "kernels.h", "ecut_internal.h", "sectors.cpp"):
-        with open(os.path.join(ROOT, "paper_2605_07621_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2605_07621_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

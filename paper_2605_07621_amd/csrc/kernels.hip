@@ -945,7 +945,7 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
                 double v[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = lds_at(xs, (uint32_t)(t[m] >> (16 * i)) & 0xffffu);
-                // the last word's pad entries are dR (the zero slot) and
+                // the last word's pad entries are the zero slot's offset and
                 // their coefficients 0, so all 4 terms are summed unguarded
 #pragma unroll
                 for (int i = 0; i < 4; ++i) ra[m] += cf[i] * v[i];

@@ -217,6 +217,27 @@ def test_bench_traffic_lookup(tmp_path, monkeypatch):
     assert bench.traffic_from_profile("k_x", "w", 0) == (None, None)
 
 
+def test_kernel_hash_follows_code_not_comments(tmp_path, monkeypatch):
+    """The hash that guards the counter summaries changes with the kernels'
+    code and not with their comments or spacing."""
+    import shutil
+    import bench
+    src = os.path.join(ROOT, "paper_2605_07621_amd", "csrc")
+    dst = tmp_path / "paper_2605_07621_amd" / "csrc"
+    dst.mkdir(parents=True)
+    for name in ("kernels.hip", "kernels.h", "ecut_internal.h", "sectors.cpp"):
+        shutil.copy(os.path.join(src, name), dst / name)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+    k = dst / "kernels.h"
+    text = k.read_text()
+    k.write_text(text.replace("namespace ecut {", "namespace ecut {  // a comment\n/* and a\n block */\n", 1))
+    assert bench.kernel_source_hash() == h0
+    k.write_text(text.replace("constexpr int HUBD_NB = 8;", "constexpr int HUBD_NB = 16;", 1))
+    assert "HUBD_NB = 16" in k.read_text()
+    assert bench.kernel_source_hash() != h0
+
+
 def test_option_structs_match_header():
     # the binding's ctypes structs follow the header's field order and types
     import ctypes
