@@ -1373,19 +1373,20 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
             double v[HUB3_M];
 #pragma unroll
             for (int m = 0; m < HUB3_M; ++m) v[m] = col_m[m] >= 0 ? x0row[col_m[m]] : 0.0;
+            // split mode: the up-spin hops' sum is already in y; it is loaded
+            // here, so its loads are in flight with the tile's
+            if constexpr (!UP) {
+#pragma unroll
+                for (int m = 0; m < HUB3_M; ++m)
+                    acc[m] = col_m[m] >= 0 ? A.y[(int64_t)it.row0 * dR + col_m[m]] : 0.0;
+            }
 #pragma unroll
             for (int m = 0; m < HUB3_M; ++m)
                 if (col_m[m] >= 0) xs[(p + m * per_pass) * Lp + j] = v[m];
             for (int sr = tid; sr < nsr; sr += NT) xs[sr * Lp + L] = 0.0;
         }
-        // up-spin hops: neighbour rows at the same columns (split mode: already in y)
-        if (!UP) {
-            double v[HUB3_M];
-#pragma unroll
-            for (int m = 0; m < HUB3_M; ++m) v[m] = col_m[m] >= 0 ? A.y[(int64_t)it.row0 * dR + col_m[m]] : 0.0;
-#pragma unroll
-            for (int m = 0; m < HUB3_M; ++m) acc[m] = v[m];
-        } else if (one_row) {
+        // up-spin hops (fused mode): neighbour rows at the same columns
+        if (UP && one_row) {
             const int uq0 = A.hl_ptr[it.row0], uq1 = A.hl_ptr[it.row0 + 1];
             for (int q = uq0; q < uq1; ++q) {
                 const double *__restrict__ xn = A.x + (size_t)A.hl_col[q] * (size_t)dR;
@@ -1395,7 +1396,7 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
 #pragma unroll
                 for (int m = 0; m < HUB3_M; ++m) acc[m] += v[m];
             }
-        } else {
+        } else if (UP) {
 #pragma unroll
             for (int m = 0; m < HUB3_M; ++m) {
                 if (col_m[m] < 0) continue;
@@ -1435,7 +1436,10 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
             for (int m = 0; m < HUB3_M; ++m) acc[m] += UP ? v[m] : A.hop * v[m];
         }
         __syncthreads();
-        // down-spin hops inside the tile, diagonal, epilogue
+        // down-spin hops inside the tile, diagonal, epilogue. Split mode:
+        // every result first (into acc), then the stores, so that no slot's
+        // loads wait for an earlier slot's store (the memory counter counts
+        // both); the fused kernel, short of registers, stores as it goes.
         double part = 0.0;
         const uint32_t aw0 = A.lwords[it.row0];
 #pragma unroll
@@ -1466,8 +1470,21 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
                 else
                     y -= ef.y * A.z[gi];
             }
-            store_result<STREAM>(&A.y[gi], y);
-            part += x0 * y;
+            if constexpr (UP) {
+                store_result<STREAM>(&A.y[gi], y);
+                part += x0 * y;
+            } else {
+                acc[m] = y;
+            }
+        }
+        if constexpr (!UP) {
+#pragma unroll
+            for (int m = 0; m < HUB3_M; ++m) {
+                if (col_m[m] < 0) continue;
+                const double x0 = xs[(p + m * per_pass) * Lp + j];
+                store_result<STREAM>(&A.y[(int64_t)it.row0 * dR + col_m[m]], acc[m]);
+                part += x0 * acc[m];
+            }
         }
         if (A.partials) {
             const double sum = block_sum(part, red);
