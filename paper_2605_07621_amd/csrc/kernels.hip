@@ -952,18 +952,30 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             }
         }
     }
+    if constexpr (!LEFT) {
+        // the right operator's sum joins acc (the order of the sum is
+        // unchanged), and ra takes the diagonal of every slot, all loads in
+        // flight together instead of one wait per slot
+#pragma unroll
+        for (int m = 0; m < M; ++m) acc[m] += ra[m];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = tid + m * NT;
+            ra[m] = e < dR ? P.diag_r[B.rbase + e] : 0.0;
+        }
+    }
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int e = tid + m * NT;
         if (e >= dR) continue;
         const uint32_t w = wr[m];
-        double a = ra[m];
+        double a = LEFT ? ra[m] : 0.0;
         if constexpr (LEFT)
             for (int f = 0; f < n_flip; ++f) {
                 const uint32_t msk = fm[f];
                 if (__popc(w & msk) == 1) a += fc[f] * xs[rank16(w ^ msk, rl, rh)];
             }
-        double dg = dgl + P.diag_r[B.rbase + e];
+        double dg = dgl + (LEFT ? P.diag_r[B.rbase + e] : ra[m]);
         if (!FERM && P.n_xr > 0) {
             if constexpr (LEFT) {   // one pass: the table entry's sum, computed in place
                 double t = 0.0;
@@ -999,11 +1011,26 @@ __device__ __forceinline__ void spin_one_row(const ProblemDev &P, const BlockDev
             }
         }
         const double x0 = xs[e];
-        double yv = ef.x * (acc[m] + a + dg * x0);
+        double yv = LEFT ? ef.x * (acc[m] + a + dg * x0) : ef.x * (acc[m] + dg * x0);
         const int64_t gi = B.offset + (int64_t)l * dR + e;
         if (P.z) yv -= ef.y * P.z[gi];
-        P.y[gi] = yv;
-        part += x0 * yv;
+        if constexpr (LEFT) {
+            P.y[gi] = yv;
+            part += x0 * yv;
+        } else {
+            acc[m] = yv;
+        }
+    }
+    if constexpr (!LEFT) {
+        // the stores after every slot's loads: a wait for a load also waits
+        // for the stores issued before it (the memory counter counts both)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int e = tid + m * NT;
+            if (e >= dR) continue;
+            P.y[B.offset + (int64_t)l * dR + e] = acc[m];
+            part += xs[e] * acc[m];
+        }
     }
     if (P.partials) {
         const double sum = block_sum(part, red);
