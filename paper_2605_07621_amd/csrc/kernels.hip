@@ -1394,6 +1394,8 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
             acc[m] = 0.0;
         }
         const double *__restrict__ x0row = A.x + (int64_t)it.row0 * dR;
+        // fused kernel: the first row's word, in flight with the tile's loads
+        const uint32_t aw0_v = UP ? A.lwords[it.row0] : 0u;
         // stage the tile (row stride L+1, zero in the pad slot); every load
         // of a phase is issued before any result is consumed
         {
@@ -1467,14 +1469,21 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
         // every result first (into acc), then the stores, so that no slot's
         // loads wait for an earlier slot's store (the memory counter counts
         // both); the fused kernel, short of registers, stores as it goes.
+        // The two item kinds run separate copies of the loop (ONE: a one-row
+        // item, whose row word is aw0), so a one-row item's slots load no row
+        // word, and no wait for such a load holds back the next slot.
         double part = 0.0;
-        const uint32_t aw0 = A.lwords[it.row0];
+        // the first row's word (fused kernel: in a scalar register, so that no
+        // slot waits on its load, and with it on the previous slot's store)
+        const uint32_t aw0 = UP ? __builtin_amdgcn_readfirstlane(aw0_v) : A.lwords[it.row0];
+        auto epilogue = [&](auto one_c) {
+        constexpr bool ONE = decltype(one_c)::value;
 #pragma unroll
         for (int m = 0; m < HUB3_M; ++m) {
             if (col_m[m] < 0) continue;
             const int sr = p + m * per_pass;
             int r = 0, s = sr;
-            if (!one_row) {
+            if (!ONE) {
                 r = (int)(((float)sr + 0.5f) * inv_nseg);
                 s = sr - r * nseg;
             }
@@ -1486,7 +1495,7 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
             const int hc = hcnt[s];
             const int32_t *hq = hnb + s * hs;
             for (int q = 0; q < hc; ++q) dn += xs[rb + (hq[q] - s) * Lp + j];
-            const uint32_t aw = one_row ? aw0 : A.lwords[it.row0 + r];
+            const uint32_t aw = ONE ? aw0 : A.lwords[it.row0 + r];
             const uint32_t bw = ((uint32_t)sinf[s].y << A.h) | (uint32_t)li.x;
             const double dg = A.u0 * (double)__popc(aw & bw);
             const int64_t gi = (int64_t)it.row0 * dR + col_m[m];
@@ -1504,6 +1513,9 @@ __global__ __launch_bounds__(HUB3_THREADS, HUB3_WAVES_PER_EU) void k_hub3(const 
                 acc[m] = y;
             }
         }
+        };
+        if (one_row) epilogue(std::true_type{});
+        else epilogue(std::false_type{});
         if constexpr (!UP) {
 #pragma unroll
             for (int m = 0; m < HUB3_M; ++m) {
