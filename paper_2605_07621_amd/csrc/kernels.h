@@ -18,7 +18,7 @@ constexpr int HUB2_M = 16;                   // element passes per thread and it
 constexpr int HUB2_LOREG = 8;                // low-hop entries kept in registers
 constexpr int HUB2_NB = 8;                   // left-operator neighbour loads issued together per element
 constexpr int HUB3_THREADS = 512;            // threads of the fast class-tile kernel
-constexpr int HUB3_M = 11;                   // element slots per thread and item in the fast kernel
+constexpr int HUB3_M = 10;                   // element slots per thread and item in the fast kernel
 constexpr int HUB3_WAVES_PER_EU = 4;         // occupancy hint of that kernel (sets its register budget)
 constexpr int HUBSEG_THREADS = 512;
 constexpr int HUBSEG_M = 10;                 // element slots per thread and item in the segment-tile kernel
